@@ -1,0 +1,97 @@
+"""Store-all reverse mode through the BullFrog PM run, in FP64 (test
+infrastructure only).
+
+This is the "discretise-then-optimise" gradient of Sec. "Adjoint method":
+every midpoint state X^{n+1/2} of the forward run is kept and the exact VJPs
+of each drift and kick are applied backwards.  It never integrates the primal
+state backwards, so it is independent of the reverse-trajectory trick of the
+adjoint method that the GPU uses; the recurrences for the cotangents are
+those of tab. adjoint_dkd, and the VJP of the force is assembled from the
+scatter/gather rules of App. "Custom VJP and JVP":
+
+* gather w.r.t. positions (a gather with grad W, weighted by the cotangent),
+* gather w.r.t. the mesh (a scatter of the cotangent with W),
+* the transposed Fourier multiplier (conj K_c),
+* scatter w.r.t. positions (a gather of the mesh cotangent with grad W).
+
+The initial-condition VJP uses Psi^0 = D_start psi, V^0 = psi and the
+transposed IC multiplier; psi is proportional to sigma8 and the BullFrog
+coefficients do not depend on it, so dL/dsigma8 = <psi_bar, psi> / sigma8.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ics, mesh
+from .force import force_multipliers, PMConfig
+
+
+def force_vjp(cfg: PMConfig, psi, s, u):
+    """J_A(Psi)^T u for the PM force A(Psi) of ``force.pm_force``; u (3, N)."""
+    n, N = cfg.n_g, cfg.N
+    delta = mesh.contrast(mesh.deposit(psi, cfg.n_p, n, cfg.order), N, n)
+    dk = np.fft.rfftn(delta.reshape(n, n, n))
+    K = force_multipliers(cfg, s)
+    xbar = np.zeros((3, N))
+    dbar_k = np.zeros_like(dk)
+    for c in range(3):
+        g_c = np.fft.irfftn(K[c] * dk, s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
+        # direct part: d/dX_i of gather(g_c)(X_i), weighted by u_c
+        xbar += mesh.grad_gather(g_c, psi, cfg.n_p, n, cfg.order) * u[c]
+        # mesh part: gather^T = scatter of u_c, then the transposed multiplier
+        gbar = mesh.deposit(psi, cfg.n_p, n, cfg.order, weights=u[c])
+        dbar_k += np.conj(K[c]) * np.fft.rfftn(gbar.reshape(n, n, n))
+    dbar = np.fft.irfftn(dbar_k, s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
+    # delta = (n^3/N) m - 1, and m = scatter(1): scatter^T w.r.t. positions
+    xbar += mesh.grad_gather(dbar * (n ** 3 / N), psi, cfg.n_p, n, cfg.order)
+    return xbar
+
+
+def density_vjp(psi, n_p, n_g, dbar):
+    """VJP of the final CIC contrast delta(Psi) w.r.t. Psi."""
+    return mesh.grad_gather(np.asarray(dbar, dtype=np.float64) * (n_g ** 3 / n_p ** 3),
+                            psi, n_p, n_g, 2)
+
+
+def final_density(prob, psi):
+    n_p, n_g = prob.pm.n_p, prob.pm.n_g
+    return mesh.contrast(mesh.deposit(psi, n_p, n_g, 2), n_p ** 3, n_g)
+
+
+def ic_vjp(prob, psibar):
+    """w_bar = sum_c T_c^T psibar_c with psi_c = T_c w = IDFT(h_c DFT(w))."""
+    n = prob.pm.n_p
+    h = ics.ic_multipliers(n, prob.pm.box, prob.spectrum_fn(), prob.D_ref())
+    acc = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+    for c in range(3):
+        acc += np.conj(h[c]) * np.fft.rfftn(np.asarray(psibar[c]).reshape(n, n, n))
+    return np.fft.irfftn(acc, s=(n, n, n), axes=(0, 1, 2))
+
+
+def gradient(prob, w, dL_ddelta):
+    """Reverse-mode gradient of L(delta_final) w.r.t. the white noise w and
+    sigma8, given a function dL_ddelta(delta) -> cotangent mesh.
+    Returns (w_bar (n_p^3,), dL/dsigma8, delta_final)."""
+    from .nbody import initial_state, run_from
+    psi0, vel0, psi_lin = initial_state(prob, w)
+    record = []
+    psiN, _ = run_from(prob, psi0, vel0, record=record)
+    delta = final_density(prob, psiN)
+    xbar = density_vjp(psiN, prob.pm.n_p, prob.pm.n_g, dL_ddelta(delta))
+    vbar = np.zeros_like(xbar)
+    xbar, vbar = reverse_cotangents(prob, record, xbar, vbar)
+    psibar = prob.D_start() * xbar + vbar
+    wbar = ic_vjp(prob, psibar)
+    dsig = float(np.sum(psibar * psi_lin)) / prob.sigma8
+    return wbar.reshape(-1), dsig, delta
+
+
+def reverse_cotangents(prob, record, xbar, vbar):
+    """Apply the cotangent recurrences of tab. adjoint_dkd over the stored
+    midpoints, last step first."""
+    for st, (psi_half, _acc) in zip(reversed(prob.steps()), reversed(record)):
+        vbar = vbar + st.tau2 * xbar                    # adjoint of drift 2
+        xbar = xbar + force_vjp(prob.pm, psi_half, st.s, st.beta * vbar)  # adjoint kick
+        vbar = st.alpha * vbar                          # velocity rescale
+        vbar = vbar + st.tau1 * xbar                    # adjoint of drift 1
+    return xbar, vbar

@@ -1,0 +1,213 @@
+"""Non-uniform FFT force in FP64 (test infrastructure only).
+
+Follows Sec. "Force evaluation" (paragraphs on the NUFFT density, the
+deconvolution and the NUFFT interpolation) and eq. NUDFTII:
+  F_m     = sum_i exp(-2 pi i m.X_i / L)                 (type 1, unit masses)
+  delta_m = (n_p^3 / N) F_m for m != 0, 0 at m = 0
+  g_c,m   = i k_c / k^2 s delta_m                         (exact i k gradient)
+  A_i,c   = (1/n_p^3) sum_m g_c,m exp(+2 pi i m.X_i / L)  (type 2)
+with m restricted to the particle reciprocal lattice strictly below the
+particle Nyquist mode, |m_a| < n_p/2 per axis.
+
+Readings (the paper prints no kernel formula and writes the sums over
+{0..N_d-1}^3, which is read as the centred set above):
+* "exponential of semicircle" kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)) for
+  |z| < 1, 0 otherwise, with z = x / (w/2) for a fine-grid offset x in cells
+  (Barnett, Magland & af Klinteberg 2019); width w = 6, beta = 2.3 w, upsampling
+  sigma = n_f / n_p = 2;
+* phi_hat(theta) = int phi(x) cos(theta x) dx by Gauss-Legendre quadrature;
+* spreading: b_j = sum_i phi(j - u_i) on the periodic n_f^3 grid with
+  u = (q + Psi) sigma in fine cells, F_m ~ DFT(b)_m / phi_hat(theta_m);
+  interpolation: A_i = (1/n_p^3) sum_j c_j phi(u_i - j) with
+  c = n_f^3 IDFT(zero-padded g / phi_hat).
+
+Fixed-point ES spreading (the bit pattern the GPU reproduces): the 1D weight
+of a node at fixed-point distance d (B = 20 fraction bits) is integer linear
+interpolation in a table T[t] = rne(phi(t / 4096) 2^20), t = 0 .. 3*4096,
+  w = T[i] + floor(((T[i+1] - T[i]) f + 128) / 256),  i = d >> 8, f = d & 255,
+and the 3D product of three such weights is rounded half-to-even to the 2^32
+mass unit (no remainder step: the ES kernel is not a partition of unity).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import mesh
+
+TAB_PER_CELL = 4096
+K_ES = 20
+
+
+def es_phi(z, beta):
+    z = np.asarray(z, dtype=np.float64)
+    inside = np.abs(z) < 1.0
+    return np.where(inside, np.exp(beta * (np.sqrt(np.clip(1.0 - z * z, 0.0, None)) - 1.0)), 0.0)
+
+
+def es_kernel(x, width, beta):
+    """phi at a fine-grid offset x (cells)."""
+    return es_phi(np.asarray(x, dtype=np.float64) / (width / 2.0), beta)
+
+
+def es_phihat(theta, width, beta, n_quad=400):
+    """int_{-w/2}^{w/2} phi(x) cos(theta x) dx."""
+    t, wq = np.polynomial.legendre.leggauss(n_quad)
+    half = width / 2.0
+    x = half * t
+    fx = es_kernel(x, width, beta) * wq * half
+    theta = np.asarray(theta, dtype=np.float64)
+    return np.cos(np.multiply.outer(theta, x)) @ fx
+
+
+def kept_modes(n_p):
+    """Centred modes strictly below the particle Nyquist mode."""
+    return np.arange(-(n_p // 2) + 1, n_p // 2)
+
+
+def fine_coords(psi, n_p, n_f):
+    return mesh.mesh_coords(psi, n_p, n_f)
+
+
+def _force_multiplier(mx, my, mz, n_p, s):
+    """i k_c s / k^2 in lattice units (k = 2 pi m / n_p), zero at m = 0."""
+    k = [2 * np.pi * m / n_p for m in (mx, my, mz)]
+    k2 = k[0] ** 2 + k[1] ** 2 + k[2] ** 2
+    zero = k2 == 0
+    k2s = np.where(zero, 1.0, k2)
+    return [np.where(zero, 0.0, 1j * kc * s / k2s) for kc in k]
+
+
+def nudft_force_direct(n_p, n_f, psi, s):
+    """Brute-force type-1 and type-2 sums, O(N n_p^3); tiny inputs only."""
+    u = fine_coords(psi, n_p, n_f)
+    ms = kept_modes(n_p)
+    mx, my, mz = np.meshgrid(ms, ms, ms, indexing="ij")
+    mx, my, mz = mx.reshape(-1), my.reshape(-1), mz.reshape(-1)
+    phase = 2 * np.pi / n_f * (np.outer(mx, u[0]) + np.outer(my, u[1]) + np.outer(mz, u[2]))
+    E = np.exp(-1j * phase)                   # (M, N)
+    F = E.sum(axis=1)
+    N = psi.shape[1]
+    delta = F * (n_p ** 3 / N)
+    K = _force_multiplier(mx, my, mz, n_p, s)
+    A = np.stack([np.real((K[c] * delta) @ np.conj(E)) for c in range(3)]) / n_p ** 3
+    return A
+
+
+def _spread_float(u, n_f, width, beta, weights=None):
+    """b_j = sum_i w_i phi(j - u_i) on the periodic n_f^3 grid (FP64); the
+    stencil is the w nodes floor(u) - w/2 + 1 .. floor(u) + w/2 (even w)."""
+    assert width % 2 == 0
+    N = u.shape[1]
+    w_i = np.ones(N) if weights is None else weights
+    base = np.floor(u).astype(np.int64) - (width // 2 - 1)
+    wts = [np.stack([es_kernel(base[a] + o - u[a], width, beta) for o in range(width)])
+           for a in range(3)]
+    out = np.zeros(n_f ** 3)
+    for a in range(width):
+        ix = (base[0] + a) % n_f
+        for b in range(width):
+            iy = (base[1] + b) % n_f
+            wab = wts[0][a] * wts[1][b] * w_i
+            for c in range(width):
+                iz = (base[2] + c) % n_f
+                out += np.bincount((ix * n_f + iy) * n_f + iz, weights=wab * wts[2][c],
+                                   minlength=n_f ** 3)
+    return out
+
+
+def _interp_float(field, u, n_f, width, beta):
+    N = u.shape[1]
+    f = field.reshape(-1)
+    base = np.floor(u).astype(np.int64) - (width // 2 - 1)
+    wts = [np.stack([es_kernel(base[a] + o - u[a], width, beta) for o in range(width)])
+           for a in range(3)]
+    v = np.zeros(N)
+    for a in range(width):
+        ix = (base[0] + a) % n_f
+        for b in range(width):
+            iy = (base[1] + b) % n_f
+            wab = wts[0][a] * wts[1][b]
+            for c in range(width):
+                iz = (base[2] + c) % n_f
+                v += f[(ix * n_f + iy) * n_f + iz] * wab * wts[2][c]
+    return v
+
+
+def nufft_force(n_p, n_f, psi, s, width=6, beta=13.8):
+    """Spreading-based NUFFT force A(X) (3, N) in dq units per unit D."""
+    u = fine_coords(psi, n_p, n_f)
+    N = u.shape[1]
+    b = _spread_float(u, n_f, width, beta).reshape(n_f, n_f, n_f)
+    bk = np.fft.rfftn(b)
+    ms = kept_modes(n_p)
+    mz = np.arange(0, n_p // 2)
+    ix = ms % n_f
+    ph = lambda m: es_phihat(2 * np.pi * m / n_f, width, beta)
+    sub = bk[np.ix_(ix, ix, mz)] / (ph(ms)[:, None, None] * ph(ms)[None, :, None]
+                                    * ph(mz)[None, None, :])
+    delta = sub * (n_p ** 3 / N)
+    MX, MY, MZ = np.meshgrid(ms, ms, mz, indexing="ij")
+    K = _force_multiplier(MX, MY, MZ, n_p, s)
+    A = np.empty((3, N))
+    for c in range(3):
+        g = K[c] * delta / (ph(ms)[:, None, None] * ph(ms)[None, :, None] * ph(mz)[None, None, :])
+        full = np.zeros((n_f, n_f, n_f // 2 + 1), dtype=np.complex128)
+        full[np.ix_(ix, ix, mz)] = g
+        c_j = np.fft.irfftn(full, s=(n_f, n_f, n_f), axes=(0, 1, 2)) * n_f ** 3
+        A[c] = _interp_float(c_j, u, n_f, width, beta) / n_p ** 3
+    return A
+
+
+# --------------------------------------------------------------------------
+# Fixed-point specification of the ES spreading
+# --------------------------------------------------------------------------
+
+def es_table(width=6, beta=13.8):
+    t = np.arange((width // 2) * TAB_PER_CELL + 2, dtype=np.float64) / TAB_PER_CELL
+    return np.rint(es_kernel(t, width, beta) * 2.0 ** K_ES).astype(np.int64)
+
+
+def es_fixed_weight(dist_fixed, table):
+    """Integer 1D weight for a non-negative fixed-point distance (B = 20)."""
+    shift = mesh.B_FRAC - int(math.log2(TAB_PER_CELL))       # 8
+    i = dist_fixed >> shift
+    f = dist_fixed & ((1 << shift) - 1)
+    ok = i < table.size - 1
+    ic = np.where(ok, i, 0)
+    t0, t1 = table[ic], table[ic + 1]
+    w = t0 + (((t1 - t0) * f + (1 << (shift - 1))) >> shift)
+    return np.where(ok, w, 0)
+
+
+def deposit_fixedpoint_es(psi_f32, n_p, n_f, width=6, beta=13.8):
+    """Integer ES spreading onto n_f^3 (flat int64) from FP32 Psi."""
+    U = mesh.fixed_coords(psi_f32, n_p, n_f)
+    table = es_table(width, beta)
+    one = 1 << mesh.B_FRAC
+    base = (U >> mesh.B_FRAC) - (width // 2 - 1)
+    W = []
+    for a in range(3):
+        rows = []
+        for o in range(width):
+            d = np.abs(((base[a] + o) << mesh.B_FRAC) - U[a])
+            # strictly inside the support: |z| < 1
+            rows.append(np.where(d < (width // 2) * one, es_fixed_weight(d, table), 0))
+        W.append(np.stack(rows))
+    shift = 3 * K_ES - 32
+    out = np.zeros(n_f ** 3, dtype=np.int64)
+    for a in range(width):
+        ix = (base[0] + a) % n_f
+        for b in range(width):
+            iy = (base[1] + b) % n_f
+            wab = W[0][a] * W[1][b]
+            for c in range(width):
+                iz = (base[2] + c) % n_f
+                w3 = mesh._rne_shift(wab * W[2][c], shift)
+                lin = (ix * n_f + iy) * n_f + iz
+                hi = w3 >> 17
+                lo = w3 - (hi << 17)
+                out += np.rint(np.bincount(lin, weights=hi, minlength=n_f ** 3)).astype(np.int64) << 17
+                out += np.rint(np.bincount(lin, weights=lo, minlength=n_f ** 3)).astype(np.int64)
+    return out

@@ -1,0 +1,96 @@
+"""Pins of the oracle's cosmology, growth and BullFrog coefficients against
+closed forms and the paper's printed series (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cosmo
+
+
+@pytest.fixture(scope="module")
+def growth():
+    return cosmo.Growth(0.31)
+
+
+@pytest.mark.parametrize("a", [0.02, 0.1, 0.3, 0.6, 1.0])
+def test_growth_matches_closed_form_integral(growth, a):
+    # flat-LCDM growing mode D = 5/2 Om H int da/(aH)^3 (D ~ a early): pins the
+    # (2 - 3 gamma) friction reading of eq. growth_odes
+    assert abs(float(growth.D(a)) / cosmo.growth_closed_form(a, 0.31) - 1) < 1e-10
+
+
+@pytest.mark.parametrize("a", [0.02, 0.05, 0.1])
+def test_second_order_growth_matches_paper_series(growth, a):
+    # Sec. "Time stepping": E = -(3/7) D^2 - (3/1001) Lambda D^5 + O(Lambda^2 D^8)
+    lam = (1 - 0.31) / 0.31
+    D = float(growth.D(a))
+    series = -3 / 7 * D ** 2 - 3 / 1001 * lam * D ** 5
+    assert abs(float(growth.E(a)) / series - 1) < 1e-7
+
+
+def test_second_order_growth_within_one_percent_today(growth):
+    # App. growth: the D^n approximation of E errs by < 1% at z = 0
+    D1 = float(growth.D(1.0))
+    dev = abs(float(growth.E(1.0)) / (-3 / 7 * D1 ** 2) - 1)
+    assert 0.001 < dev < 0.01
+
+
+def test_eds_growth_is_exact():
+    g = cosmo.Growth(1.0)
+    for a in (0.02, 0.3, 1.0):
+        assert abs(float(g.D(a)) / a - 1) < 1e-11
+        assert abs(float(g.E(a)) / (-3 / 7 * a * a) - 1) < 1e-10
+        assert abs(g.dEdD(float(g.D(a))) / (-6 / 7 * a) - 1) < 1e-10
+
+
+def _bullfrog_toy_run(steps, D0):
+    """2LPT test trajectory in EdS with the linear toy force along
+    (psi1, psi2) = (e1, e2): X = D e1 + c e2 feels A = X / D^2 - e2, which has
+    X = D e1 + E(D) e2, E = -(3/7) D^2, as an exact solution of the D-time
+    equation of motion dV/dD = (3/2)(A - V/D)."""
+    X = np.array([D0, -3 / 7 * D0 ** 2])
+    V = np.array([1.0, -6 / 7 * D0])
+    for st in steps:
+        X = X + st.tau1 * V
+        A = X * st.s - np.array([0.0, 1.0])
+        V = st.alpha * V + st.beta * A
+        X = X + st.tau2 * V
+    return X, V
+
+
+@pytest.mark.parametrize("a0,a1,n", [(0.02, 1.0, 6), (0.5, 1.0, 1), (0.1, 0.11, 1), (0.02, 1.0, 1),
+                                     (0.05, 0.8, 13)])
+def test_bullfrog_is_2lpt_exact_in_eds(a0, a1, n):
+    # BullFrog aligns the trajectory with 2LPT after every step; in EdS the
+    # 2LPT trajectory is exact for the toy force, so any step size reproduces it
+    steps = cosmo.bullfrog_steps(1.0, a0, a1, n)
+    X, V = _bullfrog_toy_run(steps, a0)
+    assert np.allclose(X, [a1, -3 / 7 * a1 ** 2], rtol=1e-12, atol=1e-15)
+    assert np.allclose(V, [1.0, -6 / 7 * a1], rtol=1e-12, atol=1e-15)
+
+
+def test_bullfrog_zeldovich_consistency_and_schedule():
+    steps = cosmo.bullfrog_steps(0.31, 0.02, 1.0, 10)
+    D0 = cosmo.D_of_a(0.31, 0.02)
+    D1 = cosmo.D_of_a(0.31, 1.0)
+    assert abs(steps[0].D_n - D0) < 1e-15 and abs(steps[-1].D_np1 - D1) < 1e-12
+    for st in steps:
+        # a linear-theory state V = psi, A = psi / D_half stays V = psi
+        assert abs(st.alpha + st.beta / st.D_half - 1) < 1e-13
+        assert abs(st.tau1 - st.tau2) < 1e-13
+        assert abs(st.s * st.D_half ** 2 - 1) < 1e-14
+
+
+def test_bbks_limits_and_sigma8_normalisation():
+    # parity unpinned against the paper (BBKS is not used there): pinned only
+    # by the published formula's limits and an independent quadrature
+    assert abs(float(cosmo.bbks_transfer(1e-7, 0.31, 0.68)) - 1) < 1e-5
+    assert float(cosmo.bbks_transfer(10.0, 0.31, 0.68)) < 1e-3
+    sp = cosmo.bbks_spectrum(0.31, 0.68, 0.965, 0.81)
+    from scipy import integrate
+    f = lambda lnk: math.exp(lnk) ** 3 * float(sp(math.exp(lnk))) * float(
+        cosmo.tophat_window(8 * math.exp(lnk))) ** 2
+    v = sum(integrate.quad(f, lo, lo + 0.5, limit=200)[0]
+            for lo in np.arange(math.log(1e-6), math.log(1e3), 0.5))
+    assert abs(math.sqrt(v / (2 * math.pi ** 2)) / 0.81 - 1) < 1e-6

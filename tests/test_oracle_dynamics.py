@@ -1,0 +1,206 @@
+"""Pins of the oracle's N-body run, NUFFT force, power spectrum and
+store-all adjoint (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import adjoint, cosmo, ics, mesh, nbody, nufft, pk
+from oracle.force import PMConfig
+
+
+def _plane_wave_run(n_g, A_w=0.5, order=3):
+    n_p, box = 32, 100.0
+    cfg = PMConfig(n_p, n_g, box, order=order, deconvolve=False, grad_order=4, lap_order=0)
+    prob = nbody.Problem(cfg, omega_m=1.0, spectrum="powerlaw", a_start=0.02, a_end=1.0, n_steps=6)
+    kw = 2 * math.pi / box
+    q = mesh.lattice(n_p)[0] * (box / n_p)
+    dq = box / n_p
+    psi = np.zeros((3, n_p ** 3))
+    psi[0] = -(A_w / kw) * np.sin(kw * q) / dq
+    out, _ = nbody.run_from(prob, 0.02 * psi, psi)
+    return out, 1.0 * psi, A_w / kw / dq
+
+
+def test_plane_wave_follows_zeldovich_before_shell_crossing():
+    # EdS, D = a; BullFrog is Zel'dovich consistent, so only PM force error
+    # remains, and it must shrink with the mesh.  TSC keeps the lattice's
+    # aliasing error below 1%; CIC errs by a few per cent (discreteness) and
+    # is checked only for convergence
+    errs = []
+    for n_g in (64, 128):
+        out, exact, amp = _plane_wave_run(n_g)
+        errs.append(np.abs(out - exact).max() / amp)
+    assert errs[0] < 0.015 and errs[1] < errs[0]
+    e64 = _plane_wave_run(64, order=2)
+    e128 = _plane_wave_run(128, order=2)
+    c = [np.abs(o - e).max() / a for o, e, a in (e64, e128)]
+    assert c[0] < 0.06 and c[1] < 0.7 * c[0]
+
+
+def test_low_k_power_grows_as_D_squared():
+    cfg = PMConfig(32, 64, 100.0, order=2, deconvolve=False, grad_order=4, lap_order=0)
+    # C1 geometry; the lowest bin grows as D^2 up to a mode-coupling
+    # correction that itself grows with D (0.5% at a = 0.05, 1.2% at 0.1)
+    dev = []
+    for a1 in (0.05, 0.1):
+        prob = nbody.Problem(cfg, omega_m=1.0, spectrum="powerlaw", a_start=0.02, a_end=a1, n_steps=4)
+        w = nbody.white_noise(prob, 54321)
+        psi0, v0, _ = nbody.initial_state(prob, w)
+        psi, _ = nbody.run_from(prob, psi0, v0)
+        p0 = pk.power_spectrum(adjoint.final_density(prob, psi0), 100.0, 4)[1]
+        p1 = pk.power_spectrum(adjoint.final_density(prob, psi), 100.0, 4)[1]
+        dev.append(abs(p1[0] / p0[0] / (a1 / 0.02) ** 2 - 1))
+    assert dev[0] < 0.01 and dev[0] < dev[1] < 0.02
+
+
+def test_reverse_integration_recovers_initial_state():
+    # primal rows of tab. adjoint_dkd undo the forward step (time reversibility)
+    cfg = PMConfig(16, 32, 50.0, order=3, deconvolve=True, grad_order=4, lap_order=0)
+    prob = nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=5)
+    psi0, v0, _ = nbody.initial_state(prob, nbody.white_noise(prob, 11))
+    psi, vel = nbody.run_from(prob, psi0, v0)
+    force = prob.force_fn()
+    for st in reversed(prob.steps()):
+        psi = psi - st.tau2 * vel
+        vel = (vel - st.beta * force(psi, st.s)) / st.alpha
+        psi = psi - st.tau1 * vel
+    assert np.abs(psi - psi0).max() < 1e-9 * np.abs(psi0).max()
+    assert np.abs(vel - v0).max() < 1e-9 * np.abs(v0).max()
+
+
+# ---------------------------------------------------------------- NUFFT ----
+
+def test_nufft_spreading_matches_direct_nudft():
+    n_p, n_f = 8, 16
+    psi = np.random.default_rng(1).normal(0, 0.7, (3, n_p ** 3))
+    A1 = nufft.nudft_force_direct(n_p, n_f, psi, 1.0)
+    A2 = nufft.nufft_force(n_p, n_f, psi, 1.0, 6, 13.8)
+    assert np.linalg.norm(A1 - A2) / np.linalg.norm(A1) < 1.5e-5
+
+
+def test_nufft_uniform_lattice_reduces_to_dft():
+    # particles on the lattice: the NUDFT is the plain DFT of a constant, so
+    # every kept mode but m = 0 vanishes and the force is zero
+    n_p, n_f = 8, 16
+    A = nufft.nufft_force(n_p, n_f, np.zeros((3, n_p ** 3)), 1.0)
+    assert np.abs(A).max() < 1e-12
+
+
+def test_nufft_net_force_and_linear_displacement():
+    n_p, n_f = 8, 16
+    psi = np.random.default_rng(2).normal(0, 0.5, (3, n_p ** 3))
+    A = nufft.nufft_force(n_p, n_f, psi, 1.0)
+    assert np.abs(A.sum(axis=1)).max() < 1e-10 * np.abs(A).sum()
+    # a single low Fourier mode of small displacement: -grad Lap^-1 delta
+    # equals the displacement itself to first order
+    q = mesh.lattice(n_p)
+    eps = 1e-4
+    psi = np.zeros((3, n_p ** 3))
+    psi[1] = eps * np.sin(2 * math.pi * q[1] / n_p)
+    # the direct sums are exact here (the spreading path errs by ~1e-5 of the
+    # total mass per mode, which swamps a 1e-4 perturbation)
+    A = nufft.nudft_force_direct(n_p, n_f, psi, 1.0)
+    assert np.abs(A[1] - psi[1]).max() < 1e-6 * eps
+
+
+def test_es_fixedpoint_spread_matches_float_spread():
+    n_p, n_f = 8, 16
+    psi = np.random.default_rng(3).normal(0, 1.0, (3, n_p ** 3)).astype(np.float32)
+    fx = nufft.deposit_fixedpoint_es(psi, n_p, n_f)
+    fl = nufft._spread_float(mesh.mesh_coords(psi.astype(np.float64), n_p, n_f), n_f, 6, 13.8)
+    assert np.linalg.norm(fx / 2.0 ** 32 - fl) / np.linalg.norm(fl) < 2e-6
+
+
+# ------------------------------------------------------------------ P(k) ---
+
+def test_pk_single_cosine_mode():
+    n, box, amp = 16, 80.0, 0.3
+    m0 = np.array([1, 2, 3])
+    j = np.indices((n, n, n)).reshape(3, -1)
+    delta = amp * np.cos(2 * math.pi * (m0 @ j) / n)
+    kb, p, cnt = pk.power_spectrum(delta, box, 8)
+    b = int(pk.bin_index(np.array([m0 @ m0]))[0])
+    th = 2 * math.pi * m0 / n
+    W = np.prod((np.sin(th / 2) / (th / 2)) ** 2)
+    assert abs(p[b - 1] / (amp ** 2 * box ** 3 / (2 * W * W * cnt[b - 1])) - 1) < 1e-12
+    others = np.delete(p, b - 1)
+    assert np.all(np.abs(others) < 1e-20)
+
+
+def test_pk_bin_counts_match_brute_force_full_grid():
+    n = 12
+    m = np.fft.fftfreq(n, 1.0 / n)
+    mx, my, mz = np.meshgrid(m, m, m, indexing="ij")
+    t = 4 * (mx ** 2 + my ** 2 + mz ** 2)
+    _, _, cnt = pk.power_spectrum(np.zeros(n ** 3) + 1e-3 * np.arange(n ** 3) % 1, 1.0, n // 2)
+    # modes with m_z = -n/2 are folded onto +n/2 in the half spectrum
+    for b in range(1, n // 2 + 1):
+        brute = np.sum(((2 * b - 1) ** 2 <= t) & (t < (2 * b + 1) ** 2))
+        assert cnt[b - 1] == brute
+
+
+def test_pk_white_noise_level():
+    n, box = 32, 100.0
+    rng = np.random.default_rng(4)
+    ps = np.mean([pk.power_spectrum(rng.normal(size=n ** 3), box, 16, deconvolve_cic=False)[1]
+                  for _ in range(4)], axis=0)
+    assert abs(np.sum(ps[4:]) / (12 * box ** 3 / n ** 3) - 1) < 0.03
+
+
+# --------------------------------------------------------------- adjoint ---
+
+def _small_problem():
+    cfg = PMConfig(8, 16, 40.0, order=2, deconvolve=False, grad_order=4, lap_order=0)
+    return nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=0.9)
+
+
+def test_force_vjp_matches_finite_differences():
+    prob = _small_problem()
+    cfg = prob.pm
+    rng = np.random.default_rng(5)
+    psi = rng.normal(0, 1.0, (3, cfg.N))
+    u = rng.normal(size=(3, cfg.N))
+    v = rng.normal(size=(3, cfg.N))
+    jt = adjoint.force_vjp(cfg, psi, 2.0, u)
+    eps = 1e-6
+    fd = (np.sum(u * prob.force_fn()(psi + eps * v, 2.0))
+          - np.sum(u * prob.force_fn()(psi - eps * v, 2.0))) / (2 * eps)
+    assert abs(np.sum(jt * v) - fd) < 1e-6 * abs(fd)
+
+
+def test_ic_vjp_is_the_transpose():
+    prob = _small_problem()
+    n = prob.pm.n_p
+    rng = np.random.default_rng(6)
+    w = rng.normal(size=(n, n, n))
+    pb = rng.normal(size=(3, n ** 3))
+    psi = ics.zeldovich_psi(w, prob.pm.box, prob.spectrum_fn(), prob.D_ref())
+    lhs = np.sum(psi * pb)
+    rhs = np.sum(w.reshape(-1) * adjoint.ic_vjp(prob, pb).reshape(-1))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_full_gradient_matches_finite_differences():
+    prob = _small_problem()
+    n = prob.pm.n_p
+    rng = np.random.default_rng(7)
+    w = nbody.white_noise(prob, 3).astype(np.float64)
+    target = rng.normal(size=prob.pm.n_g ** 3)
+
+    def loss_of(w_, prob_=prob):
+        psi0, v0, _ = nbody.initial_state(prob_, w_.reshape(n, n, n))
+        psi, _ = nbody.run_from(prob_, psi0, v0)
+        return np.sum((adjoint.final_density(prob_, psi) - target) ** 2)
+
+    wbar, dsig, _ = adjoint.gradient(prob, w, lambda d: 2 * (d - target))
+    for k in range(3):
+        dirn = rng.normal(size=n ** 3)
+        dirn /= np.linalg.norm(dirn)
+        eps = 1e-6
+        fd = (loss_of(w.reshape(-1) + eps * dirn) - loss_of(w.reshape(-1) - eps * dirn)) / (2 * eps)
+        assert abs(np.dot(wbar, dirn) - fd) < 1e-5 * abs(fd) + 1e-9
+    p2 = nbody.Problem(prob.pm, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=0.9 + 1e-6)
+    p3 = nbody.Problem(prob.pm, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=0.9 - 1e-6)
+    fd = (loss_of(w.reshape(-1), p2) - loss_of(w.reshape(-1), p3)) / 2e-6
+    assert abs(dsig - fd) < 1e-5 * abs(fd)

@@ -1,0 +1,152 @@
+"""Pins of the oracle's FFT convention and PM force: stencils vs Fourier
+kernels, convergence order, symmetry invariants, Ewald pair force and a plane
+wave (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erfc
+
+from oracle import force, mesh
+from oracle.force import PMConfig
+
+# real-space stencils printed in tab. derivative_kernels (offsets -h..h)
+GRAD_STENCILS = {
+    2: np.array([-1, 0, 1]) / 2.0,
+    4: np.array([1, -8, 0, 8, -1]) / 12.0,
+    6: np.array([-1, 9, -45, 0, 45, -9, 1]) / 60.0,
+}
+LAP_STENCILS = {
+    2: np.array([1, -2, 1]) / 1.0,
+    4: np.array([-1, 16, -30, 16, -1]) / 12.0,
+    6: np.array([2, -27, 270, -490, 270, -27, 2]) / 180.0,
+}
+
+
+def test_fft_matches_naive_dft_8cubed():
+    n = 8
+    f = np.random.default_rng(0).normal(size=(n, n, n))
+    j = np.arange(n)
+    E = np.exp(-2j * np.pi * np.outer(j, j) / n)
+    naive = np.einsum("ax,by,cz,xyz->abc", E, E, E, f)
+    assert np.abs(np.fft.rfftn(f) - naive[:, :, : n // 2 + 1]).max() < 1e-12
+    assert np.abs(np.fft.irfftn(np.fft.rfftn(f), s=(n, n, n), axes=(0, 1, 2)) - f).max() < 1e-14
+
+
+def _stencil_multiplier(stencil, n):
+    """Apply sum_s c_s f(x + s) by rolls and read off the Fourier multiplier."""
+    f = np.random.default_rng(1).normal(size=n)
+    h = len(stencil) // 2
+    g = sum(c * np.roll(f, -s) for s, c in zip(range(-h, h + 1), stencil))
+    return np.fft.fft(g) / np.fft.fft(f), 2 * np.pi * np.fft.fftfreq(n)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_fourier_kernels_equal_printed_stencils(order):
+    mg, th = _stencil_multiplier(GRAD_STENCILS[order], 32)
+    assert np.allclose(force.grad_kernel(th, order), mg, atol=1e-12)
+    ml, th = _stencil_multiplier(LAP_STENCILS[order], 32)
+    assert np.allclose(force.lap_kernel_1d(th, order), ml, atol=1e-12)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_fd_kernels_converge_at_their_order(order):
+    errs = []
+    for th in (0.2, 0.1):
+        eg = abs(force.grad_kernel(th, order) / (1j * th) - 1)
+        el = abs(force.lap_kernel_1d(th, order) / (-th * th) - 1)
+        errs.append((eg, el))
+    assert abs(math.log2(errs[0][0] / errs[1][0]) - order) < 0.1
+    assert abs(math.log2(errs[0][1] / errs[1][1]) - order) < 0.1
+
+
+CONFIGS = [
+    PMConfig(8, 16, 20.0, order=2, deconvolve=False, grad_order=4, lap_order=0),
+    PMConfig(8, 16, 20.0, order=3, deconvolve=True, grad_order=4, lap_order=0),
+    PMConfig(8, 16, 20.0, order=2, deconvolve=False, grad_order=0, lap_order=0),
+    PMConfig(8, 16, 20.0, order=3, deconvolve=False, grad_order=2, lap_order=2),
+]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"o{c.order}d{int(c.deconvolve)}g{c.grad_order}l{c.lap_order}")
+def test_lone_particle_feels_no_self_force(cfg):
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        u = rng.uniform(0, cfg.n_g, (3, 1))
+        a = force.pm_force_u(cfg, u, 1.0)
+        # reference scale: the force between two particles one cell apart
+        pair = force.pm_force_u(cfg, np.concatenate([u, u + np.array([[1.0], [0], [0]])], 1), 1.0)
+        assert np.abs(a).max() < 1e-12 * np.abs(pair).max()
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"o{c.order}d{int(c.deconvolve)}g{c.grad_order}l{c.lap_order}")
+def test_net_force_vanishes(cfg):
+    psi = np.random.default_rng(4).normal(0, 2.0, (3, cfg.N))
+    A = force.pm_force(cfg, psi, 1.0)
+    assert np.abs(A.sum(axis=1)).max() < 1e-12 * np.abs(A).sum()
+
+
+def test_unperturbed_lattice_feels_no_force():
+    cfg = CONFIGS[1]
+    A = force.pm_force(cfg, np.zeros((3, cfg.N)), 1.0)
+    assert np.abs(A).max() < 1e-13
+
+
+def ewald_field(r, box, alpha=None, nmax=3, kmax=8):
+    """E = -grad sum_n 1/|r + nL| with a neutralising background (Ewald)."""
+    alpha = alpha or 5.0 / box
+    E = np.zeros(3)
+    rng_ = range(-nmax, nmax + 1)
+    for nx in rng_:
+        for ny in rng_:
+            for nz in rng_:
+                rn = r + box * np.array([nx, ny, nz])
+                d = np.linalg.norm(rn)
+                E += rn / d ** 3 * (erfc(alpha * d) + 2 * alpha * d / math.sqrt(math.pi) * math.exp(-(alpha * d) ** 2))
+    kr = range(-kmax, kmax + 1)
+    for mx in kr:
+        for my in kr:
+            for mz in kr:
+                if mx == my == mz == 0:
+                    continue
+                k = 2 * math.pi / box * np.array([mx, my, mz])
+                k2 = k @ k
+                E += 4 * math.pi / box ** 3 * k / k2 * math.exp(-k2 / (4 * alpha ** 2)) * math.sin(k @ r)
+    return E
+
+
+def test_pair_force_matches_ewald_beyond_a_few_cells():
+    # a particle of mass L^3/N (contrast units) at distance r: the periodic
+    # point-mass force -(M / 4 pi) E_ewald, in mesh units and converted to dq
+    cfg = PMConfig(16, 32, 32.0, order=2, deconvolve=False, grad_order=4, lap_order=0)
+    rng = np.random.default_rng(5)
+    M = cfg.n_g ** 3 / cfg.N
+    rel = {}
+    for r in (4.0, 6.0, 8.0):
+        errs = []
+        for _ in range(16):
+            d = rng.normal(size=3)
+            d *= r / np.linalg.norm(d)
+            u1 = rng.uniform(0, cfg.n_g, 3)
+            u = np.stack([u1, u1 + d], axis=1)
+            a = force.pm_force_u(cfg, u, 1.0)[:, 0]
+            ref = -(M / (4 * math.pi)) * ewald_field(-d, float(cfg.n_g)) / cfg.r
+            errs.append(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+        rel[r] = math.sqrt(np.mean(np.square(errs)))
+    assert rel[4.0] < 0.03 and rel[6.0] < 0.015 and rel[8.0] < 0.01, rel
+
+
+def test_plane_wave_force_converges_at_fourth_order():
+    # delta = eps cos(theta x) on the mesh: exact A = -eps sin(theta x)/theta
+    # (mesh units) times s / r; the FD4 gradient errs by O(theta^4)
+    errs = []
+    for n in (16, 32):
+        cfg = PMConfig(n // 2, n, 10.0, order=2, deconvolve=False, grad_order=4, lap_order=0)
+        th = 2 * math.pi * 2 / n
+        x = np.indices((n, n, n))[0].reshape(-1)
+        delta = 0.01 * np.cos(th * x)
+        g = force.force_meshes(cfg, delta, 1.0)
+        exact = -0.01 * np.sin(th * x) / th / cfg.r
+        assert np.abs(g[1]).max() < 1e-15 and np.abs(g[2]).max() < 1e-15
+        errs.append(np.abs(g[0] - exact).max() / np.abs(exact).max())
+    assert 14 < errs[0] / errs[1] < 18
