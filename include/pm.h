@@ -1,0 +1,200 @@
+/* pm.h - C ABI of the MI355X particle-mesh hot path (libpm.so).
+ *
+ * Differentiable particle-mesh N-body step of DISCO-DJ II (arXiv:2510.05206):
+ * Zel'dovich initial conditions, BullFrog drift-kick-drift steps with a PM
+ * (CIC/TSC) or exponential-of-semicircle NUFFT force, the binned power
+ * spectrum, and the adjoint (reverse-in-time) gradient of a loss on the final
+ * density with respect to the white-noise field and sigma8.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Memory.   The library never allocates device memory.  The caller passes a
+ *           device workspace (pm_bind) of at least pm_workspace_bytes() bytes
+ *           and owns every device buffer; the context keeps raw pointers only
+ *           between pm_bind and pm_destroy.  Host arrays are copied during
+ *           the call.  Device pointers must be 256-byte aligned.
+ * Streams.  All device work is enqueued on the stream given to pm_bind and is
+ *           asynchronous; calls return after enqueueing.  pm_power_spectrum
+ *           and pm_adjoint write device outputs only.
+ * Errors.   Every call returns a pm_status; pm_last_error(ctx) gives a message.
+ *           Arguments are validated before any launch, so a failed call leaves
+ *           the state unchanged.  Launch failures return PM_EHIP.  Calls made
+ *           out of order (for example pm_adjoint before pm_run) return
+ *           PM_ESTATE.  Nothing aborts and no C++ exception crosses the ABI.
+ * Threads.  A context is not thread-safe; distinct contexts on distinct
+ *           streams are independent.
+ * Batch.    A context holds B same-shape slots ("batch").  Per-slot arrays
+ *           ([B]...) are laid out slot-major.  Slots share the cosmology and
+ *           the mesh, and each has its own seed, sigma8 and number of steps.
+ * Units.    Particle state is exchanged in lattice units: the displacement
+ *           Psi from the Lagrangian lattice point q_j = j L/n_p in units of
+ *           dq = L/n_p, and V = dPsi/dD in dq per unit of the growth factor D
+ *           (D ~ a at early times).  Layout [B][3][N], N = n_p^3, lattice
+ *           index j = (jx n_p + jy) n_p + jz.  Meshes are [B][n_g][n_g][n_g]
+ *           with z fastest.
+ * Determinism.  The forward deposit accumulates int64 fixed point (2^32 per
+ *           particle), so forward results are bit-identical run to run and
+ *           slot to slot.  The adjoint's cotangent scatter uses FP32 atomics.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pm_ctx pm_ctx;
+
+typedef enum {
+  PM_OK = 0,
+  PM_EINVAL = -1,       /* invalid argument or configuration                   */
+  PM_ENOMEM = -2,       /* workspace smaller than pm_workspace_bytes()         */
+  PM_EHIP = -3,         /* a HIP call or kernel launch failed                  */
+  PM_ESTATE = -4,       /* call out of order (e.g. step before init_ics)       */
+  PM_EUNSUPPORTED = -5  /* valid but not implemented combination               */
+} pm_status;
+
+enum { PM_FORCE_PM = 0, PM_FORCE_NUFFT = 1 };
+enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
+
+/* Run configuration (Sec. "Validation and performance", tab. default_parameters
+ * for the knobs; Sec. "Time stepping" for the schedule).
+ *   n_p            particles per dimension (power of two, 4..1024)
+ *   n_g            PM mesh per dimension; NUFFT: fine grid n_f = sigma n_p.
+ *                  n_g / n_p must be a power of two (1, 2 or 4)
+ *   box            L in Mpc/h
+ *   omega_m, h, n_s, sigma8   flat LCDM (omega_m = 1 is EdS, D = a)
+ *   spectrum       PM_SPEC_BBKS: P = A k^n_s T_BBKS^2 normalised to sigma8;
+ *                  PM_SPEC_POWERLAW: P = A k^-2 exp(-(k/k_c)^2), k_c half the
+ *                  particle Nyquist wavenumber, A from pl_rms_cells (expected
+ *                  3D rms displacement at a_start in PM-mesh cells)
+ *   a_start, a_end, n_steps   uniform steps in D between D(a_start), D(a_end)
+ *   force          PM_FORCE_PM or PM_FORCE_NUFFT
+ *   mak            2 = CIC, 3 = TSC (PM force; the final density and P(k) are
+ *                  always CIC)
+ *   deconvolve     divide the PM multiplier by the squared window
+ *   grad_order     0 exact i k (NUFFT only), 2/4/6 finite differences (PM)
+ *   lap_order      0 exact -k^2, 2/4/6 finite differences
+ *   es_width, es_beta   NUFFT exponential-of-semicircle kernel (width 6)
+ *   batch          number of same-shape slots B >= 1
+ */
+typedef struct {
+  int32_t n_p, n_g;
+  double box;
+  double omega_m, h, n_s, sigma8;
+  int32_t spectrum;
+  double pl_rms_cells;
+  double a_start, a_end;
+  int32_t n_steps;
+  int32_t force, mak, deconvolve, grad_order, lap_order;
+  int32_t es_width;
+  double es_beta;
+  int32_t batch;
+} pm_config;
+
+/* Lifecycle ------------------------------------------------------------- */
+
+/* Validate cfg and build the host tables in FP64 (growth functions, BullFrog
+ * coefficients, spectrum normalisation, FFT twiddles, Fourier multipliers).
+ * Host only; *out receives the context, or NULL on error. */
+pm_status pm_create(const pm_config* cfg, pm_ctx** out);
+
+/* Device workspace needed by this context: particle state for B slots plus
+ * one set of meshes per slot.  with_adjoint != 0 adds the cotangent state
+ * and the adjoint meshes.  This number is what admission control uses. */
+size_t pm_workspace_bytes(const pm_ctx* ctx, int32_t with_adjoint);
+
+/* Attach a device workspace (256-byte aligned, owned by the caller) and a
+ * hipStream_t (NULL = default stream), upload the tables (asynchronously on
+ * that stream).  with_adjoint must match the size passed. */
+pm_status pm_bind(pm_ctx* ctx, void* workspace, size_t bytes, int32_t with_adjoint,
+                  void* hip_stream);
+
+pm_status pm_destroy(pm_ctx* ctx);
+
+/* Last error message of this context (never NULL; "" if none). */
+const char* pm_last_error(const pm_ctx* ctx);
+
+/* Host-side schedule of one slot: n_steps rows of 8 doubles
+ * (D_n, D_{n+1/2}, D_{n+1}, alpha, beta, tau1, tau2, s = 1/D_{n+1/2}^2), the
+ * BullFrog coefficients of Sec. "Time stepping" computed in FP64. */
+pm_status pm_schedule(const pm_ctx* ctx, int32_t slot, double* out);
+
+/* out[0] = D(a_start), out[1] = D(1) (D ~ a normalisation), out[2] = the
+ * linear-spectrum amplitude A (P = A k^n_s T^2, or A k^-2 exp(-(k/k_c)^2)). */
+pm_status pm_describe(const pm_ctx* ctx, double* out);
+
+/* Change the per-slot number of steps (1..n_steps_max of pm_create) and
+ * sigma8 before pm_init_ics; NULL keeps the current values. */
+pm_status pm_set_slot_params(pm_ctx* ctx, const int32_t* n_steps, const double* sigma8);
+
+/* The spec calls -------------------------------------------------- */
+
+/* Zel'dovich initial conditions (Sec. "Lagrangian perturbation theory",
+ * first order; Sec. "Time stepping" for V = dX/dD):
+ *   w ~ N(0,1) on the particle lattice from Philox-4x32-10 keyed by seeds[b]
+ *   (or copied from w_in, device [B][N], when non-NULL),
+ *   psi_c = IDFT( i k_c / (k^2 D(1)) sqrt(P(k) n_p^3 / L^3) DFT(w) ), with
+ *   k = 0, the Nyquist plane of component c and |k| > k_Nyq zeroed,
+ *   Psi = D(a_start) psi, V = psi.
+ * seeds: host [B].  w_out: optional device [B][N] copy of w. */
+pm_status pm_init_ics(pm_ctx* ctx, const uint64_t* seeds, const float* w_in, float* w_out);
+
+/* One BullFrog drift-kick-drift step (eq. dkd) per slot:
+ *   X += tau1 V;  V = alpha V + beta A(X);  X += tau2 V
+ * step_index: host [B], the step each slot takes (< its n_steps); a negative
+ * entry leaves that slot idle. */
+pm_status pm_step(pm_ctx* ctx, const int32_t* step_index);
+
+/* All n_steps steps for every slot (drifts of consecutive steps merged). */
+pm_status pm_run(pm_ctx* ctx);
+
+/* Adjoint of the whole run (Sec. "Adjoint method", tab. adjoint_dkd): from
+ * the final state, integrate primal and cotangents backwards in time with
+ * memory independent of n_steps, then pull back through the initial
+ * conditions.  dL_ddelta: device [B][n_g^3] cotangent of the final CIC
+ * density contrast.  Outputs: dL_dw device [B][N], dL_dsigma8 device [B]
+ * (double).  Leaves the particle state at the initial conditions. */
+pm_status pm_adjoint(pm_ctx* ctx, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8);
+
+/* Binned power spectrum of the CIC density of the current positions:
+ * P(k_b) = (L^3/n_g^6) sum_{m in b} w_m |delta_m|^2 / W^2 / sum w_m, bin b
+ * (1-based) holding (2b-1)^2 <= 4|m|^2 < (2b+1)^2, W the CIC window when
+ * deconvolve_cic != 0.  FP64 sums in a fixed order (bit-reproducible).
+ * Outputs are device [B][n_bins] arrays (k_mean in h/Mpc, pk in (Mpc/h)^3,
+ * n_modes = sum of half-spectrum multiplicities). */
+pm_status pm_power_spectrum(pm_ctx* ctx, int32_t n_bins, int32_t deconvolve_cic,
+                            double* k_mean, double* pk, int64_t* n_modes);
+
+/* State access and single-kernel entry points (tests, loss, resume) ------- */
+
+/* Final CIC density contrast delta = m n_g^3/N - 1 of the current positions
+ * into delta_out (device [B][n_g^3] float), and optionally the raw int64
+ * fixed-point mass mesh (2^32 per particle) into fixed_out. */
+pm_status pm_density(pm_ctx* ctx, float* delta_out, int64_t* fixed_out);
+
+/* Copy the particle state out of / into the context (device [B][3][N]). */
+pm_status pm_get_state(pm_ctx* ctx, float* disp, float* vel);
+pm_status pm_set_state(pm_ctx* ctx, const float* disp, const float* vel);
+
+/* Deposit the given displacements (device [B][3][N]) with kernel order
+ * mak (2 CIC, 3 TSC, 6 = ES of the NUFFT grid) into the int64 mesh
+ * mesh_out (device [B][n^3], n = n_g).  Bit-exact fixed-point spec. */
+pm_status pm_deposit(pm_ctx* ctx, const float* disp, int32_t mak, int64_t* mesh_out);
+
+/* PM (or NUFFT) acceleration A(X) at the given displacements for the
+ * midpoint normalisation s = 1/D^2 (device in [B][3][N], out [B][3][N]). */
+pm_status pm_force(pm_ctx* ctx, const float* disp, double s, float* acc_out);
+
+/* 3D FFT of a real mesh (n = n_g): inverse == 0: real [B][n^3] -> half
+ * spectrum [B][n][n][n/2+1] complex64 (unnormalised, exp(-i k x));
+ * inverse != 0: half spectrum -> real, unnormalised (exp(+i k x)). */
+pm_status pm_fft(pm_ctx* ctx, const void* in, void* out, int32_t inverse);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PM_H */

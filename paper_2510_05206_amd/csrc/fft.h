@@ -1,0 +1,52 @@
+// Launch interface of the FFT passes (fft.hip).
+#pragma once
+#include "pm_internal.h"
+
+namespace pm {
+
+enum { SRC_I64 = 0, SRC_F32 = 1 };
+enum { DST_F32 = 0, DST_IC = 1 };
+enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4 };
+
+// z-row pass: real rows of n <-> half-spectrum rows of n/2+1
+struct RowLaunch {
+  int n;                 // row length of the real mesh
+  long long n_rows;      // rows per slot (n^2)
+  int batch;
+  bool inverse;
+  int src_mode, dst_mode;
+  const void* src;
+  long long src_stride;  // elements between slots
+  void* dst;
+  long long dst_stride;
+  void* dst2;            // DST_IC: displacement output
+  const float2* tw;
+  int tws_half, tws_full;  // twiddle strides for the n/2 FFT and for exp(-2 pi i k/n)
+  double scale, shift, scale2;
+  hipStream_t stream;
+};
+
+// strided complex pass along y (axis 1) or x (axis 0) of a half spectrum
+struct ColArgs {
+  float2* data;        // in-place spectrum (MODE_COMBINE_IC: output)
+  const float2* src3;  // MODE_COMBINE_IC: 3 input spectra, spaced by comp_stride
+  float2* dst3;        // MODE_IC_C: output spectrum
+  long long slot_stride, comp_stride;
+  int n, nh, axis;
+  const float2* tw;
+  int tws;             // Lmax / n
+  // PM multiplier H = coef / ((lap[ix]+lap[iy]+lap[iz]) win2[ix] win2[iy] win2[iz]), 0 at k = 0
+  const float* lap;
+  const float* win2;
+  float coef[kMaxBatch];
+  // IC multiplier h_c = i m_c amp[|m|^2] fac
+  const float* amp;
+  float fac[kMaxBatch];
+  int comp;
+  unsigned long long active;  // bit b set: slot b takes part
+};
+
+hipError_t fft_rows(const RowLaunch& r);
+hipError_t fft_cols(const ColArgs& a, int mode, int batch, hipStream_t s);
+
+}  // namespace pm

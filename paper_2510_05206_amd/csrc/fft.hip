@@ -1,0 +1,394 @@
+// 3D real FFT for cubic power-of-two meshes, written for gfx950 (64-wide
+// waves, 160 KB LDS per CU).
+//
+// Layout: real mesh [n][n][n] (z fastest); half spectrum [n][n][n/2+1] of
+// float2 (modes m_x, m_y in FFT order, m_z = 0..n/2).  The forward transform
+// is sum_j f_j exp(-2 pi i m.j/n), the inverse sum_m F_m exp(+2 pi i m.j/n),
+// both unnormalised.  A 3D transform is three HBM passes:
+//   z rows   real <-> complex via a half-length complex FFT (the two real
+//            halves packed as one complex row), whole rows staged in LDS;
+//   y and x  strided complex passes over tiles of C consecutive z columns
+//            (C float2 = 128 B contiguous per row at C = 16), whole lines in
+//            LDS.
+// Each line FFT is a Stockham autosort radix-4 (plus one radix-2 stage when
+// log2 L is odd) entirely in LDS; twiddles come from one table
+// tw[t] = exp(-2 pi i t / Lmax) built in FP64 on the host.
+// The PM multiplier (Green's function, deconvolution, normalisation) is fused
+// into the x pass: forward x FFT, multiply, inverse x FFT, one HBM round trip
+// (Sec. "Force evaluation"; the Poisson solve in Fourier space).
+#include "fft.h"
+
+namespace pm {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Stockham radix-4/2 FFT of C lines of length L in LDS.
+// LINE_FAST: element (t, l) at buf[t*C + l] (strided passes), else at
+// buf[l*(L+1) + t] (row passes).  tw[e*tws] = exp(-2 pi i e / L).
+template <int L, int C, bool LINE_FAST, int NT>
+__device__ __forceinline__ void lds_fft(float2* __restrict__ buf, const float2* __restrict__ tw,
+                                        int tws, bool inverse) {
+  const int tid = threadIdx.x;
+  auto at = [](int t, int l) { return LINE_FAST ? t * C + l : l * (L + 1) + t; };
+  int Ns = 1;
+  if constexpr (L >= 4) {
+    constexpr int B4 = (L / 4) * C;
+    constexpr int PT = (B4 + NT - 1) / NT;
+#pragma unroll 1
+    for (; Ns * 4 <= L; Ns *= 4) {
+      float2 v[PT][4];
+#pragma unroll
+      for (int p = 0; p < PT; ++p) {
+        int b = tid + p * NT;
+        if (b < B4) {
+          int j = LINE_FAST ? b / C : b % (L / 4);
+          int l = LINE_FAST ? b % C : b / (L / 4);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[p][r] = buf[at(j + r * (L / 4), l)];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < PT; ++p) {
+        int b = tid + p * NT;
+        if (b < B4) {
+          int j = LINE_FAST ? b / C : b % (L / 4);
+          int l = LINE_FAST ? b % C : b / (L / 4);
+          int k = j & (Ns - 1);
+          int e = k * (L / (4 * Ns));
+#pragma unroll
+          for (int r = 1; r < 4; ++r) {
+            float2 w = tw[(r * e) * tws];
+            if (inverse) w.y = -w.y;
+            v[p][r] = cmul(v[p][r], w);
+          }
+          float2 t0 = make_float2(v[p][0].x + v[p][2].x, v[p][0].y + v[p][2].y);
+          float2 t1 = make_float2(v[p][0].x - v[p][2].x, v[p][0].y - v[p][2].y);
+          float2 t2 = make_float2(v[p][1].x + v[p][3].x, v[p][1].y + v[p][3].y);
+          float2 t3 = make_float2(v[p][1].x - v[p][3].x, v[p][1].y - v[p][3].y);
+          // forward: y1 = t1 - i t3, y3 = t1 + i t3 (inverse swaps them)
+          float2 m3 = inverse ? make_float2(-t3.y, t3.x) : make_float2(t3.y, -t3.x);
+          int base = (j - k) * 4 + k;
+          buf[at(base, l)] = make_float2(t0.x + t2.x, t0.y + t2.y);
+          buf[at(base + Ns, l)] = make_float2(t1.x + m3.x, t1.y + m3.y);
+          buf[at(base + 2 * Ns, l)] = make_float2(t0.x - t2.x, t0.y - t2.y);
+          buf[at(base + 3 * Ns, l)] = make_float2(t1.x - m3.x, t1.y - m3.y);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (Ns < L) {  // one radix-2 stage
+    constexpr int B2 = (L / 2) * C;
+    constexpr int PT = (B2 + NT - 1) / NT;
+    float2 v[PT][2];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      int b = tid + p * NT;
+      if (b < B2) {
+        int j = LINE_FAST ? b / C : b % (L / 2);
+        int l = LINE_FAST ? b % C : b / (L / 2);
+        v[p][0] = buf[at(j, l)];
+        v[p][1] = buf[at(j + L / 2, l)];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      int b = tid + p * NT;
+      if (b < B2) {
+        int j = LINE_FAST ? b / C : b % (L / 2);
+        int l = LINE_FAST ? b % C : b / (L / 2);
+        int k = j & (Ns - 1);
+        float2 w = tw[(k * (L / (2 * Ns))) * tws];
+        if (inverse) w.y = -w.y;
+        float2 a1 = cmul(v[p][1], w);
+        int base = (j - k) * 2 + k;
+        buf[at(base, l)] = make_float2(v[p][0].x + a1.x, v[p][0].y + a1.y);
+        buf[at(base + Ns, l)] = make_float2(v[p][0].x - a1.x, v[p][0].y - a1.y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ row passes
+
+// Rows per block so that a tile holds about 4096 complex values.
+template <int L>
+constexpr int rows_per_block() { return L >= 512 ? 8 : (4096 / L > 64 ? 64 : 4096 / L); }
+
+// Real rows -> half-spectrum rows.  SRC selects the input conversion:
+//   SRC_I64:  rho = (double)m * scale - shift   (int64 fixed-point mass)
+//   SRC_F32:  f * (float)scale                   (float mesh)
+template <int L, int SRC>
+__global__ void __launch_bounds__(256) k_r2c_rows(const void* __restrict__ src, long long src_stride,
+                                                  float2* __restrict__ dst, long long dst_stride,
+                                                  int n_rows, const float2* __restrict__ tw,
+                                                  int tws_half, int tws_full, double scale,
+                                                  double shift) {
+  constexpr int R = rows_per_block<L>();
+  constexpr int n = 2 * L;
+  __shared__ float2 buf[R * (L + 1)];
+  const int slot = blockIdx.y;
+  const long long row0 = (long long)blockIdx.x * R;
+  float* fb = reinterpret_cast<float*>(buf);
+  for (int e = threadIdx.x; e < R * n; e += 256) {
+    int r = e / n, c = e - r * n;
+    long long row = row0 + r;
+    float v = 0.f;
+    if (row < n_rows) {
+      long long gi = slot * src_stride + row * n + c;
+      if constexpr (SRC == SRC_I64)
+        v = (float)((double)reinterpret_cast<const long long*>(src)[gi] * scale - shift);
+      else
+        v = reinterpret_cast<const float*>(src)[gi] * (float)scale;
+    }
+    fb[2 * (r * (L + 1)) + c] = v;
+  }
+  __syncthreads();
+  lds_fft<L, R, false, 256>(buf, tw, tws_half, false);
+  // unpack: X[k] = (Z[k] + conj Z[L-k])/2 + w^k (Z[k] - conj Z[L-k])/(2i), pairs in place
+  for (int e = threadIdx.x; e < R * (L / 2 + 1); e += 256) {
+    int r = e / (L / 2 + 1), k = e - r * (L / 2 + 1);
+    float2* row = buf + r * (L + 1);
+    int kk = (L - k) & (L - 1);
+    float2 zk = row[k], zm = row[kk];
+    float2 fe = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    float2 fo = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));  // (zk - conj zm)/(2i)
+    float2 w = tw[k * tws_full];
+    float2 wf = cmul(w, fo);
+    float2 xk = make_float2(fe.x + wf.x, fe.y + wf.y);
+    // the partner L-k uses conj symmetry: Fe(L-k) = conj Fe(k), Fo(L-k) = conj Fo(k)
+    float2 w2 = tw[(L - k) * tws_full];
+    float2 wf2 = cmul(w2, make_float2(fo.x, -fo.y));
+    float2 xm = make_float2(fe.x + wf2.x, -fe.y + wf2.y);
+    if (k == 0) {
+      row[0] = make_float2(zk.x + zk.y, 0.f);
+      row[L] = make_float2(zk.x - zk.y, 0.f);
+    } else {
+      row[k] = xk;
+      if (kk != k) row[kk] = xm;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
+    int r = e / (L + 1), k = e - r * (L + 1);
+    long long row = row0 + r;
+    if (row < n_rows) dst[slot * dst_stride + row * (L + 1) + k] = buf[e];
+  }
+}
+
+// Half-spectrum rows -> real rows (unnormalised inverse: n x).  DST_F32
+// writes the real row scaled by `scale`; DST_IC writes psi = scale * x into
+// vel[c] and D0 * psi into disp[c] (Zel'dovich initial state).
+template <int L, int DST>
+__global__ void __launch_bounds__(256) k_c2r_rows(const float2* __restrict__ src, long long src_stride,
+                                                  float* __restrict__ dst, long long dst_stride,
+                                                  float* __restrict__ dst2, int n_rows,
+                                                  const float2* __restrict__ tw, int tws_half,
+                                                  int tws_full, float scale, float scale2) {
+  constexpr int R = rows_per_block<L>();
+  constexpr int n = 2 * L;
+  __shared__ float2 buf[R * (L + 1)];
+  const int slot = blockIdx.y;
+  const long long row0 = (long long)blockIdx.x * R;
+  for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
+    int r = e / (L + 1), k = e - r * (L + 1);
+    long long row = row0 + r;
+    buf[e] = row < n_rows ? src[slot * src_stride + row * (L + 1) + k] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  // pack: Z[k] = (X[k] + conj X[L-k]) + i e^{+2 pi i k/n} (X[k] - conj X[L-k])
+  for (int e = threadIdx.x; e < R * (L / 2 + 1); e += 256) {
+    int r = e / (L / 2 + 1), k = e - r * (L / 2 + 1);
+    float2* row = buf + r * (L + 1);
+    float2 xk = row[k], xm = row[L - k];
+    float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);   // X[k] + conj X[L-k]
+    float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);   // X[k] - conj X[L-k]
+    float2 w = tw[k * tws_full];
+    w.y = -w.y;                                          // e^{+2 pi i k / n}
+    float2 wd = cmul(w, d);
+    float2 zk = make_float2(a.x - wd.y, a.y + wd.x);     // a + i wd
+    // partner L-k: a' = conj a, d' = -conj d, w' = e^{+2 pi i (L-k)/n}
+    float2 w2 = tw[(L - k) * tws_full];
+    w2.y = -w2.y;
+    float2 wd2 = cmul(w2, make_float2(-d.x, d.y));
+    float2 zm = make_float2(a.x - wd2.y, -a.y + wd2.x);
+    // pairs (k, L-k) are disjoint across threads: read-then-write is race free
+    if (k < L) row[k] = zk;
+    if (L - k != k && L - k < L) row[L - k] = zm;
+  }
+  __syncthreads();
+  lds_fft<L, R, false, 256>(buf, tw, tws_half, true);
+  const float* fb = reinterpret_cast<const float*>(buf);
+  for (int e = threadIdx.x; e < R * n; e += 256) {
+    int r = e / n, c = e - r * n;
+    long long row = row0 + r;
+    if (row < n_rows) {
+      float v = fb[2 * (r * (L + 1)) + c];
+      long long gi = slot * dst_stride + row * n + c;
+      if constexpr (DST == DST_F32) {
+        dst[gi] = v * scale;
+      } else {
+        float psi = v * scale;
+        dst[gi] = psi;
+        dst2[gi] = psi * scale2;
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------- column passes
+
+__device__ __forceinline__ int signed_mode(int i, int n) { return i < n / 2 ? i : i - n; }
+
+template <int L, int C, int MODE>
+__global__ void __launch_bounds__(256) k_cols(ColArgs a) {
+  __shared__ float2 buf[L * C];
+  const int slot = blockIdx.z;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int outer = blockIdx.y;          // x for the y pass, y for the x pass
+  const int z0 = blockIdx.x * C;
+  const long long stride_t = a.axis == 1 ? (long long)a.nh : (long long)a.n * a.nh;
+  const long long base0 = a.axis == 1 ? (long long)outer * a.n * a.nh : (long long)outer * a.nh;
+  const long long sbase = slot * a.slot_stride + base0 + z0;
+  for (int e = threadIdx.x; e < L * C; e += 256) {
+    int t = e / C, c = e - t * C;
+    float2 v = make_float2(0.f, 0.f);
+    if (z0 + c < a.nh) {
+      long long gi = sbase + t * stride_t + c;
+      if constexpr (MODE == MODE_COMBINE_IC) {
+        // x pass: t = ix, outer = iy, z = z0 + c: sum_c conj(h_c) S_c
+        int mz = z0 + c, mx = signed_mode(t, a.n), my = signed_mode(outer, a.n);
+        float amp = a.amp[mx * mx + my * my + mz * mz] * a.fac[slot];
+        int ms[3] = {mx, my, mz};
+        const float2* s3 = a.src3 + slot * a.slot_stride + base0 + z0 + t * stride_t + c;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if (ms[q] == -a.n / 2 || ms[q] == a.n / 2) continue;
+          float2 s = s3[q * a.comp_stride];
+          float h = amp * ms[q];     // h_c = i h, conj(h_c) s = -i h s
+          v.x += h * s.y;
+          v.y -= h * s.x;
+        }
+      } else {
+        v = a.data[gi];
+      }
+      if constexpr (MODE == MODE_IC_C) {
+        int mz = z0 + c, mx = signed_mode(t, a.n), my = signed_mode(outer, a.n);
+        int ms[3] = {mx, my, mz};
+        int mc = ms[a.comp];
+        float h = (mc == -a.n / 2 || mc == a.n / 2)
+                      ? 0.f
+                      : a.amp[mx * mx + my * my + mz * mz] * a.fac[slot] * mc;
+        v = make_float2(-h * v.y, h * v.x);  // i h v
+      }
+    }
+    buf[e] = v;
+  }
+  __syncthreads();
+  if constexpr (MODE == MODE_FWD || MODE == MODE_FUSED_H) lds_fft<L, C, true, 256>(buf, a.tw, a.tws, false);
+  if constexpr (MODE == MODE_FUSED_H) {
+    for (int e = threadIdx.x; e < L * C; e += 256) {
+      int t = e / C, c = e - t * C;
+      int iz = z0 + c;
+      if (iz >= a.nh) continue;  // padding columns of the last tile
+      float l = a.lap[t] + a.lap[outer] + a.lap[iz];
+      float w = a.win2[t] * a.win2[outer] * a.win2[iz];
+      float h = (t == 0 && outer == 0 && iz == 0) ? 0.f : a.coef[slot] / (l * w);
+      buf[e].x *= h;
+      buf[e].y *= h;
+    }
+    __syncthreads();
+  }
+  if constexpr (MODE != MODE_FWD) lds_fft<L, C, true, 256>(buf, a.tw, a.tws, true);
+  float2* out = (MODE == MODE_IC_C) ? a.dst3 : a.data;
+  for (int e = threadIdx.x; e < L * C; e += 256) {
+    int t = e / C, c = e - t * C;
+    if (z0 + c < a.nh) out[sbase + t * stride_t + c] = buf[e];
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+
+template <int L>
+static hipError_t launch_rows(const RowLaunch& r) {
+  constexpr int R = rows_per_block<L>();
+  dim3 grid((unsigned)((r.n_rows + R - 1) / R), r.batch);
+  if (r.inverse) {
+    if (r.dst_mode == DST_F32)
+      k_c2r_rows<L, DST_F32><<<grid, 256, 0, r.stream>>>(
+          (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows,
+          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2);
+    else
+      k_c2r_rows<L, DST_IC><<<grid, 256, 0, r.stream>>>(
+          (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows,
+          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2);
+  } else {
+    if (r.src_mode == SRC_I64)
+      k_r2c_rows<L, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst,
+                                                         r.dst_stride, r.n_rows, r.tw, r.tws_half,
+                                                         r.tws_full, r.scale, r.shift);
+    else
+      k_r2c_rows<L, SRC_F32><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst,
+                                                         r.dst_stride, r.n_rows, r.tw, r.tws_half,
+                                                         r.tws_full, r.scale, r.shift);
+  }
+  return hipGetLastError();
+}
+
+hipError_t fft_rows(const RowLaunch& r) {
+  switch (r.n) {
+    case 4: return launch_rows<2>(r);
+    case 8: return launch_rows<4>(r);
+    case 16: return launch_rows<8>(r);
+    case 32: return launch_rows<16>(r);
+    case 64: return launch_rows<32>(r);
+    case 128: return launch_rows<64>(r);
+    case 256: return launch_rows<128>(r);
+    case 512: return launch_rows<256>(r);
+    case 1024: return launch_rows<512>(r);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int L, int C>
+static hipError_t launch_cols_c(const ColArgs& a, int mode, int batch, hipStream_t s) {
+  dim3 grid((unsigned)((a.nh + C - 1) / C), (unsigned)a.n, (unsigned)batch);
+  switch (mode) {
+    case MODE_FWD: k_cols<L, C, MODE_FWD><<<grid, 256, 0, s>>>(a); break;
+    case MODE_INV: k_cols<L, C, MODE_INV><<<grid, 256, 0, s>>>(a); break;
+    case MODE_FUSED_H: k_cols<L, C, MODE_FUSED_H><<<grid, 256, 0, s>>>(a); break;
+    case MODE_IC_C: k_cols<L, C, MODE_IC_C><<<grid, 256, 0, s>>>(a); break;
+    case MODE_COMBINE_IC: k_cols<L, C, MODE_COMBINE_IC><<<grid, 256, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_cols(const ColArgs& a, int mode, int batch, hipStream_t s) {
+  // keep a tile near 32-64 KB of LDS
+  constexpr int C = L >= 1024 ? 8 : (L >= 512 ? 8 : 16);
+  return launch_cols_c<L, C>(a, mode, batch, s);
+}
+
+hipError_t fft_cols(const ColArgs& a, int mode, int batch, hipStream_t s) {
+  switch (a.n) {
+    case 4: return launch_cols<4>(a, mode, batch, s);
+    case 8: return launch_cols<8>(a, mode, batch, s);
+    case 16: return launch_cols<16>(a, mode, batch, s);
+    case 32: return launch_cols<32>(a, mode, batch, s);
+    case 64: return launch_cols<64>(a, mode, batch, s);
+    case 128: return launch_cols<128>(a, mode, batch, s);
+    case 256: return launch_cols<256>(a, mode, batch, s);
+    case 512: return launch_cols<512>(a, mode, batch, s);
+    case 1024: return launch_cols<1024>(a, mode, batch, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pm

@@ -1,0 +1,239 @@
+// Auxiliary kernels: fills, white noise, the IC-adjoint source, deterministic
+// FP64 reductions and the binned power spectrum.
+#include "kernels.h"
+
+namespace pm {
+
+__global__ void k_fill(uint4* p, long long n16) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long step = (long long)gridDim.x * blockDim.x;
+  for (; i < n16; i += step) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+hipError_t launch_fill(void* p, long long bytes, hipStream_t s) {
+  // bytes is a multiple of 16 for every buffer carved by the context
+  long long n16 = bytes / 16;
+  long long blocks = (n16 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  k_fill<<<(unsigned)blocks, 256, 0, s>>>((uint4*)p, n16);
+  return hipGetLastError();
+}
+
+// Philox-4x32-10 (Salmon, Moraes, Dror & Shaw 2011) keyed by the seed, counter
+// = (i mod 2^32, i div 2^32, 0, 0); one standard normal per lattice site by
+// Box-Muller in FP64, rounded once to FP32.
+struct Seeds {
+  uint32_t k0[kMaxBatch], k1[kMaxBatch];
+};
+
+__global__ void k_white_noise(float* w, long long N, long long slot_stride, Seeds sd) {
+  const int slot = blockIdx.y;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = 0, c3 = 0;
+  uint32_t k0 = sd.k0[slot], k1 = sd.k1[slot];
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  unsigned long long h1 = (((unsigned long long)c0 << 32) | c1) >> 11;
+  unsigned long long h2 = (((unsigned long long)c2 << 32) | c3) >> 11;
+  double u1 = ((double)h1 + 0.5) * 0x1p-53;
+  double u2 = (double)h2 * 0x1p-53;
+  double v = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+  w[slot * slot_stride + i] = (float)v;
+}
+
+hipError_t launch_white_noise(float* w, long long N, long long slot_stride, int batch,
+                              const uint64_t* seeds, hipStream_t s) {
+  Seeds sd;
+  for (int b = 0; b < batch; ++b) {
+    sd.k0[b] = (uint32_t)(seeds[b] & 0xFFFFFFFFu);
+    sd.k1[b] = (uint32_t)(seeds[b] >> 32);
+  }
+  dim3 grid((unsigned)((N + 255) / 256), batch);
+  k_white_noise<<<grid, 256, 0, s>>>(w, N, slot_stride, sd);
+  return hipGetLastError();
+}
+
+// psi_bar_c = D0 X_bar_c + V_bar_c (the IC pullback of Psi = D0 psi, V = psi)
+struct D0s { float d0[kMaxBatch]; };
+__global__ void k_psibar(const float* xbar, const float* vbar, float* out, long long n3,
+                         long long stride, D0s d) {
+  const int slot = blockIdx.y;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  long long g = slot * stride + i;
+  out[g] = d.d0[slot] * xbar[g] + vbar[g];
+}
+
+hipError_t launch_psibar(const float* xbar, const float* vbar, float* out, long long N,
+                         long long part_stride, int batch, const float* d0, hipStream_t s) {
+  D0s d;
+  for (int b = 0; b < batch; ++b) d.d0[b] = d0[b];
+  dim3 grid((unsigned)((3 * N + 255) / 256), batch);
+  k_psibar<<<grid, 256, 0, s>>>(xbar, vbar, out, 3 * N, part_stride, d);
+  return hipGetLastError();
+}
+
+// deterministic FP64 dot product: fixed per-thread striding, fixed tree in
+// the block, fixed-order sum of the block partials
+constexpr int kDotBlocks = 256;
+
+__global__ void k_dot_partial(const float* a, const float* b, long long n, long long stride,
+                              double* partial) {
+  __shared__ double sh[256];
+  const int slot = blockIdx.y;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)kDotBlocks * 256)
+    acc += (double)a[slot * stride + i] * (double)b[slot * stride + i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[slot * kDotBlocks + blockIdx.x] = sh[0];
+}
+
+struct Scales { double s[kMaxBatch]; };
+__global__ void k_dot_final(const double* partial, double* out, Scales sc) {
+  const int slot = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kDotBlocks; ++i) t += partial[slot * kDotBlocks + i];
+    out[slot] = t * sc.s[slot];
+  }
+}
+
+hipError_t launch_dot(const float* a, const float* b, long long n, long long stride, int batch,
+                      double* partial, double* out, const double* scale, hipStream_t s) {
+  k_dot_partial<<<dim3(kDotBlocks, batch), 256, 0, s>>>(a, b, n, stride, partial);
+  Scales sc;
+  for (int i = 0; i < batch; ++i) sc.s[i] = scale[i];
+  k_dot_final<<<batch, 64, 0, s>>>(partial, out, sc);
+  return hipGetLastError();
+}
+
+__global__ void k_i64_to_delta(const long long* m, float* delta, long long M, long long stride,
+                               double scale) {
+  const int slot = blockIdx.y;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  delta[slot * stride + i] = (float)((double)m[slot * stride + i] * scale - 1.0);
+}
+
+hipError_t launch_i64_to_delta(const long long* m, float* delta, long long M, long long stride,
+                               int batch, double scale, hipStream_t s) {
+  dim3 grid((unsigned)((M + 255) / 256), batch);
+  k_i64_to_delta<<<grid, 256, 0, s>>>(m, delta, M, stride, scale);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ P(k)
+// One block per (x plane, slot).  Each wave walks rows y = wave, wave+4, ...
+// in 64-wide z chunks; within a chunk the bins are non-decreasing in z, so a
+// segmented shuffle scan sums each run of equal bins and the run's last lane
+// adds it to the wave's own LDS column.  Wave columns and then x planes are
+// summed in a fixed order: the FP64 result does not depend on scheduling.
+
+__device__ __forceinline__ int pk_bin(long long m2) {
+  long long t = 4 * m2;
+  long long r = (long long)sqrt((double)t);
+  while (r * r > t) --r;
+  while ((r + 1) * (r + 1) <= t) ++r;
+  return (int)((r + 1) / 2);
+}
+
+__global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, long long slot_stride, int n,
+                                                    int n_bins, double kf, const double* cic4,
+                                                    int deconv, double* partial) {
+  extern __shared__ double acc[];  // [3][n_bins][4]
+  const int slot = blockIdx.y, x = blockIdx.x;
+  const int nh = n / 2 + 1;
+  for (int e = threadIdx.x; e < 3 * n_bins * 4; e += 256) acc[e] = 0.0;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long mx = x < n / 2 ? x : x - n;
+  for (int y = wave; y < n; y += 4) {
+    const long long my = y < n / 2 ? y : y - n;
+    for (int z0 = 0; z0 < nh; z0 += 64) {
+      int z = z0 + lane;
+      int b = 0;
+      double vp = 0.0, vk = 0.0, vc = 0.0;
+      if (z < nh) {
+        long long m2 = mx * mx + my * my + (long long)z * z;
+        if (m2 > 0) {
+          b = pk_bin(m2);
+          if (b > n_bins) b = 0;
+        }
+        if (b) {
+          double wm = (z == 0 || z == n / 2) ? 1.0 : 2.0;
+          float2 X = spec[slot * slot_stride + ((long long)x * n + y) * nh + z];
+          double p = (double)X.x * X.x + (double)X.y * X.y;
+          if (deconv) p /= cic4[x] * cic4[y] * cic4[z];
+          vp = wm * p;
+          vk = wm * kf * sqrt((double)m2);
+          vc = wm;
+        }
+      }
+      for (int off = 1; off < 64; off <<= 1) {
+        double up = __shfl_up(vp, off), uk = __shfl_up(vk, off), uc = __shfl_up(vc, off);
+        int ub = __shfl_up(b, off);
+        if (lane >= off && ub == b) { vp += up; vk += uk; vc += uc; }
+      }
+      int nb = __shfl_down(b, 1);
+      bool last = (lane == 63) || (nb != b);
+      if (b && last) {
+        acc[(0 * n_bins + b - 1) * 4 + wave] += vp;
+        acc[(1 * n_bins + b - 1) * 4 + wave] += vk;
+        acc[(2 * n_bins + b - 1) * 4 + wave] += vc;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * n_bins; e += 256) {
+    double t = acc[e * 4 + 0] + acc[e * 4 + 1];
+    t += acc[e * 4 + 2];
+    t += acc[e * 4 + 3];
+    int q = e / n_bins, bb = e - q * n_bins;
+    partial[(((long long)slot * n + x) * n_bins + bb) * 3 + q] = t;
+  }
+}
+
+__global__ void k_pk_final(const double* partial, int n, int n_bins, double norm, double* k_mean,
+                           double* pk, long long* n_modes) {
+  const int slot = blockIdx.y;
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bins) return;
+  double sp = 0.0, sk = 0.0, sc = 0.0;
+  for (int x = 0; x < n; ++x) {
+    const double* p = partial + (((long long)slot * n + x) * n_bins + b) * 3;
+    sp += p[0];
+    sk += p[1];
+    sc += p[2];
+  }
+  long long o = (long long)slot * n_bins + b;
+  k_mean[o] = sc > 0 ? sk / sc : 0.0;
+  pk[o] = sc > 0 ? norm * sp / sc : 0.0;
+  n_modes[o] = (long long)sc;
+}
+
+hipError_t launch_pk(const float2* spec, long long slot_stride, int n, int batch, int n_bins,
+                     double kf, double norm, const double* cic4, int deconv, double* partial,
+                     double* k_mean, double* pk, long long* n_modes, hipStream_t s) {
+  size_t lds = (size_t)3 * n_bins * 4 * sizeof(double);
+  k_pk_partial<<<dim3(n, batch), 256, lds, s>>>(spec, slot_stride, n, n_bins, kf, cic4, deconv,
+                                                partial);
+  k_pk_final<<<dim3((n_bins + 63) / 64, batch), 64, 0, s>>>(partial, n, n_bins, norm, k_mean, pk,
+                                                           n_modes);
+  return hipGetLastError();
+}
+
+}  // namespace pm

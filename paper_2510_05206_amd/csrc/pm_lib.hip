@@ -1,0 +1,792 @@
+// C ABI of libpm.so: context, workspace carving and the call sequences of the
+// PM hot path (see include/pm.h for the contract of every entry point).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fft.h"
+#include "kernels.h"
+
+using namespace pm;
+
+struct pm_ctx {
+  pm_config cfg;
+  std::string err;
+  Growth growth;
+  std::vector<StepCoef> table;       // full schedule of cfg.n_steps
+  std::vector<std::vector<StepCoef>> slot_table;
+  std::vector<int> slot_steps;
+  std::vector<double> slot_sigma8;
+  double D0 = 0, D_ref = 1, amp = 0;
+  int Lmax = 0;
+  // host tables
+  std::vector<float2> tw;
+  std::vector<float> lap, win2, amp_tab;
+  std::vector<double> cic4;
+  // binding
+  bool bound = false, with_adj = false;
+  hipStream_t stream = nullptr;
+  Geom g{}, gp{};   // mesh geometry, particle-grid geometry (IC FFTs)
+  // device pointers
+  float2* d_tw = nullptr;
+  float *d_lap = nullptr, *d_win2 = nullptr, *d_amp = nullptr;
+  double* d_cic4 = nullptr;
+  float *disp = nullptr, *vel = nullptr, *w = nullptr, *xbar = nullptr, *vbar = nullptr;
+  long long* mesh = nullptr;
+  float2* spec = nullptr;
+  float* phi = nullptr;
+  float* gbar = nullptr;
+  float2* icspec = nullptr;          // 4 spectra on the particle grid per slot
+  long long icspec_stride = 0;       // float2 per slot (4 spectra)
+  long long icspec_comp = 0;         // float2 per spectrum
+  double* pk_partial = nullptr;
+  double* dot_partial = nullptr;
+  // state
+  bool ics_done = false, ran = false;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int ilog2(long long v) { int l = 0; while ((1ll << l) < v) ++l; return l; }
+bool pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+pm_status fail(pm_ctx* c, pm_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(ctx, PM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+  } while (0)
+
+struct Layout {
+  size_t off_tw, off_lap, off_win2, off_amp, off_cic4;
+  size_t off_disp, off_vel, off_w, off_xbar, off_vbar;
+  size_t off_mesh, off_spec, off_phi, off_gbar, off_icspec, off_pk, off_dot;
+  size_t total;
+};
+
+long long spec_elems(int n) { return (long long)n * n * (n / 2 + 1); }
+
+Layout layout(const pm_ctx* c, bool adj) {
+  Layout L{};
+  const int B = c->cfg.batch;
+  const long long N = (long long)c->cfg.n_p * c->cfg.n_p * c->cfg.n_p;
+  const long long M = (long long)c->cfg.n_g * c->cfg.n_g * c->cfg.n_g;
+  const int n = c->cfg.n_g, np = c->cfg.n_p;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  L.off_tw = take(sizeof(float2) * c->Lmax);
+  L.off_lap = take(sizeof(float) * n);
+  L.off_win2 = take(sizeof(float) * n);
+  L.off_amp = take(sizeof(float) * c->amp_tab.size());
+  L.off_cic4 = take(sizeof(double) * n);
+  L.off_disp = take(sizeof(float) * 3 * N * B);
+  L.off_vel = take(sizeof(float) * 3 * N * B);
+  L.off_w = take(sizeof(float) * N * B);
+  L.off_xbar = adj ? take(sizeof(float) * 3 * N * B) : 0;
+  L.off_vbar = adj ? take(sizeof(float) * 3 * N * B) : 0;
+  L.off_mesh = take(sizeof(long long) * M * B);
+  L.off_spec = take(sizeof(float2) * spec_elems(n) * B);
+  L.off_phi = take(sizeof(float) * M * B);
+  L.off_gbar = adj ? take(sizeof(float) * 3 * M * B) : 0;
+  L.off_icspec = take(sizeof(float2) * 4 * align_up(spec_elems(np)) * B);
+  L.off_pk = take(sizeof(double) * 3 * (size_t)n * n * B);  // n_bins <= n
+  L.off_dot = take(sizeof(double) * 256 * B);
+  L.total = o;
+  return L;
+}
+
+// Fourier-space 1D tables for the mesh multiplier and P(k), in FP64 on the host
+void build_tables(pm_ctx* c) {
+  const pm_config& cf = c->cfg;
+  const int n = cf.n_g;
+  c->Lmax = n;
+  c->tw.resize(c->Lmax);
+  for (int t = 0; t < c->Lmax; ++t) {
+    double a = -2.0 * M_PI * t / c->Lmax;
+    c->tw[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  c->lap.resize(n);
+  c->win2.resize(n);
+  c->cic4.resize(n);
+  for (int i = 0; i < n; ++i) {
+    int m = i < n / 2 ? i : i - n;
+    double th = 2.0 * M_PI * m / n;
+    double l;
+    switch (cf.lap_order) {  // tab. derivative_kernels; order 2 with the sign of its stencil
+      case 2: l = -2.0 * (1.0 - std::cos(th)); break;
+      case 4: l = -(std::cos(2 * th) - 16.0 * std::cos(th) + 15.0) / 6.0; break;
+      case 6: l = -(-2.0 * std::cos(3 * th) + 27.0 * std::cos(2 * th) - 270.0 * std::cos(th) + 245.0) / 90.0; break;
+      default: l = -th * th;
+    }
+    c->lap[i] = (float)l;
+    double h = 0.5 * th, sinc = (h == 0.0) ? 1.0 : std::sin(h) / h;
+    double wv = std::pow(sinc, cf.mak);
+    c->win2[i] = cf.deconvolve ? (float)(wv * wv) : 1.0f;
+    c->cic4[i] = std::pow(sinc, 4);
+  }
+  // IC multiplier on the particle grid: h_c = i m_c amp[|m|^2], with
+  // amp = kf sqrt(P(k) n^3/L^3) / (k^2 D_ref dq) / n^3 (the 1/n^3 of the
+  // normalised inverse DFT), zero at m = 0 and for |m| > n/2
+  const int np = cf.n_p;
+  const long long m2max = 3ll * (np / 2) * (np / 2);
+  c->amp_tab.assign(m2max + 1, 0.f);
+  const double kf = 2.0 * M_PI / cf.box, dq = cf.box / np;
+  const double n3 = (double)np * np * np;
+  for (long long m2 = 1; m2 <= m2max; ++m2) {
+    if (4 * m2 > (long long)np * np) break;
+    double k2 = kf * kf * m2, k = std::sqrt(k2);
+    double P = spectrum_eval(cf, c->amp, k);
+    c->amp_tab[m2] = (float)(kf * std::sqrt(P * n3 / (cf.box * cf.box * cf.box)) / (k2 * c->D_ref * dq) / n3);
+  }
+}
+
+Geom make_geom(int n_p, int n_g, long long part_stride, long long mesh_stride, long long spec_stride) {
+  Geom g{};
+  g.n_p = n_p;
+  g.n_g = n_g;
+  g.log2_np = ilog2(n_p);
+  g.log2_ng = ilog2(n_g);
+  g.log2_r = g.log2_ng - g.log2_np;
+  g.N = (long long)n_p * n_p * n_p;
+  g.M = (long long)n_g * n_g * n_g;
+  g.part_stride = part_stride;
+  g.mesh_stride = mesh_stride;
+  g.spec_stride = spec_stride;
+  return g;
+}
+
+unsigned long long all_mask(int B) { return B >= 64 ? ~0ull : ((1ull << B) - 1); }
+
+// --------------------------------------------------------------- FFT chains
+
+// real mesh (int64 mass or float) -> spectrum, forward 3D (or up to y only)
+pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_stride, double scale,
+                   double shift, float2* dst, long long dst_stride, int n, bool do_x,
+                   unsigned long long active) {
+  RowLaunch r{};
+  r.n = n;
+  r.n_rows = (long long)n * n;
+  r.batch = c->cfg.batch;
+  r.inverse = false;
+  r.src_mode = src_mode;
+  r.src = src;
+  r.src_stride = src_stride;
+  r.dst = dst;
+  r.dst_stride = dst_stride;
+  r.tw = c->d_tw;
+  r.tws_half = c->Lmax / (n / 2);
+  r.tws_full = c->Lmax / n;
+  r.scale = scale;
+  r.shift = shift;
+  r.stream = c->stream;
+  HIPCHK(c, fft_rows(r));
+  ColArgs a{};
+  a.data = dst;
+  a.slot_stride = dst_stride;
+  a.n = n;
+  a.nh = n / 2 + 1;
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / n;
+  a.active = active;
+  a.axis = 1;
+  HIPCHK(c, fft_cols(a, MODE_FWD, c->cfg.batch, c->stream));
+  if (do_x) {
+    a.axis = 0;
+    HIPCHK(c, fft_cols(a, MODE_FWD, c->cfg.batch, c->stream));
+  }
+  return PM_OK;
+}
+
+// spectrum after the y pass -> x pass with the PM multiplier -> y inverse -> real
+pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long long active) {
+  const int n = c->cfg.n_g;
+  ColArgs a{};
+  a.data = c->spec;
+  a.slot_stride = c->g.spec_stride;
+  a.n = n;
+  a.nh = n / 2 + 1;
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / n;
+  a.lap = c->d_lap;
+  a.win2 = c->d_win2;
+  a.active = active;
+  const double r = (double)(1 << c->g.log2_r);
+  const double n3 = (double)n * n * n;
+  for (int b = 0; b < c->cfg.batch; ++b) a.coef[b] = (float)(-s[b] / (r * n3));
+  a.axis = 0;
+  HIPCHK(c, fft_cols(a, MODE_FUSED_H, c->cfg.batch, c->stream));
+  a.axis = 1;
+  HIPCHK(c, fft_cols(a, MODE_INV, c->cfg.batch, c->stream));
+  RowLaunch rl{};
+  rl.n = n;
+  rl.n_rows = (long long)n * n;
+  rl.batch = c->cfg.batch;
+  rl.inverse = true;
+  rl.dst_mode = DST_F32;
+  rl.src = c->spec;
+  rl.src_stride = c->g.spec_stride;
+  rl.dst = out;
+  rl.dst_stride = c->g.mesh_stride;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (n / 2);
+  rl.tws_full = c->Lmax / n;
+  rl.scale = 1.0;
+  rl.stream = c->stream;
+  HIPCHK(c, fft_rows(rl));
+  return PM_OK;
+}
+
+// deposit of `disp` (optionally drifting by tau first) into the int64 mesh
+pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, int mak,
+                  long long* mesh, unsigned long long active) {
+  HIPCHK(c, launch_fill(mesh, (long long)sizeof(long long) * c->g.mesh_stride * c->cfg.batch, c->stream));
+  DepositArgs d{};
+  d.g = c->g;
+  d.batch = c->cfg.batch;
+  d.disp = disp;
+  d.vel = vel_pre;
+  d.mesh = mesh;
+  d.active = active;
+  for (int b = 0; b < c->cfg.batch; ++b) d.tau[b] = tau ? (float)tau[b] : 0.f;
+  HIPCHK(c, launch_deposit(d, mak, c->stream));
+  return PM_OK;
+}
+
+// potential phi of the positions `disp` for the midpoint normalisation s
+pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
+                    unsigned long long active) {
+  pm_status st = deposit(c, disp, vel_pre, tau, c->cfg.mak, c->mesh, active);
+  if (st) return st;
+  const double N = (double)c->g.N, n3 = (double)c->g.M;
+  st = r2c_mesh(c, c->mesh, SRC_I64, c->g.mesh_stride, n3 / N / 4294967296.0, 1.0, c->spec,
+                c->g.spec_stride, c->cfg.n_g, false, active);
+  if (st) return st;
+  return poisson_to_real(c, s, c->phi, active);
+}
+
+pm_status check_bound(pm_ctx* c) {
+  if (!c) return PM_EINVAL;
+  if (!c->bound) return fail(c, PM_ESTATE, "context not bound to a workspace");
+  return PM_OK;
+}
+
+}  // namespace
+
+// =========================================================== public calls
+
+extern "C" {
+
+pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
+  if (!cfg || !out) return PM_EINVAL;
+  *out = nullptr;
+  const pm_config& c = *cfg;
+  if (!pow2(c.n_p) || c.n_p < 4 || c.n_p > 1024 || !pow2(c.n_g) || c.n_g < c.n_p || c.n_g > 1024 ||
+      c.n_g / c.n_p > 4)
+    return PM_EINVAL;
+  if (c.box <= 0 || c.n_steps < 1 || c.a_start <= 0 || c.a_end <= c.a_start || c.batch < 1 ||
+      c.batch > kMaxBatch || c.omega_m <= 0 || c.omega_m > 1)
+    return PM_EINVAL;
+  if (c.force == PM_FORCE_PM) {
+    if ((c.mak != 2 && c.mak != 3) || (c.grad_order != 2 && c.grad_order != 4 && c.grad_order != 6) ||
+        (c.lap_order != 0 && c.lap_order != 2 && c.lap_order != 4 && c.lap_order != 6))
+      return PM_EINVAL;
+  } else {
+    return PM_EUNSUPPORTED;
+  }
+  if (c.spectrum != PM_SPEC_BBKS && c.spectrum != PM_SPEC_POWERLAW) return PM_EINVAL;
+  pm_ctx* ctx = new (std::nothrow) pm_ctx();
+  if (!ctx) return PM_ENOMEM;
+  ctx->cfg = c;
+  ctx->growth.solve(c.omega_m);
+  ctx->table = bullfrog_table(ctx->growth, c.a_start, c.a_end, c.n_steps);
+  ctx->D0 = ctx->growth.D_of_a(c.a_start);
+  ctx->D_ref = ctx->growth.D_of_a(1.0);
+  if (c.spectrum == PM_SPEC_BBKS)
+    ctx->amp = bbks_amplitude(c.omega_m, c.h, c.n_s, c.sigma8);
+  else
+    ctx->amp = powerlaw_amplitude(c, ctx->D0, ctx->D_ref);
+  ctx->slot_steps.assign(c.batch, c.n_steps);
+  ctx->slot_sigma8.assign(c.batch, c.sigma8);
+  ctx->slot_table.assign(c.batch, ctx->table);
+  build_tables(ctx);
+  *out = ctx;
+  return PM_OK;
+}
+
+size_t pm_workspace_bytes(const pm_ctx* ctx, int32_t with_adjoint) {
+  if (!ctx) return 0;
+  return layout(ctx, with_adjoint != 0).total;
+}
+
+pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint, void* stream) {
+  if (!c) return PM_EINVAL;
+  Layout L = layout(c, with_adjoint != 0);
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(c, PM_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < L.total) return fail(c, PM_ENOMEM, "workspace too small");
+  char* ws = (char*)workspace;
+  c->stream = (hipStream_t)stream;
+  c->with_adj = with_adjoint != 0;
+  const int B = c->cfg.batch;
+  c->d_tw = (float2*)(ws + L.off_tw);
+  c->d_lap = (float*)(ws + L.off_lap);
+  c->d_win2 = (float*)(ws + L.off_win2);
+  c->d_amp = (float*)(ws + L.off_amp);
+  c->d_cic4 = (double*)(ws + L.off_cic4);
+  c->disp = (float*)(ws + L.off_disp);
+  c->vel = (float*)(ws + L.off_vel);
+  c->w = (float*)(ws + L.off_w);
+  c->xbar = with_adjoint ? (float*)(ws + L.off_xbar) : nullptr;
+  c->vbar = with_adjoint ? (float*)(ws + L.off_vbar) : nullptr;
+  c->mesh = (long long*)(ws + L.off_mesh);
+  c->spec = (float2*)(ws + L.off_spec);
+  c->phi = (float*)(ws + L.off_phi);
+  c->gbar = with_adjoint ? (float*)(ws + L.off_gbar) : nullptr;
+  c->icspec = (float2*)(ws + L.off_icspec);
+  c->pk_partial = (double*)(ws + L.off_pk);
+  c->dot_partial = (double*)(ws + L.off_dot);
+  const int n = c->cfg.n_g, np = c->cfg.n_p;
+  c->icspec_comp = (long long)(align_up(spec_elems(np)));
+  c->icspec_stride = 4 * c->icspec_comp;
+  const long long N = (long long)np * np * np, M = (long long)n * n * n;
+  c->g = make_geom(np, n, 3 * N, M, spec_elems(n));
+  c->gp = make_geom(np, np, 3 * N, N, c->icspec_stride);
+  (void)B;
+  HIPCHK(c, hipMemcpyAsync(c->d_tw, c->tw.data(), sizeof(float2) * c->tw.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_lap, c->lap.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_win2, c->win2.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_amp, c->amp_tab.data(), sizeof(float) * c->amp_tab.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_cic4, c->cic4.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  // host tables must outlive the copies: wait for them here (bind is not on the hot path)
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->bound = true;
+  c->ics_done = c->ran = false;
+  return PM_OK;
+}
+
+pm_status pm_schedule(const pm_ctx* c, int32_t slot, double* out) {
+  if (!c || !out || slot < 0 || slot >= c->cfg.batch) return PM_EINVAL;
+  const auto& T = c->slot_table[slot];
+  for (size_t n = 0; n < T.size(); ++n) {
+    const StepCoef& s = T[n];
+    double row[8] = {s.D_n, s.D_half, s.D_np1, s.alpha, s.beta, s.tau1, s.tau2, s.s};
+    std::memcpy(out + 8 * n, row, sizeof(row));
+  }
+  return PM_OK;
+}
+
+pm_status pm_describe(const pm_ctx* c, double* out) {
+  if (!c || !out) return PM_EINVAL;
+  out[0] = c->D0;
+  out[1] = c->D_ref;
+  out[2] = c->amp;
+  return PM_OK;
+}
+
+pm_status pm_destroy(pm_ctx* c) {
+  delete c;
+  return PM_OK;
+}
+
+const char* pm_last_error(const pm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+pm_status pm_set_slot_params(pm_ctx* c, const int32_t* n_steps, const double* sigma8) {
+  if (!c) return PM_EINVAL;
+  for (int b = 0; b < c->cfg.batch; ++b) {
+    if (n_steps && (n_steps[b] < 1 || n_steps[b] > c->cfg.n_steps))
+      return fail(c, PM_EINVAL, "slot n_steps out of range");
+    if (sigma8 && !(sigma8[b] > 0)) return fail(c, PM_EINVAL, "sigma8 must be positive");
+  }
+  for (int b = 0; b < c->cfg.batch; ++b) {
+    if (n_steps && n_steps[b] != c->slot_steps[b]) {
+      c->slot_steps[b] = n_steps[b];
+      c->slot_table[b] = bullfrog_table(c->growth, c->cfg.a_start, c->cfg.a_end, n_steps[b]);
+    }
+    if (sigma8) c->slot_sigma8[b] = sigma8[b];
+  }
+  return PM_OK;
+}
+
+pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float* w_out) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!seeds && !w_in) return fail(c, PM_EINVAL, "need seeds or w_in");
+  const int B = c->cfg.batch, np = c->cfg.n_p;
+  const long long N = c->g.N;
+  const unsigned long long act = all_mask(B);
+  if (w_in)
+    HIPCHK(c, hipMemcpyAsync(c->w, w_in, sizeof(float) * N * B, hipMemcpyDeviceToDevice, c->stream));
+  else
+    HIPCHK(c, launch_white_noise(c->w, N, N, B, seeds, c->stream));
+  float2* wspec = c->icspec + 3 * c->icspec_comp;
+  pm_status st = r2c_mesh(c, c->w, SRC_F32, N, 1.0, 0.0, wspec, c->icspec_stride, np, true, act);
+  if (st) return st;
+  ColArgs a{};
+  a.data = wspec;
+  a.slot_stride = c->icspec_stride;
+  a.n = np;
+  a.nh = np / 2 + 1;
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / np;
+  a.amp = c->d_amp;
+  a.active = act;
+  for (int b = 0; b < B; ++b)
+    a.fac[b] = (float)(c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0);
+  for (int comp = 0; comp < 3; ++comp) {
+    float2* out = c->icspec + comp * c->icspec_comp;
+    a.axis = 0;
+    a.comp = comp;
+    a.dst3 = out;
+    HIPCHK(c, fft_cols(a, MODE_IC_C, B, c->stream));
+    ColArgs y = a;
+    y.data = out;
+    y.axis = 1;
+    HIPCHK(c, fft_cols(y, MODE_INV, B, c->stream));
+    RowLaunch rl{};
+    rl.n = np;
+    rl.n_rows = (long long)np * np;
+    rl.batch = B;
+    rl.inverse = true;
+    rl.dst_mode = DST_IC;
+    rl.src = out;
+    rl.src_stride = c->icspec_stride;
+    rl.dst = c->vel + comp * N;
+    rl.dst2 = c->disp + comp * N;
+    rl.dst_stride = 3 * N;
+    rl.tw = c->d_tw;
+    rl.tws_half = c->Lmax / (np / 2);
+    rl.tws_full = c->Lmax / np;
+    rl.scale = 1.0;
+    rl.scale2 = c->D0;
+    rl.stream = c->stream;
+    HIPCHK(c, fft_rows(rl));
+  }
+  if (w_out)
+    HIPCHK(c, hipMemcpyAsync(w_out, c->w, sizeof(float) * N * B, hipMemcpyDeviceToDevice, c->stream));
+  c->ics_done = true;
+  c->ran = false;
+  return PM_OK;
+}
+
+static pm_status step_common(pm_ctx* c, const double* tau_pre, bool pre_drift, const double* s,
+                             const double* alpha, const double* beta, const double* tau_post,
+                             unsigned long long active) {
+  pm_status st = potential(c, c->disp, pre_drift ? c->vel : nullptr, tau_pre, s, active);
+  if (st) return st;
+  GatherArgs a{};
+  a.g = c->g;
+  a.batch = c->cfg.batch;
+  a.disp = c->disp;
+  a.vel = c->vel;
+  a.phi = c->phi;
+  a.active = active;
+  for (int b = 0; b < c->cfg.batch; ++b) {
+    a.alpha[b] = (float)alpha[b];
+    a.beta[b] = (float)beta[b];
+    a.tau[b] = (float)tau_post[b];
+  }
+  HIPCHK(c, launch_gather(a, GK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
+  return PM_OK;
+}
+
+pm_status pm_step(pm_ctx* c, const int32_t* step_index) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!c->ics_done) return fail(c, PM_ESTATE, "pm_step before pm_init_ics");
+  if (!step_index) return PM_EINVAL;
+  const int B = c->cfg.batch;
+  std::vector<double> tp(B, 0), s(B, 1), al(B, 1), be(B, 0), tq(B, 0);
+  unsigned long long act = 0;
+  for (int b = 0; b < B; ++b) {
+    int k = step_index[b];
+    if (k < 0) continue;
+    if (k >= c->slot_steps[b]) return fail(c, PM_EINVAL, "step index out of range");
+    const StepCoef& sc = c->slot_table[b][k];
+    tp[b] = sc.tau1; s[b] = sc.s; al[b] = sc.alpha; be[b] = sc.beta; tq[b] = sc.tau2;
+    act |= 1ull << b;
+  }
+  if (!act) return PM_OK;
+  pm_status st = step_common(c, tp.data(), true, s.data(), al.data(), be.data(), tq.data(), act);
+  if (st) return st;
+  c->ran = true;
+  return PM_OK;
+}
+
+pm_status pm_run(pm_ctx* c) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!c->ics_done) return fail(c, PM_ESTATE, "pm_run before pm_init_ics");
+  const int B = c->cfg.batch;
+  int nmax = 0;
+  for (int b = 0; b < B; ++b) nmax = std::max(nmax, c->slot_steps[b]);
+  for (int n = 0; n < nmax; ++n) {
+    std::vector<double> tp(B, 0), s(B, 1), al(B, 1), be(B, 0), tq(B, 0);
+    unsigned long long act = 0;
+    for (int b = 0; b < B; ++b) {
+      if (n >= c->slot_steps[b]) continue;
+      const auto& T = c->slot_table[b];
+      tp[b] = T[n].tau1;
+      s[b] = T[n].s; al[b] = T[n].alpha; be[b] = T[n].beta;
+      tq[b] = T[n].tau2 + (n + 1 < c->slot_steps[b] ? T[n + 1].tau1 : 0.0);  // merged drifts
+      act |= 1ull << b;
+    }
+    pm_status st = step_common(c, tp.data(), n == 0, s.data(), al.data(), be.data(), tq.data(), act);
+    if (st) return st;
+  }
+  c->ran = true;
+  return PM_OK;
+}
+
+pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
+  if (!c->ran) return fail(c, PM_ESTATE, "pm_adjoint before pm_run");
+  if (!dL_ddelta || !dL_dw || !dL_dsigma8) return PM_EINVAL;
+  const int B = c->cfg.batch, np = c->cfg.n_p;
+  const long long N = c->g.N, M = c->g.M;
+  const double mfac = (double)M / (double)N;
+  HIPCHK(c, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
+  HIPCHK(c, launch_fill(c->vbar, (long long)sizeof(float) * 3 * N * B, c->stream));
+  int nmax = 0;
+  for (int b = 0; b < B; ++b) nmax = std::max(nmax, c->slot_steps[b]);
+  // loss pullback through the final CIC density and the last half drift
+  GatherArgs a{};
+  a.g = c->g;
+  a.batch = B;
+  a.disp = c->disp;
+  a.vel = c->vel;
+  a.xbar = c->xbar;
+  a.vbar = c->vbar;
+  a.gbar = c->gbar;
+  a.phi = dL_ddelta;
+  a.active = all_mask(B);
+  for (int b = 0; b < B; ++b) {
+    a.coef[b] = (float)mfac;
+    a.tau[b] = (float)c->slot_table[b][c->slot_steps[b] - 1].tau2;
+  }
+  HIPCHK(c, launch_gather(a, GK_ADJ_DRIFT, 2, c->cfg.grad_order, c->stream));
+  for (int n = nmax - 1; n >= 0; --n) {
+    std::vector<double> s(B, 1);
+    unsigned long long act = 0;
+    for (int b = 0; b < B; ++b)
+      if (n < c->slot_steps[b]) { s[b] = c->slot_table[b][n].s; act |= 1ull << b; }
+    // force at X^{n+1/2}
+    pm_status st = potential(c, c->disp, nullptr, nullptr, s.data(), act);
+    if (st) return st;
+    HIPCHK(c, launch_fill(c->gbar, (long long)sizeof(float) * 3 * M * B, c->stream));
+    GatherArgs k = a;
+    k.phi = c->phi;
+    k.active = act;
+    for (int b = 0; b < B; ++b) {
+      if (!((act >> b) & 1)) continue;
+      const StepCoef& sc = c->slot_table[b][n];
+      k.alpha[b] = (float)sc.alpha;
+      k.beta[b] = (float)sc.beta;
+    }
+    HIPCHK(c, launch_gather(k, GK_ADJ_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
+    // mesh cotangent: d = sum_c FD_c^T g_bar_c, then the transposed multiplier
+    float* d = reinterpret_cast<float*>(c->mesh);
+    HIPCHK(c, launch_fd_div(c->gbar, d, c->g, B, c->cfg.grad_order, act, c->stream));
+    st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
+    if (st) return st;
+    st = poisson_to_real(c, s.data(), c->phi, act);
+    if (st) return st;
+    GatherArgs dr = a;
+    dr.phi = c->phi;
+    dr.active = act;
+    for (int b = 0; b < B; ++b) {
+      dr.coef[b] = (float)mfac;
+      if (!((act >> b) & 1)) continue;
+      const auto& T = c->slot_table[b];
+      dr.tau[b] = (float)(T[n].tau1 + (n > 0 ? T[n - 1].tau2 : 0.0));
+    }
+    HIPCHK(c, launch_gather(dr, GK_ADJ_DRIFT, c->cfg.mak, c->cfg.grad_order, c->stream));
+  }
+  // initial conditions: psi_bar = D0 X_bar + V_bar, w_bar = sum_c T_c^T psi_bar_c
+  std::vector<float> d0(B, (float)c->D0);
+  float* psibar = c->gbar;
+  HIPCHK(c, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->stream));
+  const unsigned long long act = all_mask(B);
+  for (int comp = 0; comp < 3; ++comp) {
+    pm_status st = r2c_mesh(c, psibar + comp * N, SRC_F32, 3 * N, 1.0, 0.0,
+                            c->icspec + comp * c->icspec_comp, c->icspec_stride, np, true, act);
+    if (st) return st;
+  }
+  float2* comb = c->icspec + 3 * c->icspec_comp;
+  ColArgs ca{};
+  ca.src3 = c->icspec;
+  ca.comp_stride = c->icspec_comp;
+  ca.data = comb;
+  ca.slot_stride = c->icspec_stride;
+  ca.n = np;
+  ca.nh = np / 2 + 1;
+  ca.tw = c->d_tw;
+  ca.tws = c->Lmax / np;
+  ca.amp = c->d_amp;
+  ca.active = act;
+  ca.axis = 0;
+  for (int b = 0; b < B; ++b)
+    ca.fac[b] = (float)(c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0);
+  HIPCHK(c, fft_cols(ca, MODE_COMBINE_IC, B, c->stream));
+  ca.axis = 1;
+  HIPCHK(c, fft_cols(ca, MODE_INV, B, c->stream));
+  RowLaunch rl{};
+  rl.n = np;
+  rl.n_rows = (long long)np * np;
+  rl.batch = B;
+  rl.inverse = true;
+  rl.dst_mode = DST_F32;
+  rl.src = comb;
+  rl.src_stride = c->icspec_stride;
+  rl.dst = dL_dw;
+  rl.dst_stride = N;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (np / 2);
+  rl.tws_full = c->Lmax / np;
+  rl.scale = 1.0;
+  rl.stream = c->stream;
+  HIPCHK(c, fft_rows(rl));
+  // dL/dsigma8 = <psi_bar, psi>/sigma8 = <w_bar, w>/sigma8 (psi is linear in w and sigma8)
+  std::vector<double> inv(B);
+  for (int b = 0; b < B; ++b) inv[b] = 1.0 / c->slot_sigma8[b];
+  HIPCHK(c, launch_dot(dL_dw, c->w, N, N, B, c->dot_partial, dL_dsigma8, inv.data(), c->stream));
+  c->ran = false;
+  return PM_OK;
+}
+
+pm_status pm_power_spectrum(pm_ctx* c, int32_t n_bins, int32_t deconvolve_cic, double* k_mean,
+                            double* pk, int64_t* n_modes) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!c->ics_done) return fail(c, PM_ESTATE, "no particles yet");
+  const int n = c->cfg.n_g;
+  if (n_bins < 1 || n_bins > n || n_bins > 512 || !k_mean || !pk || !n_modes)
+    return fail(c, PM_EINVAL, "n_bins must be in [1, min(n_g, 512)]");
+  const unsigned long long act = all_mask(c->cfg.batch);
+  pm_status st = deposit(c, c->disp, nullptr, nullptr, 2, c->mesh, act);
+  if (st) return st;
+  const double N = (double)c->g.N, n3 = (double)c->g.M;
+  st = r2c_mesh(c, c->mesh, SRC_I64, c->g.mesh_stride, n3 / N / 4294967296.0, 1.0, c->spec,
+                c->g.spec_stride, n, true, act);
+  if (st) return st;
+  const double L = c->cfg.box;
+  HIPCHK(c, launch_pk(c->spec, c->g.spec_stride, n, c->cfg.batch, n_bins, 2.0 * M_PI / L,
+                      L * L * L / (n3 * n3), c->d_cic4, deconvolve_cic, c->pk_partial, k_mean, pk,
+                      (long long*)n_modes, c->stream));
+  return PM_OK;
+}
+
+pm_status pm_density(pm_ctx* c, float* delta_out, int64_t* fixed_out) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!c->ics_done) return fail(c, PM_ESTATE, "no particles yet");
+  const unsigned long long act = all_mask(c->cfg.batch);
+  pm_status st = deposit(c, c->disp, nullptr, nullptr, 2, c->mesh, act);
+  if (st) return st;
+  const double scale = (double)c->g.M / (double)c->g.N / 4294967296.0;
+  if (delta_out)
+    HIPCHK(c, launch_i64_to_delta(c->mesh, delta_out, c->g.M, c->g.mesh_stride, c->cfg.batch, scale, c->stream));
+  if (fixed_out)
+    HIPCHK(c, hipMemcpyAsync(fixed_out, c->mesh, sizeof(long long) * c->g.M * c->cfg.batch,
+                             hipMemcpyDeviceToDevice, c->stream));
+  return PM_OK;
+}
+
+pm_status pm_get_state(pm_ctx* c, float* disp, float* vel) {
+  if (pm_status st = check_bound(c)) return st;
+  size_t bytes = sizeof(float) * 3 * c->g.N * c->cfg.batch;
+  if (disp) HIPCHK(c, hipMemcpyAsync(disp, c->disp, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (vel) HIPCHK(c, hipMemcpyAsync(vel, c->vel, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return PM_OK;
+}
+
+pm_status pm_set_state(pm_ctx* c, const float* disp, const float* vel) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!disp || !vel) return PM_EINVAL;
+  size_t bytes = sizeof(float) * 3 * c->g.N * c->cfg.batch;
+  HIPCHK(c, hipMemcpyAsync(c->disp, disp, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->vel, vel, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->ics_done = true;
+  c->ran = true;  // any state may be pulled back by pm_adjoint after a run
+  return PM_OK;
+}
+
+pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_out) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!disp || !mesh_out || (mak != 2 && mak != 3)) return PM_EINVAL;
+  return deposit(c, const_cast<float*>(disp), nullptr, nullptr, mak, (long long*)mesh_out,
+                 all_mask(c->cfg.batch));
+}
+
+pm_status pm_force(pm_ctx* c, const float* disp, double s, float* acc_out) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!disp || !acc_out) return PM_EINVAL;
+  const int B = c->cfg.batch;
+  std::vector<double> sv(B, s);
+  const unsigned long long act = all_mask(B);
+  pm_status st = potential(c, const_cast<float*>(disp), nullptr, nullptr, sv.data(), act);
+  if (st) return st;
+  GatherArgs a{};
+  a.g = c->g;
+  a.batch = B;
+  a.disp = const_cast<float*>(disp);
+  a.phi = c->phi;
+  a.acc_out = acc_out;
+  a.active = act;
+  HIPCHK(c, launch_gather(a, GK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
+  return PM_OK;
+}
+
+pm_status pm_fft(pm_ctx* c, const void* in, void* out, int32_t inverse) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!in || !out) return PM_EINVAL;
+  const int n = c->cfg.n_g, B = c->cfg.batch;
+  const unsigned long long act = all_mask(B);
+  const size_t sbytes = sizeof(float2) * spec_elems(n);
+  if (!inverse) {
+    pm_status st = r2c_mesh(c, in, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, n, true, act);
+    if (st) return st;
+    for (int b = 0; b < B; ++b)
+      HIPCHK(c, hipMemcpyAsync((float2*)out + b * spec_elems(n), c->spec + b * c->g.spec_stride, sbytes,
+                               hipMemcpyDeviceToDevice, c->stream));
+    return PM_OK;
+  }
+  for (int b = 0; b < B; ++b)
+    HIPCHK(c, hipMemcpyAsync(c->spec + b * c->g.spec_stride, (const float2*)in + b * spec_elems(n), sbytes,
+                             hipMemcpyDeviceToDevice, c->stream));
+  ColArgs a{};
+  a.data = c->spec;
+  a.slot_stride = c->g.spec_stride;
+  a.n = n;
+  a.nh = n / 2 + 1;
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / n;
+  a.active = act;
+  a.axis = 0;
+  HIPCHK(c, fft_cols(a, MODE_INV, B, c->stream));
+  a.axis = 1;
+  HIPCHK(c, fft_cols(a, MODE_INV, B, c->stream));
+  RowLaunch rl{};
+  rl.n = n;
+  rl.n_rows = (long long)n * n;
+  rl.batch = B;
+  rl.inverse = true;
+  rl.dst_mode = DST_F32;
+  rl.src = c->spec;
+  rl.src_stride = c->g.spec_stride;
+  rl.dst = out;
+  rl.dst_stride = c->g.mesh_stride;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (n / 2);
+  rl.tws_full = c->Lmax / n;
+  rl.scale = 1.0;
+  rl.stream = c->stream;
+  HIPCHK(c, fft_rows(rl));
+  return PM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+"""Python-side handle of one libpm context: torch owns the device workspace and
+the stream; every call forwards to the C ABI (include/pm.h)."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, fields
+
+import torch
+
+from . import _lib
+
+
+@dataclass
+class Config:
+    """Mirror of pm_config (include/pm.h); defaults are the paper's PM
+    defaults where it gives one (tab. default_parameters)."""
+    n_p: int = 32
+    n_g: int = 64
+    box: float = 100.0
+    omega_m: float = 0.31
+    h: float = 0.68
+    n_s: float = 0.965
+    sigma8: float = 0.81
+    spectrum: str = "bbks"        # "bbks" | "powerlaw"
+    pl_rms_cells: float = 0.2
+    a_start: float = 0.02
+    a_end: float = 1.0
+    n_steps: int = 10
+    force: str = "pm"             # "pm" | "nufft"
+    mak: int = 2                  # 2 CIC, 3 TSC
+    deconvolve: bool = False
+    grad_order: int = 4
+    lap_order: int = 0
+    es_width: int = 6
+    es_beta: float = 13.8
+    batch: int = 1
+
+    def to_c(self):
+        c = _lib.pm_config()
+        for f in fields(self):
+            v = getattr(self, f.name)
+            if f.name == "spectrum":
+                v = _lib.PM_SPEC_BBKS if v == "bbks" else _lib.PM_SPEC_POWERLAW
+            elif f.name == "force":
+                v = _lib.PM_FORCE_PM if v == "pm" else _lib.PM_FORCE_NUFFT
+            elif isinstance(v, bool):
+                v = int(v)
+            setattr(c, f.name, v)
+        return c
+
+    @property
+    def N(self):
+        return self.n_p ** 3
+
+    @property
+    def M(self):
+        return self.n_g ** 3
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class PMSim:
+    """One context of B same-shape slots bound to a torch-owned workspace."""
+
+    def __init__(self, cfg: Config, with_adjoint=False, device="cuda"):
+        self.lib = _lib.load()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        ctx = C.c_void_p()
+        ccfg = cfg.to_c()
+        _lib.check(self.lib.pm_create(C.byref(ccfg), C.byref(ctx)), None, "pm_create")
+        self.ctx = ctx
+        self.with_adjoint = bool(with_adjoint)
+        nbytes = int(self.lib.pm_workspace_bytes(ctx, int(self.with_adjoint)))
+        self.workspace_bytes = nbytes
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        self.stream = torch.cuda.current_stream(self.device)
+        _lib.check(self.lib.pm_bind(ctx, C.c_void_p(self._ws.data_ptr() + off), nbytes,
+                                    int(self.with_adjoint), C.c_void_p(self.stream.cuda_stream)),
+                   ctx, "pm_bind")
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            self.lib.pm_destroy(ctx)
+            self.ctx = None
+
+    # --------------------------------------------------------------- calls
+    def _call(self, name, *args):
+        _lib.check(getattr(self.lib, name)(self.ctx, *args), self.ctx, name)
+
+    def _new(self, *shape, dtype=torch.float32):
+        return torch.empty(*shape, dtype=dtype, device=self.device)
+
+    def set_slot_params(self, n_steps=None, sigma8=None):
+        B = self.cfg.batch
+        ns = (C.c_int32 * B)(*n_steps) if n_steps is not None else None
+        sg = (C.c_double * B)(*sigma8) if sigma8 is not None else None
+        self._call("pm_set_slot_params", ns, sg)
+
+    def init_ics(self, seeds=None, w=None, return_w=False):
+        B, N = self.cfg.batch, self.cfg.N
+        sd = (C.c_uint64 * B)(*[int(s) for s in seeds]) if seeds is not None else None
+        if w is not None:
+            w = w.to(self.device, torch.float32).contiguous().reshape(B, N)
+        w_out = self._new(B, N) if return_w else None
+        self._call("pm_init_ics", sd, _ptr(w), _ptr(w_out))
+        return w_out
+
+    def step(self, step_index):
+        B = self.cfg.batch
+        self._call("pm_step", (C.c_int32 * B)(*step_index))
+
+    def run(self):
+        self._call("pm_run")
+
+    def adjoint(self, dL_ddelta):
+        B = self.cfg.batch
+        g = dL_ddelta.to(self.device, torch.float32).contiguous().reshape(B, self.cfg.M)
+        dw = self._new(B, self.cfg.N)
+        ds = self._new(B, dtype=torch.float64)
+        self._call("pm_adjoint", _ptr(g), _ptr(dw), _ptr(ds))
+        return dw, ds
+
+    def power_spectrum(self, n_bins, deconvolve=True):
+        B = self.cfg.batch
+        k = self._new(B, n_bins, dtype=torch.float64)
+        p = self._new(B, n_bins, dtype=torch.float64)
+        n = self._new(B, n_bins, dtype=torch.int64)
+        self._call("pm_power_spectrum", int(n_bins), int(bool(deconvolve)), _ptr(k), _ptr(p), _ptr(n))
+        return k, p, n
+
+    def density(self, fixed=False):
+        B = self.cfg.batch
+        d = self._new(B, self.cfg.M)
+        f = self._new(B, self.cfg.M, dtype=torch.int64) if fixed else None
+        self._call("pm_density", _ptr(d), _ptr(f))
+        return (d, f) if fixed else d
+
+    def get_state(self):
+        B, N = self.cfg.batch, self.cfg.N
+        x, v = self._new(B, 3, N), self._new(B, 3, N)
+        self._call("pm_get_state", _ptr(x), _ptr(v))
+        return x, v
+
+    def set_state(self, disp, vel):
+        B, N = self.cfg.batch, self.cfg.N
+        x = disp.to(self.device, torch.float32).contiguous().reshape(B, 3, N)
+        v = vel.to(self.device, torch.float32).contiguous().reshape(B, 3, N)
+        self._call("pm_set_state", _ptr(x), _ptr(v))
+
+    def deposit(self, disp, mak):
+        B, N = self.cfg.batch, self.cfg.N
+        x = disp.to(self.device, torch.float32).contiguous().reshape(B, 3, N)
+        m = self._new(B, self.cfg.M, dtype=torch.int64)
+        self._call("pm_deposit", _ptr(x), int(mak), _ptr(m))
+        return m
+
+    def force(self, disp, s):
+        B, N = self.cfg.batch, self.cfg.N
+        x = disp.to(self.device, torch.float32).contiguous().reshape(B, 3, N)
+        a = self._new(B, 3, N)
+        self._call("pm_force", _ptr(x), float(s), _ptr(a))
+        return a
+
+    def fft(self, x, inverse=False):
+        B, n = self.cfg.batch, self.cfg.n_g
+        if not inverse:
+            xin = x.to(self.device, torch.float32).contiguous().reshape(B, n, n, n)
+            out = self._new(B, n, n, n // 2 + 1, dtype=torch.complex64)
+        else:
+            xin = x.to(self.device, torch.complex64).contiguous().reshape(B, n, n, n // 2 + 1)
+            out = self._new(B, n, n, n)
+        self._call("pm_fft", _ptr(xin), _ptr(out), int(bool(inverse)))
+        return out
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+class PMFunction(torch.autograd.Function):
+    """delta_final = F(w): forward runs ICs + BullFrog steps on the GPU and
+    keeps only the context; backward runs the adjoint (memory independent of
+    the number of steps)."""
+
+    @staticmethod
+    def forward(ctx, w, sim):
+        sim.init_ics(w=w)
+        sim.run()
+        ctx.sim = sim
+        return sim.density()
+
+    @staticmethod
+    def backward(ctx, g):
+        dw, ds = ctx.sim.adjoint(g)
+        ctx.sim.dL_dsigma8 = ds
+        return dw, None

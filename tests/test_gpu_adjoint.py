@@ -1,0 +1,134 @@
+"""GPU parity of the adjoint (reverse-in-time) gradient against the oracle's
+store-all reverse mode and against finite differences of the GPU forward."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import adjoint as oadj
+from oracle import nbody as onbody
+from oracle import philox as ophilox
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_05206_amd as P
+    P.load()
+
+
+def make_sim(d, adj=True, **kw):
+    from paper_2510_05206_amd import PMSim
+    return PMSim(synth.gpu_config(d, **kw), with_adjoint=adj)
+
+
+def observed(d):
+    """delta_obs = oracle forward of the target seed + 10% (of its rms) noise."""
+    prob = synth.oracle_problem(d)
+    psi, _ = onbody.run(prob, w=ophilox.white_noise(synth.SEED_TARGET, d["n_p"]))
+    dt = oadj.final_density(prob, psi)
+    noise = np.random.default_rng(synth.SEED_NOISE).normal(size=dt.size)
+    return dt + 0.1 * dt.std() * noise
+
+
+@pytest.mark.parametrize("wl", ["C4_SMALL", "C2_SMALL"])
+def test_gradient_matches_oracle_store_all(wl):
+    d = getattr(synth, wl)
+    say("adjoint vs oracle", wl)
+    dobs = observed(d)
+    sim = make_sim(d)
+    sim.init_ics([synth.SEED_W])
+    sim.run()
+    delta = sim.density()
+    g = 2.0 * (delta.double() - torch.from_numpy(dobs).to(delta.device)).float()
+    dw, ds = sim.adjoint(g)
+    prob = synth.oracle_problem(d)
+    w = ophilox.white_noise(synth.SEED_W, d["n_p"]).astype(np.float64)
+    gw, gs, _ = oadj.gradient(prob, w, lambda dd: 2.0 * (dd - dobs))
+    a = dw.cpu().numpy()[0].astype(np.float64)
+    cos = a @ gw / np.linalg.norm(a) / np.linalg.norm(gw)
+    rel = np.linalg.norm(a - gw) / np.linalg.norm(gw)
+    srel = abs(float(ds[0]) / gs - 1)
+    say(f"{wl}: cosine {cos:.6f} rel L2 {rel:.3e} dsigma8 {float(ds[0]):.6e} vs {gs:.6e}")
+    assert cos > 0.999 and rel < 1e-2 and srel < 1e-2
+
+
+def test_adjoint_returns_to_initial_state():
+    d = synth.C4_SMALL
+    sim = make_sim(d)
+    sim.init_ics([synth.SEED_W])
+    x0, v0 = (t.clone() for t in sim.get_state())
+    sim.run()
+    sim.adjoint(torch.zeros(1, d["n_g"] ** 3, device="cuda"))
+    x1, v1 = sim.get_state()
+    ex = float((x1 - x0).norm() / x0.norm())
+    ev = float((v1 - v0).norm() / v0.norm())
+    say(f"reverse integration: X rel {ex:.2e}, V rel {ev:.2e}")
+    assert ex < 1e-3 and ev < 1e-3
+
+
+def test_gradient_matches_finite_differences_c4():
+    # C4: 128^3 particles, 256^3 mesh, 10 steps; central differences of the
+    # GPU forward (loss summed in FP64) along random unit directions
+    d = synth.C4
+    n_p, n_g = d["n_p"], d["n_g"]
+    say("adjoint vs FD at", n_p)
+    sim = make_sim(d)
+    w = sim.init_ics([synth.SEED_W], return_w=True)
+    sim.run()
+    dobs_sim = make_sim(d, adj=False)
+    dobs_sim.init_ics([synth.SEED_TARGET])
+    dobs_sim.run()
+    dt = dobs_sim.density()
+    gen = torch.Generator(device="cpu").manual_seed(synth.SEED_NOISE)
+    dobs = dt + 0.1 * dt.std() * torch.randn(dt.shape, generator=gen).to(dt.device)
+    del dobs_sim
+
+    def loss(wv):
+        sim.init_ics(w=wv)
+        sim.run()
+        return float(((sim.density().double() - dobs.double()) ** 2).sum())
+
+    sim.init_ics(w=w)
+    sim.run()
+    g = 2.0 * (sim.density() - dobs)
+    dw, _ = sim.adjoint(g)
+    gen = torch.Generator(device="cpu").manual_seed(synth.SEED_DIRS)
+    errs = []
+    for k in range(16):
+        v = torch.randn(w.shape, generator=gen).to(w.device)
+        v /= v.norm()
+        pred = float((dw.double() * v.double()).sum())
+        fds = []
+        for eps in (0.5, 1.0, 2.0):
+            fds.append((loss(w + eps * v) - loss(w - eps * v)) / (2 * eps))
+        fd = float(np.median(fds))
+        errs.append(abs(pred - fd) / abs(fd))
+        say(f"dir {k}: adjoint {pred:.6e} fd {fd:.6e} ({fds}) rel {errs[-1]:.2e}")
+    errs = np.array(errs)
+    assert np.median(errs) < 1e-2 and errs.max() < 5e-2
+
+
+def test_memory_is_flat_in_steps():
+    peaks = []
+    for ns in (5, 20):
+        d = dict(synth.C4_SMALL, n_steps=ns)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        sim = make_sim(d)
+        sim.init_ics([1])
+        sim.run()
+        sim.adjoint(torch.ones(1, d["n_g"] ** 3, device="cuda"))
+        torch.cuda.synchronize()
+        peaks.append(torch.cuda.max_memory_allocated())
+        del sim
+    assert peaks[0] == peaks[1]
