@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark of the PM hot path on one MI355X.
+
+One bench step = one whole pass of the path over one synthetic universe:
+Zel'dovich ICs from seeded white noise, n_steps BullFrog PM steps, the final
+CIC density and its binned P(k), the loss cotangent (L2 distance to a fixed
+observed density), and the adjoint back to dL/dw and dL/dsigma8.
+value = particle-steps/s of forward + adjoint = N n_steps K / t(K steps).
+
+Default workload: 256^3 particles on a 512^3 mesh, L = 500 Mpc/h, flat LCDM
+with BBKS, TSC with deconvolution, 10 steps (FP32 bulk, int64 deposit).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BASE = dict(omega_m=0.31, h=0.68, n_s=0.965, sigma8=0.81, spectrum="bbks", a_start=0.02,
+            a_end=1.0, grad_order=4, lap_order=0)
+WORKLOADS = {
+    "pm_256_512_tsc": dict(BASE, n_p=256, n_g=512, box=500.0, n_steps=10, mak=3, deconvolve=True),
+    "pm_128_256_cic": dict(BASE, n_p=128, n_g=256, box=250.0, n_steps=10, mak=2, deconvolve=False),
+    "pm_512_1024_tsc": dict(BASE, n_p=512, n_g=1024, box=1000.0, n_steps=6, mak=3, deconvolve=True),
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(cls, N, M):
+    """Minimum HBM bytes of one launch of a kernel class (per slot): particle
+    arrays are FP32 [3][N], meshes int64 or FP32 [M]."""
+    return {
+        "deposit": 12 * N + 8 * M,          # read Psi, write the int64 mesh once
+        "gather_kick": 48 * N + 4 * M,      # read/write Psi, V; read phi
+        "adj_kick": 84 * N + 16 * M,        # read Psi,V,Xb,Vb; write V,Xb,Vb; read phi; 3 meshes
+        "adj_drift": 84 * N + 4 * M,        # read Psi,V,Xb,Vb; write Psi,Xb,Vb; read rho_bar
+        "fd_div": 16 * M,                   # read 3 meshes, write 1
+        "fill": None, "fft_rows": None, "fft_cols": None, "misc": None,
+    }[cls]
+
+
+def cpu_baseline():
+    """The FP64 oracle (untuned), same physics at a bounded size."""
+    import numpy as np
+
+    from oracle import adjoint, philox
+    from oracle.force import PMConfig
+    from oracle.nbody import Problem
+
+    n_p, n_g, box, steps = 64, 128, 125.0, 4
+    pm = PMConfig(n_p, n_g, box, order=3, deconvolve=True, grad_order=4, lap_order=0)
+    prob = Problem(pm, omega_m=0.31, h=0.68, n_s=0.965, sigma8=0.81, spectrum="bbks",
+                   a_start=0.02, a_end=1.0, n_steps=steps)
+    w = philox.white_noise(54321, n_p).astype(np.float64)
+    prob.spectrum_fn(), prob.steps()
+    t = time.perf_counter()
+    adjoint.gradient(prob, w, lambda d: 2.0 * d)
+    dt = time.perf_counter() - t
+    return {"value": n_p ** 3 * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 numpy oracle, same physics at {n_p}^3 particles / {n_g}^3 mesh "
+                      f"(L={box} Mpc/h, TSC+deconv, BBKS), {steps} BullFrog steps forward + "
+                      f"store-all reverse, {dt:.1f} s single-threaded on a host with "
+                      f"{os.cpu_count()} cores"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="pm_256_512_tsc", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the path would shard as described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2510_05206_amd as P
+
+    torch.cuda.set_device(0)
+    d = WORKLOADS[args.workload]
+    cfg = P.Config(**d)
+    N, M, n_steps = cfg.N, cfg.M, cfg.n_steps
+    sim = P.PMSim(cfg, with_adjoint=True)
+    # observed density (untimed): the forward of another seed plus 10% noise
+    sim.init_ics([54322])
+    sim.run()
+    dt = sim.density()
+    gen = torch.Generator(device="cpu").manual_seed(54323)
+    dobs = dt + 0.1 * dt.std() * torch.randn(dt.shape, generator=gen).to(dt.device)
+    n_bins = cfg.n_g // 2
+    out = {}
+
+    def one_step(i):
+        sim.init_ics([54321 + i])
+        sim.run()
+        delta = sim.density()
+        out["pk"] = sim.power_spectrum(n_bins)
+        dw, ds = sim.adjoint(2.0 * (delta - dobs))
+        out["dw"], out["ds"] = dw, ds
+
+    for i in range(args.warmup):
+        one_step(i)
+    torch.cuda.synchronize()
+    if not args.no_kernel_timing:
+        sim.profile(True)
+        sim.kernel_times()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step(args.warmup + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = N * n_steps * args.steps / elapsed
+
+    roof = None
+    kt = {}
+    if not args.no_kernel_timing:
+        kt = sim.kernel_times()
+        sim.profile(False)
+        cands = {k: v for k, v in kt.items() if algorithmic_bytes(k, N, M) is not None and v[1] > 0}
+        dom = max(cands, key=lambda k: cands[k][0])
+        ms, n = cands[dom]
+        per = algorithmic_bytes(dom, N, M)
+        achieved = per / (ms / n * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_us": round(ms / n * 1e3, 1), "bytes_per_launch": per}
+    assert math.isfinite(float(out["ds"][0]))
+
+    line = {
+        "metric": "particle-steps/s fwd+adjoint",
+        "value": round(value, 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Philox white noise, BBKS LCDM)",
+        "config": {"workload": args.workload, "n_p": cfg.n_p, "n_g": cfg.n_g, "box": cfg.box,
+                   "n_steps": n_steps, "mak": cfg.mak, "deconvolve": cfg.deconvolve,
+                   "particles": N, "parallelism": "single GPU"},
+        "roofline": roof,
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in kt.items()},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,6 +127,29 @@ pm_status pm_schedule(const pm_ctx* ctx, int32_t slot, double* out);
  * linear-spectrum amplitude A (P = A k^n_s T^2, or A k^-2 exp(-(k/k_c)^2)). */
 pm_status pm_describe(const pm_ctx* ctx, double* out);
 
+/* Kernel classes timed by pm_profile (HIP events on the bound stream). */
+enum {
+  PM_K_FILL = 0,        /* zeroing of meshes and cotangents              */
+  PM_K_DEPOSIT = 1,     /* fixed-point mass assignment                   */
+  PM_K_FFT_ROWS = 2,    /* z-row real<->complex FFT passes               */
+  PM_K_FFT_COLS = 3,    /* y/x strided passes (incl. the fused multiplier) */
+  PM_K_GATHER_KICK = 4, /* force gather + kick + drift                   */
+  PM_K_ADJ_KICK = 5,    /* adjoint kick: reverse kick, direct X_bar, scatter */
+  PM_K_FD_DIV = 6,      /* transposed FD gradient of the cotangent meshes */
+  PM_K_ADJ_DRIFT = 7,   /* scatter-position VJP + reverse drifts          */
+  PM_K_MISC = 8,        /* RNG, P(k), reductions, conversions            */
+  PM_K_COUNT = 9
+};
+
+/* Enable (on != 0) or disable per-launch event timing of the kernel classes
+ * above.  Adds two event records per launch; off by default. */
+pm_status pm_profile(pm_ctx* ctx, int32_t on);
+
+/* Synchronise the bound stream, then return and reset the accumulated time
+ * (ms[PM_K_COUNT], milliseconds) and launch count (launches[PM_K_COUNT]) per
+ * kernel class since the previous call.  Host arrays. */
+pm_status pm_kernel_times(pm_ctx* ctx, double* ms, int64_t* launches);
+
 /* Change the per-slot number of steps (1..n_steps_max of pm_create) and
  * sigma8 before pm_init_ics; NULL keeps the current values. */
 pm_status pm_set_slot_params(pm_ctx* ctx, const int32_t* n_steps, const double* sigma8);

@@ -46,6 +46,17 @@ struct pm_ctx {
   double* dot_partial = nullptr;
   // state
   bool ics_done = false, ran = false;
+  // per-kernel-class event timing (pm_profile / pm_kernel_times)
+  bool prof = false;
+  struct Pending { int cls; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[PM_K_COUNT] = {};
+  long long prof_n[PM_K_COUNT] = {};
+  ~pm_ctx() {
+    for (auto& p : pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+    for (auto e : pool) hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -65,6 +76,38 @@ pm_status fail(pm_ctx* c, pm_status s, const std::string& m) {
     hipError_t _e = (expr);                                                            \
     if (_e != hipSuccess)                                                              \
       return fail(ctx, PM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+  } while (0)
+
+hipEvent_t take_event(pm_ctx* c) {
+  hipEvent_t e = nullptr;
+  if (!c->pool.empty()) {
+    e = c->pool.back();
+    c->pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+void prof_begin(pm_ctx* c, int cls) {
+  if (!c->prof) return;
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return;
+  hipEventRecord(a, c->stream);
+  c->pending.push_back({cls, a, b});
+}
+
+void prof_end(pm_ctx* c) {
+  if (!c->prof || c->pending.empty()) return;
+  hipEventRecord(c->pending.back().b, c->stream);
+}
+
+// launch with optional event timing of its kernel class
+#define KLAUNCH(ctx, cls, expr)   \
+  do {                            \
+    prof_begin(ctx, cls);         \
+    HIPCHK(ctx, expr);            \
+    prof_end(ctx);                \
   } while (0)
 
 struct Layout {
@@ -189,7 +232,7 @@ pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_strid
   r.scale = scale;
   r.shift = shift;
   r.stream = c->stream;
-  HIPCHK(c, fft_rows(r));
+  KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(r));
   ColArgs a{};
   a.data = dst;
   a.slot_stride = dst_stride;
@@ -199,10 +242,10 @@ pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_strid
   a.tws = c->Lmax / n;
   a.active = active;
   a.axis = 1;
-  HIPCHK(c, fft_cols(a, MODE_FWD, c->cfg.batch, c->stream));
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_FWD, c->cfg.batch, c->stream));
   if (do_x) {
     a.axis = 0;
-    HIPCHK(c, fft_cols(a, MODE_FWD, c->cfg.batch, c->stream));
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_FWD, c->cfg.batch, c->stream));
   }
   return PM_OK;
 }
@@ -224,9 +267,9 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
   const double n3 = (double)n * n * n;
   for (int b = 0; b < c->cfg.batch; ++b) a.coef[b] = (float)(-s[b] / (r * n3));
   a.axis = 0;
-  HIPCHK(c, fft_cols(a, MODE_FUSED_H, c->cfg.batch, c->stream));
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_FUSED_H, c->cfg.batch, c->stream));
   a.axis = 1;
-  HIPCHK(c, fft_cols(a, MODE_INV, c->cfg.batch, c->stream));
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_INV, c->cfg.batch, c->stream));
   RowLaunch rl{};
   rl.n = n;
   rl.n_rows = (long long)n * n;
@@ -242,14 +285,14 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
   rl.tws_full = c->Lmax / n;
   rl.scale = 1.0;
   rl.stream = c->stream;
-  HIPCHK(c, fft_rows(rl));
+  KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   return PM_OK;
 }
 
 // deposit of `disp` (optionally drifting by tau first) into the int64 mesh
 pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, int mak,
                   long long* mesh, unsigned long long active) {
-  HIPCHK(c, launch_fill(mesh, (long long)sizeof(long long) * c->g.mesh_stride * c->cfg.batch, c->stream));
+  KLAUNCH(c, PM_K_FILL, launch_fill(mesh, (long long)sizeof(long long) * c->g.mesh_stride * c->cfg.batch, c->stream));
   DepositArgs d{};
   d.g = c->g;
   d.batch = c->cfg.batch;
@@ -258,7 +301,7 @@ pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* ta
   d.mesh = mesh;
   d.active = active;
   for (int b = 0; b < c->cfg.batch; ++b) d.tau[b] = tau ? (float)tau[b] : 0.f;
-  HIPCHK(c, launch_deposit(d, mak, c->stream));
+  KLAUNCH(c, PM_K_DEPOSIT, launch_deposit(d, mak, c->stream));
   return PM_OK;
 }
 
@@ -392,6 +435,34 @@ pm_status pm_describe(const pm_ctx* c, double* out) {
   return PM_OK;
 }
 
+pm_status pm_profile(pm_ctx* c, int32_t on) {
+  if (!c) return PM_EINVAL;
+  c->prof = on != 0;
+  return PM_OK;
+}
+
+pm_status pm_kernel_times(pm_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return PM_EINVAL;
+  if (!c->pending.empty()) HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& p : c->pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+      c->prof_ms[p.cls] += t;
+      c->prof_n[p.cls] += 1;
+    }
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+  for (int k = 0; k < PM_K_COUNT; ++k) {
+    ms[k] = c->prof_ms[k];
+    launches[k] = c->prof_n[k];
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  return PM_OK;
+}
+
 pm_status pm_destroy(pm_ctx* c) {
   delete c;
   return PM_OK;
@@ -425,7 +496,7 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
   if (w_in)
     HIPCHK(c, hipMemcpyAsync(c->w, w_in, sizeof(float) * N * B, hipMemcpyDeviceToDevice, c->stream));
   else
-    HIPCHK(c, launch_white_noise(c->w, N, N, B, seeds, c->stream));
+    KLAUNCH(c, PM_K_MISC, launch_white_noise(c->w, N, N, B, seeds, c->stream));
   float2* wspec = c->icspec + 3 * c->icspec_comp;
   pm_status st = r2c_mesh(c, c->w, SRC_F32, N, 1.0, 0.0, wspec, c->icspec_stride, np, true, act);
   if (st) return st;
@@ -445,11 +516,11 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
     a.axis = 0;
     a.comp = comp;
     a.dst3 = out;
-    HIPCHK(c, fft_cols(a, MODE_IC_C, B, c->stream));
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_IC_C, B, c->stream));
     ColArgs y = a;
     y.data = out;
     y.axis = 1;
-    HIPCHK(c, fft_cols(y, MODE_INV, B, c->stream));
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
     RowLaunch rl{};
     rl.n = np;
     rl.n_rows = (long long)np * np;
@@ -467,7 +538,7 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
     rl.scale = 1.0;
     rl.scale2 = c->D0;
     rl.stream = c->stream;
-    HIPCHK(c, fft_rows(rl));
+    KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   }
   if (w_out)
     HIPCHK(c, hipMemcpyAsync(w_out, c->w, sizeof(float) * N * B, hipMemcpyDeviceToDevice, c->stream));
@@ -493,7 +564,7 @@ static pm_status step_common(pm_ctx* c, const double* tau_pre, bool pre_drift, c
     a.beta[b] = (float)beta[b];
     a.tau[b] = (float)tau_post[b];
   }
-  HIPCHK(c, launch_gather(a, GK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
+  KLAUNCH(c, PM_K_GATHER_KICK, launch_gather(a, GK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
   return PM_OK;
 }
 
@@ -551,8 +622,8 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   const int B = c->cfg.batch, np = c->cfg.n_p;
   const long long N = c->g.N, M = c->g.M;
   const double mfac = (double)M / (double)N;
-  HIPCHK(c, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
-  HIPCHK(c, launch_fill(c->vbar, (long long)sizeof(float) * 3 * N * B, c->stream));
+  KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
+  KLAUNCH(c, PM_K_FILL, launch_fill(c->vbar, (long long)sizeof(float) * 3 * N * B, c->stream));
   int nmax = 0;
   for (int b = 0; b < B; ++b) nmax = std::max(nmax, c->slot_steps[b]);
   // loss pullback through the final CIC density and the last half drift
@@ -570,7 +641,7 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
     a.coef[b] = (float)mfac;
     a.tau[b] = (float)c->slot_table[b][c->slot_steps[b] - 1].tau2;
   }
-  HIPCHK(c, launch_gather(a, GK_ADJ_DRIFT, 2, c->cfg.grad_order, c->stream));
+  KLAUNCH(c, PM_K_ADJ_DRIFT, launch_gather(a, GK_ADJ_DRIFT, 2, c->cfg.grad_order, c->stream));
   for (int n = nmax - 1; n >= 0; --n) {
     std::vector<double> s(B, 1);
     unsigned long long act = 0;
@@ -579,7 +650,7 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
     // force at X^{n+1/2}
     pm_status st = potential(c, c->disp, nullptr, nullptr, s.data(), act);
     if (st) return st;
-    HIPCHK(c, launch_fill(c->gbar, (long long)sizeof(float) * 3 * M * B, c->stream));
+    KLAUNCH(c, PM_K_FILL, launch_fill(c->gbar, (long long)sizeof(float) * 3 * M * B, c->stream));
     GatherArgs k = a;
     k.phi = c->phi;
     k.active = act;
@@ -589,10 +660,10 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
       k.alpha[b] = (float)sc.alpha;
       k.beta[b] = (float)sc.beta;
     }
-    HIPCHK(c, launch_gather(k, GK_ADJ_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
+    KLAUNCH(c, PM_K_ADJ_KICK, launch_gather(k, GK_ADJ_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
     // mesh cotangent: d = sum_c FD_c^T g_bar_c, then the transposed multiplier
     float* d = reinterpret_cast<float*>(c->mesh);
-    HIPCHK(c, launch_fd_div(c->gbar, d, c->g, B, c->cfg.grad_order, act, c->stream));
+    KLAUNCH(c, PM_K_FD_DIV, launch_fd_div(c->gbar, d, c->g, B, c->cfg.grad_order, act, c->stream));
     st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
     if (st) return st;
     st = poisson_to_real(c, s.data(), c->phi, act);
@@ -606,12 +677,12 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
       const auto& T = c->slot_table[b];
       dr.tau[b] = (float)(T[n].tau1 + (n > 0 ? T[n - 1].tau2 : 0.0));
     }
-    HIPCHK(c, launch_gather(dr, GK_ADJ_DRIFT, c->cfg.mak, c->cfg.grad_order, c->stream));
+    KLAUNCH(c, PM_K_ADJ_DRIFT, launch_gather(dr, GK_ADJ_DRIFT, c->cfg.mak, c->cfg.grad_order, c->stream));
   }
   // initial conditions: psi_bar = D0 X_bar + V_bar, w_bar = sum_c T_c^T psi_bar_c
   std::vector<float> d0(B, (float)c->D0);
   float* psibar = c->gbar;
-  HIPCHK(c, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->stream));
+  KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->stream));
   const unsigned long long act = all_mask(B);
   for (int comp = 0; comp < 3; ++comp) {
     pm_status st = r2c_mesh(c, psibar + comp * N, SRC_F32, 3 * N, 1.0, 0.0,
@@ -633,9 +704,9 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   ca.axis = 0;
   for (int b = 0; b < B; ++b)
     ca.fac[b] = (float)(c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0);
-  HIPCHK(c, fft_cols(ca, MODE_COMBINE_IC, B, c->stream));
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(ca, MODE_COMBINE_IC, B, c->stream));
   ca.axis = 1;
-  HIPCHK(c, fft_cols(ca, MODE_INV, B, c->stream));
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(ca, MODE_INV, B, c->stream));
   RowLaunch rl{};
   rl.n = np;
   rl.n_rows = (long long)np * np;
@@ -651,11 +722,11 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   rl.tws_full = c->Lmax / np;
   rl.scale = 1.0;
   rl.stream = c->stream;
-  HIPCHK(c, fft_rows(rl));
+  KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   // dL/dsigma8 = <psi_bar, psi>/sigma8 = <w_bar, w>/sigma8 (psi is linear in w and sigma8)
   std::vector<double> inv(B);
   for (int b = 0; b < B; ++b) inv[b] = 1.0 / c->slot_sigma8[b];
-  HIPCHK(c, launch_dot(dL_dw, c->w, N, N, B, c->dot_partial, dL_dsigma8, inv.data(), c->stream));
+  KLAUNCH(c, PM_K_MISC, launch_dot(dL_dw, c->w, N, N, B, c->dot_partial, dL_dsigma8, inv.data(), c->stream));
   c->ran = false;
   return PM_OK;
 }
@@ -675,7 +746,7 @@ pm_status pm_power_spectrum(pm_ctx* c, int32_t n_bins, int32_t deconvolve_cic, d
                 c->g.spec_stride, n, true, act);
   if (st) return st;
   const double L = c->cfg.box;
-  HIPCHK(c, launch_pk(c->spec, c->g.spec_stride, n, c->cfg.batch, n_bins, 2.0 * M_PI / L,
+  KLAUNCH(c, PM_K_MISC, launch_pk(c->spec, c->g.spec_stride, n, c->cfg.batch, n_bins, 2.0 * M_PI / L,
                       L * L * L / (n3 * n3), c->d_cic4, deconvolve_cic, c->pk_partial, k_mean, pk,
                       (long long*)n_modes, c->stream));
   return PM_OK;
@@ -689,7 +760,7 @@ pm_status pm_density(pm_ctx* c, float* delta_out, int64_t* fixed_out) {
   if (st) return st;
   const double scale = (double)c->g.M / (double)c->g.N / 4294967296.0;
   if (delta_out)
-    HIPCHK(c, launch_i64_to_delta(c->mesh, delta_out, c->g.M, c->g.mesh_stride, c->cfg.batch, scale, c->stream));
+    KLAUNCH(c, PM_K_MISC, launch_i64_to_delta(c->mesh, delta_out, c->g.M, c->g.mesh_stride, c->cfg.batch, scale, c->stream));
   if (fixed_out)
     HIPCHK(c, hipMemcpyAsync(fixed_out, c->mesh, sizeof(long long) * c->g.M * c->cfg.batch,
                              hipMemcpyDeviceToDevice, c->stream));
@@ -737,7 +808,7 @@ pm_status pm_force(pm_ctx* c, const float* disp, double s, float* acc_out) {
   a.phi = c->phi;
   a.acc_out = acc_out;
   a.active = act;
-  HIPCHK(c, launch_gather(a, GK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
+  KLAUNCH(c, PM_K_GATHER_KICK, launch_gather(a, GK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
   return PM_OK;
 }
 
@@ -767,9 +838,9 @@ pm_status pm_fft(pm_ctx* c, const void* in, void* out, int32_t inverse) {
   a.tws = c->Lmax / n;
   a.active = act;
   a.axis = 0;
-  HIPCHK(c, fft_cols(a, MODE_INV, B, c->stream));
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_INV, B, c->stream));
   a.axis = 1;
-  HIPCHK(c, fft_cols(a, MODE_INV, B, c->stream));
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_INV, B, c->stream));
   RowLaunch rl{};
   rl.n = n;
   rl.n_rows = (long long)n * n;
@@ -785,7 +856,7 @@ pm_status pm_fft(pm_ctx* c, const void* in, void* out, int32_t inverse) {
   rl.tws_full = c->Lmax / n;
   rl.scale = 1.0;
   rl.stream = c->stream;
-  HIPCHK(c, fft_rows(rl));
+  KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   return PM_OK;
 }
 

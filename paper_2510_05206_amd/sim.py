@@ -180,6 +180,17 @@ class PMSim:
     def synchronize(self):
         self.stream.synchronize()
 
+    def profile(self, on=True):
+        self._call("pm_profile", int(bool(on)))
+
+    def kernel_times(self):
+        """{class: (total ms, launches)} since the previous call (synchronises)."""
+        K = len(_lib.KERNEL_CLASSES)
+        ms = (C.c_double * K)()
+        n = (C.c_int64 * K)()
+        self._call("pm_kernel_times", C.cast(ms, C.c_void_p), C.cast(n, C.c_void_p))
+        return {name: (ms[i], n[i]) for i, name in enumerate(_lib.KERNEL_CLASSES)}
+
 
 class PMFunction(torch.autograd.Function):
     """delta_final = F(w): forward runs ICs + BullFrog steps on the GPU and
