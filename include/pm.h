@@ -129,16 +129,18 @@ pm_status pm_describe(const pm_ctx* ctx, double* out);
 
 /* Kernel classes timed by pm_profile (HIP events on the bound stream). */
 enum {
-  PM_K_FILL = 0,        /* zeroing of meshes and cotangents              */
-  PM_K_DEPOSIT = 1,     /* fixed-point mass assignment                   */
+  PM_K_FILL = 0,        /* zeroing of counters and cotangents            */
+  PM_K_DEPOSIT = 1,     /* fixed-point mass assignment into tile windows */
   PM_K_FFT_ROWS = 2,    /* z-row real<->complex FFT passes               */
   PM_K_FFT_COLS = 3,    /* y/x strided passes (incl. the fused multiplier) */
   PM_K_GATHER_KICK = 4, /* force gather + kick + drift                   */
-  PM_K_ADJ_KICK = 5,    /* adjoint kick: reverse kick, direct X_bar, scatter */
-  PM_K_FD_DIV = 6,      /* transposed FD gradient of the cotangent meshes */
+  PM_K_ADJ_KICK = 5,    /* adjoint kick: reverse kick, direct X_bar       */
+  PM_K_DIPOLE = 6,      /* transposed force gather of the cotangent       */
   PM_K_ADJ_DRIFT = 7,   /* scatter-position VJP + reverse drifts          */
   PM_K_MISC = 8,        /* RNG, P(k), reductions, conversions            */
-  PM_K_COUNT = 9
+  PM_K_BIN = 9,         /* counting sort of particles by mesh tile        */
+  PM_K_ASSEMBLE = 10,   /* halo sum of the tile windows into a mesh       */
+  PM_K_COUNT = 11
 };
 
 /* Enable (on != 0) or disable per-launch event timing of the kernel classes
@@ -149,6 +151,13 @@ pm_status pm_profile(pm_ctx* ctx, int32_t on);
  * (ms[PM_K_COUNT], milliseconds) and launch count (launches[PM_K_COUNT]) per
  * kernel class since the previous call.  Host arrays. */
 pm_status pm_kernel_times(pm_ctx* ctx, double* ms, int64_t* launches);
+
+/* Restrict pm_init_ics, pm_step, pm_run, pm_adjoint, pm_power_spectrum and
+ * pm_density to the slots whose bit is set in mask (default: all B slots);
+ * the other slots' state and outputs are left untouched.  This is how a
+ * serving loop refills and reads out single slots of a running batch.
+ * PM_EINVAL for an empty mask or bits beyond the batch. */
+pm_status pm_set_active(pm_ctx* ctx, uint64_t mask);
 
 /* Change the per-slot number of steps (1..n_steps_max of pm_create) and
  * sigma8 before pm_init_ics; NULL keeps the current values. */

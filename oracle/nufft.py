@@ -95,35 +95,42 @@ def nudft_force_direct(n_p, n_f, psi, s):
     return A
 
 
+def _es_axis_weights(u, width, beta):
+    """First node floor(u) - w/2 + 1 and the w kernel values per axis."""
+    base = np.floor(u).astype(np.int64) - (width // 2 - 1)
+    wts = [np.stack([es_kernel(base[a] + o - u[a], width, beta) for o in range(width)])
+           for a in range(3)]
+    return base, wts
+
+
 def _spread_float(u, n_f, width, beta, weights=None):
     """b_j = sum_i w_i phi(j - u_i) on the periodic n_f^3 grid (FP64); the
     stencil is the w nodes floor(u) - w/2 + 1 .. floor(u) + w/2 (even w)."""
     assert width % 2 == 0
     N = u.shape[1]
     w_i = np.ones(N) if weights is None else weights
-    base = np.floor(u).astype(np.int64) - (width // 2 - 1)
-    wts = [np.stack([es_kernel(base[a] + o - u[a], width, beta) for o in range(width)])
-           for a in range(3)]
+    base, wts = _es_axis_weights(u, width, beta)
     out = np.zeros(n_f ** 3)
     for a in range(width):
         ix = (base[0] + a) % n_f
+        idx, val = [], []
         for b in range(width):
             iy = (base[1] + b) % n_f
             wab = wts[0][a] * wts[1][b] * w_i
             for c in range(width):
                 iz = (base[2] + c) % n_f
-                out += np.bincount((ix * n_f + iy) * n_f + iz, weights=wab * wts[2][c],
-                                   minlength=n_f ** 3)
+                idx.append((ix * n_f + iy) * n_f + iz)
+                val.append(wab * wts[2][c])
+        # one accumulation per x offset (same sum, fewer passes over the grid)
+        out += np.bincount(np.concatenate(idx), weights=np.concatenate(val), minlength=n_f ** 3)
     return out
 
 
 def _interp_float(field, u, n_f, width, beta):
-    N = u.shape[1]
-    f = field.reshape(-1)
-    base = np.floor(u).astype(np.int64) - (width // 2 - 1)
-    wts = [np.stack([es_kernel(base[a] + o - u[a], width, beta) for o in range(width)])
-           for a in range(3)]
-    v = np.zeros(N)
+    """v_i = sum_j field_j phi(u_i - j); field may carry trailing components."""
+    f = field.reshape(n_f ** 3, -1)
+    base, wts = _es_axis_weights(u, width, beta)
+    v = np.zeros((u.shape[1], f.shape[1]))
     for a in range(width):
         ix = (base[0] + a) % n_f
         for b in range(width):
@@ -131,7 +138,7 @@ def _interp_float(field, u, n_f, width, beta):
             wab = wts[0][a] * wts[1][b]
             for c in range(width):
                 iz = (base[2] + c) % n_f
-                v += f[(ix * n_f + iy) * n_f + iz] * wab * wts[2][c]
+                v += f[(ix * n_f + iy) * n_f + iz] * (wab * wts[2][c])[:, None]
     return v
 
 
@@ -150,14 +157,14 @@ def nufft_force(n_p, n_f, psi, s, width=6, beta=13.8):
     delta = sub * (n_p ** 3 / N)
     MX, MY, MZ = np.meshgrid(ms, ms, mz, indexing="ij")
     K = _force_multiplier(MX, MY, MZ, n_p, s)
-    A = np.empty((3, N))
+    meshes = []
     for c in range(3):
         g = K[c] * delta / (ph(ms)[:, None, None] * ph(ms)[None, :, None] * ph(mz)[None, None, :])
         full = np.zeros((n_f, n_f, n_f // 2 + 1), dtype=np.complex128)
         full[np.ix_(ix, ix, mz)] = g
-        c_j = np.fft.irfftn(full, s=(n_f, n_f, n_f), axes=(0, 1, 2)) * n_f ** 3
-        A[c] = _interp_float(c_j, u, n_f, width, beta) / n_p ** 3
-    return A
+        meshes.append(np.fft.irfftn(full, s=(n_f, n_f, n_f), axes=(0, 1, 2)).reshape(-1) * n_f ** 3)
+    # interpolate the three components together
+    return _interp_float(np.stack(meshes, axis=1), u, n_f, width, beta).T / n_p ** 3
 
 
 # --------------------------------------------------------------------------

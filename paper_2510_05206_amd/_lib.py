@@ -15,8 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libpm.so")
 PM_OK, PM_EINVAL, PM_ENOMEM, PM_EHIP, PM_ESTATE, PM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_ENOMEM", -3: "PM_EHIP", -4: "PM_ESTATE",
                 -5: "PM_EUNSUPPORTED"}
-KERNEL_CLASSES = ["fill", "deposit", "fft_rows", "fft_cols", "gather_kick", "adj_kick", "fd_div",
-                  "adj_drift", "misc"]
+KERNEL_CLASSES = ["fill", "deposit", "fft_rows", "fft_cols", "gather_kick", "adj_kick", "dipole",
+                  "adj_drift", "misc", "bin", "assemble"]
 PM_FORCE_PM, PM_FORCE_NUFFT = 0, 1
 PM_SPEC_POWERLAW, PM_SPEC_BBKS = 0, 1
 
@@ -47,6 +47,7 @@ EXPORTS = {
     "pm_describe": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pm_last_error": (C.c_char_p, [C.c_void_p]),
     "pm_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pm_set_active": (C.c_int, [C.c_void_p, C.c_uint64]),
     "pm_kernel_times": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_set_slot_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_init_ics": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

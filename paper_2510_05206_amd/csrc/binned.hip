@@ -1,0 +1,693 @@
+// Tile-binned particle <-> mesh kernels (no global atomics on the mesh).
+//
+// Once per force evaluation the particles are counting-sorted by the
+// 16^3-cell tile that holds their home node (k_bin_count / k_bin_scan /
+// k_bin_scatter).  Each later kernel runs one workgroup per tile over that
+// tile's particles:
+//   k_tile_deposit   accumulates the fixed-point CIC/TSC mass in an int64 LDS
+//                    window (tile + 1 cell each side) and writes the whole
+//                    window to a scratch slab;
+//   k_assemble       sums, for every cell, the window values of the (up to 8)
+//                    tiles whose window covers it (integers: order-free);
+//   k_tile_kick      stages the potential over the tile + stencil reach in LDS
+//                    and does the FD-gradient gather, kick and drift;
+//   k_tile_adj_kick  the same gather with the position gradient for the
+//                    adjoint kick, writing u = beta V_bar in sorted order;
+//   k_tile_dipole    scatters u through the transposed gather (kernel x FD
+//                    stencil) into an int64 LDS window, in fixed point with a
+//                    scale set by max|u| (deterministic);
+//   k_tile_adj_drift gradient gather of the mesh cotangent and reverse drifts.
+// The windows make each HBM access coalesced and each particle's stencil an
+// LDS access; the mesh is written once per pass.
+#include "mak.h"
+
+namespace pm {
+
+constexpr int kTileMax = 16;
+
+struct TileGeo {
+  int T, log2T, log2nt, n_tiles;
+  long long ts;  // ints per slot of count/offset
+};
+
+__device__ __forceinline__ void tile_origin(int t, const TileGeo& tg, int o[3]) {
+  const int m = (1 << tg.log2nt) - 1;
+  o[2] = (t & m) << tg.log2T;
+  o[1] = ((t >> tg.log2nt) & m) << tg.log2T;
+  o[0] = (t >> (2 * tg.log2nt)) << tg.log2T;
+}
+
+// ------------------------------------------------------------- binning
+
+template <int P>
+__global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
+  const int slot = blockIdx.y;
+  if (!((a.active >> slot) & 1ull)) return;
+  const long long N = a.g.N;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = i < N;
+  const long long ps = slot * a.g.part_stride;
+  int tile = -1;
+  if (valid) {
+    float p[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    if (a.vel) {  // merged first drift X += tau V, written back
+      const float t = a.tau[slot];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        p[c] += t * a.vel[ps + c * N + i];
+        a.disp[ps + c * N + i] = p[c];
+      }
+    }
+    long long j[3];
+    lattice_of(i, a.g.log2_np, j);
+    const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+    const int nm = a.g.n_g - 1;
+    int h[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) h[c] = home_node<P>(fixed_coord(j[c], p[c], a.g.log2_r, umask), nm);
+    tile = (((h[0] >> a.log2T) << a.log2nt | (h[1] >> a.log2T)) << a.log2nt) | (h[2] >> a.log2T);
+  }
+  // wave-aggregated counting: one atomic per distinct tile in the wave
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(valid);
+  int rank = 0;
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const int lt = __shfl(tile, leader);
+    const unsigned long long m = __ballot(valid && tile == lt) & pending;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(a.count + slot * a.ts + lt, (int)__popcll(m));
+    base = __shfl(base, leader);
+    if ((m >> lane) & 1ull) rank = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+    pending &= ~m;
+  }
+  if (valid) {
+    a.key[slot * N + i] = tile;
+    a.rank[slot * N + i] = rank;
+  }
+}
+
+// exclusive scan of the tile counts, one 1024-thread block per slot
+__global__ void __launch_bounds__(1024) k_bin_scan(const int32_t* count, int32_t* offset, int n_tiles,
+                                                   long long ts) {
+  __shared__ int sh[1024];
+  const int slot = blockIdx.x;
+  const int32_t* cn = count + slot * ts;
+  int32_t* of = offset + slot * ts;
+  const int chunk = (n_tiles + 1023) / 1024;
+  const int s0 = threadIdx.x * chunk;
+  int sum = 0;
+  for (int k = 0; k < chunk; ++k)
+    if (s0 + k < n_tiles) sum += cn[s0 + k];
+  sh[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - sum;  // exclusive prefix of this chunk
+  for (int k = 0; k < chunk; ++k)
+    if (s0 + k < n_tiles) {
+      of[s0 + k] = run;
+      run += cn[s0 + k];
+    }
+  if (threadIdx.x == 1023) of[n_tiles] = sh[1023];
+}
+
+__global__ void __launch_bounds__(256) k_bin_scatter(BinArgs a) {
+  const int slot = blockIdx.y;
+  if (!((a.active >> slot) & 1ull)) return;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.g.N) return;
+  const long long N = a.g.N;
+  const int t = a.key[slot * N + i];
+  a.sorted[slot * N + a.offset[slot * a.ts + t] + a.rank[slot * N + i]] = (int32_t)i;
+}
+
+// ------------------------------------------------------------- deposit
+
+template <int P>
+__global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
+  __shared__ unsigned long long win[(kTileMax + 2) * (kTileMax + 2) * (kTileMax + 2)];
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int T = a.T, W = T + 2, W3 = W * W * W;
+  for (int e = threadIdx.x; e < W3; e += 256) win[e] = 0ull;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  __syncthreads();
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+  constexpr int shift = 3 * kWeightBits - kMassBits;
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    long long j[3];
+    lattice_of(i, a.g.log2_np, j);
+    int w[3][P], l0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
+      weights1d<P>(U, w[c]);
+      // local index of the first stencil node in the window (home at h - o + 1)
+      l0[c] = home_node<P>(U, nm) - o[c] + 1 - (P == 3 ? 1 : 0);
+    }
+    unsigned long long sum = 0, best = 0;
+    int home = 0;
+#pragma unroll
+    for (int x = 0; x < P; ++x)
+#pragma unroll
+      for (int y = 0; y < P; ++y) {
+        unsigned long long wxy = (unsigned long long)w[0][x] * (unsigned)w[1][y];
+#pragma unroll
+        for (int z = 0; z < P; ++z) {
+          unsigned long long q = wxy * (unsigned)w[2][z];
+          sum += rne_shift(q, shift);
+          if (q > best) { best = q; home = (x * P + y) * P + z; }
+        }
+      }
+    const long long rem = (1ll << kMassBits) - (long long)sum;
+#pragma unroll
+    for (int x = 0; x < P; ++x)
+#pragma unroll
+      for (int y = 0; y < P; ++y) {
+        unsigned long long wxy = (unsigned long long)w[0][x] * (unsigned)w[1][y];
+        const int bxy = ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
+#pragma unroll
+        for (int z = 0; z < P; ++z) {
+          long long v = (long long)rne_shift(wxy * (unsigned)w[2][z], shift);
+          if ((x * P + y) * P + z == home) v += rem;
+          if (v) atomicAdd(&win[bxy + z], (unsigned long long)v);
+        }
+      }
+  }
+  __syncthreads();
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(a.scratch) +
+                            ((long long)slot * a.n_tiles + t) * W3;
+  for (int e = threadIdx.x; e < W3; e += 256) out[e] = win[e];
+}
+
+// Sum the windows covering each cell: along each axis the own tile at
+// local l + R, the previous tile at l + T + R when l < R, the next tile at
+// l - T + R when l >= T - R.  OUT_F32 converts int64 sums with inv_scale.
+template <bool OUT_F32>
+__global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
+  const int slot = blockIdx.y;
+  if (!((a.active >> slot) & 1ull)) return;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.g.M) return;
+  const int L = a.g.log2_ng, nm = a.g.n_g - 1;
+  const int x[3] = {(int)(e >> (2 * L)), (int)((e >> L) & nm), (int)(e & nm)};
+  const int T = a.T, R = a.R, W = T + 2 * R;
+  const int ntm = (1 << a.log2nt) - 1;
+  int tl[3][3], ll[3][3], nc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int tc = x[c] >> a.log2T, l = x[c] & (T - 1);
+    int k = 0;
+    tl[c][k] = tc; ll[c][k] = l + R; ++k;
+    if (l < R) { tl[c][k] = (tc - 1) & ntm; ll[c][k] = l + T + R; ++k; }
+    if (l >= T - R) { tl[c][k] = (tc + 1) & ntm; ll[c][k] = l - T + R; ++k; }
+    nc[c] = k;
+  }
+  const long long* src = reinterpret_cast<const long long*>(a.scratch);
+  const long long W3 = (long long)W * W * W;
+  long long acc = 0;
+  for (int p = 0; p < nc[0]; ++p)
+    for (int q = 0; q < nc[1]; ++q)
+      for (int r = 0; r < nc[2]; ++r) {
+        long long t = ((long long)tl[0][p] << (2 * a.log2nt)) | (tl[1][q] << a.log2nt) | tl[2][r];
+        acc += src[((long long)slot * a.n_tiles + t) * W3 + ((long long)ll[0][p] * W + ll[1][q]) * W + ll[2][r]];
+      }
+  if constexpr (OUT_F32)
+    reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = (float)((double)acc * a.inv_scale[slot]);
+  else
+    reinterpret_cast<long long*>(a.out)[slot * a.g.mesh_stride + e] = acc;
+}
+
+// ----------------------------------------------------- windowed gathers
+
+// stage mesh values over the tile + R cells each side into LDS
+__device__ __forceinline__ void load_window(float* win, const float* mesh, const int o[3], int T, int R,
+                                            int L, int nm) {
+  const int W = T + 2 * R, W3 = W * W * W;
+  for (int e = threadIdx.x; e < W3; e += 256) {
+    int lz = e % W, r = e / W, ly = r % W, lx = r / W;
+    int gx = (o[0] - R + lx) & nm, gy = (o[1] - R + ly) & nm, gz = (o[2] - R + lz) & nm;
+    win[e] = mesh[((long long)((gx << L) + gy) << L) + gz];
+  }
+}
+
+struct WinAcc {
+  const float* w;
+  int W;
+  __device__ float operator()(int x, int y, int z) const { return w[(x * W + y) * W + z]; }
+};
+
+// kernel weights (float) and the window-local first node of each axis
+template <int P>
+__device__ __forceinline__ void tile_weights(const TileArgs& a, long long i, const float p[3], const int o[3],
+                                             int R, float w[3][P], float dw[3][P], int l0[3]) {
+  long long j[3];
+  lattice_of(i, a.g.log2_np, j);
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    long long U = fixed_coord(j[c], p[c], a.g.log2_r, umask);
+    weights1d_f<P>(U, w[c], dw[c]);
+    l0[c] = home_node<P>(U, nm) - o[c] + R - (P == 3 ? 1 : 0);
+  }
+}
+
+// forward: A = gather(FD phi); V = alpha V + beta A; X += tau V (or A only)
+template <int P, int ORD>
+__global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
+  constexpr int R = 1 + ORD / 2;
+  __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, a.g.log2_ng, a.g.n_g - 1);
+  __syncthreads();
+  const WinAcc acc{win, a.T + 2 * R};
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const float al = a.alpha[slot], be = a.beta[slot], tp = a.tau[slot];
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][P], dw[3][P], A[3], dA[3][3];
+    int l0[3];
+    tile_weights<P>(a, i, x, o, R, w, dw, l0);
+    fd_gather<P, ORD, false>(acc, l0, w, dw, A, dA);
+    if (a.acc_out) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.acc_out[ps + c * N + i] = A[c];
+      continue;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float v = al * a.vel[ps + c * N + i] + be * A[c];
+      a.vel[ps + c * N + i] = v;
+      a.disp[ps + c * N + i] = x[c] + tp * v;
+    }
+  }
+}
+
+// adjoint kick at X^{n-1/2}: V^{n-1} = (V^n - beta A)/alpha; X_bar += r sum_c
+// u_c dA_c/du (u = beta V_bar); V_bar *= alpha; u stored in sorted order and
+// max|u| reduced per slot (fixed-point scale of the scatter)
+template <int P, int ORD>
+__global__ void __launch_bounds__(256) k_tile_adj_kick(TileArgs a) {
+  constexpr int R = 1 + ORD / 2;
+  __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
+  __shared__ float red[256];
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, a.g.log2_ng, a.g.n_g - 1);
+  __syncthreads();
+  const WinAcc acc{win, a.T + 2 * R};
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const float al = a.alpha[slot], be = a.beta[slot];
+  const float r = (float)(1 << a.g.log2_r);
+  float umax = 0.f;
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][P], dw[3][P], A[3], dA[3][3];
+    int l0[3];
+    tile_weights<P>(a, i, x, o, R, w, dw, l0);
+    fd_gather<P, ORD, true>(acc, l0, w, dw, A, dA);
+    float u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float vb = a.vbar[ps + c * N + i];
+      u[c] = be * vb;
+      a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A[c]) / al;
+      a.vbar[ps + c * N + i] = al * vb;
+      a.u_sorted[ps + c * N + p] = u[c];
+      umax = fmaxf(umax, fabsf(u[c]));
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      a.xbar[ps + d * N + i] += r * (u[0] * dA[0][d] + u[1] * dA[1][d] + u[2] * dA[2][d]);
+  }
+  red[threadIdx.x] = umax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] > 0.f)
+    atomicMax(reinterpret_cast<unsigned int*>(a.umax) + slot, __float_as_uint(red[0]));
+}
+
+// fixed-point scale of the cotangent scatter: every node sum is bounded by
+// N max|u| sum|c_s| (times 3 components), kept below 2^61
+__global__ void k_dipole_scale(const unsigned int* umax_bits, double* scale, double* inv_scale, double bound_per_u,
+                               int batch) {
+  const int s = threadIdx.x;
+  if (s >= batch) return;
+  double m = (double)__uint_as_float(umax_bits[s]) * bound_per_u;
+  int e = m > 0.0 ? ilogb(m) + 1 : 0;
+  if (e < -200) e = -200;
+  scale[s] = ldexp(1.0, 61 - e);
+  inv_scale[s] = ldexp(1.0, e - 61);
+}
+
+// transposed FD gather (mesh cotangent of the force), into an int64 window
+// covering the tile + R cells: phi_bar(node) += u_c G_c[t] w w
+template <int P, int ORD>
+__global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
+  constexpr int H = ORD / 2, R = 1 + H, Q = P + 2 * H;
+  extern __shared__ unsigned long long dwin[];
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int W = a.T + 2 * R, W3 = W * W * W;
+  for (int e = threadIdx.x; e < W3; e += 256) dwin[e] = 0ull;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  __syncthreads();
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const double S = a.scale[slot];
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][P], dw[3][P];
+    int l0[3];
+    tile_weights<P>(a, i, x, o, R, w, dw, l0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float uc = a.u_sorted[ps + c * N + p];
+      float G[Q];
+#pragma unroll
+      for (int tt = 0; tt < Q; ++tt) {
+        float g = 0.f;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          int s = tt - H - q;
+          if (s >= -H && s <= H) g += w[c][q] * fd_coef<ORD>(s);
+        }
+        G[tt] = g * uc;
+      }
+      const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+#pragma unroll
+      for (int tt = 0; tt < Q; ++tt) {
+        if (G[tt] == 0.f) continue;
+#pragma unroll
+        for (int q1 = 0; q1 < P; ++q1)
+#pragma unroll
+          for (int q2 = 0; q2 < P; ++q2) {
+            int n3[3];
+            n3[c] = l0[c] - H + tt;
+            n3[a1] = l0[a1] + q1;
+            n3[a2] = l0[a2] + q2;
+            long long v = llrint((double)(G[tt] * w[a1][q1] * w[a2][q2]) * S);
+            if (v) atomicAdd(&dwin[(n3[0] * W + n3[1]) * W + n3[2]], (unsigned long long)v);
+          }
+      }
+    }
+  }
+  __syncthreads();
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(a.scratch) + ((long long)slot * a.n_tiles + t) * W3;
+  for (int e = threadIdx.x; e < W3; e += 256) out[e] = dwin[e];
+}
+
+// scatter-w.r.t.-positions: X_bar += coef r sum_j rho_bar_j dW_j/du, then the
+// reverse drift X -= tau V, V_bar += tau X_bar
+template <int P>
+__global__ void __launch_bounds__(256) k_tile_adj_drift(TileArgs a) {
+  constexpr int R = 1;
+  __shared__ float win[(kTileMax + 2) * (kTileMax + 2) * (kTileMax + 2)];
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, a.g.log2_ng, a.g.n_g - 1);
+  __syncthreads();
+  const int W = a.T + 2;
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const float cf = a.coef[slot] * (float)(1 << a.g.log2_r), tau = a.tau[slot];
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][P], dw[3][P];
+    int l0[3];
+    tile_weights<P>(a, i, x, o, R, w, dw, l0);
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int xx = 0; xx < P; ++xx)
+#pragma unroll
+      for (int yy = 0; yy < P; ++yy) {
+        const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+#pragma unroll
+        for (int zz = 0; zz < P; ++zz) {
+          float f = win[b + zz];
+          gx += f * dw[0][xx] * w[1][yy] * w[2][zz];
+          gy += f * w[0][xx] * dw[1][yy] * w[2][zz];
+          gz += f * w[0][xx] * w[1][yy] * dw[2][zz];
+        }
+      }
+    float g[3] = {gx, gy, gz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float xb = a.xbar[ps + c * N + i] + cf * g[c];
+      float v = a.vel[ps + c * N + i];
+      a.disp[ps + c * N + i] = x[c] - tau * v;
+      a.xbar[ps + c * N + i] = xb;
+      a.vbar[ps + c * N + i] += tau * xb;
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s) {
+  dim3 grid((unsigned)((a.g.N + 255) / 256), a.batch);
+  if (mak == 2) k_bin_count<2><<<grid, 256, 0, s>>>(a);
+  else k_bin_count<3><<<grid, 256, 0, s>>>(a);
+  k_bin_scan<<<a.batch, 1024, 0, s>>>(a.count, a.offset, a.n_tiles, a.ts);
+  k_bin_scatter<<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile(const TileArgs& a, int kind, int mak, int ord, hipStream_t s) {
+  dim3 grid((unsigned)a.n_tiles, a.batch);
+#define PM_TILE_ORD(KER, P)                                                   \
+  do {                                                                        \
+    if (ord == 2) KER<P, 2><<<grid, 256, 0, s>>>(a);                          \
+    else if (ord == 4) KER<P, 4><<<grid, 256, 0, s>>>(a);                     \
+    else KER<P, 6><<<grid, 256, 0, s>>>(a);                                   \
+  } while (0)
+  switch (kind) {
+    case TK_DEPOSIT:
+      if (mak == 2) k_tile_deposit<2><<<grid, 256, 0, s>>>(a);
+      else k_tile_deposit<3><<<grid, 256, 0, s>>>(a);
+      break;
+    case TK_KICK:
+      if (mak == 2) PM_TILE_ORD(k_tile_kick, 2); else PM_TILE_ORD(k_tile_kick, 3);
+      break;
+    case TK_ADJ_KICK:
+      if (mak == 2) PM_TILE_ORD(k_tile_adj_kick, 2); else PM_TILE_ORD(k_tile_adj_kick, 3);
+      break;
+    case TK_ADJ_DRIFT:
+      if (mak == 2) k_tile_adj_drift<2><<<grid, 256, 0, s>>>(a);
+      else k_tile_adj_drift<3><<<grid, 256, 0, s>>>(a);
+      break;
+    case TK_DIPOLE: {
+      int R = 1 + ord / 2, W = a.T + 2 * R;
+      size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
+      // ORD 6 needs 110 KB of LDS: above the default dynamic limit
+#define PM_DIPOLE(P, O)                                                                       \
+  do {                                                                                        \
+    hipFuncSetAttribute((const void*)k_tile_dipole<P, O>,                                     \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+    k_tile_dipole<P, O><<<grid, 256, lds, s>>>(a);                                            \
+  } while (0)
+      if (mak == 2) {
+        if (ord == 2) PM_DIPOLE(2, 2); else if (ord == 4) PM_DIPOLE(2, 4); else PM_DIPOLE(2, 6);
+      } else {
+        if (ord == 2) PM_DIPOLE(3, 2); else if (ord == 4) PM_DIPOLE(3, 4); else PM_DIPOLE(3, 6);
+      }
+#undef PM_DIPOLE
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PM_TILE_ORD
+  return hipGetLastError();
+}
+
+hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, double* inv_scale,
+                               double bound_per_u, int batch, hipStream_t s) {
+  k_dipole_scale<<<1, 64, 0, s>>>(umax_bits, scale, inv_scale, bound_per_u, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s) {
+  dim3 grid((unsigned)((a.g.M + 255) / 256), a.batch);
+  if (out_f32) k_assemble<true><<<grid, 256, 0, s>>>(a);
+  else k_assemble<false><<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// ============================================================ NUFFT (ES)
+// Exponential-of-semicircle spreading and interpolation (Sec. "Force
+// evaluation", NUFFT paragraphs): width 6 on the fine grid, 1D weights by
+// integer linear interpolation in a table of phi at 4096 samples per cell
+// (20-bit values), so spreading is bit-reproducible; the 3D product is
+// rounded half-even to the 2^32 mass unit (no remainder: the ES kernel is not
+// a partition of unity).  Home node floor(u); window halo 3.
+namespace {
+constexpr int kEsW = 6, kEsR = 3, kEsShift = kFracBits - 12;  // 4096 samples per cell
+
+__device__ __forceinline__ int es_weight(long long dist, const int32_t* __restrict__ tab) {
+  if (dist >= (long long)(kEsW / 2) << kFracBits) return 0;  // strictly inside |z| < 1
+  int i = (int)(dist >> kEsShift), f = (int)(dist & ((1 << kEsShift) - 1));
+  int t0 = tab[i], t1 = tab[i + 1];
+  return t0 + (((t1 - t0) * f + (1 << (kEsShift - 1))) >> kEsShift);
+}
+
+// integer weights of the 6 nodes floor(u) - 2 .. floor(u) + 3 on one axis
+__device__ __forceinline__ int es_weights(long long U, const int32_t* tab, int w[kEsW]) {
+  const long long h = U >> kFracBits;
+#pragma unroll
+  for (int o = 0; o < kEsW; ++o) {
+    long long d = ((h - 2 + o) << kFracBits) - U;
+    w[o] = es_weight(d < 0 ? -d : d, tab);
+  }
+  return (int)h;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
+  extern __shared__ unsigned long long ewin[];
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int W = a.T + 2 * kEsR, W3 = W * W * W;
+  for (int e = threadIdx.x; e < W3; e += 256) ewin[e] = 0ull;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  __syncthreads();
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+  constexpr int shift = 3 * kWeightBits - kMassBits;
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    long long j[3];
+    lattice_of(i, a.g.log2_np, j);
+    int w[3][kEsW], l0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
+      int h = es_weights(U, a.es_tab, w[c]) & nm;
+      l0[c] = h - o[c] + kEsR - 2;
+    }
+    for (int x = 0; x < kEsW; ++x)
+      for (int y = 0; y < kEsW; ++y) {
+        unsigned long long wxy = (unsigned long long)w[0][x] * (unsigned)w[1][y];
+        if (!wxy) continue;
+        const int bxy = ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
+#pragma unroll
+        for (int z = 0; z < kEsW; ++z) {
+          unsigned long long v = rne_shift(wxy * (unsigned)w[2][z], shift);
+          if (v) atomicAdd(&ewin[bxy + z], v);
+        }
+      }
+  }
+  __syncthreads();
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(a.scratch) + ((long long)slot * a.n_tiles + t) * W3;
+  for (int e = threadIdx.x; e < W3; e += 256) out[e] = ewin[e];
+}
+
+// A_c = sum_j g_c(j) phi(u - j) from the three force meshes, then the kick
+// and drift (or A only for the force hook)
+__global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
+  extern __shared__ float fwin[];  // 3 windows of (T + 6)^3
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int W = a.T + 2 * kEsR, W3 = W * W * W;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  for (int c = 0; c < 3; ++c)
+    load_window(fwin + c * W3, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsR,
+                a.g.log2_ng, a.g.n_g - 1);
+  __syncthreads();
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+  const float al = a.alpha[slot], be = a.beta[slot], tp = a.tau[slot];
+  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    long long j[3];
+    lattice_of(i, a.g.log2_np, j);
+    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][kEsW];
+    int l0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int wi[kEsW];
+      long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
+      int h = es_weights(U, a.es_tab, wi) & nm;
+      l0[c] = h - o[c] + kEsR - 2;
+#pragma unroll
+      for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
+    }
+    float A[3] = {0.f, 0.f, 0.f};
+    for (int xx = 0; xx < kEsW; ++xx)
+      for (int yy = 0; yy < kEsW; ++yy) {
+        const float wxy = w[0][xx] * w[1][yy];
+        const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+#pragma unroll
+        for (int zz = 0; zz < kEsW; ++zz) {
+          const float wt = wxy * w[2][zz];
+          A[0] += wt * fwin[b + zz];
+          A[1] += wt * fwin[W3 + b + zz];
+          A[2] += wt * fwin[2 * W3 + b + zz];
+        }
+      }
+    if (a.acc_out) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.acc_out[ps + c * N + i] = A[c];
+      continue;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float v = al * a.vel[ps + c * N + i] + be * A[c];
+      a.vel[ps + c * N + i] = v;
+      a.disp[ps + c * N + i] = x[c] + tp * v;
+    }
+  }
+}
+
+hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
+  dim3 grid((unsigned)a.n_tiles, a.batch);
+  const int W = a.T + 2 * kEsR;
+  if (kind == TK_ES_DEPOSIT) {
+    size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
+    hipFuncSetAttribute((const void*)k_tile_es_deposit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_tile_es_deposit<<<grid, 256, lds, s>>>(a);
+  } else {
+    size_t lds = (size_t)3 * W * W * W * sizeof(float);
+    hipFuncSetAttribute((const void*)k_tile_es_kick, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_tile_es_kick<<<grid, 256, lds, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pm

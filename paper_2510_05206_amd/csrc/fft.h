@@ -6,7 +6,7 @@ namespace pm {
 
 enum { SRC_I64 = 0, SRC_F32 = 1 };
 enum { DST_F32 = 0, DST_IC = 1 };
-enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4 };
+enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4, MODE_NUFFT_C = 5 };
 
 // z-row pass: real rows of n <-> half-spectrum rows of n/2+1
 struct RowLaunch {
@@ -23,6 +23,7 @@ struct RowLaunch {
   const float2* tw;
   int tws_half, tws_full;  // twiddle strides for the n/2 FFT and for exp(-2 pi i k/n)
   double scale, shift, scale2;
+  unsigned long long active;  // bit b set: slot b takes part
   hipStream_t stream;
 };
 
@@ -43,6 +44,11 @@ struct ColArgs {
   const float* amp;
   float fac[kMaxBatch];
   int comp;
+  // NUFFT multiplier for component comp (x pass): i theta_c / |theta|^2 * coef *
+  // esdec[ix] esdec[iy] esdec[iz], theta = 2 pi m / n_p; esdec is 1/phi_hat^2 on
+  // the kept modes |m| < n_p/2 and 0 elsewhere (truncation)
+  const float* esdec;
+  int n_p;
   unsigned long long active;  // bit b set: slot b takes part
 };
 

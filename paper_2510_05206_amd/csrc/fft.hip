@@ -128,11 +128,12 @@ __global__ void __launch_bounds__(256) k_r2c_rows(const void* __restrict__ src, 
                                                   float2* __restrict__ dst, long long dst_stride,
                                                   int n_rows, const float2* __restrict__ tw,
                                                   int tws_half, int tws_full, double scale,
-                                                  double shift) {
+                                                  double shift, unsigned long long active) {
   constexpr int R = rows_per_block<L>();
   constexpr int n = 2 * L;
   __shared__ float2 buf[R * (L + 1)];
   const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
   const long long row0 = (long long)blockIdx.x * R;
   float* fb = reinterpret_cast<float*>(buf);
   for (int e = threadIdx.x; e < R * n; e += 256) {
@@ -189,11 +190,13 @@ __global__ void __launch_bounds__(256) k_c2r_rows(const float2* __restrict__ src
                                                   float* __restrict__ dst, long long dst_stride,
                                                   float* __restrict__ dst2, int n_rows,
                                                   const float2* __restrict__ tw, int tws_half,
-                                                  int tws_full, float scale, float scale2) {
+                                                  int tws_full, float scale, float scale2,
+                                                  unsigned long long active) {
   constexpr int R = rows_per_block<L>();
   constexpr int n = 2 * L;
   __shared__ float2 buf[R * (L + 1)];
   const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
   const long long row0 = (long long)blockIdx.x * R;
   for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
     int r = e / (L + 1), k = e - r * (L + 1);
@@ -277,6 +280,18 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
       } else {
         v = a.data[gi];
       }
+      if constexpr (MODE == MODE_NUFFT_C) {
+        // x pass: t = ix, outer = iy, z = z0 + c
+        int iz = z0 + c;
+        float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
+        int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
+        float th2 = 0.f;
+        const float k0 = 6.283185307179586f / (float)a.n_p;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
+        float h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
+        v = make_float2(-h * v.y, h * v.x);  // i h v
+      }
       if constexpr (MODE == MODE_IC_C) {
         int mz = z0 + c, mx = signed_mode(t, a.n), my = signed_mode(outer, a.n);
         int ms[3] = {mx, my, mz};
@@ -305,7 +320,7 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
     __syncthreads();
   }
   if constexpr (MODE != MODE_FWD) lds_fft<L, C, true, 256>(buf, a.tw, a.tws, true);
-  float2* out = (MODE == MODE_IC_C) ? a.dst3 : a.data;
+  float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C) ? a.dst3 : a.data;
   for (int e = threadIdx.x; e < L * C; e += 256) {
     int t = e / C, c = e - t * C;
     if (z0 + c < a.nh) out[sbase + t * stride_t + c] = buf[e];
@@ -322,20 +337,20 @@ static hipError_t launch_rows(const RowLaunch& r) {
     if (r.dst_mode == DST_F32)
       k_c2r_rows<L, DST_F32><<<grid, 256, 0, r.stream>>>(
           (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows,
-          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2);
+          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active);
     else
       k_c2r_rows<L, DST_IC><<<grid, 256, 0, r.stream>>>(
           (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows,
-          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2);
+          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active);
   } else {
     if (r.src_mode == SRC_I64)
       k_r2c_rows<L, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst,
                                                          r.dst_stride, r.n_rows, r.tw, r.tws_half,
-                                                         r.tws_full, r.scale, r.shift);
+                                                         r.tws_full, r.scale, r.shift, r.active);
     else
       k_r2c_rows<L, SRC_F32><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst,
                                                          r.dst_stride, r.n_rows, r.tw, r.tws_half,
-                                                         r.tws_full, r.scale, r.shift);
+                                                         r.tws_full, r.scale, r.shift, r.active);
   }
   return hipGetLastError();
 }
@@ -364,6 +379,7 @@ static hipError_t launch_cols_c(const ColArgs& a, int mode, int batch, hipStream
     case MODE_FUSED_H: k_cols<L, C, MODE_FUSED_H><<<grid, 256, 0, s>>>(a); break;
     case MODE_IC_C: k_cols<L, C, MODE_IC_C><<<grid, 256, 0, s>>>(a); break;
     case MODE_COMBINE_IC: k_cols<L, C, MODE_COMBINE_IC><<<grid, 256, 0, s>>>(a); break;
+    case MODE_NUFFT_C: k_cols<L, C, MODE_NUFFT_C><<<grid, 256, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -4,70 +4,84 @@
 
 namespace pm {
 
-struct DepositArgs {
+// ------------------------------------------------ tile-binned kernels (binned.hip)
+struct BinArgs {
   Geom g;
   int batch;
-  float* disp;             // [B][3][N]
-  const float* vel;        // non-null: drift X += tau V first and write X back
-  long long* mesh;         // [B][M] int64 (must be zero on entry)
+  unsigned long long active;
+  float* disp;             // [B][3][N]; drifted in place when vel != null
+  const float* vel;
   float tau[kMaxBatch];
-  unsigned long long active;  // bit b set: slot b takes part
+  int log2T, log2nt, n_tiles;
+  long long ts;            // ints per slot of count / offset
+  int32_t* key;            // [B][N] tile of each particle
+  int32_t* rank;           // [B][N] rank inside its tile
+  int32_t* sorted;         // [B][N] particle indices grouped by tile
+  int32_t* count;          // [B][ts], zero on entry
+  int32_t* offset;         // [B][ts], n_tiles + 1 entries used
 };
 
-enum { GK_KICK = 0, GK_ADJ_KICK = 1, GK_ADJ_DRIFT = 2 };
+enum { TK_DEPOSIT = 0, TK_KICK = 1, TK_ADJ_KICK = 2, TK_ADJ_DRIFT = 3, TK_DIPOLE = 4, TK_ES_DEPOSIT = 5,
+       TK_ES_KICK = 6 };
 
-struct GatherArgs {
+struct TileArgs {
   Geom g;
   int batch;
+  unsigned long long active;
+  int T, log2T, log2nt, n_tiles;
+  long long ts;
+  const int32_t* sorted;
+  const int32_t* offset;
   float* disp;
   float* vel;
   float* xbar;
   float* vbar;
-  const float* phi;        // potential (kick) or mesh cotangent (adjoint drift)
-  float* gbar;             // [B][3][M] cotangent meshes (adjoint kick)
-  float* acc_out;          // force-only output (test hook)
+  const float* mesh_in;    // potential (kicks) or mesh cotangent (adjoint drift)
+  void* scratch;           // window slab [B][n_tiles][W^3] int64
+  float* acc_out;          // force-only output
+  float* u_sorted;         // [B][3][N] u = beta V_bar in sorted order
+  float* umax;             // [B] max |u| (as uint bits)
+  const double* scale;     // [B] fixed-point scale of the cotangent scatter
+  const int32_t* es_tab;   // integer exponential-of-semicircle table (NUFFT)
+  long long comp_stride;   // floats between the 3 force meshes (NUFFT kick)
   float alpha[kMaxBatch];
   float beta[kMaxBatch];
   float tau[kMaxBatch];
   float coef[kMaxBatch];
-  unsigned long long active;  // bit b set: slot b takes part
 };
 
-hipError_t launch_deposit(const DepositArgs& a, int mak, hipStream_t s);
-hipError_t launch_gather(const GatherArgs& a, int kind, int mak, int fd_order, hipStream_t s);
-hipError_t launch_fd_div(const float* gbar, float* d, const Geom& g, int batch, int fd_order,
-                         unsigned long long active, hipStream_t s);
+struct AssembleArgs {
+  Geom g;
+  int batch;
+  unsigned long long active;
+  int T, R, log2T, log2nt, n_tiles;
+  const void* scratch;
+  void* out;               // int64 mesh, or float mesh scaled by inv_scale
+  const double* inv_scale;
+};
+
+hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s);
+hipError_t launch_tile(const TileArgs& a, int kind, int mak, int fd_order, hipStream_t s);
+hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s);
+hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s);
+hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, double* inv_scale,
+                               double bound_per_u, int batch, hipStream_t s);
 
 // auxiliary kernels (misc.hip)
 hipError_t launch_fill(void* p, long long bytes, hipStream_t s);
 hipError_t launch_white_noise(float* w, long long N, long long slot_stride, int batch,
-                              const uint64_t* seeds_host, hipStream_t s);
+                              const uint64_t* seeds_host, unsigned long long active, hipStream_t s);
 hipError_t launch_psibar(const float* xbar, const float* vbar, float* out, long long N,
-                         long long part_stride, int batch, const float* d0, hipStream_t s);
+                         long long part_stride, int batch, const float* d0, unsigned long long active,
+                         hipStream_t s);
 hipError_t launch_dot(const float* a, const float* b, long long n, long long stride, int batch,
-                      double* partial, double* out, const double* scale, hipStream_t s);
+                      double* partial, double* out, const double* scale, unsigned long long active,
+                      hipStream_t s);
 hipError_t launch_i64_to_delta(const long long* m, float* delta, long long M, long long stride,
-                               int batch, double scale, hipStream_t s);
+                               int batch, double scale, unsigned long long active, hipStream_t s);
 hipError_t launch_pk(const float2* spec, long long slot_stride, int n, int batch, int n_bins,
                      double kf, double norm, const double* cic4, int deconv, double* partial,
-                     double* k_mean, double* pk, long long* n_modes, hipStream_t s);
-
-// ES / NUFFT kernels (nufft.hip)
-struct EsArgs {
-  Geom g;                  // n_g = fine grid n_f
-  int batch;
-  int width;
-  float* disp;
-  float* vel;
-  const float* vel_pre;    // deposit: merged drift
-  long long* mesh;
-  const float* force3;     // [B][3][M] interpolation meshes
-  float* acc_out;
-  const int32_t* tab;      // integer ES table
-  float alpha[kMaxBatch], beta[kMaxBatch], tau[kMaxBatch];
-  unsigned long long active;  // bit b set: slot b takes part
-};
-hipError_t launch_es_deposit(const EsArgs& a, hipStream_t s);
-hipError_t launch_es_gather(const EsArgs& a, hipStream_t s);
+                     double* k_mean, double* pk, long long* n_modes, unsigned long long active,
+                     hipStream_t s);
 
 }  // namespace pm

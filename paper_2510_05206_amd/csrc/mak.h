@@ -1,0 +1,153 @@
+// Device helpers of the mass-assignment kernels (tab. interpolation_kernels):
+// fixed-point mesh coordinates, integer 1D weights, their float values and
+// derivatives, and the finite-difference gradient stencils of
+// tab. derivative_kernels.
+#pragma once
+#include "kernels.h"
+
+namespace pm {
+
+// U = j r 2^20 + rne(Psi r 2^20) mod n_g 2^20; exact from FP32 Psi (r = 2^k)
+__device__ __forceinline__ long long fixed_coord(long long j, float psi, int log2_r, long long umask) {
+  float t = psi * (float)(1 << (log2_r + kFracBits));
+  long long f = (long long)rintf(t);  // round half to even
+  return ((j << (log2_r + kFracBits)) + f) & umask;
+}
+
+__device__ __forceinline__ unsigned long long rne_shift(unsigned long long p, int s) {
+  unsigned long long q = p >> s, rem = p & ((1ull << s) - 1), half = 1ull << (s - 1);
+  return q + ((rem > half) || (rem == half && (q & 1ull)));
+}
+
+// home node of a particle on one axis (wrapped): CIC floor(u), TSC round(u)
+template <int P>
+__device__ __forceinline__ int home_node(long long U, int nm) {
+  if constexpr (P == 2) return (int)(U >> kFracBits) & nm;
+  else return (int)((U + (1ll << (kFracBits - 1))) >> kFracBits) & nm;
+}
+
+// integer 1D weights (sum 2^20); returns the first node, unwrapped
+template <int P>
+__device__ __forceinline__ int weights1d(long long U, int w[P]) {
+  constexpr long long one = 1ll << kFracBits;
+  if constexpr (P == 2) {
+    int f = (int)(U & (one - 1));
+    w[0] = (int)one - f;
+    w[1] = f;
+    return (int)(U >> kFracBits);
+  } else {
+    long long n = (U + (one >> 1)) >> kFracBits;
+    long long X = U - (n << kFracBits);
+    long long a = (one >> 1) - X, b = (one >> 1) + X;
+    int wl = (int)rne_shift((unsigned long long)(a * a), 2 * kFracBits + 1 - kWeightBits);
+    int wr = (int)rne_shift((unsigned long long)(b * b), 2 * kFracBits + 1 - kWeightBits);
+    w[0] = wl;
+    w[1] = (1 << kWeightBits) - wl - wr;
+    w[2] = wr;
+    return (int)n - 1;
+  }
+}
+
+// float weights and d/du (u in mesh cells)
+template <int P>
+__device__ __forceinline__ int weights1d_f(long long U, float w[P], float dw[P]) {
+  int wi[P];
+  int i0 = weights1d<P>(U, wi);
+  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
+#pragma unroll
+  for (int a = 0; a < P; ++a) w[a] = (float)wi[a] * inv;
+  if constexpr (P == 2) {
+    dw[0] = -1.f;
+    dw[1] = 1.f;
+  } else {
+    constexpr long long one = 1ll << kFracBits;
+    long long n = (U + (one >> 1)) >> kFracBits;
+    float x = (float)(U - (n << kFracBits)) * (1.0f / (float)one);
+    dw[0] = -(0.5f - x);
+    dw[1] = -2.f * x;
+    dw[2] = 0.5f + x;
+  }
+  return i0;
+}
+
+__device__ __forceinline__ void lattice_of(long long i, int log2_np, long long j[3]) {
+  long long m = (1ll << log2_np) - 1;
+  j[2] = i & m;
+  j[1] = (i >> log2_np) & m;
+  j[0] = i >> (2 * log2_np);
+}
+
+// finite-difference stencil c_s (s = -H..H) of d/dx
+template <int ORD>
+__device__ __forceinline__ float fd_coef(int s) {
+  if constexpr (ORD == 2) {
+    return s == 1 ? 0.5f : (s == -1 ? -0.5f : 0.f);
+  } else if constexpr (ORD == 4) {
+    const float c[5] = {1.f / 12, -8.f / 12, 0.f, 8.f / 12, -1.f / 12};
+    return c[s + 2];
+  } else {
+    const float c[7] = {-1.f / 60, 9.f / 60, -45.f / 60, 0.f, 45.f / 60, -9.f / 60, 1.f / 60};
+    return c[s + 3];
+  }
+}
+
+// A_c = sum_j W_j (FD_c phi)_j and, when GRAD, dA_c/du_a, for a particle with
+// P-point kernels starting at node i0 (per axis); `at(x, y, z)` loads phi at
+// node offsets (which may run H below i0 and P-1+H above).  The c-axis
+// weights are the kernel convolved with the stencil (P + 2H points).
+template <int P, int ORD, bool GRAD, class Acc>
+__device__ __forceinline__ void fd_gather(const Acc& at, const int i0[3], const float w[3][P],
+                                          const float dw[3][P], float A[3], float dA[3][3]) {
+  constexpr int H = ORD / 2;
+  constexpr int Q = P + 2 * H;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float G[Q], dG[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+      float g = 0.f, d = 0.f;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        int s = t - H - q;
+        if (s >= -H && s <= H) {
+          float cs = fd_coef<ORD>(s);
+          g += w[c][q] * cs;
+          d += dw[c][q] * cs;
+        }
+      }
+      G[t] = g;
+      dG[t] = d;
+    }
+    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+    float acc = 0.f, d_c = 0.f, d_1 = 0.f, d_2 = 0.f;
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+#pragma unroll
+      for (int q1 = 0; q1 < P; ++q1) {
+#pragma unroll
+        for (int q2 = 0; q2 < P; ++q2) {
+          int o[3];
+          o[c] = i0[c] - H + t;
+          o[a1] = i0[a1] + q1;
+          o[a2] = i0[a2] + q2;
+          float f = at(o[0], o[1], o[2]);
+          float w12 = w[a1][q1] * w[a2][q2];
+          acc += G[t] * w12 * f;
+          if constexpr (GRAD) {
+            d_c += dG[t] * w12 * f;
+            d_1 += G[t] * dw[a1][q1] * w[a2][q2] * f;
+            d_2 += G[t] * w[a1][q1] * dw[a2][q2] * f;
+          }
+        }
+      }
+    }
+    A[c] = acc;
+    if constexpr (GRAD) {
+      dA[c][c] = d_c;
+      dA[c][a1] = d_1;
+      dA[c][a2] = d_2;
+    }
+  }
+}
+
+}  // namespace pm

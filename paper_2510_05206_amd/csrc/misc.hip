@@ -27,8 +27,10 @@ struct Seeds {
   uint32_t k0[kMaxBatch], k1[kMaxBatch];
 };
 
-__global__ void k_white_noise(float* w, long long N, long long slot_stride, Seeds sd) {
+__global__ void k_white_noise(float* w, long long N, long long slot_stride, Seeds sd,
+                              unsigned long long active) {
   const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = 0, c3 = 0;
@@ -51,22 +53,24 @@ __global__ void k_white_noise(float* w, long long N, long long slot_stride, Seed
 }
 
 hipError_t launch_white_noise(float* w, long long N, long long slot_stride, int batch,
-                              const uint64_t* seeds, hipStream_t s) {
+                              const uint64_t* seeds, unsigned long long active, hipStream_t s) {
   Seeds sd;
   for (int b = 0; b < batch; ++b) {
+    if (!((active >> b) & 1ull)) continue;
     sd.k0[b] = (uint32_t)(seeds[b] & 0xFFFFFFFFu);
     sd.k1[b] = (uint32_t)(seeds[b] >> 32);
   }
   dim3 grid((unsigned)((N + 255) / 256), batch);
-  k_white_noise<<<grid, 256, 0, s>>>(w, N, slot_stride, sd);
+  k_white_noise<<<grid, 256, 0, s>>>(w, N, slot_stride, sd, active);
   return hipGetLastError();
 }
 
 // psi_bar_c = D0 X_bar_c + V_bar_c (the IC pullback of Psi = D0 psi, V = psi)
 struct D0s { float d0[kMaxBatch]; };
 __global__ void k_psibar(const float* xbar, const float* vbar, float* out, long long n3,
-                         long long stride, D0s d) {
+                         long long stride, D0s d, unsigned long long active) {
   const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
   long long g = slot * stride + i;
@@ -74,11 +78,12 @@ __global__ void k_psibar(const float* xbar, const float* vbar, float* out, long 
 }
 
 hipError_t launch_psibar(const float* xbar, const float* vbar, float* out, long long N,
-                         long long part_stride, int batch, const float* d0, hipStream_t s) {
+                         long long part_stride, int batch, const float* d0,
+                         unsigned long long active, hipStream_t s) {
   D0s d;
   for (int b = 0; b < batch; ++b) d.d0[b] = d0[b];
   dim3 grid((unsigned)((3 * N + 255) / 256), batch);
-  k_psibar<<<grid, 256, 0, s>>>(xbar, vbar, out, 3 * N, part_stride, d);
+  k_psibar<<<grid, 256, 0, s>>>(xbar, vbar, out, 3 * N, part_stride, d, active);
   return hipGetLastError();
 }
 
@@ -87,9 +92,10 @@ hipError_t launch_psibar(const float* xbar, const float* vbar, float* out, long 
 constexpr int kDotBlocks = 256;
 
 __global__ void k_dot_partial(const float* a, const float* b, long long n, long long stride,
-                              double* partial) {
+                              double* partial, unsigned long long active) {
   __shared__ double sh[256];
   const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)kDotBlocks * 256)
     acc += (double)a[slot * stride + i] * (double)b[slot * stride + i];
@@ -103,8 +109,9 @@ __global__ void k_dot_partial(const float* a, const float* b, long long n, long 
 }
 
 struct Scales { double s[kMaxBatch]; };
-__global__ void k_dot_final(const double* partial, double* out, Scales sc) {
+__global__ void k_dot_final(const double* partial, double* out, Scales sc, unsigned long long active) {
   const int slot = blockIdx.x;
+  if (!((active >> slot) & 1ull)) return;
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int i = 0; i < kDotBlocks; ++i) t += partial[slot * kDotBlocks + i];
@@ -113,26 +120,28 @@ __global__ void k_dot_final(const double* partial, double* out, Scales sc) {
 }
 
 hipError_t launch_dot(const float* a, const float* b, long long n, long long stride, int batch,
-                      double* partial, double* out, const double* scale, hipStream_t s) {
-  k_dot_partial<<<dim3(kDotBlocks, batch), 256, 0, s>>>(a, b, n, stride, partial);
+                      double* partial, double* out, const double* scale, unsigned long long active,
+                      hipStream_t s) {
+  k_dot_partial<<<dim3(kDotBlocks, batch), 256, 0, s>>>(a, b, n, stride, partial, active);
   Scales sc;
   for (int i = 0; i < batch; ++i) sc.s[i] = scale[i];
-  k_dot_final<<<batch, 64, 0, s>>>(partial, out, sc);
+  k_dot_final<<<batch, 64, 0, s>>>(partial, out, sc, active);
   return hipGetLastError();
 }
 
 __global__ void k_i64_to_delta(const long long* m, float* delta, long long M, long long stride,
-                               double scale) {
+                               double scale, unsigned long long active) {
   const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
   delta[slot * stride + i] = (float)((double)m[slot * stride + i] * scale - 1.0);
 }
 
 hipError_t launch_i64_to_delta(const long long* m, float* delta, long long M, long long stride,
-                               int batch, double scale, hipStream_t s) {
+                               int batch, double scale, unsigned long long active, hipStream_t s) {
   dim3 grid((unsigned)((M + 255) / 256), batch);
-  k_i64_to_delta<<<grid, 256, 0, s>>>(m, delta, M, stride, scale);
+  k_i64_to_delta<<<grid, 256, 0, s>>>(m, delta, M, stride, scale, active);
   return hipGetLastError();
 }
 
@@ -153,9 +162,11 @@ __device__ __forceinline__ int pk_bin(long long m2) {
 
 __global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, long long slot_stride, int n,
                                                     int n_bins, double kf, const double* cic4,
-                                                    int deconv, double* partial) {
+                                                    int deconv, double* partial,
+                                                    unsigned long long active) {
   extern __shared__ double acc[];  // [3][n_bins][4]
   const int slot = blockIdx.y, x = blockIdx.x;
+  if (!((active >> slot) & 1ull)) return;
   const int nh = n / 2 + 1;
   for (int e = threadIdx.x; e < 3 * n_bins * 4; e += 256) acc[e] = 0.0;
   __syncthreads();
@@ -208,8 +219,9 @@ __global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, long lon
 }
 
 __global__ void k_pk_final(const double* partial, int n, int n_bins, double norm, double* k_mean,
-                           double* pk, long long* n_modes) {
+                           double* pk, long long* n_modes, unsigned long long active) {
   const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_bins) return;
   double sp = 0.0, sk = 0.0, sc = 0.0;
@@ -227,12 +239,13 @@ __global__ void k_pk_final(const double* partial, int n, int n_bins, double norm
 
 hipError_t launch_pk(const float2* spec, long long slot_stride, int n, int batch, int n_bins,
                      double kf, double norm, const double* cic4, int deconv, double* partial,
-                     double* k_mean, double* pk, long long* n_modes, hipStream_t s) {
+                     double* k_mean, double* pk, long long* n_modes, unsigned long long active,
+                     hipStream_t s) {
   size_t lds = (size_t)3 * n_bins * 4 * sizeof(double);
   k_pk_partial<<<dim3(n, batch), 256, lds, s>>>(spec, slot_stride, n, n_bins, kf, cic4, deconv,
-                                                partial);
+                                                partial, active);
   k_pk_final<<<dim3((n_bins + 63) / 64, batch), 64, 0, s>>>(partial, n, n_bins, norm, k_mean, pk,
-                                                           n_modes);
+                                                           n_modes, active);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // C ABI of libpm.so: context, workspace carving and the call sequences of the
 // PM hot path (see include/pm.h for the contract of every entry point).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -26,6 +27,8 @@ struct pm_ctx {
   std::vector<float2> tw;
   std::vector<float> lap, win2, amp_tab;
   std::vector<double> cic4;
+  std::vector<int32_t> es_tab;       // NUFFT: integer ES table (4096 samples per cell)
+  std::vector<float> esdec;          // NUFFT: 1/phi_hat^2 on kept modes, 0 elsewhere
   // binding
   bool bound = false, with_adj = false;
   hipStream_t stream = nullptr;
@@ -34,11 +37,22 @@ struct pm_ctx {
   float2* d_tw = nullptr;
   float *d_lap = nullptr, *d_win2 = nullptr, *d_amp = nullptr;
   double* d_cic4 = nullptr;
+  int32_t* d_es_tab = nullptr;
+  float* d_esdec = nullptr;
+  float* force3 = nullptr;           // NUFFT: 3 force meshes [B][3][M]
+  float2* spec2 = nullptr;           // NUFFT: per-component spectrum
   float *disp = nullptr, *vel = nullptr, *w = nullptr, *xbar = nullptr, *vbar = nullptr;
   long long* mesh = nullptr;
   float2* spec = nullptr;
   float* phi = nullptr;
-  float* gbar = nullptr;
+  // tile binning and window slabs
+  int T = 16, log2T = 4, log2nt = 0, n_tiles = 1;
+  long long ts = 0;
+  int32_t *key = nullptr, *rank = nullptr, *sorted = nullptr, *count = nullptr, *offset = nullptr;
+  void* scratch = nullptr;
+  float* u_sorted = nullptr;    // adjoint: u in sorted order; IC adjoint: psi_bar
+  float* umax = nullptr;
+  double *scale = nullptr, *inv_scale = nullptr;
   float2* icspec = nullptr;          // 4 spectra on the particle grid per slot
   long long icspec_stride = 0;       // float2 per slot (4 spectra)
   long long icspec_comp = 0;         // float2 per spectrum
@@ -46,6 +60,7 @@ struct pm_ctx {
   double* dot_partial = nullptr;
   // state
   bool ics_done = false, ran = false;
+  unsigned long long user_mask = 1;  // slots the whole-context calls act on (pm_set_active)
   // per-kernel-class event timing (pm_profile / pm_kernel_times)
   bool prof = false;
   struct Pending { int cls; hipEvent_t a, b; };
@@ -113,9 +128,16 @@ void prof_end(pm_ctx* c) {
 struct Layout {
   size_t off_tw, off_lap, off_win2, off_amp, off_cic4;
   size_t off_disp, off_vel, off_w, off_xbar, off_vbar;
-  size_t off_mesh, off_spec, off_phi, off_gbar, off_icspec, off_pk, off_dot;
+  size_t off_mesh, off_spec, off_phi, off_icspec, off_pk, off_dot;
+  size_t off_key, off_rank, off_sorted, off_count, off_offset, off_scratch, off_u, off_umax, off_scale;
+  size_t off_es_tab, off_esdec, off_force3, off_spec2;
   size_t total;
 };
+
+// tile edge (16 cells, or the whole mesh when smaller), and the window halo
+// of the adjoint's transposed FD gather (kernel reach 1 + FD reach)
+int tile_edge(int n) { return n < 16 ? n : 16; }
+int dipole_halo(int grad_order) { return 1 + grad_order / 2; }
 
 long long spec_elems(int n) { return (long long)n * n * (n / 2 + 1); }
 
@@ -140,7 +162,26 @@ Layout layout(const pm_ctx* c, bool adj) {
   L.off_mesh = take(sizeof(long long) * M * B);
   L.off_spec = take(sizeof(float2) * spec_elems(n) * B);
   L.off_phi = take(sizeof(float) * M * B);
-  L.off_gbar = adj ? take(sizeof(float) * 3 * M * B) : 0;
+  const int T = tile_edge(n);
+  const long long nt = n / T, n_tiles = nt * nt * nt;
+  const long long ts = (n_tiles + 1 + 63) / 64 * 64;
+  L.off_key = take(sizeof(int32_t) * N * B);
+  L.off_rank = take(sizeof(int32_t) * N * B);
+  L.off_sorted = take(sizeof(int32_t) * N * B);
+  L.off_count = take(sizeof(int32_t) * ts * B);
+  L.off_offset = take(sizeof(int32_t) * ts * B);
+  const bool nufft = c->cfg.force == PM_FORCE_NUFFT;
+  long long W = T + 2;
+  if (adj) W = std::max(W, (long long)T + 2 * dipole_halo(c->cfg.grad_order));
+  if (nufft) W = std::max(W, (long long)T + 6);
+  L.off_es_tab = take(sizeof(int32_t) * c->es_tab.size());
+  L.off_esdec = take(sizeof(float) * n);
+  L.off_force3 = nufft ? take(sizeof(float) * 3 * M * B) : 0;
+  L.off_spec2 = nufft ? take(sizeof(float2) * spec_elems(n) * B) : 0;
+  L.off_scratch = take(sizeof(long long) * W * W * W * n_tiles * B);
+  L.off_u = adj ? take(sizeof(float) * 3 * N * B) : 0;
+  L.off_umax = take(sizeof(float) * kMaxBatch);
+  L.off_scale = take(sizeof(double) * 2 * kMaxBatch);
   L.off_icspec = take(sizeof(float2) * 4 * align_up(spec_elems(np)) * B);
   L.off_pk = take(sizeof(double) * 3 * (size_t)n * n * B);  // n_bins <= n
   L.off_dot = take(sizeof(double) * 256 * B);
@@ -176,6 +217,29 @@ void build_tables(pm_ctx* c) {
     double wv = std::pow(sinc, cf.mak);
     c->win2[i] = cf.deconvolve ? (float)(wv * wv) : 1.0f;
     c->cic4[i] = std::pow(sinc, 4);
+  }
+  // NUFFT: exponential-of-semicircle table (phi at t/4096 cells, 20-bit
+  // integers, round half even) and the deconvolution 1/phi_hat^2 on the modes
+  // strictly below the particle Nyquist mode (truncation: 0 elsewhere)
+  if (cf.force == PM_FORCE_NUFFT) {
+    const int w = cf.es_width, tabn = (w / 2) * kEsTabPerCell + 2;
+    c->es_tab.resize(tabn);
+    for (int t = 0; t < tabn; ++t) {
+      double x = (double)t / kEsTabPerCell, z = x / (0.5 * w);
+      double phi = z < 1.0 ? std::exp(cf.es_beta * (std::sqrt(1.0 - z * z) - 1.0)) : 0.0;
+      c->es_tab[t] = (int32_t)std::nearbyint(phi * (double)(1 << kWeightBits));
+    }
+    c->esdec.assign(n, 0.f);
+    for (int i = 0; i < n; ++i) {
+      int m = i < n / 2 ? i : i - n;
+      if (2 * std::abs(m) < cf.n_p) {
+        double ph = es_phihat(2.0 * M_PI * m / n, w, cf.es_beta);
+        c->esdec[i] = (float)(1.0 / (ph * ph));
+      }
+    }
+  } else {
+    c->es_tab.assign(4, 0);
+    c->esdec.assign(n, 0.f);
   }
   // IC multiplier on the particle grid: h_c = i m_c amp[|m|^2], with
   // amp = kf sqrt(P(k) n^3/L^3) / (k^2 D_ref dq) / n^3 (the 1/n^3 of the
@@ -232,6 +296,7 @@ pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_strid
   r.scale = scale;
   r.shift = shift;
   r.stream = c->stream;
+  r.active = active;
   KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(r));
   ColArgs a{};
   a.data = dst;
@@ -285,29 +350,96 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
   rl.tws_full = c->Lmax / n;
   rl.scale = 1.0;
   rl.stream = c->stream;
+  rl.active = active;
   KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   return PM_OK;
 }
 
 // deposit of `disp` (optionally drifting by tau first) into the int64 mesh
-pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, int mak,
-                  long long* mesh, unsigned long long active) {
-  KLAUNCH(c, PM_K_FILL, launch_fill(mesh, (long long)sizeof(long long) * c->g.mesh_stride * c->cfg.batch, c->stream));
-  DepositArgs d{};
-  d.g = c->g;
-  d.batch = c->cfg.batch;
-  d.disp = disp;
-  d.vel = vel_pre;
-  d.mesh = mesh;
-  d.active = active;
-  for (int b = 0; b < c->cfg.batch; ++b) d.tau[b] = tau ? (float)tau[b] : 0.f;
-  KLAUNCH(c, PM_K_DEPOSIT, launch_deposit(d, mak, c->stream));
+// counting sort of the particles of `disp` by the tile of their home node
+// (optionally drifting them by tau first); fills key/rank/sorted/offset
+pm_status bin(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, int mak,
+              unsigned long long active) {
+  KLAUNCH(c, PM_K_FILL, launch_fill(c->count, (long long)sizeof(int32_t) * c->ts * c->cfg.batch, c->stream));
+  BinArgs b{};
+  b.g = c->g;
+  b.batch = c->cfg.batch;
+  b.active = active;
+  b.disp = disp;
+  b.vel = vel_pre;
+  for (int s = 0; s < c->cfg.batch; ++s) b.tau[s] = tau ? (float)tau[s] : 0.f;
+  b.log2T = c->log2T;
+  b.log2nt = c->log2nt;
+  b.n_tiles = c->n_tiles;
+  b.ts = c->ts;
+  b.key = c->key;
+  b.rank = c->rank;
+  b.sorted = c->sorted;
+  b.count = c->count;
+  b.offset = c->offset;
+  KLAUNCH(c, PM_K_BIN, launch_binning(b, mak, c->stream));
   return PM_OK;
 }
 
+TileArgs tile_args(pm_ctx* c, float* disp, unsigned long long active) {
+  TileArgs t{};
+  t.g = c->g;
+  t.batch = c->cfg.batch;
+  t.active = active;
+  t.T = c->T;
+  t.log2T = c->log2T;
+  t.log2nt = c->log2nt;
+  t.n_tiles = c->n_tiles;
+  t.ts = c->ts;
+  t.sorted = c->sorted;
+  t.offset = c->offset;
+  t.disp = disp;
+  t.vel = c->vel;
+  t.xbar = c->xbar;
+  t.vbar = c->vbar;
+  t.scratch = c->scratch;
+  t.u_sorted = c->u_sorted;
+  t.umax = c->umax;
+  t.scale = c->scale;
+  return t;
+}
+
+AssembleArgs assemble_args(pm_ctx* c, int R, void* out, unsigned long long active) {
+  AssembleArgs a{};
+  a.g = c->g;
+  a.batch = c->cfg.batch;
+  a.active = active;
+  a.T = c->T;
+  a.R = R;
+  a.log2T = c->log2T;
+  a.log2nt = c->log2nt;
+  a.n_tiles = c->n_tiles;
+  a.scratch = c->scratch;
+  a.out = out;
+  a.inv_scale = c->inv_scale;
+  return a;
+}
+
+// fixed-point deposit of `disp` (after binning) into the int64 mesh
+pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, int mak,
+                  long long* mesh, unsigned long long active) {
+  pm_status st = bin(c, disp, vel_pre, tau, mak, active);
+  if (st) return st;
+  TileArgs t = tile_args(c, disp, active);
+  KLAUNCH(c, PM_K_DEPOSIT, launch_tile(t, TK_DEPOSIT, mak, 0, c->stream));
+  AssembleArgs a = assemble_args(c, 1, mesh, active);
+  KLAUNCH(c, PM_K_ASSEMBLE, launch_assemble(a, false, c->stream));
+  return PM_OK;
+}
+
+pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
+                       unsigned long long active);
+
 // potential phi of the positions `disp` for the midpoint normalisation s
+// (NUFFT: the three force meshes)
 pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
                     unsigned long long active) {
+  if (c->cfg.force == PM_FORCE_NUFFT) return nufft_meshes(c, disp, vel_pre, tau, s, active);
   pm_status st = deposit(c, disp, vel_pre, tau, c->cfg.mak, c->mesh, active);
   if (st) return st;
   const double N = (double)c->g.N, n3 = (double)c->g.M;
@@ -315,6 +447,88 @@ pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* 
                 c->g.spec_stride, c->cfg.n_g, false, active);
   if (st) return st;
   return poisson_to_real(c, s, c->phi, active);
+}
+
+// NUFFT force meshes: ES spreading (type 1) -> R2C -> truncate, deconvolve,
+// i k_c s / k^2, deconvolve -> zero-padded C2R per component (type 2 grid)
+pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
+                       unsigned long long active) {
+  pm_status st = bin(c, disp, vel_pre, tau, 2, active);  // home node floor(u), as CIC
+  if (st) return st;
+  TileArgs t = tile_args(c, disp, active);
+  t.es_tab = c->d_es_tab;
+  KLAUNCH(c, PM_K_DEPOSIT, launch_tile_es(t, TK_ES_DEPOSIT, c->stream));
+  AssembleArgs as = assemble_args(c, 3, c->mesh, active);
+  KLAUNCH(c, PM_K_ASSEMBLE, launch_assemble(as, false, c->stream));
+  const int n = c->cfg.n_g, np = c->cfg.n_p;
+  const double N = (double)c->g.N;
+  const double ph0 = es_phihat(0.0, c->cfg.es_width, c->cfg.es_beta);
+  const double mean = N * ph0 * ph0 * ph0 / (double)c->g.M;  // removes most of k = 0
+  st = r2c_mesh(c, c->mesh, SRC_I64, c->g.mesh_stride, 1.0 / 4294967296.0, mean, c->spec,
+                c->g.spec_stride, n, true, active);
+  if (st) return st;
+  ColArgs a{};
+  a.data = c->spec;
+  a.slot_stride = c->g.spec_stride;
+  a.n = n;
+  a.nh = n / 2 + 1;
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / n;
+  a.active = active;
+  a.esdec = c->d_esdec;
+  a.n_p = np;
+  a.dst3 = c->spec2;
+  const double np3 = (double)np * np * np;
+  for (int b = 0; b < c->cfg.batch; ++b) a.coef[b] = (float)(s[b] / np3 * (np3 / N));
+  for (int comp = 0; comp < 3; ++comp) {
+    a.comp = comp;
+    a.axis = 0;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_NUFFT_C, c->cfg.batch, c->stream));
+    ColArgs y = a;
+    y.data = c->spec2;
+    y.axis = 1;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, c->cfg.batch, c->stream));
+    RowLaunch rl{};
+    rl.n = n;
+    rl.n_rows = (long long)n * n;
+    rl.batch = c->cfg.batch;
+    rl.inverse = true;
+    rl.dst_mode = DST_F32;
+    rl.src = c->spec2;
+    rl.src_stride = c->g.spec_stride;
+    rl.dst = c->force3 + comp * c->g.M;
+    rl.dst_stride = 3 * c->g.M;
+    rl.tw = c->d_tw;
+    rl.tws_half = c->Lmax / (n / 2);
+    rl.tws_full = c->Lmax / n;
+    rl.scale = 1.0;
+    rl.stream = c->stream;
+    rl.active = active;
+    KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
+  }
+  return PM_OK;
+}
+
+// gather of the force and kick/drift (or force only into acc_out)
+pm_status kick(pm_ctx* c, float* disp, const double* alpha, const double* beta, const double* tau_post,
+               float* acc_out, unsigned long long active) {
+  TileArgs a = tile_args(c, disp, active);
+  a.acc_out = acc_out;
+  for (int b = 0; b < c->cfg.batch; ++b) {
+    a.alpha[b] = alpha ? (float)alpha[b] : 1.f;
+    a.beta[b] = beta ? (float)beta[b] : 0.f;
+    a.tau[b] = tau_post ? (float)tau_post[b] : 0.f;
+  }
+  if (c->cfg.force == PM_FORCE_NUFFT) {
+    a.mesh_in = c->force3;
+    a.comp_stride = c->g.M;
+    a.es_tab = c->d_es_tab;
+    KLAUNCH(c, PM_K_GATHER_KICK, launch_tile_es(a, TK_ES_KICK, c->stream));
+  } else {
+    a.mesh_in = c->phi;
+    KLAUNCH(c, PM_K_GATHER_KICK, launch_tile(a, TK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
+  }
+  return PM_OK;
 }
 
 pm_status check_bound(pm_ctx* c) {
@@ -343,8 +557,14 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
     if ((c.mak != 2 && c.mak != 3) || (c.grad_order != 2 && c.grad_order != 4 && c.grad_order != 6) ||
         (c.lap_order != 0 && c.lap_order != 2 && c.lap_order != 4 && c.lap_order != 6))
       return PM_EINVAL;
+  } else if (c.force == PM_FORCE_NUFFT) {
+    // exact i k gradient and -k^2 (Sec. "Force evaluation"), width-6 ES kernel on
+    // a grid upsampled by 2
+    if (c.es_width != 6 || c.n_g != 2 * c.n_p || c.grad_order != 0 || c.lap_order != 0 ||
+        !(c.es_beta > 0))
+      return PM_EINVAL;
   } else {
-    return PM_EUNSUPPORTED;
+    return PM_EINVAL;
   }
   if (c.spectrum != PM_SPEC_BBKS && c.spectrum != PM_SPEC_POWERLAW) return PM_EINVAL;
   pm_ctx* ctx = new (std::nothrow) pm_ctx();
@@ -361,6 +581,7 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
   ctx->slot_steps.assign(c.batch, c.n_steps);
   ctx->slot_sigma8.assign(c.batch, c.sigma8);
   ctx->slot_table.assign(c.batch, ctx->table);
+  ctx->user_mask = all_mask(c.batch);
   build_tables(ctx);
   *out = ctx;
   return PM_OK;
@@ -393,7 +614,25 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   c->mesh = (long long*)(ws + L.off_mesh);
   c->spec = (float2*)(ws + L.off_spec);
   c->phi = (float*)(ws + L.off_phi);
-  c->gbar = with_adjoint ? (float*)(ws + L.off_gbar) : nullptr;
+  c->T = tile_edge(c->cfg.n_g);
+  c->log2T = ilog2(c->T);
+  c->log2nt = ilog2(c->cfg.n_g / c->T);
+  c->n_tiles = 1 << (3 * c->log2nt);
+  c->ts = (c->n_tiles + 1 + 63) / 64 * 64;
+  c->key = (int32_t*)(ws + L.off_key);
+  c->rank = (int32_t*)(ws + L.off_rank);
+  c->sorted = (int32_t*)(ws + L.off_sorted);
+  c->count = (int32_t*)(ws + L.off_count);
+  c->offset = (int32_t*)(ws + L.off_offset);
+  c->scratch = (void*)(ws + L.off_scratch);
+  c->u_sorted = with_adjoint ? (float*)(ws + L.off_u) : nullptr;
+  c->d_es_tab = (int32_t*)(ws + L.off_es_tab);
+  c->d_esdec = (float*)(ws + L.off_esdec);
+  c->force3 = c->cfg.force == PM_FORCE_NUFFT ? (float*)(ws + L.off_force3) : nullptr;
+  c->spec2 = c->cfg.force == PM_FORCE_NUFFT ? (float2*)(ws + L.off_spec2) : nullptr;
+  c->umax = (float*)(ws + L.off_umax);
+  c->scale = (double*)(ws + L.off_scale);
+  c->inv_scale = c->scale + kMaxBatch;
   c->icspec = (float2*)(ws + L.off_icspec);
   c->pk_partial = (double*)(ws + L.off_pk);
   c->dot_partial = (double*)(ws + L.off_dot);
@@ -409,6 +648,8 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   HIPCHK(c, hipMemcpyAsync(c->d_win2, c->win2.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_amp, c->amp_tab.data(), sizeof(float) * c->amp_tab.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_cic4, c->cic4.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_es_tab, c->es_tab.data(), sizeof(int32_t) * c->es_tab.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_esdec, c->esdec.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
   // host tables must outlive the copies: wait for them here (bind is not on the hot path)
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->bound = true;
@@ -432,6 +673,13 @@ pm_status pm_describe(const pm_ctx* c, double* out) {
   out[0] = c->D0;
   out[1] = c->D_ref;
   out[2] = c->amp;
+  return PM_OK;
+}
+
+pm_status pm_set_active(pm_ctx* c, uint64_t mask) {
+  if (!c) return PM_EINVAL;
+  if (!mask || (mask & ~all_mask(c->cfg.batch))) return fail(c, PM_EINVAL, "slot mask empty or beyond the batch");
+  c->user_mask = mask;
   return PM_OK;
 }
 
@@ -492,11 +740,13 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
   if (!seeds && !w_in) return fail(c, PM_EINVAL, "need seeds or w_in");
   const int B = c->cfg.batch, np = c->cfg.n_p;
   const long long N = c->g.N;
-  const unsigned long long act = all_mask(B);
-  if (w_in)
-    HIPCHK(c, hipMemcpyAsync(c->w, w_in, sizeof(float) * N * B, hipMemcpyDeviceToDevice, c->stream));
-  else
-    KLAUNCH(c, PM_K_MISC, launch_white_noise(c->w, N, N, B, seeds, c->stream));
+  const unsigned long long act = c->user_mask;
+  if (w_in) {
+    for (int b = 0; b < B; ++b)
+      if ((act >> b) & 1ull)
+        HIPCHK(c, hipMemcpyAsync(c->w + b * N, w_in + b * N, sizeof(float) * N, hipMemcpyDeviceToDevice, c->stream));
+  } else
+    KLAUNCH(c, PM_K_MISC, launch_white_noise(c->w, N, N, B, seeds, act, c->stream));
   float2* wspec = c->icspec + 3 * c->icspec_comp;
   pm_status st = r2c_mesh(c, c->w, SRC_F32, N, 1.0, 0.0, wspec, c->icspec_stride, np, true, act);
   if (st) return st;
@@ -538,10 +788,13 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
     rl.scale = 1.0;
     rl.scale2 = c->D0;
     rl.stream = c->stream;
+    rl.active = act;
     KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   }
   if (w_out)
-    HIPCHK(c, hipMemcpyAsync(w_out, c->w, sizeof(float) * N * B, hipMemcpyDeviceToDevice, c->stream));
+    for (int b = 0; b < B; ++b)
+      if ((act >> b) & 1ull)
+        HIPCHK(c, hipMemcpyAsync(w_out + b * N, c->w + b * N, sizeof(float) * N, hipMemcpyDeviceToDevice, c->stream));
   c->ics_done = true;
   c->ran = false;
   return PM_OK;
@@ -552,20 +805,7 @@ static pm_status step_common(pm_ctx* c, const double* tau_pre, bool pre_drift, c
                              unsigned long long active) {
   pm_status st = potential(c, c->disp, pre_drift ? c->vel : nullptr, tau_pre, s, active);
   if (st) return st;
-  GatherArgs a{};
-  a.g = c->g;
-  a.batch = c->cfg.batch;
-  a.disp = c->disp;
-  a.vel = c->vel;
-  a.phi = c->phi;
-  a.active = active;
-  for (int b = 0; b < c->cfg.batch; ++b) {
-    a.alpha[b] = (float)alpha[b];
-    a.beta[b] = (float)beta[b];
-    a.tau[b] = (float)tau_post[b];
-  }
-  KLAUNCH(c, PM_K_GATHER_KICK, launch_gather(a, GK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
-  return PM_OK;
+  return kick(c, c->disp, alpha, beta, tau_post, nullptr, active);
 }
 
 pm_status pm_step(pm_ctx* c, const int32_t* step_index) {
@@ -583,6 +823,7 @@ pm_status pm_step(pm_ctx* c, const int32_t* step_index) {
     tp[b] = sc.tau1; s[b] = sc.s; al[b] = sc.alpha; be[b] = sc.beta; tq[b] = sc.tau2;
     act |= 1ull << b;
   }
+  act &= c->user_mask;
   if (!act) return PM_OK;
   pm_status st = step_common(c, tp.data(), true, s.data(), al.data(), be.data(), tq.data(), act);
   if (st) return st;
@@ -607,6 +848,8 @@ pm_status pm_run(pm_ctx* c) {
       tq[b] = T[n].tau2 + (n + 1 < c->slot_steps[b] ? T[n + 1].tau1 : 0.0);  // merged drifts
       act |= 1ull << b;
     }
+    act &= c->user_mask;
+    if (!act) continue;
     pm_status st = step_common(c, tp.data(), n == 0, s.data(), al.data(), be.data(), tq.data(), act);
     if (st) return st;
   }
@@ -618,6 +861,7 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!c->ran) return fail(c, PM_ESTATE, "pm_adjoint before pm_run");
+  if (c->cfg.force != PM_FORCE_PM) return fail(c, PM_EUNSUPPORTED, "adjoint of the NUFFT force is not built");
   if (!dL_ddelta || !dL_dw || !dL_dsigma8) return PM_EINVAL;
   const int B = c->cfg.batch, np = c->cfg.n_p;
   const long long N = c->g.N, M = c->g.M;
@@ -627,63 +871,66 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   int nmax = 0;
   for (int b = 0; b < B; ++b) nmax = std::max(nmax, c->slot_steps[b]);
   // loss pullback through the final CIC density and the last half drift
-  GatherArgs a{};
-  a.g = c->g;
-  a.batch = B;
-  a.disp = c->disp;
-  a.vel = c->vel;
-  a.xbar = c->xbar;
-  a.vbar = c->vbar;
-  a.gbar = c->gbar;
-  a.phi = dL_ddelta;
-  a.active = all_mask(B);
+  const unsigned long long all = c->user_mask;
+  pm_status st0 = bin(c, c->disp, nullptr, nullptr, 2, all);
+  if (st0) return st0;
+  TileArgs lv = tile_args(c, c->disp, all);
+  lv.mesh_in = dL_ddelta;
   for (int b = 0; b < B; ++b) {
-    a.coef[b] = (float)mfac;
-    a.tau[b] = (float)c->slot_table[b][c->slot_steps[b] - 1].tau2;
+    lv.coef[b] = (float)mfac;
+    lv.tau[b] = (float)c->slot_table[b][c->slot_steps[b] - 1].tau2;
   }
-  KLAUNCH(c, PM_K_ADJ_DRIFT, launch_gather(a, GK_ADJ_DRIFT, 2, c->cfg.grad_order, c->stream));
+  KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile(lv, TK_ADJ_DRIFT, 2, c->cfg.grad_order, c->stream));
+  // sum |c_s| of the FD stencil: bounds the transposed gather per unit |u|
+  const double fd_l1 = c->cfg.grad_order == 2 ? 1.0 : (c->cfg.grad_order == 4 ? 1.5 : 110.0 / 60.0);
+  const int ord = c->cfg.grad_order, mak = c->cfg.mak;
   for (int n = nmax - 1; n >= 0; --n) {
     std::vector<double> s(B, 1);
     unsigned long long act = 0;
     for (int b = 0; b < B; ++b)
       if (n < c->slot_steps[b]) { s[b] = c->slot_table[b][n].s; act |= 1ull << b; }
-    // force at X^{n+1/2}
+    act &= c->user_mask;
+    if (!act) continue;
+    // force at X^{n+1/2} (bins the particles by tile for the kernels below)
     pm_status st = potential(c, c->disp, nullptr, nullptr, s.data(), act);
     if (st) return st;
-    KLAUNCH(c, PM_K_FILL, launch_fill(c->gbar, (long long)sizeof(float) * 3 * M * B, c->stream));
-    GatherArgs k = a;
-    k.phi = c->phi;
-    k.active = act;
+    KLAUNCH(c, PM_K_FILL, launch_fill(c->umax, (long long)sizeof(float) * kMaxBatch, c->stream));
+    TileArgs k = tile_args(c, c->disp, act);
+    k.mesh_in = c->phi;
     for (int b = 0; b < B; ++b) {
       if (!((act >> b) & 1)) continue;
       const StepCoef& sc = c->slot_table[b][n];
       k.alpha[b] = (float)sc.alpha;
       k.beta[b] = (float)sc.beta;
     }
-    KLAUNCH(c, PM_K_ADJ_KICK, launch_gather(k, GK_ADJ_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
-    // mesh cotangent: d = sum_c FD_c^T g_bar_c, then the transposed multiplier
+    KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(k, TK_ADJ_KICK, mak, ord, c->stream));
+    // mesh cotangent of the force: transposed FD gather in fixed point
+    KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
+                                              3.0 * fd_l1 * (double)N, B, c->stream));
+    KLAUNCH(c, PM_K_DIPOLE, launch_tile(k, TK_DIPOLE, mak, ord, c->stream));
     float* d = reinterpret_cast<float*>(c->mesh);
-    KLAUNCH(c, PM_K_FD_DIV, launch_fd_div(c->gbar, d, c->g, B, c->cfg.grad_order, act, c->stream));
+    AssembleArgs as = assemble_args(c, dipole_halo(ord), d, act);
+    KLAUNCH(c, PM_K_ASSEMBLE, launch_assemble(as, true, c->stream));
+    // transposed multiplier (H is real and even)
     st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
     if (st) return st;
     st = poisson_to_real(c, s.data(), c->phi, act);
     if (st) return st;
-    GatherArgs dr = a;
-    dr.phi = c->phi;
-    dr.active = act;
+    TileArgs dr = tile_args(c, c->disp, act);
+    dr.mesh_in = c->phi;
     for (int b = 0; b < B; ++b) {
       dr.coef[b] = (float)mfac;
       if (!((act >> b) & 1)) continue;
       const auto& T = c->slot_table[b];
       dr.tau[b] = (float)(T[n].tau1 + (n > 0 ? T[n - 1].tau2 : 0.0));
     }
-    KLAUNCH(c, PM_K_ADJ_DRIFT, launch_gather(dr, GK_ADJ_DRIFT, c->cfg.mak, c->cfg.grad_order, c->stream));
+    KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile(dr, TK_ADJ_DRIFT, mak, ord, c->stream));
   }
   // initial conditions: psi_bar = D0 X_bar + V_bar, w_bar = sum_c T_c^T psi_bar_c
   std::vector<float> d0(B, (float)c->D0);
-  float* psibar = c->gbar;
-  KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->stream));
-  const unsigned long long act = all_mask(B);
+  float* psibar = c->u_sorted;
+  KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->user_mask, c->stream));
+  const unsigned long long act = c->user_mask;
   for (int comp = 0; comp < 3; ++comp) {
     pm_status st = r2c_mesh(c, psibar + comp * N, SRC_F32, 3 * N, 1.0, 0.0,
                             c->icspec + comp * c->icspec_comp, c->icspec_stride, np, true, act);
@@ -722,11 +969,12 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   rl.tws_full = c->Lmax / np;
   rl.scale = 1.0;
   rl.stream = c->stream;
+  rl.active = act;
   KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   // dL/dsigma8 = <psi_bar, psi>/sigma8 = <w_bar, w>/sigma8 (psi is linear in w and sigma8)
   std::vector<double> inv(B);
   for (int b = 0; b < B; ++b) inv[b] = 1.0 / c->slot_sigma8[b];
-  KLAUNCH(c, PM_K_MISC, launch_dot(dL_dw, c->w, N, N, B, c->dot_partial, dL_dsigma8, inv.data(), c->stream));
+  KLAUNCH(c, PM_K_MISC, launch_dot(dL_dw, c->w, N, N, B, c->dot_partial, dL_dsigma8, inv.data(), act, c->stream));
   c->ran = false;
   return PM_OK;
 }
@@ -738,7 +986,7 @@ pm_status pm_power_spectrum(pm_ctx* c, int32_t n_bins, int32_t deconvolve_cic, d
   const int n = c->cfg.n_g;
   if (n_bins < 1 || n_bins > n || n_bins > 512 || !k_mean || !pk || !n_modes)
     return fail(c, PM_EINVAL, "n_bins must be in [1, min(n_g, 512)]");
-  const unsigned long long act = all_mask(c->cfg.batch);
+  const unsigned long long act = c->user_mask;
   pm_status st = deposit(c, c->disp, nullptr, nullptr, 2, c->mesh, act);
   if (st) return st;
   const double N = (double)c->g.N, n3 = (double)c->g.M;
@@ -748,22 +996,24 @@ pm_status pm_power_spectrum(pm_ctx* c, int32_t n_bins, int32_t deconvolve_cic, d
   const double L = c->cfg.box;
   KLAUNCH(c, PM_K_MISC, launch_pk(c->spec, c->g.spec_stride, n, c->cfg.batch, n_bins, 2.0 * M_PI / L,
                       L * L * L / (n3 * n3), c->d_cic4, deconvolve_cic, c->pk_partial, k_mean, pk,
-                      (long long*)n_modes, c->stream));
+                      (long long*)n_modes, act, c->stream));
   return PM_OK;
 }
 
 pm_status pm_density(pm_ctx* c, float* delta_out, int64_t* fixed_out) {
   if (pm_status st = check_bound(c)) return st;
   if (!c->ics_done) return fail(c, PM_ESTATE, "no particles yet");
-  const unsigned long long act = all_mask(c->cfg.batch);
+  const unsigned long long act = c->user_mask;
   pm_status st = deposit(c, c->disp, nullptr, nullptr, 2, c->mesh, act);
   if (st) return st;
   const double scale = (double)c->g.M / (double)c->g.N / 4294967296.0;
   if (delta_out)
-    KLAUNCH(c, PM_K_MISC, launch_i64_to_delta(c->mesh, delta_out, c->g.M, c->g.mesh_stride, c->cfg.batch, scale, c->stream));
+    KLAUNCH(c, PM_K_MISC, launch_i64_to_delta(c->mesh, delta_out, c->g.M, c->g.mesh_stride, c->cfg.batch, scale, act, c->stream));
   if (fixed_out)
-    HIPCHK(c, hipMemcpyAsync(fixed_out, c->mesh, sizeof(long long) * c->g.M * c->cfg.batch,
-                             hipMemcpyDeviceToDevice, c->stream));
+    for (int b = 0; b < c->cfg.batch; ++b)
+      if ((act >> b) & 1ull)
+        HIPCHK(c, hipMemcpyAsync(fixed_out + b * c->g.M, c->mesh + b * c->g.mesh_stride, sizeof(long long) * c->g.M,
+                                 hipMemcpyDeviceToDevice, c->stream));
   return PM_OK;
 }
 
@@ -788,9 +1038,20 @@ pm_status pm_set_state(pm_ctx* c, const float* disp, const float* vel) {
 
 pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_out) {
   if (pm_status st = check_bound(c)) return st;
-  if (!disp || !mesh_out || (mak != 2 && mak != 3)) return PM_EINVAL;
-  return deposit(c, const_cast<float*>(disp), nullptr, nullptr, mak, (long long*)mesh_out,
-                 all_mask(c->cfg.batch));
+  if (!disp || !mesh_out || (mak != 2 && mak != 3 && mak != 6)) return PM_EINVAL;
+  if (mak == 6 && c->cfg.force != PM_FORCE_NUFFT)
+    return fail(c, PM_EINVAL, "ES spreading needs a NUFFT context");
+  float* x = const_cast<float*>(disp);
+  const unsigned long long act = all_mask(c->cfg.batch);
+  if (mak != 6) return deposit(c, x, nullptr, nullptr, mak, (long long*)mesh_out, act);
+  pm_status st = bin(c, x, nullptr, nullptr, 2, act);
+  if (st) return st;
+  TileArgs t = tile_args(c, x, act);
+  t.es_tab = c->d_es_tab;
+  KLAUNCH(c, PM_K_DEPOSIT, launch_tile_es(t, TK_ES_DEPOSIT, c->stream));
+  AssembleArgs as = assemble_args(c, 3, mesh_out, act);
+  KLAUNCH(c, PM_K_ASSEMBLE, launch_assemble(as, false, c->stream));
+  return PM_OK;
 }
 
 pm_status pm_force(pm_ctx* c, const float* disp, double s, float* acc_out) {
@@ -799,17 +1060,10 @@ pm_status pm_force(pm_ctx* c, const float* disp, double s, float* acc_out) {
   const int B = c->cfg.batch;
   std::vector<double> sv(B, s);
   const unsigned long long act = all_mask(B);
-  pm_status st = potential(c, const_cast<float*>(disp), nullptr, nullptr, sv.data(), act);
+  float* x = const_cast<float*>(disp);
+  pm_status st = potential(c, x, nullptr, nullptr, sv.data(), act);
   if (st) return st;
-  GatherArgs a{};
-  a.g = c->g;
-  a.batch = B;
-  a.disp = const_cast<float*>(disp);
-  a.phi = c->phi;
-  a.acc_out = acc_out;
-  a.active = act;
-  KLAUNCH(c, PM_K_GATHER_KICK, launch_gather(a, GK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
-  return PM_OK;
+  return kick(c, x, nullptr, nullptr, nullptr, acc_out, act);
 }
 
 pm_status pm_fft(pm_ctx* c, const void* in, void* out, int32_t inverse) {
@@ -856,6 +1110,7 @@ pm_status pm_fft(pm_ctx* c, const void* in, void* out, int32_t inverse) {
   rl.tws_full = c->Lmax / n;
   rl.scale = 1.0;
   rl.stream = c->stream;
+  rl.active = act;
   KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   return PM_OK;
 }

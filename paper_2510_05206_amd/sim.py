@@ -180,6 +180,12 @@ class PMSim:
     def synchronize(self):
         self.stream.synchronize()
 
+    def set_active(self, slots=None):
+        """Restrict whole-context calls to the given slot indices (None: all)."""
+        B = self.cfg.batch
+        mask = (1 << B) - 1 if slots is None else sum(1 << int(b) for b in slots)
+        self._call("pm_set_active", C.c_uint64(mask))
+
     def profile(self, on=True):
         self._call("pm_profile", int(bool(on)))
 

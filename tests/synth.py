@@ -33,13 +33,16 @@ def oracle_problem(d, **kw):
     from oracle.force import PMConfig
     from oracle.nbody import Problem
     d = dict(d, **kw)
+    extra = {}
+    if d.get("force") == "nufft":
+        extra = dict(force="nufft", es_width=d["es_width"], es_beta=d["es_beta"])
     pm = PMConfig(d["n_p"], d["n_g"], d["box"], order=d.get("mak", 2),
                   deconvolve=d.get("deconvolve", False), grad_order=d.get("grad_order", 4),
                   lap_order=d.get("lap_order", 0))
     return Problem(pm, omega_m=d.get("omega_m", 0.31), h=d.get("h", 0.68), n_s=d.get("n_s", 0.965),
                    sigma8=d.get("sigma8", 0.81), spectrum=d.get("spectrum", "bbks"),
                    rms_cells=d.get("pl_rms_cells", 0.2), a_start=d.get("a_start", 0.02),
-                   a_end=d.get("a_end", 1.0), n_steps=d.get("n_steps", 6))
+                   a_end=d.get("a_end", 1.0), n_steps=d.get("n_steps", 6), **extra)
 
 
 def displacements(n_p, seed, scale=1.5, kind="gauss"):
@@ -70,3 +73,10 @@ def random_mesh(n, seed):
 
 def cotangent(n_g, seed):
     return np.random.default_rng(seed).normal(size=n_g ** 3).astype(np.float32)
+
+# NUFFT force (ES width 6 at 2x upsampling, exact i k and -k^2)
+C3 = dict(n_p=512, n_g=1024, box=1000.0, omega_m=0.31, h=0.68, n_s=0.965, sigma8=0.81,
+          spectrum="bbks", a_start=0.02, a_end=1.0, n_steps=6, force="nufft", es_width=6,
+          es_beta=13.8, grad_order=0, lap_order=0, mak=2, deconvolve=False)
+C3_SUB = dict(C3, n_p=128, n_g=256, box=250.0)      # the 128^3 sub-problem (same resolution)
+C3_SMALL = dict(C3, n_p=32, n_g=64, box=62.5)

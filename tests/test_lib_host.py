@@ -72,3 +72,17 @@ def test_host_schedule_matches_oracle(lib, wl):
     prob = synth.oracle_problem(d)
     assert abs(desc[2] / prob.spectrum_fn().amp - 1) < 1e-8
     lib.pm_destroy(ctx)
+
+
+def test_serving_admission_respects_the_hbm_budget():
+    from paper_2510_05206_amd import serve
+    plan = serve.plan_batches(20e9, 16)
+    per = {(k, n): serve.workspace_bytes(serve.shape_config(n, 1), k == "grad") for (k, n) in plan}
+    used = sum(B * per[key] for key, B in plan.items())
+    # each bucket keeps at least one slot; beyond that the plan fits the budget
+    assert used <= max(20e9, sum(per.values())) * 1.0001
+    assert all(B >= 1 for B in plan.values())
+    # memory of the adjoint does not grow with the number of steps
+    a = serve.workspace_bytes(serve.shape_config(64, 1, max_steps=5), True)
+    b = serve.workspace_bytes(serve.shape_config(64, 1, max_steps=20), True)
+    assert a == b
