@@ -24,6 +24,7 @@ struct RowLaunch {
   int tws_half, tws_full;  // twiddle strides for the n/2 FFT and for exp(-2 pi i k/n)
   double scale, shift, scale2;
   unsigned long long active;  // bit b set: slot b takes part
+  int rs;                     // row stride of the half spectrum (float2), >= n/2 + 1
   hipStream_t stream;
 };
 
@@ -34,6 +35,7 @@ struct ColArgs {
   float2* dst3;        // MODE_IC_C: output spectrum
   long long slot_stride, comp_stride;
   int n, nh, axis;
+  int rs;              // row stride of the half spectrum (float2), >= nh
   const float2* tw;
   int tws;             // Lmax / n
   // PM multiplier H = coef / ((lap[ix]+lap[iy]+lap[iz]) win2[ix] win2[iy] win2[iz]), 0 at k = 0

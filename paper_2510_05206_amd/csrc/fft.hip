@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows(const void* __restrict__ src, 
                                                   float2* __restrict__ dst, long long dst_stride,
                                                   int n_rows, const float2* __restrict__ tw,
                                                   int tws_half, int tws_full, double scale,
-                                                  double shift, unsigned long long active) {
+                                                  double shift, unsigned long long active, int rs) {
   constexpr int R = rows_per_block<L>();
   constexpr int n = 2 * L;
   __shared__ float2 buf[R * (L + 1)];
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows(const void* __restrict__ src, 
   for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
     int r = e / (L + 1), k = e - r * (L + 1);
     long long row = row0 + r;
-    if (row < n_rows) dst[slot * dst_stride + row * (L + 1) + k] = buf[e];
+    if (row < n_rows) dst[slot * dst_stride + row * rs + k] = buf[e];
   }
 }
 
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) k_c2r_rows(const float2* __restrict__ src
                                                   float* __restrict__ dst2, int n_rows,
                                                   const float2* __restrict__ tw, int tws_half,
                                                   int tws_full, float scale, float scale2,
-                                                  unsigned long long active) {
+                                                  unsigned long long active, int rs) {
   constexpr int R = rows_per_block<L>();
   constexpr int n = 2 * L;
   __shared__ float2 buf[R * (L + 1)];
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) k_c2r_rows(const float2* __restrict__ src
   for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
     int r = e / (L + 1), k = e - r * (L + 1);
     long long row = row0 + r;
-    buf[e] = row < n_rows ? src[slot * src_stride + row * (L + 1) + k] : make_float2(0.f, 0.f);
+    buf[e] = row < n_rows ? src[slot * src_stride + row * rs + k] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   // pack: Z[k] = (X[k] + conj X[L-k]) + i e^{+2 pi i k/n} (X[k] - conj X[L-k])
@@ -255,8 +255,8 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
   if (!((a.active >> slot) & 1ull)) return;
   const int outer = blockIdx.y;          // x for the y pass, y for the x pass
   const int z0 = blockIdx.x * C;
-  const long long stride_t = a.axis == 1 ? (long long)a.nh : (long long)a.n * a.nh;
-  const long long base0 = a.axis == 1 ? (long long)outer * a.n * a.nh : (long long)outer * a.nh;
+  const long long stride_t = a.axis == 1 ? (long long)a.rs : (long long)a.n * a.rs;
+  const long long base0 = a.axis == 1 ? (long long)outer * a.n * a.rs : (long long)outer * a.rs;
   const long long sbase = slot * a.slot_stride + base0 + z0;
   for (int e = threadIdx.x; e < L * C; e += 256) {
     int t = e / C, c = e - t * C;
@@ -337,20 +337,20 @@ static hipError_t launch_rows(const RowLaunch& r) {
     if (r.dst_mode == DST_F32)
       k_c2r_rows<L, DST_F32><<<grid, 256, 0, r.stream>>>(
           (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows,
-          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active);
+          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs);
     else
       k_c2r_rows<L, DST_IC><<<grid, 256, 0, r.stream>>>(
           (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows,
-          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active);
+          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs);
   } else {
     if (r.src_mode == SRC_I64)
       k_r2c_rows<L, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst,
                                                          r.dst_stride, r.n_rows, r.tw, r.tws_half,
-                                                         r.tws_full, r.scale, r.shift, r.active);
+                                                         r.tws_full, r.scale, r.shift, r.active, r.rs);
     else
       k_r2c_rows<L, SRC_F32><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst,
                                                          r.dst_stride, r.n_rows, r.tw, r.tws_half,
-                                                         r.tws_full, r.scale, r.shift, r.active);
+                                                         r.tws_full, r.scale, r.shift, r.active, r.rs);
   }
   return hipGetLastError();
 }
@@ -387,8 +387,9 @@ static hipError_t launch_cols_c(const ColArgs& a, int mode, int batch, hipStream
 
 template <int L>
 static hipError_t launch_cols(const ColArgs& a, int mode, int batch, hipStream_t s) {
-  // keep a tile near 32-64 KB of LDS
-  constexpr int C = L >= 1024 ? 8 : (L >= 512 ? 8 : 16);
+  // 16 columns = one 128-byte line per row (rows are padded to 16 complex);
+  // 64 KB of LDS at n = 512, 8 columns at n = 1024
+  constexpr int C = L >= 1024 ? 8 : 16;
   return launch_cols_c<L, C>(a, mode, batch, s);
 }
 

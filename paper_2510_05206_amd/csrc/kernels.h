@@ -82,6 +82,6 @@ hipError_t launch_i64_to_delta(const long long* m, float* delta, long long M, lo
 hipError_t launch_pk(const float2* spec, long long slot_stride, int n, int batch, int n_bins,
                      double kf, double norm, const double* cic4, int deconv, double* partial,
                      double* k_mean, double* pk, long long* n_modes, unsigned long long active,
-                     hipStream_t s);
+                     int rs, hipStream_t s);
 
 }  // namespace pm

@@ -163,7 +163,7 @@ __device__ __forceinline__ int pk_bin(long long m2) {
 __global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, long long slot_stride, int n,
                                                     int n_bins, double kf, const double* cic4,
                                                     int deconv, double* partial,
-                                                    unsigned long long active) {
+                                                    unsigned long long active, int rs) {
   extern __shared__ double acc[];  // [3][n_bins][4]
   const int slot = blockIdx.y, x = blockIdx.x;
   if (!((active >> slot) & 1ull)) return;
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, long lon
         }
         if (b) {
           double wm = (z == 0 || z == n / 2) ? 1.0 : 2.0;
-          float2 X = spec[slot * slot_stride + ((long long)x * n + y) * nh + z];
+          float2 X = spec[slot * slot_stride + ((long long)x * n + y) * rs + z];
           double p = (double)X.x * X.x + (double)X.y * X.y;
           if (deconv) p /= cic4[x] * cic4[y] * cic4[z];
           vp = wm * p;
@@ -240,10 +240,10 @@ __global__ void k_pk_final(const double* partial, int n, int n_bins, double norm
 hipError_t launch_pk(const float2* spec, long long slot_stride, int n, int batch, int n_bins,
                      double kf, double norm, const double* cic4, int deconv, double* partial,
                      double* k_mean, double* pk, long long* n_modes, unsigned long long active,
-                     hipStream_t s) {
+                     int rs, hipStream_t s) {
   size_t lds = (size_t)3 * n_bins * 4 * sizeof(double);
   k_pk_partial<<<dim3(n, batch), 256, lds, s>>>(spec, slot_stride, n, n_bins, kf, cic4, deconv,
-                                                partial, active);
+                                                partial, active, rs);
   k_pk_final<<<dim3((n_bins + 63) / 64, batch), 64, 0, s>>>(partial, n, n_bins, norm, k_mean, pk,
                                                            n_modes, active);
   return hipGetLastError();

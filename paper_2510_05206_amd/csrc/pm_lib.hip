@@ -139,7 +139,10 @@ struct Layout {
 int tile_edge(int n) { return n < 16 ? n : 16; }
 int dipole_halo(int grad_order) { return 1 + grad_order / 2; }
 
-long long spec_elems(int n) { return (long long)n * n * (n / 2 + 1); }
+// half-spectrum row stride: n/2 + 1 complex, padded to 16 (one 128-byte line)
+// from n = 32 so that column tiles read whole aligned lines
+int spec_rs(int n) { int nh = n / 2 + 1; return n >= 32 ? (nh + 15) / 16 * 16 : nh; }
+long long spec_elems(int n) { return (long long)n * n * spec_rs(n); }
 
 Layout layout(const pm_ctx* c, bool adj) {
   Layout L{};
@@ -282,6 +285,7 @@ pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_strid
                    unsigned long long active) {
   RowLaunch r{};
   r.n = n;
+  r.rs = spec_rs(n);
   r.n_rows = (long long)n * n;
   r.batch = c->cfg.batch;
   r.inverse = false;
@@ -303,6 +307,7 @@ pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_strid
   a.slot_stride = dst_stride;
   a.n = n;
   a.nh = n / 2 + 1;
+  a.rs = spec_rs(n);
   a.tw = c->d_tw;
   a.tws = c->Lmax / n;
   a.active = active;
@@ -323,6 +328,7 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
   a.slot_stride = c->g.spec_stride;
   a.n = n;
   a.nh = n / 2 + 1;
+  a.rs = spec_rs(n);
   a.tw = c->d_tw;
   a.tws = c->Lmax / n;
   a.lap = c->d_lap;
@@ -337,6 +343,7 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_INV, c->cfg.batch, c->stream));
   RowLaunch rl{};
   rl.n = n;
+  rl.rs = spec_rs(n);
   rl.n_rows = (long long)n * n;
   rl.batch = c->cfg.batch;
   rl.inverse = true;
@@ -472,6 +479,7 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   a.slot_stride = c->g.spec_stride;
   a.n = n;
   a.nh = n / 2 + 1;
+  a.rs = spec_rs(n);
   a.tw = c->d_tw;
   a.tws = c->Lmax / n;
   a.active = active;
@@ -490,6 +498,7 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
     KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, c->cfg.batch, c->stream));
     RowLaunch rl{};
     rl.n = n;
+    rl.rs = spec_rs(n);
     rl.n_rows = (long long)n * n;
     rl.batch = c->cfg.batch;
     rl.inverse = true;
@@ -755,6 +764,7 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
   a.slot_stride = c->icspec_stride;
   a.n = np;
   a.nh = np / 2 + 1;
+  a.rs = spec_rs(np);
   a.tw = c->d_tw;
   a.tws = c->Lmax / np;
   a.amp = c->d_amp;
@@ -773,6 +783,7 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
     KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
     RowLaunch rl{};
     rl.n = np;
+    rl.rs = spec_rs(np);
     rl.n_rows = (long long)np * np;
     rl.batch = B;
     rl.inverse = true;
@@ -944,6 +955,7 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   ca.slot_stride = c->icspec_stride;
   ca.n = np;
   ca.nh = np / 2 + 1;
+  ca.rs = spec_rs(np);
   ca.tw = c->d_tw;
   ca.tws = c->Lmax / np;
   ca.amp = c->d_amp;
@@ -956,6 +968,7 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(ca, MODE_INV, B, c->stream));
   RowLaunch rl{};
   rl.n = np;
+  rl.rs = spec_rs(np);
   rl.n_rows = (long long)np * np;
   rl.batch = B;
   rl.inverse = true;
@@ -996,7 +1009,7 @@ pm_status pm_power_spectrum(pm_ctx* c, int32_t n_bins, int32_t deconvolve_cic, d
   const double L = c->cfg.box;
   KLAUNCH(c, PM_K_MISC, launch_pk(c->spec, c->g.spec_stride, n, c->cfg.batch, n_bins, 2.0 * M_PI / L,
                       L * L * L / (n3 * n3), c->d_cic4, deconvolve_cic, c->pk_partial, k_mean, pk,
-                      (long long*)n_modes, act, c->stream));
+                      (long long*)n_modes, act, spec_rs(n), c->stream));
   return PM_OK;
 }
 
@@ -1071,23 +1084,26 @@ pm_status pm_fft(pm_ctx* c, const void* in, void* out, int32_t inverse) {
   if (!in || !out) return PM_EINVAL;
   const int n = c->cfg.n_g, B = c->cfg.batch;
   const unsigned long long act = all_mask(B);
-  const size_t sbytes = sizeof(float2) * spec_elems(n);
+  const long long nh = n / 2 + 1, cn = (long long)n * n * nh;  // compact user layout
   if (!inverse) {
     pm_status st = r2c_mesh(c, in, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, n, true, act);
     if (st) return st;
     for (int b = 0; b < B; ++b)
-      HIPCHK(c, hipMemcpyAsync((float2*)out + b * spec_elems(n), c->spec + b * c->g.spec_stride, sbytes,
-                               hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpy2DAsync((float2*)out + b * cn, sizeof(float2) * nh, c->spec + b * c->g.spec_stride,
+                                 sizeof(float2) * spec_rs(n), sizeof(float2) * nh, (size_t)n * n,
+                                 hipMemcpyDeviceToDevice, c->stream));
     return PM_OK;
   }
   for (int b = 0; b < B; ++b)
-    HIPCHK(c, hipMemcpyAsync(c->spec + b * c->g.spec_stride, (const float2*)in + b * spec_elems(n), sbytes,
-                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpy2DAsync(c->spec + b * c->g.spec_stride, sizeof(float2) * spec_rs(n),
+                               (const float2*)in + b * cn, sizeof(float2) * nh, sizeof(float2) * nh,
+                               (size_t)n * n, hipMemcpyDeviceToDevice, c->stream));
   ColArgs a{};
   a.data = c->spec;
   a.slot_stride = c->g.spec_stride;
   a.n = n;
   a.nh = n / 2 + 1;
+  a.rs = spec_rs(n);
   a.tw = c->d_tw;
   a.tws = c->Lmax / n;
   a.active = act;
@@ -1097,6 +1113,7 @@ pm_status pm_fft(pm_ctx* c, const void* in, void* out, int32_t inverse) {
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_INV, B, c->stream));
   RowLaunch rl{};
   rl.n = n;
+  rl.rs = spec_rs(n);
   rl.n_rows = (long long)n * n;
   rl.batch = B;
   rl.inverse = true;
