@@ -47,6 +47,14 @@ def force_vjp(cfg: PMConfig, psi, s, u):
     return xbar
 
 
+def problem_force_vjp(prob, psi, s, u):
+    """VJP of the force the problem uses (PM or NUFFT)."""
+    if prob.force == "pm":
+        return force_vjp(prob.pm, psi, s, u)
+    from . import nufft
+    return nufft.nufft_force_vjp(prob.pm.n_p, prob.pm.n_g, psi, s, u, prob.es_width, prob.es_beta)
+
+
 def density_vjp(psi, n_p, n_g, dbar):
     """VJP of the final CIC contrast delta(Psi) w.r.t. Psi."""
     return mesh.grad_gather(np.asarray(dbar, dtype=np.float64) * (n_g ** 3 / n_p ** 3),
@@ -91,7 +99,7 @@ def reverse_cotangents(prob, record, xbar, vbar):
     midpoints, last step first."""
     for st, (psi_half, _acc) in zip(reversed(prob.steps()), reversed(record)):
         vbar = vbar + st.tau2 * xbar                    # adjoint of drift 2
-        xbar = xbar + force_vjp(prob.pm, psi_half, st.s, st.beta * vbar)  # adjoint kick
+        xbar = xbar + problem_force_vjp(prob, psi_half, st.s, st.beta * vbar)  # adjoint kick
         vbar = st.alpha * vbar                          # velocity rescale
         vbar = vbar + st.tau1 * xbar                    # adjoint of drift 1
     return xbar, vbar

@@ -95,6 +95,16 @@ def nudft_force_direct(n_p, n_f, psi, s):
     return A
 
 
+def es_kernel_deriv(x, width, beta):
+    """d phi / dx at a fine-grid offset x (cells), inside the support; the
+    jump of phi at |z| = 1 (of size exp(-beta)) carries no derivative."""
+    half = width / 2.0
+    z = np.asarray(x, dtype=np.float64) / half
+    inside = np.abs(z) < 1.0
+    root = np.sqrt(np.clip(1.0 - z * z, 1e-300, None))
+    return np.where(inside, es_phi(z, beta) * beta * (-z / root) / half, 0.0)
+
+
 def _es_axis_weights(u, width, beta):
     """First node floor(u) - w/2 + 1 and the w kernel values per axis."""
     base = np.floor(u).astype(np.int64) - (width // 2 - 1)
@@ -140,6 +150,79 @@ def _interp_float(field, u, n_f, width, beta):
                 iz = (base[2] + c) % n_f
                 v += f[(ix * n_f + iy) * n_f + iz] * (wab * wts[2][c])[:, None]
     return v
+
+
+def _interp_grad(field, u, n_f, width, beta):
+    """d/du_i of sum_j field_j phi(u_i - j): shape (N, components, 3)."""
+    f = field.reshape(n_f ** 3, -1)
+    base = np.floor(u).astype(np.int64) - (width // 2 - 1)
+    w = [np.stack([es_kernel(base[a] + o - u[a], width, beta) for o in range(width)]) for a in range(3)]
+    # d/du phi(u - j) = phi'(u - j): offsets are u - node
+    d = [np.stack([es_kernel_deriv(u[a] - (base[a] + o), width, beta) for o in range(width)])
+         for a in range(3)]
+    g = np.zeros((u.shape[1], f.shape[1], 3))
+    for a in range(width):
+        ix = (base[0] + a) % n_f
+        for b in range(width):
+            iy = (base[1] + b) % n_f
+            for c in range(width):
+                iz = (base[2] + c) % n_f
+                fv = f[(ix * n_f + iy) * n_f + iz]
+                g[:, :, 0] += fv * (d[0][a] * w[1][b] * w[2][c])[:, None]
+                g[:, :, 1] += fv * (w[0][a] * d[1][b] * w[2][c])[:, None]
+                g[:, :, 2] += fv * (w[0][a] * w[1][b] * d[2][c])[:, None]
+    return g
+
+
+def _nufft_pieces(n_p, n_f, N, s, width, beta):
+    """Kept-mode index sets and the multipliers of the map b -> c_c:
+    c_c = n_f^3 IDFT(pad(D_c restrict(DFT(b)))), D_c = K_c (n_p^3/N) / Phi^2,
+    Phi = phi_hat(mx) phi_hat(my) phi_hat(mz)."""
+    ms = kept_modes(n_p)
+    mz = np.arange(0, n_p // 2)
+    ix = ms % n_f
+    ph = lambda m: es_phihat(2 * np.pi * m / n_f, width, beta)
+    Phi = ph(ms)[:, None, None] * ph(ms)[None, :, None] * ph(mz)[None, None, :]
+    MX, MY, MZ = np.meshgrid(ms, ms, mz, indexing="ij")
+    K = _force_multiplier(MX, MY, MZ, n_p, s)
+    D = [K[c] * (n_p ** 3 / N) / Phi ** 2 for c in range(3)]
+    return ix, mz, D
+
+
+def nufft_force_vjp(n_p, n_f, psi, s, v, width=6, beta=13.8):
+    """J_A(Psi)^T v for the spreading NUFFT force of ``nufft_force``; v (3, N).
+
+    A_c(u_i) = (1/n_p^3) sum_j c_c,j phi(u_i - j), c_c = G_c b, b = spread(u),
+    u = (q + Psi) sigma.  Two parts (App. "Custom VJP and JVP"): the
+    interpolation differentiated w.r.t. the positions, and the transposed mesh
+    path G_c^T = n_f^3 IDFT(pad(conj(D_c) restrict(DFT(.)))) applied to the
+    spread of v_c / n_p^3, whose result is gathered with grad phi (the
+    spreading differentiated w.r.t. the positions)."""
+    u = fine_coords(psi, n_p, n_f)
+    N = u.shape[1]
+    sig = n_f / n_p
+    b = _spread_float(u, n_f, width, beta).reshape(n_f, n_f, n_f)
+    bk = np.fft.rfftn(b)
+    ix, mz, D = _nufft_pieces(n_p, n_f, N, s, width, beta)
+    sub = bk[np.ix_(ix, ix, mz)]
+    meshes = []
+    for c in range(3):
+        full = np.zeros((n_f, n_f, n_f // 2 + 1), dtype=np.complex128)
+        full[np.ix_(ix, ix, mz)] = D[c] * sub
+        meshes.append(np.fft.irfftn(full, s=(n_f, n_f, n_f), axes=(0, 1, 2)).reshape(-1) * n_f ** 3)
+    # direct part
+    g = _interp_grad(np.stack(meshes, axis=1), u, n_f, width, beta) / n_p ** 3   # (N, 3, 3)
+    xbar = np.einsum("ci,icd->di", v, g)
+    # mesh part
+    acc = np.zeros((len(ix), len(ix), len(mz)), dtype=np.complex128)
+    for c in range(3):
+        cbar = _spread_float(u, n_f, width, beta, weights=v[c] / n_p ** 3).reshape(n_f, n_f, n_f)
+        acc += np.conj(D[c]) * np.fft.rfftn(cbar)[np.ix_(ix, ix, mz)]
+    full = np.zeros((n_f, n_f, n_f // 2 + 1), dtype=np.complex128)
+    full[np.ix_(ix, ix, mz)] = acc
+    bbar = np.fft.irfftn(full, s=(n_f, n_f, n_f), axes=(0, 1, 2)).reshape(-1) * n_f ** 3
+    xbar += _interp_grad(bbar[:, None], u, n_f, width, beta)[:, 0, :].T
+    return xbar * sig
 
 
 def nufft_force(n_p, n_f, psi, s, width=6, beta=13.8):
