@@ -32,17 +32,84 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(cls, N, M):
-    """Minimum HBM bytes of one launch of a kernel class (per slot): particle
-    arrays are FP32 [3][N], meshes int64 or FP32 [M]."""
+def launch_model(cfg):
+    """Algorithmic HBM bytes of every timed launch of one bench step (ICs, the
+    forward run, density, P(k) and the adjoint of one slot, PM force), per
+    kernel class: a list of (launches, bytes per launch).  Minimum traffic:
+    every input read once and every output written once; particle arrays FP32
+    SoA [3][N] (12 B per particle each), the deposit mesh int64 [M], the other
+    meshes FP32 [M], half spectra complex64 of n^2 (n/2+1) modes (unpadded).
+    The lattice index of a particle and the tile binning tables are the
+    design's overhead, not algorithmic bytes."""
+    n, p, K = cfg.n_g, cfg.n_p, cfg.n_steps
+    M, N = n ** 3, p ** 3
+    Sn, Sp = 8 * n * n * (n // 2 + 1), 8 * p * p * (p // 2 + 1)   # bytes of one half spectrum
     return {
-        "deposit": 12 * N + 8 * M,          # read Psi, write the int64 mesh once
-        "gather_kick": 48 * N + 4 * M,      # read/write Psi, V; read phi
-        "adj_kick": 84 * N + 16 * M,        # read Psi,V,Xb,Vb; write V,Xb,Vb; read phi; 3 meshes
-        "adj_drift": 84 * N + 4 * M,        # read Psi,V,Xb,Vb; write Psi,Xb,Vb; read rho_bar
-        "fd_div": 16 * M,                   # read 3 meshes, write 1
-        "fill": None, "fft_rows": None, "fft_cols": None, "misc": None,
-    }[cls]
+        # fixed-point mass assignment: read the positions, write the int64 mesh
+        "deposit": [(2 * K + 2, 12 * N + 8 * M)],
+        # counting sort: read positions, write the sorted index (the first
+        # force evaluation also drifts: read V, write the positions)
+        "bin": [(1, 40 * N), (2 * K + 2, 16 * N)],
+        # z rows: int64 or FP32 mesh -> half spectrum, and back to FP32
+        "fft_rows": [(2 * K + 1, 8 * M + Sn), (K, 4 * M + Sn), (3 * K, Sn + 4 * M),
+                     (4, 4 * N + Sp), (3, Sp + 8 * N), (1, Sp + 4 * N)],
+        # y / x passes (one with the fused multiplier): read + write the spectrum
+        "fft_cols": [(9 * K + 2, 2 * Sn), (15, 2 * Sp), (1, 4 * Sp)],
+        # read X, V and phi, write X, V
+        "gather_kick": [(K, 48 * N + 4 * M)],
+        # read X, V, X_bar, V_bar and phi; write V, X_bar, V_bar and u
+        "adj_kick": [(K, 96 * N + 4 * M)],
+        # read u and X, write the FP32 mesh cotangent
+        "dipole": [(K, 24 * N + 4 * M)],
+        # read X, V, X_bar, V_bar and the mesh cotangent; write X, X_bar, V_bar
+        "adj_drift": [(K + 1, 84 * N + 4 * M)],
+    }
+
+
+def source_digest():
+    """sha256 over the HIP/C++ sources of the library: HBM counter readings are
+    valid only for the kernels they were taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2510_05206_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per class and bench step from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary of this workload (scaled by a plain copy of
+    known size), or None when the summary is missing or the kernels changed
+    since it was taken."""
+    f = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(f):
+        return None
+    for line in open(f):
+        if line.startswith("<!-- traffic-json:"):
+            rec = json.loads(line[len("<!-- traffic-json:"):].rsplit("-->", 1)[0])
+            return rec["bytes_per_step"] if rec.get("sources_sha256") == source_digest() else None
+    return None
+
+
+def rooflines(cfg, kt, steps):
+    """Per-class HBM roofline: the model's bytes over the class's measured
+    time, after checking the model's launch count against the measured one."""
+    out = {}
+    for cls, parts in launch_model(cfg).items():
+        ms, nl = kt.get(cls, (0.0, 0))
+        count = sum(c for c, _ in parts) * steps
+        total = sum(c * b for c, b in parts) * steps
+        if nl != count or ms <= 0:
+            out[cls] = {"error": f"launch count {nl} != model {count}"}
+            continue
+        gbs = total / (ms * 1e-3) / 1e9
+        out[cls] = {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "ms_per_step": round(ms / steps, 3), "launches_per_step": count // steps,
+                    "avg_launch_us": round(ms / nl * 1e3, 2), "bytes_per_launch": round(total / count)}
+    return out
 
 
 def cpu_baseline():
@@ -117,6 +184,9 @@ def main():
     ap.add_argument("--workload", default="pm_256_512_tsc", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="one plain device copy of this size right before the timed steps "
+                         "(reference dispatch for HBM byte counters)")
     ap.add_argument("--serve", action="store_true", help="run the mixed-size serving trace instead")
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--hbm-budget-gb", type=float, default=160.0)
@@ -160,6 +230,12 @@ def main():
     for i in range(args.warmup):
         one_step(i)
     torch.cuda.synchronize()
+    if args.calibrate_copy_gib > 0:
+        src = torch.ones(int(args.calibrate_copy_gib * 2 ** 28), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)          # one elementwise read + write of known size
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_kernel_timing:
         sim.profile(True)
         sim.kernel_times()
@@ -177,14 +253,18 @@ def main():
     if not args.no_kernel_timing:
         kt = sim.kernel_times()
         sim.profile(False)
-        cands = {k: v for k, v in kt.items() if algorithmic_bytes(k, N, M) is not None and v[1] > 0}
-        dom = max(cands, key=lambda k: cands[k][0])
-        ms, n = cands[dom]
-        per = algorithmic_bytes(dom, N, M)
-        achieved = per / (ms / n * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-                "avg_launch_us": round(ms / n * 1e3, 1), "bytes_per_launch": per}
+        if cfg.force == "pm":
+            by_class = rooflines(cfg, kt, args.steps)
+            ok = {k: v for k, v in by_class.items() if "achieved" in v}
+            dom = max(ok, key=lambda k: ok[k]["ms_per_step"])
+            r = ok[dom]
+            traffic = measured_traffic(args.workload)
+            if traffic is not None:
+                traffic = round(traffic[dom] / r["launches_per_step"])
+            roof = {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": r["frac"], "traffic": traffic, "kernel": dom,
+                    "avg_launch_us": r["avg_launch_us"], "bytes_per_launch": r["bytes_per_launch"],
+                    "by_class": by_class}
     assert math.isfinite(float(out["ds"][0]))
 
     line = {

@@ -130,17 +130,16 @@ pm_status pm_describe(const pm_ctx* ctx, double* out);
 /* Kernel classes timed by pm_profile (HIP events on the bound stream). */
 enum {
   PM_K_FILL = 0,        /* zeroing of counters and cotangents            */
-  PM_K_DEPOSIT = 1,     /* fixed-point mass assignment into tile windows */
+  PM_K_DEPOSIT = 1,     /* fixed-point mass assignment: tile windows + halo sum into the mesh */
   PM_K_FFT_ROWS = 2,    /* z-row real<->complex FFT passes               */
   PM_K_FFT_COLS = 3,    /* y/x strided passes (incl. the fused multiplier) */
   PM_K_GATHER_KICK = 4, /* force gather + kick + drift                   */
   PM_K_ADJ_KICK = 5,    /* adjoint kick: reverse kick, direct X_bar       */
-  PM_K_DIPOLE = 6,      /* transposed force gather of the cotangent       */
+  PM_K_DIPOLE = 6,      /* transposed force gather of the cotangent: tile windows + halo sum */
   PM_K_ADJ_DRIFT = 7,   /* scatter-position VJP + reverse drifts          */
   PM_K_MISC = 8,        /* RNG, P(k), reductions, conversions            */
   PM_K_BIN = 9,         /* counting sort of particles by mesh tile        */
-  PM_K_ASSEMBLE = 10,   /* halo sum of the tile windows into a mesh       */
-  PM_K_COUNT = 11
+  PM_K_COUNT = 10
 };
 
 /* Enable (on != 0) or disable per-launch event timing of the kernel classes

@@ -16,7 +16,7 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EHIP, PM_ESTATE, PM_EUNSUPPORTED = 0, -1, -2, -3
 STATUS_NAMES = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_ENOMEM", -3: "PM_EHIP", -4: "PM_ESTATE",
                 -5: "PM_EUNSUPPORTED"}
 KERNEL_CLASSES = ["fill", "deposit", "fft_rows", "fft_cols", "gather_kick", "adj_kick", "dipole",
-                  "adj_drift", "misc", "bin", "assemble"]
+                  "adj_drift", "misc", "bin"]
 PM_FORCE_PM, PM_FORCE_NUFFT = 0, 1
 PM_SPEC_POWERLAW, PM_SPEC_BBKS = 0, 1
 

@@ -569,6 +569,31 @@ __device__ __forceinline__ int es_weights(long long U, const int32_t* tab, int w
   }
   return (int)h;
 }
+
+// float weights of the 6 nodes and d/du phi(u - node): the slope of the
+// table's linear interpolation (the derivative of the weights used above)
+__device__ __forceinline__ int es_weights_d(long long U, const int32_t* __restrict__ tab, float w[kEsW],
+                                            float dw[kEsW]) {
+  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
+  constexpr float slope = (float)(1 << (kFracBits - kEsShift)) * inv;  // 4096 samples per cell
+  const long long h = U >> kFracBits;
+#pragma unroll
+  for (int o = 0; o < kEsW; ++o) {
+    long long d = ((h - 2 + o) << kFracBits) - U;  // node - u
+    long long dist = d < 0 ? -d : d;
+    if (dist >= (long long)(kEsW / 2) << kFracBits) {
+      w[o] = 0.f;
+      dw[o] = 0.f;
+      continue;
+    }
+    int i = (int)(dist >> kEsShift), f = (int)(dist & ((1 << kEsShift) - 1));
+    int t0 = tab[i], t1 = tab[i + 1];
+    w[o] = (float)(t0 + (((t1 - t0) * f + (1 << (kEsShift - 1))) >> kEsShift)) * inv;
+    const float sl = (float)(t1 - t0) * slope;  // d phi / d dist
+    dw[o] = d < 0 ? sl : -sl;                   // d dist / du = sign(u - node)
+  }
+  return (int)h;
+}
 }  // namespace
 
 __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
@@ -675,6 +700,190 @@ __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
   }
 }
 
+// ------------------------------------------------ NUFFT adjoint (ES kernel)
+
+// reverse kick with the ES gather of the 3 force meshes and its position
+// gradient: V = (V - beta A) / alpha, V_bar = alpha V_bar, u = beta V_bar,
+// X_bar += r sum_c u_c dA_c/du; u kept in sorted order with max |u|
+__global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
+  extern __shared__ float fwin[];  // 3 windows of (T + 6)^3
+  __shared__ float red[256];
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int W = a.T + 2 * kEsR, W3 = W * W * W;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  for (int c = 0; c < 3; ++c)
+    load_window(fwin + c * W3, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsR,
+                a.g.log2_ng, a.g.n_g - 1);
+  __syncthreads();
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+  const float al = a.alpha[slot], be = a.beta[slot];
+  const float r = (float)(1 << a.g.log2_r);
+  float umax = 0.f;
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    long long j[3];
+    lattice_of(i, a.g.log2_np, j);
+    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][kEsW], dw[3][kEsW];
+    int l0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
+      int h = es_weights_d(U, a.es_tab, w[c], dw[c]) & nm;
+      l0[c] = h - o[c] + kEsR - 2;
+    }
+    float A[3] = {0.f, 0.f, 0.f}, dA[3][3] = {};
+    for (int xx = 0; xx < kEsW; ++xx)
+      for (int yy = 0; yy < kEsW; ++yy) {
+        const float wxy = w[0][xx] * w[1][yy], gxy = dw[0][xx] * w[1][yy], hxy = w[0][xx] * dw[1][yy];
+        const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+#pragma unroll
+        for (int zz = 0; zz < kEsW; ++zz) {
+          const float wt = wxy * w[2][zz], gx = gxy * w[2][zz], gy = hxy * w[2][zz], gz = wxy * dw[2][zz];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float f = fwin[c * W3 + b + zz];
+            A[c] += wt * f;
+            dA[c][0] += gx * f;
+            dA[c][1] += gy * f;
+            dA[c][2] += gz * f;
+          }
+        }
+      }
+    float u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float vb = a.vbar[ps + c * N + i];
+      u[c] = be * vb;
+      a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A[c]) / al;
+      a.vbar[ps + c * N + i] = al * vb;
+      a.u_sorted[ps + c * N + p] = u[c];
+      umax = fmaxf(umax, fabsf(u[c]));
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      a.xbar[ps + d * N + i] += r * (u[0] * dA[0][d] + u[1] * dA[1][d] + u[2] * dA[2][d]);
+  }
+  red[threadIdx.x] = umax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] > 0.f)
+    atomicMax(reinterpret_cast<unsigned int*>(a.umax) + slot, __float_as_uint(red[0]));
+}
+
+// spreading of component comp of u with the ES weights (the transpose of the
+// interpolation), int64 fixed point at the scale set from max |u|
+__global__ void __launch_bounds__(256) k_tile_es_dipole(TileArgs a) {
+  extern __shared__ unsigned long long ewin[];
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int W = a.T + 2 * kEsR, W3 = W * W * W;
+  for (int e = threadIdx.x; e < W3; e += 256) ewin[e] = 0ull;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  __syncthreads();
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+  const double S = a.scale[slot];
+  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const float uc = a.u_sorted[ps + a.comp * N + p];
+    if (uc == 0.f) continue;
+    const long long i = a.sorted[slot * N + p];
+    long long j[3];
+    lattice_of(i, a.g.log2_np, j);
+    float w[3][kEsW];
+    int l0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int wi[kEsW];
+      long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
+      int h = es_weights(U, a.es_tab, wi) & nm;
+      l0[c] = h - o[c] + kEsR - 2;
+#pragma unroll
+      for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
+    }
+    for (int x = 0; x < kEsW; ++x)
+      for (int y = 0; y < kEsW; ++y) {
+        const float wxy = w[0][x] * w[1][y] * uc;
+        if (wxy == 0.f) continue;
+        const int bxy = ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
+#pragma unroll
+        for (int z = 0; z < kEsW; ++z) {
+          long long v = llrint((double)(wxy * w[2][z]) * S);
+          if (v) atomicAdd(&ewin[bxy + z], (unsigned long long)v);
+        }
+      }
+  }
+  __syncthreads();
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(a.scratch) + ((long long)slot * a.n_tiles + t) * W3;
+  for (int e = threadIdx.x; e < W3; e += 256) out[e] = ewin[e];
+}
+
+// X_bar += coef r sum_j b_bar_j d/du phi(u - j) (the spreading differentiated
+// w.r.t. the positions), then the reverse drift X -= tau V, V_bar += tau X_bar
+__global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
+  extern __shared__ float bwin[];  // (T + 6)^3
+  const int slot = blockIdx.y, t = blockIdx.x;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int W = a.T + 2 * kEsR;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  load_window(bwin, a.mesh_in + slot * a.g.mesh_stride, o, a.T, kEsR, a.g.log2_ng, a.g.n_g - 1);
+  __syncthreads();
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+  const float cf = a.coef[slot] * (float)(1 << a.g.log2_r), tau = a.tau[slot];
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    long long j[3];
+    lattice_of(i, a.g.log2_np, j);
+    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][kEsW], dw[3][kEsW];
+    int l0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
+      int h = es_weights_d(U, a.es_tab, w[c], dw[c]) & nm;
+      l0[c] = h - o[c] + kEsR - 2;
+    }
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    for (int xx = 0; xx < kEsW; ++xx)
+      for (int yy = 0; yy < kEsW; ++yy) {
+        const float wxy = w[0][xx] * w[1][yy], gxy = dw[0][xx] * w[1][yy], hxy = w[0][xx] * dw[1][yy];
+        const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+#pragma unroll
+        for (int zz = 0; zz < kEsW; ++zz) {
+          const float f = bwin[b + zz];
+          gx += f * gxy * w[2][zz];
+          gy += f * hxy * w[2][zz];
+          gz += f * wxy * dw[2][zz];
+        }
+      }
+    float g[3] = {gx, gy, gz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float xb = a.xbar[ps + c * N + i] + cf * g[c];
+      float v = a.vel[ps + c * N + i];
+      a.disp[ps + c * N + i] = x[c] - tau * v;
+      a.xbar[ps + c * N + i] = xb;
+      a.vbar[ps + c * N + i] += tau * xb;
+    }
+  }
+}
+
 hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
   dim3 grid((unsigned)a.n_tiles, a.batch);
   const int W = a.T + 2 * kEsR;
@@ -682,10 +891,25 @@ hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
     hipFuncSetAttribute((const void*)k_tile_es_deposit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_tile_es_deposit<<<grid, 256, lds, s>>>(a);
-  } else {
+  } else if (kind == TK_ES_KICK) {
     size_t lds = (size_t)3 * W * W * W * sizeof(float);
     hipFuncSetAttribute((const void*)k_tile_es_kick, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_tile_es_kick<<<grid, 256, lds, s>>>(a);
+  } else if (kind == TK_ES_ADJ_KICK) {
+    size_t lds = (size_t)3 * W * W * W * sizeof(float);
+    hipFuncSetAttribute((const void*)k_tile_es_adj_kick, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_tile_es_adj_kick<<<grid, 256, lds, s>>>(a);
+  } else if (kind == TK_ES_DIPOLE) {
+    if (a.comp < 0 || a.comp > 2) return hipErrorInvalidValue;
+    size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
+    hipFuncSetAttribute((const void*)k_tile_es_dipole, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_tile_es_dipole<<<grid, 256, lds, s>>>(a);
+  } else if (kind == TK_ES_ADJ_DRIFT) {
+    size_t lds = (size_t)W * W * W * sizeof(float);
+    hipFuncSetAttribute((const void*)k_tile_es_adj_drift, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_tile_es_adj_drift<<<grid, 256, lds, s>>>(a);
+  } else {
+    return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

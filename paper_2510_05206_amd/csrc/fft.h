@@ -6,7 +6,8 @@ namespace pm {
 
 enum { SRC_I64 = 0, SRC_F32 = 1 };
 enum { DST_F32 = 0, DST_IC = 1 };
-enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4, MODE_NUFFT_C = 5 };
+enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4, MODE_NUFFT_C = 5,
+       MODE_NUFFT_ADJ = 6 };
 
 // z-row pass: real rows of n <-> half-spectrum rows of n/2+1
 struct RowLaunch {

@@ -305,7 +305,35 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
     buf[e] = v;
   }
   __syncthreads();
-  if constexpr (MODE == MODE_FWD || MODE == MODE_FUSED_H) lds_fft<L, C, true, 256>(buf, a.tw, a.tws, false);
+  if constexpr (MODE == MODE_FWD || MODE == MODE_FUSED_H || MODE == MODE_NUFFT_ADJ)
+    lds_fft<L, C, true, 256>(buf, a.tw, a.tws, false);
+  if constexpr (MODE == MODE_NUFFT_ADJ) {
+    // transposed NUFFT multiplier of component comp, conj(i h) = -i h, summed
+    // over the components into dst3; the last component also runs the
+    // inverse x transform of the sum
+    const float k0 = 6.283185307179586f / (float)a.n_p;
+    for (int e = threadIdx.x; e < L * C; e += 256) {
+      int t = e / C, c = e - t * C;
+      int iz = z0 + c;
+      if (iz >= a.nh) continue;
+      float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
+      int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
+      float th2 = 0.f;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
+      float h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
+      float2 v = buf[e];
+      float2 r = make_float2(h * v.y, -h * v.x);  // -i h v
+      if (a.comp > 0) {
+        float2 acc = a.dst3[sbase + t * stride_t + c];
+        r.x += acc.x;
+        r.y += acc.y;
+      }
+      buf[e] = r;
+    }
+    __syncthreads();
+    if (a.comp == 2) lds_fft<L, C, true, 256>(buf, a.tw, a.tws, true);
+  }
   if constexpr (MODE == MODE_FUSED_H) {
     for (int e = threadIdx.x; e < L * C; e += 256) {
       int t = e / C, c = e - t * C;
@@ -319,8 +347,8 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
     }
     __syncthreads();
   }
-  if constexpr (MODE != MODE_FWD) lds_fft<L, C, true, 256>(buf, a.tw, a.tws, true);
-  float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C) ? a.dst3 : a.data;
+  if constexpr (MODE != MODE_FWD && MODE != MODE_NUFFT_ADJ) lds_fft<L, C, true, 256>(buf, a.tw, a.tws, true);
+  float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ) ? a.dst3 : a.data;
   for (int e = threadIdx.x; e < L * C; e += 256) {
     int t = e / C, c = e - t * C;
     if (z0 + c < a.nh) out[sbase + t * stride_t + c] = buf[e];
@@ -380,6 +408,7 @@ static hipError_t launch_cols_c(const ColArgs& a, int mode, int batch, hipStream
     case MODE_IC_C: k_cols<L, C, MODE_IC_C><<<grid, 256, 0, s>>>(a); break;
     case MODE_COMBINE_IC: k_cols<L, C, MODE_COMBINE_IC><<<grid, 256, 0, s>>>(a); break;
     case MODE_NUFFT_C: k_cols<L, C, MODE_NUFFT_C><<<grid, 256, 0, s>>>(a); break;
+    case MODE_NUFFT_ADJ: k_cols<L, C, MODE_NUFFT_ADJ><<<grid, 256, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

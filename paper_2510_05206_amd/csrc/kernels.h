@@ -22,7 +22,7 @@ struct BinArgs {
 };
 
 enum { TK_DEPOSIT = 0, TK_KICK = 1, TK_ADJ_KICK = 2, TK_ADJ_DRIFT = 3, TK_DIPOLE = 4, TK_ES_DEPOSIT = 5,
-       TK_ES_KICK = 6 };
+       TK_ES_KICK = 6, TK_ES_ADJ_KICK = 7, TK_ES_DIPOLE = 8, TK_ES_ADJ_DRIFT = 9 };
 
 struct TileArgs {
   Geom g;
@@ -44,6 +44,7 @@ struct TileArgs {
   const double* scale;     // [B] fixed-point scale of the cotangent scatter
   const int32_t* es_tab;   // integer exponential-of-semicircle table (NUFFT)
   long long comp_stride;   // floats between the 3 force meshes (NUFFT kick)
+  int comp;                // component scattered by the NUFFT adjoint's spreading
   float alpha[kMaxBatch];
   float beta[kMaxBatch];
   float tau[kMaxBatch];

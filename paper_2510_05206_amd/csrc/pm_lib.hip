@@ -117,6 +117,9 @@ void prof_end(pm_ctx* c) {
   hipEventRecord(c->pending.back().b, c->stream);
 }
 
+// two launches timed as one stage (the first error wins)
+hipError_t both(hipError_t a, hipError_t b) { return a != hipSuccess ? a : b; }
+
 // launch with optional event timing of its kernel class
 #define KLAUNCH(ctx, cls, expr)   \
   do {                            \
@@ -433,9 +436,8 @@ pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* ta
   pm_status st = bin(c, disp, vel_pre, tau, mak, active);
   if (st) return st;
   TileArgs t = tile_args(c, disp, active);
-  KLAUNCH(c, PM_K_DEPOSIT, launch_tile(t, TK_DEPOSIT, mak, 0, c->stream));
   AssembleArgs a = assemble_args(c, 1, mesh, active);
-  KLAUNCH(c, PM_K_ASSEMBLE, launch_assemble(a, false, c->stream));
+  KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile(t, TK_DEPOSIT, mak, 0, c->stream), launch_assemble(a, false, c->stream)));
   return PM_OK;
 }
 
@@ -464,9 +466,8 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   if (st) return st;
   TileArgs t = tile_args(c, disp, active);
   t.es_tab = c->d_es_tab;
-  KLAUNCH(c, PM_K_DEPOSIT, launch_tile_es(t, TK_ES_DEPOSIT, c->stream));
   AssembleArgs as = assemble_args(c, 3, c->mesh, active);
-  KLAUNCH(c, PM_K_ASSEMBLE, launch_assemble(as, false, c->stream));
+  KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile_es(t, TK_ES_DEPOSIT, c->stream), launch_assemble(as, false, c->stream)));
   const int n = c->cfg.n_g, np = c->cfg.n_p;
   const double N = (double)c->g.N;
   const double ph0 = es_phihat(0.0, c->cfg.es_width, c->cfg.es_beta);
@@ -868,11 +869,91 @@ pm_status pm_run(pm_ctx* c) {
   return PM_OK;
 }
 
+// one reverse step of the NUFFT force after its force meshes are rebuilt at
+// X^{n+1/2}: reverse kick with the direct position gradient; per component
+// the ES spreading of u (the transposed interpolation), R2C and the
+// transposed multiplier -i h_c summed over components; C2R of the sum; its
+// gradient gather (the transposed spreading) fused with the reverse drift
+pm_status nufft_adjoint_step(pm_ctx* c, int n, const double* s, unsigned long long act) {
+  const int B = c->cfg.batch, ng = c->cfg.n_g;
+  const long long N = c->g.N, M = c->g.M;
+  TileArgs k = tile_args(c, c->disp, act);
+  k.mesh_in = c->force3;
+  k.comp_stride = M;
+  k.es_tab = c->d_es_tab;
+  for (int b = 0; b < B; ++b) {
+    if (!((act >> b) & 1)) continue;
+    const StepCoef& sc = c->slot_table[b][n];
+    k.alpha[b] = (float)sc.alpha;
+    k.beta[b] = (float)sc.beta;
+  }
+  KLAUNCH(c, PM_K_ADJ_KICK, launch_tile_es(k, TK_ES_ADJ_KICK, c->stream));
+  // every node sum of u_c phi is bounded by N max|u| (phi <= 1)
+  KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale, (double)N, B,
+                                            c->stream));
+  float* d = reinterpret_cast<float*>(c->mesh);
+  ColArgs x{};
+  x.data = c->spec;
+  x.dst3 = c->spec2;
+  x.slot_stride = c->g.spec_stride;
+  x.n = ng;
+  x.nh = ng / 2 + 1;
+  x.rs = spec_rs(ng);
+  x.tw = c->d_tw;
+  x.tws = c->Lmax / ng;
+  x.active = act;
+  x.esdec = c->d_esdec;
+  x.n_p = c->cfg.n_p;
+  x.axis = 0;
+  for (int b = 0; b < B; ++b) x.coef[b] = (float)(s[b] / (double)N);
+  for (int comp = 0; comp < 3; ++comp) {
+    k.comp = comp;
+    AssembleArgs as = assemble_args(c, 3, d, act);
+    KLAUNCH(c, PM_K_DIPOLE, both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
+    pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act);
+    if (st) return st;
+    x.comp = comp;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(x, MODE_NUFFT_ADJ, B, c->stream));
+  }
+  ColArgs y = x;
+  y.data = c->spec2;
+  y.axis = 1;
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
+  RowLaunch rl{};
+  rl.n = ng;
+  rl.rs = spec_rs(ng);
+  rl.n_rows = (long long)ng * ng;
+  rl.batch = B;
+  rl.inverse = true;
+  rl.dst_mode = DST_F32;
+  rl.src = c->spec2;
+  rl.src_stride = c->g.spec_stride;
+  rl.dst = c->phi;
+  rl.dst_stride = c->g.mesh_stride;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (ng / 2);
+  rl.tws_full = c->Lmax / ng;
+  rl.scale = 1.0;
+  rl.stream = c->stream;
+  rl.active = act;
+  KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
+  TileArgs dr = tile_args(c, c->disp, act);
+  dr.mesh_in = c->phi;
+  dr.es_tab = c->d_es_tab;
+  for (int b = 0; b < B; ++b) {
+    dr.coef[b] = 1.f;
+    if (!((act >> b) & 1)) continue;
+    const auto& T = c->slot_table[b];
+    dr.tau[b] = (float)(T[n].tau1 + (n > 0 ? T[n - 1].tau2 : 0.0));
+  }
+  KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile_es(dr, TK_ES_ADJ_DRIFT, c->stream));
+  return PM_OK;
+}
+
 pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8) {
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!c->ran) return fail(c, PM_ESTATE, "pm_adjoint before pm_run");
-  if (c->cfg.force != PM_FORCE_PM) return fail(c, PM_EUNSUPPORTED, "adjoint of the NUFFT force is not built");
   if (!dL_ddelta || !dL_dw || !dL_dsigma8) return PM_EINVAL;
   const int B = c->cfg.batch, np = c->cfg.n_p;
   const long long N = c->g.N, M = c->g.M;
@@ -906,6 +987,11 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
     pm_status st = potential(c, c->disp, nullptr, nullptr, s.data(), act);
     if (st) return st;
     KLAUNCH(c, PM_K_FILL, launch_fill(c->umax, (long long)sizeof(float) * kMaxBatch, c->stream));
+    if (c->cfg.force == PM_FORCE_NUFFT) {
+      st = nufft_adjoint_step(c, n, s.data(), act);
+      if (st) return st;
+      continue;
+    }
     TileArgs k = tile_args(c, c->disp, act);
     k.mesh_in = c->phi;
     for (int b = 0; b < B; ++b) {
@@ -918,10 +1004,9 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
     // mesh cotangent of the force: transposed FD gather in fixed point
     KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
                                               3.0 * fd_l1 * (double)N, B, c->stream));
-    KLAUNCH(c, PM_K_DIPOLE, launch_tile(k, TK_DIPOLE, mak, ord, c->stream));
     float* d = reinterpret_cast<float*>(c->mesh);
     AssembleArgs as = assemble_args(c, dipole_halo(ord), d, act);
-    KLAUNCH(c, PM_K_ASSEMBLE, launch_assemble(as, true, c->stream));
+    KLAUNCH(c, PM_K_DIPOLE, both(launch_tile(k, TK_DIPOLE, mak, ord, c->stream), launch_assemble(as, true, c->stream)));
     // transposed multiplier (H is real and even)
     st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
     if (st) return st;
@@ -1061,9 +1146,8 @@ pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_ou
   if (st) return st;
   TileArgs t = tile_args(c, x, act);
   t.es_tab = c->d_es_tab;
-  KLAUNCH(c, PM_K_DEPOSIT, launch_tile_es(t, TK_ES_DEPOSIT, c->stream));
   AssembleArgs as = assemble_args(c, 3, mesh_out, act);
-  KLAUNCH(c, PM_K_ASSEMBLE, launch_assemble(as, false, c->stream));
+  KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile_es(t, TK_ES_DEPOSIT, c->stream), launch_assemble(as, false, c->stream)));
   return PM_OK;
 }
 

@@ -91,3 +91,91 @@ def test_nufft_run_matches_oracle(wl):
     perr = np.abs(p[sel] / pr[sel] - 1).max()
     say(f"{wl}: density rel L2 {err:.3e}, P(k<kNyq/2) max rel {perr:.3e} (oracle {time.time() - t0:.0f} s)")
     assert err < 1e-4 and perr < 1e-5
+
+
+def _adj_sim(d):
+    from paper_2510_05206_amd import PMSim
+    return PMSim(synth.gpu_config(d), with_adjoint=True)
+
+
+def test_nufft_gradient_matches_oracle_store_all():
+    """Reverse-in-time adjoint of the NUFFT force run against the oracle's
+    store-all reverse mode (L2 loss on the final CIC density)."""
+    d = synth.C3_SMALL
+    say("nufft adjoint vs oracle", d["n_p"])
+    prob = synth.oracle_problem(d)
+    psi_t, _ = onbody.run(prob, w=ophilox.white_noise(synth.SEED_TARGET, d["n_p"]))
+    dt = oadj.final_density(prob, psi_t)
+    dobs = dt + 0.1 * dt.std() * np.random.default_rng(synth.SEED_NOISE).normal(size=dt.size)
+    sim = _adj_sim(d)
+    sim.init_ics([synth.SEED_W])
+    sim.run()
+    delta = sim.density()
+    g = 2.0 * (delta.double() - torch.from_numpy(dobs).to(delta.device)).float()
+    dw, ds = sim.adjoint(g)
+    w = ophilox.white_noise(synth.SEED_W, d["n_p"]).astype(np.float64)
+    gw, gs, _ = oadj.gradient(prob, w, lambda dd: 2.0 * (dd - dobs))
+    gw = gw.reshape(-1)
+    a = dw.cpu().numpy()[0].astype(np.float64)
+    cos = a @ gw / np.linalg.norm(a) / np.linalg.norm(gw)
+    rel = np.linalg.norm(a - gw) / np.linalg.norm(gw)
+    srel = abs(float(ds[0]) / gs - 1)
+    say(f"nufft: cosine {cos:.6f} rel L2 {rel:.3e} dsigma8 {float(ds[0]):.6e} vs {gs:.6e}")
+    assert cos > 0.999 and rel < 1e-2 and srel < 1e-2
+
+
+def test_nufft_adjoint_returns_to_initial_state():
+    d = synth.C3_SMALL
+    sim = _adj_sim(d)
+    sim.init_ics([synth.SEED_W])
+    x0, v0 = (t.clone() for t in sim.get_state())
+    sim.run()
+    sim.adjoint(torch.zeros(1, d["n_g"] ** 3, device="cuda"))
+    x1, v1 = sim.get_state()
+    ex = float((x1 - x0).norm() / x0.norm())
+    ev = float((v1 - v0).norm() / v0.norm())
+    say(f"nufft reverse integration: X rel {ex:.2e}, V rel {ev:.2e}")
+    assert ex < 1e-3 and ev < 1e-3
+
+
+def test_nufft_gradient_matches_finite_differences():
+    """64^3 particles on the 128^3 fine grid (the C3 resolution, L = 125),
+    central differences of the GPU forward along random unit directions."""
+    d = dict(synth.C3, n_p=64, n_g=128, box=125.0)
+    say("nufft adjoint vs FD at", d["n_p"])
+    sim = _adj_sim(d)
+    w = sim.init_ics([synth.SEED_W], return_w=True)
+    tgt = make_sim(d)
+    tgt.init_ics([synth.SEED_TARGET])
+    tgt.run()
+    dt = tgt.density()
+    gen = torch.Generator(device="cpu").manual_seed(synth.SEED_NOISE)
+    dobs = dt + 0.1 * dt.std() * torch.randn(dt.shape, generator=gen).to(dt.device)
+    del tgt
+
+    def loss(wv):
+        sim.init_ics(w=wv)
+        sim.run()
+        return float(((sim.density().double() - dobs.double()) ** 2).sum())
+
+    sim.init_ics(w=w)
+    sim.run()
+    dw, _ = sim.adjoint(2.0 * (sim.density() - dobs))
+    gen = torch.Generator(device="cpu").manual_seed(synth.SEED_DIRS)
+    preds, fdv, spread = [], [], []
+    for k in range(8):
+        v = torch.randn(w.shape, generator=gen).to(w.device)
+        v /= v.norm()
+        pred = float((dw.double() * v.double()).sum())
+        fds = [(loss(w + eps * v) - loss(w - eps * v)) / (2 * eps) for eps in (0.05, 0.1, 0.2)]
+        fd = float(np.median(fds))
+        preds.append(pred)
+        fdv.append(fd)
+        spread.append(float(np.max(np.abs(np.array(fds) - fd))))
+        say(f"dir {k}: adjoint {pred:.6e} fd {fd:.6e} ({fds}) rel {abs(pred - fd) / abs(fd):.2e}")
+    preds, fdv, spread = map(np.array, (preds, fdv, spread))
+    rel = np.abs(preds - fdv) / np.abs(fdv)
+    ok = np.abs(preds - fdv) <= np.maximum(0.02 * np.abs(fdv), 2 * spread)
+    cos = preds @ fdv / np.linalg.norm(preds) / np.linalg.norm(fdv)
+    say(f"median rel {np.median(rel):.3e}, agree {ok.sum()}/8, cosine over directions {cos:.6f}")
+    assert np.median(rel) < 2e-2 and ok.sum() >= 7 and cos > 0.999
