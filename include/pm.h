@@ -180,8 +180,15 @@ pm_status pm_init_ics(pm_ctx* ctx, const uint64_t* seeds, const float* w_in, flo
  * entry leaves that slot idle. */
 pm_status pm_step(pm_ctx* ctx, const int32_t* step_index);
 
-/* All n_steps steps for every slot (drifts of consecutive steps merged). */
+/* All n_steps steps for every slot (drifts of consecutive steps merged).
+ * Unless profiling is on or graphs are disabled (pm_use_graphs), the whole
+ * launch sequence is captured once into a HIP graph and replayed on later
+ * calls; the graph is rebuilt after pm_bind, pm_set_slot_params or a change
+ * of pm_set_active.  Results are bit-identical to the eager launches. */
 pm_status pm_run(pm_ctx* ctx);
+
+/* Enable (default) or disable the HIP-graph replay of pm_run. */
+pm_status pm_use_graphs(pm_ctx* ctx, int32_t enable);
 
 /* Adjoint of the whole run (Sec. "Adjoint method", tab. adjoint_dkd): from
  * the final state, integrate primal and cotangents backwards in time with

@@ -47,6 +47,7 @@ EXPORTS = {
     "pm_describe": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pm_last_error": (C.c_char_p, [C.c_void_p]),
     "pm_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pm_use_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "pm_set_active": (C.c_int, [C.c_void_p, C.c_uint64]),
     "pm_kernel_times": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_set_slot_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

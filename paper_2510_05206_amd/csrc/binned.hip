@@ -507,13 +507,9 @@ hipError_t launch_tile(const TileArgs& a, int kind, int mak, int ord, hipStream_
     case TK_DIPOLE: {
       int R = 1 + ord / 2, W = a.T + 2 * R;
       size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
-      // ORD 6 needs 110 KB of LDS: above the default dynamic limit
-#define PM_DIPOLE(P, O)                                                                       \
-  do {                                                                                        \
-    hipFuncSetAttribute((const void*)k_tile_dipole<P, O>,                                     \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-    k_tile_dipole<P, O><<<grid, 256, lds, s>>>(a);                                            \
-  } while (0)
+      // ORD 6 needs 110 KB of LDS: above the default dynamic limit (raised
+      // once by configure_tile_kernels)
+#define PM_DIPOLE(P, O) k_tile_dipole<P, O><<<grid, 256, lds, s>>>(a)
       if (mak == 2) {
         if (ord == 2) PM_DIPOLE(2, 2); else if (ord == 4) PM_DIPOLE(2, 4); else PM_DIPOLE(2, 6);
       } else {
@@ -884,29 +880,51 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
   }
 }
 
+// raise the dynamic-LDS limit of every kernel that needs more than the
+// default, to its largest window (16^3 tiles); called once per bind, outside
+// any stream capture
+hipError_t configure_tile_kernels() {
+  constexpr int We = kTileMax + 2 * kEsR;
+  const int es64 = We * We * We * 8, es32x3 = 3 * We * We * We * 4, es32 = We * We * We * 4;
+  auto dip = [](int o) { int W = kTileMax + 2 * (1 + o / 2); return W * W * W * 8; };
+  const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f, int bytes) {
+    hipError_t r = hipFuncSetAttribute(f, A, bytes);
+    if (e == hipSuccess) e = r;
+  };
+  set((const void*)k_tile_dipole<2, 2>, dip(2));
+  set((const void*)k_tile_dipole<2, 4>, dip(4));
+  set((const void*)k_tile_dipole<2, 6>, dip(6));
+  set((const void*)k_tile_dipole<3, 2>, dip(2));
+  set((const void*)k_tile_dipole<3, 4>, dip(4));
+  set((const void*)k_tile_dipole<3, 6>, dip(6));
+  set((const void*)k_tile_es_deposit, es64);
+  set((const void*)k_tile_es_kick, es32x3);
+  set((const void*)k_tile_es_adj_kick, es32x3);
+  set((const void*)k_tile_es_dipole, es64);
+  set((const void*)k_tile_es_adj_drift, es32);
+  return e;
+}
+
 hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
   dim3 grid((unsigned)a.n_tiles, a.batch);
   const int W = a.T + 2 * kEsR;
   if (kind == TK_ES_DEPOSIT) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
-    hipFuncSetAttribute((const void*)k_tile_es_deposit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_tile_es_deposit<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_KICK) {
     size_t lds = (size_t)3 * W * W * W * sizeof(float);
-    hipFuncSetAttribute((const void*)k_tile_es_kick, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_tile_es_kick<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_ADJ_KICK) {
     size_t lds = (size_t)3 * W * W * W * sizeof(float);
-    hipFuncSetAttribute((const void*)k_tile_es_adj_kick, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_tile_es_adj_kick<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_DIPOLE) {
     if (a.comp < 0 || a.comp > 2) return hipErrorInvalidValue;
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
-    hipFuncSetAttribute((const void*)k_tile_es_dipole, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_tile_es_dipole<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_ADJ_DRIFT) {
     size_t lds = (size_t)W * W * W * sizeof(float);
-    hipFuncSetAttribute((const void*)k_tile_es_adj_drift, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_tile_es_adj_drift<<<grid, 256, lds, s>>>(a);
   } else {
     return hipErrorInvalidValue;

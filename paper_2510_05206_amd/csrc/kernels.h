@@ -65,6 +65,7 @@ hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s);
 hipError_t launch_tile(const TileArgs& a, int kind, int mak, int fd_order, hipStream_t s);
 hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s);
 hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s);
+hipError_t configure_tile_kernels();
 hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, double* inv_scale,
                                double bound_per_u, int batch, hipStream_t s);
 

@@ -68,9 +68,17 @@ struct pm_ctx {
   std::vector<hipEvent_t> pool;
   double prof_ms[PM_K_COUNT] = {};
   long long prof_n[PM_K_COUNT] = {};
+  // pm_run as one captured HIP graph, rebuilt when anything it bakes in
+  // (buffers, per-slot schedules, slot mask) changes: gen counts such changes
+  bool use_graph = true;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t run_exec = nullptr;
+  unsigned long long gen = 1, run_gen = 0;
   ~pm_ctx() {
     for (auto& p : pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : pool) hipEventDestroy(e);
+    if (run_exec) hipGraphExecDestroy(run_exec);
+    if (cap) hipStreamDestroy(cap);
   }
 };
 
@@ -610,6 +618,9 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   char* ws = (char*)workspace;
   c->stream = (hipStream_t)stream;
   c->with_adj = with_adjoint != 0;
+  HIPCHK(c, configure_tile_kernels());
+  if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  ++c->gen;
   const int B = c->cfg.batch;
   c->d_tw = (float2*)(ws + L.off_tw);
   c->d_lap = (float*)(ws + L.off_lap);
@@ -689,7 +700,14 @@ pm_status pm_describe(const pm_ctx* c, double* out) {
 pm_status pm_set_active(pm_ctx* c, uint64_t mask) {
   if (!c) return PM_EINVAL;
   if (!mask || (mask & ~all_mask(c->cfg.batch))) return fail(c, PM_EINVAL, "slot mask empty or beyond the batch");
+  if (mask != c->user_mask) ++c->gen;
   c->user_mask = mask;
+  return PM_OK;
+}
+
+pm_status pm_use_graphs(pm_ctx* c, int32_t enable) {
+  if (!c) return PM_EINVAL;
+  c->use_graph = enable != 0;
   return PM_OK;
 }
 
@@ -735,6 +753,7 @@ pm_status pm_set_slot_params(pm_ctx* c, const int32_t* n_steps, const double* si
       return fail(c, PM_EINVAL, "slot n_steps out of range");
     if (sigma8 && !(sigma8[b] > 0)) return fail(c, PM_EINVAL, "sigma8 must be positive");
   }
+  ++c->gen;
   for (int b = 0; b < c->cfg.batch; ++b) {
     if (n_steps && n_steps[b] != c->slot_steps[b]) {
       c->slot_steps[b] = n_steps[b];
@@ -843,9 +862,50 @@ pm_status pm_step(pm_ctx* c, const int32_t* step_index) {
   return PM_OK;
 }
 
+static pm_status run_steps(pm_ctx* c);
+
 pm_status pm_run(pm_ctx* c) {
   if (pm_status st = check_bound(c)) return st;
   if (!c->ics_done) return fail(c, PM_ESTATE, "pm_run before pm_init_ics");
+  if (!c->use_graph || c->prof) {
+    pm_status st = run_steps(c);
+    if (st) return st;
+  } else {
+    if (!c->run_exec || c->run_gen != c->gen) {
+      if (c->run_exec) {
+        HIPCHK(c, hipGraphExecDestroy(c->run_exec));
+        c->run_exec = nullptr;
+      }
+      // capture on the context's own stream (the bound one may be the null
+      // stream); nothing runs during capture
+      hipStream_t user = c->stream;
+      c->stream = c->cap;
+      HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+      pm_status st = run_steps(c);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->cap, &g);
+      c->stream = user;
+      if (st) {
+        if (g) hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(c, PM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&c->run_exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        c->run_exec = nullptr;
+        return fail(c, PM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+      }
+      c->run_gen = c->gen;
+    }
+    HIPCHK(c, hipGraphLaunch(c->run_exec, c->stream));
+  }
+  c->ran = true;
+  return PM_OK;
+}
+
+// every step of the run: slot b stops after its own step count
+static pm_status run_steps(pm_ctx* c) {
   const int B = c->cfg.batch;
   int nmax = 0;
   for (int b = 0; b < B; ++b) nmax = std::max(nmax, c->slot_steps[b]);
@@ -865,7 +925,6 @@ pm_status pm_run(pm_ctx* c) {
     pm_status st = step_common(c, tp.data(), n == 0, s.data(), al.data(), be.data(), tq.data(), act);
     if (st) return st;
   }
-  c->ran = true;
   return PM_OK;
 }
 

@@ -189,6 +189,10 @@ class PMSim:
     def profile(self, on=True):
         self._call("pm_profile", int(bool(on)))
 
+    def use_graphs(self, on=True):
+        """Replay run() from a captured HIP graph (default) or launch eagerly."""
+        self._call("pm_use_graphs", int(bool(on)))
+
     def kernel_times(self):
         """{class: (total ms, launches)} since the previous call (synchronises)."""
         K = len(_lib.KERNEL_CLASSES)

@@ -255,3 +255,33 @@ def test_step_by_step_equals_run():
     # pm_run merges consecutive drifts: equal up to FP32 rounding
     assert rel_l2(xb.cpu().numpy(), xa.cpu().numpy()) < 1e-5
     assert rel_l2(vb.cpu().numpy(), va.cpu().numpy()) < 1e-5
+
+
+def test_graph_replay_matches_eager_launches():
+    """pm_run replayed from its captured HIP graph gives the bits of the eager
+    launch sequence, on every replay, with eager work in between, and after a
+    slot-parameter change forces a new capture."""
+    from paper_2510_05206_amd import PMSim
+    d = dict(synth.C2_SMALL, batch=2)
+    sim = PMSim(synth.gpu_config(d), with_adjoint=False)
+
+    def run_once(graph, steps=None):
+        sim.use_graphs(graph)
+        if steps is not None:
+            sim.set_slot_params(n_steps=steps)
+        sim.init_ics([11, 12])
+        sim.run()
+        x, v = sim.get_state()
+        return x.clone(), v.clone()
+
+    ref = run_once(False)
+    for k in range(3):
+        got = run_once(True)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), k
+        sim.density()          # eager work between replays
+        torch.cuda.synchronize()
+    ref2 = run_once(False, steps=[4, 7])
+    for k in range(2):
+        got = run_once(True)
+        assert torch.equal(got[0], ref2[0]) and torch.equal(got[1], ref2[1]), k
