@@ -17,6 +17,7 @@
 // into the x pass: forward x FFT, multiply, inverse x FFT, one HBM round trip
 // (Sec. "Force evaluation"; the Poisson solve in Fourier space).
 #include "fft.h"
+#include "fft_reg.h"
 
 namespace pm {
 
@@ -355,6 +356,131 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
   }
 }
 
+// ---------------------------------------- column passes, register FFT
+
+// The same passes as k_cols, with the column transform held in registers
+// (four-step split, one LDS exchange per transform; fft_reg.h).  Per-mode
+// arithmetic is applied on load (input layout, t = n1 + P r) or after the
+// forward transform (output layout).
+template <int L, int C, int MODE>
+__global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
+  using S = freg::Shape<L, C>;
+  __shared__ float2 lds[S::LDS];
+  const int slot = blockIdx.z;
+  if (!((a.active >> slot) & 1ull)) return;
+  const int outer = blockIdx.y;  // x for the y pass, y for the x pass
+  const int c = threadIdx.x % C, n1 = threadIdx.x / C;
+  const int iz = blockIdx.x * C + c;
+  const bool valid = iz < a.nh;
+  const long long stride_t = a.axis == 1 ? (long long)a.rs : (long long)a.n * a.rs;
+  const long long base0 = a.axis == 1 ? (long long)outer * a.n * a.rs : (long long)outer * a.rs;
+  const long long col = slot * a.slot_stride + base0 + iz;
+  float2 v[S::E];
+#pragma unroll
+  for (int r = 0; r < S::E; ++r) {
+    const int t = S::t_in(n1, r);
+    float2 x = make_float2(0.f, 0.f);
+    if (valid) {
+      if constexpr (MODE == MODE_COMBINE_IC) {
+        // x pass: t = ix, outer = iy: sum_c conj(h_c) S_c, h_c = i h
+        int mx = signed_mode(t, a.n), my = signed_mode(outer, a.n);
+        float amp = a.amp[mx * mx + my * my + iz * iz] * a.fac[slot];
+        int ms[3] = {mx, my, iz};
+        const float2* s3 = a.src3 + col + t * stride_t;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if (ms[q] == -a.n / 2 || ms[q] == a.n / 2) continue;
+          float2 sv = s3[q * a.comp_stride];
+          float h = amp * ms[q];
+          x.x += h * sv.y;
+          x.y -= h * sv.x;
+        }
+      } else {
+        x = a.data[col + t * stride_t];
+      }
+      if constexpr (MODE == MODE_NUFFT_C) {
+        float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
+        int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
+        const float k0 = 6.283185307179586f / (float)a.n_p;
+        float th2 = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
+        float h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
+        x = make_float2(-h * x.y, h * x.x);  // i h x
+      }
+      if constexpr (MODE == MODE_IC_C) {
+        int mx = signed_mode(t, a.n), my = signed_mode(outer, a.n);
+        int ms[3] = {mx, my, iz};
+        int mc = ms[a.comp];
+        float h = (mc == -a.n / 2 || mc == a.n / 2) ? 0.f : a.amp[mx * mx + my * my + iz * iz] * a.fac[slot] * mc;
+        x = make_float2(-h * x.y, h * x.x);  // i h x
+      }
+    }
+    v[r] = x;
+  }
+  constexpr bool kFwdFirst = MODE == MODE_FWD || MODE == MODE_FUSED_H || MODE == MODE_NUFFT_ADJ;
+  bool inverse_next = !kFwdFirst;  // input layout holds data for an inverse transform
+  if constexpr (kFwdFirst) {
+    freg::pass_a<L, C, false>(v, n1, a.tw, a.tws);
+    freg::store_y<L, C>(v, lds, n1, c);
+    __syncthreads();
+    freg::pass_b<L, C, false>(v, lds, n1, c);
+    if constexpr (MODE == MODE_FUSED_H) {
+#pragma unroll
+      for (int r = 0; r < S::E; ++r) {
+        const int t = S::t_out(n1, r);
+        float l = a.lap[t] + a.lap[outer] + (valid ? a.lap[iz] : 0.f);
+        float w = a.win2[t] * a.win2[outer] * (valid ? a.win2[iz] : 1.f);
+        float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : a.coef[slot] / (l * w);
+        v[r].x *= h;
+        v[r].y *= h;
+      }
+      inverse_next = true;
+    }
+    if constexpr (MODE == MODE_NUFFT_ADJ) {
+      const float k0 = 6.283185307179586f / (float)a.n_p;
+#pragma unroll
+      for (int r = 0; r < S::E; ++r) {
+        const int t = S::t_out(n1, r);
+        float h = 0.f;
+        if (valid) {
+          float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
+          int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
+          float th2 = 0.f;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
+          h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
+        }
+        float2 y = make_float2(h * v[r].y, -h * v[r].x);  // -i h v
+        if (valid && a.comp > 0) {
+          float2 acc = a.dst3[col + t * stride_t];
+          y.x += acc.x;
+          y.y += acc.y;
+        }
+        v[r] = y;
+      }
+      inverse_next = a.comp == 2;
+    }
+    if (inverse_next) {  // back to the input layout for the inverse transform
+      __syncthreads();
+      freg::store_nat_out<L, C>(v, lds, n1, c);
+      __syncthreads();
+      freg::load_nat_in<L, C>(v, lds, n1, c);
+    }
+  }
+  if (inverse_next) {
+    freg::pass_a<L, C, true>(v, n1, a.tw, a.tws);
+    __syncthreads();
+    freg::store_y<L, C>(v, lds, n1, c);
+    __syncthreads();
+    freg::pass_b<L, C, true>(v, lds, n1, c);
+  }
+  if (!valid) return;
+  float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ) ? a.dst3 : a.data;
+#pragma unroll
+  for (int r = 0; r < S::E; ++r) out[col + S::t_out(n1, r) * stride_t] = v[r];
+}
+
 // ------------------------------------------------------------ dispatch
 
 template <int L>
@@ -414,12 +540,32 @@ static hipError_t launch_cols_c(const ColArgs& a, int mode, int batch, hipStream
   return hipGetLastError();
 }
 
+template <int L, int C>
+static hipError_t launch_cols_r(const ColArgs& a, int mode, int batch, hipStream_t s) {
+  dim3 grid((unsigned)((a.nh + C - 1) / C), (unsigned)a.n, (unsigned)batch);
+  switch (mode) {
+    case MODE_FWD: k_cols_reg<L, C, MODE_FWD><<<grid, 256, 0, s>>>(a); break;
+    case MODE_INV: k_cols_reg<L, C, MODE_INV><<<grid, 256, 0, s>>>(a); break;
+    case MODE_FUSED_H: k_cols_reg<L, C, MODE_FUSED_H><<<grid, 256, 0, s>>>(a); break;
+    case MODE_IC_C: k_cols_reg<L, C, MODE_IC_C><<<grid, 256, 0, s>>>(a); break;
+    case MODE_COMBINE_IC: k_cols_reg<L, C, MODE_COMBINE_IC><<<grid, 256, 0, s>>>(a); break;
+    case MODE_NUFFT_C: k_cols_reg<L, C, MODE_NUFFT_C><<<grid, 256, 0, s>>>(a); break;
+    case MODE_NUFFT_ADJ: k_cols_reg<L, C, MODE_NUFFT_ADJ><<<grid, 256, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int L>
 static hipError_t launch_cols(const ColArgs& a, int mode, int batch, hipStream_t s) {
-  // 16 columns = one 128-byte line per row (rows are padded to 16 complex);
-  // 64 KB of LDS at n = 512, 8 columns at n = 1024
-  constexpr int C = L >= 1024 ? 8 : 16;
-  return launch_cols_c<L, C>(a, mode, batch, s);
+  // register FFT from L = 16: P = 256 / C threads per column must not exceed
+  // the E = L / P elements each holds
+  if constexpr (L >= 16) {
+    constexpr int C = L >= 1024 ? 8 : (L >= 256 ? 16 : (L >= 64 ? 32 : 64));
+    return launch_cols_r<L, C>(a, mode, batch, s);
+  } else {
+    return launch_cols_c<L, 16>(a, mode, batch, s);
+  }
 }
 
 hipError_t fft_cols(const ColArgs& a, int mode, int batch, hipStream_t s) {

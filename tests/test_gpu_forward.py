@@ -61,7 +61,7 @@ def test_white_noise_matches_oracle_philox(n_p, seed):
 
 # ------------------------------------------------------------------- FFT
 
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512])
 def test_fft_matches_numpy(n):
     say("fft", n)
     sim = make_sim(synth.C1, n_p=n // 2, n_g=n)
@@ -71,6 +71,36 @@ def test_fft_matches_numpy(n):
     assert rel_l2(X, ref) < 3e-7 * max(1.0, math.log2(n) / 3)
     back = sim.fft(torch.from_numpy(X), inverse=True).cpu().numpy()[0]
     assert rel_l2(back / n ** 3, x) < 3e-7 * max(1.0, math.log2(n) / 3)
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_fft_plane_waves_exact_spectrum(n):
+    """cos(2 pi m.j/n) + 0.5 sin(2 pi m'.j/n) has exactly two nonzero modes in
+    the half spectrum (n^3/2 and -i n^3/4); checked on the device at the
+    largest mesh sizes, with the inverse round trip on random data."""
+    say("fft plane waves", n)
+    sim = make_sim(synth.C1, n_p=n // 4, n_g=n)
+    m, mp = (3, n // 2 - 5, 7), (n - 9, 1, n // 2 - 1)
+    j = torch.arange(n, device="cuda", dtype=torch.float64)
+    ph = lambda k: 2 * math.pi * (k[0] * j[:, None, None] + k[1] * j[None, :, None] + k[2] * j[None, None, :]) / n
+    x = (torch.cos(ph(m)) + 0.5 * torch.sin(ph(mp))).float()
+    X = sim.fft(x)[0]
+    ref_a, ref_b = n ** 3 / 2, -0.5j * n ** 3 / 2
+    ea = X[m] - ref_a
+    eb = X[mp] - ref_b
+    X[m] = 0
+    X[mp] = 0
+    err = math.sqrt(float(X.abs().pow(2).sum()) + abs(complex(ea)) ** 2 + abs(complex(eb)) ** 2)
+    rel = err / math.hypot(ref_a, abs(ref_b))
+    say(f"n={n}: plane-wave spectrum rel error {rel:.2e}")
+    assert rel < 3e-7 * math.log2(n) / 3 * 4
+    del X, x
+    gen = torch.Generator(device="cuda").manual_seed(n)
+    r = torch.randn((n, n, n), device="cuda", generator=gen)
+    back = sim.fft(sim.fft(r), inverse=True)[0] / n ** 3
+    rt = float((back - r).norm() / r.norm())
+    say(f"n={n}: round trip rel L2 {rt:.2e}")
+    assert rt < 3e-7 * math.log2(n) / 3 * 2
 
 
 def test_fft_naive_dft_8cubed():
