@@ -356,6 +356,127 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
   }
 }
 
+// ------------------------------------------- row passes, register FFT
+
+// Real rows -> half-spectrum rows with the half-length complex transform held
+// in registers (fft_reg.h, RowShape); same conversions as k_r2c_rows.
+template <int L, int P, int SRC>
+__global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ src, long long src_stride,
+                                                      float2* __restrict__ dst, long long dst_stride,
+                                                      int n_rows, const float2* __restrict__ tw, int tws_half,
+                                                      int tws_full, double scale, double shift,
+                                                      unsigned long long active, int rs) {
+  using S = freg::RowShape<L, P>;
+  constexpr int n = 2 * L;
+  __shared__ float2 lds[S::LDS];
+  const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
+  const int n1 = S::lane_n1(threadIdx.x), c = S::lane_c(threadIdx.x);
+  const long long row = (long long)blockIdx.x * S::R + c;
+  const bool valid = row < n_rows;
+  float2 v[S::E];
+#pragma unroll
+  for (int r = 0; r < S::E; ++r) {
+    const int t = S::t_in(n1, r);  // z[t] = x[2t] + i x[2t+1]
+    float2 z = make_float2(0.f, 0.f);
+    if (valid) {
+      const long long gi = slot * src_stride + row * n + 2 * t;
+      if constexpr (SRC == SRC_I64) {
+        const longlong2 m = *reinterpret_cast<const longlong2*>(reinterpret_cast<const long long*>(src) + gi);
+        z = make_float2((float)((double)m.x * scale - shift), (float)((double)m.y * scale - shift));
+      } else {
+        const float2 f = *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(src) + gi);
+        z = make_float2(f.x * (float)scale, f.y * (float)scale);
+      }
+    }
+    v[r] = z;
+  }
+  freg::pass_a<S, false>(v, n1, tw, tws_half);
+  freg::store_y<S>(v, lds, n1, c);
+  __syncthreads();
+  freg::pass_b<S, false>(v, lds, n1, c);
+  __syncthreads();
+  freg::store_nat_out<S>(v, lds, n1, c);
+  __syncthreads();
+  if (!valid) return;
+  // unpack: X[k] = (Z[k] + conj Z[L-k])/2 + w^k (Z[k] - conj Z[L-k])/(2i)
+  const float2* zr = lds + S::nat_idx(0, c);
+  float2* out = dst + slot * dst_stride + row * rs;
+  for (int k = n1; k <= L / 2; k += P) {
+    const int kk = (L - k) & (L - 1);
+    const float2 zk = zr[k], zm = zr[kk];
+    if (k == 0) {
+      out[0] = make_float2(zk.x + zk.y, 0.f);
+      out[L] = make_float2(zk.x - zk.y, 0.f);
+      continue;
+    }
+    const float2 fe = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    const float2 fo = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+    const float2 wf = cmul(tw[k * tws_full], fo);
+    out[k] = make_float2(fe.x + wf.x, fe.y + wf.y);
+    if (kk != k) {
+      const float2 wf2 = cmul(tw[(L - k) * tws_full], make_float2(fo.x, -fo.y));
+      out[kk] = make_float2(fe.x + wf2.x, -fe.y + wf2.y);
+    }
+  }
+}
+
+// Half-spectrum rows -> real rows, register transform; as k_c2r_rows.
+template <int L, int P, int DST>
+__global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__ src, long long src_stride,
+                                                      float* __restrict__ dst, long long dst_stride,
+                                                      float* __restrict__ dst2, int n_rows,
+                                                      const float2* __restrict__ tw, int tws_half, int tws_full,
+                                                      float scale, float scale2, unsigned long long active,
+                                                      int rs) {
+  using S = freg::RowShape<L, P>;
+  constexpr int n = 2 * L;
+  __shared__ float2 lds[S::LDS];
+  const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
+  const int n1 = S::lane_n1(threadIdx.x), c = S::lane_c(threadIdx.x);
+  const long long row = (long long)blockIdx.x * S::R + c;
+  const bool valid = row < n_rows;
+  float2* zr = lds + S::nat_idx(0, c);
+  const float2* in = src + slot * src_stride + row * rs;
+  // pack: Z[k] = (X[k] + conj X[L-k]) + i e^{+2 pi i k/n} (X[k] - conj X[L-k])
+  for (int k = n1; k <= L / 2; k += P) {
+    float2 xk = make_float2(0.f, 0.f), xm = xk;
+    if (valid) {
+      xk = in[k];
+      xm = in[L - k];
+    }
+    const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);
+    const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
+    float2 w = tw[k * tws_full];
+    w.y = -w.y;
+    const float2 wd = cmul(w, d);
+    zr[k] = make_float2(a.x - wd.y, a.y + wd.x);  // k < L here (k <= L / 2)
+    if (L - k != k && L - k < L) {
+      float2 w2 = tw[(L - k) * tws_full];
+      w2.y = -w2.y;
+      const float2 wd2 = cmul(w2, make_float2(-d.x, d.y));
+      zr[L - k] = make_float2(a.x - wd2.y, -a.y + wd2.x);
+    }
+  }
+  __syncthreads();
+  float2 v[S::E];
+  freg::load_nat_in<S>(v, lds, n1, c);
+  freg::pass_a<S, true>(v, n1, tw, tws_half);
+  __syncthreads();
+  freg::store_y<S>(v, lds, n1, c);
+  __syncthreads();
+  freg::pass_b<S, true>(v, lds, n1, c);
+  if (!valid) return;
+#pragma unroll
+  for (int r = 0; r < S::E; ++r) {
+    const long long gi = slot * dst_stride + row * n + 2 * S::t_out(n1, r);
+    const float2 z = make_float2(v[r].x * scale, v[r].y * scale);
+    *reinterpret_cast<float2*>(dst + gi) = z;
+    if constexpr (DST == DST_IC) *reinterpret_cast<float2*>(dst2 + gi) = make_float2(z.x * scale2, z.y * scale2);
+  }
+}
+
 // ---------------------------------------- column passes, register FFT
 
 // The same passes as k_cols, with the column transform held in registers
@@ -421,10 +542,10 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
   constexpr bool kFwdFirst = MODE == MODE_FWD || MODE == MODE_FUSED_H || MODE == MODE_NUFFT_ADJ;
   bool inverse_next = !kFwdFirst;  // input layout holds data for an inverse transform
   if constexpr (kFwdFirst) {
-    freg::pass_a<L, C, false>(v, n1, a.tw, a.tws);
-    freg::store_y<L, C>(v, lds, n1, c);
+    freg::pass_a<S, false>(v, n1, a.tw, a.tws);
+    freg::store_y<S>(v, lds, n1, c);
     __syncthreads();
-    freg::pass_b<L, C, false>(v, lds, n1, c);
+    freg::pass_b<S, false>(v, lds, n1, c);
     if constexpr (MODE == MODE_FUSED_H) {
 #pragma unroll
       for (int r = 0; r < S::E; ++r) {
@@ -463,17 +584,17 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
     }
     if (inverse_next) {  // back to the input layout for the inverse transform
       __syncthreads();
-      freg::store_nat_out<L, C>(v, lds, n1, c);
+      freg::store_nat_out<S>(v, lds, n1, c);
       __syncthreads();
-      freg::load_nat_in<L, C>(v, lds, n1, c);
+      freg::load_nat_in<S>(v, lds, n1, c);
     }
   }
   if (inverse_next) {
-    freg::pass_a<L, C, true>(v, n1, a.tw, a.tws);
+    freg::pass_a<S, true>(v, n1, a.tw, a.tws);
     __syncthreads();
-    freg::store_y<L, C>(v, lds, n1, c);
+    freg::store_y<S>(v, lds, n1, c);
     __syncthreads();
-    freg::pass_b<L, C, true>(v, lds, n1, c);
+    freg::pass_b<S, true>(v, lds, n1, c);
   }
   if (!valid) return;
   float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ) ? a.dst3 : a.data;
@@ -509,17 +630,48 @@ static hipError_t launch_rows(const RowLaunch& r) {
   return hipGetLastError();
 }
 
+template <int L, int P>
+static hipError_t launch_rows_reg(const RowLaunch& r) {
+  constexpr int R = 256 / P;
+  dim3 grid((unsigned)((r.n_rows + R - 1) / R), r.batch);
+  if (r.inverse) {
+    if (r.dst_mode == DST_F32)
+      k_c2r_rows_reg<L, P, DST_F32><<<grid, 256, 0, r.stream>>>(
+          (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows, r.tw,
+          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs);
+    else
+      k_c2r_rows_reg<L, P, DST_IC><<<grid, 256, 0, r.stream>>>(
+          (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows, r.tw,
+          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs);
+  } else {
+    if (r.src_mode == SRC_I64)
+      k_r2c_rows_reg<L, P, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
+                                                                r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
+                                                                r.shift, r.active, r.rs);
+    else
+      k_r2c_rows_reg<L, P, SRC_F32><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
+                                                                r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
+                                                                r.shift, r.active, r.rs);
+  }
+  return hipGetLastError();
+}
+
 hipError_t fft_rows(const RowLaunch& r) {
+  // register transforms from n = 32 (half length 16): P threads per row with
+  // P <= L / P
   switch (r.n) {
+    case 32: return launch_rows_reg<16, 4>(r);
+    case 64: return launch_rows_reg<32, 4>(r);
+    case 128: return launch_rows_reg<64, 8>(r);
+    case 256: return launch_rows_reg<128, 8>(r);
+    case 512: return launch_rows_reg<256, 16>(r);
+    case 1024: return launch_rows_reg<512, 16>(r);
+    default: break;
+  }
+  switch (r.n) {  // small meshes: LDS Stockham rows
     case 4: return launch_rows<2>(r);
     case 8: return launch_rows<4>(r);
     case 16: return launch_rows<8>(r);
-    case 32: return launch_rows<16>(r);
-    case 64: return launch_rows<32>(r);
-    case 128: return launch_rows<64>(r);
-    case 256: return launch_rows<128>(r);
-    case 512: return launch_rows<256>(r);
-    case 1024: return launch_rows<512>(r);
     default: return hipErrorInvalidValue;
   }
 }

@@ -74,8 +74,11 @@ struct Dft<1, INV> {
   __host__ __device__ static __forceinline__ void run(float2*) {}
 };
 
-template <int L, int C>
+// column passes: C columns per block, lanes run over columns first so that a
+// wave reads C consecutive complex values of several rows
+template <int L_, int C>
 struct Shape {
+  static constexpr int L = L_;
   static constexpr int P = 256 / C;   // threads per column
   static constexpr int E = L / P;     // elements per thread
   static constexpr int J = E / P;     // pass-B DFTs per thread
@@ -84,17 +87,41 @@ struct Shape {
   static constexpr int LDS = (E * KS > L * C) ? E * KS : L * C;  // float2
   static_assert(P * C == 256, "256 threads per block");
   static_assert(E >= P && E % P == 0 && E <= 32 && P <= 32, "shape");
+  __host__ __device__ static int lane_c(int tid) { return tid % C; }
+  __host__ __device__ static int lane_n1(int tid) { return tid / C; }
   __host__ __device__ static int y_idx(int k2, int n1, int c) { return k2 * KS + n1 * C + c; }
   __host__ __device__ static int nat_idx(int t, int c) { return t * C + c; }
   __host__ __device__ static int t_in(int n1, int r) { return n1 + P * r; }
   __host__ __device__ static int t_out(int n1, int r) { return (n1 + (r / P) * P) + E * (r % P); }
 };
 
+// row passes: R contiguous rows per block, lanes run along the row first so
+// that a wave reads P consecutive values of each of 64 / P rows
+template <int L_, int P_>
+struct RowShape {
+  static constexpr int L = L_;
+  static constexpr int P = P_;
+  static constexpr int R = 256 / P;   // rows per block
+  static constexpr int E = L / P;
+  static constexpr int J = E / P;
+  static constexpr int PAD = 16;
+  static constexpr int KS = P * R + PAD;
+  static constexpr int RS = L + 1;    // natural row stride in LDS
+  static constexpr int LDS = (E * KS > R * RS) ? E * KS : R * RS;
+  static_assert(P * R == 256, "256 threads per block");
+  static_assert(E >= P && E % P == 0 && E <= 32 && P <= 32, "shape");
+  __host__ __device__ static int lane_c(int tid) { return tid / P; }
+  __host__ __device__ static int lane_n1(int tid) { return tid % P; }
+  __host__ __device__ static int y_idx(int k2, int n1, int c) { return k2 * KS + c * P + n1; }
+  __host__ __device__ static int nat_idx(int t, int c) { return c * RS + t; }
+  __host__ __device__ static int t_in(int n1, int r) { return n1 + P * r; }
+  __host__ __device__ static int t_out(int n1, int r) { return (n1 + (r / P) * P) + E * (r % P); }
+};
+
 // pass A in registers: DFT over n2, then the twiddle W_L^(n1 k2) from the
 // table tw[t] = exp(-2 pi i t / Lmax), read with stride tws = Lmax / L
-template <int L, int C, bool INV>
+template <class S, bool INV>
 __host__ __device__ __forceinline__ void pass_a(float2* v, int n1, const float2* tw, int tws) {
-  using S = Shape<L, C>;
   Dft<S::E, INV>::run(v);
 #pragma unroll
   for (int k2 = 1; k2 < S::E; ++k2) {
@@ -104,17 +131,15 @@ __host__ __device__ __forceinline__ void pass_a(float2* v, int n1, const float2*
   }
 }
 
-template <int L, int C>
+template <class S>
 __host__ __device__ __forceinline__ void store_y(const float2* v, float2* lds, int n1, int c) {
-  using S = Shape<L, C>;
 #pragma unroll
   for (int k2 = 0; k2 < S::E; ++k2) lds[S::y_idx(k2, n1, c)] = v[k2];
 }
 
 // pass B: P-point DFTs over n1 for k2 = n1 + j P; output layout
-template <int L, int C, bool INV>
+template <class S, bool INV>
 __host__ __device__ __forceinline__ void pass_b(float2* v, const float2* lds, int n1, int c) {
-  using S = Shape<L, C>;
 #pragma unroll
   for (int j = 0; j < S::J; ++j) {
     const int k2 = n1 + j * S::P;
@@ -129,15 +154,13 @@ __host__ __device__ __forceinline__ void pass_b(float2* v, const float2* lds, in
 
 // output layout -> natural order in LDS -> input layout (to chain a second
 // transform on the same columns)
-template <int L, int C>
+template <class S>
 __host__ __device__ __forceinline__ void store_nat_out(const float2* v, float2* lds, int n1, int c) {
-  using S = Shape<L, C>;
 #pragma unroll
   for (int r = 0; r < S::E; ++r) lds[S::nat_idx(S::t_out(n1, r), c)] = v[r];
 }
-template <int L, int C>
+template <class S>
 __host__ __device__ __forceinline__ void load_nat_in(float2* v, const float2* lds, int n1, int c) {
-  using S = Shape<L, C>;
 #pragma unroll
   for (int r = 0; r < S::E; ++r) v[r] = lds[S::nat_idx(S::t_in(n1, r), c)];
 }
