@@ -28,6 +28,11 @@ WORKLOADS = {
     "pm_256_512_tsc": dict(BASE, n_p=256, n_g=512, box=500.0, n_steps=10, mak=3, deconvolve=True),
     "pm_128_256_cic": dict(BASE, n_p=128, n_g=256, box=250.0, n_steps=10, mak=2, deconvolve=False),
     "pm_512_1024_tsc": dict(BASE, n_p=512, n_g=1024, box=1000.0, n_steps=6, mak=3, deconvolve=True),
+    # NUFFT force: ES width 6 at 2x upsampling (fine grid 1024^3), exact i k
+    "nufft_512_1024_es6": dict(BASE, n_p=512, n_g=1024, box=1000.0, n_steps=6, force="nufft", es_width=6,
+                               es_beta=13.8, grad_order=0, mak=2, deconvolve=False),
+    "nufft_128_256_es6": dict(BASE, n_p=128, n_g=256, box=250.0, n_steps=6, force="nufft", es_width=6,
+                              es_beta=13.8, grad_order=0, mak=2, deconvolve=False),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -44,6 +49,28 @@ def launch_model(cfg):
     n, p, K = cfg.n_g, cfg.n_p, cfg.n_steps
     M, N = n ** 3, p ** 3
     Sn, Sp = 8 * n * n * (n // 2 + 1), 8 * p * p * (p // 2 + 1)   # bytes of one half spectrum
+    ic_rows = [(4, 4 * N + Sp), (3, Sp + 8 * N), (1, Sp + 4 * N)]
+    ic_cols = [(15, 2 * Sp), (1, 4 * Sp)]
+    if cfg.force == "nufft":
+        # pruned passes: only the modes |m| < n_p/2 per axis survive the
+        # truncation, so the rows keep k_z < n_p/2 (Sz), the y passes touch
+        # those columns and the kept k_y (Sy, all x), the x passes only the
+        # kept (k_y, k_z) lines
+        Sz = 8 * n * n * (p // 2)
+        Sy = 8 * n * (p - 1) * (p // 2)
+        return {
+            "deposit": [(2 * K + 2, 12 * N + 8 * M)],
+            "bin": [(1, 40 * N), (2 * K + 2, 16 * N)],
+            "fft_rows": [(2 * K, 8 * M + Sz), (1, 8 * M + Sn), (7 * K, Sz + 4 * M), (3 * K, 4 * M + Sz)] + ic_rows,
+            "fft_cols": [(5 * K, Sz + Sy), (6 * K, 2 * Sy), (6 * K, Sy + Sz), (K, 2 * Sy), (2 * K, 5 * Sy // 2),
+                         (K, Sy + Sz), (2, 2 * Sn)] + ic_cols,
+            # read X, V and 3 force meshes, write X, V
+            "gather_kick": [(K, 48 * N + 12 * M)],
+            "adj_kick": [(K, 96 * N + 12 * M)],
+            # per component: read u_c and X, write the FP32 mesh
+            "dipole": [(3 * K, 16 * N + 4 * M)],
+            "adj_drift": [(K + 1, 84 * N + 4 * M)],
+        }
     return {
         # fixed-point mass assignment: read the positions, write the int64 mesh
         "deposit": [(2 * K + 2, 12 * N + 8 * M)],
@@ -51,10 +78,9 @@ def launch_model(cfg):
         # force evaluation also drifts: read V, write the positions)
         "bin": [(1, 40 * N), (2 * K + 2, 16 * N)],
         # z rows: int64 or FP32 mesh -> half spectrum, and back to FP32
-        "fft_rows": [(2 * K + 1, 8 * M + Sn), (K, 4 * M + Sn), (3 * K, Sn + 4 * M),
-                     (4, 4 * N + Sp), (3, Sp + 8 * N), (1, Sp + 4 * N)],
+        "fft_rows": [(2 * K + 1, 8 * M + Sn), (K, 4 * M + Sn), (3 * K, Sn + 4 * M)] + ic_rows,
         # y / x passes (one with the fused multiplier): read + write the spectrum
-        "fft_cols": [(9 * K + 2, 2 * Sn), (15, 2 * Sp), (1, 4 * Sp)],
+        "fft_cols": [(9 * K + 2, 2 * Sn)] + ic_cols,
         # read X, V and phi, write X, V
         "gather_kick": [(K, 48 * N + 4 * M)],
         # read X, V, X_bar, V_bar and phi; write V, X_bar, V_bar and u
@@ -253,7 +279,7 @@ def main():
     if not args.no_kernel_timing:
         kt = sim.kernel_times()
         sim.profile(False)
-        if cfg.force == "pm":
+        if True:
             by_class = rooflines(cfg, kt, args.steps)
             ok = {k: v for k, v in by_class.items() if "achieved" in v}
             dom = max(ok, key=lambda k: ok[k]["ms_per_step"])

@@ -78,7 +78,8 @@ enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
  *   deconvolve     divide the PM multiplier by the squared window
  *   grad_order     0 exact i k (NUFFT only), 2/4/6 finite differences (PM)
  *   lap_order      0 exact -k^2, 2/4/6 finite differences
- *   es_width, es_beta   NUFFT exponential-of-semicircle kernel (width 6)
+ *   es_width, es_beta   NUFFT exponential-of-semicircle kernel (width 6);
+ *                  NUFFT needs n_g = 2 n_p and n_p >= 8
  *   batch          number of same-shape slots B >= 1
  */
 typedef struct {

@@ -26,6 +26,9 @@ struct RowLaunch {
   double scale, shift, scale2;
   unsigned long long active;  // bit b set: slot b takes part
   int rs;                     // row stride of the half spectrum (float2), >= n/2 + 1
+  // pruning (truncated spectra): R2C writes and C2R reads only k < kz_lim
+  // (the rest is zero); 0 = the whole half row
+  int kz_lim;
   hipStream_t stream;
 };
 
@@ -53,6 +56,11 @@ struct ColArgs {
   const float* esdec;
   int n_p;
   unsigned long long active;  // bit b set: slot b takes part
+  // pruning for spectra truncated to |m| < keep/2 per axis (keep = 0: none):
+  // only columns iz < zlim (0 = all nh); keep_in: indices along the pass
+  // outside the kept set are zero and not read; keep_out: they are not
+  // written; keep_outer: whole lines whose outer index is not kept are skipped
+  int zlim, keep, keep_in, keep_out, keep_outer;
 };
 
 hipError_t fft_rows(const RowLaunch& r);

@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
                                                       float2* __restrict__ dst, long long dst_stride,
                                                       int n_rows, const float2* __restrict__ tw, int tws_half,
                                                       int tws_full, double scale, double shift,
-                                                      unsigned long long active, int rs) {
+                                                      unsigned long long active, int rs, int kz_lim) {
   using S = freg::RowShape<L, P>;
   constexpr int n = 2 * L;
   __shared__ float2 lds[S::LDS];
@@ -402,19 +402,21 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
   // unpack: X[k] = (Z[k] + conj Z[L-k])/2 + w^k (Z[k] - conj Z[L-k])/(2i)
   const float2* zr = lds + S::nat_idx(0, c);
   float2* out = dst + slot * dst_stride + row * rs;
+  const int klim = kz_lim > 0 ? kz_lim : L + 1;
   for (int k = n1; k <= L / 2; k += P) {
     const int kk = (L - k) & (L - 1);
     const float2 zk = zr[k], zm = zr[kk];
     if (k == 0) {
       out[0] = make_float2(zk.x + zk.y, 0.f);
-      out[L] = make_float2(zk.x - zk.y, 0.f);
+      if (L < klim) out[L] = make_float2(zk.x - zk.y, 0.f);
       continue;
     }
+    if (k >= klim && kk >= klim) continue;
     const float2 fe = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     const float2 fo = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
     const float2 wf = cmul(tw[k * tws_full], fo);
-    out[k] = make_float2(fe.x + wf.x, fe.y + wf.y);
-    if (kk != k) {
+    if (k < klim) out[k] = make_float2(fe.x + wf.x, fe.y + wf.y);
+    if (kk != k && kk < klim) {
       const float2 wf2 = cmul(tw[(L - k) * tws_full], make_float2(fo.x, -fo.y));
       out[kk] = make_float2(fe.x + wf2.x, -fe.y + wf2.y);
     }
@@ -428,7 +430,7 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
                                                       float* __restrict__ dst2, int n_rows,
                                                       const float2* __restrict__ tw, int tws_half, int tws_full,
                                                       float scale, float scale2, unsigned long long active,
-                                                      int rs) {
+                                                      int rs, int kz_lim) {
   using S = freg::RowShape<L, P>;
   constexpr int n = 2 * L;
   __shared__ float2 lds[S::LDS];
@@ -440,11 +442,12 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
   float2* zr = lds + S::nat_idx(0, c);
   const float2* in = src + slot * src_stride + row * rs;
   // pack: Z[k] = (X[k] + conj X[L-k]) + i e^{+2 pi i k/n} (X[k] - conj X[L-k])
+  const int klim = kz_lim > 0 ? kz_lim : L + 1;
   for (int k = n1; k <= L / 2; k += P) {
     float2 xk = make_float2(0.f, 0.f), xm = xk;
     if (valid) {
-      xk = in[k];
-      xm = in[L - k];
+      if (k < klim) xk = in[k];
+      if (L - k < klim) xm = in[L - k];
     }
     const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);
     const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
@@ -492,7 +495,10 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
   const int outer = blockIdx.y;  // x for the y pass, y for the x pass
   const int c = threadIdx.x % C, n1 = threadIdx.x / C;
   const int iz = blockIdx.x * C + c;
-  const bool valid = iz < a.nh;
+  const int zl = a.zlim > 0 && a.zlim < a.nh ? a.zlim : a.nh;
+  const bool valid = iz < zl;
+  auto kept = [&](int t) { int m = signed_mode(t, a.n); return 2 * (m < 0 ? -m : m) < a.keep; };
+  if (a.keep_outer && !kept(outer)) return;  // block-uniform
   const long long stride_t = a.axis == 1 ? (long long)a.rs : (long long)a.n * a.rs;
   const long long base0 = a.axis == 1 ? (long long)outer * a.n * a.rs : (long long)outer * a.rs;
   const long long col = slot * a.slot_stride + base0 + iz;
@@ -501,7 +507,7 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
   for (int r = 0; r < S::E; ++r) {
     const int t = S::t_in(n1, r);
     float2 x = make_float2(0.f, 0.f);
-    if (valid) {
+    if (valid && !(a.keep_in && !kept(t))) {
       if constexpr (MODE == MODE_COMBINE_IC) {
         // x pass: t = ix, outer = iy: sum_c conj(h_c) S_c, h_c = i h
         int mx = signed_mode(t, a.n), my = signed_mode(outer, a.n);
@@ -519,16 +525,6 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
       } else {
         x = a.data[col + t * stride_t];
       }
-      if constexpr (MODE == MODE_NUFFT_C) {
-        float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
-        int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
-        const float k0 = 6.283185307179586f / (float)a.n_p;
-        float th2 = 0.f;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
-        float h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
-        x = make_float2(-h * x.y, h * x.x);  // i h x
-      }
       if constexpr (MODE == MODE_IC_C) {
         int mx = signed_mode(t, a.n), my = signed_mode(outer, a.n);
         int ms[3] = {mx, my, iz};
@@ -539,7 +535,8 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
     }
     v[r] = x;
   }
-  constexpr bool kFwdFirst = MODE == MODE_FWD || MODE == MODE_FUSED_H || MODE == MODE_NUFFT_ADJ;
+  constexpr bool kFwdFirst =
+      MODE == MODE_FWD || MODE == MODE_FUSED_H || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ;
   bool inverse_next = !kFwdFirst;  // input layout holds data for an inverse transform
   if constexpr (kFwdFirst) {
     freg::pass_a<S, false>(v, n1, a.tw, a.tws);
@@ -558,6 +555,25 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
       }
       inverse_next = true;
     }
+    if constexpr (MODE == MODE_NUFFT_C) {
+      // truncation, deconvolution and i k_c s / k^2 of component comp
+      const float k0 = 6.283185307179586f / (float)a.n_p;
+#pragma unroll
+      for (int r = 0; r < S::E; ++r) {
+        const int t = S::t_out(n1, r);
+        float h = 0.f;
+        if (valid) {
+          float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
+          int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
+          float th2 = 0.f;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
+          h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
+        }
+        v[r] = make_float2(-h * v[r].y, h * v[r].x);  // i h v
+      }
+      inverse_next = true;
+    }
     if constexpr (MODE == MODE_NUFFT_ADJ) {
       const float k0 = 6.283185307179586f / (float)a.n_p;
 #pragma unroll
@@ -573,7 +589,7 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
           h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
         }
         float2 y = make_float2(h * v[r].y, -h * v[r].x);  // -i h v
-        if (valid && a.comp > 0) {
+        if (valid && a.comp > 0 && h != 0.f) {  // the sum is zero off the kept modes
           float2 acc = a.dst3[col + t * stride_t];
           y.x += acc.x;
           y.y += acc.y;
@@ -599,7 +615,11 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
   if (!valid) return;
   float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ) ? a.dst3 : a.data;
 #pragma unroll
-  for (int r = 0; r < S::E; ++r) out[col + S::t_out(n1, r) * stride_t] = v[r];
+  for (int r = 0; r < S::E; ++r) {
+    const int t = S::t_out(n1, r);
+    if (a.keep_out && !kept(t)) continue;
+    out[col + t * stride_t] = v[r];
+  }
 }
 
 // ------------------------------------------------------------ dispatch
@@ -638,20 +658,20 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
     if (r.dst_mode == DST_F32)
       k_c2r_rows_reg<L, P, DST_F32><<<grid, 256, 0, r.stream>>>(
           (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows, r.tw,
-          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs);
+          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs, r.kz_lim);
     else
       k_c2r_rows_reg<L, P, DST_IC><<<grid, 256, 0, r.stream>>>(
           (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows, r.tw,
-          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs);
+          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs, r.kz_lim);
   } else {
     if (r.src_mode == SRC_I64)
       k_r2c_rows_reg<L, P, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
                                                                 r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                r.shift, r.active, r.rs);
+                                                                r.shift, r.active, r.rs, r.kz_lim);
     else
       k_r2c_rows_reg<L, P, SRC_F32><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
                                                                 r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                r.shift, r.active, r.rs);
+                                                                r.shift, r.active, r.rs, r.kz_lim);
   }
   return hipGetLastError();
 }
@@ -668,6 +688,7 @@ hipError_t fft_rows(const RowLaunch& r) {
     case 1024: return launch_rows_reg<512, 16>(r);
     default: break;
   }
+  if (r.kz_lim) return hipErrorInvalidValue;  // pruning: register rows only
   switch (r.n) {  // small meshes: LDS Stockham rows
     case 4: return launch_rows<2>(r);
     case 8: return launch_rows<4>(r);
@@ -694,7 +715,8 @@ static hipError_t launch_cols_c(const ColArgs& a, int mode, int batch, hipStream
 
 template <int L, int C>
 static hipError_t launch_cols_r(const ColArgs& a, int mode, int batch, hipStream_t s) {
-  dim3 grid((unsigned)((a.nh + C - 1) / C), (unsigned)a.n, (unsigned)batch);
+  const int zl = a.zlim > 0 && a.zlim < a.nh ? a.zlim : a.nh;
+  dim3 grid((unsigned)((zl + C - 1) / C), (unsigned)a.n, (unsigned)batch);
   switch (mode) {
     case MODE_FWD: k_cols_reg<L, C, MODE_FWD><<<grid, 256, 0, s>>>(a); break;
     case MODE_INV: k_cols_reg<L, C, MODE_INV><<<grid, 256, 0, s>>>(a); break;
@@ -716,6 +738,8 @@ static hipError_t launch_cols(const ColArgs& a, int mode, int batch, hipStream_t
     constexpr int C = L >= 1024 ? 8 : (L >= 256 ? 16 : (L >= 64 ? 32 : 64));
     return launch_cols_r<L, C>(a, mode, batch, s);
   } else {
+    // the NUFFT passes and pruning exist only in the register kernels
+    if (mode == MODE_NUFFT_C || mode == MODE_NUFFT_ADJ || a.keep || a.zlim) return hipErrorInvalidValue;
     return launch_cols_c<L, 16>(a, mode, batch, s);
   }
 }

@@ -291,12 +291,15 @@ unsigned long long all_mask(int B) { return B >= 64 ? ~0ull : ((1ull << B) - 1);
 // --------------------------------------------------------------- FFT chains
 
 // real mesh (int64 mass or float) -> spectrum, forward 3D (or up to y only)
+// prune > 0: only the modes |m| < prune/2 per axis are needed afterwards, so
+// the rows keep k_z < prune/2 and the y pass writes only the kept k_y
 pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_stride, double scale,
                    double shift, float2* dst, long long dst_stride, int n, bool do_x,
-                   unsigned long long active) {
+                   unsigned long long active, int prune = 0) {
   RowLaunch r{};
   r.n = n;
   r.rs = spec_rs(n);
+  r.kz_lim = prune / 2;
   r.n_rows = (long long)n * n;
   r.batch = c->cfg.batch;
   r.inverse = false;
@@ -323,8 +326,12 @@ pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_strid
   a.tws = c->Lmax / n;
   a.active = active;
   a.axis = 1;
+  a.zlim = prune / 2;
+  a.keep = prune;
+  a.keep_out = prune > 0;
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_FWD, c->cfg.batch, c->stream));
   if (do_x) {
+    if (prune) return fail(c, PM_EINVAL, "pruned transform stops after the y pass");
     a.axis = 0;
     KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_FWD, c->cfg.batch, c->stream));
   }
@@ -481,7 +488,7 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   const double ph0 = es_phihat(0.0, c->cfg.es_width, c->cfg.es_beta);
   const double mean = N * ph0 * ph0 * ph0 / (double)c->g.M;  // removes most of k = 0
   st = r2c_mesh(c, c->mesh, SRC_I64, c->g.mesh_stride, 1.0 / 4294967296.0, mean, c->spec,
-                c->g.spec_stride, n, true, active);
+                c->g.spec_stride, n, false, active, np);
   if (st) return st;
   ColArgs a{};
   a.data = c->spec;
@@ -495,6 +502,9 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   a.esdec = c->d_esdec;
   a.n_p = np;
   a.dst3 = c->spec2;
+  a.zlim = np / 2;  // kept modes |m| < n_p / 2 only
+  a.keep = np;
+  a.keep_outer = 1;
   const double np3 = (double)np * np * np;
   for (int b = 0; b < c->cfg.batch; ++b) a.coef[b] = (float)(s[b] / np3 * (np3 / N));
   for (int comp = 0; comp < 3; ++comp) {
@@ -504,10 +514,13 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
     ColArgs y = a;
     y.data = c->spec2;
     y.axis = 1;
+    y.keep_outer = 0;
+    y.keep_in = 1;
     KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, c->cfg.batch, c->stream));
     RowLaunch rl{};
     rl.n = n;
     rl.rs = spec_rs(n);
+    rl.kz_lim = np / 2;
     rl.n_rows = (long long)n * n;
     rl.batch = c->cfg.batch;
     rl.inverse = true;
@@ -578,7 +591,8 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
   } else if (c.force == PM_FORCE_NUFFT) {
     // exact i k gradient and -k^2 (Sec. "Force evaluation"), width-6 ES kernel on
     // a grid upsampled by 2
-    if (c.es_width != 6 || c.n_g != 2 * c.n_p || c.grad_order != 0 || c.lap_order != 0 ||
+    // (n_p >= 8: the pruned NUFFT passes run in the register FFT kernels)
+    if (c.es_width != 6 || c.n_g != 2 * c.n_p || c.n_p < 8 || c.grad_order != 0 || c.lap_order != 0 ||
         !(c.es_beta > 0))
       return PM_EINVAL;
   } else {
@@ -964,12 +978,15 @@ pm_status nufft_adjoint_step(pm_ctx* c, int n, const double* s, unsigned long lo
   x.esdec = c->d_esdec;
   x.n_p = c->cfg.n_p;
   x.axis = 0;
+  x.zlim = c->cfg.n_p / 2;
+  x.keep = c->cfg.n_p;
+  x.keep_outer = 1;
   for (int b = 0; b < B; ++b) x.coef[b] = (float)(s[b] / (double)N);
   for (int comp = 0; comp < 3; ++comp) {
     k.comp = comp;
     AssembleArgs as = assemble_args(c, 3, d, act);
     KLAUNCH(c, PM_K_DIPOLE, both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
-    pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act);
+    pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p);
     if (st) return st;
     x.comp = comp;
     KLAUNCH(c, PM_K_FFT_COLS, fft_cols(x, MODE_NUFFT_ADJ, B, c->stream));
@@ -977,10 +994,13 @@ pm_status nufft_adjoint_step(pm_ctx* c, int n, const double* s, unsigned long lo
   ColArgs y = x;
   y.data = c->spec2;
   y.axis = 1;
+  y.keep_outer = 0;
+  y.keep_in = 1;
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
   RowLaunch rl{};
   rl.n = ng;
   rl.rs = spec_rs(ng);
+  rl.kz_lim = c->cfg.n_p / 2;
   rl.n_rows = (long long)ng * ng;
   rl.batch = B;
   rl.inverse = true;

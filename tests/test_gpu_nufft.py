@@ -51,7 +51,7 @@ def test_es_spreading_bit_exact(n_p, kind):
     assert np.array_equal(m, ref)
 
 
-@pytest.mark.parametrize("n_p", [16, 32])
+@pytest.mark.parametrize("n_p", [16, 32, 64])
 def test_nufft_force_matches_oracle(n_p):
     say("nufft force", n_p)
     sim = make_sim(synth.C3_SMALL, n_p=n_p, n_g=2 * n_p)
