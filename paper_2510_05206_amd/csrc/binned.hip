@@ -20,6 +20,7 @@
 // The windows make each HBM access coalesced and each particle's stencil an
 // LDS access; the mesh is written once per pass.
 #include "mak.h"
+#include "windows.h"
 
 namespace pm {
 
@@ -190,9 +191,8 @@ __global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
   for (int e = threadIdx.x; e < W3; e += 256) out[e] = win[e];
 }
 
-// Sum the windows covering each cell: along each axis the own tile at
-// local l + R, the previous tile at l + T + R when l < R, the next tile at
-// l - T + R when l >= T - R.  OUT_F32 converts int64 sums with inv_scale.
+// Sum the windows covering each cell (windows.h).  OUT_F32 converts the
+// int64 sums with inv_scale.
 template <bool OUT_F32>
 __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
   const int slot = blockIdx.y;
@@ -200,28 +200,14 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= a.g.M) return;
   const int L = a.g.log2_ng, nm = a.g.n_g - 1;
-  const int x[3] = {(int)(e >> (2 * L)), (int)((e >> L) & nm), (int)(e & nm)};
   const int T = a.T, R = a.R, W = T + 2 * R;
   const int ntm = (1 << a.log2nt) - 1;
-  int tl[3][3], ll[3][3], nc[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    int tc = x[c] >> a.log2T, l = x[c] & (T - 1);
-    int k = 0;
-    tl[c][k] = tc; ll[c][k] = l + R; ++k;
-    if (l < R) { tl[c][k] = (tc - 1) & ntm; ll[c][k] = l + T + R; ++k; }
-    if (l >= T - R) { tl[c][k] = (tc + 1) & ntm; ll[c][k] = l - T + R; ++k; }
-    nc[c] = k;
-  }
-  const long long* src = reinterpret_cast<const long long*>(a.scratch);
+  const WinCover cx = win_cover((int)(e >> (2 * L)), T, R, a.log2T, ntm);
+  const WinCover cy = win_cover((int)((e >> L) & nm), T, R, a.log2T, ntm);
+  const WinCover cz = win_cover((int)(e & nm), T, R, a.log2T, ntm);
   const long long W3 = (long long)W * W * W;
-  long long acc = 0;
-  for (int p = 0; p < nc[0]; ++p)
-    for (int q = 0; q < nc[1]; ++q)
-      for (int r = 0; r < nc[2]; ++r) {
-        long long t = ((long long)tl[0][p] << (2 * a.log2nt)) | (tl[1][q] << a.log2nt) | tl[2][r];
-        acc += src[((long long)slot * a.n_tiles + t) * W3 + ((long long)ll[0][p] * W + ll[1][q]) * W + ll[2][r]];
-      }
+  const long long* slab = reinterpret_cast<const long long*>(a.scratch) + (long long)slot * a.n_tiles * W3;
+  const long long acc = win_sum(slab, cx, cy, cz, W, a.log2nt);
   if constexpr (OUT_F32)
     reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = (float)((double)acc * a.inv_scale[slot]);
   else

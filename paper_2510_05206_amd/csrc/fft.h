@@ -4,7 +4,15 @@
 
 namespace pm {
 
-enum { SRC_I64 = 0, SRC_F32 = 1 };
+enum { SRC_I64 = 0, SRC_F32 = 1, SRC_WIN = 2 };
+
+// SRC_WIN: the R2C reads the mesh as the sum of int64 tile windows
+// (windows.h) instead of an assembled mesh; value = sum * scale - shift, or
+// sum * wscale[slot] when wscale is set
+struct RowWin {
+  int T, R, log2T, log2nt, n_tiles;
+  const double* wscale;
+};
 enum { DST_F32 = 0, DST_IC = 1 };
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4, MODE_NUFFT_C = 5,
        MODE_NUFFT_ADJ = 6 };
@@ -29,6 +37,7 @@ struct RowLaunch {
   // pruning (truncated spectra): R2C writes and C2R reads only k < kz_lim
   // (the rest is zero); 0 = the whole half row
   int kz_lim;
+  RowWin win;
   hipStream_t stream;
 };
 

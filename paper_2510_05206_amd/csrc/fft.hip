@@ -18,6 +18,7 @@
 // (Sec. "Force evaluation"; the Poisson solve in Fourier space).
 #include "fft.h"
 #include "fft_reg.h"
+#include "windows.h"
 
 namespace pm {
 
@@ -365,7 +366,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
                                                       float2* __restrict__ dst, long long dst_stride,
                                                       int n_rows, const float2* __restrict__ tw, int tws_half,
                                                       int tws_full, double scale, double shift,
-                                                      unsigned long long active, int rs, int kz_lim) {
+                                                      unsigned long long active, int rs, int kz_lim, RowWin win) {
   using S = freg::RowShape<L, P>;
   constexpr int n = 2 * L;
   __shared__ float2 lds[S::LDS];
@@ -374,6 +375,20 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
   const int n1 = S::lane_n1(threadIdx.x), c = S::lane_c(threadIdx.x);
   const long long row = (long long)blockIdx.x * S::R + c;
   const bool valid = row < n_rows;
+  [[maybe_unused]] WinCover cx{}, cy{};
+  [[maybe_unused]] const long long* slab = nullptr;
+  [[maybe_unused]] double wsc = scale, wsh = shift;
+  if constexpr (SRC == SRC_WIN) {
+    const int ntm = (1 << win.log2nt) - 1;
+    cx = win_cover((int)(row / n), win.T, win.R, win.log2T, ntm);
+    cy = win_cover((int)(row % n), win.T, win.R, win.log2T, ntm);
+    const long long W = win.T + 2 * win.R;
+    slab = reinterpret_cast<const long long*>(src) + (long long)slot * win.n_tiles * W * W * W;
+    if (win.wscale) {
+      wsc = win.wscale[slot];
+      wsh = 0.0;
+    }
+  }
   float2 v[S::E];
 #pragma unroll
   for (int r = 0; r < S::E; ++r) {
@@ -381,7 +396,12 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
     float2 z = make_float2(0.f, 0.f);
     if (valid) {
       const long long gi = slot * src_stride + row * n + 2 * t;
-      if constexpr (SRC == SRC_I64) {
+      if constexpr (SRC == SRC_WIN) {
+        const int ntm = (1 << win.log2nt) - 1, W = win.T + 2 * win.R;
+        const long long m0 = win_sum(slab, cx, cy, win_cover(2 * t, win.T, win.R, win.log2T, ntm), W, win.log2nt);
+        const long long m1 = win_sum(slab, cx, cy, win_cover(2 * t + 1, win.T, win.R, win.log2T, ntm), W, win.log2nt);
+        z = make_float2((float)((double)m0 * wsc - wsh), (float)((double)m1 * wsc - wsh));
+      } else if constexpr (SRC == SRC_I64) {
         const longlong2 m = *reinterpret_cast<const longlong2*>(reinterpret_cast<const long long*>(src) + gi);
         z = make_float2((float)((double)m.x * scale - shift), (float)((double)m.y * scale - shift));
       } else {
@@ -667,11 +687,15 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
     if (r.src_mode == SRC_I64)
       k_r2c_rows_reg<L, P, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
                                                                 r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                r.shift, r.active, r.rs, r.kz_lim);
-    else
+                                                                r.shift, r.active, r.rs, r.kz_lim, r.win);
+    else if (r.src_mode == SRC_F32)
       k_r2c_rows_reg<L, P, SRC_F32><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
                                                                 r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                r.shift, r.active, r.rs, r.kz_lim);
+                                                                r.shift, r.active, r.rs, r.kz_lim, r.win);
+    else
+      k_r2c_rows_reg<L, P, SRC_WIN><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
+                                                                r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
+                                                                r.shift, r.active, r.rs, r.kz_lim, r.win);
   }
   return hipGetLastError();
 }
@@ -688,7 +712,7 @@ hipError_t fft_rows(const RowLaunch& r) {
     case 1024: return launch_rows_reg<512, 16>(r);
     default: break;
   }
-  if (r.kz_lim) return hipErrorInvalidValue;  // pruning: register rows only
+  if (r.kz_lim || (!r.inverse && r.src_mode == SRC_WIN)) return hipErrorInvalidValue;  // register rows only
   switch (r.n) {  // small meshes: LDS Stockham rows
     case 4: return launch_rows<2>(r);
     case 8: return launch_rows<4>(r);
