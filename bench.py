@@ -60,7 +60,7 @@ def launch_model(cfg):
         Sy = 8 * n * (p - 1) * (p // 2)
         return {
             "deposit": [(2 * K + 2, 12 * N + 8 * M)],
-            "bin": [(1, 40 * N), (2 * K + 2, 16 * N)],
+            "bin": [(K, 40 * N), (K + 3, 16 * N)],
             "fft_rows": [(2 * K, 8 * M + Sz), (1, 8 * M + Sn), (7 * K, Sz + 4 * M), (3 * K, 4 * M + Sz)] + ic_rows,
             "fft_cols": [(5 * K, Sz + Sy), (6 * K, 2 * Sy), (6 * K, Sy + Sz), (K, 2 * Sy), (2 * K, 5 * Sy // 2),
                          (K, Sy + Sz), (2, 2 * Sn)] + ic_cols,
@@ -74,9 +74,9 @@ def launch_model(cfg):
     return {
         # fixed-point mass assignment: read the positions, write the int64 mesh
         "deposit": [(2 * K + 2, 12 * N + 8 * M)],
-        # counting sort: read positions, write the sorted index (the first
-        # force evaluation also drifts: read V, write the positions)
-        "bin": [(1, 40 * N), (2 * K + 2, 16 * N)],
+        # counting sort: read positions, write the sorted index (in the run
+        # it also applies the first drift: read V, write the positions)
+        "bin": [(K, 40 * N), (K + 3, 16 * N)],
         # z rows: int64 or FP32 mesh -> half spectrum, and back to FP32
         "fft_rows": [(2 * K + 1, 8 * M + Sn), (K, 4 * M + Sn), (3 * K, Sn + 4 * M)] + ic_rows,
         # y / x passes (one with the fused multiplier): read + write the spectrum

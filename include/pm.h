@@ -181,7 +181,7 @@ pm_status pm_init_ics(pm_ctx* ctx, const uint64_t* seeds, const float* w_in, flo
  * entry leaves that slot idle. */
 pm_status pm_step(pm_ctx* ctx, const int32_t* step_index);
 
-/* All n_steps steps for every slot (drifts of consecutive steps merged).
+/* All n_steps steps for every slot: bit-identical to pm_step(0 .. n-1).
  * Unless profiling is on or graphs are disabled (pm_use_graphs), the whole
  * launch sequence is captured once into a HIP graph and replayed on later
  * calls; the graph is rebuilt after pm_bind, pm_set_slot_params or a change
@@ -227,6 +227,16 @@ pm_status pm_deposit(pm_ctx* ctx, const float* disp, int32_t mak, int64_t* mesh_
 /* PM (or NUFFT) acceleration A(X) at the given displacements for the
  * midpoint normalisation s = 1/D^2 (device in [B][3][N], out [B][3][N]). */
 pm_status pm_force(pm_ctx* ctx, const float* disp, double s, float* acc_out);
+
+/* Vector-Jacobian product of that acceleration (App. "Custom VJP and JVP":
+ * gather w.r.t. positions, gather w.r.t. the mesh, transposed multiplier,
+ * scatter w.r.t. positions): xbar_out = J_A(disp)^T u, all device
+ * [B][3][N].  parts: 1 = the direct term (the gather differentiated w.r.t.
+ * the positions) only, 2 = the term through the mesh only, 3 = both.  Needs
+ * a workspace bound with adjoint buffers (PM_ESTATE otherwise); overwrites
+ * the context's particle state (positions = disp, velocities = 0). */
+pm_status pm_force_vjp(pm_ctx* ctx, const float* disp, double s, const float* u, int32_t parts,
+                       float* xbar_out);
 
 /* 3D FFT of a real mesh (n = n_g): inverse == 0: real [B][n^3] -> half
  * spectrum [B][n][n][n/2+1] complex64 (unnormalised, exp(-i k x));

@@ -26,8 +26,10 @@ from . import ics, mesh
 from .force import force_multipliers, PMConfig
 
 
-def force_vjp(cfg: PMConfig, psi, s, u):
-    """J_A(Psi)^T u for the PM force A(Psi) of ``force.pm_force``; u (3, N)."""
+def force_vjp(cfg: PMConfig, psi, s, u, parts=3):
+    """J_A(Psi)^T u for the PM force A(Psi) of ``force.pm_force``; u (3, N).
+    parts: 1 the direct term (gather w.r.t. positions) only, 2 the terms
+    through the mesh only, 3 both."""
     n, N = cfg.n_g, cfg.N
     delta = mesh.contrast(mesh.deposit(psi, cfg.n_p, n, cfg.order), N, n)
     dk = np.fft.rfftn(delta.reshape(n, n, n))
@@ -37,13 +39,15 @@ def force_vjp(cfg: PMConfig, psi, s, u):
     for c in range(3):
         g_c = np.fft.irfftn(K[c] * dk, s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
         # direct part: d/dX_i of gather(g_c)(X_i), weighted by u_c
-        xbar += mesh.grad_gather(g_c, psi, cfg.n_p, n, cfg.order) * u[c]
+        if parts & 1:
+            xbar += mesh.grad_gather(g_c, psi, cfg.n_p, n, cfg.order) * u[c]
         # mesh part: gather^T = scatter of u_c, then the transposed multiplier
         gbar = mesh.deposit(psi, cfg.n_p, n, cfg.order, weights=u[c])
         dbar_k += np.conj(K[c]) * np.fft.rfftn(gbar.reshape(n, n, n))
     dbar = np.fft.irfftn(dbar_k, s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
     # delta = (n^3/N) m - 1, and m = scatter(1): scatter^T w.r.t. positions
-    xbar += mesh.grad_gather(dbar * (n ** 3 / N), psi, cfg.n_p, n, cfg.order)
+    if parts & 2:
+        xbar += mesh.grad_gather(dbar * (n ** 3 / N), psi, cfg.n_p, n, cfg.order)
     return xbar
 
 

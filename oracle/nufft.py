@@ -189,7 +189,7 @@ def _nufft_pieces(n_p, n_f, N, s, width, beta):
     return ix, mz, D
 
 
-def nufft_force_vjp(n_p, n_f, psi, s, v, width=6, beta=13.8):
+def nufft_force_vjp(n_p, n_f, psi, s, v, width=6, beta=13.8, parts=3):
     """J_A(Psi)^T v for the spreading NUFFT force of ``nufft_force``; v (3, N).
 
     A_c(u_i) = (1/n_p^3) sum_j c_c,j phi(u_i - j), c_c = G_c b, b = spread(u),
@@ -197,7 +197,8 @@ def nufft_force_vjp(n_p, n_f, psi, s, v, width=6, beta=13.8):
     interpolation differentiated w.r.t. the positions, and the transposed mesh
     path G_c^T = n_f^3 IDFT(pad(conj(D_c) restrict(DFT(.)))) applied to the
     spread of v_c / n_p^3, whose result is gathered with grad phi (the
-    spreading differentiated w.r.t. the positions)."""
+    spreading differentiated w.r.t. the positions).  parts: 1 the first
+    term only, 2 the second only, 3 both."""
     u = fine_coords(psi, n_p, n_f)
     N = u.shape[1]
     sig = n_f / n_p
@@ -212,7 +213,9 @@ def nufft_force_vjp(n_p, n_f, psi, s, v, width=6, beta=13.8):
         meshes.append(np.fft.irfftn(full, s=(n_f, n_f, n_f), axes=(0, 1, 2)).reshape(-1) * n_f ** 3)
     # direct part
     g = _interp_grad(np.stack(meshes, axis=1), u, n_f, width, beta) / n_p ** 3   # (N, 3, 3)
-    xbar = np.einsum("ci,icd->di", v, g)
+    xbar = np.einsum("ci,icd->di", v, g) if parts & 1 else np.zeros((3, N))
+    if not parts & 2:
+        return xbar * sig
     # mesh part
     acc = np.zeros((len(ix), len(ix), len(mz)), dtype=np.complex128)
     for c in range(3):

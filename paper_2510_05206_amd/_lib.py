@@ -61,6 +61,7 @@ EXPORTS = {
     "pm_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_deposit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "pm_force": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "pm_force_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_int32, C.c_void_p]),
     "pm_fft": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
 }
 

@@ -1,18 +1,19 @@
 // 3D real FFT for cubic power-of-two meshes, written for gfx950 (64-wide
 // waves, 160 KB LDS per CU).
 //
-// Layout: real mesh [n][n][n] (z fastest); half spectrum [n][n][n/2+1] of
-// float2 (modes m_x, m_y in FFT order, m_z = 0..n/2).  The forward transform
-// is sum_j f_j exp(-2 pi i m.j/n), the inverse sum_m F_m exp(+2 pi i m.j/n),
-// both unnormalised.  A 3D transform is three HBM passes:
+// Layout: real mesh [n][n][n] (z fastest); half spectrum [n][n][rs] of float2
+// (modes m_x, m_y in FFT order, m_z = 0..n/2, rows padded to rs >= n/2+1).
+// The forward transform is sum_j f_j exp(-2 pi i m.j/n), the inverse
+// sum_m F_m exp(+2 pi i m.j/n), both unnormalised.  A 3D transform is three
+// HBM passes:
 //   z rows   real <-> complex via a half-length complex FFT (the two real
-//            halves packed as one complex row), whole rows staged in LDS;
+//            halves packed as one complex row);
 //   y and x  strided complex passes over tiles of C consecutive z columns
-//            (C float2 = 128 B contiguous per row at C = 16), whole lines in
-//            LDS.
-// Each line FFT is a Stockham autosort radix-4 (plus one radix-2 stage when
-// log2 L is odd) entirely in LDS; twiddles come from one table
-// tw[t] = exp(-2 pi i t / Lmax) built in FP64 on the host.
+//            (C float2 = 128 B contiguous per row at C = 16).
+// Every line transform is held in registers with a four-step split and one
+// LDS exchange (fft_reg.h); only the column passes of meshes below n = 16
+// use the LDS Stockham radix-4/2 transform (lds_fft).  Twiddles come from one
+// table tw[t] = exp(-2 pi i t / Lmax) built in FP64 on the host.
 // The PM multiplier (Green's function, deconvolution, normalisation) is fused
 // into the x pass: forward x FFT, multiply, inverse x FFT, one HBM round trip
 // (Sec. "Force evaluation"; the Poisson solve in Fourier space).
@@ -113,136 +114,6 @@ __device__ __forceinline__ void lds_fft(float2* __restrict__ buf, const float2* 
       }
     }
     __syncthreads();
-  }
-}
-
-// ------------------------------------------------------------ row passes
-
-// Rows per block so that a tile holds about 4096 complex values.
-template <int L>
-constexpr int rows_per_block() { return L >= 512 ? 8 : (4096 / L > 64 ? 64 : 4096 / L); }
-
-// Real rows -> half-spectrum rows.  SRC selects the input conversion:
-//   SRC_I64:  rho = (double)m * scale - shift   (int64 fixed-point mass)
-//   SRC_F32:  f * (float)scale                   (float mesh)
-template <int L, int SRC>
-__global__ void __launch_bounds__(256) k_r2c_rows(const void* __restrict__ src, long long src_stride,
-                                                  float2* __restrict__ dst, long long dst_stride,
-                                                  int n_rows, const float2* __restrict__ tw,
-                                                  int tws_half, int tws_full, double scale,
-                                                  double shift, unsigned long long active, int rs) {
-  constexpr int R = rows_per_block<L>();
-  constexpr int n = 2 * L;
-  __shared__ float2 buf[R * (L + 1)];
-  const int slot = blockIdx.y;
-  if (!((active >> slot) & 1ull)) return;
-  const long long row0 = (long long)blockIdx.x * R;
-  float* fb = reinterpret_cast<float*>(buf);
-  for (int e = threadIdx.x; e < R * n; e += 256) {
-    int r = e / n, c = e - r * n;
-    long long row = row0 + r;
-    float v = 0.f;
-    if (row < n_rows) {
-      long long gi = slot * src_stride + row * n + c;
-      if constexpr (SRC == SRC_I64)
-        v = (float)((double)reinterpret_cast<const long long*>(src)[gi] * scale - shift);
-      else
-        v = reinterpret_cast<const float*>(src)[gi] * (float)scale;
-    }
-    fb[2 * (r * (L + 1)) + c] = v;
-  }
-  __syncthreads();
-  lds_fft<L, R, false, 256>(buf, tw, tws_half, false);
-  // unpack: X[k] = (Z[k] + conj Z[L-k])/2 + w^k (Z[k] - conj Z[L-k])/(2i), pairs in place
-  for (int e = threadIdx.x; e < R * (L / 2 + 1); e += 256) {
-    int r = e / (L / 2 + 1), k = e - r * (L / 2 + 1);
-    float2* row = buf + r * (L + 1);
-    int kk = (L - k) & (L - 1);
-    float2 zk = row[k], zm = row[kk];
-    float2 fe = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    float2 fo = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));  // (zk - conj zm)/(2i)
-    float2 w = tw[k * tws_full];
-    float2 wf = cmul(w, fo);
-    float2 xk = make_float2(fe.x + wf.x, fe.y + wf.y);
-    // the partner L-k uses conj symmetry: Fe(L-k) = conj Fe(k), Fo(L-k) = conj Fo(k)
-    float2 w2 = tw[(L - k) * tws_full];
-    float2 wf2 = cmul(w2, make_float2(fo.x, -fo.y));
-    float2 xm = make_float2(fe.x + wf2.x, -fe.y + wf2.y);
-    if (k == 0) {
-      row[0] = make_float2(zk.x + zk.y, 0.f);
-      row[L] = make_float2(zk.x - zk.y, 0.f);
-    } else {
-      row[k] = xk;
-      if (kk != k) row[kk] = xm;
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
-    int r = e / (L + 1), k = e - r * (L + 1);
-    long long row = row0 + r;
-    if (row < n_rows) dst[slot * dst_stride + row * rs + k] = buf[e];
-  }
-}
-
-// Half-spectrum rows -> real rows (unnormalised inverse: n x).  DST_F32
-// writes the real row scaled by `scale`; DST_IC writes psi = scale * x into
-// vel[c] and D0 * psi into disp[c] (Zel'dovich initial state).
-template <int L, int DST>
-__global__ void __launch_bounds__(256) k_c2r_rows(const float2* __restrict__ src, long long src_stride,
-                                                  float* __restrict__ dst, long long dst_stride,
-                                                  float* __restrict__ dst2, int n_rows,
-                                                  const float2* __restrict__ tw, int tws_half,
-                                                  int tws_full, float scale, float scale2,
-                                                  unsigned long long active, int rs) {
-  constexpr int R = rows_per_block<L>();
-  constexpr int n = 2 * L;
-  __shared__ float2 buf[R * (L + 1)];
-  const int slot = blockIdx.y;
-  if (!((active >> slot) & 1ull)) return;
-  const long long row0 = (long long)blockIdx.x * R;
-  for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
-    int r = e / (L + 1), k = e - r * (L + 1);
-    long long row = row0 + r;
-    buf[e] = row < n_rows ? src[slot * src_stride + row * rs + k] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  // pack: Z[k] = (X[k] + conj X[L-k]) + i e^{+2 pi i k/n} (X[k] - conj X[L-k])
-  for (int e = threadIdx.x; e < R * (L / 2 + 1); e += 256) {
-    int r = e / (L / 2 + 1), k = e - r * (L / 2 + 1);
-    float2* row = buf + r * (L + 1);
-    float2 xk = row[k], xm = row[L - k];
-    float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);   // X[k] + conj X[L-k]
-    float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);   // X[k] - conj X[L-k]
-    float2 w = tw[k * tws_full];
-    w.y = -w.y;                                          // e^{+2 pi i k / n}
-    float2 wd = cmul(w, d);
-    float2 zk = make_float2(a.x - wd.y, a.y + wd.x);     // a + i wd
-    // partner L-k: a' = conj a, d' = -conj d, w' = e^{+2 pi i (L-k)/n}
-    float2 w2 = tw[(L - k) * tws_full];
-    w2.y = -w2.y;
-    float2 wd2 = cmul(w2, make_float2(-d.x, d.y));
-    float2 zm = make_float2(a.x - wd2.y, -a.y + wd2.x);
-    // pairs (k, L-k) are disjoint across threads: read-then-write is race free
-    if (k < L) row[k] = zk;
-    if (L - k != k && L - k < L) row[L - k] = zm;
-  }
-  __syncthreads();
-  lds_fft<L, R, false, 256>(buf, tw, tws_half, true);
-  const float* fb = reinterpret_cast<const float*>(buf);
-  for (int e = threadIdx.x; e < R * n; e += 256) {
-    int r = e / n, c = e - r * n;
-    long long row = row0 + r;
-    if (row < n_rows) {
-      float v = fb[2 * (r * (L + 1)) + c];
-      long long gi = slot * dst_stride + row * n + c;
-      if constexpr (DST == DST_F32) {
-        dst[gi] = v * scale;
-      } else {
-        float psi = v * scale;
-        dst[gi] = psi;
-        dst2[gi] = psi * scale2;
-      }
-    }
   }
 }
 
@@ -360,7 +231,11 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
 // ------------------------------------------- row passes, register FFT
 
 // Real rows -> half-spectrum rows with the half-length complex transform held
-// in registers (fft_reg.h, RowShape); same conversions as k_r2c_rows.
+// in registers (fft_reg.h, RowShape).  SRC selects the input conversion:
+//   SRC_I64:  (double)m * scale - shift   (int64 fixed-point mass mesh)
+//   SRC_F32:  f * (float)scale            (float mesh)
+//   SRC_WIN:  the int64 tile-window sums of each cell, as SRC_I64 (or times
+//             the per-slot wscale)
 template <int L, int P, int SRC>
 __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ src, long long src_stride,
                                                       float2* __restrict__ dst, long long dst_stride,
@@ -443,7 +318,9 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
   }
 }
 
-// Half-spectrum rows -> real rows, register transform; as k_c2r_rows.
+// Half-spectrum rows -> real rows (unnormalised inverse), register
+// transform.  DST_F32 writes the real row scaled by `scale`; DST_IC writes
+// psi = scale * x into vel[c] and D0 * psi into disp[c] (Zel'dovich state).
 template <int L, int P, int DST>
 __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__ src, long long src_stride,
                                                       float* __restrict__ dst, long long dst_stride,
@@ -644,32 +521,6 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
 
 // ------------------------------------------------------------ dispatch
 
-template <int L>
-static hipError_t launch_rows(const RowLaunch& r) {
-  constexpr int R = rows_per_block<L>();
-  dim3 grid((unsigned)((r.n_rows + R - 1) / R), r.batch);
-  if (r.inverse) {
-    if (r.dst_mode == DST_F32)
-      k_c2r_rows<L, DST_F32><<<grid, 256, 0, r.stream>>>(
-          (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows,
-          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs);
-    else
-      k_c2r_rows<L, DST_IC><<<grid, 256, 0, r.stream>>>(
-          (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows,
-          r.tw, r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs);
-  } else {
-    if (r.src_mode == SRC_I64)
-      k_r2c_rows<L, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst,
-                                                         r.dst_stride, r.n_rows, r.tw, r.tws_half,
-                                                         r.tws_full, r.scale, r.shift, r.active, r.rs);
-    else
-      k_r2c_rows<L, SRC_F32><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst,
-                                                         r.dst_stride, r.n_rows, r.tw, r.tws_half,
-                                                         r.tws_full, r.scale, r.shift, r.active, r.rs);
-  }
-  return hipGetLastError();
-}
-
 template <int L, int P>
 static hipError_t launch_rows_reg(const RowLaunch& r) {
   constexpr int R = 256 / P;
@@ -701,22 +552,17 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
 }
 
 hipError_t fft_rows(const RowLaunch& r) {
-  // register transforms from n = 32 (half length 16): P threads per row with
-  // P <= L / P
+  // P threads per row with P <= L / P (L = n / 2)
   switch (r.n) {
+    case 4: return launch_rows_reg<2, 1>(r);
+    case 8: return launch_rows_reg<4, 2>(r);
+    case 16: return launch_rows_reg<8, 2>(r);
     case 32: return launch_rows_reg<16, 4>(r);
     case 64: return launch_rows_reg<32, 4>(r);
     case 128: return launch_rows_reg<64, 8>(r);
     case 256: return launch_rows_reg<128, 8>(r);
     case 512: return launch_rows_reg<256, 16>(r);
     case 1024: return launch_rows_reg<512, 16>(r);
-    default: break;
-  }
-  if (r.kz_lim || (!r.inverse && r.src_mode == SRC_WIN)) return hipErrorInvalidValue;  // register rows only
-  switch (r.n) {  // small meshes: LDS Stockham rows
-    case 4: return launch_rows<2>(r);
-    case 8: return launch_rows<4>(r);
-    case 16: return launch_rows<8>(r);
     default: return hipErrorInvalidValue;
   }
 }

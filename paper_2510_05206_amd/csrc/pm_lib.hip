@@ -966,12 +966,15 @@ static pm_status run_steps(pm_ctx* c) {
       const auto& T = c->slot_table[b];
       tp[b] = T[n].tau1;
       s[b] = T[n].s; al[b] = T[n].alpha; be[b] = T[n].beta;
-      tq[b] = T[n].tau2 + (n + 1 < c->slot_steps[b] ? T[n + 1].tau1 : 0.0);  // merged drifts
+      tq[b] = T[n].tau2;
       act |= 1ull << b;
     }
     act &= c->user_mask;
     if (!act) continue;
-    pm_status st = step_common(c, tp.data(), n == 0, s.data(), al.data(), be.data(), tq.data(), act);
+    // the same launches as pm_step(n): the first drift rides on the binning
+    // pass, the second on the gather-kick, so a run equals its steps bit for
+    // bit (and a slot served step by step equals a run)
+    pm_status st = step_common(c, tp.data(), true, s.data(), al.data(), be.data(), tq.data(), act);
     if (st) return st;
   }
   return PM_OK;
@@ -982,7 +985,8 @@ static pm_status run_steps(pm_ctx* c) {
 // the ES spreading of u (the transposed interpolation), R2C and the
 // transposed multiplier -i h_c summed over components; C2R of the sum; its
 // gradient gather (the transposed spreading) fused with the reverse drift
-pm_status nufft_adjoint_step(pm_ctx* c, int n, const double* s, unsigned long long act) {
+pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, const double* beta,
+                             const double* tau, unsigned long long act, int parts) {
   const int B = c->cfg.batch, ng = c->cfg.n_g;
   const long long N = c->g.N, M = c->g.M;
   TileArgs k = tile_args(c, c->disp, act);
@@ -990,12 +994,13 @@ pm_status nufft_adjoint_step(pm_ctx* c, int n, const double* s, unsigned long lo
   k.comp_stride = M;
   k.es_tab = c->d_es_tab;
   for (int b = 0; b < B; ++b) {
-    if (!((act >> b) & 1)) continue;
-    const StepCoef& sc = c->slot_table[b][n];
-    k.alpha[b] = (float)sc.alpha;
-    k.beta[b] = (float)sc.beta;
+    k.alpha[b] = (float)alpha[b];
+    k.beta[b] = (float)beta[b];
   }
   KLAUNCH(c, PM_K_ADJ_KICK, launch_tile_es(k, TK_ES_ADJ_KICK, c->stream));
+  if (!(parts & 1))
+    KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
+  if (!(parts & 2)) return PM_OK;
   // every node sum of u_c phi is bounded by N max|u| (phi <= 1)
   KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale, (double)N, B,
                                             c->stream));
@@ -1064,11 +1069,64 @@ pm_status nufft_adjoint_step(pm_ctx* c, int n, const double* s, unsigned long lo
   dr.es_tab = c->d_es_tab;
   for (int b = 0; b < B; ++b) {
     dr.coef[b] = 1.f;
-    if (!((act >> b) & 1)) continue;
-    const auto& T = c->slot_table[b];
-    dr.tau[b] = (float)(T[n].tau1 + (n > 0 ? T[n - 1].tau2 : 0.0));
+    dr.tau[b] = (float)tau[b];
   }
   KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile_es(dr, TK_ES_ADJ_DRIFT, c->stream));
+  return PM_OK;
+}
+
+// One reverse step after the force of X^{n+1/2} was rebuilt (particles binned):
+// reverse kick V = (V - beta A)/alpha with the direct X_bar term, V_bar =
+// alpha V_bar, u = beta V_bar; the mesh path of the force VJP; the
+// scatter-w.r.t.-positions term with the reverse drift by tau.  parts: bit 0
+// keeps the direct term, bit 1 runs the mesh path (the force-VJP test hook
+// separates them; the adjoint uses both).
+pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, const double* beta,
+                             const double* tau, unsigned long long act, int parts) {
+  KLAUNCH(c, PM_K_FILL, launch_fill(c->umax, (long long)sizeof(float) * kMaxBatch, c->stream));
+  if (c->cfg.force == PM_FORCE_NUFFT) return nufft_adjoint_step(c, s, alpha, beta, tau, act, parts);
+  const int B = c->cfg.batch;
+  const long long N = c->g.N, M = c->g.M;
+  const double mfac = (double)M / (double)N;
+  const int ord = c->cfg.grad_order, mak = c->cfg.mak;
+  // sum |c_s| of the FD stencil: bounds the transposed gather per unit |u|
+  const double fd_l1 = ord == 2 ? 1.0 : (ord == 4 ? 1.5 : 110.0 / 60.0);
+  TileArgs k = tile_args(c, c->disp, act);
+  k.mesh_in = c->phi;
+  for (int b = 0; b < B; ++b) {
+    k.alpha[b] = (float)alpha[b];
+    k.beta[b] = (float)beta[b];
+  }
+  KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(k, TK_ADJ_KICK, mak, ord, c->stream));
+  if (!(parts & 1))
+    KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
+  if (!(parts & 2)) return PM_OK;
+  // mesh cotangent of the force: transposed FD gather in fixed point
+  KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
+                                            3.0 * fd_l1 * (double)N, B, c->stream));
+  // transposed multiplier (H is real and even)
+  pm_status st;
+  if (fuse_windows(c)) {
+    KLAUNCH(c, PM_K_DIPOLE, launch_tile(k, TK_DIPOLE, mak, ord, c->stream));
+    const RowWin w = row_win(c, dipole_halo(ord), c->inv_scale);
+    st = r2c_mesh(c, c->scratch, SRC_WIN, 0, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act, 0, &w);
+  } else {
+    float* d = reinterpret_cast<float*>(c->mesh);
+    AssembleArgs as = assemble_args(c, dipole_halo(ord), d, act);
+    KLAUNCH(c, PM_K_DIPOLE,
+            both(launch_tile(k, TK_DIPOLE, mak, ord, c->stream), launch_assemble(as, true, c->stream)));
+    st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
+  }
+  if (st) return st;
+  st = poisson_to_real(c, s, c->phi, act);
+  if (st) return st;
+  TileArgs dr = tile_args(c, c->disp, act);
+  dr.mesh_in = c->phi;
+  for (int b = 0; b < B; ++b) {
+    dr.coef[b] = (float)mfac;
+    dr.tau[b] = (float)tau[b];
+  }
+  KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile(dr, TK_ADJ_DRIFT, mak, ord, c->stream));
   return PM_OK;
 }
 
@@ -1095,9 +1153,6 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
     lv.tau[b] = (float)c->slot_table[b][c->slot_steps[b] - 1].tau2;
   }
   KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile(lv, TK_ADJ_DRIFT, 2, c->cfg.grad_order, c->stream));
-  // sum |c_s| of the FD stencil: bounds the transposed gather per unit |u|
-  const double fd_l1 = c->cfg.grad_order == 2 ? 1.0 : (c->cfg.grad_order == 4 ? 1.5 : 110.0 / 60.0);
-  const int ord = c->cfg.grad_order, mak = c->cfg.mak;
   for (int n = nmax - 1; n >= 0; --n) {
     std::vector<double> s(B, 1);
     unsigned long long act = 0;
@@ -1108,48 +1163,16 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
     // force at X^{n+1/2} (bins the particles by tile for the kernels below)
     pm_status st = potential(c, c->disp, nullptr, nullptr, s.data(), act);
     if (st) return st;
-    KLAUNCH(c, PM_K_FILL, launch_fill(c->umax, (long long)sizeof(float) * kMaxBatch, c->stream));
-    if (c->cfg.force == PM_FORCE_NUFFT) {
-      st = nufft_adjoint_step(c, n, s.data(), act);
-      if (st) return st;
-      continue;
-    }
-    TileArgs k = tile_args(c, c->disp, act);
-    k.mesh_in = c->phi;
+    std::vector<double> al(B, 1), be(B, 0), tau(B, 0);
     for (int b = 0; b < B; ++b) {
-      if (!((act >> b) & 1)) continue;
-      const StepCoef& sc = c->slot_table[b][n];
-      k.alpha[b] = (float)sc.alpha;
-      k.beta[b] = (float)sc.beta;
-    }
-    KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(k, TK_ADJ_KICK, mak, ord, c->stream));
-    // mesh cotangent of the force: transposed FD gather in fixed point
-    KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
-                                              3.0 * fd_l1 * (double)N, B, c->stream));
-    // transposed multiplier (H is real and even)
-    if (fuse_windows(c)) {
-      KLAUNCH(c, PM_K_DIPOLE, launch_tile(k, TK_DIPOLE, mak, ord, c->stream));
-      const RowWin w = row_win(c, dipole_halo(ord), c->inv_scale);
-      st = r2c_mesh(c, c->scratch, SRC_WIN, 0, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act, 0, &w);
-    } else {
-      float* d = reinterpret_cast<float*>(c->mesh);
-      AssembleArgs as = assemble_args(c, dipole_halo(ord), d, act);
-      KLAUNCH(c, PM_K_DIPOLE,
-              both(launch_tile(k, TK_DIPOLE, mak, ord, c->stream), launch_assemble(as, true, c->stream)));
-      st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
-    }
-    if (st) return st;
-    st = poisson_to_real(c, s.data(), c->phi, act);
-    if (st) return st;
-    TileArgs dr = tile_args(c, c->disp, act);
-    dr.mesh_in = c->phi;
-    for (int b = 0; b < B; ++b) {
-      dr.coef[b] = (float)mfac;
       if (!((act >> b) & 1)) continue;
       const auto& T = c->slot_table[b];
-      dr.tau[b] = (float)(T[n].tau1 + (n > 0 ? T[n - 1].tau2 : 0.0));
+      al[b] = T[n].alpha;
+      be[b] = T[n].beta;
+      tau[b] = T[n].tau1 + (n > 0 ? T[n - 1].tau2 : 0.0);
     }
-    KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile(dr, TK_ADJ_DRIFT, mak, ord, c->stream));
+    st = reverse_force_step(c, s.data(), al.data(), be.data(), tau.data(), act, 3);
+    if (st) return st;
   }
   // initial conditions: psi_bar = D0 X_bar + V_bar, w_bar = sum_c T_c^T psi_bar_c
   std::vector<float> d0(B, (float)c->D0);
@@ -1290,6 +1313,30 @@ pm_status pm_force(pm_ctx* c, const float* disp, double s, float* acc_out) {
   pm_status st = potential(c, x, nullptr, nullptr, sv.data(), act);
   if (st) return st;
   return kick(c, x, nullptr, nullptr, nullptr, acc_out, act);
+}
+
+pm_status pm_force_vjp(pm_ctx* c, const float* disp, double s, const float* u, int32_t parts, float* xbar_out) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
+  if (!disp || !u || !xbar_out || parts < 1 || parts > 3) return PM_EINVAL;
+  const int B = c->cfg.batch;
+  const long long N = c->g.N;
+  const size_t bytes = sizeof(float) * 3 * N * B;
+  const unsigned long long act = all_mask(B);
+  HIPCHK(c, hipMemcpyAsync(c->disp, disp, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->vbar, u, bytes, hipMemcpyDeviceToDevice, c->stream));
+  KLAUNCH(c, PM_K_FILL, launch_fill(c->vel, (long long)bytes, c->stream));
+  KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)bytes, c->stream));
+  std::vector<double> sv(B, s), one(B, 1.0), zero(B, 0.0);
+  pm_status st = potential(c, c->disp, nullptr, nullptr, sv.data(), act);
+  if (st) return st;
+  // alpha = beta = 1, tau = 0: X_bar = J_A^T u, the drift is the identity
+  st = reverse_force_step(c, sv.data(), one.data(), one.data(), zero.data(), act, parts);
+  if (st) return st;
+  HIPCHK(c, hipMemcpyAsync(xbar_out, c->xbar, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->ics_done = true;
+  c->ran = false;
+  return PM_OK;
 }
 
 pm_status pm_fft(pm_ctx* c, const void* in, void* out, int32_t inverse) {

@@ -166,6 +166,15 @@ class PMSim:
         self._call("pm_force", _ptr(x), float(s), _ptr(a))
         return a
 
+    def force_vjp(self, disp, s, u, parts=3):
+        """J_A(disp)^T u of the force (parts: 1 direct, 2 through the mesh, 3 both)."""
+        B, N = self.cfg.batch, self.cfg.N
+        x = disp.to(self.device, torch.float32).contiguous().reshape(B, 3, N)
+        uu = u.to(self.device, torch.float32).contiguous().reshape(B, 3, N)
+        out = self._new(B, 3, N)
+        self._call("pm_force_vjp", _ptr(x), float(s), _ptr(uu), int(parts), _ptr(out))
+        return out
+
     def fft(self, x, inverse=False):
         B, n = self.cfg.batch, self.cfg.n_g
         if not inverse:

@@ -139,3 +139,34 @@ def test_memory_is_flat_in_steps():
         peaks.append(torch.cuda.max_memory_allocated())
         del sim
     assert peaks[0] == peaks[1]
+
+
+@pytest.mark.parametrize("parts", [1, 2, 3])
+@pytest.mark.parametrize("mak,dec,g", [(2, False, 4), (3, True, 4)])
+def test_pm_force_vjp_matches_oracle(mak, dec, g, parts):
+    """J_A^T u of the PM force on identical positions, each term separately
+    (App. "Custom VJP and JVP")."""
+    d = dict(synth.C1, mak=mak, deconvolve=dec, grad_order=g)
+    sim = make_sim(d)
+    psi = synth.displacements(32, 21, 1.5)
+    u = synth.displacements(32, 22, 1.0)
+    a = sim.force_vjp(torch.from_numpy(psi), 2.0, torch.from_numpy(u), parts).cpu().numpy()[0]
+    prob = synth.oracle_problem(d)
+    ref = oadj.force_vjp(prob.pm, psi.astype(np.float64), 2.0, u.astype(np.float64), parts)
+    err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    say(f"PM force VJP mak {mak} parts {parts}: rel L2 {err:.2e}")
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("parts", [1, 2, 3])
+def test_nufft_force_vjp_matches_oracle(parts):
+    from oracle import nufft as onufft
+    d = dict(synth.C3_SMALL, n_p=16, n_g=32, box=31.25)
+    sim = make_sim(d)
+    psi = synth.displacements(16, 23, 1.2)
+    u = synth.displacements(16, 24, 1.0)
+    a = sim.force_vjp(torch.from_numpy(psi), 2.0, torch.from_numpy(u), parts).cpu().numpy()[0]
+    ref = onufft.nufft_force_vjp(16, 32, psi.astype(np.float64), 2.0, u.astype(np.float64), 6, 13.8, parts)
+    err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    say(f"NUFFT force VJP parts {parts}: rel L2 {err:.2e}")
+    assert err < 1e-4

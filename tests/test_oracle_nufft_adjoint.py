@@ -77,3 +77,18 @@ def test_nufft_gradient_matches_fd_of_the_loss():
     eps = 1e-5
     fd = (loss(w + eps * dw) - loss(w - eps * dw)) / (2 * eps)
     assert abs(fd / np.dot(wb.reshape(-1), dw.reshape(-1)) - 1) < 1e-7
+
+
+def test_vjp_parts_add_up():
+    """The direct and mesh terms of both force VJPs sum to the whole VJP."""
+    from oracle import adjoint as oadj
+    from oracle.force import PMConfig
+    rng = np.random.default_rng(8)
+    psi, v = rng.normal(0, 0.6, (3, 64)), rng.normal(size=(3, 64))
+    whole = nufft.nufft_force_vjp(4, 8, psi, 1.1, v)
+    split = nufft.nufft_force_vjp(4, 8, psi, 1.1, v, parts=1) + nufft.nufft_force_vjp(4, 8, psi, 1.1, v, parts=2)
+    assert np.allclose(whole, split, rtol=1e-12, atol=1e-14)
+    cfg = PMConfig(4, 8, 10.0, order=3, deconvolve=True, grad_order=4, lap_order=0)
+    whole = oadj.force_vjp(cfg, psi, 1.1, v)
+    split = oadj.force_vjp(cfg, psi, 1.1, v, parts=1) + oadj.force_vjp(cfg, psi, 1.1, v, parts=2)
+    assert np.allclose(whole, split, rtol=1e-12, atol=1e-14)
