@@ -202,12 +202,28 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
   const int L = a.g.log2_ng, nm = a.g.n_g - 1;
   const int T = a.T, R = a.R, W = T + 2 * R;
   const int ntm = (1 << a.log2nt) - 1;
-  const WinCover cx = win_cover((int)(e >> (2 * L)), T, R, a.log2T, ntm);
-  const WinCover cy = win_cover((int)((e >> L) & nm), T, R, a.log2T, ntm);
-  const WinCover cz = win_cover((int)(e & nm), T, R, a.log2T, ntm);
+  const int x = (int)(e >> (2 * L)), y = (int)((e >> L) & nm), z = (int)(e & nm);
   const long long W3 = (long long)W * W * W;
   const long long* slab = reinterpret_cast<const long long*>(a.scratch) + (long long)slot * a.n_tiles * W3;
-  const long long acc = win_sum(slab, cx, cy, cz, W, a.log2nt);
+  long long acc = 0;
+  if (2 * R < T) {  // at most two windows per axis: scalar covers
+    const Cover2 c[3] = {cover2(x, T, R, a.log2T, ntm), cover2(y, T, R, a.log2T, ntm), cover2(z, T, R, a.log2T, ntm)};
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          if ((p && !c[0].two) || (q && !c[1].two) || (r && !c[2].two)) continue;
+          const long long t = ((long long)(p ? c[0].t1 : c[0].t0) << (2 * a.log2nt)) |
+                              ((long long)(q ? c[1].t1 : c[1].t0) << a.log2nt) | (r ? c[2].t1 : c[2].t0);
+          acc += slab[t * W3 + ((long long)(p ? c[0].l1 : c[0].l0) * W + (q ? c[1].l1 : c[1].l0)) * W +
+                      (r ? c[2].l1 : c[2].l0)];
+        }
+  } else {  // small meshes (one or two tiles per axis, wide halo)
+    acc = win_sum(slab, win_cover(x, T, R, a.log2T, ntm), win_cover(y, T, R, a.log2T, ntm),
+                  win_cover(z, T, R, a.log2T, ntm), W, a.log2nt);
+  }
   if constexpr (OUT_F32)
     reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = (float)((double)acc * a.inv_scale[slot]);
   else
@@ -552,27 +568,32 @@ __device__ __forceinline__ int es_weights(long long U, const int32_t* tab, int w
   return (int)h;
 }
 
-// float weights of the 6 nodes and d/du phi(u - node): the slope of the
-// table's linear interpolation (the derivative of the weights used above)
-__device__ __forceinline__ int es_weights_d(long long U, const int32_t* __restrict__ tab, float w[kEsW],
-                                            float dw[kEsW]) {
+// float weights of the 6 nodes (the table values used by the spreading) and
+// d/du phi(u - node) from the kernel's closed form: with z = dist / 3 cells,
+// d phi / d dist = -phi beta z / (3 sqrt(1 - z^2)); 1 - z = (3 - dist) / 3 is
+// formed from the integer distance, so the edge of the support stays exact
+__device__ __forceinline__ int es_weights_d(long long U, const int32_t* __restrict__ tab, float beta,
+                                            float w[kEsW], float dw[kEsW]) {
   constexpr float inv = 1.0f / (float)(1 << kWeightBits);
-  constexpr float slope = (float)(1 << (kFracBits - kEsShift)) * inv;  // 4096 samples per cell
+  constexpr long long kHalf = (long long)(kEsW / 2) << kFracBits;          // 3 cells
+  constexpr float kInvHalf = 1.0f / (float)((long long)(kEsW / 2) << kFracBits);
   const long long h = U >> kFracBits;
 #pragma unroll
   for (int o = 0; o < kEsW; ++o) {
     long long d = ((h - 2 + o) << kFracBits) - U;  // node - u
     long long dist = d < 0 ? -d : d;
-    if (dist >= (long long)(kEsW / 2) << kFracBits) {
+    if (dist >= kHalf) {
       w[o] = 0.f;
       dw[o] = 0.f;
       continue;
     }
     int i = (int)(dist >> kEsShift), f = (int)(dist & ((1 << kEsShift) - 1));
     int t0 = tab[i], t1 = tab[i + 1];
-    w[o] = (float)(t0 + (((t1 - t0) * f + (1 << (kEsShift - 1))) >> kEsShift)) * inv;
-    const float sl = (float)(t1 - t0) * slope;  // d phi / d dist
-    dw[o] = d < 0 ? sl : -sl;                   // d dist / du = sign(u - node)
+    const float phi = (float)(t0 + (((t1 - t0) * f + (1 << (kEsShift - 1))) >> kEsShift)) * inv;
+    w[o] = phi;
+    const float z = (float)dist * kInvHalf, omz = (float)(kHalf - dist) * kInvHalf;
+    const float dphi = -phi * beta * z / ((float)(kEsW / 2) * sqrtf(omz * (1.f + z)));
+    dw[o] = d < 0 ? dphi : -dphi;  // d dist / du = sign(u - node)
   }
   return (int)h;
 }
@@ -716,7 +737,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
-      int h = es_weights_d(U, a.es_tab, w[c], dw[c]) & nm;
+      int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
       l0[c] = h - o[c] + kEsR - 2;
     }
     float A[3] = {0.f, 0.f, 0.f}, dA[3][3] = {};
@@ -838,7 +859,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
-      int h = es_weights_d(U, a.es_tab, w[c], dw[c]) & nm;
+      int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
       l0[c] = h - o[c] + kEsR - 2;
     }
     float gx = 0.f, gy = 0.f, gz = 0.f;

@@ -250,15 +250,29 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
   const int n1 = S::lane_n1(threadIdx.x), c = S::lane_c(threadIdx.x);
   const long long row = (long long)blockIdx.x * S::R + c;
   const bool valid = row < n_rows;
-  [[maybe_unused]] WinCover cx{}, cy{};
+  // SRC_WIN (T > 2R): the up to 2 x 2 windows covering this row's (x, y),
+  // as base offsets with a validity flag each
+  [[maybe_unused]] long long bxy[4] = {0, 0, 0, 0};
+  [[maybe_unused]] bool vxy[4] = {false, false, false, false};
   [[maybe_unused]] const long long* slab = nullptr;
   [[maybe_unused]] double wsc = scale, wsh = shift;
+  [[maybe_unused]] long long W3 = 0;
   if constexpr (SRC == SRC_WIN) {
-    const int ntm = (1 << win.log2nt) - 1;
-    cx = win_cover((int)(row / n), win.T, win.R, win.log2T, ntm);
-    cy = win_cover((int)(row % n), win.T, win.R, win.log2T, ntm);
-    const long long W = win.T + 2 * win.R;
-    slab = reinterpret_cast<const long long*>(src) + (long long)slot * win.n_tiles * W * W * W;
+    const int ntm = (1 << win.log2nt) - 1, W = win.T + 2 * win.R;
+    W3 = (long long)W * W * W;
+    const Cover2 cx = cover2((int)(row / n), win.T, win.R, win.log2T, ntm);
+    const Cover2 cy = cover2((int)(row % n), win.T, win.R, win.log2T, ntm);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int tx = p ? cx.t1 : cx.t0, lx = p ? cx.l1 : cx.l0;
+        const int ty = q ? cy.t1 : cy.t0, ly = q ? cy.l1 : cy.l0;
+        bxy[2 * p + q] = (((long long)tx << (2 * win.log2nt)) | ((long long)ty << win.log2nt)) * W3 +
+                         ((long long)lx * W + ly) * W;
+        vxy[2 * p + q] = (p == 0 || cx.two) && (q == 0 || cy.two);
+      }
+    slab = reinterpret_cast<const long long*>(src) + (long long)slot * win.n_tiles * W3;
     if (win.wscale) {
       wsc = win.wscale[slot];
       wsh = 0.0;
@@ -272,10 +286,20 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
     if (valid) {
       const long long gi = slot * src_stride + row * n + 2 * t;
       if constexpr (SRC == SRC_WIN) {
-        const int ntm = (1 << win.log2nt) - 1, W = win.T + 2 * win.R;
-        const long long m0 = win_sum(slab, cx, cy, win_cover(2 * t, win.T, win.R, win.log2T, ntm), W, win.log2nt);
-        const long long m1 = win_sum(slab, cx, cy, win_cover(2 * t + 1, win.T, win.R, win.log2T, ntm), W, win.log2nt);
-        z = make_float2((float)((double)m0 * wsc - wsh), (float)((double)m1 * wsc - wsh));
+        const int ntm = (1 << win.log2nt) - 1;
+        long long m[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const Cover2 cz = cover2(2 * t + h, win.T, win.R, win.log2T, ntm);
+          const long long z0 = cz.t0 * W3 + cz.l0, z1 = cz.t1 * W3 + cz.l1;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (!vxy[k]) continue;
+            m[h] += slab[bxy[k] + z0];
+            if (cz.two) m[h] += slab[bxy[k] + z1];
+          }
+        }
+        z = make_float2((float)((double)m[0] * wsc - wsh), (float)((double)m[1] * wsc - wsh));
       } else if constexpr (SRC == SRC_I64) {
         const longlong2 m = *reinterpret_cast<const longlong2*>(reinterpret_cast<const long long*>(src) + gi);
         z = make_float2((float)((double)m.x * scale - shift), (float)((double)m.y * scale - shift));
@@ -477,16 +501,20 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
       for (int r = 0; r < S::E; ++r) {
         const int t = S::t_out(n1, r);
         float h = 0.f;
+        bool kept_mode = false;
         if (valid) {
           float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
           int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
           float th2 = 0.f;
 #pragma unroll
           for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
-          h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
+          kept_mode = dec != 0.f;
+          h = (!kept_mode || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
         }
         float2 y = make_float2(h * v[r].y, -h * v[r].x);  // -i h v
-        if (valid && a.comp > 0 && h != 0.f) {  // the sum is zero off the kept modes
+        // running sum over components on every kept mode (this component's
+        // multiplier vanishes on its own zero plane, the others' need not)
+        if (kept_mode && a.comp > 0) {
           float2 acc = a.dst3[col + t * stride_t];
           y.x += acc.x;
           y.y += acc.y;

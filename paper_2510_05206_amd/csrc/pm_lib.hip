@@ -427,6 +427,7 @@ TileArgs tile_args(pm_ctx* c, float* disp, unsigned long long active) {
   t.u_sorted = c->u_sorted;
   t.umax = c->umax;
   t.scale = c->scale;
+  t.es_beta = (float)c->cfg.es_beta;
   return t;
 }
 

@@ -38,4 +38,22 @@ __device__ __forceinline__ long long win_sum(const long long* __restrict__ slab,
   return acc;
 }
 
+// the same cover when T > 2R: the own tile and at most one neighbour, in
+// scalars (no dynamically indexed arrays, so nothing spills to scratch)
+struct Cover2 {
+  int t0, l0, t1, l1;
+  bool two;
+};
+
+__device__ __forceinline__ Cover2 cover2(int x, int T, int R, int log2T, int ntm) {
+  Cover2 c;
+  const int tc = x >> log2T, l = x & (T - 1);
+  c.t0 = tc;
+  c.l0 = l + R;
+  c.two = l < R || l >= T - R;
+  c.t1 = (l < R ? tc - 1 : tc + 1) & ntm;
+  c.l1 = l < R ? l + T + R : l - T + R;
+  return c;
+}
+
 }  // namespace pm
