@@ -183,7 +183,7 @@ def serve_bench(n_requests, budget_gb):
     # the same request alone and in the mix gives the same bits
     a = {r.rid: r for r in seq}
     same = all((np.array_equal(r.pk, a[r.rid].pk) if r.kind == "pk"
-                else (r.dsigma8 == a[r.rid].dsigma8 and r.dw_norm == a[r.rid].dw_norm)) for r in bat)
+                else (r.dsigma8 == a[r.rid].dsigma8 and r.dw_bits == a[r.rid].dw_bits)) for r in bat)
     # saturation: the whole trace at once
     burst = serve.make_trace(n_requests, rate=0.0, seed=2001)
     bb, st_b = serve.serve_batched(burst, hbm_budget_gb=budget_gb, targets=targets)

@@ -54,6 +54,7 @@ class Result:
     pk: np.ndarray | None = None
     dsigma8: float | None = None
     dw_norm: float | None = None
+    dw_bits: int | None = None       # sum of the FP32 bit patterns of dL/dw (order-free, exact)
     batch: int = 1
 
     @property
@@ -216,21 +217,22 @@ class _GradBucket:
             g = 2.0 * (delta - self.target.unsqueeze(0))
             dw, ds = self.sim.adjoint(g)
             dwn = dw.double().norm(dim=1)
+            dwb = dw.view(torch.int32).long().sum(dim=1)
             self.sim.set_active(None)
             ev = torch.cuda.Event()
             ev.record(self.stream)
         self.occupancy.append(len(reqs) / self.B)
-        self.inflight = (ev, reqs, ds, dwn)
+        self.inflight = (ev, reqs, ds, dwn, dwb)
 
     def collect(self, now_fn, results):
         if self.inflight is None or not self.inflight[0].query():
             return
-        _, reqs, ds, dwn = self.inflight
-        ds, dwn = ds.cpu().numpy(), dwn.cpu().numpy()
+        _, reqs, ds, dwn, dwb = self.inflight
+        ds, dwn, dwb = ds.cpu().numpy(), dwn.cpu().numpy(), dwb.cpu().numpy()
         t = now_fn()
         for b, r in enumerate(reqs):
             results.append(Result(r.rid, "grad", r.arrival, t, dsigma8=float(ds[b]), dw_norm=float(dwn[b]),
-                                  batch=self.B))
+                                  dw_bits=int(dwb[b]), batch=self.B))
         self.inflight = None
 
 
@@ -326,7 +328,9 @@ def serve_sequential(requests, targets=None):
             delta = sim.density()
             dw, ds = sim.adjoint(2.0 * (delta - targets.get(r.n_p).unsqueeze(0)))
             dwn = float(dw.double().norm())
-            results.append(Result(r.rid, "grad", r.arrival, now(), dsigma8=float(ds.cpu()[0]), dw_norm=dwn))
+            dwb = int(dw.view(torch.int32).long().sum())
+            results.append(Result(r.rid, "grad", r.arrival, now(), dsigma8=float(ds.cpu()[0]), dw_norm=dwn,
+                                  dw_bits=dwb))
         service.append(now() - s)
     return results, {"makespan_s": now(), "mean_service_s": float(np.mean(service))}
 
