@@ -186,9 +186,8 @@ __global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
       }
   }
   __syncthreads();
-  unsigned long long* out = reinterpret_cast<unsigned long long*>(a.scratch) +
-                            ((long long)slot * a.n_tiles + t) * W3;
-  for (int e = threadIdx.x; e < W3; e += 256) out[e] = win[e];
+  store_window(win, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
+               a.log2nt);
 }
 
 // Sum the windows covering each cell (windows.h).  OUT_F32 converts the
@@ -215,14 +214,13 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
           if ((p && !c[0].two) || (q && !c[1].two) || (r && !c[2].two)) continue;
-          const long long t = ((long long)(p ? c[0].t1 : c[0].t0) << (2 * a.log2nt)) |
-                              ((long long)(q ? c[1].t1 : c[1].t0) << a.log2nt) | (r ? c[2].t1 : c[2].t0);
-          acc += slab[t * W3 + ((long long)(p ? c[0].l1 : c[0].l0) * W + (q ? c[1].l1 : c[1].l0)) * W +
+          acc += slab[slab_row(p ? c[0].t1 : c[0].t0, q ? c[1].t1 : c[1].t0, r ? c[2].t1 : c[2].t0,
+                               p ? c[0].l1 : c[0].l0, q ? c[1].l1 : c[1].l0, W, 1 << a.log2nt) +
                       (r ? c[2].l1 : c[2].l0)];
         }
   } else {  // small meshes (one or two tiles per axis, wide halo)
     acc = win_sum(slab, win_cover(x, T, R, a.log2T, ntm), win_cover(y, T, R, a.log2T, ntm),
-                  win_cover(z, T, R, a.log2T, ntm), W, a.log2nt);
+                  win_cover(z, T, R, a.log2T, ntm), W, 1 << a.log2nt);
   }
   if constexpr (OUT_F32)
     reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = (float)((double)acc * a.inv_scale[slot]);
@@ -233,13 +231,33 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
 // ----------------------------------------------------- windowed gathers
 
 // stage mesh values over the tile + R cells each side into LDS
+// Rows of W <= 32 consecutive z values: 8 groups of 32 lanes take rows
+// (lx, ly) in turn, each lane one z; 8 rows per group are loaded before any
+// is stored, so every thread keeps 8 HBM reads in flight.
 __device__ __forceinline__ void load_window(float* win, const float* mesh, const int o[3], int T, int R,
                                             int L, int nm) {
-  const int W = T + 2 * R, W3 = W * W * W;
-  for (int e = threadIdx.x; e < W3; e += 256) {
-    int lz = e % W, r = e / W, ly = r % W, lx = r / W;
-    int gx = (o[0] - R + lx) & nm, gy = (o[1] - R + ly) & nm, gz = (o[2] - R + lz) & nm;
-    win[e] = mesh[((long long)((gx << L) + gy) << L) + gz];
+  constexpr int U = 8;
+  const int W = T + 2 * R, W2 = W * W;
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const bool zok = lane < W;
+  const long long gz = (o[2] - R + lane) & nm;
+  for (int r0 = grp; r0 < W2; r0 += 8 * U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + 8 * u;
+      v[u] = 0.f;
+      if (zok && r < W2) {
+        const int lx = r / W, ly = r - lx * W;
+        const int gx = (o[0] - R + lx) & nm, gy = (o[1] - R + ly) & nm;
+        v[u] = mesh[((long long)((gx << L) + gy) << L) + gz];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + 8 * u;
+      if (zok && r < W2) win[r * W + lane] = v[u];
+    }
   }
 }
 
@@ -420,8 +438,8 @@ __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
     }
   }
   __syncthreads();
-  unsigned long long* out = reinterpret_cast<unsigned long long*>(a.scratch) + ((long long)slot * a.n_tiles + t) * W3;
-  for (int e = threadIdx.x; e < W3; e += 256) out[e] = dwin[e];
+  store_window(dwin, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
+               a.log2nt);
 }
 
 // scatter-w.r.t.-positions: X_bar += coef r sum_j rho_bar_j dW_j/du, then the
@@ -637,8 +655,8 @@ __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
       }
   }
   __syncthreads();
-  unsigned long long* out = reinterpret_cast<unsigned long long*>(a.scratch) + ((long long)slot * a.n_tiles + t) * W3;
-  for (int e = threadIdx.x; e < W3; e += 256) out[e] = ewin[e];
+  store_window(ewin, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
+               a.log2nt);
 }
 
 // A_c = sum_j g_c(j) phi(u - j) from the three force meshes, then the kick
@@ -829,8 +847,8 @@ __global__ void __launch_bounds__(256) k_tile_es_dipole(TileArgs a) {
       }
   }
   __syncthreads();
-  unsigned long long* out = reinterpret_cast<unsigned long long*>(a.scratch) + ((long long)slot * a.n_tiles + t) * W3;
-  for (int e = threadIdx.x; e < W3; e += 256) out[e] = ewin[e];
+  store_window(ewin, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
+               a.log2nt);
 }
 
 // X_bar += coef r sum_j b_bar_j d/du phi(u - j) (the spreading differentiated

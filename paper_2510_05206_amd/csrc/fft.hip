@@ -268,8 +268,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
       for (int q = 0; q < 2; ++q) {
         const int tx = p ? cx.t1 : cx.t0, lx = p ? cx.l1 : cx.l0;
         const int ty = q ? cy.t1 : cy.t0, ly = q ? cy.l1 : cy.l0;
-        bxy[2 * p + q] = (((long long)tx << (2 * win.log2nt)) | ((long long)ty << win.log2nt)) * W3 +
-                         ((long long)lx * W + ly) * W;
+        bxy[2 * p + q] = slab_row(tx, ty, 0, lx, ly, W, 1 << win.log2nt);  // the row's run over all tz
         vxy[2 * p + q] = (p == 0 || cx.two) && (q == 0 || cy.two);
       }
     slab = reinterpret_cast<const long long*>(src) + (long long)slot * win.n_tiles * W3;
@@ -291,7 +290,8 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const Cover2 cz = cover2(2 * t + h, win.T, win.R, win.log2T, ntm);
-          const long long z0 = cz.t0 * W3 + cz.l0, z1 = cz.t1 * W3 + cz.l1;
+          const int W = win.T + 2 * win.R;
+          const long long z0 = cz.t0 * W + cz.l0, z1 = cz.t1 * W + cz.l1;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             if (!vxy[k]) continue;

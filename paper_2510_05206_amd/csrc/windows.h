@@ -1,9 +1,14 @@
-// Tile windows: the mesh is cut into (n/T)^3 tiles of T^3 cells; the window
-// of a tile covers the tile plus R cells beyond each face (W = T + 2R per
-// axis, z fastest) and lives in a slab [slot][tile][W^3] of int64 partial
-// sums.  A cell's value is the sum of the windows that cover it: along each
-// axis the own tile at local l + R, the previous tile at l + T + R when
-// l < R, the next one at l - T + R when l >= T - R (indices periodic).
+// Tile windows: the mesh is cut into (n/T)^3 tiles of T^3 cells (nt per
+// axis); the window of a tile covers the tile plus R cells beyond each face
+// (W = T + 2R per axis) and holds int64 partial sums.  In the slab of one
+// slot the windows are stored row-major over the mesh: the window row
+// (lx, ly) of tile (tx, ty, tz) is W values at
+//   ((((tx nt + ty) W + lx) W + ly) nt + tz) W,
+// so the rows of all tz at fixed (tx, ty, lx, ly) are one contiguous run of
+// nt W values, which a z-row pass reads in one sweep.  A cell's value is the
+// sum of the windows that cover it: along each axis the own tile at local
+// l + R, the previous tile at l + T + R when l < R, the next one at l - T + R
+// when l >= T - R (indices periodic).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -24,18 +29,33 @@ __device__ __forceinline__ WinCover win_cover(int x, int T, int R, int log2T, in
   return w;
 }
 
-// sum of the windows covering the cell whose x and y covers are cx, cy
+// offset of window row (lx, ly) of tile (tx, ty, tz) in a slot's slab
+__device__ __forceinline__ long long slab_row(int tx, int ty, int tz, int lx, int ly, int W, int nt) {
+  return (((((long long)tx * nt + ty) * W + lx) * W + ly) * nt + tz) * W;
+}
+
+// sum of the windows covering a cell with covers cx, cy, cz
 __device__ __forceinline__ long long win_sum(const long long* __restrict__ slab, const WinCover& cx,
-                                             const WinCover& cy, const WinCover& cz, int W, int log2nt) {
-  const long long W3 = (long long)W * W * W;
+                                             const WinCover& cy, const WinCover& cz, int W, int nt) {
   long long acc = 0;
   for (int p = 0; p < cx.n; ++p)
     for (int q = 0; q < cy.n; ++q)
-      for (int r = 0; r < cz.n; ++r) {
-        const long long t = ((long long)cx.t[p] << (2 * log2nt)) | (cy.t[q] << log2nt) | cz.t[r];
-        acc += slab[t * W3 + ((long long)cx.l[p] * W + cy.l[q]) * W + cz.l[r]];
-      }
+      for (int r = 0; r < cz.n; ++r) acc += slab[slab_row(cx.t[p], cy.t[q], cz.t[r], cx.l[p], cy.l[q], W, nt) + cz.l[r]];
   return acc;
+}
+
+// store an LDS window (z fastest, W <= 32) of tile t into the slot's slab:
+// 8 groups of 32 lanes take rows (lx, ly) in turn, one lane per z
+template <class V>
+__device__ __forceinline__ void store_window(const V* win, V* slab, int t, int W, int log2nt) {
+  const int nt = 1 << log2nt, m = nt - 1;
+  const int tx = t >> (2 * log2nt), ty = (t >> log2nt) & m, tz = t & m;
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5, W2 = W * W;
+  if (lane >= W) return;
+  for (int r = grp; r < W2; r += 8) {
+    const int lx = r / W, ly = r - lx * W;
+    slab[slab_row(tx, ty, tz, lx, ly, W, nt) + lane] = win[r * W + lane];
+  }
 }
 
 // the same cover when T > 2R: the own tile and at most one neighbour, in
