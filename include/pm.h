@@ -30,11 +30,13 @@
  *           Psi from the Lagrangian lattice point q_j = j L/n_p in units of
  *           dq = L/n_p, and V = dPsi/dD in dq per unit of the growth factor D
  *           (D ~ a at early times).  Layout [B][3][N], N = n_p^3, lattice
- *           index j = (jx n_p + jy) n_p + jz.  Meshes are [B][n_g][n_g][n_g]
- *           with z fastest.
+ *           index j = (jx n_p + jy) n_p + jz at every call (inside, the
+ *           context keeps particles in lattice blocks that match its mesh
+ *           tiles).  Meshes are [B][n_g][n_g][n_g] with z fastest.
  * Determinism.  The forward deposit accumulates int64 fixed point (2^32 per
- *           particle), so forward results are bit-identical run to run and
- *           slot to slot.  The adjoint's cotangent scatter uses FP32 atomics.
+ *           particle) and the adjoint's cotangent scatter int64 fixed point
+ *           at a power-of-two scale, so results are bit-identical run to run
+ *           and slot to slot.
  */
 #ifndef PM_H
 #define PM_H
@@ -221,11 +223,14 @@ pm_status pm_set_state(pm_ctx* ctx, const float* disp, const float* vel);
 
 /* Deposit the given displacements (device [B][3][N]) with kernel order
  * mak (2 CIC, 3 TSC, 6 = ES of the NUFFT grid) into the int64 mesh
- * mesh_out (device [B][n^3], n = n_g).  Bit-exact fixed-point spec. */
+ * mesh_out (device [B][n^3], n = n_g).  Bit-exact fixed-point spec.
+ * This and the two hooks below load disp as the context's particle
+ * positions (the previous state is overwritten). */
 pm_status pm_deposit(pm_ctx* ctx, const float* disp, int32_t mak, int64_t* mesh_out);
 
 /* PM (or NUFFT) acceleration A(X) at the given displacements for the
- * midpoint normalisation s = 1/D^2 (device in [B][3][N], out [B][3][N]). */
+ * midpoint normalisation s = 1/D^2 (device in [B][3][N], out [B][3][N]).
+ * Overwrites the context's particle state. */
 pm_status pm_force(pm_ctx* ctx, const float* disp, double s, float* acc_out);
 
 /* Vector-Jacobian product of that acceleration (App. "Custom VJP and JVP":

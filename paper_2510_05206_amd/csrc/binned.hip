@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
       }
     }
     long long j[3];
-    lattice_of(i, a.g.log2_np, j);
+    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
     const int nm = a.g.n_g - 1;
     int h[3];
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
   for (int p = beg + threadIdx.x; p < end; p += 256) {
     const long long i = a.sorted[slot * N + p];
     long long j[3];
-    lattice_of(i, a.g.log2_np, j);
+    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     int w[3][P], l0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -272,7 +272,7 @@ template <int P>
 __device__ __forceinline__ void tile_weights(const TileArgs& a, long long i, const float p[3], const int o[3],
                                              int R, float w[3][P], float dw[3][P], int l0[3]) {
   long long j[3];
-  lattice_of(i, a.g.log2_np, j);
+  lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
 #pragma unroll
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
   for (int p = beg + threadIdx.x; p < end; p += 256) {
     const long long i = a.sorted[slot * N + p];
     long long j[3];
-    lattice_of(i, a.g.log2_np, j);
+    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     int w[3][kEsW], l0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
   for (int p = beg + threadIdx.x; p < end; p += 256) {
     const long long i = a.sorted[slot * N + p];
     long long j[3];
-    lattice_of(i, a.g.log2_np, j);
+    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
     float w[3][kEsW];
     int l0[3];
@@ -748,7 +748,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
   for (int p = beg + threadIdx.x; p < end; p += 256) {
     const long long i = a.sorted[slot * N + p];
     long long j[3];
-    lattice_of(i, a.g.log2_np, j);
+    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
     float w[3][kEsW], dw[3][kEsW];
     int l0[3];
@@ -822,7 +822,7 @@ __global__ void __launch_bounds__(256) k_tile_es_dipole(TileArgs a) {
     if (uc == 0.f) continue;
     const long long i = a.sorted[slot * N + p];
     long long j[3];
-    lattice_of(i, a.g.log2_np, j);
+    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     float w[3][kEsW];
     int l0[3];
 #pragma unroll
@@ -870,7 +870,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
   for (int p = beg + threadIdx.x; p < end; p += 256) {
     const long long i = a.sorted[slot * N + p];
     long long j[3];
-    lattice_of(i, a.g.log2_np, j);
+    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
     float w[3][kEsW], dw[3][kEsW];
     int l0[3];

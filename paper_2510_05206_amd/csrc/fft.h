@@ -38,6 +38,7 @@ struct RowLaunch {
   // (the rest is zero); 0 = the whole half row
   int kz_lim;
   RowWin win;
+  int ic_log2pb;         // DST_IC: particle arrays in lattice blocks of 2^ic_log2pb (mak.h)
   hipStream_t stream;
 };
 

@@ -20,6 +20,7 @@
 #include "fft.h"
 #include "fft_reg.h"
 #include "windows.h"
+#include "mak.h"
 
 namespace pm {
 
@@ -351,7 +352,7 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
                                                       float* __restrict__ dst2, int n_rows,
                                                       const float2* __restrict__ tw, int tws_half, int tws_full,
                                                       float scale, float scale2, unsigned long long active,
-                                                      int rs, int kz_lim) {
+                                                      int rs, int kz_lim, int log2pb) {
   using S = freg::RowShape<L, P>;
   constexpr int n = 2 * L;
   __shared__ float2 lds[S::LDS];
@@ -392,9 +393,13 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
   __syncthreads();
   freg::pass_b<S, true>(v, lds, n1, c);
   if (!valid) return;
+  constexpr int log2n = __builtin_ctz(n);
 #pragma unroll
   for (int r = 0; r < S::E; ++r) {
-    const long long gi = slot * dst_stride + row * n + 2 * S::t_out(n1, r);
+    // DST_IC: particle arrays in lattice-block order (z pairs stay adjacent)
+    const long long gi = slot * dst_stride + (DST == DST_IC ? blocked_index(row / n, row % n, 2 * S::t_out(n1, r),
+                                                                            log2n, log2pb)
+                                                            : row * n + 2 * S::t_out(n1, r));
     const float2 z = make_float2(v[r].x * scale, v[r].y * scale);
     *reinterpret_cast<float2*>(dst + gi) = z;
     if constexpr (DST == DST_IC) *reinterpret_cast<float2*>(dst2 + gi) = make_float2(z.x * scale2, z.y * scale2);
@@ -557,11 +562,11 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
     if (r.dst_mode == DST_F32)
       k_c2r_rows_reg<L, P, DST_F32><<<grid, 256, 0, r.stream>>>(
           (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows, r.tw,
-          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs, r.kz_lim);
+          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs, r.kz_lim, r.ic_log2pb);
     else
       k_c2r_rows_reg<L, P, DST_IC><<<grid, 256, 0, r.stream>>>(
           (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows, r.tw,
-          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs, r.kz_lim);
+          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs, r.kz_lim, r.ic_log2pb);
   } else {
     if (r.src_mode == SRC_I64)
       k_r2c_rows_reg<L, P, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,

@@ -75,8 +75,10 @@ hipError_t launch_fill(void* p, long long bytes, hipStream_t s);
 hipError_t launch_white_noise(float* w, long long N, long long slot_stride, int batch,
                               const uint64_t* seeds_host, unsigned long long active, hipStream_t s);
 hipError_t launch_psibar(const float* xbar, const float* vbar, float* out, long long N,
-                         long long part_stride, int batch, const float* d0, unsigned long long active,
-                         hipStream_t s);
+                         long long part_stride, int batch, const float* d0, int log2_np, int log2_pb,
+                         unsigned long long active, hipStream_t s);
+hipError_t launch_reorder(const float* src, float* dst, long long N, long long stride, int ncomp, int batch,
+                          int log2_np, int log2_pb, bool to_blocked, unsigned long long active, hipStream_t s);
 hipError_t launch_dot(const float* a, const float* b, long long n, long long stride, int batch,
                       double* partial, double* out, const double* scale, unsigned long long active,
                       hipStream_t s);

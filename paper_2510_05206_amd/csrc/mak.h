@@ -70,11 +70,25 @@ __device__ __forceinline__ int weights1d_f(long long U, float w[P], float dw[P])
   return i0;
 }
 
-__device__ __forceinline__ void lattice_of(long long i, int log2_np, long long j[3]) {
-  long long m = (1ll << log2_np) - 1;
-  j[2] = i & m;
-  j[1] = (i >> log2_np) & m;
-  j[0] = i >> (2 * log2_np);
+// Particle storage order: the lattice is cut into blocks of B = 2^b sites per
+// axis (B^3 consecutive particles, z fastest inside a block, blocks in x-major
+// order).  With B = tile edge / (n_g / n_p) an unperturbed block fills exactly
+// one mesh tile, so the particles of a tile are a contiguous run.  b = log2
+// n_p is plain row-major order.
+__device__ __forceinline__ void lattice_of(long long i, int log2_np, int b, long long j[3]) {
+  const int nb = log2_np - b;
+  const long long bm = (1ll << b) - 1, nm = (1ll << nb) - 1;
+  const long long loc = i & ((1ll << (3 * b)) - 1), blk = i >> (3 * b);
+  j[2] = ((blk & nm) << b) | (loc & bm);
+  j[1] = (((blk >> nb) & nm) << b) | ((loc >> b) & bm);
+  j[0] = ((blk >> (2 * nb)) << b) | (loc >> (2 * b));
+}
+
+__host__ __device__ __forceinline__ long long blocked_index(long long x, long long y, long long z, int log2_np, int b) {
+  const int nb = log2_np - b;
+  const long long bm = (1ll << b) - 1;
+  const long long blk = (((x >> b) << nb | (y >> b)) << nb) | (z >> b);
+  return (blk << (3 * b)) | ((((x & bm) << b) | (y & bm)) << b) | (z & bm);
 }
 
 // finite-difference stencil c_s (s = -H..H) of d/dx

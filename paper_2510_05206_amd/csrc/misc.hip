@@ -1,6 +1,7 @@
 // Auxiliary kernels: fills, white noise, the IC-adjoint source, deterministic
 // FP64 reductions and the binned power spectrum.
 #include "kernels.h"
+#include "mak.h"
 
 namespace pm {
 
@@ -67,23 +68,53 @@ hipError_t launch_white_noise(float* w, long long N, long long slot_stride, int 
 
 // psi_bar_c = D0 X_bar_c + V_bar_c (the IC pullback of Psi = D0 psi, V = psi)
 struct D0s { float d0[kMaxBatch]; };
-__global__ void k_psibar(const float* xbar, const float* vbar, float* out, long long n3,
-                         long long stride, D0s d, unsigned long long active) {
+// psi_bar = D0 X_bar + V_bar, from the lattice-block particle order into
+// row-major lattice order (the layout of the initial-condition transforms)
+__global__ void k_psibar(const float* xbar, const float* vbar, float* out, long long N,
+                         long long stride, D0s d, int log2_np, int log2_pb, unsigned long long active) {
   const int slot = blockIdx.y;
   if (!((active >> slot) & 1ull)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n3) return;
-  long long g = slot * stride + i;
-  out[g] = d.d0[slot] * xbar[g] + vbar[g];
+  if (i >= 3 * N) return;
+  const long long c = i / N, p = i - c * N;
+  long long j[3];
+  lattice_of(p, log2_np, log2_pb, j);
+  const long long g = slot * stride + i;
+  out[slot * stride + c * N + ((j[0] << log2_np | j[1]) << log2_np | j[2])] = d.d0[slot] * xbar[g] + vbar[g];
 }
 
 hipError_t launch_psibar(const float* xbar, const float* vbar, float* out, long long N,
-                         long long part_stride, int batch, const float* d0,
+                         long long part_stride, int batch, const float* d0, int log2_np, int log2_pb,
                          unsigned long long active, hipStream_t s) {
   D0s d;
   for (int b = 0; b < batch; ++b) d.d0[b] = d0[b];
   dim3 grid((unsigned)((3 * N + 255) / 256), batch);
-  k_psibar<<<grid, 256, 0, s>>>(xbar, vbar, out, 3 * N, part_stride, d, active);
+  k_psibar<<<grid, 256, 0, s>>>(xbar, vbar, out, N, part_stride, d, log2_np, log2_pb, active);
+  return hipGetLastError();
+}
+
+// particle arrays [B][ncomp][N] between row-major lattice order and the
+// lattice-block storage order (to_blocked: row-major in, blocked out)
+__global__ void k_reorder(const float* src, float* dst, long long N, long long stride, int ncomp, int log2_np,
+                          int log2_pb, bool to_blocked, unsigned long long active) {
+  const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncomp * N) return;
+  const long long c = i / N, r = i - c * N;  // r: row-major lattice index
+  const long long m = (1ll << log2_np) - 1;
+  const long long b = blocked_index(r >> (2 * log2_np), (r >> log2_np) & m, r & m, log2_np, log2_pb);
+  const long long base = slot * stride + c * N;
+  if (to_blocked)
+    dst[base + b] = src[base + r];
+  else
+    dst[base + r] = src[base + b];
+}
+
+hipError_t launch_reorder(const float* src, float* dst, long long N, long long stride, int ncomp, int batch,
+                          int log2_np, int log2_pb, bool to_blocked, unsigned long long active, hipStream_t s) {
+  dim3 grid((unsigned)((ncomp * N + 255) / 256), batch);
+  k_reorder<<<grid, 256, 0, s>>>(src, dst, N, stride, ncomp, log2_np, log2_pb, to_blocked, active);
   return hipGetLastError();
 }
 

@@ -51,6 +51,7 @@ struct SlotStep {          // per-slot scalars of one launch, passed by value
 
 struct Geom {
   int n_p, n_g, log2_np, log2_ng, log2_r;  // r = n_g / n_p
+  int log2_pb;                // particle storage: lattice blocks of 2^log2_pb per axis
   long long N, M;             // particles, mesh cells (per slot)
   long long part_stride;      // floats between slots of a [3][N] array
   long long mesh_stride;      // elements between slots of a mesh

@@ -278,6 +278,8 @@ Geom make_geom(int n_p, int n_g, long long part_stride, long long mesh_stride, l
   g.log2_np = ilog2(n_p);
   g.log2_ng = ilog2(n_g);
   g.log2_r = g.log2_ng - g.log2_np;
+  // lattice blocks that fill one mesh tile (tile edge min(16, n_g) cells)
+  g.log2_pb = std::max(0, std::min(g.log2_np, ilog2(n_g < 16 ? n_g : 16) - g.log2_r));
   g.N = (long long)n_p * n_p * n_p;
   g.M = (long long)n_g * n_g * n_g;
   g.part_stride = part_stride;
@@ -868,6 +870,7 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
     rl.tws_full = c->Lmax / np;
     rl.scale = 1.0;
     rl.scale2 = c->D0;
+    rl.ic_log2pb = c->g.log2_pb;
     rl.stream = c->stream;
     rl.active = act;
     KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
@@ -1178,7 +1181,8 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   // initial conditions: psi_bar = D0 X_bar + V_bar, w_bar = sum_c T_c^T psi_bar_c
   std::vector<float> d0(B, (float)c->D0);
   float* psibar = c->u_sorted;
-  KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->user_mask, c->stream));
+  KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->g.log2_np, c->g.log2_pb,
+                                       c->user_mask, c->stream));
   const unsigned long long act = c->user_mask;
   for (int comp = 0; comp < 3; ++comp) {
     pm_status st = r2c_mesh(c, psibar + comp * N, SRC_F32, 3 * N, 1.0, 0.0,
@@ -1268,20 +1272,34 @@ pm_status pm_density(pm_ctx* c, float* delta_out, int64_t* fixed_out) {
   return PM_OK;
 }
 
+// particle arrays [B][3][N]: row-major lattice order at the boundary,
+// lattice-block order inside (mak.h)
+static pm_status to_user_order(pm_ctx* c, const float* internal, float* user) {
+  KLAUNCH(c, PM_K_MISC, launch_reorder(internal, user, c->g.N, 3 * c->g.N, 3, c->cfg.batch, c->g.log2_np,
+                                       c->g.log2_pb, false, all_mask(c->cfg.batch), c->stream));
+  return PM_OK;
+}
+
+static pm_status from_user_order(pm_ctx* c, const float* user, float* internal) {
+  KLAUNCH(c, PM_K_MISC, launch_reorder(user, internal, c->g.N, 3 * c->g.N, 3, c->cfg.batch, c->g.log2_np,
+                                       c->g.log2_pb, true, all_mask(c->cfg.batch), c->stream));
+  return PM_OK;
+}
+
 pm_status pm_get_state(pm_ctx* c, float* disp, float* vel) {
   if (pm_status st = check_bound(c)) return st;
-  size_t bytes = sizeof(float) * 3 * c->g.N * c->cfg.batch;
-  if (disp) HIPCHK(c, hipMemcpyAsync(disp, c->disp, bytes, hipMemcpyDeviceToDevice, c->stream));
-  if (vel) HIPCHK(c, hipMemcpyAsync(vel, c->vel, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (disp)
+    if (pm_status st = to_user_order(c, c->disp, disp)) return st;
+  if (vel)
+    if (pm_status st = to_user_order(c, c->vel, vel)) return st;
   return PM_OK;
 }
 
 pm_status pm_set_state(pm_ctx* c, const float* disp, const float* vel) {
   if (pm_status st = check_bound(c)) return st;
   if (!disp || !vel) return PM_EINVAL;
-  size_t bytes = sizeof(float) * 3 * c->g.N * c->cfg.batch;
-  HIPCHK(c, hipMemcpyAsync(c->disp, disp, bytes, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->vel, vel, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (pm_status st = from_user_order(c, disp, c->disp)) return st;
+  if (pm_status st = from_user_order(c, vel, c->vel)) return st;
   c->ics_done = true;
   c->ran = true;  // any state may be pulled back by pm_adjoint after a run
   return PM_OK;
@@ -1292,7 +1310,8 @@ pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_ou
   if (!disp || !mesh_out || (mak != 2 && mak != 3 && mak != 6)) return PM_EINVAL;
   if (mak == 6 && c->cfg.force != PM_FORCE_NUFFT)
     return fail(c, PM_EINVAL, "ES spreading needs a NUFFT context");
-  float* x = const_cast<float*>(disp);
+  if (pm_status st = from_user_order(c, disp, c->disp)) return st;  // the hooks use the particle state
+  float* x = c->disp;
   const unsigned long long act = all_mask(c->cfg.batch);
   if (mak != 6) return deposit(c, x, nullptr, nullptr, mak, (long long*)mesh_out, act);
   pm_status st = bin(c, x, nullptr, nullptr, 2, act);
@@ -1310,10 +1329,12 @@ pm_status pm_force(pm_ctx* c, const float* disp, double s, float* acc_out) {
   const int B = c->cfg.batch;
   std::vector<double> sv(B, s);
   const unsigned long long act = all_mask(B);
-  float* x = const_cast<float*>(disp);
-  pm_status st = potential(c, x, nullptr, nullptr, sv.data(), act);
+  if (pm_status st = from_user_order(c, disp, c->disp)) return st;  // the hooks use the particle state
+  pm_status st = potential(c, c->disp, nullptr, nullptr, sv.data(), act);
   if (st) return st;
-  return kick(c, x, nullptr, nullptr, nullptr, acc_out, act);
+  st = kick(c, c->disp, nullptr, nullptr, nullptr, c->vel, act);
+  if (st) return st;
+  return to_user_order(c, c->vel, acc_out);
 }
 
 pm_status pm_force_vjp(pm_ctx* c, const float* disp, double s, const float* u, int32_t parts, float* xbar_out) {
@@ -1324,8 +1345,8 @@ pm_status pm_force_vjp(pm_ctx* c, const float* disp, double s, const float* u, i
   const long long N = c->g.N;
   const size_t bytes = sizeof(float) * 3 * N * B;
   const unsigned long long act = all_mask(B);
-  HIPCHK(c, hipMemcpyAsync(c->disp, disp, bytes, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->vbar, u, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (pm_status st = from_user_order(c, disp, c->disp)) return st;
+  if (pm_status st = from_user_order(c, u, c->vbar)) return st;
   KLAUNCH(c, PM_K_FILL, launch_fill(c->vel, (long long)bytes, c->stream));
   KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)bytes, c->stream));
   std::vector<double> sv(B, s), one(B, 1.0), zero(B, 0.0);
@@ -1334,7 +1355,7 @@ pm_status pm_force_vjp(pm_ctx* c, const float* disp, double s, const float* u, i
   // alpha = beta = 1, tau = 0: X_bar = J_A^T u, the drift is the identity
   st = reverse_force_step(c, sv.data(), one.data(), one.data(), zero.data(), act, parts);
   if (st) return st;
-  HIPCHK(c, hipMemcpyAsync(xbar_out, c->xbar, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (pm_status st = to_user_order(c, c->xbar, xbar_out)) return st;
   c->ics_done = true;
   c->ran = false;
   return PM_OK;
