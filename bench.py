@@ -61,14 +61,18 @@ def launch_model(cfg):
         return {
             "deposit": [(2 * K + 2, 12 * N + 8 * M)],
             "bin": [(K, 40 * N), (K + 3, 16 * N)],
-            "fft_rows": [(2 * K, 8 * M + Sz), (1, 8 * M + Sn), (7 * K, Sz + 4 * M), (3 * K, 4 * M + Sz)] + ic_rows,
-            "fft_cols": [(5 * K, Sz + Sy), (6 * K, 2 * Sy), (6 * K, Sy + Sz), (K, 2 * Sy), (2 * K, 5 * Sy // 2),
-                         (K, Sy + Sz), (2, 2 * Sn)] + ic_cols,
+            # R2C of the mass (run, adjoint recompute, P(k) unpruned), 3 force
+            # C2R per force evaluation plus the adjoint's b_bar, the R2C of
+            # the adjoint's spread kernel gradient
+            "fft_rows": [(2 * K, 8 * M + Sz), (1, 8 * M + Sn), (7 * K, Sz + 4 * M), (K, 4 * M + Sz)] + ic_rows,
+            # y forward (mass and the adjoint's gradient spread), x passes
+            # (multiplier between forward and inverse x), inverse y
+            "fft_cols": [(3 * K, Sz + Sy), (7 * K, 2 * Sy), (7 * K, Sy + Sz), (2, 2 * Sn)] + ic_cols,
             # read X, V and 3 force meshes, write X, V
             "gather_kick": [(K, 48 * N + 12 * M)],
             "adj_kick": [(K, 96 * N + 12 * M)],
-            # per component: read u_c and X, write the FP32 mesh
-            "dipole": [(3 * K, 16 * N + 4 * M)],
+            # spread of u . grad phi: read u and X, write the mesh (int64)
+            "dipole": [(K, 24 * N + 8 * M)],
             "adj_drift": [(K + 1, 84 * N + 4 * M)],
         }
     return {

@@ -694,19 +694,26 @@ __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
 #pragma unroll
       for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
     }
+    // separable contraction: z sums per (x, y) row, then y, then x
     float A[3] = {0.f, 0.f, 0.f};
-    for (int xx = 0; xx < kEsW; ++xx)
+#pragma unroll
+    for (int xx = 0; xx < kEsW; ++xx) {
+      float sx[3] = {0.f, 0.f, 0.f};
+#pragma unroll
       for (int yy = 0; yy < kEsW; ++yy) {
-        const float wxy = w[0][xx] * w[1][yy];
         const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+        float r[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int zz = 0; zz < kEsW; ++zz) {
-          const float wt = wxy * w[2][zz];
-          A[0] += wt * fwin[b + zz];
-          A[1] += wt * fwin[W3 + b + zz];
-          A[2] += wt * fwin[2 * W3 + b + zz];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) r[c] += w[2][zz] * fwin[c * W3 + b + zz];
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sx[c] += w[1][yy] * r[c];
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A[c] += w[0][xx] * sx[c];
+    }
     if (a.acc_out) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.acc_out[ps + c * N + i] = A[c];
@@ -758,24 +765,40 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
       int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
       l0[c] = h - o[c] + kEsR - 2;
     }
+    // separable contraction of the value and its gradient: per (x, y) row
+    // the sums with w_z and w_z', then with w_y / w_y', then w_x / w_x'
     float A[3] = {0.f, 0.f, 0.f}, dA[3][3] = {};
-    for (int xx = 0; xx < kEsW; ++xx)
+#pragma unroll
+    for (int xx = 0; xx < kEsW; ++xx) {
+      float sww[3] = {0.f, 0.f, 0.f}, sdw[3] = {0.f, 0.f, 0.f}, swd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
       for (int yy = 0; yy < kEsW; ++yy) {
-        const float wxy = w[0][xx] * w[1][yy], gxy = dw[0][xx] * w[1][yy], hxy = w[0][xx] * dw[1][yy];
         const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+        float rw[3] = {0.f, 0.f, 0.f}, rd[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int zz = 0; zz < kEsW; ++zz) {
-          const float wt = wxy * w[2][zz], gx = gxy * w[2][zz], gy = hxy * w[2][zz], gz = wxy * dw[2][zz];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const float f = fwin[c * W3 + b + zz];
-            A[c] += wt * f;
-            dA[c][0] += gx * f;
-            dA[c][1] += gy * f;
-            dA[c][2] += gz * f;
+            rw[c] += w[2][zz] * f;
+            rd[c] += dw[2][zz] * f;
           }
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          sww[c] += w[1][yy] * rw[c];
+          sdw[c] += dw[1][yy] * rw[c];
+          swd[c] += w[1][yy] * rd[c];
+        }
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        A[c] += w[0][xx] * sww[c];
+        dA[c][0] += dw[0][xx] * sww[c];
+        dA[c][1] += w[0][xx] * sdw[c];
+        dA[c][2] += w[0][xx] * swd[c];
+      }
+    }
     float u[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -800,9 +823,12 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
     atomicMax(reinterpret_cast<unsigned int*>(a.umax) + slot, __float_as_uint(red[0]));
 }
 
-// spreading of component comp of u with the ES weights (the transpose of the
-// interpolation), int64 fixed point at the scale set from max |u|
-__global__ void __launch_bounds__(256) k_tile_es_dipole(TileArgs a) {
+// Spreading of d(j) = sum_c u_c d/du_c phi3(u - j) (the kernel's gradient
+// along the cotangent u) for the adjoint's mesh term: the Fourier transform
+// of the spread gradient is -i k_c times that of the spread of u_c, so one
+// spread replaces the three per-component spreads and their transforms.
+// int64 fixed point at the scale set from max |u| (|phi| <= 1, |phi'| < 1).
+__global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
   extern __shared__ unsigned long long ewin[];
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
@@ -816,32 +842,30 @@ __global__ void __launch_bounds__(256) k_tile_es_dipole(TileArgs a) {
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
   const double S = a.scale[slot];
-  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
   for (int p = beg + threadIdx.x; p < end; p += 256) {
-    const float uc = a.u_sorted[ps + a.comp * N + p];
-    if (uc == 0.f) continue;
+    const float u[3] = {a.u_sorted[ps + p], a.u_sorted[ps + N + p], a.u_sorted[ps + 2 * N + p]};
+    if (u[0] == 0.f && u[1] == 0.f && u[2] == 0.f) continue;
     const long long i = a.sorted[slot * N + p];
     long long j[3];
     lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
-    float w[3][kEsW];
+    float w[3][kEsW], dw[3][kEsW];
     int l0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      int wi[kEsW];
       long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
-      int h = es_weights(U, a.es_tab, wi) & nm;
+      int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
       l0[c] = h - o[c] + kEsR - 2;
-#pragma unroll
-      for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
     }
     for (int x = 0; x < kEsW; ++x)
       for (int y = 0; y < kEsW; ++y) {
-        const float wxy = w[0][x] * w[1][y] * uc;
-        if (wxy == 0.f) continue;
+        // v(z) = (u_x w0' w1 + u_y w0 w1') w2(z) + u_z w0 w1 w2'(z)
+        const float pa = u[0] * dw[0][x] * w[1][y] + u[1] * w[0][x] * dw[1][y];
+        const float pb = u[2] * w[0][x] * w[1][y];
+        if (pa == 0.f && pb == 0.f) continue;
         const int bxy = ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
 #pragma unroll
         for (int z = 0; z < kEsW; ++z) {
-          long long v = llrint((double)(wxy * w[2][z]) * S);
+          long long v = llrint((double)(pa * w[2][z] + pb * dw[2][z]) * S);
           if (v) atomicAdd(&ewin[bxy + z], (unsigned long long)v);
         }
       }
@@ -881,18 +905,27 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
       l0[c] = h - o[c] + kEsR - 2;
     }
     float gx = 0.f, gy = 0.f, gz = 0.f;
-    for (int xx = 0; xx < kEsW; ++xx)
+#pragma unroll
+    for (int xx = 0; xx < kEsW; ++xx) {
+      float sww = 0.f, sdw = 0.f, swd = 0.f;
+#pragma unroll
       for (int yy = 0; yy < kEsW; ++yy) {
-        const float wxy = w[0][xx] * w[1][yy], gxy = dw[0][xx] * w[1][yy], hxy = w[0][xx] * dw[1][yy];
         const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+        float rw = 0.f, rd = 0.f;
 #pragma unroll
         for (int zz = 0; zz < kEsW; ++zz) {
           const float f = bwin[b + zz];
-          gx += f * gxy * w[2][zz];
-          gy += f * hxy * w[2][zz];
-          gz += f * wxy * dw[2][zz];
+          rw += w[2][zz] * f;
+          rd += dw[2][zz] * f;
         }
+        sww += w[1][yy] * rw;
+        sdw += dw[1][yy] * rw;
+        swd += w[1][yy] * rd;
       }
+      gx += dw[0][xx] * sww;
+      gy += w[0][xx] * sdw;
+      gz += w[0][xx] * swd;
+    }
     float g[3] = {gx, gy, gz};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -927,7 +960,7 @@ hipError_t configure_tile_kernels() {
   set((const void*)k_tile_es_deposit, es64);
   set((const void*)k_tile_es_kick, es32x3);
   set((const void*)k_tile_es_adj_kick, es32x3);
-  set((const void*)k_tile_es_dipole, es64);
+  set((const void*)k_tile_es_divspread, es64);
   set((const void*)k_tile_es_adj_drift, es32);
   return e;
 }
@@ -945,9 +978,8 @@ hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
     size_t lds = (size_t)3 * W * W * W * sizeof(float);
     k_tile_es_adj_kick<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_DIPOLE) {
-    if (a.comp < 0 || a.comp > 2) return hipErrorInvalidValue;
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
-    k_tile_es_dipole<<<grid, 256, lds, s>>>(a);
+    k_tile_es_divspread<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_ADJ_DRIFT) {
     size_t lds = (size_t)W * W * W * sizeof(float);
     k_tile_es_adj_drift<<<grid, 256, lds, s>>>(a);

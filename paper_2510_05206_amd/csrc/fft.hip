@@ -501,32 +501,26 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
       inverse_next = true;
     }
     if constexpr (MODE == MODE_NUFFT_ADJ) {
+      // adjoint mesh term: the spread kernel gradient already carries the
+      // -i k_c of the transposed multiplier, what is left is real:
+      // coef / (k^2 Phi^2) on the kept modes (coef includes n_f / n_p)
       const float k0 = 6.283185307179586f / (float)a.n_p;
 #pragma unroll
       for (int r = 0; r < S::E; ++r) {
         const int t = S::t_out(n1, r);
         float h = 0.f;
-        bool kept_mode = false;
         if (valid) {
           float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
           int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
           float th2 = 0.f;
 #pragma unroll
           for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
-          kept_mode = dec != 0.f;
-          h = (!kept_mode || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
+          h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec / th2;
         }
-        float2 y = make_float2(h * v[r].y, -h * v[r].x);  // -i h v
-        // running sum over components on every kept mode (this component's
-        // multiplier vanishes on its own zero plane, the others' need not)
-        if (kept_mode && a.comp > 0) {
-          float2 acc = a.dst3[col + t * stride_t];
-          y.x += acc.x;
-          y.y += acc.y;
-        }
-        v[r] = y;
+        v[r].x *= h;
+        v[r].y *= h;
       }
-      inverse_next = a.comp == 2;
+      inverse_next = true;
     }
     if (inverse_next) {  // back to the input layout for the inverse transform
       __syncthreads();

@@ -45,7 +45,6 @@ struct TileArgs {
   const int32_t* es_tab;   // integer exponential-of-semicircle table (NUFFT)
   float es_beta;           // its shape parameter (closed-form derivative)
   long long comp_stride;   // floats between the 3 force meshes (NUFFT kick)
-  int comp;                // component scattered by the NUFFT adjoint's spreading
   float alpha[kMaxBatch];
   float beta[kMaxBatch];
   float tau[kMaxBatch];

@@ -985,10 +985,11 @@ static pm_status run_steps(pm_ctx* c) {
 }
 
 // one reverse step of the NUFFT force after its force meshes are rebuilt at
-// X^{n+1/2}: reverse kick with the direct position gradient; per component
-// the ES spreading of u (the transposed interpolation), R2C and the
-// transposed multiplier -i h_c summed over components; C2R of the sum; its
-// gradient gather (the transposed spreading) fused with the reverse drift
+// X^{n+1/2}: reverse kick with the direct position gradient; the mesh term
+// sum_c G_c^T (spread of u_c) as one spread of u . grad phi (its transform
+// is -i k_c times that of the spread of u_c), R2C, the real remainder of the
+// multiplier, C2R; its gradient gather (the transposed spreading) fused with
+// the reverse drift
 pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, const double* beta,
                              const double* tau, unsigned long long act, int parts) {
   const int B = c->cfg.batch, ng = c->cfg.n_g;
@@ -1005,10 +1006,24 @@ pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, co
   if (!(parts & 1))
     KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
   if (!(parts & 2)) return PM_OK;
-  // every node sum of u_c phi is bounded by N max|u| (phi <= 1)
-  KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale, (double)N, B,
-                                            c->stream));
-  float* d = reinterpret_cast<float*>(c->mesh);
+  // every node value sum_c u_c d/du_c phi3 is bounded by 3 max|u| per
+  // particle (|phi| <= 1, |phi'| < 1 cell^-1)
+  KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale, 3.0 * (double)N,
+                                            B, c->stream));
+  pm_status st;
+  if (fuse_windows(c)) {
+    KLAUNCH(c, PM_K_DIPOLE, launch_tile_es(k, TK_ES_DIPOLE, c->stream));
+    const RowWin w = row_win(c, 3, c->inv_scale);
+    st = r2c_mesh(c, c->scratch, SRC_WIN, 0, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p, &w);
+  } else {
+    float* d = reinterpret_cast<float*>(c->mesh);
+    AssembleArgs as = assemble_args(c, 3, d, act);
+    KLAUNCH(c, PM_K_DIPOLE,
+            both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
+    st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p);
+  }
+  if (st) return st;
+  // x pass: forward, real multiplier (n_f / n_p) (s / N) / (k^2 Phi^2), inverse
   ColArgs x{};
   x.data = c->spec;
   x.dst3 = c->spec2;
@@ -1025,24 +1040,8 @@ pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, co
   x.zlim = c->cfg.n_p / 2;
   x.keep = c->cfg.n_p;
   x.keep_outer = 1;
-  for (int b = 0; b < B; ++b) x.coef[b] = (float)(s[b] / (double)N);
-  for (int comp = 0; comp < 3; ++comp) {
-    k.comp = comp;
-    pm_status st;
-    if (fuse_windows(c)) {
-      KLAUNCH(c, PM_K_DIPOLE, launch_tile_es(k, TK_ES_DIPOLE, c->stream));
-      const RowWin w = row_win(c, 3, c->inv_scale);
-      st = r2c_mesh(c, c->scratch, SRC_WIN, 0, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p, &w);
-    } else {
-      AssembleArgs as = assemble_args(c, 3, d, act);
-      KLAUNCH(c, PM_K_DIPOLE,
-              both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
-      st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p);
-    }
-    if (st) return st;
-    x.comp = comp;
-    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(x, MODE_NUFFT_ADJ, B, c->stream));
-  }
+  for (int b = 0; b < B; ++b) x.coef[b] = (float)(s[b] / (double)N * ((double)ng / c->cfg.n_p));
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(x, MODE_NUFFT_ADJ, B, c->stream));
   ColArgs y = x;
   y.data = c->spec2;
   y.axis = 1;
