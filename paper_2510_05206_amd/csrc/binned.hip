@@ -660,71 +660,78 @@ __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
 }
 
 // A_c = sum_j g_c(j) phi(u - j) from the three force meshes, then the kick
-// and drift (or A only for the force hook)
+// and drift (or A only for the force hook).  The components take turns in
+// one LDS window (V_c = alpha V_c + beta A_c is per component), so three
+// workgroups fit on a CU; the drift follows once every V_c is updated.
+__device__ __forceinline__ float es_contract(const float* __restrict__ win, int W, const int l0[3],
+                                             const float (&w)[3][kEsW]) {
+  float A = 0.f;
+#pragma unroll
+  for (int xx = 0; xx < kEsW; ++xx) {
+    float sx = 0.f;
+#pragma unroll
+    for (int yy = 0; yy < kEsW; ++yy) {
+      const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+      float r = 0.f;
+#pragma unroll
+      for (int zz = 0; zz < kEsW; ++zz) r += w[2][zz] * win[b + zz];
+      sx += w[1][yy] * r;
+    }
+    A += w[0][xx] * sx;
+  }
+  return A;
+}
+
+__device__ __forceinline__ void es_particle(const TileArgs& a, long long i, const int o[3], long long umask, int nm,
+                                            float (&w)[3][kEsW], int (&l0)[3]) {
+  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
+  const long long N = a.g.N, ps = (long long)blockIdx.y * a.g.part_stride;
+  long long j[3];
+  lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int wi[kEsW];
+    long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
+    int h = es_weights(U, a.es_tab, wi) & nm;
+    l0[c] = h - o[c] + kEsR - 2;
+#pragma unroll
+    for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
-  extern __shared__ float fwin[];  // 3 windows of (T + 6)^3
+  extern __shared__ float fwin[];  // one (T + 6)^3 window, the components in turn
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + 2 * kEsR, W3 = W * W * W;
+  const int W = a.T + 2 * kEsR;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
-  for (int c = 0; c < 3; ++c)
-    load_window(fwin + c * W3, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsR,
-                a.g.log2_ng, a.g.n_g - 1);
-  __syncthreads();
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
   const float al = a.alpha[slot], be = a.beta[slot], tp = a.tau[slot];
-  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
-  for (int p = beg + threadIdx.x; p < end; p += 256) {
+  for (int c = 0; c < 3; ++c) {
+    if (c) __syncthreads();  // the previous component's reads are done
+    load_window(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsR, a.g.log2_ng, nm);
+    __syncthreads();
+    for (int p = beg + threadIdx.x; p < end; p += 256) {
+      const long long i = a.sorted[slot * N + p];
+      float w[3][kEsW];
+      int l0[3];
+      es_particle(a, i, o, umask, nm, w, l0);
+      const float A = es_contract(fwin, W, l0, w);
+      if (a.acc_out)
+        a.acc_out[ps + c * N + i] = A;
+      else
+        a.vel[ps + c * N + i] = al * a.vel[ps + c * N + i] + be * A;
+    }
+  }
+  if (a.acc_out) return;
+  for (int p = beg + threadIdx.x; p < end; p += 256) {  // drift (this thread's own V writes)
     const long long i = a.sorted[slot * N + p];
-    long long j[3];
-    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
-    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
-    float w[3][kEsW];
-    int l0[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      int wi[kEsW];
-      long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
-      int h = es_weights(U, a.es_tab, wi) & nm;
-      l0[c] = h - o[c] + kEsR - 2;
-#pragma unroll
-      for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
-    }
-    // separable contraction: z sums per (x, y) row, then y, then x
-    float A[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int xx = 0; xx < kEsW; ++xx) {
-      float sx[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int yy = 0; yy < kEsW; ++yy) {
-        const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
-        float r[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int zz = 0; zz < kEsW; ++zz) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) r[c] += w[2][zz] * fwin[c * W3 + b + zz];
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sx[c] += w[1][yy] * r[c];
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) A[c] += w[0][xx] * sx[c];
-    }
-    if (a.acc_out) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) a.acc_out[ps + c * N + i] = A[c];
-      continue;
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float v = al * a.vel[ps + c * N + i] + be * A[c];
-      a.vel[ps + c * N + i] = v;
-      a.disp[ps + c * N + i] = x[c] + tp * v;
-    }
+    for (int c = 0; c < 3; ++c) a.disp[ps + c * N + i] += tp * a.vel[ps + c * N + i];
   }
 }
 
@@ -734,17 +741,13 @@ __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
 // gradient: V = (V - beta A) / alpha, V_bar = alpha V_bar, u = beta V_bar,
 // X_bar += r sum_c u_c dA_c/du; u kept in sorted order with max |u|
 __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
-  extern __shared__ float fwin[];  // 3 windows of (T + 6)^3
+  extern __shared__ float fwin[];  // one (T + 6)^3 window, the components in turn
   __shared__ float red[256];
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + 2 * kEsR, W3 = W * W * W;
+  const int W = a.T + 2 * kEsR;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
-  for (int c = 0; c < 3; ++c)
-    load_window(fwin + c * W3, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsR,
-                a.g.log2_ng, a.g.n_g - 1);
-  __syncthreads();
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
@@ -752,66 +755,55 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
   const float al = a.alpha[slot], be = a.beta[slot];
   const float r = (float)(1 << a.g.log2_r);
   float umax = 0.f;
-  for (int p = beg + threadIdx.x; p < end; p += 256) {
-    const long long i = a.sorted[slot * N + p];
-    long long j[3];
-    lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
-    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
-    float w[3][kEsW], dw[3][kEsW];
-    int l0[3];
+  for (int c = 0; c < 3; ++c) {
+    if (c) __syncthreads();
+    load_window(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsR, a.g.log2_ng, nm);
+    __syncthreads();
+    for (int p = beg + threadIdx.x; p < end; p += 256) {
+      const long long i = a.sorted[slot * N + p];
+      long long j[3];
+      lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+      float w[3][kEsW], dw[3][kEsW];
+      int l0[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
-      int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
-      l0[c] = h - o[c] + kEsR - 2;
-    }
-    // separable contraction of the value and its gradient: per (x, y) row
-    // the sums with w_z and w_z', then with w_y / w_y', then w_x / w_x'
-    float A[3] = {0.f, 0.f, 0.f}, dA[3][3] = {};
+      for (int d = 0; d < 3; ++d) {
+        long long U = fixed_coord(j[d], a.disp[ps + d * N + i], a.g.log2_r, umask);
+        int h = es_weights_d(U, a.es_tab, a.es_beta, w[d], dw[d]) & nm;
+        l0[d] = h - o[d] + kEsR - 2;
+      }
+      // separable contraction of the value and its gradient
+      float A = 0.f, dA[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int xx = 0; xx < kEsW; ++xx) {
-      float sww[3] = {0.f, 0.f, 0.f}, sdw[3] = {0.f, 0.f, 0.f}, swd[3] = {0.f, 0.f, 0.f};
+      for (int xx = 0; xx < kEsW; ++xx) {
+        float sww = 0.f, sdw = 0.f, swd = 0.f;
 #pragma unroll
-      for (int yy = 0; yy < kEsW; ++yy) {
-        const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
-        float rw[3] = {0.f, 0.f, 0.f}, rd[3] = {0.f, 0.f, 0.f};
+        for (int yy = 0; yy < kEsW; ++yy) {
+          const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+          float rw = 0.f, rd = 0.f;
 #pragma unroll
-        for (int zz = 0; zz < kEsW; ++zz) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const float f = fwin[c * W3 + b + zz];
-            rw[c] += w[2][zz] * f;
-            rd[c] += dw[2][zz] * f;
+          for (int zz = 0; zz < kEsW; ++zz) {
+            const float f = fwin[b + zz];
+            rw += w[2][zz] * f;
+            rd += dw[2][zz] * f;
           }
+          sww += w[1][yy] * rw;
+          sdw += dw[1][yy] * rw;
+          swd += w[1][yy] * rd;
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          sww[c] += w[1][yy] * rw[c];
-          sdw[c] += dw[1][yy] * rw[c];
-          swd[c] += w[1][yy] * rd[c];
-        }
+        A += w[0][xx] * sww;
+        dA[0] += dw[0][xx] * sww;
+        dA[1] += w[0][xx] * sdw;
+        dA[2] += w[0][xx] * swd;
       }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        A[c] += w[0][xx] * sww[c];
-        dA[c][0] += dw[0][xx] * sww[c];
-        dA[c][1] += w[0][xx] * sdw[c];
-        dA[c][2] += w[0][xx] * swd[c];
-      }
-    }
-    float u[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float vb = a.vbar[ps + c * N + i];
-      u[c] = be * vb;
-      a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A[c]) / al;
+      const float vb = a.vbar[ps + c * N + i];
+      const float u = be * vb;
+      a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A) / al;
       a.vbar[ps + c * N + i] = al * vb;
-      a.u_sorted[ps + c * N + p] = u[c];
-      umax = fmaxf(umax, fabsf(u[c]));
-    }
+      a.u_sorted[ps + c * N + p] = u;
+      umax = fmaxf(umax, fabsf(u));
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-      a.xbar[ps + d * N + i] += r * (u[0] * dA[0][d] + u[1] * dA[1][d] + u[2] * dA[2][d]);
+      for (int d = 0; d < 3; ++d) a.xbar[ps + d * N + i] += r * u * dA[d];
+    }
   }
   red[threadIdx.x] = umax;
   __syncthreads();
@@ -972,10 +964,10 @@ hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
     k_tile_es_deposit<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_KICK) {
-    size_t lds = (size_t)3 * W * W * W * sizeof(float);
+    size_t lds = (size_t)W * W * W * sizeof(float);
     k_tile_es_kick<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_ADJ_KICK) {
-    size_t lds = (size_t)3 * W * W * W * sizeof(float);
+    size_t lds = (size_t)W * W * W * sizeof(float);
     k_tile_es_adj_kick<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_DIPOLE) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
