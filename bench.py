@@ -7,8 +7,10 @@ CIC density and its binned P(k), the loss cotangent (L2 distance to a fixed
 observed density), and the adjoint back to dL/dw and dL/dsigma8.
 value = particle-steps/s of forward + adjoint = N n_steps K / t(K steps).
 
-Default workload: 256^3 particles on a 512^3 mesh, L = 500 Mpc/h, flat LCDM
-with BBKS, TSC with deconvolution, 10 steps (FP32 bulk, int64 deposit).
+Default workload: 512^3 particles, L = 1000 Mpc/h, flat LCDM with BBKS, the
+NUFFT force (exponential-of-semicircle width 6 on the 2x upsampled 1024^3
+grid, exact i k), 6 BullFrog steps (FP32 bulk, int64 fixed-point spreading).
+The PM workloads (TSC/CIC with finite differences) are selectable.
 """
 from __future__ import annotations
 
@@ -142,28 +144,39 @@ def rooflines(cfg, kt, steps):
     return out
 
 
-def cpu_baseline():
-    """The FP64 oracle (untuned), same physics at a bounded size."""
+def cpu_baseline(cfg):
+    """The FP64 oracle (untuned) on the same physics at a bounded size: one
+    forward run plus the store-all reverse pass, single-threaded."""
     import numpy as np
 
     from oracle import adjoint, philox
     from oracle.force import PMConfig
     from oracle.nbody import Problem
 
-    n_p, n_g, box, steps = 64, 128, 125.0, 4
-    pm = PMConfig(n_p, n_g, box, order=3, deconvolve=True, grad_order=4, lap_order=0)
-    prob = Problem(pm, omega_m=0.31, h=0.68, n_s=0.965, sigma8=0.81, spectrum="bbks",
-                   a_start=0.02, a_end=1.0, n_steps=steps)
+    if cfg.force == "nufft":
+        n_p, n_g, steps = 32, 64, cfg.n_steps
+        kw = dict(force="nufft", es_width=cfg.es_width, es_beta=cfg.es_beta)
+        what = f"NUFFT ES width {cfg.es_width}, fine grid {n_g}^3"
+    else:
+        n_p, n_g, steps = 64, 128, 4
+        kw = {}
+        what = f"{'TSC' if cfg.mak == 3 else 'CIC'} on {n_g}^3, FD{cfg.grad_order}"
+    box = cfg.box * n_p / cfg.n_p          # same mass resolution
+    pm = PMConfig(n_p, n_g, box, order=cfg.mak, deconvolve=cfg.deconvolve, grad_order=max(cfg.grad_order, 2),
+                  lap_order=cfg.lap_order)
+    prob = Problem(pm, omega_m=cfg.omega_m, h=cfg.h, n_s=cfg.n_s, sigma8=cfg.sigma8, spectrum=cfg.spectrum,
+                   a_start=cfg.a_start, a_end=cfg.a_end, n_steps=steps, **kw)
     w = philox.white_noise(54321, n_p).astype(np.float64)
     prob.spectrum_fn(), prob.steps()
-    t = time.perf_counter()
-    adjoint.gradient(prob, w, lambda d: 2.0 * d)
-    dt = time.perf_counter() - t
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):      # the reported core count is the one used
+        t = time.perf_counter()
+        adjoint.gradient(prob, w, lambda d: 2.0 * d)
+        dt = time.perf_counter() - t
     return {"value": n_p ** 3 * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 numpy oracle, same physics at {n_p}^3 particles / {n_g}^3 mesh "
-                      f"(L={box} Mpc/h, TSC+deconv, BBKS), {steps} BullFrog steps forward + "
-                      f"store-all reverse, {dt:.1f} s single-threaded on a host with "
-                      f"{os.cpu_count()} cores"}
+            "sample": f"FP64 numpy oracle, same physics at {n_p}^3 particles ({what}, L={box:g} Mpc/h, BBKS), "
+                      f"{steps} BullFrog steps forward + store-all reverse, {dt:.1f} s single-threaded on a "
+                      f"host with {os.cpu_count()} cores"}
 
 
 def serve_bench(n_requests, budget_gb):
@@ -211,7 +224,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="pm_256_512_tsc", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="nufft_512_1024_es6", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -317,7 +330,7 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in kt.items()},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)
 
 
