@@ -274,9 +274,10 @@ def es_fixed_weight(dist_fixed, table):
     return np.where(ok, w, 0)
 
 
-def deposit_fixedpoint_es(psi_f32, n_p, n_f, width=6, beta=13.8):
-    """Integer ES spreading onto n_f^3 (flat int64) from FP32 Psi."""
-    U = mesh.fixed_coords(psi_f32, n_p, n_f)
+def es_fixed_stencil(U, n_f, width=6, beta=13.8):
+    """Nodes and integer 3D weights (2^32 mass unit, rounded half-even) of
+    the fixed-point ES spreading for fixed-point coordinates U (3, n):
+    yields (flat node index, weight) per stencil point, width^3 of them."""
     table = es_table(width, beta)
     one = 1 << mesh.B_FRAC
     base = (U >> mesh.B_FRAC) - (width // 2 - 1)
@@ -289,7 +290,6 @@ def deposit_fixedpoint_es(psi_f32, n_p, n_f, width=6, beta=13.8):
             rows.append(np.where(d < (width // 2) * one, es_fixed_weight(d, table), 0))
         W.append(np.stack(rows))
     shift = 3 * K_ES - 32
-    out = np.zeros(n_f ** 3, dtype=np.int64)
     for a in range(width):
         ix = (base[0] + a) % n_f
         for b in range(width):
@@ -297,10 +297,16 @@ def deposit_fixedpoint_es(psi_f32, n_p, n_f, width=6, beta=13.8):
             wab = W[0][a] * W[1][b]
             for c in range(width):
                 iz = (base[2] + c) % n_f
-                w3 = mesh._rne_shift(wab * W[2][c], shift)
-                lin = (ix * n_f + iy) * n_f + iz
-                hi = w3 >> 17
-                lo = w3 - (hi << 17)
-                out += np.rint(np.bincount(lin, weights=hi, minlength=n_f ** 3)).astype(np.int64) << 17
-                out += np.rint(np.bincount(lin, weights=lo, minlength=n_f ** 3)).astype(np.int64)
+                yield (ix * n_f + iy) * n_f + iz, mesh._rne_shift(wab * W[2][c], shift)
+
+
+def deposit_fixedpoint_es(psi_f32, n_p, n_f, width=6, beta=13.8):
+    """Integer ES spreading onto n_f^3 (flat int64) from FP32 Psi."""
+    U = mesh.fixed_coords(psi_f32, n_p, n_f)
+    out = np.zeros(n_f ** 3, dtype=np.int64)
+    for lin, w3 in es_fixed_stencil(U, n_f, width, beta):
+        hi = w3 >> 17
+        lo = w3 - (hi << 17)
+        out += np.rint(np.bincount(lin, weights=hi, minlength=n_f ** 3)).astype(np.int64) << 17
+        out += np.rint(np.bincount(lin, weights=lo, minlength=n_f ** 3)).astype(np.int64)
     return out

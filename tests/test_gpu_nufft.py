@@ -184,3 +184,63 @@ def test_nufft_gradient_matches_finite_differences():
     # reports for its FP32 adjoint; the oracle comparison above pins the
     # arithmetic at 32^3
     assert np.median(rel) < 2e-2 and ok.sum() >= 12 and cos > 0.999
+
+
+def test_es_spreading_full_size_sampled_cells():
+    """The 512^3 / 1024^3 launch of the headline workload: 64 sampled cells of
+    the fixed-point ES spreading against the oracle, which evaluates only the
+    particles whose 6^3 stencil can reach them; total mass and determinism."""
+    d = synth.C3
+    n_p, n_f = d["n_p"], d["n_g"]
+    say("ES spreading full size", n_p, n_f)
+    sim = make_sim(d)
+    psi = synth.displacements(n_p, 31, 1.5)
+    m = sim.deposit(torch.from_numpy(psi), 6)
+    rng = np.random.default_rng(1)
+    cells = np.unique(rng.integers(0, n_f ** 3, 64))
+    got = m[0, torch.from_numpy(cells).to(m.device)].cpu().numpy()
+    # fixed-point coordinates of every particle, in chunks; keep the ones
+    # whose home node lies within the stencil reach of a sampled cell
+    cx, cy, cz = cells // (n_f * n_f), (cells // n_f) % n_f, cells % n_f
+    # home nodes h whose stencil h-2 .. h+3 reaches a sampled cell
+    o = np.arange(-3, 3)
+    reach = np.unique((((cx[:, None, None, None] + o[None, :, None, None]) % n_f * n_f
+                        + (cy[:, None, None, None] + o[None, None, :, None]) % n_f) * n_f
+                       + (cz[:, None, None, None] + o[None, None, None, :]) % n_f).ravel())
+    acc = {int(c): 0 for c in cells}
+    chunk = 1 << 22
+    N = n_p ** 3
+    for s in range(0, N, chunk):
+        idx = np.arange(s, min(s + chunk, N))
+        lat = np.stack([idx // (n_p * n_p), (idx // n_p) % n_p, idx % n_p])
+        r = n_f // n_p
+        frac = np.rint(psi[:, idx].astype(np.float64) * (r * 2.0 ** 20)).astype(np.int64)
+        U = np.mod(lat * (r << 20) + frac, n_f << 20)
+        h = U >> 20
+        near = np.isin((h[0] * n_f + h[1]) * n_f + h[2], reach)
+        if not near.any():
+            continue
+        for lin, w3 in onufft.es_fixed_stencil(U[:, near], n_f):
+            for c, wv in zip(lin, w3):
+                if int(c) in acc:
+                    acc[int(c)] += int(wv)
+    ref = np.array([acc[int(c)] for c in cells])
+    assert np.array_equal(got, ref)
+    # total mass: every particle's ES weights summed in the fixed-point spec
+    # is not N 2^32 (the kernel is not a partition of unity), so compare two
+    # launches bit for bit instead
+    m2 = sim.deposit(torch.from_numpy(psi), 6)
+    assert torch.equal(m, m2)
+
+
+def test_nufft_force_full_size_conserves_momentum():
+    """512^3 particles on the 1024^3 fine grid: the net NUFFT force vanishes
+    (the multiplier is odd and spreading/interpolation share one kernel)."""
+    d = synth.C3
+    sim = make_sim(d)
+    psi = synth.displacements(d["n_p"], 32, 1.5)
+    a = sim.force(torch.from_numpy(psi), 1.0)[0].double()
+    net = a.sum(dim=1).abs().max().item()
+    scale = a.abs().sum(dim=1).max().item()
+    say(f"full-size NUFFT net force {net:.3e} of {scale:.3e}")
+    assert net < 1e-6 * scale and torch.isfinite(a).all()
