@@ -196,7 +196,8 @@ def serve_bench(n_requests, budget_gb):
     trace = serve.make_trace(n_requests, rate=rate, seed=2000)
     seq, st_seq = serve.serve_sequential(trace, targets)
     bat, st_bat = serve.serve_batched(trace, hbm_budget_gb=budget_gb, targets=targets)
-    ls, lb = serve.latency_stats(seq, st_seq["makespan_s"]), serve.latency_stats(bat, st_bat["makespan_s"])
+    ls, lb = (serve.latency_stats(seq, st_seq["makespan_s"], trace),
+              serve.latency_stats(bat, st_bat["makespan_s"], trace))
     # the same request alone and in the mix gives the same bits
     a = {r.rid: r for r in seq}
     same = all((np.array_equal(r.pk, a[r.rid].pk) if r.kind == "pk"

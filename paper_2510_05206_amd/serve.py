@@ -335,8 +335,16 @@ def serve_sequential(requests, targets=None):
     return results, {"makespan_s": now(), "mean_service_s": float(np.mean(service))}
 
 
-def latency_stats(results, makespan):
+def latency_stats(results, makespan, requests=None):
     lat = np.array([r.latency for r in results])
-    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_ms": float(lat.mean() * 1e3), "throughput_rps": len(results) / makespan,
-            "completed": len(results)}
+    out = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "mean_ms": float(lat.mean() * 1e3), "throughput_rps": len(results) / makespan,
+           "completed": len(results)}
+    if requests is not None:  # per (kind, size) class
+        size = {q.rid: q.n_p for q in requests}
+        by = {}
+        for r in results:
+            by.setdefault(f"{r.kind}_{size[r.rid]}", []).append(r.latency)
+        out["by_class"] = {k: {"n": len(v), "p50_ms": float(np.percentile(v, 50) * 1e3),
+                               "p99_ms": float(np.percentile(v, 99) * 1e3)} for k, v in sorted(by.items())}
+    return out
