@@ -4,7 +4,7 @@ A request asks for the binned P(k) of one simulated universe ("pk") or for
 the gradient of an L2 density loss with respect to its white noise and sigma8
 ("grad"), with its own particle count, sigma8, number of BullFrog steps and
 seed.  The loop keeps one context per (shape, kind) bucket with B slots
-(sized by the HBM budget), each on its own HIP stream:
+(sized by the HBM budget); buckets share four HIP streams by size class:
 
 * forward buckets batch continuously: a request that arrives while others
   run is admitted into a free slot (ICs for that slot only), all busy slots
@@ -109,9 +109,9 @@ class Targets:
 # ------------------------------------------------------------ batched loop
 
 class _PkBucket:
-    def __init__(self, n_p, B):
+    def __init__(self, n_p, B, stream):
         self.n_p, self.B = n_p, B
-        self.stream = torch.cuda.Stream()
+        self.stream = stream
         with torch.cuda.stream(self.stream):
             self.sim = PMSim(shape_config(n_p, B), with_adjoint=False)
         self.req = [None] * B
@@ -187,9 +187,9 @@ class _PkBucket:
 
 
 class _GradBucket:
-    def __init__(self, n_p, B, targets):
+    def __init__(self, n_p, B, targets, stream):
         self.n_p, self.B = n_p, B
-        self.stream = torch.cuda.Stream()
+        self.stream = stream
         with torch.cuda.stream(self.stream):
             self.sim = PMSim(shape_config(n_p, B), with_adjoint=True)
         self.queue = deque()
@@ -270,8 +270,16 @@ def serve_batched(requests, hbm_budget_gb=160.0, max_batch=16, targets=None):
     targets = targets or Targets()
     sizes = sorted({r.n_p for r in requests})
     plan = plan_batches(hbm_budget_gb * 1e9, max_batch, MIX_N, MIX_W)
-    pk_b = {n: _PkBucket(n, plan[("pk", n)]) for n in sizes}
-    gr_b = {n: _GradBucket(n, plan[("grad", n)], targets) for n in sizes}
+    # four streams, one per hardware queue of the device (default priority):
+    # small P(k), small gradients, 128^3, 256^3; a long large-request launch
+    # sequence then never sits in front of a small request in one queue
+    lanes = [torch.cuda.Stream() for _ in range(4)]
+
+    def lane(kind, n):
+        return lanes[0 if (n <= 64 and kind == "pk") else 1 if n <= 64 else 2 if n <= 128 else 3]
+
+    pk_b = {n: _PkBucket(n, plan[("pk", n)], lane("pk", n)) for n in sizes}
+    gr_b = {n: _GradBucket(n, plan[("grad", n)], targets, lane("grad", n)) for n in sizes}
     torch.cuda.synchronize()
     reqs = deque(sorted(requests, key=lambda r: r.arrival))
     results = []
