@@ -4,12 +4,13 @@ A request asks for the binned P(k) of one simulated universe ("pk") or for
 the gradient of an L2 density loss with respect to its white noise and sigma8
 ("grad"), with its own particle count, sigma8, number of BullFrog steps and
 seed.  The loop keeps one context per (shape, kind) bucket with B slots
-(sized by the HBM budget); buckets share four HIP streams by size class:
+(sized by the HBM budget), each on its own HIP stream:
 
 * forward buckets batch continuously: a request that arrives while others
   run is admitted into a free slot (ICs for that slot only), all busy slots
-  advance one BullFrog step per launch whatever their step index, and a slot
-  that finishes is read out and refilled at once;
+  advance one BullFrog step per launch whatever their step index (up to three
+  steps queued ahead of the host loop), and a slot that finishes is read out
+  and refilled at once;
 * gradient buckets run the requests waiting at launch time as one batch
   (forward, loss cotangent, adjoint), because the adjoint integrates every
   slot of a context backwards together.
@@ -109,6 +110,8 @@ class Targets:
 # ------------------------------------------------------------ batched loop
 
 class _PkBucket:
+    AHEAD = 3  # steps queued ahead of the host loop
+
     def __init__(self, n_p, B, stream):
         self.n_p, self.B = n_p, B
         self.stream = stream
@@ -146,8 +149,8 @@ class _PkBucket:
     def advance(self):
         """Enqueue one step for every slot that still has steps to run, then
         the read-out of the slots that just finished."""
-        if any(p[0] is not None and not p[0].query() for p in self.pending[-1:]):
-            return  # keep at most one step in flight per bucket
+        if sum(1 for p in self.pending if not p[0].query()) >= self.AHEAD:
+            return  # at most AHEAD steps in flight per bucket
         idx = [self.k[b] if (self.req[b] is not None and self.k[b] < self.steps[b]) else -1
                for b in range(self.B)]
         if all(i < 0 for i in idx):
@@ -270,16 +273,8 @@ def serve_batched(requests, hbm_budget_gb=160.0, max_batch=16, targets=None):
     targets = targets or Targets()
     sizes = sorted({r.n_p for r in requests})
     plan = plan_batches(hbm_budget_gb * 1e9, max_batch, MIX_N, MIX_W)
-    # four streams, one per hardware queue of the device (default priority):
-    # small P(k), small gradients, 128^3, 256^3; a long large-request launch
-    # sequence then never sits in front of a small request in one queue
-    lanes = [torch.cuda.Stream() for _ in range(4)]
-
-    def lane(kind, n):
-        return lanes[0 if (n <= 64 and kind == "pk") else 1 if n <= 64 else 2 if n <= 128 else 3]
-
-    pk_b = {n: _PkBucket(n, plan[("pk", n)], lane("pk", n)) for n in sizes}
-    gr_b = {n: _GradBucket(n, plan[("grad", n)], targets, lane("grad", n)) for n in sizes}
+    pk_b = {n: _PkBucket(n, plan[("pk", n)], torch.cuda.Stream()) for n in sizes}
+    gr_b = {n: _GradBucket(n, plan[("grad", n)], targets, torch.cuda.Stream()) for n in sizes}
     torch.cuda.synchronize()
     reqs = deque(sorted(requests, key=lambda r: r.arrival))
     results = []
