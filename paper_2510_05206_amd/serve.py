@@ -4,7 +4,9 @@ A request asks for the binned P(k) of one simulated universe ("pk") or for
 the gradient of an L2 density loss with respect to its white noise and sigma8
 ("grad"), with its own particle count, sigma8, number of BullFrog steps and
 seed.  The loop keeps one context per (shape, kind) bucket with B slots
-(sized by the HBM budget), each on its own HIP stream:
+(sized by the HBM budget), each on its own HIP stream (streams shared
+between buckets measured slower: a bucket's queued steps then wait for the
+other bucket's work):
 
 * forward buckets batch continuously: a request that arrives while others
   run is admitted into a free slot (ICs for that slot only), all busy slots
