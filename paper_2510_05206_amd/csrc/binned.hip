@@ -222,9 +222,10 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
     acc = win_sum(slab, win_cover(x, T, R, a.log2T, ntm), win_cover(y, T, R, a.log2T, ntm),
                   win_cover(z, T, R, a.log2T, ntm), W, 1 << a.log2nt);
   }
-  if constexpr (OUT_F32)
-    reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = (float)((double)acc * a.inv_scale[slot]);
-  else
+  if constexpr (OUT_F32) {
+    const double v = a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift;
+    reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = (float)v;
+  } else
     reinterpret_cast<long long*>(a.out)[slot * a.g.mesh_stride + e] = acc;
 }
 

@@ -4,15 +4,7 @@
 
 namespace pm {
 
-enum { SRC_I64 = 0, SRC_F32 = 1, SRC_WIN = 2 };
-
-// SRC_WIN: the R2C reads the mesh as the sum of int64 tile windows
-// (windows.h) instead of an assembled mesh; value = sum * scale - shift, or
-// sum * wscale[slot] when wscale is set
-struct RowWin {
-  int T, R, log2T, log2nt, n_tiles;
-  const double* wscale;
-};
+enum { SRC_I64 = 0, SRC_F32 = 1 };
 enum { DST_F32 = 0, DST_IC = 1 };
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4, MODE_NUFFT_C = 5,
        MODE_NUFFT_ADJ = 6 };
@@ -37,7 +29,6 @@ struct RowLaunch {
   // pruning (truncated spectra): R2C writes and C2R reads only k < kz_lim
   // (the rest is zero); 0 = the whole half row
   int kz_lim;
-  RowWin win;
   int ic_log2pb;         // DST_IC: particle arrays in lattice blocks of 2^ic_log2pb (mak.h)
   hipStream_t stream;
 };

@@ -19,7 +19,6 @@
 // (Sec. "Force evaluation"; the Poisson solve in Fourier space).
 #include "fft.h"
 #include "fft_reg.h"
-#include "windows.h"
 #include "mak.h"
 
 namespace pm {
@@ -235,14 +234,12 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
 // in registers (fft_reg.h, RowShape).  SRC selects the input conversion:
 //   SRC_I64:  (double)m * scale - shift   (int64 fixed-point mass mesh)
 //   SRC_F32:  f * (float)scale            (float mesh)
-//   SRC_WIN:  the int64 tile-window sums of each cell, as SRC_I64 (or times
-//             the per-slot wscale)
 template <int L, int P, int SRC>
 __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ src, long long src_stride,
                                                       float2* __restrict__ dst, long long dst_stride,
                                                       int n_rows, const float2* __restrict__ tw, int tws_half,
                                                       int tws_full, double scale, double shift,
-                                                      unsigned long long active, int rs, int kz_lim, RowWin win) {
+                                                      unsigned long long active, int rs, int kz_lim) {
   using S = freg::RowShape<L, P>;
   constexpr int n = 2 * L;
   __shared__ float2 lds[S::LDS];
@@ -251,33 +248,6 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
   const int n1 = S::lane_n1(threadIdx.x), c = S::lane_c(threadIdx.x);
   const long long row = (long long)blockIdx.x * S::R + c;
   const bool valid = row < n_rows;
-  // SRC_WIN (T > 2R): the up to 2 x 2 windows covering this row's (x, y),
-  // as base offsets with a validity flag each
-  [[maybe_unused]] long long bxy[4] = {0, 0, 0, 0};
-  [[maybe_unused]] bool vxy[4] = {false, false, false, false};
-  [[maybe_unused]] const long long* slab = nullptr;
-  [[maybe_unused]] double wsc = scale, wsh = shift;
-  [[maybe_unused]] long long W3 = 0;
-  if constexpr (SRC == SRC_WIN) {
-    const int ntm = (1 << win.log2nt) - 1, W = win.T + 2 * win.R;
-    W3 = (long long)W * W * W;
-    const Cover2 cx = cover2((int)(row / n), win.T, win.R, win.log2T, ntm);
-    const Cover2 cy = cover2((int)(row % n), win.T, win.R, win.log2T, ntm);
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int tx = p ? cx.t1 : cx.t0, lx = p ? cx.l1 : cx.l0;
-        const int ty = q ? cy.t1 : cy.t0, ly = q ? cy.l1 : cy.l0;
-        bxy[2 * p + q] = slab_row(tx, ty, 0, lx, ly, W, 1 << win.log2nt);  // the row's run over all tz
-        vxy[2 * p + q] = (p == 0 || cx.two) && (q == 0 || cy.two);
-      }
-    slab = reinterpret_cast<const long long*>(src) + (long long)slot * win.n_tiles * W3;
-    if (win.wscale) {
-      wsc = win.wscale[slot];
-      wsh = 0.0;
-    }
-  }
   float2 v[S::E];
 #pragma unroll
   for (int r = 0; r < S::E; ++r) {
@@ -285,23 +255,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows_reg(const void* __restrict__ s
     float2 z = make_float2(0.f, 0.f);
     if (valid) {
       const long long gi = slot * src_stride + row * n + 2 * t;
-      if constexpr (SRC == SRC_WIN) {
-        const int ntm = (1 << win.log2nt) - 1;
-        long long m[2] = {0, 0};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const Cover2 cz = cover2(2 * t + h, win.T, win.R, win.log2T, ntm);
-          const int W = win.T + 2 * win.R;
-          const long long z0 = cz.t0 * W + cz.l0, z1 = cz.t1 * W + cz.l1;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            if (!vxy[k]) continue;
-            m[h] += slab[bxy[k] + z0];
-            if (cz.two) m[h] += slab[bxy[k] + z1];
-          }
-        }
-        z = make_float2((float)((double)m[0] * wsc - wsh), (float)((double)m[1] * wsc - wsh));
-      } else if constexpr (SRC == SRC_I64) {
+      if constexpr (SRC == SRC_I64) {
         const longlong2 m = *reinterpret_cast<const longlong2*>(reinterpret_cast<const long long*>(src) + gi);
         z = make_float2((float)((double)m.x * scale - shift), (float)((double)m.y * scale - shift));
       } else {
@@ -365,12 +319,24 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
   const float2* in = src + slot * src_stride + row * rs;
   // pack: Z[k] = (X[k] + conj X[L-k]) + i e^{+2 pi i k/n} (X[k] - conj X[L-k])
   const int klim = kz_lim > 0 ? kz_lim : L + 1;
-  for (int k = n1; k <= L / 2; k += P) {
-    float2 xk = make_float2(0.f, 0.f), xm = xk;
-    if (valid) {
-      if (k < klim) xk = in[k];
-      if (L - k < klim) xm = in[L - k];
+  // all of this thread's loads first (k = n1 + P q), then the arithmetic
+  constexpr int NK = L / 2 / P + 1;
+  float2 xks[NK], xms[NK];
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    const int k = n1 + P * q;
+    xks[q] = make_float2(0.f, 0.f);
+    xms[q] = xks[q];
+    if (valid && k <= L / 2) {
+      if (k < klim) xks[q] = in[k];
+      if (L - k < klim) xms[q] = in[L - k];
     }
+  }
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    const int k = n1 + P * q;
+    if (k > L / 2) continue;
+    const float2 xk = xks[q], xm = xms[q];
     const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);
     const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
     float2 w = tw[k * tws_full];
@@ -565,15 +531,11 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
     if (r.src_mode == SRC_I64)
       k_r2c_rows_reg<L, P, SRC_I64><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
                                                                 r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                r.shift, r.active, r.rs, r.kz_lim, r.win);
-    else if (r.src_mode == SRC_F32)
+                                                                r.shift, r.active, r.rs, r.kz_lim);
+    else
       k_r2c_rows_reg<L, P, SRC_F32><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
                                                                 r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                r.shift, r.active, r.rs, r.kz_lim, r.win);
-    else
-      k_r2c_rows_reg<L, P, SRC_WIN><<<grid, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
-                                                                r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                r.shift, r.active, r.rs, r.kz_lim, r.win);
+                                                                r.shift, r.active, r.rs, r.kz_lim);
   }
   return hipGetLastError();
 }

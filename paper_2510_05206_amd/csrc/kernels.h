@@ -57,8 +57,11 @@ struct AssembleArgs {
   unsigned long long active;
   int T, R, log2T, log2nt, n_tiles;
   const void* scratch;
-  void* out;               // int64 mesh, or float mesh scaled by inv_scale
+  void* out;               // int64 mesh, or float mesh (below)
+  // float output: acc * inv_scale[slot] when inv_scale is set (fixed-point
+  // dipole meshes), else (double)acc * scale - shift (mass meshes)
   const double* inv_scale;
+  double scale, shift;
 };
 
 hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s);

@@ -297,12 +297,11 @@ unsigned long long all_mask(int B) { return B >= 64 ? ~0ull : ((1ull << B) - 1);
 // the rows keep k_z < prune/2 and the y pass writes only the kept k_y
 pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_stride, double scale,
                    double shift, float2* dst, long long dst_stride, int n, bool do_x,
-                   unsigned long long active, int prune = 0, const RowWin* win = nullptr) {
+                   unsigned long long active, int prune = 0) {
   RowLaunch r{};
   r.n = n;
   r.rs = spec_rs(n);
   r.kz_lim = prune / 2;
-  if (win) r.win = *win;
   r.n_rows = (long long)n * n;
   r.batch = c->cfg.batch;
   r.inverse = false;
@@ -449,21 +448,6 @@ AssembleArgs assemble_args(pm_ctx* c, int R, void* out, unsigned long long activ
   return a;
 }
 
-// From n = 32 on the force chain never assembles a mesh: the R2C rows sum
-// the tile windows themselves (SRC_WIN), which saves a mesh write and read
-bool fuse_windows(const pm_ctx* c) { return c->cfg.n_g >= 32; }
-
-RowWin row_win(const pm_ctx* c, int R, const double* wscale) {
-  RowWin w{};
-  w.T = c->T;
-  w.R = R;
-  w.log2T = c->log2T;
-  w.log2nt = c->log2nt;
-  w.n_tiles = c->n_tiles;
-  w.wscale = wscale;
-  return w;
-}
-
 // fixed-point deposit of `disp` (after binning) into the int64 mesh
 pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, int mak,
                   long long* mesh, unsigned long long active) {
@@ -484,21 +468,17 @@ pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* 
                     unsigned long long active) {
   if (c->cfg.force == PM_FORCE_NUFFT) return nufft_meshes(c, disp, vel_pre, tau, s, active);
   const double N = (double)c->g.N, n3 = (double)c->g.M;
-  pm_status st;
-  if (fuse_windows(c)) {
-    st = bin(c, disp, vel_pre, tau, c->cfg.mak, active);
-    if (st) return st;
-    TileArgs t = tile_args(c, disp, active);
-    KLAUNCH(c, PM_K_DEPOSIT, launch_tile(t, TK_DEPOSIT, c->cfg.mak, 0, c->stream));
-    const RowWin w = row_win(c, 1, nullptr);
-    st = r2c_mesh(c, c->scratch, SRC_WIN, 0, n3 / N / 4294967296.0, 1.0, c->spec, c->g.spec_stride,
-                  c->cfg.n_g, false, active, 0, &w);
-  } else {
-    st = deposit(c, disp, vel_pre, tau, c->cfg.mak, c->mesh, active);
-    if (st) return st;
-    st = r2c_mesh(c, c->mesh, SRC_I64, c->g.mesh_stride, n3 / N / 4294967296.0, 1.0, c->spec,
-                  c->g.spec_stride, c->cfg.n_g, false, active);
-  }
+  // the halo sum of the int64 windows writes the FP32 contrast directly
+  pm_status st = bin(c, disp, vel_pre, tau, c->cfg.mak, active);
+  if (st) return st;
+  TileArgs t = tile_args(c, disp, active);
+  float* rho = reinterpret_cast<float*>(c->mesh);
+  AssembleArgs as = assemble_args(c, 1, rho, active);
+  as.inv_scale = nullptr;
+  as.scale = n3 / N / 4294967296.0;
+  as.shift = 1.0;
+  KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile(t, TK_DEPOSIT, c->cfg.mak, 0, c->stream), launch_assemble(as, true, c->stream)));
+  st = r2c_mesh(c, rho, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, active);
   if (st) return st;
   return poisson_to_real(c, s, c->phi, active);
 }
@@ -515,18 +495,13 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   const double N = (double)c->g.N;
   const double ph0 = es_phihat(0.0, c->cfg.es_width, c->cfg.es_beta);
   const double mean = N * ph0 * ph0 * ph0 / (double)c->g.M;  // removes most of k = 0
-  if (fuse_windows(c)) {
-    KLAUNCH(c, PM_K_DEPOSIT, launch_tile_es(t, TK_ES_DEPOSIT, c->stream));
-    const RowWin w = row_win(c, 3, nullptr);
-    st = r2c_mesh(c, c->scratch, SRC_WIN, 0, 1.0 / 4294967296.0, mean, c->spec, c->g.spec_stride, n, false,
-                  active, np, &w);
-  } else {
-    AssembleArgs as = assemble_args(c, 3, c->mesh, active);
-    KLAUNCH(c, PM_K_DEPOSIT,
-            both(launch_tile_es(t, TK_ES_DEPOSIT, c->stream), launch_assemble(as, false, c->stream)));
-    st = r2c_mesh(c, c->mesh, SRC_I64, c->g.mesh_stride, 1.0 / 4294967296.0, mean, c->spec,
-                  c->g.spec_stride, n, false, active, np);
-  }
+  float* rho = reinterpret_cast<float*>(c->mesh);
+  AssembleArgs as = assemble_args(c, 3, rho, active);
+  as.inv_scale = nullptr;
+  as.scale = 1.0 / 4294967296.0;
+  as.shift = mean;
+  KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile_es(t, TK_ES_DEPOSIT, c->stream), launch_assemble(as, true, c->stream)));
+  st = r2c_mesh(c, rho, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, n, false, active, np);
   if (st) return st;
   ColArgs a{};
   a.data = c->spec;
@@ -1010,18 +985,10 @@ pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, co
   // particle (|phi| <= 1, |phi'| < 1 cell^-1)
   KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale, 3.0 * (double)N,
                                             B, c->stream));
-  pm_status st;
-  if (fuse_windows(c)) {
-    KLAUNCH(c, PM_K_DIPOLE, launch_tile_es(k, TK_ES_DIPOLE, c->stream));
-    const RowWin w = row_win(c, 3, c->inv_scale);
-    st = r2c_mesh(c, c->scratch, SRC_WIN, 0, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p, &w);
-  } else {
-    float* d = reinterpret_cast<float*>(c->mesh);
-    AssembleArgs as = assemble_args(c, 3, d, act);
-    KLAUNCH(c, PM_K_DIPOLE,
-            both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
-    st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p);
-  }
+  float* d = reinterpret_cast<float*>(c->mesh);
+  AssembleArgs as = assemble_args(c, 3, d, act);
+  KLAUNCH(c, PM_K_DIPOLE, both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
+  pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p);
   if (st) return st;
   // x pass: forward, real multiplier (n_f / n_p) (s / N) / (k^2 Phi^2), inverse
   ColArgs x{};
@@ -1108,18 +1075,10 @@ pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, co
   KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
                                             3.0 * fd_l1 * (double)N, B, c->stream));
   // transposed multiplier (H is real and even)
-  pm_status st;
-  if (fuse_windows(c)) {
-    KLAUNCH(c, PM_K_DIPOLE, launch_tile(k, TK_DIPOLE, mak, ord, c->stream));
-    const RowWin w = row_win(c, dipole_halo(ord), c->inv_scale);
-    st = r2c_mesh(c, c->scratch, SRC_WIN, 0, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act, 0, &w);
-  } else {
-    float* d = reinterpret_cast<float*>(c->mesh);
-    AssembleArgs as = assemble_args(c, dipole_halo(ord), d, act);
-    KLAUNCH(c, PM_K_DIPOLE,
-            both(launch_tile(k, TK_DIPOLE, mak, ord, c->stream), launch_assemble(as, true, c->stream)));
-    st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
-  }
+  float* d = reinterpret_cast<float*>(c->mesh);
+  AssembleArgs as = assemble_args(c, dipole_halo(ord), d, act);
+  KLAUNCH(c, PM_K_DIPOLE, both(launch_tile(k, TK_DIPOLE, mak, ord, c->stream), launch_assemble(as, true, c->stream)));
+  pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
   if (st) return st;
   st = poisson_to_real(c, s, c->phi, act);
   if (st) return st;
