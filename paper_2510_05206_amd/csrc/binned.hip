@@ -199,14 +199,15 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= a.g.M) return;
   const int L = a.g.log2_ng, nm = a.g.n_g - 1;
-  const int T = a.T, R = a.R, W = T + 2 * R;
+  const int T = a.T, Rlo = a.Rlo, Rhi = a.Rhi, W = T + Rlo + Rhi;
   const int ntm = (1 << a.log2nt) - 1;
   const int x = (int)(e >> (2 * L)), y = (int)((e >> L) & nm), z = (int)(e & nm);
   const long long W3 = (long long)W * W * W;
   const long long* slab = reinterpret_cast<const long long*>(a.scratch) + (long long)slot * a.n_tiles * W3;
   long long acc = 0;
-  if (2 * R < T) {  // at most two windows per axis: scalar covers
-    const Cover2 c[3] = {cover2(x, T, R, a.log2T, ntm), cover2(y, T, R, a.log2T, ntm), cover2(z, T, R, a.log2T, ntm)};
+  if (Rlo + Rhi <= T) {  // at most two windows per axis: scalar covers
+    const Cover2 c[3] = {cover2(x, T, Rlo, Rhi, a.log2T, ntm), cover2(y, T, Rlo, Rhi, a.log2T, ntm),
+                         cover2(z, T, Rlo, Rhi, a.log2T, ntm)};
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -219,8 +220,8 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
                       (r ? c[2].l1 : c[2].l0)];
         }
   } else {  // small meshes (one or two tiles per axis, wide halo)
-    acc = win_sum(slab, win_cover(x, T, R, a.log2T, ntm), win_cover(y, T, R, a.log2T, ntm),
-                  win_cover(z, T, R, a.log2T, ntm), W, 1 << a.log2nt);
+    acc = win_sum(slab, win_cover(x, T, Rlo, Rhi, a.log2T, ntm), win_cover(y, T, Rlo, Rhi, a.log2T, ntm),
+                  win_cover(z, T, Rlo, Rhi, a.log2T, ntm), W, 1 << a.log2nt);
   }
   if constexpr (OUT_F32) {
     const double v = a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift;
@@ -231,17 +232,17 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
 
 // ----------------------------------------------------- windowed gathers
 
-// stage mesh values over the tile + R cells each side into LDS
+// stage mesh values over the tile + Rlo cells below / Rhi above into LDS
 // Rows of W <= 32 consecutive z values: 8 groups of 32 lanes take rows
 // (lx, ly) in turn, each lane one z; 8 rows per group are loaded before any
 // is stored, so every thread keeps 8 HBM reads in flight.
-__device__ __forceinline__ void load_window(float* win, const float* mesh, const int o[3], int T, int R,
-                                            int L, int nm) {
+__device__ __forceinline__ void load_window(float* win, const float* mesh, const int o[3], int T, int Rlo,
+                                            int Rhi, int L, int nm) {
   constexpr int U = 8;
-  const int W = T + 2 * R, W2 = W * W;
+  const int W = T + Rlo + Rhi, W2 = W * W;
   const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
   const bool zok = lane < W;
-  const long long gz = (o[2] - R + lane) & nm;
+  const long long gz = (o[2] - Rlo + lane) & nm;
   for (int r0 = grp; r0 < W2; r0 += 8 * U) {
     float v[U];
 #pragma unroll
@@ -250,7 +251,7 @@ __device__ __forceinline__ void load_window(float* win, const float* mesh, const
       v[u] = 0.f;
       if (zok && r < W2) {
         const int lx = r / W, ly = r - lx * W;
-        const int gx = (o[0] - R + lx) & nm, gy = (o[1] - R + ly) & nm;
+        const int gx = (o[0] - Rlo + lx) & nm, gy = (o[1] - Rlo + ly) & nm;
         v[u] = mesh[((long long)((gx << L) + gy) << L) + gz];
       }
     }
@@ -293,7 +294,7 @@ __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
   if (!((a.active >> slot) & 1ull)) return;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
-  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, a.g.log2_ng, a.g.n_g - 1);
+  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, R, a.g.log2_ng, a.g.n_g - 1);
   __syncthreads();
   const WinAcc acc{win, a.T + 2 * R};
   const long long N = a.g.N, ps = slot * a.g.part_stride;
@@ -332,7 +333,7 @@ __global__ void __launch_bounds__(256) k_tile_adj_kick(TileArgs a) {
   if (!((a.active >> slot) & 1ull)) return;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
-  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, a.g.log2_ng, a.g.n_g - 1);
+  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, R, a.g.log2_ng, a.g.n_g - 1);
   __syncthreads();
   const WinAcc acc{win, a.T + 2 * R};
   const long long N = a.g.N, ps = slot * a.g.part_stride;
@@ -372,16 +373,23 @@ __global__ void __launch_bounds__(256) k_tile_adj_kick(TileArgs a) {
 }
 
 // fixed-point scale of the cotangent scatter: every node sum is bounded by
-// N max|u| sum|c_s| (times 3 components), kept below 2^61
+// N max|u| sum|c_s| (times 3 components), kept below 2^61; with
+// node_per_u > 0 every single node value (< node_per_u max|u|) is also kept
+// below 2^31
 __global__ void k_dipole_scale(const unsigned int* umax_bits, double* scale, double* inv_scale, double bound_per_u,
-                               int batch) {
+                               double node_per_u, int batch) {
   const int s = threadIdx.x;
   if (s >= batch) return;
-  double m = (double)__uint_as_float(umax_bits[s]) * bound_per_u;
-  int e = m > 0.0 ? ilogb(m) + 1 : 0;
-  if (e < -200) e = -200;
-  scale[s] = ldexp(1.0, 61 - e);
-  inv_scale[s] = ldexp(1.0, e - 61);
+  const double um = (double)__uint_as_float(umax_bits[s]);
+  const double m = um * bound_per_u;
+  int k = m > 0.0 ? 61 - (ilogb(m) + 1) : 200;
+  if (node_per_u > 0.0) {  // FP32 scaling on the device: a finite float power of two
+    if (um > 0.0) k = min(k, 31 - (ilogb(um * node_per_u) + 1));
+    k = min(k, 120);
+  }
+  if (k > 200) k = 200;
+  scale[s] = ldexp(1.0, k);
+  inv_scale[s] = ldexp(1.0, -k);
 }
 
 // transposed FD gather (mesh cotangent of the force), into an int64 window
@@ -453,7 +461,7 @@ __global__ void __launch_bounds__(256) k_tile_adj_drift(TileArgs a) {
   if (!((a.active >> slot) & 1ull)) return;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
-  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, a.g.log2_ng, a.g.n_g - 1);
+  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, R, a.g.log2_ng, a.g.n_g - 1);
   __syncthreads();
   const int W = a.T + 2;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
@@ -547,8 +555,8 @@ hipError_t launch_tile(const TileArgs& a, int kind, int mak, int ord, hipStream_
 }
 
 hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, double* inv_scale,
-                               double bound_per_u, int batch, hipStream_t s) {
-  k_dipole_scale<<<1, 64, 0, s>>>(umax_bits, scale, inv_scale, bound_per_u, batch);
+                               double bound_per_u, double node_per_u, int batch, hipStream_t s) {
+  k_dipole_scale<<<1, 64, 0, s>>>(umax_bits, scale, inv_scale, bound_per_u, node_per_u, batch);
   return hipGetLastError();
 }
 
@@ -565,94 +573,164 @@ hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s) {
 // integer linear interpolation in a table of phi at 4096 samples per cell
 // (20-bit values), so spreading is bit-reproducible; the 3D product is
 // rounded half-even to the 2^32 mass unit (no remainder: the ES kernel is not
-// a partition of unity).  Home node floor(u); window halo 3.
+// a partition of unity).  Home node floor(u); the window reaches 2 cells
+// below the tile and 3 above.
 namespace {
-constexpr int kEsW = 6, kEsR = 3, kEsShift = kFracBits - 12;  // 4096 samples per cell
+constexpr int kEsW = 6, kEsLo = kEsHaloLo, kEsHi = kEsHaloHi;
+constexpr int kEsShift = kFracBits - 12;  // 4096 samples per cell
+constexpr int kEsSub = (1 << kEsShift) - 1;
 
-__device__ __forceinline__ int es_weight(long long dist, const int32_t* __restrict__ tab) {
-  if (dist >= (long long)(kEsW / 2) << kFracBits) return 0;  // strictly inside |z| < 1
-  int i = (int)(dist >> kEsShift), f = (int)(dist & ((1 << kEsShift) - 1));
-  int t0 = tab[i], t1 = tab[i + 1];
+__device__ __forceinline__ int es_interp(int t0, int t1, int f) {
   return t0 + (((t1 - t0) * f + (1 << (kEsShift - 1))) >> kEsShift);
 }
 
-// integer weights of the 6 nodes floor(u) - 2 .. floor(u) + 3 on one axis
-__device__ __forceinline__ int es_weights(long long U, const int32_t* tab, int w[kEsW]) {
-  const long long h = U >> kFracBits;
-#pragma unroll
-  for (int o = 0; o < kEsW; ++o) {
-    long long d = ((h - 2 + o) << kFracBits) - U;
-    w[o] = es_weight(d < 0 ? -d : d, tab);
-  }
-  return (int)h;
+// Table rows of one axis.  With f = frac(u) in 2^-20 cells and g = 1 - f,
+// node floor(u) - m (m = 0, 1, 2) lies m + f cells from u and node
+// floor(u) + 1 + m lies m + g cells away; the host table's row k holds the
+// sample pairs at k + 4096 m, so row (f >> 8) serves the three nodes below
+// and row (g >> 8) the three above (g = 1 reads row 4096: exact 1, 2, 3
+// cells; phi is 0 at 3 cells).
+struct EsAxis {
+  int4 a0, b0;
+  int2 a1, b1;
+  int fa, fb;  // in-sample fractions (8 bits)
+  int f, g;    // distances of the nodes floor(u) and floor(u) + 1
+};
+
+__device__ __forceinline__ int es_axis(long long U, const int32_t* __restrict__ tab, EsAxis& e) {
+  e.f = (int)(U & ((1 << kFracBits) - 1));
+  e.g = (1 << kFracBits) - e.f;
+  const int32_t* ra = tab + 8 * (e.f >> kEsShift);
+  const int32_t* rb = tab + 8 * (e.g >> kEsShift);
+  e.a0 = *reinterpret_cast<const int4*>(ra);
+  e.a1 = *reinterpret_cast<const int2*>(ra + 4);
+  e.b0 = *reinterpret_cast<const int4*>(rb);
+  e.b1 = *reinterpret_cast<const int2*>(rb + 4);
+  e.fa = e.f & kEsSub;
+  e.fb = e.g & kEsSub;
+  return (int)(U >> kFracBits);
 }
 
-// float weights of the 6 nodes (the table values used by the spreading) and
-// d/du phi(u - node) from the kernel's closed form: with z = dist / 3 cells,
+// integer weights of the nodes floor(u) - 2 .. floor(u) + 3
+__device__ __forceinline__ void es_int_weights(const EsAxis& e, int w[kEsW]) {
+  w[0] = es_interp(e.a1.x, e.a1.y, e.fa);
+  w[1] = es_interp(e.a0.z, e.a0.w, e.fa);
+  w[2] = es_interp(e.a0.x, e.a0.y, e.fa);
+  w[3] = es_interp(e.b0.x, e.b0.y, e.fb);
+  w[4] = es_interp(e.b0.z, e.b0.w, e.fb);
+  w[5] = es_interp(e.b1.x, e.b1.y, e.fb);
+}
+
+__device__ __forceinline__ int es_weights(long long U, const int32_t* tab, int w[kEsW]) {
+  EsAxis e;
+  const int h = es_axis(U, tab, e);
+  es_int_weights(e, w);
+  return h;
+}
+
+// float weight and d/du phi(u - node) of one node at distance dist (2^-20
+// cells), from the kernel's closed form: with z = dist / 3 cells,
 // d phi / d dist = -phi beta z / (3 sqrt(1 - z^2)); 1 - z = (3 - dist) / 3 is
-// formed from the integer distance, so the edge of the support stays exact
+// formed from the integer distance, so the edge of the support stays exact.
+// below: the node lies below u (d dist / du = +1), else above (-1)
+__device__ __forceinline__ void es_node_d(int wi, int dist, bool below, float beta, float& w, float& dw) {
+  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
+  constexpr int kHalf = (kEsW / 2) << kFracBits;  // 3 cells
+  constexpr float kInvHalf = 1.0f / (float)kHalf;
+  if (dist >= kHalf) {
+    w = 0.f;
+    dw = 0.f;
+    return;
+  }
+  const float phi = (float)wi * inv;
+  w = phi;
+  const float z = (float)dist * kInvHalf, omz = (float)(kHalf - dist) * kInvHalf;
+  const float dphi = -phi * beta * z / ((float)(kEsW / 2) * sqrtf(omz * (1.f + z)));
+  dw = (below && dist > 0) ? dphi : -dphi;
+}
+
 __device__ __forceinline__ int es_weights_d(long long U, const int32_t* __restrict__ tab, float beta,
                                             float w[kEsW], float dw[kEsW]) {
-  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
-  constexpr long long kHalf = (long long)(kEsW / 2) << kFracBits;          // 3 cells
-  constexpr float kInvHalf = 1.0f / (float)((long long)(kEsW / 2) << kFracBits);
-  const long long h = U >> kFracBits;
-#pragma unroll
-  for (int o = 0; o < kEsW; ++o) {
-    long long d = ((h - 2 + o) << kFracBits) - U;  // node - u
-    long long dist = d < 0 ? -d : d;
-    if (dist >= kHalf) {
-      w[o] = 0.f;
-      dw[o] = 0.f;
-      continue;
-    }
-    int i = (int)(dist >> kEsShift), f = (int)(dist & ((1 << kEsShift) - 1));
-    int t0 = tab[i], t1 = tab[i + 1];
-    const float phi = (float)(t0 + (((t1 - t0) * f + (1 << (kEsShift - 1))) >> kEsShift)) * inv;
-    w[o] = phi;
-    const float z = (float)dist * kInvHalf, omz = (float)(kHalf - dist) * kInvHalf;
-    const float dphi = -phi * beta * z / ((float)(kEsW / 2) * sqrtf(omz * (1.f + z)));
-    dw[o] = d < 0 ? dphi : -dphi;  // d dist / du = sign(u - node)
-  }
-  return (int)h;
+  EsAxis e;
+  const int h = es_axis(U, tab, e);
+  int wi[kEsW];
+  es_int_weights(e, wi);
+  constexpr int one = 1 << kFracBits;
+  es_node_d(wi[0], 2 * one + e.f, true, beta, w[0], dw[0]);
+  es_node_d(wi[1], one + e.f, true, beta, w[1], dw[1]);
+  es_node_d(wi[2], e.f, true, beta, w[2], dw[2]);
+  es_node_d(wi[3], e.g, false, beta, w[3], dw[3]);
+  es_node_d(wi[4], one + e.g, false, beta, w[4], dw[4]);
+  es_node_d(wi[5], 2 * one + e.g, false, beta, w[5], dw[5]);
+  return h;
+}
+
+// round-half-even of a b c / 2^28 for 1D weights in [0, 2^20] (the
+// fixed-point mass of one node, <= 2^32), with ab = a b given as
+// ab = A1 2^24 + A0: four 24-bit multiplies and 32-bit rounding.
+__device__ __forceinline__ unsigned long long es_node_mass(unsigned A0, unsigned A1, unsigned c) {
+  const unsigned long long p0 = (unsigned long long)(A0 & 0xffffffu) * (c & 0xffffffu);
+  const unsigned long long p1 = (unsigned long long)(A1 & 0xffffffu) * (c & 0xffffffu);
+  const unsigned long long P = p0 + (p1 << 24);  // < 2^61
+  const unsigned hi = (unsigned)(P >> 32), lo = (unsigned)P;
+  unsigned q = (hi << 4) | (lo >> 28);          // floor(P / 2^28) mod 2^32
+  const unsigned rem = lo & 0x0fffffffu;
+  q += (rem + 0x07ffffffu + (q & 1u)) >> 28;    // half-even
+  return ((unsigned long long)(hi >> 28) << 32) | q;
 }
 }  // namespace
 
+// Particle loads are software-pipelined: the next particle's index and
+// coordinates are in flight while the current one scatters.
 __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
   extern __shared__ unsigned long long ewin[];
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + 2 * kEsR, W3 = W * W * W;
+  const int W = a.T + kEsLo + kEsHi, W3 = W * W * W;
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  int p = beg + threadIdx.x;
+  long long i = 0;
+  float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+  if (p < end) {
+    i = a.sorted[slot * N + p];
+    x0 = a.disp[ps + i];
+    x1 = a.disp[ps + N + i];
+    x2 = a.disp[ps + 2 * N + i];
+  }
   for (int e = threadIdx.x; e < W3; e += 256) ewin[e] = 0ull;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   __syncthreads();
-  const long long N = a.g.N, ps = slot * a.g.part_stride;
-  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
-  constexpr int shift = 3 * kWeightBits - kMassBits;
-  for (int p = beg + threadIdx.x; p < end; p += 256) {
-    const long long i = a.sorted[slot * N + p];
+  for (; p < end; p += 256) {
     long long j[3];
     lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+    const float xc[3] = {x0, x1, x2};
     int w[3][kEsW], l0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
-      int h = es_weights(U, a.es_tab, w[c]) & nm;
-      l0[c] = h - o[c] + kEsR - 2;
+      const long long U = fixed_coord(j[c], xc[c], a.g.log2_r, umask);
+      const int h = es_weights(U, a.es_tab, w[c]) & nm;
+      l0[c] = h - o[c];  // window-local node floor(u) - 2
     }
-    for (int x = 0; x < kEsW; ++x)
-      for (int y = 0; y < kEsW; ++y) {
-        unsigned long long wxy = (unsigned long long)w[0][x] * (unsigned)w[1][y];
-        if (!wxy) continue;
-        const int bxy = ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
+    if (p + 256 < end) {
+      i = a.sorted[slot * N + p + 256];
+      x0 = a.disp[ps + i];
+      x1 = a.disp[ps + N + i];
+      x2 = a.disp[ps + 2 * N + i];
+    }
 #pragma unroll
-        for (int z = 0; z < kEsW; ++z) {
-          unsigned long long v = rne_shift(wxy * (unsigned)w[2][z], shift);
-          if (v) atomicAdd(&ewin[bxy + z], v);
-        }
+    for (int x = 0; x < kEsW; ++x)
+#pragma unroll
+      for (int y = 0; y < kEsW; ++y) {
+        const unsigned long long ab =
+            (unsigned long long)((unsigned)w[0][x] & 0xffffffu) * ((unsigned)w[1][y] & 0xffffffu);  // <= 2^40
+        const unsigned A0 = (unsigned)ab & 0xffffffu, A1 = (unsigned)(ab >> 24);
+        unsigned long long* row = ewin + ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
+#pragma unroll
+        for (int z = 0; z < kEsW; ++z) atomicAdd(row + z, es_node_mass(A0, A1, (unsigned)w[2][z]));
       }
   }
   __syncthreads();
@@ -694,17 +772,17 @@ __device__ __forceinline__ void es_particle(const TileArgs& a, long long i, cons
     int wi[kEsW];
     long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
     int h = es_weights(U, a.es_tab, wi) & nm;
-    l0[c] = h - o[c] + kEsR - 2;
+    l0[c] = h - o[c];
 #pragma unroll
     for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
   }
 }
 
 __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
-  extern __shared__ float fwin[];  // one (T + 6)^3 window, the components in turn
+  extern __shared__ float fwin[];  // one (T + 5)^3 window, the components in turn
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + 2 * kEsR;
+  const int W = a.T + kEsLo + kEsHi;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   const long long N = a.g.N, ps = slot * a.g.part_stride;
@@ -714,7 +792,7 @@ __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
   const float al = a.alpha[slot], be = a.beta[slot], tp = a.tau[slot];
   for (int c = 0; c < 3; ++c) {
     if (c) __syncthreads();  // the previous component's reads are done
-    load_window(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsR, a.g.log2_ng, nm);
+    load_window(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsLo, kEsHi, a.g.log2_ng, nm);
     __syncthreads();
     for (int p = beg + threadIdx.x; p < end; p += 256) {
       const long long i = a.sorted[slot * N + p];
@@ -742,11 +820,11 @@ __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
 // gradient: V = (V - beta A) / alpha, V_bar = alpha V_bar, u = beta V_bar,
 // X_bar += r sum_c u_c dA_c/du; u kept in sorted order with max |u|
 __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
-  extern __shared__ float fwin[];  // one (T + 6)^3 window, the components in turn
+  extern __shared__ float fwin[];  // one (T + 5)^3 window, the components in turn
   __shared__ float red[256];
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + 2 * kEsR;
+  const int W = a.T + kEsLo + kEsHi;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   const long long N = a.g.N, ps = slot * a.g.part_stride;
@@ -758,7 +836,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
   float umax = 0.f;
   for (int c = 0; c < 3; ++c) {
     if (c) __syncthreads();
-    load_window(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsR, a.g.log2_ng, nm);
+    load_window(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsLo, kEsHi, a.g.log2_ng, nm);
     __syncthreads();
     for (int p = beg + threadIdx.x; p < end; p += 256) {
       const long long i = a.sorted[slot * N + p];
@@ -770,7 +848,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
       for (int d = 0; d < 3; ++d) {
         long long U = fixed_coord(j[d], a.disp[ps + d * N + i], a.g.log2_r, umask);
         int h = es_weights_d(U, a.es_tab, a.es_beta, w[d], dw[d]) & nm;
-        l0[d] = h - o[d] + kEsR - 2;
+        l0[d] = h - o[d];
       }
       // separable contraction of the value and its gradient
       float A = 0.f, dA[3] = {0.f, 0.f, 0.f};
@@ -820,46 +898,72 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
 // along the cotangent u) for the adjoint's mesh term: the Fourier transform
 // of the spread gradient is -i k_c times that of the spread of u_c, so one
 // spread replaces the three per-component spreads and their transforms.
-// int64 fixed point at the scale set from max |u| (|phi| <= 1, |phi'| < 1).
+// Fixed point at the scale set from max |u|: each node value is below 2^31
+// (|phi| <= 1, |phi'| < 1 per cell, so |d| < 3 max|u|), rounded half-even in
+// FP32 and summed as int64 (order-free).
 __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
   extern __shared__ unsigned long long ewin[];
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + 2 * kEsR, W3 = W * W * W;
+  const int W = a.T + kEsLo + kEsHi, W3 = W * W * W;
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  int p = beg + threadIdx.x;
+  long long i = 0;
+  float u0 = 0.f, u1 = 0.f, u2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
+  if (p < end) {
+    i = a.sorted[slot * N + p];
+    u0 = a.u_sorted[ps + p];
+    u1 = a.u_sorted[ps + N + p];
+    u2 = a.u_sorted[ps + 2 * N + p];
+    x0 = a.disp[ps + i];
+    x1 = a.disp[ps + N + i];
+    x2 = a.disp[ps + 2 * N + i];
+  }
   for (int e = threadIdx.x; e < W3; e += 256) ewin[e] = 0ull;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   __syncthreads();
-  const long long N = a.g.N, ps = slot * a.g.part_stride;
-  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
-  const double S = a.scale[slot];
-  for (int p = beg + threadIdx.x; p < end; p += 256) {
-    const float u[3] = {a.u_sorted[ps + p], a.u_sorted[ps + N + p], a.u_sorted[ps + 2 * N + p]};
-    if (u[0] == 0.f && u[1] == 0.f && u[2] == 0.f) continue;
-    const long long i = a.sorted[slot * N + p];
+  const float S = (float)a.scale[slot];  // a power of two
+  for (; p < end; p += 256) {
+    const bool any = u0 != 0.f || u1 != 0.f || u2 != 0.f;
+    const float u[3] = {u0 * S, u1 * S, u2 * S};
     long long j[3];
     lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+    const float xc[3] = {x0, x1, x2};
     float w[3][kEsW], dw[3][kEsW];
     int l0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
-      int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
-      l0[c] = h - o[c] + kEsR - 2;
+      const long long U = fixed_coord(j[c], xc[c], a.g.log2_r, umask);
+      const int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
+      l0[c] = h - o[c];
     }
+    if (p + 256 < end) {
+      const int q = p + 256;
+      i = a.sorted[slot * N + q];
+      u0 = a.u_sorted[ps + q];
+      u1 = a.u_sorted[ps + N + q];
+      u2 = a.u_sorted[ps + 2 * N + q];
+      x0 = a.disp[ps + i];
+      x1 = a.disp[ps + N + i];
+      x2 = a.disp[ps + 2 * N + i];
+    }
+    if (!any) continue;
+#pragma unroll
     for (int x = 0; x < kEsW; ++x)
+#pragma unroll
       for (int y = 0; y < kEsW; ++y) {
         // v(z) = (u_x w0' w1 + u_y w0 w1') w2(z) + u_z w0 w1 w2'(z)
         const float pa = u[0] * dw[0][x] * w[1][y] + u[1] * w[0][x] * dw[1][y];
         const float pb = u[2] * w[0][x] * w[1][y];
-        if (pa == 0.f && pb == 0.f) continue;
-        const int bxy = ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
+        unsigned long long* row = ewin + ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
 #pragma unroll
         for (int z = 0; z < kEsW; ++z) {
-          long long v = llrint((double)(pa * w[2][z] + pb * dw[2][z]) * S);
-          if (v) atomicAdd(&ewin[bxy + z], (unsigned long long)v);
+          const int v = (int)rintf(pa * w[2][z] + pb * dw[2][z]);
+          atomicAdd(row + z, (unsigned long long)(long long)v);
         }
       }
   }
@@ -871,13 +975,13 @@ __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
 // X_bar += coef r sum_j b_bar_j d/du phi(u - j) (the spreading differentiated
 // w.r.t. the positions), then the reverse drift X -= tau V, V_bar += tau X_bar
 __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
-  extern __shared__ float bwin[];  // (T + 6)^3
+  extern __shared__ float bwin[];  // (T + 5)^3
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + 2 * kEsR;
+  const int W = a.T + kEsLo + kEsHi;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
-  load_window(bwin, a.mesh_in + slot * a.g.mesh_stride, o, a.T, kEsR, a.g.log2_ng, a.g.n_g - 1);
+  load_window(bwin, a.mesh_in + slot * a.g.mesh_stride, o, a.T, kEsLo, kEsHi, a.g.log2_ng, a.g.n_g - 1);
   __syncthreads();
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
@@ -895,7 +999,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
     for (int c = 0; c < 3; ++c) {
       long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
       int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
-      l0[c] = h - o[c] + kEsR - 2;
+      l0[c] = h - o[c];
     }
     float gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll
@@ -935,7 +1039,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
 // default, to its largest window (16^3 tiles); called once per bind, outside
 // any stream capture
 hipError_t configure_tile_kernels() {
-  constexpr int We = kTileMax + 2 * kEsR;
+  constexpr int We = kTileMax + kEsLo + kEsHi;
   const int es64 = We * We * We * 8, es32x3 = 3 * We * We * We * 4, es32 = We * We * We * 4;
   auto dip = [](int o) { int W = kTileMax + 2 * (1 + o / 2); return W * W * W * 8; };
   const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
@@ -960,7 +1064,7 @@ hipError_t configure_tile_kernels() {
 
 hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
   dim3 grid((unsigned)a.n_tiles, a.batch);
-  const int W = a.T + 2 * kEsR;
+  const int W = a.T + kEsLo + kEsHi;
   if (kind == TK_ES_DEPOSIT) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
     k_tile_es_deposit<<<grid, 256, lds, s>>>(a);

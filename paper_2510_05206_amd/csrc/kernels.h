@@ -55,7 +55,7 @@ struct AssembleArgs {
   Geom g;
   int batch;
   unsigned long long active;
-  int T, R, log2T, log2nt, n_tiles;
+  int T, Rlo, Rhi, log2T, log2nt, n_tiles;  // window halo below / above
   const void* scratch;
   void* out;               // int64 mesh, or float mesh (below)
   // float output: acc * inv_scale[slot] when inv_scale is set (fixed-point
@@ -70,7 +70,7 @@ hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s);
 hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s);
 hipError_t configure_tile_kernels();
 hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, double* inv_scale,
-                               double bound_per_u, int batch, hipStream_t s);
+                               double bound_per_u, double node_per_u, int batch, hipStream_t s);
 
 // auxiliary kernels (misc.hip)
 hipError_t launch_fill(void* p, long long bytes, hipStream_t s);

@@ -187,7 +187,7 @@ Layout layout(const pm_ctx* c, bool adj) {
   const bool nufft = c->cfg.force == PM_FORCE_NUFFT;
   long long W = T + 2;
   if (adj) W = std::max(W, (long long)T + 2 * dipole_halo(c->cfg.grad_order));
-  if (nufft) W = std::max(W, (long long)T + 6);
+  if (nufft) W = std::max(W, (long long)T + kEsHaloLo + kEsHaloHi);
   L.off_es_tab = take(sizeof(int32_t) * c->es_tab.size());
   L.off_esdec = take(sizeof(float) * n);
   L.off_force3 = nufft ? take(sizeof(float) * 3 * M * B) : 0;
@@ -234,15 +234,24 @@ void build_tables(pm_ctx* c) {
   }
   // NUFFT: exponential-of-semicircle table (phi at t/4096 cells, 20-bit
   // integers, round half even) and the deconvolution 1/phi_hat^2 on the modes
-  // strictly below the particle Nyquist mode (truncation: 0 elsewhere)
+  // strictly below the particle Nyquist mode (truncation: 0 elsewhere).
+  // Device layout: row k (k = 0 .. 4096) holds the interpolation pairs
+  // (phi_t, phi_t+1) at t = k, k + 4096, k + 8192, padded to 8 ints, so the
+  // three nodes on one side of a particle come from one 32-byte row.
   if (cf.force == PM_FORCE_NUFFT) {
     const int w = cf.es_width, tabn = (w / 2) * kEsTabPerCell + 2;
-    c->es_tab.resize(tabn);
+    std::vector<int32_t> lin(tabn);
     for (int t = 0; t < tabn; ++t) {
       double x = (double)t / kEsTabPerCell, z = x / (0.5 * w);
       double phi = z < 1.0 ? std::exp(cf.es_beta * (std::sqrt(1.0 - z * z) - 1.0)) : 0.0;
-      c->es_tab[t] = (int32_t)std::nearbyint(phi * (double)(1 << kWeightBits));
+      lin[t] = (int32_t)std::nearbyint(phi * (double)(1 << kWeightBits));
     }
+    c->es_tab.assign((size_t)(kEsTabPerCell + 1) * 8, 0);
+    for (int k = 0; k <= kEsTabPerCell; ++k)
+      for (int m = 0; m < w / 2; ++m) {
+        c->es_tab[8 * k + 2 * m] = lin[k + m * kEsTabPerCell];
+        c->es_tab[8 * k + 2 * m + 1] = lin[k + m * kEsTabPerCell + 1];
+      }
     c->esdec.assign(n, 0.f);
     for (int i = 0; i < n; ++i) {
       int m = i < n / 2 ? i : i - n;
@@ -432,13 +441,14 @@ TileArgs tile_args(pm_ctx* c, float* disp, unsigned long long active) {
   return t;
 }
 
-AssembleArgs assemble_args(pm_ctx* c, int R, void* out, unsigned long long active) {
+AssembleArgs assemble_args(pm_ctx* c, int Rlo, int Rhi, void* out, unsigned long long active) {
   AssembleArgs a{};
   a.g = c->g;
   a.batch = c->cfg.batch;
   a.active = active;
   a.T = c->T;
-  a.R = R;
+  a.Rlo = Rlo;
+  a.Rhi = Rhi;
   a.log2T = c->log2T;
   a.log2nt = c->log2nt;
   a.n_tiles = c->n_tiles;
@@ -454,7 +464,7 @@ pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* ta
   pm_status st = bin(c, disp, vel_pre, tau, mak, active);
   if (st) return st;
   TileArgs t = tile_args(c, disp, active);
-  AssembleArgs a = assemble_args(c, 1, mesh, active);
+  AssembleArgs a = assemble_args(c, 1, 1, mesh, active);
   KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile(t, TK_DEPOSIT, mak, 0, c->stream), launch_assemble(a, false, c->stream)));
   return PM_OK;
 }
@@ -473,7 +483,7 @@ pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* 
   if (st) return st;
   TileArgs t = tile_args(c, disp, active);
   float* rho = reinterpret_cast<float*>(c->mesh);
-  AssembleArgs as = assemble_args(c, 1, rho, active);
+  AssembleArgs as = assemble_args(c, 1, 1, rho, active);
   as.inv_scale = nullptr;
   as.scale = n3 / N / 4294967296.0;
   as.shift = 1.0;
@@ -496,7 +506,7 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   const double ph0 = es_phihat(0.0, c->cfg.es_width, c->cfg.es_beta);
   const double mean = N * ph0 * ph0 * ph0 / (double)c->g.M;  // removes most of k = 0
   float* rho = reinterpret_cast<float*>(c->mesh);
-  AssembleArgs as = assemble_args(c, 3, rho, active);
+  AssembleArgs as = assemble_args(c, kEsHaloLo, kEsHaloHi, rho, active);
   as.inv_scale = nullptr;
   as.scale = 1.0 / 4294967296.0;
   as.shift = mean;
@@ -984,9 +994,9 @@ pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, co
   // every node value sum_c u_c d/du_c phi3 is bounded by 3 max|u| per
   // particle (|phi| <= 1, |phi'| < 1 cell^-1)
   KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale, 3.0 * (double)N,
-                                            B, c->stream));
+                                            3.0, B, c->stream));
   float* d = reinterpret_cast<float*>(c->mesh);
-  AssembleArgs as = assemble_args(c, 3, d, act);
+  AssembleArgs as = assemble_args(c, kEsHaloLo, kEsHaloHi, d, act);
   KLAUNCH(c, PM_K_DIPOLE, both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
   pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p);
   if (st) return st;
@@ -1073,10 +1083,10 @@ pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, co
   if (!(parts & 2)) return PM_OK;
   // mesh cotangent of the force: transposed FD gather in fixed point
   KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
-                                            3.0 * fd_l1 * (double)N, B, c->stream));
+                                            3.0 * fd_l1 * (double)N, 0.0, B, c->stream));
   // transposed multiplier (H is real and even)
   float* d = reinterpret_cast<float*>(c->mesh);
-  AssembleArgs as = assemble_args(c, dipole_halo(ord), d, act);
+  AssembleArgs as = assemble_args(c, dipole_halo(ord), dipole_halo(ord), d, act);
   KLAUNCH(c, PM_K_DIPOLE, both(launch_tile(k, TK_DIPOLE, mak, ord, c->stream), launch_assemble(as, true, c->stream)));
   pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
   if (st) return st;
@@ -1276,7 +1286,7 @@ pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_ou
   if (st) return st;
   TileArgs t = tile_args(c, x, act);
   t.es_tab = c->d_es_tab;
-  AssembleArgs as = assemble_args(c, 3, mesh_out, act);
+  AssembleArgs as = assemble_args(c, kEsHaloLo, kEsHaloHi, mesh_out, act);
   KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile_es(t, TK_ES_DEPOSIT, c->stream), launch_assemble(as, false, c->stream)));
   return PM_OK;
 }

@@ -1,14 +1,16 @@
 // Tile windows: the mesh is cut into (n/T)^3 tiles of T^3 cells (nt per
-// axis); the window of a tile covers the tile plus R cells beyond each face
-// (W = T + 2R per axis) and holds int64 partial sums.  In the slab of one
-// slot the windows are stored row-major over the mesh: the window row
-// (lx, ly) of tile (tx, ty, tz) is W values at
+// axis); the window of a tile covers the tile plus Rlo cells below and Rhi
+// cells above each axis (W = T + Rlo + Rhi) and holds int64 partial sums.
+// The halo is asymmetric where the stencil is: a width-6 kernel anchored at
+// floor(u) reaches 2 nodes below and 3 above.  In the slab of one slot the
+// windows are stored row-major over the mesh: the window row (lx, ly) of
+// tile (tx, ty, tz) is W values at
 //   ((((tx nt + ty) W + lx) W + ly) nt + tz) W,
 // so the rows of all tz at fixed (tx, ty, lx, ly) are one contiguous run of
-// nt W values, which a z-row pass reads in one sweep.  A cell's value is the
-// sum of the windows that cover it: along each axis the own tile at local
-// l + R, the previous tile at l + T + R when l < R, the next one at l - T + R
-// when l >= T - R (indices periodic).
+// nt W values.  A cell's value is the sum of the windows that cover it:
+// along each axis the own tile at local l + Rlo, the previous tile at
+// l + T + Rlo when l < Rhi, the next one at l - T + Rlo when l >= T - Rlo
+// (indices periodic).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -18,13 +20,13 @@ struct WinCover {
   int t[3], l[3], n;  // covering tiles and local coordinates along one axis
 };
 
-__device__ __forceinline__ WinCover win_cover(int x, int T, int R, int log2T, int ntm) {
+__device__ __forceinline__ WinCover win_cover(int x, int T, int Rlo, int Rhi, int log2T, int ntm) {
   WinCover w;
   const int tc = x >> log2T, l = x & (T - 1);
   int k = 0;
-  w.t[k] = tc; w.l[k] = l + R; ++k;
-  if (l < R) { w.t[k] = (tc - 1) & ntm; w.l[k] = l + T + R; ++k; }
-  if (l >= T - R) { w.t[k] = (tc + 1) & ntm; w.l[k] = l - T + R; ++k; }
+  w.t[k] = tc; w.l[k] = l + Rlo; ++k;
+  if (l < Rhi) { w.t[k] = (tc - 1) & ntm; w.l[k] = l + T + Rlo; ++k; }
+  if (l >= T - Rlo) { w.t[k] = (tc + 1) & ntm; w.l[k] = l - T + Rlo; ++k; }
   w.n = k;
   return w;
 }
@@ -58,21 +60,21 @@ __device__ __forceinline__ void store_window(const V* win, V* slab, int t, int W
   }
 }
 
-// the same cover when T > 2R: the own tile and at most one neighbour, in
-// scalars (no dynamically indexed arrays, so nothing spills to scratch)
+// the same cover when Rlo + Rhi <= T: the own tile and at most one
+// neighbour, in scalars (no dynamically indexed arrays, so nothing spills)
 struct Cover2 {
   int t0, l0, t1, l1;
   bool two;
 };
 
-__device__ __forceinline__ Cover2 cover2(int x, int T, int R, int log2T, int ntm) {
+__device__ __forceinline__ Cover2 cover2(int x, int T, int Rlo, int Rhi, int log2T, int ntm) {
   Cover2 c;
   const int tc = x >> log2T, l = x & (T - 1);
   c.t0 = tc;
-  c.l0 = l + R;
-  c.two = l < R || l >= T - R;
-  c.t1 = (l < R ? tc - 1 : tc + 1) & ntm;
-  c.l1 = l < R ? l + T + R : l - T + R;
+  c.l0 = l + Rlo;
+  c.two = l < Rhi || l >= T - Rlo;
+  c.t1 = (l < Rhi ? tc - 1 : tc + 1) & ntm;
+  c.l1 = l < Rhi ? l + T + Rlo : l - T + Rlo;
   return c;
 }
 
