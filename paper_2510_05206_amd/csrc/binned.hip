@@ -645,7 +645,7 @@ __device__ __forceinline__ void es_node_d(int wi, int dist, bool below, float be
   const float phi = (float)wi * inv;
   w = phi;
   const float z = (float)dist * kInvHalf, omz = (float)(kHalf - dist) * kInvHalf;
-  const float dphi = -phi * beta * z / ((float)(kEsW / 2) * sqrtf(omz * (1.f + z)));
+  const float dphi = -phi * beta * z * (1.0f / (float)(kEsW / 2)) * rsqrtf(omz * (1.f + z));
   dw = (below && dist > 0) ? dphi : -dphi;
 }
 
@@ -678,6 +678,32 @@ __device__ __forceinline__ unsigned long long es_node_mass(unsigned A0, unsigned
   q += (rem + 0x07ffffffu + (q & 1u)) >> 28;    // half-even
   return ((unsigned long long)(hi >> 28) << 32) | q;
 }
+
+// The ES windows are (16 + 5)^3 (every NUFFT mesh has 16-cell tiles) and are
+// loaded straight into LDS (global_load_lds_dword: lane l of a wave writes
+// the dword at M0 + 4 l), element e = 256 k + 64 wave + lane, so no data
+// passes through registers and every load of the window is in flight at
+// once: one HBM round trip per window.  The LDS buffer is padded to whole
+// rounds (kEsWinLds floats); lanes past the window re-read a valid cell into
+// the padding.
+constexpr int kEsWin = kTileMax + kEsLo + kEsHi;
+constexpr int kEsWin3 = kEsWin * kEsWin * kEsWin;
+constexpr int kEsWinLds = (kEsWin3 + 255) / 256 * 256;
+
+__device__ __forceinline__ void load_window_es(float* win, const float* __restrict__ mesh, const int o[3], int L,
+                                               int nm) {
+  constexpr int W = kEsWin, W2 = W * W, NE = kEsWinLds / 256;
+  const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
+#pragma unroll 4
+  for (int k = 0; k < NE; ++k) {
+    const int e0 = 256 * k + wbase, e = min(e0 + lane, kEsWin3 - 1);
+    const int lx = e / W2, r = e - lx * W2, ly = r / W, lz = r - ly * W;
+    const int gx = (o[0] - kEsLo + lx) & nm, gy = (o[1] - kEsLo + ly) & nm, gz = (o[2] - kEsLo + lz) & nm;
+    const float* src = mesh + (((long long)((gx << L) + gy) << L) + gz);
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(win + e0), 4, 0, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's window loads have landed (the caller's barrier does the rest)
+}
 }  // namespace
 
 // Particle loads are software-pipelined: the next particle's index and
@@ -686,7 +712,7 @@ __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
   extern __shared__ unsigned long long ewin[];
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + kEsLo + kEsHi, W3 = W * W * W;
+  constexpr int W = kEsWin, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   int p = beg + threadIdx.x;
@@ -757,8 +783,26 @@ __device__ __forceinline__ float es_contract(const float* __restrict__ win, int 
       sx += w[1][yy] * r;
     }
     A += w[0][xx] * sx;
+    __builtin_amdgcn_sched_barrier(0);  // one x plane of reads in flight at a time (register pressure)
   }
   return A;
+}
+
+// weights and window-local first nodes from given coordinates
+__device__ __forceinline__ void es_particle_x(const TileArgs& a, long long i, const float x[3], const int o[3],
+                                              long long umask, int nm, float (&w)[3][kEsW], int (&l0)[3]) {
+  constexpr float inv = 1.0f / (float)(1 << kWeightBits);
+  long long j[3];
+  lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int wi[kEsW];
+    long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
+    int h = es_weights(U, a.es_tab, wi) & nm;
+    l0[c] = h - o[c];
+#pragma unroll
+    for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
+  }
 }
 
 __device__ __forceinline__ void es_particle(const TileArgs& a, long long i, const int o[3], long long umask, int nm,
@@ -778,8 +822,13 @@ __device__ __forceinline__ void es_particle(const TileArgs& a, long long i, cons
   }
 }
 
-__global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
+// The first two particles of every thread (a tile holds 512 on average)
+// keep their weights, positions and velocities in registers over the three
+// components, so their dependent loads (index, position, table rows) are
+// paid once; particles of denser tiles recompute them per component.
+__global__ void __launch_bounds__(256, 3) k_tile_es_kick(TileArgs a) {  // <= 168 VGPRs: 3 waves per SIMD
   extern __shared__ float fwin[];  // one (T + 5)^3 window, the components in turn
+  constexpr int K = 2;
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
   const int W = a.T + kEsLo + kEsHi;
@@ -790,24 +839,62 @@ __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
   const float al = a.alpha[slot], be = a.beta[slot], tp = a.tau[slot];
+  const bool force_only = a.acc_out != nullptr;
+  float wk[K][3][kEsW], xk[K][3], vk[K][3];
+  int lk[K][3];
+  long long ik[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int p = beg + threadIdx.x + 256 * k;
+    ik[k] = p < end ? a.sorted[slot * N + p] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool ok = beg + (int)threadIdx.x + 256 * k < end;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xk[k][c] = ok ? a.disp[ps + c * N + ik[k]] : 0.f;
+      vk[k][c] = ok && !force_only ? a.vel[ps + c * N + ik[k]] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) es_particle_x(a, ik[k], xk[k], o, umask, nm, wk[k], lk[k]);
   for (int c = 0; c < 3; ++c) {
     if (c) __syncthreads();  // the previous component's reads are done
-    load_window(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsLo, kEsHi, a.g.log2_ng, nm);
+    load_window_es(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.g.log2_ng, nm);
     __syncthreads();
-    for (int p = beg + threadIdx.x; p < end; p += 256) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (beg + (int)threadIdx.x + 256 * k >= end) continue;
+      const float A = es_contract(fwin, W, lk[k], wk[k]);
+      if (force_only)
+        a.acc_out[ps + c * N + ik[k]] = A;
+      else
+        vk[k][c] = al * vk[k][c] + be * A;
+    }
+    for (int p = beg + threadIdx.x + 256 * K; p < end; p += 256) {
       const long long i = a.sorted[slot * N + p];
       float w[3][kEsW];
       int l0[3];
       es_particle(a, i, o, umask, nm, w, l0);
       const float A = es_contract(fwin, W, l0, w);
-      if (a.acc_out)
+      if (force_only)
         a.acc_out[ps + c * N + i] = A;
       else
         a.vel[ps + c * N + i] = al * a.vel[ps + c * N + i] + be * A;
     }
   }
-  if (a.acc_out) return;
-  for (int p = beg + threadIdx.x; p < end; p += 256) {  // drift (this thread's own V writes)
+  if (force_only) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {  // drift
+    if (beg + (int)threadIdx.x + 256 * k >= end) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.vel[ps + c * N + ik[k]] = vk[k][c];
+      a.disp[ps + c * N + ik[k]] = xk[k][c] + tp * vk[k][c];
+    }
+  }
+  for (int p = beg + threadIdx.x + 256 * K; p < end; p += 256) {  // this thread's own V writes
     const long long i = a.sorted[slot * N + p];
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.disp[ps + c * N + i] += tp * a.vel[ps + c * N + i];
@@ -819,12 +906,72 @@ __global__ void __launch_bounds__(256) k_tile_es_kick(TileArgs a) {
 // reverse kick with the ES gather of the 3 force meshes and its position
 // gradient: V = (V - beta A) / alpha, V_bar = alpha V_bar, u = beta V_bar,
 // X_bar += r sum_c u_c dA_c/du; u kept in sorted order with max |u|
+// separable contraction of a window with the weights and their gradient:
+// A = sum w0 w1 w2 f, dA[d] = the same with w_d replaced by dw_d
+__device__ __forceinline__ void es_contract_grad(const float* __restrict__ win, int W, const int l0[3],
+                                                 const float (&w)[3][kEsW], const float (&dw)[3][kEsW], float& A,
+                                                 float (&dA)[3]) {
+  A = 0.f;
+  dA[0] = dA[1] = dA[2] = 0.f;
+#pragma unroll
+  for (int xx = 0; xx < kEsW; ++xx) {
+    float sww = 0.f, sdw = 0.f, swd = 0.f;
+#pragma unroll
+    for (int yy = 0; yy < kEsW; ++yy) {
+      const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+      float rw = 0.f, rd = 0.f;
+#pragma unroll
+      for (int zz = 0; zz < kEsW; ++zz) {
+        const float f = win[b + zz];
+        rw += w[2][zz] * f;
+        rd += dw[2][zz] * f;
+      }
+      sww += w[1][yy] * rw;
+      sdw += dw[1][yy] * rw;
+      swd += w[1][yy] * rd;
+    }
+    A += w[0][xx] * sww;
+    dA[0] += dw[0][xx] * sww;
+    dA[1] += w[0][xx] * sdw;
+    dA[2] += w[0][xx] * swd;
+  }
+}
+
+__device__ __forceinline__ void es_particle_d(const TileArgs& a, long long i, const float x[3], const int o[3],
+                                              long long umask, int nm, float (&w)[3][kEsW], float (&dw)[3][kEsW],
+                                              int (&l0)[3]) {
+  long long j[3];
+  lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    long long U = fixed_coord(j[d], x[d], a.g.log2_r, umask);
+    int h = es_weights_d(U, a.es_tab, a.es_beta, w[d], dw[d]) & nm;
+    l0[d] = h - o[d];
+  }
+}
+
+// reverse kick of one particle and component from its window contraction
+__device__ __forceinline__ void es_adj_kick_one(const TileArgs& a, long long i, int p, int c, float A,
+                                                const float (&dA)[3], float al, float be, float r, float& umax) {
+  const long long N = a.g.N, ps = (long long)blockIdx.y * a.g.part_stride;
+  const float vb = a.vbar[ps + c * N + i];
+  const float u = be * vb;
+  a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A) / al;
+  a.vbar[ps + c * N + i] = al * vb;
+  a.u_sorted[ps + c * N + p] = u;
+  umax = fmaxf(umax, fabsf(u));
+#pragma unroll
+  for (int d = 0; d < 3; ++d) a.xbar[ps + d * N + i] += r * u * dA[d];
+}
+
+// The weights are recomputed per component: keeping them in registers over
+// the components costs more registers than the occupancy allows.
 __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
   extern __shared__ float fwin[];  // one (T + 5)^3 window, the components in turn
   __shared__ float red[256];
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + kEsLo + kEsHi;
+  const int W = a.T + kEsLo + kEsHi;  // (a runtime stride keeps the contraction compact)
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   const long long N = a.g.N, ps = slot * a.g.part_stride;
@@ -836,52 +983,17 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
   float umax = 0.f;
   for (int c = 0; c < 3; ++c) {
     if (c) __syncthreads();
-    load_window(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.T, kEsLo, kEsHi, a.g.log2_ng, nm);
+    load_window_es(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.g.log2_ng, nm);
     __syncthreads();
     for (int p = beg + threadIdx.x; p < end; p += 256) {
       const long long i = a.sorted[slot * N + p];
-      long long j[3];
-      lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+      const float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
       float w[3][kEsW], dw[3][kEsW];
       int l0[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        long long U = fixed_coord(j[d], a.disp[ps + d * N + i], a.g.log2_r, umask);
-        int h = es_weights_d(U, a.es_tab, a.es_beta, w[d], dw[d]) & nm;
-        l0[d] = h - o[d];
-      }
-      // separable contraction of the value and its gradient
-      float A = 0.f, dA[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int xx = 0; xx < kEsW; ++xx) {
-        float sww = 0.f, sdw = 0.f, swd = 0.f;
-#pragma unroll
-        for (int yy = 0; yy < kEsW; ++yy) {
-          const int b = ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
-          float rw = 0.f, rd = 0.f;
-#pragma unroll
-          for (int zz = 0; zz < kEsW; ++zz) {
-            const float f = fwin[b + zz];
-            rw += w[2][zz] * f;
-            rd += dw[2][zz] * f;
-          }
-          sww += w[1][yy] * rw;
-          sdw += dw[1][yy] * rw;
-          swd += w[1][yy] * rd;
-        }
-        A += w[0][xx] * sww;
-        dA[0] += dw[0][xx] * sww;
-        dA[1] += w[0][xx] * sdw;
-        dA[2] += w[0][xx] * swd;
-      }
-      const float vb = a.vbar[ps + c * N + i];
-      const float u = be * vb;
-      a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A) / al;
-      a.vbar[ps + c * N + i] = al * vb;
-      a.u_sorted[ps + c * N + p] = u;
-      umax = fmaxf(umax, fabsf(u));
-#pragma unroll
-      for (int d = 0; d < 3; ++d) a.xbar[ps + d * N + i] += r * u * dA[d];
+      es_particle_d(a, i, x, o, umask, nm, w, dw, l0);
+      float A, dA[3];
+      es_contract_grad(fwin, W, l0, w, dw, A, dA);
+      es_adj_kick_one(a, i, p, c, A, dA, al, be, r, umax);
     }
   }
   red[threadIdx.x] = umax;
@@ -905,7 +1017,7 @@ __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
   extern __shared__ unsigned long long ewin[];
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + kEsLo + kEsHi, W3 = W * W * W;
+  constexpr int W = kEsWin, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   int p = beg + threadIdx.x;
@@ -978,10 +1090,10 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
   extern __shared__ float bwin[];  // (T + 5)^3
   const int slot = blockIdx.y, t = blockIdx.x;
   if (!((a.active >> slot) & 1ull)) return;
-  const int W = a.T + kEsLo + kEsHi;
+  const int W = a.T + kEsLo + kEsHi;  // (a runtime stride keeps the contraction compact)
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
-  load_window(bwin, a.mesh_in + slot * a.g.mesh_stride, o, a.T, kEsLo, kEsHi, a.g.log2_ng, a.g.n_g - 1);
+  load_window_es(bwin, a.mesh_in + slot * a.g.mesh_stride, o, a.g.log2_ng, a.g.n_g - 1);
   __syncthreads();
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
@@ -1040,7 +1152,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
 // any stream capture
 hipError_t configure_tile_kernels() {
   constexpr int We = kTileMax + kEsLo + kEsHi;
-  const int es64 = We * We * We * 8, es32x3 = 3 * We * We * We * 4, es32 = We * We * We * 4;
+  const int es64 = We * We * We * 8, es32 = kEsWinLds * 4;
   auto dip = [](int o) { int W = kTileMax + 2 * (1 + o / 2); return W * W * W * 8; };
   const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
   hipError_t e = hipSuccess;
@@ -1055,8 +1167,8 @@ hipError_t configure_tile_kernels() {
   set((const void*)k_tile_dipole<3, 4>, dip(4));
   set((const void*)k_tile_dipole<3, 6>, dip(6));
   set((const void*)k_tile_es_deposit, es64);
-  set((const void*)k_tile_es_kick, es32x3);
-  set((const void*)k_tile_es_adj_kick, es32x3);
+  set((const void*)k_tile_es_kick, es32);
+  set((const void*)k_tile_es_adj_kick, es32);
   set((const void*)k_tile_es_divspread, es64);
   set((const void*)k_tile_es_adj_drift, es32);
   return e;
@@ -1064,22 +1176,21 @@ hipError_t configure_tile_kernels() {
 
 hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
   dim3 grid((unsigned)a.n_tiles, a.batch);
-  const int W = a.T + kEsLo + kEsHi;
+  if (a.T != kTileMax) return hipErrorInvalidValue;  // the ES kernels assume 16-cell tiles
+  const int W = kEsWin;
+  const size_t fl = (size_t)kEsWinLds * sizeof(float);  // gather windows (padded)
   if (kind == TK_ES_DEPOSIT) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
     k_tile_es_deposit<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_KICK) {
-    size_t lds = (size_t)W * W * W * sizeof(float);
-    k_tile_es_kick<<<grid, 256, lds, s>>>(a);
+    k_tile_es_kick<<<grid, 256, fl, s>>>(a);
   } else if (kind == TK_ES_ADJ_KICK) {
-    size_t lds = (size_t)W * W * W * sizeof(float);
-    k_tile_es_adj_kick<<<grid, 256, lds, s>>>(a);
+    k_tile_es_adj_kick<<<grid, 256, fl, s>>>(a);
   } else if (kind == TK_ES_DIPOLE) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
     k_tile_es_divspread<<<grid, 256, lds, s>>>(a);
   } else if (kind == TK_ES_ADJ_DRIFT) {
-    size_t lds = (size_t)W * W * W * sizeof(float);
-    k_tile_es_adj_drift<<<grid, 256, lds, s>>>(a);
+    k_tile_es_adj_drift<<<grid, 256, fl, s>>>(a);
   } else {
     return hipErrorInvalidValue;
   }
