@@ -61,12 +61,14 @@ def launch_model(cfg):
         Sz = 8 * n * n * (p // 2)
         Sy = 8 * n * (p - 1) * (p // 2)
         return {
-            "deposit": [(2 * K + 2, 12 * N + 8 * M)],
+            # force spreads write the FP32 density; the observed field and the
+            # P(k) mesh are the int64 fixed-point mesh
+            "deposit": [(2 * K, 12 * N + 4 * M), (2, 12 * N + 8 * M)],
             "bin": [(K, 40 * N), (K + 3, 16 * N)],
-            # R2C of the mass (run, adjoint recompute, P(k) unpruned), 3 force
-            # C2R per force evaluation plus the adjoint's b_bar, the R2C of
-            # the adjoint's spread kernel gradient
-            "fft_rows": [(2 * K, 8 * M + Sz), (1, 8 * M + Sn), (7 * K, Sz + 4 * M), (K, 4 * M + Sz)] + ic_rows,
+            # R2C of the mass (run, adjoint recompute; P(k) unpruned from the
+            # int64 mesh), 3 force C2R per force evaluation plus the adjoint's
+            # b_bar, the R2C of the adjoint's spread kernel gradient
+            "fft_rows": [(2 * K, 4 * M + Sz), (1, 8 * M + Sn), (7 * K, Sz + 4 * M), (K, 4 * M + Sz)] + ic_rows,
             # y forward (mass and the adjoint's gradient spread), x passes
             # (multiplier between forward and inverse x), inverse y
             "fft_cols": [(3 * K, Sz + Sy), (7 * K, 2 * Sy), (7 * K, Sy + Sz), (2, 2 * Sn)] + ic_cols,

@@ -190,21 +190,14 @@ __global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
                a.log2nt);
 }
 
-// Sum the windows covering each cell (windows.h).  OUT_F32 converts the
-// int64 sums with inv_scale.
-template <bool OUT_F32>
-__global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
-  const int slot = blockIdx.y;
-  if (!((a.active >> slot) & 1ull)) return;
-  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= a.g.M) return;
-  const int L = a.g.log2_ng, nm = a.g.n_g - 1;
+// Sum the windows covering each cell (windows.h), in a fixed order.  OUT_F32
+// converts the int64 sums with inv_scale (or scale and shift); with an FP32
+// slab the partial sums add in FP32 and the shift follows.
+template <class V>
+__device__ __forceinline__ V assemble_cell(const AssembleArgs& a, const V* __restrict__ slab, int x, int y, int z) {
   const int T = a.T, Rlo = a.Rlo, Rhi = a.Rhi, W = T + Rlo + Rhi;
   const int ntm = (1 << a.log2nt) - 1;
-  const int x = (int)(e >> (2 * L)), y = (int)((e >> L) & nm), z = (int)(e & nm);
-  const long long W3 = (long long)W * W * W;
-  const long long* slab = reinterpret_cast<const long long*>(a.scratch) + (long long)slot * a.n_tiles * W3;
-  long long acc = 0;
+  V acc = 0;
   if (Rlo + Rhi <= T) {  // at most two windows per axis: scalar covers
     const Cover2 c[3] = {cover2(x, T, Rlo, Rhi, a.log2T, ntm), cover2(y, T, Rlo, Rhi, a.log2T, ntm),
                          cover2(z, T, Rlo, Rhi, a.log2T, ntm)};
@@ -223,11 +216,32 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
     acc = win_sum(slab, win_cover(x, T, Rlo, Rhi, a.log2T, ntm), win_cover(y, T, Rlo, Rhi, a.log2T, ntm),
                   win_cover(z, T, Rlo, Rhi, a.log2T, ntm), W, 1 << a.log2nt);
   }
+  return acc;
+}
+
+template <bool OUT_F32>
+__global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
+  const int slot = blockIdx.y;
+  if (!((a.active >> slot) & 1ull)) return;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.g.M) return;
+  const int L = a.g.log2_ng, nm = a.g.n_g - 1;
+  const int x = (int)(e >> (2 * L)), y = (int)((e >> L) & nm), z = (int)(e & nm);
+  const int W = a.T + a.Rlo + a.Rhi;
+  const long long sl = (long long)slot * a.n_tiles * W * W * W;
   if constexpr (OUT_F32) {
-    const double v = a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift;
-    reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = (float)v;
-  } else
-    reinterpret_cast<long long*>(a.out)[slot * a.g.mesh_stride + e] = acc;
+    float v;
+    if (a.slab_f32) {
+      v = assemble_cell(a, reinterpret_cast<const float*>(a.scratch) + sl, x, y, z) - (float)a.shift;
+    } else {
+      const long long acc = assemble_cell(a, reinterpret_cast<const long long*>(a.scratch) + sl, x, y, z);
+      v = (float)(a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift);
+    }
+    reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = v;
+  } else {
+    reinterpret_cast<long long*>(a.out)[slot * a.g.mesh_stride + e] =
+        assemble_cell(a, reinterpret_cast<const long long*>(a.scratch) + sl, x, y, z);
+  }
 }
 
 // ----------------------------------------------------- windowed gathers
@@ -760,8 +774,12 @@ __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
       }
   }
   __syncthreads();
-  store_window(ewin, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
-               a.log2nt);
+  if (a.win_f32)
+    store_window_f32(ewin, reinterpret_cast<float*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W, a.log2nt,
+                     a.win_scale != 0.0 ? a.win_scale : a.inv_scale[slot]);
+  else
+    store_window(ewin, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
+                 a.log2nt);
 }
 
 // A_c = sum_j g_c(j) phi(u - j) from the three force meshes, then the kick
@@ -1080,8 +1098,12 @@ __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
       }
   }
   __syncthreads();
-  store_window(ewin, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
-               a.log2nt);
+  if (a.win_f32)
+    store_window_f32(ewin, reinterpret_cast<float*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W, a.log2nt,
+                     a.win_scale != 0.0 ? a.win_scale : a.inv_scale[slot]);
+  else
+    store_window(ewin, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
+                 a.log2nt);
 }
 
 // X_bar += coef r sum_j b_bar_j d/du phi(u - j) (the spreading differentiated

@@ -43,6 +43,12 @@ struct TileArgs {
   float* umax;             // [B] max |u| (as uint bits)
   const double* scale;     // [B] fixed-point scale of the cotangent scatter
   const int32_t* es_tab;   // integer exponential-of-semicircle table (NUFFT)
+  // ES spreads into a force chain: the window is stored as FP32 partial
+  // sums, acc * win_scale (or acc * inv_scale[slot] when win_scale is 0),
+  // instead of int64 (the exact path for the deposited mesh itself)
+  int win_f32;
+  double win_scale;
+  const double* inv_scale;
   float es_beta;           // its shape parameter (closed-form derivative)
   long long comp_stride;   // floats between the 3 force meshes (NUFFT kick)
   float alpha[kMaxBatch];
@@ -62,6 +68,7 @@ struct AssembleArgs {
   // dipole meshes), else (double)acc * scale - shift (mass meshes)
   const double* inv_scale;
   double scale, shift;
+  int slab_f32;            // the windows are FP32 partial sums: out = sum - shift
 };
 
 hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s);

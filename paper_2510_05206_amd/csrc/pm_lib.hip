@@ -505,10 +505,12 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   const double N = (double)c->g.N;
   const double ph0 = es_phihat(0.0, c->cfg.es_width, c->cfg.es_beta);
   const double mean = N * ph0 * ph0 * ph0 / (double)c->g.M;  // removes most of k = 0
+  // FP32 partial sums per window (the force chain is FP32 from here on)
+  t.win_f32 = 1;
+  t.win_scale = 1.0 / 4294967296.0;
   float* rho = reinterpret_cast<float*>(c->mesh);
   AssembleArgs as = assemble_args(c, kEsHaloLo, kEsHaloHi, rho, active);
-  as.inv_scale = nullptr;
-  as.scale = 1.0 / 4294967296.0;
+  as.slab_f32 = 1;
   as.shift = mean;
   KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile_es(t, TK_ES_DEPOSIT, c->stream), launch_assemble(as, true, c->stream)));
   st = r2c_mesh(c, rho, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, n, false, active, np);
@@ -996,7 +998,12 @@ pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, co
   KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale, 3.0 * (double)N,
                                             3.0, B, c->stream));
   float* d = reinterpret_cast<float*>(c->mesh);
+  k.win_f32 = 1;  // FP32 partial sums at the slot's inverse scale
+  k.win_scale = 0.0;
+  k.inv_scale = c->inv_scale;
   AssembleArgs as = assemble_args(c, kEsHaloLo, kEsHaloHi, d, act);
+  as.slab_f32 = 1;
+  as.shift = 0.0;
   KLAUNCH(c, PM_K_DIPOLE, both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
   pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, ng, false, act, c->cfg.n_p);
   if (st) return st;

@@ -37,9 +37,10 @@ __device__ __forceinline__ long long slab_row(int tx, int ty, int tz, int lx, in
 }
 
 // sum of the windows covering a cell with covers cx, cy, cz
-__device__ __forceinline__ long long win_sum(const long long* __restrict__ slab, const WinCover& cx,
-                                             const WinCover& cy, const WinCover& cz, int W, int nt) {
-  long long acc = 0;
+template <class V>
+__device__ __forceinline__ V win_sum(const V* __restrict__ slab, const WinCover& cx, const WinCover& cy,
+                                     const WinCover& cz, int W, int nt) {
+  V acc = 0;
   for (int p = 0; p < cx.n; ++p)
     for (int q = 0; q < cy.n; ++q)
       for (int r = 0; r < cz.n; ++r) acc += slab[slab_row(cx.t[p], cy.t[q], cz.t[r], cx.l[p], cy.l[q], W, nt) + cz.l[r]];
@@ -57,6 +58,20 @@ __device__ __forceinline__ void store_window(const V* win, V* slab, int t, int W
   for (int r = grp; r < W2; r += 8) {
     const int lx = r / W, ly = r - lx * W;
     slab[slab_row(tx, ty, tz, lx, ly, W, nt) + lane] = win[r * W + lane];
+  }
+}
+
+// the same with the int64 window converted to FP32 partial sums (value
+// times scale) on the way out
+__device__ __forceinline__ void store_window_f32(const unsigned long long* win, float* slab, int t, int W, int log2nt,
+                                                 double scale) {
+  const int nt = 1 << log2nt, m = nt - 1;
+  const int tx = t >> (2 * log2nt), ty = (t >> log2nt) & m, tz = t & m;
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5, W2 = W * W;
+  if (lane >= W) return;
+  for (int r = grp; r < W2; r += 8) {
+    const int lx = r / W, ly = r - lx * W;
+    slab[slab_row(tx, ty, tz, lx, ly, W, nt) + lane] = (float)((double)(long long)win[r * W + lane] * scale);
   }
 }
 
