@@ -197,25 +197,30 @@ template <class V>
 __device__ __forceinline__ V assemble_cell(const AssembleArgs& a, const V* __restrict__ slab, int x, int y, int z) {
   const int T = a.T, Rlo = a.Rlo, Rhi = a.Rhi, W = T + Rlo + Rhi;
   const int ntm = (1 << a.log2nt) - 1;
+  return win_sum(slab, win_cover(x, T, Rlo, Rhi, a.log2T, ntm), win_cover(y, T, Rlo, Rhi, a.log2T, ntm),
+                 win_cover(z, T, Rlo, Rhi, a.log2T, ntm), W, 1 << a.log2nt);
+}
+
+// z-run of one block (n >= 256): the x and y covers are block-uniform, so the
+// window-row bases are scalar and each thread only adds its z offset
+template <class V>
+__device__ __forceinline__ V assemble_run(const AssembleArgs& a, const V* __restrict__ slab, int x, int y, int z) {
+  const int T = a.T, Rlo = a.Rlo, Rhi = a.Rhi, W = T + Rlo + Rhi;
+  const int nt = 1 << a.log2nt, ntm = nt - 1;
+  const Cover2 cx = cover2(x, T, Rlo, Rhi, a.log2T, ntm), cy = cover2(y, T, Rlo, Rhi, a.log2T, ntm);
+  const Cover2 cz = cover2(z, T, Rlo, Rhi, a.log2T, ntm);
+  const int oz0 = cz.t0 * W + cz.l0, oz1 = cz.t1 * W + cz.l1;  // offsets within a row run of nt W values
   V acc = 0;
-  if (Rlo + Rhi <= T) {  // at most two windows per axis: scalar covers
-    const Cover2 c[3] = {cover2(x, T, Rlo, Rhi, a.log2T, ntm), cover2(y, T, Rlo, Rhi, a.log2T, ntm),
-                         cover2(z, T, Rlo, Rhi, a.log2T, ntm)};
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+  for (int p = 0; p < 2; ++p)
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          if ((p && !c[0].two) || (q && !c[1].two) || (r && !c[2].two)) continue;
-          acc += slab[slab_row(p ? c[0].t1 : c[0].t0, q ? c[1].t1 : c[1].t0, r ? c[2].t1 : c[2].t0,
-                               p ? c[0].l1 : c[0].l0, q ? c[1].l1 : c[1].l0, W, 1 << a.log2nt) +
-                      (r ? c[2].l1 : c[2].l0)];
-        }
-  } else {  // small meshes (one or two tiles per axis, wide halo)
-    acc = win_sum(slab, win_cover(x, T, Rlo, Rhi, a.log2T, ntm), win_cover(y, T, Rlo, Rhi, a.log2T, ntm),
-                  win_cover(z, T, Rlo, Rhi, a.log2T, ntm), W, 1 << a.log2nt);
-  }
+    for (int q = 0; q < 2; ++q) {
+      if ((p && !cx.two) || (q && !cy.two)) continue;
+      const V* row = slab + slab_row(p ? cx.t1 : cx.t0, q ? cy.t1 : cy.t0, 0, p ? cx.l1 : cx.l0, q ? cy.l1 : cy.l0,
+                                     W, nt);
+      acc += row[oz0];
+      if (cz.two) acc += row[oz1];
+    }
   return acc;
 }
 
@@ -223,24 +228,30 @@ template <bool OUT_F32>
 __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
   const int slot = blockIdx.y;
   if (!((a.active >> slot) & 1ull)) return;
-  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= a.g.M) return;
   const int L = a.g.log2_ng, nm = a.g.n_g - 1;
-  const int x = (int)(e >> (2 * L)), y = (int)((e >> L) & nm), z = (int)(e & nm);
+  const long long e0 = (long long)blockIdx.x * 256, e = e0 + threadIdx.x;
+  if (e >= a.g.M) return;
   const int W = a.T + a.Rlo + a.Rhi;
   const long long sl = (long long)slot * a.n_tiles * W * W * W;
+  // with n >= 256 and Rlo + Rhi <= T every block is one z-run of one (x, y) row
+  const bool run = L >= 8 && a.Rlo + a.Rhi <= a.T;
+  const long long eb = run ? e0 : e;  // (x, y) from the block start: uniform
+  const int x = (int)(eb >> (2 * L)), y = (int)((eb >> L) & nm), z = (int)(e & nm);
   if constexpr (OUT_F32) {
     float v;
     if (a.slab_f32) {
-      v = assemble_cell(a, reinterpret_cast<const float*>(a.scratch) + sl, x, y, z) - (float)a.shift;
+      const float* sf = reinterpret_cast<const float*>(a.scratch) + sl;
+      v = (run ? assemble_run(a, sf, x, y, z) : assemble_cell(a, sf, x, y, z)) - (float)a.shift;
     } else {
-      const long long acc = assemble_cell(a, reinterpret_cast<const long long*>(a.scratch) + sl, x, y, z);
+      const long long* si = reinterpret_cast<const long long*>(a.scratch) + sl;
+      const long long acc = run ? assemble_run(a, si, x, y, z) : assemble_cell(a, si, x, y, z);
       v = (float)(a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift);
     }
     reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = v;
   } else {
+    const long long* si = reinterpret_cast<const long long*>(a.scratch) + sl;
     reinterpret_cast<long long*>(a.out)[slot * a.g.mesh_stride + e] =
-        assemble_cell(a, reinterpret_cast<const long long*>(a.scratch) + sl, x, y, z);
+        run ? assemble_run(a, si, x, y, z) : assemble_cell(a, si, x, y, z);
   }
 }
 
