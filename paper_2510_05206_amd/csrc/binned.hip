@@ -21,6 +21,7 @@
 // LDS access; the mesh is written once per pass.
 #include "mak.h"
 #include "windows.h"
+#include "xcd.h"
 
 namespace pm {
 
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(BinArgs a) {
 template <int P>
 __global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
   __shared__ unsigned long long win[(kTileMax + 2) * (kTileMax + 2) * (kTileMax + 2)];
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   const int T = a.T, W = T + 2, W3 = W * W * W;
   for (int e = threadIdx.x; e < W3; e += 256) win[e] = 0ull;
@@ -229,7 +230,7 @@ __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
   const int slot = blockIdx.y;
   if (!((a.active >> slot) & 1ull)) return;
   const int L = a.g.log2_ng, nm = a.g.n_g - 1;
-  const long long e0 = (long long)blockIdx.x * 256, e = e0 + threadIdx.x;
+  const long long e0 = (long long)xcd_block(blockIdx.x, gridDim.x) * 256, e = e0 + threadIdx.x;
   if (e >= a.g.M) return;
   const int W = a.T + a.Rlo + a.Rhi;
   const long long sl = (long long)slot * a.n_tiles * W * W * W;
@@ -315,7 +316,7 @@ template <int P, int ORD>
 __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
   constexpr int R = 1 + ORD / 2;
   __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
@@ -354,7 +355,7 @@ __global__ void __launch_bounds__(256) k_tile_adj_kick(TileArgs a) {
   constexpr int R = 1 + ORD / 2;
   __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
   __shared__ float red[256];
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
@@ -423,7 +424,7 @@ template <int P, int ORD>
 __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
   constexpr int H = ORD / 2, R = 1 + H, Q = P + 2 * H;
   extern __shared__ unsigned long long dwin[];
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   const int W = a.T + 2 * R, W3 = W * W * W;
   for (int e = threadIdx.x; e < W3; e += 256) dwin[e] = 0ull;
@@ -482,7 +483,7 @@ template <int P>
 __global__ void __launch_bounds__(256) k_tile_adj_drift(TileArgs a) {
   constexpr int R = 1;
   __shared__ float win[(kTileMax + 2) * (kTileMax + 2) * (kTileMax + 2)];
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
@@ -735,7 +736,7 @@ __device__ __forceinline__ void load_window_es(float* win, const float* __restri
 // coordinates are in flight while the current one scatters.
 __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
   extern __shared__ unsigned long long ewin[];
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   constexpr int W = kEsWin, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
@@ -858,7 +859,7 @@ __device__ __forceinline__ void es_particle(const TileArgs& a, long long i, cons
 __global__ void __launch_bounds__(256, 3) k_tile_es_kick(TileArgs a) {  // <= 168 VGPRs: 3 waves per SIMD
   extern __shared__ float fwin[];  // one (T + 5)^3 window, the components in turn
   constexpr int K = 2;
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   const int W = a.T + kEsLo + kEsHi;
   int o[3];
@@ -998,7 +999,7 @@ __device__ __forceinline__ void es_adj_kick_one(const TileArgs& a, long long i, 
 __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
   extern __shared__ float fwin[];  // one (T + 5)^3 window, the components in turn
   __shared__ float red[256];
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   const int W = a.T + kEsLo + kEsHi;  // (a runtime stride keeps the contraction compact)
   int o[3];
@@ -1044,7 +1045,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
 // FP32 and summed as int64 (order-free).
 __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
   extern __shared__ unsigned long long ewin[];
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   constexpr int W = kEsWin, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
@@ -1121,7 +1122,7 @@ __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
 // w.r.t. the positions), then the reverse drift X -= tau V, V_bar += tau X_bar
 __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
   extern __shared__ float bwin[];  // (T + 5)^3
-  const int slot = blockIdx.y, t = blockIdx.x;
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   const int W = a.T + kEsLo + kEsHi;  // (a runtime stride keeps the contraction compact)
   int o[3];
