@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
     const int nm = a.g.n_g - 1;
     int h[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) h[c] = home_node<P>(fixed_coord(j[c], p[c], a.g.log2_r, umask), nm);
+    for (int c = 0; c < 3; ++c) h[c] = (home_node<P>(fixed_coord(j[c], p[c], a.g.log2_r, umask), nm) - a.home_shift) & nm;
     tile = (((h[0] >> a.log2T) << a.log2nt | (h[1] >> a.log2T)) << a.log2nt) | (h[2] >> a.log2T);
   }
   // wave-aggregated counting: one atomic per distinct tile in the wave
@@ -599,8 +599,9 @@ hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s) {
 // integer linear interpolation in a table of phi at 4096 samples per cell
 // (20-bit values), so spreading is bit-reproducible; the 3D product is
 // rounded half-even to the 2^32 mass unit (no remainder: the ES kernel is not
-// a partition of unity).  Home node floor(u); the window reaches 2 cells
-// below the tile and 3 above.
+// a partition of unity).  The particles are binned by their first stencil
+// node floor(u) - 2, so the window starts at the tile origin and reaches 5
+// cells beyond it: window rows then start on the tile's 64-byte boundary.
 namespace {
 constexpr int kEsW = 6, kEsLo = kEsHaloLo, kEsHi = kEsHaloHi;
 constexpr int kEsShift = kFracBits - 12;  // 4096 samples per cell
@@ -764,8 +765,7 @@ __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long U = fixed_coord(j[c], xc[c], a.g.log2_r, umask);
-      const int h = es_weights(U, a.es_tab, w[c]) & nm;
-      l0[c] = h - o[c];  // window-local node floor(u) - 2
+      l0[c] = ((es_weights(U, a.es_tab, w[c]) - kEsAnchor) & nm) - o[c];  // first node floor(u) - 2
     }
     if (p + 256 < end) {
       i = a.sorted[slot * N + p + 256];
@@ -828,8 +828,7 @@ __device__ __forceinline__ void es_particle_x(const TileArgs& a, long long i, co
   for (int c = 0; c < 3; ++c) {
     int wi[kEsW];
     long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
-    int h = es_weights(U, a.es_tab, wi) & nm;
-    l0[c] = h - o[c];
+    l0[c] = ((es_weights(U, a.es_tab, wi) - kEsAnchor) & nm) - o[c];
 #pragma unroll
     for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
   }
@@ -845,8 +844,7 @@ __device__ __forceinline__ void es_particle(const TileArgs& a, long long i, cons
   for (int c = 0; c < 3; ++c) {
     int wi[kEsW];
     long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
-    int h = es_weights(U, a.es_tab, wi) & nm;
-    l0[c] = h - o[c];
+    l0[c] = ((es_weights(U, a.es_tab, wi) - kEsAnchor) & nm) - o[c];
 #pragma unroll
     for (int q = 0; q < kEsW; ++q) w[c][q] = (float)wi[q] * inv;
   }
@@ -975,8 +973,7 @@ __device__ __forceinline__ void es_particle_d(const TileArgs& a, long long i, co
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     long long U = fixed_coord(j[d], x[d], a.g.log2_r, umask);
-    int h = es_weights_d(U, a.es_tab, a.es_beta, w[d], dw[d]) & nm;
-    l0[d] = h - o[d];
+    l0[d] = ((es_weights_d(U, a.es_tab, a.es_beta, w[d], dw[d]) - kEsAnchor) & nm) - o[d];
   }
 }
 
@@ -1080,8 +1077,7 @@ __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long U = fixed_coord(j[c], xc[c], a.g.log2_r, umask);
-      const int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
-      l0[c] = h - o[c];
+      l0[c] = ((es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) - kEsAnchor) & nm) - o[c];
     }
     if (p + 256 < end) {
       const int q = p + 256;
@@ -1144,8 +1140,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
-      int h = es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) & nm;
-      l0[c] = h - o[c];
+      l0[c] = ((es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) - kEsAnchor) & nm) - o[c];
     }
     float gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll

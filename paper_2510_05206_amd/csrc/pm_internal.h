@@ -17,9 +17,11 @@ constexpr int kFracBits = 20;    // fixed-point fraction bits of a mesh coordina
 constexpr int kWeightBits = 20;  // bits of a 1D integer weight (sums to 2^20)
 constexpr int kMassBits = 32;    // mass unit per particle: 2^32
 constexpr int kEsTabPerCell = 4096;
-// window halo of the width-6 ES stencil anchored at floor(u): nodes
-// floor(u) - 2 .. floor(u) + 3
-constexpr int kEsHaloLo = 2, kEsHaloHi = 3;
+// width-6 ES stencil: nodes floor(u) - 2 .. floor(u) + 3.  Particles are
+// binned by the first node (anchor shift 2), so the tile window covers the
+// tile and 5 cells above it on each axis
+constexpr int kEsAnchor = 2;
+constexpr int kEsHaloLo = 0, kEsHaloHi = 5;
 
 // ---------------------------------------------------------------- host FP64
 struct StepCoef {          // one BullFrog step (Sec. "Time stepping")

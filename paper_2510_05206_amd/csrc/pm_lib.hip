@@ -395,7 +395,7 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
 // counting sort of the particles of `disp` by the tile of their home node
 // (optionally drifting them by tau first); fills key/rank/sorted/offset
 pm_status bin(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, int mak,
-              unsigned long long active) {
+              unsigned long long active, int home_shift = 0) {
   KLAUNCH(c, PM_K_FILL, launch_fill(c->count, (long long)sizeof(int32_t) * c->ts * c->cfg.batch, c->stream));
   BinArgs b{};
   b.g = c->g;
@@ -413,6 +413,7 @@ pm_status bin(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, i
   b.sorted = c->sorted;
   b.count = c->count;
   b.offset = c->offset;
+  b.home_shift = home_shift;
   KLAUNCH(c, PM_K_BIN, launch_binning(b, mak, c->stream));
   return PM_OK;
 }
@@ -497,7 +498,7 @@ pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* 
 // i k_c s / k^2, deconvolve -> zero-padded C2R per component (type 2 grid)
 pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
                        unsigned long long active) {
-  pm_status st = bin(c, disp, vel_pre, tau, 2, active);  // home node floor(u), as CIC
+  pm_status st = bin(c, disp, vel_pre, tau, 2, active, kEsAnchor);  // first stencil node floor(u) - 2
   if (st) return st;
   TileArgs t = tile_args(c, disp, active);
   t.es_tab = c->d_es_tab;
@@ -1289,7 +1290,7 @@ pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_ou
   float* x = c->disp;
   const unsigned long long act = all_mask(c->cfg.batch);
   if (mak != 6) return deposit(c, x, nullptr, nullptr, mak, (long long*)mesh_out, act);
-  pm_status st = bin(c, x, nullptr, nullptr, 2, act);
+  pm_status st = bin(c, x, nullptr, nullptr, 2, act, kEsAnchor);
   if (st) return st;
   TileArgs t = tile_args(c, x, act);
   t.es_tab = c->d_es_tab;
