@@ -20,6 +20,7 @@
 #include "fft.h"
 #include "fft_reg.h"
 #include "mak.h"
+#include "xcd.h"
 
 namespace pm {
 
@@ -408,9 +409,11 @@ __global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
   __shared__ float2 lds[S::LDS];
   const int slot = blockIdx.z;
   if (!((a.active >> slot) & 1ull)) return;
-  const int outer = blockIdx.y;  // x for the y pass, y for the x pass
+  // adjacent column groups (halves of one 128-byte line) share an XCD's L2
+  const unsigned lid = xcd_pair(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int outer = (int)(lid / gridDim.x);  // x for the y pass, y for the x pass
   const int c = threadIdx.x % C, n1 = threadIdx.x / C;
-  const int iz = blockIdx.x * C + c;
+  const int iz = (int)(lid % gridDim.x) * C + c;
   const int zl = a.zlim > 0 && a.zlim < a.nh ? a.zlim : a.nh;
   const bool valid = iz < zl;
   auto kept = [&](int t) { int m = signed_mode(t, a.n); return 2 * (m < 0 ? -m : m) < a.keep; };

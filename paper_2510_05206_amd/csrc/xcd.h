@@ -17,4 +17,13 @@ __device__ __forceinline__ unsigned xcd_block(unsigned lid, unsigned total) {
   return (lid % kXcds) * (total / kXcds) + lid / kXcds;
 }
 
+// pairs of neighbouring blocks on one XCD at about the same time, the grid
+// order otherwise kept: within every 16 dispatch ids, XCD k runs blocks 2k and
+// 2k + 1 (dispatched 8 ids apart)
+__device__ __forceinline__ unsigned xcd_pair(unsigned lid, unsigned total) {
+  if (total % (2 * kXcds)) return lid;
+  const unsigned g = lid / (2 * kXcds), r = lid % (2 * kXcds);
+  return g * (2 * kXcds) + (r % kXcds) * 2 + r / kXcds;
+}
+
 }  // namespace pm
