@@ -100,6 +100,26 @@ def launch_model(cfg):
     }
 
 
+LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz (GB/s)
+
+
+def lds_model(cfg):
+    """LDS bytes of the stencil accesses per launch of the ES tile kernels
+    (their binding roof): 216 nodes per particle, an int64 add per node in a
+    spread, an FP32 read per node and component in a gather.  The window
+    fills and write-backs are design overhead.  PM workloads: {}."""
+    if cfg.force != "nufft":
+        return {}
+    N, K = cfg.n_p ** 3, cfg.n_steps
+    return {
+        "deposit": [(2 * K, 216 * 8 * N), (2, 8 * 8 * N)],
+        "gather_kick": [(K, 3 * 216 * 4 * N)],
+        "adj_kick": [(K, 3 * 216 * 4 * N)],
+        "dipole": [(K, 216 * 8 * N)],
+        "adj_drift": [(K, 216 * 4 * N), (1, 8 * 4 * N)],
+    }
+
+
 def source_digest():
     """sha256 over the HIP/C++ sources of the library: HBM counter readings are
     valid only for the kernels they were taken on."""
@@ -132,6 +152,7 @@ def rooflines(cfg, kt, steps):
     """Per-class HBM roofline: the model's bytes over the class's measured
     time, after checking the model's launch count against the measured one."""
     out = {}
+    lmodel = lds_model(cfg)
     for cls, parts in launch_model(cfg).items():
         ms, nl = kt.get(cls, (0.0, 0))
         count = sum(c for c, _ in parts) * steps
@@ -143,6 +164,12 @@ def rooflines(cfg, kt, steps):
         out[cls] = {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                     "ms_per_step": round(ms / steps, 3), "launches_per_step": count // steps,
                     "avg_launch_us": round(ms / nl * 1e3, 2), "bytes_per_launch": round(total / count)}
+        lparts = lmodel.get(cls)
+        if lparts:
+            ltot = sum(c * b for c, b in lparts) * steps
+            lgbs = ltot / (ms * 1e-3) / 1e9
+            out[cls]["lds"] = {"bytes_per_launch": round(ltot / count), "achieved": round(lgbs, 1),
+                               "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s", "frac": round(lgbs / LDS_PEAK_GBS, 4)}
     return out
 
 
@@ -173,12 +200,15 @@ def cpu_baseline(cfg):
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):      # the reported core count is the one used
         t = time.perf_counter()
-        adjoint.gradient(prob, w, lambda d: 2.0 * d)
+        reps = 0
+        while reps < 8 and (reps == 0 or time.perf_counter() - t < 10.0):   # ~10 s of CPU work
+            adjoint.gradient(prob, w, lambda d: 2.0 * d)
+            reps += 1
         dt = time.perf_counter() - t
-    return {"value": n_p ** 3 * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+    return {"value": reps * n_p ** 3 * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 numpy oracle, same physics at {n_p}^3 particles ({what}, L={box:g} Mpc/h, BBKS), "
-                      f"{steps} BullFrog steps forward + store-all reverse, {dt:.1f} s single-threaded on a "
-                      f"host with {os.cpu_count()} cores"}
+                      f"{steps} BullFrog steps forward + store-all reverse, {reps} repetitions in {dt:.1f} s "
+                      f"single-threaded on a host with {os.cpu_count()} cores"}
 
 
 def serve_bench(n_requests, budget_gb):
