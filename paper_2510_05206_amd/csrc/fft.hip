@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
 // arithmetic is applied on load (input layout, t = n1 + P r) or after the
 // forward transform (output layout).
 template <int L, int C, int MODE>
-__global__ void __launch_bounds__(256) k_cols_reg(ColArgs a) {
+__global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGPRs: two blocks per CU (their LDS allows two)
   using S = freg::Shape<L, C>;
   __shared__ float2 lds[S::LDS];
   const int slot = blockIdx.z;
