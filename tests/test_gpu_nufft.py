@@ -41,7 +41,8 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("n_p,kind", [(16, "gauss"), (16, "clustered"), (16, "boundary"), (32, "gauss")])
+@pytest.mark.parametrize("n_p,kind", [(8, "gauss"), (8, "boundary"), (16, "gauss"), (16, "clustered"),
+                                        (16, "boundary"), (32, "gauss")])
 def test_es_spreading_bit_exact(n_p, kind):
     say("es spreading", n_p, kind)
     sim = make_sim(synth.C3_SMALL, n_p=n_p, n_g=2 * n_p)
@@ -51,7 +52,7 @@ def test_es_spreading_bit_exact(n_p, kind):
     assert np.array_equal(m, ref)
 
 
-@pytest.mark.parametrize("n_p", [16, 32, 64])
+@pytest.mark.parametrize("n_p", [8, 16, 32, 64])
 def test_nufft_force_matches_oracle(n_p):
     say("nufft force", n_p)
     sim = make_sim(synth.C3_SMALL, n_p=n_p, n_g=2 * n_p)
