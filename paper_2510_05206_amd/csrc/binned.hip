@@ -419,7 +419,9 @@ __global__ void k_dipole_scale(const unsigned int* umax_bits, double* scale, dou
 }
 
 // transposed FD gather (mesh cotangent of the force), into an int64 window
-// covering the tile + R cells: phi_bar(node) += u_c G_c[t] w w
+// covering the tile + R cells: phi_bar(node) += u_c G_c[t] w w, each node
+// value rounded to an int32 at the slot's fixed-point scale (|value| <=
+// max|u| sum|c_s| < 2^31 there)
 template <int P, int ORD>
 __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
   constexpr int H = ORD / 2, R = 1 + H, Q = P + 2 * H;
@@ -427,22 +429,43 @@ __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   const int W = a.T + 2 * R, W3 = W * W * W;
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  // the first particle's loads are in flight while the window is cleared;
+  // later ones are fetched while the current one scatters
+  int p = beg + threadIdx.x;
+  long long i = 0;
+  float x[3] = {0.f, 0.f, 0.f}, u[3] = {0.f, 0.f, 0.f};
+  if (p < end) {
+    i = a.sorted[slot * N + p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[c] = a.disp[ps + c * N + i];
+      u[c] = a.u_sorted[ps + c * N + p];
+    }
+  }
   for (int e = threadIdx.x; e < W3; e += 256) dwin[e] = 0ull;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   __syncthreads();
-  const long long N = a.g.N, ps = slot * a.g.part_stride;
-  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
-  const double S = a.scale[slot];
-  for (int p = beg + threadIdx.x; p < end; p += 256) {
-    const long long i = a.sorted[slot * N + p];
-    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+  // fixed point: every node value is below 2^31 at this scale (a power of two)
+  const float S = (float)a.scale[slot];
+  for (; p < end; p += 256) {
     float w[3][P], dw[3][P];
     int l0[3];
     tile_weights<P>(a, i, x, o, R, w, dw, l0);
+    const float us[3] = {u[0] * S, u[1] * S, u[2] * S};
+    if (p + 256 < end) {
+      const int q = p + 256;
+      i = a.sorted[slot * N + q];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        x[c] = a.disp[ps + c * N + i];
+        u[c] = a.u_sorted[ps + c * N + q];
+      }
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float uc = a.u_sorted[ps + c * N + p];
       float G[Q];
 #pragma unroll
       for (int tt = 0; tt < Q; ++tt) {
@@ -452,7 +475,7 @@ __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
           int s = tt - H - q;
           if (s >= -H && s <= H) g += w[c][q] * fd_coef<ORD>(s);
         }
-        G[tt] = g * uc;
+        G[tt] = g * us[c];
       }
       const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
 #pragma unroll
@@ -466,8 +489,8 @@ __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
             n3[c] = l0[c] - H + tt;
             n3[a1] = l0[a1] + q1;
             n3[a2] = l0[a2] + q2;
-            long long v = llrint((double)(G[tt] * w[a1][q1] * w[a2][q2]) * S);
-            if (v) atomicAdd(&dwin[(n3[0] * W + n3[1]) * W + n3[2]], (unsigned long long)v);
+            const int v = (int)rintf(G[tt] * w[a1][q1] * w[a2][q2]);
+            atomicAdd(&dwin[(n3[0] * W + n3[1]) * W + n3[2]], (unsigned long long)(long long)v);
           }
       }
     }

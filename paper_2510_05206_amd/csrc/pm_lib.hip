@@ -1091,7 +1091,7 @@ pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, co
   if (!(parts & 2)) return PM_OK;
   // mesh cotangent of the force: transposed FD gather in fixed point
   KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
-                                            3.0 * fd_l1 * (double)N, 0.0, B, c->stream));
+                                            3.0 * fd_l1 * (double)N, fd_l1, B, c->stream));
   // transposed multiplier (H is real and even)
   float* d = reinterpret_cast<float*>(c->mesh);
   AssembleArgs as = assemble_args(c, dipole_halo(ord), dipole_halo(ord), d, act);
