@@ -136,53 +136,68 @@ __global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   const int T = a.T, W = T + 2, W3 = W * W * W;
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  // the first particle's loads are in flight while the window is cleared;
+  // later ones are fetched while the current one scatters
+  int p = beg + threadIdx.x;
+  long long i = 0;
+  float x[3] = {0.f, 0.f, 0.f};
+  if (p < end) {
+    i = a.sorted[slot * N + p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[c] = a.disp[ps + c * N + i];
+  }
   for (int e = threadIdx.x; e < W3; e += 256) win[e] = 0ull;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   __syncthreads();
-  const long long N = a.g.N, ps = slot * a.g.part_stride;
-  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
   constexpr int shift = 3 * kWeightBits - kMassBits;
-  for (int p = beg + threadIdx.x; p < end; p += 256) {
-    const long long i = a.sorted[slot * N + p];
+  for (; p < end; p += 256) {
     long long j[3];
     lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     int w[3][P], l0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      long long U = fixed_coord(j[c], a.disp[ps + c * N + i], a.g.log2_r, umask);
+      long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
       weights1d<P>(U, w[c]);
       // local index of the first stencil node in the window (home at h - o + 1)
       l0[c] = home_node<P>(U, nm) - o[c] + 1 - (P == 3 ? 1 : 0);
     }
-    unsigned long long sum = 0, best = 0;
+    if (p + 256 < end) {
+      i = a.sorted[slot * N + p + 256];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) x[c] = a.disp[ps + c * N + i];
+    }
+    // node masses once; the remainder to 2^32 goes to the largest weight
+    unsigned long long v[P * P * P], sum = 0, best = 0;
     int home = 0;
 #pragma unroll
-    for (int x = 0; x < P; ++x)
+    for (int xx = 0; xx < P; ++xx)
 #pragma unroll
       for (int y = 0; y < P; ++y) {
-        unsigned long long wxy = (unsigned long long)w[0][x] * (unsigned)w[1][y];
+        unsigned long long wxy = (unsigned long long)w[0][xx] * (unsigned)w[1][y];
 #pragma unroll
         for (int z = 0; z < P; ++z) {
+          const int k = (xx * P + y) * P + z;
           unsigned long long q = wxy * (unsigned)w[2][z];
-          sum += rne_shift(q, shift);
-          if (q > best) { best = q; home = (x * P + y) * P + z; }
+          v[k] = rne_shift(q, shift);
+          sum += v[k];
+          if (q > best) { best = q; home = k; }
         }
       }
-    const long long rem = (1ll << kMassBits) - (long long)sum;
+    const unsigned long long rem = (1ull << kMassBits) - sum;
 #pragma unroll
-    for (int x = 0; x < P; ++x)
+    for (int xx = 0; xx < P; ++xx)
 #pragma unroll
       for (int y = 0; y < P; ++y) {
-        unsigned long long wxy = (unsigned long long)w[0][x] * (unsigned)w[1][y];
-        const int bxy = ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
+        const int bxy = ((l0[0] + xx) * W + l0[1] + y) * W + l0[2];
 #pragma unroll
         for (int z = 0; z < P; ++z) {
-          long long v = (long long)rne_shift(wxy * (unsigned)w[2][z], shift);
-          if ((x * P + y) * P + z == home) v += rem;
-          if (v) atomicAdd(&win[bxy + z], (unsigned long long)v);
+          const int k = (xx * P + y) * P + z;
+          atomicAdd(&win[bxy + z], v[k] + (k == home ? rem : 0ull));
         }
       }
   }
