@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   // the first particle's loads are in flight while the window is cleared;
   // later ones are fetched while the current one scatters
-  int p = beg + threadIdx.x;
+  int p = beg + (int)(((threadIdx.x & 15) << 4) | (threadIdx.x >> 4));  // lanes 16 apart in the tile list
   long long i = 0;
   float x[3] = {0.f, 0.f, 0.f}, u[3] = {0.f, 0.f, 0.f};
   if (p < end) {
