@@ -19,6 +19,8 @@
 //   k_tile_adj_drift gradient gather of the mesh cotangent and reverse drifts.
 // The windows make each HBM access coalesced and each particle's stencil an
 // LDS access; the mesh is written once per pass.
+#include <type_traits>
+
 #include "mak.h"
 #include "windows.h"
 #include "xcd.h"
@@ -240,34 +242,47 @@ __device__ __forceinline__ V assemble_run(const AssembleArgs& a, const V* __rest
   return acc;
 }
 
-template <bool OUT_F32>
+// CPT cells per thread, 256 CPT consecutive cells per block: with n >= 256 CPT
+// and Rlo + Rhi <= T a block is one z-run of one (x, y) row (scalar covers).
+// All of a thread's sums are formed before any store (the slab and the
+// output may not alias, but the compiler cannot know).
+template <bool OUT_F32, int CPT>
 __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
   const int slot = blockIdx.y;
   if (!((a.active >> slot) & 1ull)) return;
   const int L = a.g.log2_ng, nm = a.g.n_g - 1;
-  const long long e0 = (long long)xcd_block(blockIdx.x, gridDim.x) * 256, e = e0 + threadIdx.x;
-  if (e >= a.g.M) return;
+  const long long e0 = (long long)xcd_block(blockIdx.x, gridDim.x) * (256 * CPT);
   const int W = a.T + a.Rlo + a.Rhi;
   const long long sl = (long long)slot * a.n_tiles * W * W * W;
-  // with n >= 256 and Rlo + Rhi <= T every block is one z-run of one (x, y) row
-  const bool run = L >= 8 && a.Rlo + a.Rhi <= a.T;
-  const long long eb = run ? e0 : e;  // (x, y) from the block start: uniform
-  const int x = (int)(eb >> (2 * L)), y = (int)((eb >> L) & nm), z = (int)(e & nm);
-  if constexpr (OUT_F32) {
-    float v;
-    if (a.slab_f32) {
-      const float* sf = reinterpret_cast<const float*>(a.scratch) + sl;
-      v = (run ? assemble_run(a, sf, x, y, z) : assemble_cell(a, sf, x, y, z)) - (float)a.shift;
+  const bool run = (1 << L) >= 256 * CPT && a.Rlo + a.Rhi <= a.T;
+  using V = typename std::conditional<OUT_F32, float, long long>::type;
+  V out[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const long long e = e0 + threadIdx.x + 256 * k;
+    out[k] = 0;
+    if (e >= a.g.M) continue;
+    const long long eb = run ? e0 : e;  // (x, y) from the block start: uniform
+    const int x = (int)(eb >> (2 * L)), y = (int)((eb >> L) & nm), z = (int)(e & nm);
+    if constexpr (OUT_F32) {
+      if (a.slab_f32) {
+        const float* sf = reinterpret_cast<const float*>(a.scratch) + sl;
+        out[k] = (run ? assemble_run(a, sf, x, y, z) : assemble_cell(a, sf, x, y, z)) - (float)a.shift;
+      } else {
+        const long long* si = reinterpret_cast<const long long*>(a.scratch) + sl;
+        const long long acc = run ? assemble_run(a, si, x, y, z) : assemble_cell(a, si, x, y, z);
+        out[k] = (float)(a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift);
+      }
     } else {
       const long long* si = reinterpret_cast<const long long*>(a.scratch) + sl;
-      const long long acc = run ? assemble_run(a, si, x, y, z) : assemble_cell(a, si, x, y, z);
-      v = (float)(a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift);
+      out[k] = run ? assemble_run(a, si, x, y, z) : assemble_cell(a, si, x, y, z);
     }
-    reinterpret_cast<float*>(a.out)[slot * a.g.mesh_stride + e] = v;
-  } else {
-    const long long* si = reinterpret_cast<const long long*>(a.scratch) + sl;
-    reinterpret_cast<long long*>(a.out)[slot * a.g.mesh_stride + e] =
-        run ? assemble_run(a, si, x, y, z) : assemble_cell(a, si, x, y, z);
+  }
+  V* o = reinterpret_cast<V*>(a.out) + slot * a.g.mesh_stride;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const long long e = e0 + threadIdx.x + 256 * k;
+    if (e < a.g.M) o[e] = out[k];
   }
 }
 
@@ -625,9 +640,17 @@ hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, dou
 }
 
 hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s) {
-  dim3 grid((unsigned)((a.g.M + 255) / 256), a.batch);
-  if (out_f32) k_assemble<true><<<grid, 256, 0, s>>>(a);
-  else k_assemble<false><<<grid, 256, 0, s>>>(a);
+  // four cells per thread (one 1024-cell row per block) from n = 1024 on:
+  // fewer, longer blocks with four times the loads in flight per thread
+  if (a.g.n_g >= 1024) {
+    dim3 grid((unsigned)((a.g.M + 1023) / 1024), a.batch);
+    if (out_f32) k_assemble<true, 4><<<grid, 256, 0, s>>>(a);
+    else k_assemble<false, 4><<<grid, 256, 0, s>>>(a);
+  } else {
+    dim3 grid((unsigned)((a.g.M + 255) / 256), a.batch);
+    if (out_f32) k_assemble<true, 1><<<grid, 256, 0, s>>>(a);
+    else k_assemble<false, 1><<<grid, 256, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
