@@ -8,7 +8,8 @@
 //                    window (tile + 1 cell each side) and writes the whole
 //                    window to a scratch slab;
 //   k_assemble       sums, for every cell, the window values of the (up to 8)
-//                    tiles whose window covers it (integers: order-free);
+//                    tiles whose window covers it (int64: order-free; the FP32
+//                    partial sums of the ES force chains in a fixed order);
 //   k_tile_kick      stages the potential over the tile + stencil reach in LDS
 //                    and does the FD-gradient gather, kick and drift;
 //   k_tile_adj_kick  the same gather with the position gradient for the
@@ -16,7 +17,10 @@
 //   k_tile_dipole    scatters u through the transposed gather (kernel x FD
 //                    stencil) into an int64 LDS window, in fixed point with a
 //                    scale set by max|u| (deterministic);
-//   k_tile_adj_drift gradient gather of the mesh cotangent and reverse drifts.
+//   k_tile_adj_drift gradient gather of the mesh cotangent and reverse drifts;
+//   k_tile_es_*      the same roles with the width-6 ES kernel of the NUFFT
+//                    force (deposit, kick, adjoint kick, gradient spread,
+//                    adjoint drift), further down.
 // The windows make each HBM access coalesced and each particle's stencil an
 // LDS access; the mesh is written once per pass.
 #include <type_traits>
