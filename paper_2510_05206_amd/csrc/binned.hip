@@ -95,33 +95,68 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
   }
 }
 
-// exclusive scan of the tile counts, one 1024-thread block per slot
-__global__ void __launch_bounds__(1024) k_bin_scan(const int32_t* count, int32_t* offset, int n_tiles,
-                                                   long long ts) {
-  __shared__ int sh[1024];
-  const int slot = blockIdx.x;
-  const int32_t* cn = count + slot * ts;
-  int32_t* of = offset + slot * ts;
-  const int chunk = (n_tiles + 1023) / 1024;
-  const int s0 = threadIdx.x * chunk;
-  int sum = 0;
-  for (int k = 0; k < chunk; ++k)
-    if (s0 + k < n_tiles) sum += cn[s0 + k];
-  sh[threadIdx.x] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
+// exclusive scan of the tile counts in three short passes: each 1024-tile
+// block scans its counts and records its total, one block per slot scans the
+// totals (writing the grand total after the last tile), then every block adds
+// its base
+__device__ __forceinline__ int block_scan_1024(int v, int* wsum, int& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
-  int run = sh[threadIdx.x] - sum;  // exclusive prefix of this chunk
-  for (int k = 0; k < chunk; ++k)
-    if (s0 + k < n_tiles) {
-      of[s0 + k] = run;
-      run += cn[s0 + k];
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    int w = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int y = __shfl_up(w, o, 64);
+      if (lane >= o) w += y;
     }
-  if (threadIdx.x == 1023) of[n_tiles] = sh[1023];
+    if (lane < 16) wsum[lane] = w;  // inclusive over waves
+  }
+  __syncthreads();
+  total = wsum[15];
+  return x - v + (wave ? wsum[wave - 1] : 0);  // exclusive
+}
+
+__global__ void __launch_bounds__(1024) k_bin_scan_blocks(const int32_t* count, int32_t* offset, int32_t* partial,
+                                                          int n_tiles, long long ts, int np) {
+  __shared__ int wsum[16];
+  const int slot = blockIdx.y, b = blockIdx.x;
+  const int i = b * 1024 + threadIdx.x;
+  const int v = i < n_tiles ? count[slot * ts + i] : 0;
+  int total;
+  const int ex = block_scan_1024(v, wsum, total);
+  if (i < n_tiles) offset[slot * ts + i] = ex;
+  if (threadIdx.x == 0) partial[slot * np + b] = total;
+}
+
+__global__ void __launch_bounds__(1024) k_bin_scan_partials(int32_t* partial, int32_t* offset, int n_tiles,
+                                                            long long ts, int nb, int np) {
+  __shared__ int wsum[16];
+  const int slot = blockIdx.x;
+  int run = 0;
+  for (int b0 = 0; b0 < nb; b0 += 1024) {  // nb <= np partials, 1024 at a time
+    const int b = b0 + threadIdx.x;
+    const int v = b < nb ? partial[slot * np + b] : 0;
+    int total;
+    const int ex = block_scan_1024(v, wsum, total);
+    __syncthreads();  // wsum is reused by the next round
+    if (b < nb) partial[slot * np + b] = run + ex;
+    run += total;
+  }
+  if (threadIdx.x == 0) offset[slot * ts + n_tiles] = run;
+}
+
+__global__ void __launch_bounds__(1024) k_bin_scan_add(const int32_t* partial, int32_t* offset, int n_tiles,
+                                                       long long ts, int np) {
+  const int slot = blockIdx.y, b = blockIdx.x;
+  const int i = b * 1024 + threadIdx.x;
+  if (b > 0 && i < n_tiles) offset[slot * ts + i] += partial[slot * np + b];
 }
 
 __global__ void __launch_bounds__(256) k_bin_scatter(BinArgs a) {
@@ -588,7 +623,12 @@ hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s) {
   dim3 grid((unsigned)((a.g.N + 255) / 256), a.batch);
   if (mak == 2) k_bin_count<2><<<grid, 256, 0, s>>>(a);
   else k_bin_count<3><<<grid, 256, 0, s>>>(a);
-  k_bin_scan<<<a.batch, 1024, 0, s>>>(a.count, a.offset, a.n_tiles, a.ts);
+  const int nb = (a.n_tiles + 1023) / 1024;
+  if (nb > a.scan_np) return hipErrorInvalidValue;
+  k_bin_scan_blocks<<<dim3((unsigned)nb, a.batch), 1024, 0, s>>>(a.count, a.offset, a.scan_partial, a.n_tiles, a.ts,
+                                                                 a.scan_np);
+  k_bin_scan_partials<<<a.batch, 1024, 0, s>>>(a.scan_partial, a.offset, a.n_tiles, a.ts, nb, a.scan_np);
+  k_bin_scan_add<<<dim3((unsigned)nb, a.batch), 1024, 0, s>>>(a.scan_partial, a.offset, a.n_tiles, a.ts, a.scan_np);
   k_bin_scatter<<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
 }

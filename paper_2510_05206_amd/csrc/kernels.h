@@ -20,6 +20,8 @@ struct BinArgs {
   int32_t* count;          // [B][ts], zero on entry
   int32_t* offset;         // [B][ts], n_tiles + 1 entries used
   int home_shift;          // bin by home node - home_shift (ES: the first stencil node)
+  int32_t* scan_partial;   // [B][scan_np] block totals of the count scan
+  int scan_np;
 };
 
 enum { TK_DEPOSIT = 0, TK_KICK = 1, TK_ADJ_KICK = 2, TK_ADJ_DRIFT = 3, TK_DIPOLE = 4, TK_ES_DEPOSIT = 5,

@@ -49,6 +49,7 @@ struct pm_ctx {
   int T = 16, log2T = 4, log2nt = 0, n_tiles = 1;
   long long ts = 0;
   int32_t *key = nullptr, *rank = nullptr, *sorted = nullptr, *count = nullptr, *offset = nullptr;
+  int32_t* scan_partial = nullptr;  // block totals of the tile-count scan
   void* scratch = nullptr;
   float* u_sorted = nullptr;    // adjoint: u in sorted order; IC adjoint: psi_bar
   float* umax = nullptr;
@@ -140,7 +141,7 @@ struct Layout {
   size_t off_tw, off_lap, off_win2, off_amp, off_cic4;
   size_t off_disp, off_vel, off_w, off_xbar, off_vbar;
   size_t off_mesh, off_spec, off_phi, off_icspec, off_pk, off_dot;
-  size_t off_key, off_rank, off_sorted, off_count, off_offset, off_scratch, off_u, off_umax, off_scale;
+  size_t off_key, off_rank, off_sorted, off_count, off_offset, off_scanp, off_scratch, off_u, off_umax, off_scale;
   size_t off_es_tab, off_esdec, off_force3, off_spec2;
   size_t total;
 };
@@ -149,6 +150,8 @@ struct Layout {
 // of the adjoint's transposed FD gather (kernel reach 1 + FD reach)
 int tile_edge(int n) { return n < 16 ? n : 16; }
 int dipole_halo(int grad_order) { return 1 + grad_order / 2; }
+// block totals of the tile-count scan (1024 tiles per block), padded
+int scan_np(long long n_tiles) { return (int)((n_tiles + 1023) / 1024 + 63) / 64 * 64; }
 
 // half-spectrum row stride: n/2 + 1 complex, padded to 16 (one 128-byte line)
 // from n = 32 so that column tiles read whole aligned lines
@@ -184,6 +187,7 @@ Layout layout(const pm_ctx* c, bool adj) {
   L.off_sorted = take(sizeof(int32_t) * N * B);
   L.off_count = take(sizeof(int32_t) * ts * B);
   L.off_offset = take(sizeof(int32_t) * ts * B);
+  L.off_scanp = take(sizeof(int32_t) * scan_np(n_tiles) * B);
   const bool nufft = c->cfg.force == PM_FORCE_NUFFT;
   long long W = T + 2;
   if (adj) W = std::max(W, (long long)T + 2 * dipole_halo(c->cfg.grad_order));
@@ -414,6 +418,8 @@ pm_status bin(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, i
   b.count = c->count;
   b.offset = c->offset;
   b.home_shift = home_shift;
+  b.scan_partial = c->scan_partial;
+  b.scan_np = scan_np(c->n_tiles);
   KLAUNCH(c, PM_K_BIN, launch_binning(b, mak, c->stream));
   return PM_OK;
 }
@@ -685,6 +691,7 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   c->sorted = (int32_t*)(ws + L.off_sorted);
   c->count = (int32_t*)(ws + L.off_count);
   c->offset = (int32_t*)(ws + L.off_offset);
+  c->scan_partial = (int32_t*)(ws + L.off_scanp);
   c->scratch = (void*)(ws + L.off_scratch);
   c->u_sorted = with_adjoint ? (float*)(ws + L.off_u) : nullptr;
   c->d_es_tab = (int32_t*)(ws + L.off_es_tab);
