@@ -709,6 +709,7 @@ hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s) {
 // cells beyond it: window rows then start on the tile's 64-byte boundary.
 namespace {
 constexpr int kEsW = 6, kEsLo = kEsHaloLo, kEsHi = kEsHaloHi;
+constexpr int kEsSpreadThreads = 512;  // threads per ES deposit workgroup (16 waves per CU at two per CU)
 constexpr int kEsShift = kFracBits - 12;  // 4096 samples per cell
 constexpr int kEsSub = (1 << kEsShift) - 1;
 
@@ -843,14 +844,15 @@ __device__ __forceinline__ void load_window_es(float* win, const float* __restri
 // take particles 16 apart in the tile's (lattice-ordered) list: neighbours
 // in the list often share a cell, and int64 atomics of one instruction to one
 // address serialise (measured 3.5% faster than consecutive lanes).
-__global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
+__global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_deposit(TileArgs a) {
+  constexpr int NT = kEsSpreadThreads;
   extern __shared__ unsigned long long ewin[];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   constexpr int W = kEsWin, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
-  int p = beg + (int)(((threadIdx.x & 15) << 4) | (threadIdx.x >> 4));  // lanes 16 apart in the tile order
+  int p = beg + (int)(((threadIdx.x % (NT / 16)) * 16) + threadIdx.x / (NT / 16));  // lanes 16 apart in the tile order
   long long i = 0;
   float x0 = 0.f, x1 = 0.f, x2 = 0.f;
   if (p < end) {
@@ -859,13 +861,13 @@ __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
     x1 = a.disp[ps + N + i];
     x2 = a.disp[ps + 2 * N + i];
   }
-  for (int e = threadIdx.x; e < W3; e += 256) ewin[e] = 0ull;
+  for (int e = threadIdx.x; e < W3; e += NT) ewin[e] = 0ull;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   __syncthreads();
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
-  for (; p < end; p += 256) {
+  for (; p < end; p += NT) {
     long long j[3];
     lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     const float xc[3] = {x0, x1, x2};
@@ -875,8 +877,8 @@ __global__ void __launch_bounds__(256) k_tile_es_deposit(TileArgs a) {
       const long long U = fixed_coord(j[c], xc[c], a.g.log2_r, umask);
       l0[c] = ((es_weights(U, a.es_tab, w[c]) - kEsAnchor) & nm) - o[c];  // first node floor(u) - 2
     }
-    if (p + 256 < end) {
-      i = a.sorted[slot * N + p + 256];
+    if (p + NT < end) {
+      i = a.sorted[slot * N + p + NT];
       x0 = a.disp[ps + i];
       x1 = a.disp[ps + N + i];
       x2 = a.disp[ps + 2 * N + i];
@@ -1318,7 +1320,7 @@ hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
   const size_t fl = (size_t)kEsWinLds * sizeof(float);  // gather windows (padded)
   if (kind == TK_ES_DEPOSIT) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
-    k_tile_es_deposit<<<grid, 256, lds, s>>>(a);
+    k_tile_es_deposit<<<grid, kEsSpreadThreads, lds, s>>>(a);
   } else if (kind == TK_ES_KICK) {
     k_tile_es_kick<<<grid, 256, fl, s>>>(a);
   } else if (kind == TK_ES_ADJ_KICK) {

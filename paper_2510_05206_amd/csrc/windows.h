@@ -48,14 +48,14 @@ __device__ __forceinline__ V win_sum(const V* __restrict__ slab, const WinCover&
 }
 
 // store an LDS window (z fastest, W <= 32) of tile t into the slot's slab:
-// 8 groups of 32 lanes take rows (lx, ly) in turn, one lane per z
+// the block's groups of 32 lanes take rows (lx, ly) in turn, one lane per z
 template <class V>
 __device__ __forceinline__ void store_window(const V* win, V* slab, int t, int W, int log2nt) {
   const int nt = 1 << log2nt, m = nt - 1;
   const int tx = t >> (2 * log2nt), ty = (t >> log2nt) & m, tz = t & m;
-  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5, W2 = W * W;
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5, W2 = W * W, ng = blockDim.x >> 5;
   if (lane >= W) return;
-  for (int r = grp; r < W2; r += 8) {
+  for (int r = grp; r < W2; r += ng) {
     const int lx = r / W, ly = r - lx * W;
     slab[slab_row(tx, ty, tz, lx, ly, W, nt) + lane] = win[r * W + lane];
   }
@@ -67,9 +67,9 @@ __device__ __forceinline__ void store_window_f32(const unsigned long long* win, 
                                                  double scale) {
   const int nt = 1 << log2nt, m = nt - 1;
   const int tx = t >> (2 * log2nt), ty = (t >> log2nt) & m, tz = t & m;
-  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5, W2 = W * W;
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5, W2 = W * W, ng = blockDim.x >> 5;
   if (lane >= W) return;
-  for (int r = grp; r < W2; r += 8) {
+  for (int r = grp; r < W2; r += ng) {
     const int lx = r / W, ly = r - lx * W;
     slab[slab_row(tx, ty, tz, lx, ly, W, nt) + lane] = (float)((double)(long long)win[r * W + lane] * scale);
   }
