@@ -1150,14 +1150,15 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
 // Fixed point at the scale set from max |u|: each node value is below 2^31
 // (|phi| <= 1, |phi'| < 1 per cell, so |d| < 3 max|u|), rounded half-even in
 // FP32 and summed as int64 (order-free).
-__global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
+__global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_divspread(TileArgs a) {
+  constexpr int NT = kEsSpreadThreads;
   extern __shared__ unsigned long long ewin[];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   constexpr int W = kEsWin, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
-  int p = beg + (int)(((threadIdx.x & 15) << 4) | (threadIdx.x >> 4));  // lanes 16 apart in the tile order
+  int p = beg + (int)(((threadIdx.x % (NT / 16)) * 16) + threadIdx.x / (NT / 16));  // lanes 16 apart in the tile order
   long long i = 0;
   float u0 = 0.f, u1 = 0.f, u2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
   if (p < end) {
@@ -1169,14 +1170,14 @@ __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
     x1 = a.disp[ps + N + i];
     x2 = a.disp[ps + 2 * N + i];
   }
-  for (int e = threadIdx.x; e < W3; e += 256) ewin[e] = 0ull;
+  for (int e = threadIdx.x; e < W3; e += NT) ewin[e] = 0ull;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   __syncthreads();
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
   const float S = (float)a.scale[slot];  // a power of two
-  for (; p < end; p += 256) {
+  for (; p < end; p += NT) {
     const bool any = u0 != 0.f || u1 != 0.f || u2 != 0.f;
     const float u[3] = {u0 * S, u1 * S, u2 * S};
     long long j[3];
@@ -1189,8 +1190,8 @@ __global__ void __launch_bounds__(256) k_tile_es_divspread(TileArgs a) {
       const long long U = fixed_coord(j[c], xc[c], a.g.log2_r, umask);
       l0[c] = ((es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) - kEsAnchor) & nm) - o[c];
     }
-    if (p + 256 < end) {
-      const int q = p + 256;
+    if (p + NT < end) {
+      const int q = p + NT;
       i = a.sorted[slot * N + q];
       u0 = a.u_sorted[ps + q];
       u1 = a.u_sorted[ps + N + q];
@@ -1327,7 +1328,7 @@ hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
     k_tile_es_adj_kick<<<grid, 256, fl, s>>>(a);
   } else if (kind == TK_ES_DIPOLE) {
     size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
-    k_tile_es_divspread<<<grid, 256, lds, s>>>(a);
+    k_tile_es_divspread<<<grid, kEsSpreadThreads, lds, s>>>(a);
   } else if (kind == TK_ES_ADJ_DRIFT) {
     k_tile_es_adj_drift<<<grid, 256, fl, s>>>(a);
   } else {
