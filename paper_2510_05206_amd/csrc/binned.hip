@@ -32,6 +32,11 @@
 namespace pm {
 
 constexpr int kTileMax = 16;
+// threads per workgroup of the PM transposed gather: its int64 LDS window
+// (85 KB at FD4) allows one workgroup per CU, so more threads per workgroup
+// means more waves per CU
+constexpr int kPmDipoleThreads = 1024;
+constexpr int kPmDepositThreads = 256;
 
 struct TileGeo {
   int T, log2T, log2nt, n_tiles;
@@ -172,7 +177,8 @@ __global__ void __launch_bounds__(256) k_bin_scatter(BinArgs a) {
 // ------------------------------------------------------------- deposit
 
 template <int P>
-__global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
+__global__ void __launch_bounds__(kPmDepositThreads) k_tile_deposit(TileArgs a) {
+  constexpr int NT = kPmDepositThreads;
   __shared__ unsigned long long win[(kTileMax + 2) * (kTileMax + 2) * (kTileMax + 2)];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
@@ -189,14 +195,14 @@ __global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) x[c] = a.disp[ps + c * N + i];
   }
-  for (int e = threadIdx.x; e < W3; e += 256) win[e] = 0ull;
+  for (int e = threadIdx.x; e < W3; e += NT) win[e] = 0ull;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   __syncthreads();
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
   constexpr int shift = 3 * kWeightBits - kMassBits;
-  for (; p < end; p += 256) {
+  for (; p < end; p += NT) {
     long long j[3];
     lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
     int w[3][P], l0[3];
@@ -207,8 +213,8 @@ __global__ void __launch_bounds__(256) k_tile_deposit(TileArgs a) {
       // local index of the first stencil node in the window (home at h - o + 1)
       l0[c] = home_node<P>(U, nm) - o[c] + 1 - (P == 3 ? 1 : 0);
     }
-    if (p + 256 < end) {
-      i = a.sorted[slot * N + p + 256];
+    if (p + NT < end) {
+      i = a.sorted[slot * N + p + NT];
 #pragma unroll
       for (int c = 0; c < 3; ++c) x[c] = a.disp[ps + c * N + i];
     }
@@ -492,7 +498,8 @@ __global__ void k_dipole_scale(const unsigned int* umax_bits, double* scale, dou
 // value rounded to an int32 at the slot's fixed-point scale (|value| <=
 // max|u| sum|c_s| < 2^31 there)
 template <int P, int ORD>
-__global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
+__global__ void __launch_bounds__(kPmDipoleThreads) k_tile_dipole(TileArgs a) {
+  constexpr int NT = kPmDipoleThreads;
   constexpr int H = ORD / 2, R = 1 + H, Q = P + 2 * H;
   extern __shared__ unsigned long long dwin[];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -502,7 +509,7 @@ __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   // the first particle's loads are in flight while the window is cleared;
   // later ones are fetched while the current one scatters
-  int p = beg + (int)(((threadIdx.x & 15) << 4) | (threadIdx.x >> 4));  // lanes 16 apart in the tile list
+  int p = beg + (int)(((threadIdx.x % (NT / 16)) * 16) + threadIdx.x / (NT / 16));  // lanes 16 apart in the tile list
   long long i = 0;
   float x[3] = {0.f, 0.f, 0.f}, u[3] = {0.f, 0.f, 0.f};
   if (p < end) {
@@ -513,19 +520,19 @@ __global__ void __launch_bounds__(256) k_tile_dipole(TileArgs a) {
       u[c] = a.u_sorted[ps + c * N + p];
     }
   }
-  for (int e = threadIdx.x; e < W3; e += 256) dwin[e] = 0ull;
+  for (int e = threadIdx.x; e < W3; e += NT) dwin[e] = 0ull;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   __syncthreads();
   // fixed point: every node value is below 2^31 at this scale (a power of two)
   const float S = (float)a.scale[slot];
-  for (; p < end; p += 256) {
+  for (; p < end; p += NT) {
     float w[3][P], dw[3][P];
     int l0[3];
     tile_weights<P>(a, i, x, o, R, w, dw, l0);
     const float us[3] = {u[0] * S, u[1] * S, u[2] * S};
-    if (p + 256 < end) {
-      const int q = p + 256;
+    if (p + NT < end) {
+      const int q = p + NT;
       i = a.sorted[slot * N + q];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -643,8 +650,8 @@ hipError_t launch_tile(const TileArgs& a, int kind, int mak, int ord, hipStream_
   } while (0)
   switch (kind) {
     case TK_DEPOSIT:
-      if (mak == 2) k_tile_deposit<2><<<grid, 256, 0, s>>>(a);
-      else k_tile_deposit<3><<<grid, 256, 0, s>>>(a);
+      if (mak == 2) k_tile_deposit<2><<<grid, kPmDepositThreads, 0, s>>>(a);
+      else k_tile_deposit<3><<<grid, kPmDepositThreads, 0, s>>>(a);
       break;
     case TK_KICK:
       if (mak == 2) PM_TILE_ORD(k_tile_kick, 2); else PM_TILE_ORD(k_tile_kick, 3);
@@ -661,7 +668,7 @@ hipError_t launch_tile(const TileArgs& a, int kind, int mak, int ord, hipStream_
       size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
       // ORD 6 needs 110 KB of LDS: above the default dynamic limit (raised
       // once by configure_tile_kernels)
-#define PM_DIPOLE(P, O) k_tile_dipole<P, O><<<grid, 256, lds, s>>>(a)
+#define PM_DIPOLE(P, O) k_tile_dipole<P, O><<<grid, kPmDipoleThreads, lds, s>>>(a)
       if (mak == 2) {
         if (ord == 2) PM_DIPOLE(2, 2); else if (ord == 4) PM_DIPOLE(2, 4); else PM_DIPOLE(2, 6);
       } else {
