@@ -268,8 +268,8 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=160.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the path would shard as described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(one process per GPU, each on its own slots, is how it would shard)", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         import torch
