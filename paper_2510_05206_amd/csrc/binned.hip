@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(256) k_tile_adj_kick(TileArgs a) {
   red[threadIdx.x] = umax;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0 && red[0] > 0.f)
@@ -1143,7 +1143,7 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
   red[threadIdx.x] = umax;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0 && red[0] > 0.f)

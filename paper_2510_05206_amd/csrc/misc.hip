@@ -133,7 +133,7 @@ __global__ void k_dot_partial(const float* a, const float* b, long long n, long 
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[slot * kDotBlocks + blockIdx.x] = sh[0];

@@ -76,10 +76,11 @@ struct pm_ctx {
   hipGraphExec_t run_exec = nullptr;
   unsigned long long gen = 1, run_gen = 0;
   ~pm_ctx() {
-    for (auto& p : pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
-    for (auto e : pool) hipEventDestroy(e);
-    if (run_exec) hipGraphExecDestroy(run_exec);
-    if (cap) hipStreamDestroy(cap);
+    // teardown: nothing useful can be done with an error here
+    for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+    if (run_exec) (void)hipGraphExecDestroy(run_exec);
+    if (cap) (void)hipStreamDestroy(cap);
   }
 };
 
@@ -117,13 +118,13 @@ void prof_begin(pm_ctx* c, int cls) {
   if (!c->prof) return;
   hipEvent_t a = take_event(c), b = take_event(c);
   if (!a || !b) return;
-  hipEventRecord(a, c->stream);
+  (void)hipEventRecord(a, c->stream);  // timing is best effort: a failed record reads as no time
   c->pending.push_back({cls, a, b});
 }
 
 void prof_end(pm_ctx* c) {
   if (!c->prof || c->pending.empty()) return;
-  hipEventRecord(c->pending.back().b, c->stream);
+  (void)hipEventRecord(c->pending.back().b, c->stream);
 }
 
 // two launches timed as one stage (the first error wins)
@@ -934,7 +935,7 @@ pm_status pm_run(pm_ctx* c) {
       hipError_t e = hipStreamEndCapture(c->cap, &g);
       c->stream = user;
       if (st) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st;
       }
       if (e != hipSuccess) return fail(c, PM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
