@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
 // u_c dA_c/du (u = beta V_bar); V_bar *= alpha; u stored in sorted order and
 // max|u| reduced per slot (fixed-point scale of the scatter)
 template <int P, int ORD>
-__global__ void __launch_bounds__(256) k_tile_adj_kick(TileArgs a) {
+__global__ void __launch_bounds__(256, 2) k_tile_adj_kick(TileArgs a) {  // <= 256 VGPRs (two workgroups per CU)
   constexpr int R = 1 + ORD / 2;
   __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
   __shared__ float red[256];
