@@ -967,13 +967,15 @@ __device__ __forceinline__ void es_particle(const TileArgs& a, long long i, cons
   }
 }
 
-// The first two particles of every thread (a tile holds 512 on average)
-// keep their weights, positions and velocities in registers over the three
-// components, so their dependent loads (index, position, table rows) are
-// paid once; particles of denser tiles recompute them per component.
-__global__ void __launch_bounds__(256, 3) k_tile_es_kick(TileArgs a) {  // <= 168 VGPRs: 3 waves per SIMD
+// The first particle of every thread keeps its weights, position and
+// velocity in registers over the three components, so its dependent loads
+// (index, position, table rows) are paid once; the others (a tile holds 512
+// particles on average) recompute them per component.  One cached particle
+// at <= 128 VGPRs (four workgroups per CU) measured 5% faster than two at
+// <= 168 (three per CU).
+__global__ void __launch_bounds__(256, 4) k_tile_es_kick(TileArgs a) {  // <= 128 VGPRs: 4 waves per SIMD
   extern __shared__ float fwin[];  // one (T + 5)^3 window, the components in turn
-  constexpr int K = 2;
+  constexpr int K = 1;
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   const int W = a.T + kEsLo + kEsHi;
