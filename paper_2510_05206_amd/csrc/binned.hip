@@ -716,7 +716,7 @@ hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s) {
 // cells beyond it: window rows then start on the tile's 64-byte boundary.
 namespace {
 constexpr int kEsW = 6, kEsLo = kEsHaloLo, kEsHi = kEsHaloHi;
-constexpr int kEsSpreadThreads = 512;  // threads per ES deposit workgroup (16 waves per CU at two per CU)
+constexpr int kEsSpreadThreads = 512;  // threads per ES spread workgroup (deposit, gradient spread): 16 waves per CU at two per CU
 constexpr int kEsShift = kFracBits - 12;  // 4096 samples per cell
 constexpr int kEsSub = (1 << kEsShift) - 1;
 
