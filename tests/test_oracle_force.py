@@ -150,3 +150,43 @@ def test_plane_wave_force_converges_at_fourth_order():
         assert np.abs(g[1]).max() < 1e-15 and np.abs(g[2]).max() < 1e-15
         errs.append(np.abs(g[0] - exact).max() / np.abs(exact).max())
     assert 14 < errs[0] / errs[1] < 18
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_window_is_single_particle_aliased_spectrum(order):
+    # tab. interpolation_kernels, Fourier column: the DFT of one particle's
+    # real-space deposit is, by Poisson summation, the aliased sum over images
+    # of the kernel's continuous transform, sum_a W(theta + 2 pi a)
+    # exp(-i (theta + 2 pi a) u), and the 3D deposit factorises over axes
+    n = 16
+    rng = np.random.default_rng(11)
+    theta = 2 * np.pi * np.fft.fftfreq(n)
+    a = np.arange(-20000, 20001)[:, None]
+    for _ in range(3):
+        u = rng.uniform(0, n, 3)
+        rho = mesh.deposit_u(u[:, None], n, order).reshape(n, n, n)
+        got = np.fft.fftn(rho)
+        axes = []
+        for c in range(3):
+            th = theta[None, :] + 2 * np.pi * a
+            axes.append(np.sum(force.window_1d(th, order) * np.exp(-1j * th * u[c]), axis=0))
+        ref = axes[0][:, None, None] * axes[1][None, :, None] * axes[2][None, None, :]
+        assert np.abs(got - ref).max() < 1e-8
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_deconvolution_divides_by_the_squared_window(order):
+    # a plane wave on the mesh: the deconvolved multiplier is the plain one
+    # divided by W(theta_x)^2 W(theta_y)^2 W(theta_z)^2 with the kernel's own
+    # order p (window_1d pinned by the aliased-sum test above)
+    n = 16
+    m0 = np.array([2, 1, 3])
+    j = np.indices((n, n, n)).reshape(3, -1)
+    delta = 0.01 * np.cos(2 * np.pi * (m0 @ j) / n)
+    plain = PMConfig(n // 2, n, 10.0, order=order, deconvolve=False, grad_order=4, lap_order=0)
+    dec = PMConfig(n // 2, n, 10.0, order=order, deconvolve=True, grad_order=4, lap_order=0)
+    g0 = force.force_meshes(plain, delta, 1.0)
+    g1 = force.force_meshes(dec, delta, 1.0)
+    th = 2 * np.pi * m0 / n
+    W = np.prod(force.window_1d(th, order))
+    assert np.abs(g1 - g0 / (W * W)).max() < 1e-14 * np.abs(g1).max()
