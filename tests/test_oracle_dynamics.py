@@ -3,6 +3,7 @@ store-all adjoint (CPU only)."""
 import math
 
 import numpy as np
+from scipy.integrate import quad
 import pytest
 
 from oracle import adjoint, cosmo, ics, mesh, nbody, nufft, pk
@@ -122,7 +123,8 @@ def test_pk_single_cosine_mode():
     kb, p, cnt = pk.power_spectrum(delta, box, 8)
     b = int(pk.bin_index(np.array([m0 @ m0]))[0])
     th = 2 * math.pi * m0 / n
-    W = np.prod((np.sin(th / 2) / (th / 2)) ** 2)
+    # the CIC window by quadrature of the triangle kernel's Fourier integral
+    W = np.prod([quad(lambda x, t=t: (1.0 - abs(x)) * math.cos(t * x), -1.0, 1.0, points=[0.0])[0] for t in th])
     assert abs(p[b - 1] / (amp ** 2 * box ** 3 / (2 * W * W * cnt[b - 1])) - 1) < 1e-12
     others = np.delete(p, b - 1)
     assert np.all(np.abs(others) < 1e-20)
@@ -204,3 +206,18 @@ def test_full_gradient_matches_finite_differences():
     p3 = nbody.Problem(prob.pm, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=0.9 - 1e-6)
     fd = (loss_of(w.reshape(-1), p2) - loss_of(w.reshape(-1), p3)) / 2e-6
     assert abs(dsig - fd) < 1e-5 * abs(fd)
+
+
+def test_powerlaw_spectrum_gradient_has_no_sigma8_term():
+    # the power-law configuration is normalised by its rms displacement, so
+    # its forward run does not change with sigma8 and dL/dsigma8 is 0
+    cfg = PMConfig(8, 16, 25.0, order=2, deconvolve=False, grad_order=4, lap_order=0)
+    kw = dict(omega_m=1.0, spectrum="powerlaw", a_start=0.02, a_end=1.0, n_steps=2)
+    p1 = nbody.Problem(cfg, sigma8=0.8, **kw)
+    p2 = nbody.Problem(cfg, sigma8=1.1, **kw)
+    w = nbody.white_noise(p1, 9).astype(np.float64)
+    x1, _ = nbody.run(p1, w=w)
+    x2, _ = nbody.run(p2, w=w)
+    assert np.array_equal(x1, x2)
+    _, dsig, _ = adjoint.gradient(p1, w, lambda d: 2 * d)
+    assert dsig == 0.0
