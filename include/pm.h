@@ -198,7 +198,9 @@ pm_status pm_use_graphs(pm_ctx* ctx, int32_t enable);
  * memory independent of n_steps, then pull back through the initial
  * conditions.  dL_ddelta: device [B][n_g^3] cotangent of the final CIC
  * density contrast.  Outputs: dL_dw device [B][N], dL_dsigma8 device [B]
- * (double).  Leaves the particle state at the initial conditions. */
+ * (double; 0 with PM_SPEC_POWERLAW, whose amplitude is set by its rms
+ * displacement and not by sigma8).  Leaves the particle state at the
+ * initial conditions. */
 pm_status pm_adjoint(pm_ctx* ctx, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8);
 
 /* Binned power spectrum of the CIC density of the current positions:

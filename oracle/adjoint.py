@@ -15,8 +15,10 @@ scatter/gather rules of App. "Custom VJP and JVP":
 * scatter w.r.t. positions (a gather of the mesh cotangent with grad W).
 
 The initial-condition VJP uses Psi^0 = D_start psi, V^0 = psi and the
-transposed IC multiplier; psi is proportional to sigma8 and the BullFrog
-coefficients do not depend on it, so dL/dsigma8 = <psi_bar, psi> / sigma8.
+transposed IC multiplier; with the BBKS spectrum psi is proportional to
+sigma8 and the BullFrog coefficients do not depend on it, so
+dL/dsigma8 = <psi_bar, psi> / sigma8 (0 for the power-law spectrum, whose
+amplitude is set by its rms displacement).
 """
 from __future__ import annotations
 
@@ -94,7 +96,9 @@ def gradient(prob, w, dL_ddelta):
     xbar, vbar = reverse_cotangents(prob, record, xbar, vbar)
     psibar = prob.D_start() * xbar + vbar
     wbar = ic_vjp(prob, psibar)
-    dsig = float(np.sum(psibar * psi_lin)) / prob.sigma8
+    # the power-law spectrum is normalised by its rms displacement, not by
+    # sigma8, so there the initial conditions do not depend on sigma8
+    dsig = float(np.sum(psibar * psi_lin)) / prob.sigma8 if prob.spectrum == "bbks" else 0.0
     return wbar.reshape(-1), dsig, delta
 
 

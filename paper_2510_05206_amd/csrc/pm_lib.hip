@@ -801,11 +801,13 @@ pm_status pm_set_slot_params(pm_ctx* c, const int32_t* n_steps, const double* si
       return fail(c, PM_EINVAL, "slot n_steps out of range");
     if (sigma8 && !(sigma8[b] > 0)) return fail(c, PM_EINVAL, "sigma8 must be positive");
   }
-  ++c->gen;
+  // the run graph bakes in the per-slot schedules (not sigma8, which only the
+  // initial conditions read): rebuild it only when a step count changes
   for (int b = 0; b < c->cfg.batch; ++b) {
     if (n_steps && n_steps[b] != c->slot_steps[b]) {
       c->slot_steps[b] = n_steps[b];
       c->slot_table[b] = bullfrog_table(c->growth, c->cfg.a_start, c->cfg.a_end, n_steps[b]);
+      ++c->gen;
     }
     if (sigma8) c->slot_sigma8[b] = sigma8[b];
   }
@@ -1210,9 +1212,11 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   rl.stream = c->stream;
   rl.active = act;
   KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
-  // dL/dsigma8 = <psi_bar, psi>/sigma8 = <w_bar, w>/sigma8 (psi is linear in w and sigma8)
+  // dL/dsigma8 = <psi_bar, psi>/sigma8 = <w_bar, w>/sigma8 (psi is linear in w and
+  // sigma8).  The power-law spectrum is normalised by its rms displacement, so
+  // there psi does not depend on sigma8 and the derivative is 0.
   std::vector<double> inv(B);
-  for (int b = 0; b < B; ++b) inv[b] = 1.0 / c->slot_sigma8[b];
+  for (int b = 0; b < B; ++b) inv[b] = c->cfg.spectrum == PM_SPEC_BBKS ? 1.0 / c->slot_sigma8[b] : 0.0;
   KLAUNCH(c, PM_K_MISC, launch_dot(dL_dw, c->w, N, N, B, c->dot_partial, dL_dsigma8, inv.data(), act, c->stream));
   c->ran = false;
   return PM_OK;
