@@ -68,6 +68,7 @@ class PMSim:
         self.lib = _lib.load()
         self.cfg = cfg
         self.device = torch.device(device)
+        self.state_token = 0      # bumped by every call that changes the particle state
         ctx = C.c_void_p()
         ccfg = cfg.to_c()
         _lib.check(self.lib.pm_create(C.byref(ccfg), C.byref(ctx)), None, "pm_create")
@@ -89,7 +90,12 @@ class PMSim:
             self.ctx = None
 
     # --------------------------------------------------------------- calls
+    _STATE_CALLS = frozenset({"pm_init_ics", "pm_step", "pm_run", "pm_adjoint", "pm_set_state", "pm_deposit",
+                              "pm_force", "pm_force_vjp", "pm_set_active"})
+
     def _call(self, name, *args):
+        if name in self._STATE_CALLS:
+            self.state_token += 1
         _lib.check(getattr(self.lib, name)(self.ctx, *args), self.ctx, name)
 
     def _new(self, *shape, dtype=torch.float32):
@@ -212,19 +218,50 @@ class PMSim:
 
 
 class PMFunction(torch.autograd.Function):
-    """delta_final = F(w): forward runs ICs + BullFrog steps on the GPU and
-    keeps only the context; backward runs the adjoint (memory independent of
-    the number of steps)."""
+    """delta = F(w, sigma8) behind torch autograd (Sec. "Automatic
+    differentiation", Sec. "Adjoint method").
+
+    forward(w [B, N], sigma8 [B], sim) sets each slot's sigma8, runs the
+    initial conditions and the BullFrog steps on the GPU and returns the final
+    CIC density contrast [B, n_g^3]; it saves no trajectory, only the context.
+    backward(delta_bar) runs pm_adjoint, which integrates the primal state and
+    the cotangents back to the initial conditions (memory independent of the
+    number of steps), and returns (w_bar, sigma8_bar, None).  The context must
+    still hold this forward's final state: any later call that changes it
+    (another forward, a step, set_state, a test hook) makes backward raise."""
 
     @staticmethod
-    def forward(ctx, w, sim):
-        sim.init_ics(w=w)
+    def forward(ctx, w, sigma8, sim):
+        B, N = sim.cfg.batch, sim.cfg.N
+        if w.numel() != B * N:
+            raise ValueError(f"w must hold {B} x {N} values")
+        s8 = torch.as_tensor(sigma8, dtype=torch.float64).detach().reshape(-1).cpu()
+        if s8.numel() != B:
+            raise ValueError(f"sigma8 must hold {B} values")
+        sim.set_slot_params(sigma8=[float(v) for v in s8])
+        sim.init_ics(w=w.detach())
         sim.run()
+        delta = sim.density()
         ctx.sim = sim
-        return sim.density()
+        ctx.token = sim.state_token
+        ctx.w_shape, ctx.w_dtype = w.shape, w.dtype
+        st = torch.as_tensor(sigma8)
+        ctx.s_shape, ctx.s_dtype, ctx.s_device = st.shape, st.dtype, st.device
+        return delta
 
     @staticmethod
     def backward(ctx, g):
-        dw, ds = ctx.sim.adjoint(g)
-        ctx.sim.dL_dsigma8 = ds
-        return dw, None
+        sim = ctx.sim
+        if sim.state_token != ctx.token:
+            raise RuntimeError("PMFunction.backward: the context no longer holds this forward's final state "
+                               "(it was run or modified after the forward)")
+        dw, ds = sim.adjoint(g)
+        ctx.sim = None
+        return (dw.reshape(ctx.w_shape).to(ctx.w_dtype),
+                ds.reshape(ctx.s_shape).to(device=ctx.s_device, dtype=ctx.s_dtype), None)
+
+
+def simulate(w, sigma8, sim):
+    """Differentiable forward model: final CIC density contrast of the white
+    noise w and sigma8 (PMFunction.apply)."""
+    return PMFunction.apply(w, sigma8, sim)

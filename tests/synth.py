@@ -80,3 +80,5 @@ C3 = dict(n_p=512, n_g=1024, box=1000.0, omega_m=0.31, h=0.68, n_s=0.965, sigma8
           es_beta=13.8, grad_order=0, lap_order=0, mak=2, deconvolve=False)
 C3_SUB = dict(C3, n_p=128, n_g=256, box=250.0)      # the 128^3 sub-problem (same resolution)
 C3_SMALL = dict(C3, n_p=32, n_g=64, box=62.5)
+# the PM path at the headline size: 512^3 particles on a 1024^3 mesh, TSC + deconvolution
+PM_512_TSC = dict(C2, n_p=512, n_g=1024, box=1000.0, n_steps=6)
