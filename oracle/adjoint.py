@@ -82,18 +82,19 @@ def ic_vjp(prob, psibar):
     return np.fft.irfftn(acc, s=(n, n, n), axes=(0, 1, 2))
 
 
-def gradient(prob, w, dL_ddelta):
+def gradient(prob, w, dL_ddelta, progress=None):
     """Reverse-mode gradient of L(delta_final) w.r.t. the white noise w and
     sigma8, given a function dL_ddelta(delta) -> cotangent mesh.
-    Returns (w_bar (n_p^3,), dL/dsigma8, delta_final)."""
+    Returns (w_bar (n_p^3,), dL/dsigma8, delta_final).  ``progress``, if
+    given, is called with a short message after each forward and reverse step."""
     from .nbody import initial_state, run_from
     psi0, vel0, psi_lin = initial_state(prob, w)
     record = []
-    psiN, _ = run_from(prob, psi0, vel0, record=record)
+    psiN, _ = run_from(prob, psi0, vel0, record=record, progress=progress)
     delta = final_density(prob, psiN)
     xbar = density_vjp(psiN, prob.pm.n_p, prob.pm.n_g, dL_ddelta(delta))
     vbar = np.zeros_like(xbar)
-    xbar, vbar = reverse_cotangents(prob, record, xbar, vbar)
+    xbar, vbar = reverse_cotangents(prob, record, xbar, vbar, progress)
     psibar = prob.D_start() * xbar + vbar
     wbar = ic_vjp(prob, psibar)
     # the power-law spectrum is normalised by its rms displacement, not by
@@ -102,12 +103,14 @@ def gradient(prob, w, dL_ddelta):
     return wbar.reshape(-1), dsig, delta
 
 
-def reverse_cotangents(prob, record, xbar, vbar):
+def reverse_cotangents(prob, record, xbar, vbar, progress=None):
     """Apply the cotangent recurrences of tab. adjoint_dkd over the stored
     midpoints, last step first."""
-    for st, (psi_half, _acc) in zip(reversed(prob.steps()), reversed(record)):
+    for i, (st, (psi_half, _acc)) in enumerate(zip(reversed(prob.steps()), reversed(record))):
         vbar = vbar + st.tau2 * xbar                    # adjoint of drift 2
         xbar = xbar + problem_force_vjp(prob, psi_half, st.s, st.beta * vbar)  # adjoint kick
         vbar = st.alpha * vbar                          # velocity rescale
         vbar = vbar + st.tau1 * xbar                    # adjoint of drift 1
+        if progress is not None:
+            progress(f"oracle reverse step {i} done")
     return xbar, vbar

@@ -75,24 +75,27 @@ def white_noise(prob: Problem, seed):
     return philox.white_noise(seed, prob.pm.n_p)
 
 
-def run_from(prob: Problem, psi, vel, steps=None, record=None):
+def run_from(prob: Problem, psi, vel, steps=None, record=None, progress=None):
     """Integrate (Psi, V) through the BullFrog steps; ``record`` (a list), if
-    given, receives (Psi^{n+1/2}, A^{n+1/2}) per step."""
+    given, receives (Psi^{n+1/2}, A^{n+1/2}) per step; ``progress``, if given,
+    is called with a short message after each step."""
     force = prob.force_fn()
     psi = np.array(psi, dtype=np.float64)
     vel = np.array(vel, dtype=np.float64)
-    for st in (prob.steps() if steps is None else steps):
+    for i, st in enumerate(prob.steps() if steps is None else steps):
         psi += st.tau1 * vel
         acc = force(psi, st.s)
         if record is not None:
             record.append((psi.copy(), acc))
         vel = st.alpha * vel + st.beta * acc
         psi += st.tau2 * vel
+        if progress is not None:
+            progress(f"oracle forward step {i} done")
     return psi, vel
 
 
-def run(prob: Problem, seed=None, w=None):
+def run(prob: Problem, seed=None, w=None, progress=None):
     if w is None:
         w = white_noise(prob, seed)
     psi0, vel0, _ = initial_state(prob, w)
-    return run_from(prob, psi0, vel0)
+    return run_from(prob, psi0, vel0, progress=progress)

@@ -106,7 +106,7 @@ def nufft64():
         dobs["v"] = 0.5 * dd.std() * np.random.default_rng(synth.SEED_NOISE).normal(size=dd.size)
         return 2.0 * (dd - dobs["v"])
 
-    gw, gs, delta = oadj.gradient(prob, w, cot)
+    gw, gs, delta = oadj.gradient(prob, w, cot, progress=say)
     say(f"oracle 64^3 NUFFT gradient {time.time() - t0:.0f} s")
     return dict(d=d, psi0=psi0, vel0=vel0, gw=gw.reshape(-1), gs=gs, delta=delta, dobs=dobs["v"])
 
@@ -159,7 +159,7 @@ def test_gradient_matches_oracle_store_all_c4_resolution():
         return 2.0 * (dd - dobs["v"])
 
     t0 = time.time()
-    gw, gs, _ = oadj.gradient(prob, w, cot)
+    gw, gs, _ = oadj.gradient(prob, w, cot, progress=say)
     say(f"oracle 64^3 C4 gradient {time.time() - t0:.0f} s")
     sim = make_sim(d, adj=True)
     sim.init_ics([synth.SEED_W])

@@ -85,7 +85,7 @@ def test_nufft_run_matches_oracle(wl):
     k, p, cnt = (t.cpu().numpy()[0] for t in sim.power_spectrum(d["n_g"] // 2))
     t0 = time.time()
     prob = synth.oracle_problem(d)
-    psi, _ = onbody.run(prob, w=ophilox.white_noise(synth.SEED_W, d["n_p"]))
+    psi, _ = onbody.run(prob, w=ophilox.white_noise(synth.SEED_W, d["n_p"]), progress=say)
     dref = oadj.final_density(prob, psi)
     kr, pr, cr = opk.power_spectrum(dref, d["box"], d["n_g"] // 2)
     err = rel_l2(delta, dref)
