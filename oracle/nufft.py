@@ -25,8 +25,12 @@ Fixed-point ES spreading (the bit pattern the GPU reproduces): the 1D weight
 of a node at fixed-point distance d (B = 20 fraction bits) is integer linear
 interpolation in a table T[t] = rne(phi(t / 4096) 2^20), t = 0 .. 3*4096,
   w = T[i] + floor(((T[i+1] - T[i]) f + 128) / 256),  i = d >> 8, f = d & 255,
-and the 3D product of three such weights is rounded half-to-even to the 2^32
-mass unit (no remainder step: the ES kernel is not a partition of unity).
+and the 3D weight of node (x, y, z) is formed in two truncating steps,
+  A_xy = floor(w_x w_y / 2^17),  m_xyz = floor(A_xy w_z / 2^12),
+so that A_xy < 2^24 and m_xyz <= 2^31: the unit is 2^31 at the kernel's peak
+phi(0)^3, and each node costs two 24-bit products.  There is no remainder
+step (the ES kernel is not a partition of unity); the truncations bias each
+node by less than 2^-23 of the peak, far below FP32 resolution of the sums.
 """
 from __future__ import annotations
 
@@ -38,6 +42,7 @@ from . import mesh
 
 TAB_PER_CELL = 4096
 K_ES = 20
+ES_UNIT = 2.0 ** 31        # fixed-point value of phi(0)^3
 
 
 def es_phi(z, beta):
@@ -275,9 +280,10 @@ def es_fixed_weight(dist_fixed, table):
 
 
 def es_fixed_stencil(U, n_f, width=6, beta=13.8):
-    """Nodes and integer 3D weights (2^32 mass unit, rounded half-even) of
-    the fixed-point ES spreading for fixed-point coordinates U (3, n):
-    yields (flat node index, weight) per stencil point, width^3 of them."""
+    """Nodes and integer 3D weights (2^31 at the kernel's peak, two
+    truncating steps) of the fixed-point ES spreading for fixed-point
+    coordinates U (3, n): yields (flat node index, weight) per stencil point,
+    width^3 of them."""
     table = es_table(width, beta)
     one = 1 << mesh.B_FRAC
     base = (U >> mesh.B_FRAC) - (width // 2 - 1)
@@ -289,15 +295,14 @@ def es_fixed_stencil(U, n_f, width=6, beta=13.8):
             # strictly inside the support: |z| < 1
             rows.append(np.where(d < (width // 2) * one, es_fixed_weight(d, table), 0))
         W.append(np.stack(rows))
-    shift = 3 * K_ES - 32
     for a in range(width):
         ix = (base[0] + a) % n_f
         for b in range(width):
             iy = (base[1] + b) % n_f
-            wab = W[0][a] * W[1][b]
+            A = (W[0][a] * W[1][b]) >> 17
             for c in range(width):
                 iz = (base[2] + c) % n_f
-                yield (ix * n_f + iy) * n_f + iz, mesh._rne_shift(wab * W[2][c], shift)
+                yield (ix * n_f + iy) * n_f + iz, (A * W[2][c]) >> 12
 
 
 def deposit_fixedpoint_es(psi_f32, n_p, n_f, width=6, beta=13.8):

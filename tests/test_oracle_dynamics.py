@@ -110,7 +110,20 @@ def test_es_fixedpoint_spread_matches_float_spread():
     psi = np.random.default_rng(3).normal(0, 1.0, (3, n_p ** 3)).astype(np.float32)
     fx = nufft.deposit_fixedpoint_es(psi, n_p, n_f)
     fl = nufft._spread_float(mesh.mesh_coords(psi.astype(np.float64), n_p, n_f), n_f, 6, 13.8)
-    assert np.linalg.norm(fx / 2.0 ** 32 - fl) / np.linalg.norm(fl) < 2e-6
+    assert np.linalg.norm(fx / nufft.ES_UNIT - fl) / np.linalg.norm(fl) < 2e-6
+
+
+def test_es_fixedpoint_peak_and_support():
+    """A particle on a node puts phi(0)^3 = 2^31 units on it; the nodes 3
+    cells away lie on the edge of the support (phi = 0 there); a half-cell
+    offset along z weighs the two nearest nodes equally."""
+    n_f = 16
+    st = {int(l[0]): int(w[0]) for l, w in nufft.es_fixed_stencil(np.zeros((3, 1), dtype=np.int64), n_f)}
+    assert st[0] == 2 ** 31
+    assert st[3] == 0 and st[(3 * n_f) * n_f] == 0 and st[n_f - 2] > 0
+    U = np.array([[0], [0], [1 << 19]], dtype=np.int64)
+    st = {int(l[0]): int(w[0]) for l, w in nufft.es_fixed_stencil(U, n_f)}
+    assert st[0] == st[1] and st[n_f - 1] == st[2] and st[0] > st[2] > 0
 
 
 # ------------------------------------------------------------------ P(k) ---
