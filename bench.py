@@ -39,17 +39,21 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 
 
-def launch_model(cfg):
+def launch_model(cfg, int64_mass=True):
     """Algorithmic HBM bytes of every timed launch of one bench step (ICs, the
     forward run, density, P(k) and the adjoint of one slot, PM force), per
     kernel class: a list of (launches, bytes per launch).  Minimum traffic:
     every input read once and every output written once; particle arrays FP32
-    SoA [3][N] (12 B per particle each), the deposit mesh int64 [M], the other
-    meshes FP32 [M], half spectra complex64 of n^2 (n/2+1) modes (unpadded).
-    The lattice index of a particle and the tile binning tables are the
-    design's overhead, not algorithmic bytes."""
+    SoA [3][N] (12 B per particle each), the other meshes FP32 [M], half
+    spectra complex64 of n^2 (n/2+1) modes (unpadded).  With int64_mass (the
+    path's stated model) every deposit writes the int64 fixed-point mesh
+    [M] and the forward R2C reads it; without it (this design) the deposits
+    of a force evaluation write the FP32 contrast instead and the R2C reads
+    that.  The lattice index of a particle and the tile binning tables are
+    the design's overhead, not algorithmic bytes."""
     n, p, K = cfg.n_g, cfg.n_p, cfg.n_steps
     M, N = n ** 3, p ** 3
+    mb = 8 if int64_mass else 4        # bytes per cell of the force chain's mass mesh
     Sn, Sp = 8 * n * n * (n // 2 + 1), 8 * p * p * (p // 2 + 1)   # bytes of one half spectrum
     ic_rows = [(4, 4 * N + Sp), (3, Sp + 8 * N), (1, Sp + 4 * N)]
     ic_cols = [(15, 2 * Sp), (1, 4 * Sp)]
@@ -63,12 +67,12 @@ def launch_model(cfg):
         return {
             # force spreads write the FP32 density; the observed field and the
             # P(k) mesh are the int64 fixed-point mesh
-            "deposit": [(2 * K, 12 * N + 4 * M), (2, 12 * N + 8 * M)],
+            "deposit": [(2 * K, 12 * N + mb * M), (2, 12 * N + 8 * M)],
             "bin": [(K, 40 * N), (K + 3, 16 * N)],
             # R2C of the mass (run, adjoint recompute; P(k) unpruned from the
             # int64 mesh), 3 force C2R per force evaluation plus the adjoint's
             # b_bar, the R2C of the adjoint's spread kernel gradient
-            "fft_rows": [(2 * K, 4 * M + Sz), (1, 8 * M + Sn), (7 * K, Sz + 4 * M), (K, 4 * M + Sz)] + ic_rows,
+            "fft_rows": [(2 * K, mb * M + Sz), (1, 8 * M + Sn), (7 * K, Sz + 4 * M), (K, 4 * M + Sz)] + ic_rows,
             # y forward (mass and the adjoint's gradient spread), x passes
             # (multiplier between forward and inverse x), inverse y
             "fft_cols": [(3 * K, Sz + Sy), (7 * K, 2 * Sy), (7 * K, Sy + Sz), (2, 2 * Sn)] + ic_cols,
@@ -81,12 +85,12 @@ def launch_model(cfg):
         }
     return {
         # fixed-point mass assignment: read the positions, write the int64 mesh
-        "deposit": [(2 * K + 2, 12 * N + 8 * M)],
+        "deposit": [(2 * K, 12 * N + mb * M), (2, 12 * N + 8 * M)],
         # counting sort: read positions, write the sorted index (in the run
         # it also applies the first drift: read V, write the positions)
         "bin": [(K, 40 * N), (K + 3, 16 * N)],
         # z rows: int64 or FP32 mesh -> half spectrum, and back to FP32
-        "fft_rows": [(2 * K + 1, 8 * M + Sn), (K, 4 * M + Sn), (3 * K, Sn + 4 * M)] + ic_rows,
+        "fft_rows": [(2 * K, mb * M + Sn), (1, 8 * M + Sn), (K, 4 * M + Sn), (3 * K, Sn + 4 * M)] + ic_rows,
         # y / x passes (one with the fused multiplier): read + write the spectrum
         "fft_cols": [(9 * K + 2, 2 * Sn)] + ic_cols,
         # read X, V and phi, write X, V
@@ -150,9 +154,12 @@ def measured_traffic(workload):
 
 def rooflines(cfg, kt, steps):
     """Per-class HBM roofline: the model's bytes over the class's measured
-    time, after checking the model's launch count against the measured one."""
+    time, after checking the model's launch count against the measured one.
+    frac uses the stated model (int64 mass meshes); "design" gives the same
+    time against this design's own minimum bytes (FP32 contrast)."""
     out = {}
     lmodel = lds_model(cfg)
+    dmodel = launch_model(cfg, int64_mass=False)
     for cls, parts in launch_model(cfg).items():
         ms, nl = kt.get(cls, (0.0, 0))
         count = sum(c for c, _ in parts) * steps
@@ -164,6 +171,11 @@ def rooflines(cfg, kt, steps):
         out[cls] = {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                     "ms_per_step": round(ms / steps, 3), "launches_per_step": count // steps,
                     "avg_launch_us": round(ms / nl * 1e3, 2), "bytes_per_launch": round(total / count)}
+        dtot = sum(c * b for c, b in dmodel[cls]) * steps
+        if dtot != total:
+            dgbs = dtot / (ms * 1e-3) / 1e9
+            out[cls]["design"] = {"bytes_per_launch": round(dtot / count), "achieved": round(dgbs, 1),
+                                  "frac": round(dgbs / HBM_PEAK_GBS, 4)}
         lparts = lmodel.get(cls)
         if lparts:
             ltot = sum(c * b for c, b in lparts) * steps
@@ -171,6 +183,26 @@ def rooflines(cfg, kt, steps):
             out[cls]["lds"] = {"bytes_per_launch": round(ltot / count), "achieved": round(lgbs, 1),
                                "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s", "frac": round(lgbs / LDS_PEAK_GBS, 4)}
     return out
+
+
+def stream_copy_gbs(gib=1.0, reps=5):
+    """Measured HBM bandwidth of a plain device-to-device copy of `gib` GiB
+    (read + write bytes over the median HIP-event time of `reps` copies)."""
+    import torch
+    src = torch.ones(int(gib * 2 ** 28), dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    nbytes = 2 * src.numel() * 4
+    del src, dst
+    return round(nbytes / (sorted(times)[reps // 2] * 1e-3) / 1e9, 1)
 
 
 def cpu_baseline(cfg):
@@ -312,6 +344,7 @@ def main():
         torch.neg(src, out=dst)          # one elementwise read + write of known size
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = stream_copy_gbs()
     if not args.no_kernel_timing:
         sim.profile(True)
         sim.kernel_times()
@@ -339,6 +372,7 @@ def main():
                 traffic = round(traffic[dom] / r["launches_per_step"])
             roof = {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": r["frac"], "traffic": traffic, "kernel": dom,
+                    "stream_copy_gbs": copy_gbs, "frac_of_stream_copy": round(r["achieved"] / copy_gbs, 4),
                     "avg_launch_us": r["avg_launch_us"], "bytes_per_launch": r["bytes_per_launch"],
                     "by_class": by_class}
     assert math.isfinite(float(out["ds"][0]))

@@ -225,7 +225,10 @@ pm_status pm_set_state(pm_ctx* ctx, const float* disp, const float* vel);
 
 /* Deposit the given displacements (device [B][3][N]) with kernel order
  * mak (2 CIC, 3 TSC, 6 = ES of the NUFFT grid) into the int64 mesh
- * mesh_out (device [B][n^3], n = n_g).  Bit-exact fixed-point spec.
+ * mesh_out (device [B][n^3], n = n_g).  Bit-exact fixed-point spec: CIC and
+ * TSC put 2^32 per particle; the ES spreading (Sec. "Force evaluation",
+ * NUFFT paragraphs) puts floor(floor(w_x w_y / 2^17) w_z / 2^12) on each of
+ * its 6^3 nodes from 20-bit 1D table weights, 2^31 at the kernel's peak.
  * This and the two hooks below load disp as the context's particle
  * positions (the previous state is overwritten). */
 pm_status pm_deposit(pm_ctx* ctx, const float* disp, int32_t mak, int64_t* mesh_out);

@@ -709,9 +709,10 @@ hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s) {
 // Exponential-of-semicircle spreading and interpolation (Sec. "Force
 // evaluation", NUFFT paragraphs): width 6 on the fine grid, 1D weights by
 // integer linear interpolation in a table of phi at 4096 samples per cell
-// (20-bit values), so spreading is bit-reproducible; the 3D product is
-// rounded half-even to the 2^32 mass unit (no remainder: the ES kernel is not
-// a partition of unity).  The particles are binned by their first stencil
+// (20-bit values), so spreading is bit-reproducible; the 3D weight of a node
+// is formed in two truncating steps, floor(floor(w_x w_y / 2^17) w_z / 2^12),
+// which puts 2^31 at the kernel's peak phi(0)^3 (no remainder: the ES kernel
+// is not a partition of unity).  The particles are binned by their first stencil
 // node floor(u) - 2, so the window starts at the tile origin and reaches 5
 // cells beyond it: window rows then start on the tile's 64-byte boundary.
 namespace {
@@ -805,18 +806,12 @@ __device__ __forceinline__ int es_weights_d(long long U, const int32_t* __restri
   return h;
 }
 
-// round-half-even of a b c / 2^28 for 1D weights in [0, 2^20] (the
-// fixed-point mass of one node, <= 2^32), with ab = a b given as
-// ab = A1 2^24 + A0: four 24-bit multiplies and 32-bit rounding.
-__device__ __forceinline__ unsigned long long es_node_mass(unsigned A0, unsigned A1, unsigned c) {
-  const unsigned long long p0 = (unsigned long long)(A0 & 0xffffffu) * (c & 0xffffffu);
-  const unsigned long long p1 = (unsigned long long)(A1 & 0xffffffu) * (c & 0xffffffu);
-  const unsigned long long P = p0 + (p1 << 24);  // < 2^61
-  const unsigned hi = (unsigned)(P >> 32), lo = (unsigned)P;
-  unsigned q = (hi << 4) | (lo >> 28);          // floor(P / 2^28) mod 2^32
-  const unsigned rem = lo & 0x0fffffffu;
-  q += (rem + 0x07ffffffu + (q & 1u)) >> 28;    // half-even
-  return ((unsigned long long)(hi >> 28) << 32) | q;
+// fixed-point weight of one node from A = floor(w_x w_y / 2^17) < 2^24 and
+// the z weight c <= 2^20: floor(A c / 2^12) <= 2^31, the low 32 bits of a
+// 24 x 24-bit product shifted (mul_u24, mul_hi_u24, one funnel shift)
+__device__ __forceinline__ unsigned es_node_mass(unsigned A, unsigned c) {
+  const unsigned long long p = (unsigned long long)(A & 0xffffffu) * (c & 0xffffffu);  // < 2^44
+  return (unsigned)(p >> 12);
 }
 
 // The ES windows are (16 + 5)^3 (every NUFFT mesh has 16-cell tiles) and are
@@ -896,10 +891,10 @@ __global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_deposit(TileArgs a
       for (int y = 0; y < kEsW; ++y) {
         const unsigned long long ab =
             (unsigned long long)((unsigned)w[0][x] & 0xffffffu) * ((unsigned)w[1][y] & 0xffffffu);  // <= 2^40
-        const unsigned A0 = (unsigned)ab & 0xffffffu, A1 = (unsigned)(ab >> 24);
+        const unsigned A = (unsigned)(ab >> 17);                                                   // <= 2^23
         unsigned long long* row = ewin + ((l0[0] + x) * W + l0[1] + y) * W + l0[2];
 #pragma unroll
-        for (int z = 0; z < kEsW; ++z) atomicAdd(row + z, es_node_mass(A0, A1, (unsigned)w[2][z]));
+        for (int z = 0; z < kEsW; ++z) atomicAdd(row + z, (unsigned long long)es_node_mass(A, (unsigned)w[2][z]));
       }
   }
   __syncthreads();

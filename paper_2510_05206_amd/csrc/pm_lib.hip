@@ -515,7 +515,7 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   const double mean = N * ph0 * ph0 * ph0 / (double)c->g.M;  // removes most of k = 0
   // FP32 partial sums per window (the force chain is FP32 from here on)
   t.win_f32 = 1;
-  t.win_scale = 1.0 / 4294967296.0;
+  t.win_scale = 1.0 / 2147483648.0;  // the ES node weight is 2^31 at phi(0)^3
   float* rho = reinterpret_cast<float*>(c->mesh);
   AssembleArgs as = assemble_args(c, kEsHaloLo, kEsHaloHi, rho, active);
   as.slab_f32 = 1;
