@@ -88,6 +88,8 @@ def gradient(prob, w, dL_ddelta, progress=None):
     Returns (w_bar (n_p^3,), dL/dsigma8, delta_final).  ``progress``, if
     given, is called with a short message after each forward and reverse step."""
     from .nbody import initial_state, run_from
+    if prob.lpt_order != 1:
+        raise NotImplementedError("the reverse pass covers Zel'dovich initial conditions")
     psi0, vel0, psi_lin = initial_state(prob, w)
     record = []
     psiN, _ = run_from(prob, psi0, vel0, record=record, progress=progress)

@@ -50,3 +50,59 @@ def zeldovich_psi(w, box, spectrum, D_ref):
     wk = np.fft.rfftn(w)
     h = ic_multipliers(n, box, spectrum, D_ref)
     return np.stack([np.fft.irfftn(h[c] * wk, s=(n, n, n), axes=(0, 1, 2)).reshape(-1) for c in range(3)])
+
+
+def second_order_psi(psi1, n):
+    """Second-order LPT displacement psi^(2) (3, N) in lattice units from the
+    first-order field psi^(1) (3, N) on the n^3 lattice.
+
+    Sec. "Lagrangian perturbation theory", eq. LPT_L at n = 2 (the only term
+    is s = 1, with coefficient ((3-2)/2 - 1 - 1) / ((2 + 3/2)(2 - 1)) = -3/7;
+    the mu_3 sum is empty), eq. LPT_T at n = 2 (its factor n - 2s vanishes, so
+    T^(2) = 0), eq. LPT_kernels and eq. helmholtz:
+      L2 = -(3/7) mu_2L^(1,1),  mu_2L = (1/2)(psi_i,i psi_j,j - psi_i,j psi_j,i),
+      psi^(2) = Delta^-1 grad L2.
+    Derivatives are the exact i k (k = 2 pi m / n per lattice spacing) and
+    Delta^-1 is -1/k^2 (zero at k = 0).  The product mu is formed in real space
+    on a grid of 3n/2 points per axis (Orszag's 3/2 rule) from the
+    zero-padded spectra and cropped back to the modes |m_a| < n/2.
+    Reading: the source field has every Nyquist plane zeroed (with the
+    default corner-mode cut psi^(1) has none), and psi^(2) has none either.
+    """
+    psi1 = np.asarray(psi1, dtype=np.float64)
+    assert n % 2 == 0
+    P = np.stack([np.fft.fftn(psi1[c].reshape(n, n, n)) for c in range(3)])
+    m = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
+    band = np.abs(m) < n // 2
+    keep = band[:, None, None] & band[None, :, None] & band[None, None, :]
+    P = P * keep
+    k = 2.0 * np.pi * m / n
+    kk = [k[:, None, None], k[None, :, None], k[None, None, :]]
+    npad = 3 * n // 2
+    idx = m[band] % npad
+
+    def padded_real(spec):
+        big = np.zeros((npad, npad, npad), dtype=np.complex128)
+        big[np.ix_(idx, idx, idx)] = spec[np.ix_(band, band, band)]
+        return np.fft.ifftn(big).real * (npad / n) ** 3
+
+    g = [[padded_real(1j * kk[j] * P[i]) for j in range(3)] for i in range(3)]
+    mu = np.zeros((npad, npad, npad))
+    for i in range(3):
+        for j in range(3):
+            mu += 0.5 * (g[i][i] * g[j][j] - g[i][j] * g[j][i])
+    mu_big = np.fft.fftn(mu) * (n / npad) ** 3
+    mu_hat = np.zeros((n, n, n), dtype=np.complex128)
+    mu_hat[np.ix_(band, band, band)] = mu_big[np.ix_(idx, idx, idx)]
+    L2 = -3.0 / 7.0 * mu_hat
+    k2 = kk[0] ** 2 + kk[1] ** 2 + kk[2] ** 2
+    inv = np.where(k2 > 0, -1.0 / np.where(k2 > 0, k2, 1.0), 0.0)
+    return np.stack([np.fft.ifftn(1j * kk[c] * inv * L2).real.reshape(-1) for c in range(3)])
+
+
+def lpt_state(psi1, psi2, D):
+    """Displacement and D-time velocity of the LPT series truncated at second
+    order (eq. LPT, D^n approximation): Psi = D psi1 + D^2 psi2, V = dPsi/dD."""
+    if psi2 is None:
+        return D * psi1, psi1.copy()
+    return D * psi1 + D * D * psi2, psi1 + 2.0 * D * psi2

@@ -5,7 +5,8 @@ Follows eq. dkd (Sec. "Time stepping"):
   V^{n+1}   = alpha V^n + beta A(X^{n+1/2})
   X^{n+1}   = X^{n+1/2} + tau2 V^{n+1}
 with V = dX/dD, BullFrog alpha/beta, uniform steps in D, and the Zel'dovich
-initial state X = q + D(a_start) psi, V = psi.  Positions are carried as the
+initial state X = q + D(a_start) psi, V = psi (or its second-order LPT
+extension, Sec. "Lagrangian perturbation theory").  Positions are carried as the
 displacement Psi from the lattice point, in dq units.
 """
 from __future__ import annotations
@@ -31,6 +32,7 @@ class Problem:
     a_end: float = 1.0
     n_steps: int = 6
     force: str = "pm"               # "pm" or "nufft"
+    lpt_order: int = 1              # 1 Zel'dovich, 2 second-order LPT initial state
     es_width: int = 6
     es_beta: float = 13.8
     _cache: dict = field(default_factory=dict, repr=False)
@@ -67,8 +69,12 @@ class Problem:
 
 
 def initial_state(prob: Problem, w):
+    """(Psi, V, psi1) at a_start: the LPT series of eq. LPT truncated at
+    prob.lpt_order (1: Zel'dovich; 2: plus the second-order term)."""
     psi = ics.zeldovich_psi(w, prob.pm.box, prob.spectrum_fn(), prob.D_ref())
-    return prob.D_start() * psi, psi.copy(), psi
+    psi2 = ics.second_order_psi(psi, prob.pm.n_p) if prob.lpt_order == 2 else None
+    X, V = ics.lpt_state(psi, psi2, prob.D_start())
+    return X, V, psi
 
 
 def white_noise(prob: Problem, seed):
