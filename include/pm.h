@@ -83,6 +83,14 @@ enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
  *   es_width, es_beta   NUFFT exponential-of-semicircle kernel (width 6);
  *                  NUFFT needs n_g = 2 n_p and n_p >= 8
  *   batch          number of same-shape slots B >= 1
+ *   lpt_order      initial state from the LPT series of Sec. "Lagrangian
+ *                  perturbation theory" (eq. LPT, D^n approximation): 1 (or
+ *                  0) Zel'dovich, 2 adds D^2 psi^(2) (eq. LPT_L at n = 2,
+ *                  eq. helmholtz; de-aliased products).  2 needs
+ *                  n_g >= 2 n_p and n_p >= 8; pm_adjoint then returns
+ *                  PM_EUNSUPPORTED
+ *   stepper        0 BullFrog; 1 FastPM (Sec. "Time stepping")
+ *   time_var       step spacing: 0 uniform in D, 1 in a, 2 in ln a
  */
 typedef struct {
   int32_t n_p, n_g;
@@ -96,6 +104,9 @@ typedef struct {
   int32_t es_width;
   double es_beta;
   int32_t batch;
+  int32_t lpt_order;
+  int32_t stepper;
+  int32_t time_var;
 } pm_config;
 
 /* Lifecycle ------------------------------------------------------------- */

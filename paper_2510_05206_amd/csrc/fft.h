@@ -5,9 +5,14 @@
 namespace pm {
 
 enum { SRC_I64 = 0, SRC_F32 = 1 };
-enum { DST_F32 = 0, DST_IC = 1 };
+// row epilogues: DST_F32 real rows; DST_IC the Zel'dovich state; on the
+// second-order LPT grid (twice the lattice per axis) DST_MU_AB / DST_MU_ACC /
+// DST_MU_SQ accumulate the source mu from the derivative fields (dst = A, the
+// running diagonal sum, dst2 = mu), DST_IC2 adds the second-order term at the
+// lattice points (even nodes) to the state
+enum { DST_F32 = 0, DST_IC = 1, DST_MU_AB = 2, DST_MU_ACC = 3, DST_MU_SQ = 4, DST_IC2 = 5 };
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4, MODE_NUFFT_C = 5,
-       MODE_NUFFT_ADJ = 6 };
+       MODE_NUFFT_ADJ = 6, MODE_LPT_D = 7 };
 
 // z-row pass: real rows of n <-> half-spectrum rows of n/2+1
 struct RowLaunch {
@@ -56,6 +61,12 @@ struct ColArgs {
   // the kept modes |m| < n_p/2 and 0 elsewhere (truncation)
   const float* esdec;
   int n_p;
+  // MODE_LPT_D (x pass on the padded second-order grid, n = 2 n_p): the
+  // derivative field psi_{comp, comp2} = -(2 pi / n_p) m_comp m_comp2 amp fac w
+  // of the particle-grid noise spectrum src3 (row stride src_rs, slot stride
+  // src_slot_stride), zero-padded to the modes |m| < n_p / 2, into dst3
+  int comp2, src_rs;
+  long long src_slot_stride;
   unsigned long long active;  // bit b set: slot b takes part
   // pruning for spectra truncated to |m| < keep/2 per axis (keep = 0: none):
   // only columns iz < zlim (0 = all nh); keep_in: indices along the pass

@@ -222,7 +222,8 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
     __syncthreads();
   }
   if constexpr (MODE != MODE_FWD && MODE != MODE_NUFFT_ADJ) lds_fft<L, C, true, 256>(buf, a.tw, a.tws, true);
-  float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ) ? a.dst3 : a.data;
+  float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ || MODE == MODE_LPT_D) ? a.dst3
+                                                                                                       : a.data;
   for (int e = threadIdx.x; e < L * C; e += 256) {
     int t = e / C, c = e - t * C;
     if (z0 + c < a.nh) out[sbase + t * stride_t + c] = buf[e];
@@ -385,6 +386,41 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
   freg::pass_b<S, true>(v, lds, n1, c);
   if (!valid) return;
   constexpr int log2n = __builtin_ctz(n);
+  if constexpr (DST == DST_IC2) {
+    // second-order LPT grid (n = 2 n_p): the lattice points are its even
+    // nodes; add scale v to vel and scale2 v to disp (lattice-block order)
+    const long long x = row >> log2n, y = row & (n - 1);
+    if ((x | y) & 1) return;
+#pragma unroll
+    for (int r = 0; r < S::E; ++r) {
+      const long long gi = slot * dst_stride + blocked_index(x >> 1, y >> 1, S::t_out(n1, r), log2n - 1, log2pb);
+      dst[gi] += scale * v[r].x;
+      dst2[gi] += scale2 * v[r].x;
+    }
+    return;
+  }
+  if constexpr (DST == DST_MU_AB || DST == DST_MU_ACC || DST == DST_MU_SQ) {
+    // dst = A (running sum of the diagonal derivatives), dst2 = mu
+#pragma unroll
+    for (int r = 0; r < S::E; ++r) {
+      const long long gi = slot * dst_stride + row * n + 2 * S::t_out(n1, r);
+      const float2 z = make_float2(v[r].x * scale, v[r].y * scale);
+      float2* ap = reinterpret_cast<float2*>(dst + gi);
+      float2* mp = reinterpret_cast<float2*>(dst2 + gi);
+      if constexpr (DST == DST_MU_AB) {  // mu = A v, A = A + v
+        const float2 av = *ap;
+        *mp = make_float2(av.x * z.x, av.y * z.y);
+        *ap = make_float2(av.x + z.x, av.y + z.y);
+      } else if constexpr (DST == DST_MU_ACC) {  // mu += A v
+        const float2 av = *ap, mv = *mp;
+        *mp = make_float2(mv.x + av.x * z.x, mv.y + av.y * z.y);
+      } else {  // mu -= v^2
+        const float2 mv = *mp;
+        *mp = make_float2(mv.x - z.x * z.x, mv.y - z.y * z.y);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < S::E; ++r) {
     // DST_IC: particle arrays in lattice-block order (z pairs stay adjacent)
@@ -440,6 +476,17 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
           float h = amp * ms[q];
           x.x += h * sv.y;
           x.y -= h * sv.x;
+        }
+      } else if constexpr (MODE == MODE_LPT_D) {
+        // x pass: t = ix, outer = iy on the padded grid; kept modes only
+        const int mx = signed_mode(t, a.n), my = signed_mode(outer, a.n), np = a.n_p;
+        if (2 * (mx < 0 ? -mx : mx) < np && 2 * (my < 0 ? -my : my) < np && 2 * iz < np) {
+          const int ms[3] = {mx, my, iz};
+          const float2 sv = a.src3[slot * a.src_slot_stride +
+                                   (long long)((mx & (np - 1)) * np + (my & (np - 1))) * a.src_rs + iz];
+          const float h = -(6.283185307179586f / (float)np) * (float)(ms[a.comp] * ms[a.comp2]) *
+                          a.amp[mx * mx + my * my + iz * iz] * a.fac[slot];
+          x = make_float2(h * sv.x, h * sv.y);
         }
       } else {
         x = a.data[col + t * stride_t];
@@ -530,7 +577,8 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
     freg::pass_b<S, true>(v, lds, n1, c);
   }
   if (!valid) return;
-  float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ) ? a.dst3 : a.data;
+  float2* out = (MODE == MODE_IC_C || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ || MODE == MODE_LPT_D) ? a.dst3
+                                                                                                       : a.data;
 #pragma unroll
   for (int r = 0; r < S::E; ++r) {
     const int t = S::t_out(n1, r);
@@ -546,14 +594,21 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
   constexpr int R = 256 / P;
   dim3 grid((unsigned)((r.n_rows + R - 1) / R), r.batch);
   if (r.inverse) {
-    if (r.dst_mode == DST_F32)
-      k_c2r_rows_reg<L, P, DST_F32><<<grid, 256, 0, r.stream>>>(
-          (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows, r.tw,
-          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs, r.kz_lim, r.ic_log2pb);
-    else
-      k_c2r_rows_reg<L, P, DST_IC><<<grid, 256, 0, r.stream>>>(
-          (const float2*)r.src, r.src_stride, (float*)r.dst, r.dst_stride, (float*)r.dst2, r.n_rows, r.tw,
-          r.tws_half, r.tws_full, (float)r.scale, (float)r.scale2, r.active, r.rs, r.kz_lim, r.ic_log2pb);
+#define PM_C2R(D)                                                                                                \
+  k_c2r_rows_reg<L, P, D><<<grid, 256, 0, r.stream>>>((const float2*)r.src, r.src_stride, (float*)r.dst,          \
+                                                      r.dst_stride, (float*)r.dst2, r.n_rows, r.tw, r.tws_half,   \
+                                                      r.tws_full, (float)r.scale, (float)r.scale2, r.active,      \
+                                                      r.rs, r.kz_lim, r.ic_log2pb)
+    switch (r.dst_mode) {
+      case DST_F32: PM_C2R(DST_F32); break;
+      case DST_IC: PM_C2R(DST_IC); break;
+      case DST_MU_AB: PM_C2R(DST_MU_AB); break;
+      case DST_MU_ACC: PM_C2R(DST_MU_ACC); break;
+      case DST_MU_SQ: PM_C2R(DST_MU_SQ); break;
+      case DST_IC2: PM_C2R(DST_IC2); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef PM_C2R
   } else {
     // two row groups per block from L = 256 on (the next group's loads in flight)
     constexpr int G = L >= 256 ? 2 : 1;
@@ -614,6 +669,7 @@ static hipError_t launch_cols_r(const ColArgs& a, int mode, int batch, hipStream
     case MODE_COMBINE_IC: k_cols_reg<L, C, MODE_COMBINE_IC><<<grid, 256, 0, s>>>(a); break;
     case MODE_NUFFT_C: k_cols_reg<L, C, MODE_NUFFT_C><<<grid, 256, 0, s>>>(a); break;
     case MODE_NUFFT_ADJ: k_cols_reg<L, C, MODE_NUFFT_ADJ><<<grid, 256, 0, s>>>(a); break;
+    case MODE_LPT_D: k_cols_reg<L, C, MODE_LPT_D><<<grid, 256, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -628,7 +684,8 @@ static hipError_t launch_cols(const ColArgs& a, int mode, int batch, hipStream_t
     return launch_cols_r<L, C>(a, mode, batch, s);
   } else {
     // the NUFFT passes and pruning exist only in the register kernels
-    if (mode == MODE_NUFFT_C || mode == MODE_NUFFT_ADJ || a.keep || a.zlim) return hipErrorInvalidValue;
+    if (mode == MODE_NUFFT_C || mode == MODE_NUFFT_ADJ || mode == MODE_LPT_D || a.keep || a.zlim)
+      return hipErrorInvalidValue;
     return launch_cols_c<L, 16>(a, mode, batch, s);
   }
 }

@@ -29,6 +29,7 @@ struct pm_ctx {
   std::vector<double> cic4;
   std::vector<int32_t> es_tab;       // NUFFT: integer ES table (4096 samples per cell)
   std::vector<float> esdec;          // NUFFT: 1/phi_hat^2 on kept modes, 0 elsewhere
+  std::vector<float> lptkeep;        // 2LPT: 1 on the modes |m| < n_p/2 of the 2 n_p grid, 0 elsewhere
   // binding
   bool bound = false, with_adj = false;
   hipStream_t stream = nullptr;
@@ -39,6 +40,7 @@ struct pm_ctx {
   double* d_cic4 = nullptr;
   int32_t* d_es_tab = nullptr;
   float* d_esdec = nullptr;
+  float* d_lptkeep = nullptr;
   float* force3 = nullptr;           // NUFFT: 3 force meshes [B][3][M]
   float2* spec2 = nullptr;           // NUFFT: per-component spectrum
   float *disp = nullptr, *vel = nullptr, *w = nullptr, *xbar = nullptr, *vbar = nullptr;
@@ -143,7 +145,7 @@ struct Layout {
   size_t off_disp, off_vel, off_w, off_xbar, off_vbar;
   size_t off_mesh, off_spec, off_phi, off_icspec, off_pk, off_dot;
   size_t off_key, off_rank, off_sorted, off_count, off_offset, off_scanp, off_scratch, off_u, off_umax, off_scale;
-  size_t off_es_tab, off_esdec, off_force3, off_spec2;
+  size_t off_es_tab, off_esdec, off_force3, off_spec2, off_lptkeep;
   size_t total;
 };
 
@@ -195,6 +197,7 @@ Layout layout(const pm_ctx* c, bool adj) {
   if (nufft) W = std::max(W, (long long)T + kEsHaloLo + kEsHaloHi);
   L.off_es_tab = take(sizeof(int32_t) * c->es_tab.size());
   L.off_esdec = take(sizeof(float) * n);
+  L.off_lptkeep = take(sizeof(float) * n);
   L.off_force3 = nufft ? take(sizeof(float) * 3 * M * B) : 0;
   L.off_spec2 = nufft ? take(sizeof(float2) * spec_elems(n) * B) : 0;
   L.off_scratch = take(sizeof(long long) * W * W * W * n_tiles * B);
@@ -269,6 +272,14 @@ void build_tables(pm_ctx* c) {
     c->es_tab.assign(4, 0);
     c->esdec.assign(n, 0.f);
   }
+  // second-order LPT grid of 2 n_p points per axis (<= n): the modes of the
+  // particle grid strictly below its Nyquist mode
+  c->lptkeep.assign(n, 0.f);
+  if (2 * cf.n_p <= n)
+    for (int i = 0; i < 2 * cf.n_p; ++i) {
+      const int m = i < cf.n_p ? i : i - 2 * cf.n_p;
+      c->lptkeep[i] = 2 * std::abs(m) < cf.n_p ? 1.f : 0.f;
+    }
   // IC multiplier on the particle grid: h_c = i m_c amp[|m|^2], with
   // amp = kf sqrt(P(k) n^3/L^3) / (k^2 D_ref dq) / n^3 (the 1/n^3 of the
   // normalised inverse DFT), zero at m = 0 and for |m| > n/2
@@ -595,6 +606,121 @@ pm_status kick(pm_ctx* c, float* disp, const double* alpha, const double* beta, 
   return PM_OK;
 }
 
+// Second-order LPT term (Sec. "Lagrangian perturbation theory", eq. LPT_L at
+// n = 2, eq. helmholtz): the six derivative fields psi_{i,j} of the
+// first-order displacement are evaluated on a grid of P = 2 n_p points per
+// axis from their zero-padded spectra (twice the lattice resolves every
+// product of two fields of the modes |m| < n_p/2, as Orszag's 3/2 rule does),
+// mu = sum_{i<j} (psi_ii psi_jj - psi_ij^2) is formed there in the C2R
+// epilogues, transformed back to the kept modes, and
+// psi2_c = (3/7) i k_c mu / k^2 is evaluated at the lattice points (the even
+// nodes of the P grid): Psi += D0^2 psi2, V += 2 D0 psi2.  Buffers (free
+// while the initial state is built): the mesh holds A = running diagonal sum
+// and mu (P^3 floats each per slot), spec and the tile scratch hold P-grid
+// half spectra.
+pm_status lpt2(pm_ctx* c, unsigned long long act) {
+  const int np = c->cfg.n_p, P = 2 * np, B = c->cfg.batch;
+  const long long N = c->g.N, M = c->g.M;  // M = n_g^3 >= P^3
+  float* A = reinterpret_cast<float*>(c->mesh);
+  float2* fspec = c->spec;
+  float2* cspec = reinterpret_cast<float2*>(c->scratch);
+  ColArgs a{};
+  a.n = P;
+  a.nh = P / 2 + 1;
+  a.rs = spec_rs(P);
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / P;
+  a.amp = c->d_amp;
+  a.active = act;
+  a.n_p = np;
+  for (int b = 0; b < B; ++b)
+    a.fac[b] = (float)(c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0);
+  a.src3 = c->icspec + 3 * c->icspec_comp;  // noise spectrum on the particle grid
+  a.src_slot_stride = c->icspec_stride;
+  a.src_rs = spec_rs(np);
+  a.slot_stride = c->g.spec_stride;
+  a.data = fspec;
+  a.dst3 = fspec;
+  a.axis = 0;
+  a.zlim = np / 2;
+  a.keep = np;
+  a.keep_outer = 1;
+  RowLaunch rl{};
+  rl.n = P;
+  rl.rs = spec_rs(P);
+  rl.kz_lim = np / 2;
+  rl.n_rows = (long long)P * P;
+  rl.batch = B;
+  rl.inverse = true;
+  rl.src = fspec;
+  rl.src_stride = c->g.spec_stride;
+  rl.dst = A;
+  rl.dst2 = A + M;
+  rl.dst_stride = 2 * M;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (P / 2);
+  rl.tws_full = c->Lmax / P;
+  rl.scale = 1.0;
+  rl.stream = c->stream;
+  rl.active = act;
+  const int pairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  const int epi[6] = {DST_F32, DST_MU_AB, DST_MU_ACC, DST_MU_SQ, DST_MU_SQ, DST_MU_SQ};
+  for (int q = 0; q < 6; ++q) {
+    a.comp = pairs[q][0];
+    a.comp2 = pairs[q][1];
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_LPT_D, B, c->stream));
+    ColArgs y = a;
+    y.axis = 1;
+    y.keep_outer = 0;
+    y.keep_in = 1;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
+    rl.dst_mode = epi[q];
+    KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
+  }
+  pm_status st = r2c_mesh(c, A + M, SRC_F32, 2 * M, 1.0, 0.0, fspec, c->g.spec_stride, P, false, act, np);
+  if (st) return st;
+  ColArgs x{};
+  x.data = fspec;
+  x.dst3 = cspec;
+  x.slot_stride = c->g.spec_stride;
+  x.n = P;
+  x.nh = P / 2 + 1;
+  x.rs = spec_rs(P);
+  x.tw = c->d_tw;
+  x.tws = c->Lmax / P;
+  x.esdec = c->d_lptkeep;  // truncation to the kept modes (no deconvolution)
+  x.n_p = np;
+  x.active = act;
+  x.axis = 0;
+  x.zlim = np / 2;
+  x.keep = np;
+  x.keep_outer = 1;
+  // (3/7) i k_c / k^2 in lattice units; 1/P^3 takes the P-grid transform of mu
+  // to the particle grid's normalised inverse
+  for (int b = 0; b < B; ++b) x.coef[b] = (float)(3.0 / 7.0 / ((double)P * P * P));
+  RowLaunch r2 = rl;
+  r2.src = cspec;
+  r2.dst_mode = DST_IC2;
+  r2.dst_stride = 3 * N;
+  r2.scale = 2.0 * c->D0;
+  r2.scale2 = c->D0 * c->D0;
+  r2.ic_log2pb = c->g.log2_pb;
+  for (int comp = 0; comp < 3; ++comp) {
+    x.comp = comp;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(x, MODE_NUFFT_C, B, c->stream));
+    ColArgs y = x;
+    y.data = cspec;
+    y.axis = 1;
+    y.keep_outer = 0;
+    y.keep_in = 1;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
+    r2.dst = c->vel + comp * N;
+    r2.dst2 = c->disp + comp * N;
+    KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(r2));
+  }
+  return PM_OK;
+}
+
 pm_status check_bound(pm_ctx* c) {
   if (!c) return PM_EINVAL;
   if (!c->bound) return fail(c, PM_ESTATE, "context not bound to a workspace");
@@ -632,6 +758,11 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
     return PM_EINVAL;
   }
   if (c.spectrum != PM_SPEC_BBKS && c.spectrum != PM_SPEC_POWERLAW) return PM_EINVAL;
+  // second-order LPT runs its products on a 2 n_p grid held in the mesh buffers
+  // (pruned register FFT passes: n_p >= 8)
+  if (c.lpt_order < 0 || c.lpt_order > 2 || (c.lpt_order == 2 && (c.n_g < 2 * c.n_p || c.n_p < 8)))
+    return PM_EINVAL;
+  if (c.stepper != 0 || c.time_var != 0) return PM_EINVAL;
   pm_ctx* ctx = new (std::nothrow) pm_ctx();
   if (!ctx) return PM_ENOMEM;
   ctx->cfg = c;
@@ -697,6 +828,7 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   c->u_sorted = with_adjoint ? (float*)(ws + L.off_u) : nullptr;
   c->d_es_tab = (int32_t*)(ws + L.off_es_tab);
   c->d_esdec = (float*)(ws + L.off_esdec);
+  c->d_lptkeep = (float*)(ws + L.off_lptkeep);
   c->force3 = c->cfg.force == PM_FORCE_NUFFT ? (float*)(ws + L.off_force3) : nullptr;
   c->spec2 = c->cfg.force == PM_FORCE_NUFFT ? (float2*)(ws + L.off_spec2) : nullptr;
   c->umax = (float*)(ws + L.off_umax);
@@ -719,6 +851,7 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   HIPCHK(c, hipMemcpyAsync(c->d_cic4, c->cic4.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_es_tab, c->es_tab.data(), sizeof(int32_t) * c->es_tab.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_esdec, c->esdec.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_lptkeep, c->lptkeep.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
   // host tables must outlive the copies: wait for them here (bind is not on the hot path)
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->bound = true;
@@ -873,6 +1006,8 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
     rl.active = act;
     KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   }
+  if (c->cfg.lpt_order == 2)
+    if (pm_status st2 = lpt2(c, act)) return st2;
   if (w_out)
     for (int b = 0; b < B; ++b)
       if ((act >> b) & 1ull)
@@ -1125,6 +1260,8 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!c->ran) return fail(c, PM_ESTATE, "pm_adjoint before pm_run");
   if (!dL_ddelta || !dL_dw || !dL_dsigma8) return PM_EINVAL;
+  if (c->cfg.lpt_order == 2)
+    return fail(c, PM_EUNSUPPORTED, "the adjoint covers Zel'dovich initial conditions only");
   const int B = c->cfg.batch, np = c->cfg.n_p;
   const long long N = c->g.N, M = c->g.M;
   const double mfac = (double)M / (double)N;

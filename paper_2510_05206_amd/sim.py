@@ -34,6 +34,9 @@ class Config:
     es_width: int = 6
     es_beta: float = 13.8
     batch: int = 1
+    lpt_order: int = 1            # 1 Zel'dovich, 2 second-order LPT initial state
+    stepper: str = "bullfrog"     # "bullfrog" | "fastpm"
+    time_var: str = "D"           # step spacing uniform in "D" | "a" | "lna"
 
     def to_c(self):
         c = _lib.pm_config()
@@ -43,6 +46,10 @@ class Config:
                 v = _lib.PM_SPEC_BBKS if v == "bbks" else _lib.PM_SPEC_POWERLAW
             elif f.name == "force":
                 v = _lib.PM_FORCE_PM if v == "pm" else _lib.PM_FORCE_NUFFT
+            elif f.name == "stepper":
+                v = {"bullfrog": 0, "fastpm": 1}[v]
+            elif f.name == "time_var":
+                v = {"D": 0, "a": 1, "lna": 2}[v]
             elif isinstance(v, bool):
                 v = int(v)
             setattr(c, f.name, v)
