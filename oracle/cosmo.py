@@ -117,35 +117,61 @@ class StepCoeffs:
     s: float  # 1 / D_{n+1/2}^2: D-time normalisation of the acceleration
 
 
-def bullfrog_steps(omega_m, a_start, a_end, n_steps):
-    """BullFrog coefficients for uniform steps in D (Sec. "Time stepping").
+def step_table(omega_m, a_start, a_end, n_steps, stepper="bullfrog", time_var="D"):
+    """Drift-kick-drift coefficients of eq. dkd (Sec. "Time stepping").
 
-    xi    = (E_n + E'(D_n) (D_{n+1} - D_n) / 2) / D_{n+1/2} - D_{n+1/2}
-    alpha = (E'(D_{n+1}) - xi) / (E'(D_n) - xi)
-    beta  = (1 - alpha) D_{n+1/2}
+    Nodes uniform in the time variable t (D, a or ln a), the midpoint centred
+    in t: D_n = D(t_n), D_{n+1/2} = D(t_0 + (n + 1/2) dt); tau1 = D_{n+1/2} - D_n,
+    tau2 = D_{n+1} - D_{n+1/2}; beta = (1 - alpha) D_{n+1/2} (Zel'dovich
+    consistency) with
+      BullFrog: xi    = (E_n + E'(D_n) (D_{n+1} - D_n) / 2) / D_{n+1/2} - D_{n+1/2}
+                alpha = (E'(D_{n+1}) - xi) / (E'(D_n) - xi)
+      FastPM:   alpha = zeta(a_n) / zeta(a_{n+1}),  zeta(a) = H(a) a^3 dD/da.
     """
-    if omega_m == 1.0:  # EdS closed forms: D = a, E = -(3/7) D^2
+    if omega_m == 1.0:  # EdS closed forms: D = a, E = -(3/7) D^2, zeta = a^(3/2)
         Dfun = lambda a: a
+        afun = lambda D: D
         Efun = lambda D: -3.0 / 7.0 * D * D
         dEfun = lambda D: -6.0 / 7.0 * D
+        zeta = lambda a: a ** 1.5
     else:
         g = Growth(omega_m)
         Dfun = lambda a: float(g.D(a))
+        afun = g.a_of_D
         Efun = g.E_of_D
         dEfun = g.dEdD
-    D0, D1 = Dfun(a_start), Dfun(a_end)
-    dD = (D1 - D0) / n_steps
+        # H a^3 dD/da = H a^2 dD/dln a
+        zeta = lambda a: float(hubble(a, omega_m)) * a * a * float(g.dDdlna(a))
+    if time_var == "D":
+        t0, t1, D_of_t = Dfun(a_start), Dfun(a_end), (lambda t: t)
+    elif time_var == "a":
+        t0, t1, D_of_t = a_start, a_end, Dfun
+    elif time_var == "lna":
+        t0, t1, D_of_t = math.log(a_start), math.log(a_end), (lambda t: Dfun(math.exp(t)))
+    else:
+        raise ValueError(time_var)
+    dt = (t1 - t0) / n_steps
     out = []
     for n in range(n_steps):
-        Dn = D0 + n * dD
-        Dp = D0 + (n + 1) * dD
-        Dh = D0 + (n + 0.5) * dD
-        En, Epn, Epp = Efun(Dn), dEfun(Dn), dEfun(Dp)
-        xi = (En + Epn * (Dp - Dn) / 2.0) / Dh - Dh
-        alpha = (Epp - xi) / (Epn - xi)
+        Dn = D_of_t(t0 + n * dt)
+        Dp = D_of_t(t0 + (n + 1) * dt) if n + 1 < n_steps else D_of_t(t1)
+        Dh = D_of_t(t0 + (n + 0.5) * dt)
+        if stepper == "bullfrog":
+            En, Epn, Epp = Efun(Dn), dEfun(Dn), dEfun(Dp)
+            xi = (En + Epn * (Dp - Dn) / 2.0) / Dh - Dh
+            alpha = (Epp - xi) / (Epn - xi)
+        elif stepper == "fastpm":
+            alpha = zeta(afun(Dn)) / zeta(afun(Dp))
+        else:
+            raise ValueError(stepper)
         beta = (1.0 - alpha) * Dh
         out.append(StepCoeffs(Dn, Dh, Dp, alpha, beta, Dh - Dn, Dp - Dh, 1.0 / (Dh * Dh)))
     return out
+
+
+def bullfrog_steps(omega_m, a_start, a_end, n_steps):
+    """BullFrog coefficients for uniform steps in D (Sec. "Time stepping")."""
+    return step_table(omega_m, a_start, a_end, n_steps, "bullfrog", "D")
 
 
 def D_of_a(omega_m, a):

@@ -33,6 +33,8 @@ class Problem:
     n_steps: int = 6
     force: str = "pm"               # "pm" or "nufft"
     lpt_order: int = 1              # 1 Zel'dovich, 2 second-order LPT initial state
+    stepper: str = "bullfrog"       # "bullfrog" or "fastpm"
+    time_var: str = "D"             # steps uniform in "D", "a" or "lna"
     es_width: int = 6
     es_beta: float = 13.8
     _cache: dict = field(default_factory=dict, repr=False)
@@ -56,8 +58,8 @@ class Problem:
 
     def steps(self):
         if "steps" not in self._cache:
-            self._cache["steps"] = cosmo.bullfrog_steps(self.omega_m, self.a_start,
-                                                        self.a_end, self.n_steps)
+            self._cache["steps"] = cosmo.step_table(self.omega_m, self.a_start, self.a_end,
+                                                    self.n_steps, self.stepper, self.time_var)
         return self._cache["steps"]
 
     def force_fn(self):

@@ -7,7 +7,8 @@
 // disagrees with the E series of Sec. "Time stepping" outside EdS).  Solved
 // with fixed-step RK4 uniform in ln a, as the appendix describes, and cubic
 // Hermite interpolation between the steps.
-// BullFrog: Sec. "Time stepping" (alpha, beta, xi; uniform steps in D).
+// Steppers: Sec. "Time stepping" (BullFrog alpha, beta, xi; FastPM alpha from
+// zeta = H a^3 dD/da; steps uniform in D, a or ln a).
 // Spectra: BBKS fitting formula with Gamma = Omega_m h normalised to sigma8
 // (top-hat of 8 Mpc/h, composite Simpson in ln k), or a Gaussian-truncated
 // k^-2 power law normalised by an rms displacement.
@@ -111,17 +112,51 @@ void Growth::at_D(double Dv, double* Ev, double* dEdD) const {
   *dEdD = y[3] / y[1];
 }
 
-std::vector<StepCoef> bullfrog_table(const Growth& g, double a_start, double a_end, int n_steps) {
+// FastPM's zeta(a) = H(a) a^3 dD/da = H a^2 dD/dln a (EdS: a^(3/2))
+double Growth::zeta(double a) const {
+  if (eds) return a * std::sqrt(a);
+  double y[4];
+  growth_at(*this, std::log(a), y);
+  return std::sqrt(omega_m / (a * a * a) + 1.0 - omega_m) * a * a * y[1];
+}
+
+// eq. dkd coefficients (Sec. "Time stepping"): nodes uniform in the time
+// variable t (D, a or ln a) with the midpoint centred in t; Zel'dovich
+// consistency beta = (1 - alpha) D_{n+1/2}; BullFrog
+//   xi = (E_n + E'(D_n) (D_{n+1} - D_n) / 2) / D_{n+1/2} - D_{n+1/2},
+//   alpha = (E'(D_{n+1}) - xi) / (E'(D_n) - xi),
+// or FastPM alpha = zeta(a_n) / zeta(a_{n+1}).
+std::vector<StepCoef> step_table(const Growth& g, double a_start, double a_end, int n_steps, int stepper,
+                                 int time_var) {
   std::vector<StepCoef> out;
-  double D0 = g.D_of_a(a_start), D1 = g.D_of_a(a_end);
-  double dD = (D1 - D0) / n_steps;
+  auto D_of_t = [&](double t) {
+    return time_var == 1 ? g.D_of_a(t) : (time_var == 2 ? g.D_of_a(std::exp(t)) : t);
+  };
+  double t0, t1;
+  if (time_var == 1) {
+    t0 = a_start;
+    t1 = a_end;
+  } else if (time_var == 2) {
+    t0 = std::log(a_start);
+    t1 = std::log(a_end);
+  } else {
+    t0 = g.D_of_a(a_start);
+    t1 = g.D_of_a(a_end);
+  }
+  const double dt = (t1 - t0) / n_steps;
   for (int n = 0; n < n_steps; ++n) {
-    double Dn = D0 + n * dD, Dp = D0 + (n + 1) * dD, Dh = D0 + (n + 0.5) * dD;
-    double En, Epn, Ep1, tmp;
-    g.at_D(Dn, &En, &Epn);
-    g.at_D(Dp, &tmp, &Ep1);
-    double xi = (En + Epn * (Dp - Dn) / 2.0) / Dh - Dh;
-    double alpha = (Ep1 - xi) / (Epn - xi);
+    double Dn = D_of_t(t0 + n * dt), Dh = D_of_t(t0 + (n + 0.5) * dt);
+    double Dp = D_of_t(n + 1 < n_steps ? t0 + (n + 1) * dt : t1);
+    double alpha;
+    if (stepper == 1) {
+      alpha = g.zeta(g.a_of_D(Dn)) / g.zeta(g.a_of_D(Dp));
+    } else {
+      double En, Epn, Ep1, tmp;
+      g.at_D(Dn, &En, &Epn);
+      g.at_D(Dp, &tmp, &Ep1);
+      double xi = (En + Epn * (Dp - Dn) / 2.0) / Dh - Dh;
+      alpha = (Ep1 - xi) / (Epn - xi);
+    }
     double beta = (1.0 - alpha) * Dh;
     out.push_back({Dn, Dh, Dp, alpha, beta, Dh - Dn, Dp - Dh, 1.0 / (Dh * Dh)});
   }

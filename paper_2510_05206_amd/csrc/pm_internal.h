@@ -24,7 +24,7 @@ constexpr int kEsAnchor = 2;
 constexpr int kEsHaloLo = 0, kEsHaloHi = 5;
 
 // ---------------------------------------------------------------- host FP64
-struct StepCoef {          // one BullFrog step (Sec. "Time stepping")
+struct StepCoef {          // one drift-kick-drift step (Sec. "Time stepping")
   double D_n, D_half, D_np1, alpha, beta, tau1, tau2, s;
 };
 
@@ -36,9 +36,12 @@ struct Growth {            // D(a), E(a) of the growth ODEs (D ~ a normalisation
   double D_of_a(double a) const;
   double a_of_D(double D) const;
   void at_D(double Dv, double* E, double* dEdD) const;
+  double zeta(double a) const;  // H a^3 dD/da (FastPM)
 };
 
-std::vector<StepCoef> bullfrog_table(const Growth& g, double a_start, double a_end, int n_steps);
+// stepper 0 BullFrog, 1 FastPM; time_var 0 uniform in D, 1 in a, 2 in ln a
+std::vector<StepCoef> step_table(const Growth& g, double a_start, double a_end, int n_steps, int stepper,
+                                 int time_var);
 double bbks_amplitude(double omega_m, double h, double n_s, double sigma8);
 double spectrum_eval(const pm_config& c, double amp, double k);
 double powerlaw_amplitude(const pm_config& c, double D_start, double D_ref);

@@ -762,12 +762,12 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
   // (pruned register FFT passes: n_p >= 8)
   if (c.lpt_order < 0 || c.lpt_order > 2 || (c.lpt_order == 2 && (c.n_g < 2 * c.n_p || c.n_p < 8)))
     return PM_EINVAL;
-  if (c.stepper != 0 || c.time_var != 0) return PM_EINVAL;
+  if (c.stepper < 0 || c.stepper > 1 || c.time_var < 0 || c.time_var > 2) return PM_EINVAL;
   pm_ctx* ctx = new (std::nothrow) pm_ctx();
   if (!ctx) return PM_ENOMEM;
   ctx->cfg = c;
   ctx->growth.solve(c.omega_m);
-  ctx->table = bullfrog_table(ctx->growth, c.a_start, c.a_end, c.n_steps);
+  ctx->table = step_table(ctx->growth, c.a_start, c.a_end, c.n_steps, c.stepper, c.time_var);
   ctx->D0 = ctx->growth.D_of_a(c.a_start);
   ctx->D_ref = ctx->growth.D_of_a(1.0);
   if (c.spectrum == PM_SPEC_BBKS)
@@ -939,7 +939,8 @@ pm_status pm_set_slot_params(pm_ctx* c, const int32_t* n_steps, const double* si
   for (int b = 0; b < c->cfg.batch; ++b) {
     if (n_steps && n_steps[b] != c->slot_steps[b]) {
       c->slot_steps[b] = n_steps[b];
-      c->slot_table[b] = bullfrog_table(c->growth, c->cfg.a_start, c->cfg.a_end, n_steps[b]);
+      c->slot_table[b] = step_table(c->growth, c->cfg.a_start, c->cfg.a_end, n_steps[b], c->cfg.stepper,
+                                    c->cfg.time_var);
       ++c->gen;
     }
     if (sigma8) c->slot_sigma8[b] = sigma8[b];

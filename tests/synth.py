@@ -43,7 +43,8 @@ def oracle_problem(d, **kw):
                    sigma8=d.get("sigma8", 0.81), spectrum=d.get("spectrum", "bbks"),
                    rms_cells=d.get("pl_rms_cells", 0.2), a_start=d.get("a_start", 0.02),
                    a_end=d.get("a_end", 1.0), n_steps=d.get("n_steps", 6),
-                   lpt_order=d.get("lpt_order", 1), **extra)
+                   lpt_order=d.get("lpt_order", 1), stepper=d.get("stepper", "bullfrog"),
+                   time_var=d.get("time_var", "D"), **extra)
 
 
 def displacements(n_p, seed, scale=1.5, kind="gauss"):

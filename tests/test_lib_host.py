@@ -74,6 +74,21 @@ def test_host_schedule_matches_oracle(lib, wl):
     lib.pm_destroy(ctx)
 
 
+@pytest.mark.parametrize("stepper,tv", [("fastpm", "D"), ("bullfrog", "a"), ("fastpm", "lna"), ("bullfrog", "lna")])
+def test_host_schedule_variants_match_oracle(lib, stepper, tv):
+    d = dict(synth.C2, stepper=stepper, time_var=tv)
+    st, ctx = _create(lib, **d)
+    assert st == 0
+    n = d["n_steps"]
+    out = np.zeros((n, 8))
+    assert lib.pm_schedule(ctx, 0, out.ctypes.data_as(C.c_void_p)) == 0
+    ref = cosmo.step_table(d["omega_m"], d["a_start"], d["a_end"], n, stepper, tv)
+    for row, s in zip(out, ref):
+        exp = [s.D_n, s.D_half, s.D_np1, s.alpha, s.beta, s.tau1, s.tau2, s.s]
+        assert np.allclose(row, exp, rtol=1e-9, atol=1e-13), (row, exp)
+    lib.pm_destroy(ctx)
+
+
 def test_serving_admission_respects_the_hbm_budget():
     from paper_2510_05206_amd import serve
     plan = serve.plan_batches(20e9, 16)

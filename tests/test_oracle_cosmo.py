@@ -94,3 +94,55 @@ def test_bbks_limits_and_sigma8_normalisation():
     v = sum(integrate.quad(f, lo, lo + 0.5, limit=200)[0]
             for lo in np.arange(math.log(1e-6), math.log(1e3), 0.5))
     assert abs(math.sqrt(v / (2 * math.pi ** 2)) / 0.81 - 1) < 1e-6
+
+
+def _zeta_closed(a, om):
+    """H a^3 dD/da from the closed-form growth integral
+    D = (5/2) Om H(a) I(a), I = int_0^a dx / (x H)^3 (independent of the ODE)."""
+    H = float(cosmo.hubble(a, om))
+    I = cosmo.growth_closed_form(a, om) / (2.5 * om * H)
+    dH = -1.5 * om * a ** -4 / H
+    dD = 2.5 * om * (dH * I + H / (a * H) ** 3)
+    return H * a ** 3 * dD
+
+
+def test_fastpm_alpha_closed_forms():
+    # EdS: zeta = a^(3/2) (H = a^-3/2, D = a)
+    for st in cosmo.step_table(1.0, 0.02, 1.0, 7, "fastpm", "D"):
+        assert abs(st.alpha - (st.D_n / st.D_np1) ** 1.5) < 1e-14
+        assert abs(st.alpha + st.beta / st.D_half - 1) < 1e-13
+    # LCDM, steps uniform in a (the nodes are known scale factors)
+    a0, a1, n, om = 0.02, 1.0, 5, 0.31
+    steps = cosmo.step_table(om, a0, a1, n, "fastpm", "a")
+    for i, st in enumerate(steps):
+        an, ap = a0 + i * (a1 - a0) / n, a0 + (i + 1) * (a1 - a0) / n
+        assert abs(st.alpha / (_zeta_closed(an, om) / _zeta_closed(ap, om)) - 1) < 1e-8
+
+
+@pytest.mark.parametrize("tv", ["a", "lna"])
+def test_time_variable_nodes_and_midpoints(tv):
+    om, a0, a1, n = 0.31, 0.02, 1.0, 6
+    steps = cosmo.step_table(om, a0, a1, n, "bullfrog", tv)
+    if tv == "a":
+        t = lambda x: a0 + x * (a1 - a0) / n
+    else:
+        t = lambda x: a0 * (a1 / a0) ** (x / n)
+    for i, st in enumerate(steps):
+        for D, x in ((st.D_n, i), (st.D_half, i + 0.5), (st.D_np1, i + 1)):
+            assert abs(D / cosmo.growth_closed_form(t(x), om) - 1) < 1e-9
+        assert abs(st.tau1 - (st.D_half - st.D_n)) < 1e-15 and abs(st.tau2 - (st.D_np1 - st.D_half)) < 1e-15
+    # in EdS steps uniform in a are steps uniform in D: BullFrog stays 2LPT exact
+    X, V = _bullfrog_toy_run(cosmo.step_table(1.0, 0.05, 0.8, 5, "bullfrog", "a"), 0.05)
+    assert np.allclose(X, [0.8, -3 / 7 * 0.8 ** 2], rtol=1e-12)
+
+
+def test_fastpm_is_first_order_consistent_only():
+    # the toy 2LPT trajectory: FastPM keeps the Zel'dovich component exactly
+    # but misses the second-order one, by less as the steps shrink (BullFrog
+    # hits it exactly for any step)
+    errs = []
+    for n in (4, 8, 16):
+        X, V = _bullfrog_toy_run(cosmo.step_table(1.0, 0.02, 1.0, n, "fastpm", "D"), 0.02)
+        assert abs(X[0] - 1.0) < 1e-13 and abs(V[0] - 1.0) < 1e-13
+        errs.append(abs(X[1] + 3 / 7))
+    assert errs[0] > 1e-2 and errs[0] / errs[1] > 2.0 and errs[1] / errs[2] > 2.0

@@ -10,10 +10,11 @@ from oracle import adjoint, cosmo, ics, mesh, nbody, nufft, pk
 from oracle.force import PMConfig
 
 
-def _plane_wave_run(n_g, A_w=0.5, order=3):
+def _plane_wave_run(n_g, A_w=0.5, order=3, stepper="bullfrog"):
     n_p, box = 32, 100.0
     cfg = PMConfig(n_p, n_g, box, order=order, deconvolve=False, grad_order=4, lap_order=0)
-    prob = nbody.Problem(cfg, omega_m=1.0, spectrum="powerlaw", a_start=0.02, a_end=1.0, n_steps=6)
+    prob = nbody.Problem(cfg, omega_m=1.0, spectrum="powerlaw", a_start=0.02, a_end=1.0, n_steps=6,
+                         stepper=stepper)
     kw = 2 * math.pi / box
     q = mesh.lattice(n_p)[0] * (box / n_p)
     dq = box / n_p
@@ -23,14 +24,15 @@ def _plane_wave_run(n_g, A_w=0.5, order=3):
     return out, 1.0 * psi, A_w / kw / dq
 
 
-def test_plane_wave_follows_zeldovich_before_shell_crossing():
-    # EdS, D = a; BullFrog is Zel'dovich consistent, so only PM force error
-    # remains, and it must shrink with the mesh.  TSC keeps the lattice's
-    # aliasing error below 1%; CIC errs by a few per cent (discreteness) and
-    # is checked only for convergence
+@pytest.mark.parametrize("stepper", ["bullfrog", "fastpm"])
+def test_plane_wave_follows_zeldovich_before_shell_crossing(stepper):
+    # EdS, D = a; BullFrog and FastPM are Zel'dovich consistent, so only PM
+    # force error remains, and it must shrink with the mesh.  TSC keeps the
+    # lattice's aliasing error below 1%; CIC errs by a few per cent
+    # (discreteness) and is checked only for convergence
     errs = []
     for n_g in (64, 128):
-        out, exact, amp = _plane_wave_run(n_g)
+        out, exact, amp = _plane_wave_run(n_g, stepper=stepper)
         errs.append(np.abs(out - exact).max() / amp)
     assert errs[0] < 0.015 and errs[1] < errs[0]
     e64 = _plane_wave_run(64, order=2)
