@@ -264,6 +264,26 @@ pm_status pm_force_vjp(pm_ctx* ctx, const float* disp, double s, const float* u,
  * inverse != 0: half spectrum -> real, unnormalised (exp(+i k x)). */
 pm_status pm_fft(pm_ctx* ctx, const void* in, void* out, int32_t inverse);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * binned power spectrum of pm_power_spectrum, computed from a given int64
+ * fixed-point CIC mass mesh (device [n^3], 2^32 per particle, as pm_density's
+ * fixed_out writes it) of n_particles particles in a box of side box, with
+ * no context and no allocation.  Every intermediate (FFT twiddles, window
+ * table, the half spectrum, partial bin sums) lives in one static device
+ * array of about 11 MB per GPU, held until the process ends, which bounds the
+ * mesh to n <= 128 cells per axis.  Outputs: device k_mean, pk, n_modes
+ * [n_bins] as in pm_power_spectrum; asynchronous on hip_stream (NULL = the
+ * default stream).  Errors: PM_EINVAL for null pointers, n not a power of
+ * two >= 4, n_bins outside [1, n], n_particles < 1 or box <= 0; PM_ENOMEM for
+ * n > 128 (beyond the static array); PM_EHIP for a launch failure.  Nothing
+ * is launched on an error.  All calls on one GPU share its array: calls that
+ * overlap on one GPU (other streams or threads) race and must be ordered by
+ * the caller. */
+pm_status pm_power_spectrum_mesh_noalloc(const int64_t* mesh, int32_t n, int64_t n_particles, double box,
+                                         int32_t n_bins, int32_t deconvolve_cic, double* k_mean, double* pk,
+                                         int64_t* n_modes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,8 @@ EXPORTS = {
     "pm_kernel_times": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_set_slot_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_init_ics": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pm_power_spectrum_mesh_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_int32,
+                                                 C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_step": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pm_run": (C.c_int, [C.c_void_p]),
     "pm_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

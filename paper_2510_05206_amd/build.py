@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpm.so")
-SOURCES = ["host_tables.cpp", "fft.hip", "binned.hip", "misc.hip", "pm_lib.hip"]
+SOURCES = ["host_tables.cpp", "fft.hip", "binned.hip", "misc.hip", "pm_lib.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -272,3 +272,20 @@ def simulate(w, sigma8, sim):
     """Differentiable forward model: final CIC density contrast of the white
     noise w and sigma8 (PMFunction.apply)."""
     return PMFunction.apply(w, sigma8, sim)
+
+
+def power_spectrum_of_mesh_noalloc(mesh, n_particles, box, n_bins, deconvolve=True):
+    """P(k) of an int64 fixed-point CIC mass mesh (n^3 on the GPU, n <= 128)
+    through pm_power_spectrum_mesh_noalloc, which allocates nothing: the
+    outputs are allocated here by torch; returns (k_mean, pk, n_modes)."""
+    assert mesh.is_cuda and mesh.dtype == torch.int64 and mesh.is_contiguous()
+    n = round(mesh.numel() ** (1.0 / 3.0))
+    assert n ** 3 == mesh.numel()
+    k = torch.empty(n_bins, dtype=torch.float64, device=mesh.device)
+    p = torch.empty_like(k)
+    c = torch.empty(n_bins, dtype=torch.int64, device=mesh.device)
+    st = _lib.load().pm_power_spectrum_mesh_noalloc(
+        _ptr(mesh), n, int(n_particles), float(box), int(n_bins), int(bool(deconvolve)), _ptr(k), _ptr(p), _ptr(c),
+        C.c_void_p(torch.cuda.current_stream(mesh.device).cuda_stream))
+    _lib.check(st, None, "pm_power_spectrum_mesh_noalloc")
+    return k, p, c
