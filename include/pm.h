@@ -214,6 +214,23 @@ pm_status pm_use_graphs(pm_ctx* ctx, int32_t enable);
  * initial conditions. */
 pm_status pm_adjoint(pm_ctx* ctx, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8);
 
+/* Device-indexed steps for continuous batching (serving): each slot's next
+ * step index lives in device memory, so slots at different steps, admitted
+ * at different times, advance together through one captured graph with no
+ * per-step capture or argument upload.  pm_set_step_index sets the device
+ * index of every slot from step_index[B] (host): k >= 0 runs step k of that
+ * slot's schedule next, -1 makes it idle, -2 keeps its current value.
+ * pm_step_device advances every slot whose index is >= 0 by one step of eq.
+ * dkd (the same launches and scalars as pm_step) and then increments its
+ * index, which returns to -1 after the slot's last step; idle slots cost a
+ * launch but no work.  pm_get_step_index copies the indices to the host
+ * (synchronising the stream).  The slot mask of pm_set_active does not apply
+ * to these calls.  PM force contexts with n_steps <= 96 only
+ * (PM_EUNSUPPORTED otherwise). */
+pm_status pm_set_step_index(pm_ctx* ctx, const int32_t* step_index);
+pm_status pm_step_device(pm_ctx* ctx);
+pm_status pm_get_step_index(pm_ctx* ctx, int32_t* step_index);
+
 /* Binned power spectrum of the CIC density of the current positions:
  * P(k_b) = (L^3/n_g^6) sum_{m in b} w_m |delta_m|^2 / W^2 / sum w_m, bin b
  * (1-based) holding (2b-1)^2 <= 4|m|^2 < (2b+1)^2, W the CIC window when

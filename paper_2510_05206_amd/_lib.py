@@ -56,6 +56,9 @@ EXPORTS = {
     "pm_power_spectrum_mesh_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_int32,
                                                  C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_step": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pm_set_step_index": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pm_step_device": (C.c_int, [C.c_void_p]),
+    "pm_get_step_index": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pm_run": (C.c_int, [C.c_void_p]),
     "pm_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_power_spectrum": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),

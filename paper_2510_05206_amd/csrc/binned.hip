@@ -55,7 +55,7 @@ __device__ __forceinline__ void tile_origin(int t, const TileGeo& tg, int o[3]) 
 template <int P>
 __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
   const int slot = blockIdx.y;
-  if (!((a.active >> slot) & 1ull)) return;
+  if (!slot_on(a.g.gate, a.active, slot)) return;
   const long long N = a.g.N;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   const bool valid = i < N;
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
   if (valid) {
     float p[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
     if (a.vel) {  // merged first drift X += tau V, written back
-      const float t = a.tau[slot];
+      const float t = slot_f(a.g.gate, a.g.sched, a.g.sched_steps, a.tau, slot, kSchTau1);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         p[c] += t * a.vel[ps + c * N + i];
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan_add(const int32_t* partial, i
 
 __global__ void __launch_bounds__(256) k_bin_scatter(BinArgs a) {
   const int slot = blockIdx.y;
-  if (!((a.active >> slot) & 1ull)) return;
+  if (!slot_on(a.g.gate, a.active, slot)) return;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= a.g.N) return;
   const long long N = a.g.N;
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kPmDepositThreads) k_tile_deposit(TileArgs a) 
   constexpr int NT = kPmDepositThreads;
   __shared__ unsigned long long win[(kTileMax + 2) * (kTileMax + 2) * (kTileMax + 2)];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
-  if (!((a.active >> slot) & 1ull)) return;
+  if (!slot_on(a.g.gate, a.active, slot)) return;
   const int T = a.T, W = T + 2, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
@@ -294,7 +294,7 @@ __device__ __forceinline__ V assemble_run(const AssembleArgs& a, const V* __rest
 template <bool OUT_F32, int CPT>
 __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
   const int slot = blockIdx.y;
-  if (!((a.active >> slot) & 1ull)) return;
+  if (!slot_on(a.g.gate, a.active, slot)) return;
   const int L = a.g.log2_ng, nm = a.g.n_g - 1;
   const long long e0 = (long long)xcd_block(blockIdx.x, gridDim.x) * (256 * CPT);
   const int W = a.T + a.Rlo + a.Rhi;
@@ -392,7 +392,7 @@ __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
   constexpr int R = 1 + ORD / 2;
   __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
-  if (!((a.active >> slot) & 1ull)) return;
+  if (!slot_on(a.g.gate, a.active, slot)) return;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, R, a.g.log2_ng, a.g.n_g - 1);
@@ -400,7 +400,9 @@ __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
   const WinAcc acc{win, a.T + 2 * R};
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
-  const float al = a.alpha[slot], be = a.beta[slot], tp = a.tau[slot];
+  const float al = slot_f(a.g.gate, a.g.sched, a.g.sched_steps, a.alpha, slot, kSchAlpha);
+  const float be = slot_f(a.g.gate, a.g.sched, a.g.sched_steps, a.beta, slot, kSchBeta);
+  const float tp = slot_f(a.g.gate, a.g.sched, a.g.sched_steps, a.tau, slot, kSchTau2);
   for (int p = beg + threadIdx.x; p < end; p += 256) {
     const long long i = a.sorted[slot * N + p];
     float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};

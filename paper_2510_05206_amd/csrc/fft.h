@@ -35,6 +35,7 @@ struct RowLaunch {
   // (the rest is zero); 0 = the whole half row
   int kz_lim;
   int ic_log2pb;         // DST_IC: particle arrays in lattice blocks of 2^ic_log2pb (mak.h)
+  const int32_t* gate;   // device-indexed steps: slot b takes part while gate[b] >= 0 (null: all)
   hipStream_t stream;
 };
 
@@ -73,6 +74,10 @@ struct ColArgs {
   // outside the kept set are zero and not read; keep_out: they are not
   // written; keep_outer: whole lines whose outer index is not kept are skipped
   int zlim, keep, keep_in, keep_out, keep_outer;
+  // device-indexed steps (Geom): gate, and MODE_FUSED_H's coef from sched
+  const int32_t* gate;
+  const float* sched;
+  int sched_steps;
 };
 
 hipError_t fft_rows(const RowLaunch& r);

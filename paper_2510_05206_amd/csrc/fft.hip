@@ -122,11 +122,17 @@ __device__ __forceinline__ void lds_fft(float2* __restrict__ buf, const float2* 
 
 __device__ __forceinline__ int signed_mode(int i, int n) { return i < n / 2 ? i : i - n; }
 
+// the PM multiplier's per-slot coefficient (from the device schedule in
+// device-indexed steps)
+__device__ __forceinline__ float fused_coef(const ColArgs& a, int slot) {
+  return slot_f(a.gate, a.sched, a.sched_steps, a.coef, slot, kSchCoef);
+}
+
 template <int L, int C, int MODE>
 __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
   __shared__ float2 buf[L * C];
   const int slot = blockIdx.z;
-  if (!((a.active >> slot) & 1ull)) return;
+  if (!slot_on(a.gate, a.active, slot)) return;
   const int outer = blockIdx.y;          // x for the y pass, y for the x pass
   const int z0 = blockIdx.x * C;
   const long long stride_t = a.axis == 1 ? (long long)a.rs : (long long)a.n * a.rs;
@@ -215,7 +221,7 @@ __global__ void __launch_bounds__(256) k_cols(ColArgs a) {
       if (iz >= a.nh) continue;  // padding columns of the last tile
       float l = a.lap[t] + a.lap[outer] + a.lap[iz];
       float w = a.win2[t] * a.win2[outer] * a.win2[iz];
-      float h = (t == 0 && outer == 0 && iz == 0) ? 0.f : a.coef[slot] / (l * w);
+      float h = (t == 0 && outer == 0 && iz == 0) ? 0.f : fused_coef(a, slot) / (l * w);
       buf[e].x *= h;
       buf[e].y *= h;
     }
@@ -267,12 +273,13 @@ __global__ void __launch_bounds__(256, 2) k_r2c_rows_reg(const void* __restrict_
                                                       float2* __restrict__ dst, long long dst_stride,
                                                       int n_rows, const float2* __restrict__ tw, int tws_half,
                                                       int tws_full, double scale, double shift,
-                                                      unsigned long long active, int rs, int kz_lim) {
+                                                      unsigned long long active, int rs, int kz_lim,
+                                                      const int32_t* __restrict__ gate) {
   using S = freg::RowShape<L, P>;
   constexpr int n = 2 * L;
   __shared__ float2 lds[S::LDS];
   const int slot = blockIdx.y;
-  if (!((active >> slot) & 1ull)) return;
+  if (!slot_on(gate, active, slot)) return;
   const int n1 = S::lane_n1(threadIdx.x), c = S::lane_c(threadIdx.x);
   const long long row0 = (long long)blockIdx.x * (G * S::R) + c;
   const int klim = kz_lim > 0 ? kz_lim : L + 1;
@@ -332,12 +339,13 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
                                                       float* __restrict__ dst2, int n_rows,
                                                       const float2* __restrict__ tw, int tws_half, int tws_full,
                                                       float scale, float scale2, unsigned long long active,
-                                                      int rs, int kz_lim, int log2pb) {
+                                                      int rs, int kz_lim, int log2pb,
+                                                      const int32_t* __restrict__ gate) {
   using S = freg::RowShape<L, P>;
   constexpr int n = 2 * L;
   __shared__ float2 lds[S::LDS];
   const int slot = blockIdx.y;
-  if (!((active >> slot) & 1ull)) return;
+  if (!slot_on(gate, active, slot)) return;
   const int n1 = S::lane_n1(threadIdx.x), c = S::lane_c(threadIdx.x);
   const long long row = (long long)blockIdx.x * S::R + c;
   const bool valid = row < n_rows;
@@ -444,7 +452,7 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
   using S = freg::Shape<L, C>;
   __shared__ float2 lds[S::LDS];
   const int slot = blockIdx.z;
-  if (!((a.active >> slot) & 1ull)) return;
+  if (!slot_on(a.gate, a.active, slot)) return;
   // adjacent column groups (halves of one 128-byte line) share an XCD's L2
   const unsigned lid = xcd_pair(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
   const int outer = (int)(lid / gridDim.x);  // x for the y pass, y for the x pass
@@ -515,7 +523,7 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
         const int t = S::t_out(n1, r);
         float l = a.lap[t] + a.lap[outer] + (valid ? a.lap[iz] : 0.f);
         float w = a.win2[t] * a.win2[outer] * (valid ? a.win2[iz] : 1.f);
-        float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : a.coef[slot] / (l * w);
+        float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : fused_coef(a, slot) / (l * w);
         v[r].x *= h;
         v[r].y *= h;
       }
@@ -598,7 +606,7 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
   k_c2r_rows_reg<L, P, D><<<grid, 256, 0, r.stream>>>((const float2*)r.src, r.src_stride, (float*)r.dst,          \
                                                       r.dst_stride, (float*)r.dst2, r.n_rows, r.tw, r.tws_half,   \
                                                       r.tws_full, (float)r.scale, (float)r.scale2, r.active,      \
-                                                      r.rs, r.kz_lim, r.ic_log2pb)
+                                                      r.rs, r.kz_lim, r.ic_log2pb, r.gate)
     switch (r.dst_mode) {
       case DST_F32: PM_C2R(DST_F32); break;
       case DST_IC: PM_C2R(DST_IC); break;
@@ -616,11 +624,11 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
     if (r.src_mode == SRC_I64)
       k_r2c_rows_reg<L, P, SRC_I64, G><<<g2, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
                                                                  r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                 r.shift, r.active, r.rs, r.kz_lim);
+                                                                 r.shift, r.active, r.rs, r.kz_lim, r.gate);
     else
       k_r2c_rows_reg<L, P, SRC_F32, G><<<g2, 256, 0, r.stream>>>(r.src, r.src_stride, (float2*)r.dst, r.dst_stride,
                                                                  r.n_rows, r.tw, r.tws_half, r.tws_full, r.scale,
-                                                                 r.shift, r.active, r.rs, r.kz_lim);
+                                                                 r.shift, r.active, r.rs, r.kz_lim, r.gate);
   }
   return hipGetLastError();
 }

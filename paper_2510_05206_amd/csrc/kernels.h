@@ -84,6 +84,19 @@ hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, dou
 
 // auxiliary kernels (misc.hip)
 hipError_t launch_fill(void* p, long long bytes, hipStream_t s);
+// device-indexed step state (by-value uploads, no host buffers in flight)
+constexpr int kMaxSchedSteps = 96;   // steps per slot a device schedule holds
+struct GateSet {
+  int32_t k[kMaxBatch];
+  int batch;
+};
+struct SchedRows {
+  float v[kMaxSchedSteps * kSch];
+  int n, slot, stride;
+};
+hipError_t launch_set_gate(int32_t* gate, const GateSet& g, hipStream_t s);
+hipError_t launch_advance_gate(int32_t* gate, const int32_t* nsteps, int batch, hipStream_t s);
+hipError_t launch_set_sched(float* sched, int32_t* nsteps, const SchedRows& r, hipStream_t s);
 hipError_t launch_white_noise(float* w, long long N, long long slot_stride, int batch,
                               const uint64_t* seeds_host, unsigned long long active, hipStream_t s);
 hipError_t launch_psibar(const float* xbar, const float* vbar, float* out, long long N,

@@ -21,6 +21,41 @@ hipError_t launch_fill(void* p, long long bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------- device-indexed step state
+// gate[b]: the step slot b runs next (-1 idle).  Set from the host by value
+// (k[b] = -2 keeps the current value), advanced at the end of each device
+// step (the last step of a slot returns it to -1).
+__global__ void k_set_gate(int32_t* gate, GateSet g) {
+  const int b = threadIdx.x;
+  if (b < g.batch && g.k[b] != -2) gate[b] = g.k[b];
+}
+
+__global__ void k_advance_gate(int32_t* gate, const int32_t* nsteps, int batch) {
+  const int b = threadIdx.x;
+  if (b < batch && gate[b] >= 0) gate[b] = gate[b] + 1 < nsteps[b] ? gate[b] + 1 : -1;
+}
+
+// one slot's schedule rows (kSch floats per step) and its step count
+__global__ void k_set_sched(float* sched, int32_t* nsteps, SchedRows r) {
+  for (int e = threadIdx.x; e < r.n * kSch; e += blockDim.x) sched[(long long)r.slot * r.stride * kSch + e] = r.v[e];
+  if (threadIdx.x == 0) nsteps[r.slot] = r.n;
+}
+
+hipError_t launch_set_gate(int32_t* gate, const GateSet& g, hipStream_t s) {
+  k_set_gate<<<1, kMaxBatch, 0, s>>>(gate, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_gate(int32_t* gate, const int32_t* nsteps, int batch, hipStream_t s) {
+  k_advance_gate<<<1, kMaxBatch, 0, s>>>(gate, nsteps, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_sched(float* sched, int32_t* nsteps, const SchedRows& r, hipStream_t s) {
+  k_set_sched<<<1, 256, 0, s>>>(sched, nsteps, r);
+  return hipGetLastError();
+}
+
 // Philox-4x32-10 (Salmon, Moraes, Dror & Shaw 2011) keyed by the seed, counter
 // = (i mod 2^32, i div 2^32, 0, 0); one standard normal per lattice site by
 // Box-Muller in FP64, rounded once to FP32.

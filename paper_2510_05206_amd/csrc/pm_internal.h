@@ -64,6 +64,24 @@ struct Geom {
   long long part_stride;      // floats between slots of a [3][N] array
   long long mesh_stride;      // elements between slots of a mesh
   long long spec_stride;      // float2 between slots of a half spectrum
+  // device-indexed steps (pm_step_device): when gate is set, slot b takes
+  // part only while gate[b] >= 0, and its step scalars come from
+  // sched[(b sched_steps + gate[b]) kSch + field] instead of the by-value
+  // arrays of the launch
+  const int32_t* gate;
+  const float* sched;
+  int sched_steps;
 };
+
+// fields of one device schedule row (the same floats the by-value path passes)
+enum { kSchTau1 = 0, kSchAlpha = 1, kSchBeta = 2, kSchTau2 = 3, kSchCoef = 4, kSch = 5 };
+
+__host__ __device__ __forceinline__ bool slot_on(const int32_t* gate, unsigned long long active, int slot) {
+  return ((active >> slot) & 1ull) && (gate == nullptr || gate[slot] >= 0);
+}
+__host__ __device__ __forceinline__ float slot_f(const int32_t* gate, const float* sched, int sched_steps,
+                                                 const float* byval, int slot, int field) {
+  return gate ? sched[((long long)slot * sched_steps + gate[slot]) * kSch + field] : byval[slot];
+}
 
 }  // namespace pm

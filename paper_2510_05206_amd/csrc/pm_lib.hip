@@ -41,6 +41,12 @@ struct pm_ctx {
   int32_t* d_es_tab = nullptr;
   float* d_esdec = nullptr;
   float* d_lptkeep = nullptr;
+  // device-indexed steps (pm_set_step_index / pm_step_device)
+  int32_t *d_gate = nullptr, *d_gsteps = nullptr;
+  float* d_sched = nullptr;
+  std::vector<char> sched_dirty;     // slots whose device schedule must be re-uploaded
+  hipGraphExec_t step_exec = nullptr;
+  unsigned long long bind_gen = 0, step_bind_gen = 0;
   float* force3 = nullptr;           // NUFFT: 3 force meshes [B][3][M]
   float2* spec2 = nullptr;           // NUFFT: per-component spectrum
   float *disp = nullptr, *vel = nullptr, *w = nullptr, *xbar = nullptr, *vbar = nullptr;
@@ -82,6 +88,7 @@ struct pm_ctx {
     for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : pool) (void)hipEventDestroy(e);
     if (run_exec) (void)hipGraphExecDestroy(run_exec);
+    if (step_exec) (void)hipGraphExecDestroy(step_exec);
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
@@ -145,7 +152,7 @@ struct Layout {
   size_t off_disp, off_vel, off_w, off_xbar, off_vbar;
   size_t off_mesh, off_spec, off_phi, off_icspec, off_pk, off_dot;
   size_t off_key, off_rank, off_sorted, off_count, off_offset, off_scanp, off_scratch, off_u, off_umax, off_scale;
-  size_t off_es_tab, off_esdec, off_force3, off_spec2, off_lptkeep;
+  size_t off_es_tab, off_esdec, off_force3, off_spec2, off_lptkeep, off_gate, off_gsteps, off_sched;
   size_t total;
 };
 
@@ -198,6 +205,9 @@ Layout layout(const pm_ctx* c, bool adj) {
   L.off_es_tab = take(sizeof(int32_t) * c->es_tab.size());
   L.off_esdec = take(sizeof(float) * n);
   L.off_lptkeep = take(sizeof(float) * n);
+  L.off_gate = take(sizeof(int32_t) * kMaxBatch);
+  L.off_gsteps = take(sizeof(int32_t) * kMaxBatch);
+  L.off_sched = take(sizeof(float) * kSch * (size_t)kMaxSchedSteps * B);  // fixed: memory independent of n_steps
   L.off_force3 = nufft ? take(sizeof(float) * 3 * M * B) : 0;
   L.off_spec2 = nufft ? take(sizeof(float2) * spec_elems(n) * B) : 0;
   L.off_scratch = take(sizeof(long long) * W * W * W * n_tiles * B);
@@ -342,8 +352,12 @@ pm_status r2c_mesh(pm_ctx* c, const void* src, int src_mode, long long src_strid
   r.shift = shift;
   r.stream = c->stream;
   r.active = active;
+  r.gate = c->g.gate;
   KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(r));
   ColArgs a{};
+  a.gate = c->g.gate;
+  a.sched = c->g.sched;
+  a.sched_steps = c->g.sched_steps;
   a.data = dst;
   a.slot_stride = dst_stride;
   a.n = n;
@@ -379,6 +393,9 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
   a.lap = c->d_lap;
   a.win2 = c->d_win2;
   a.active = active;
+  a.gate = c->g.gate;
+  a.sched = c->g.sched;
+  a.sched_steps = c->g.sched_steps;
   const double r = (double)(1 << c->g.log2_r);
   const double n3 = (double)n * n * n;
   for (int b = 0; b < c->cfg.batch; ++b) a.coef[b] = (float)(-s[b] / (r * n3));
@@ -403,6 +420,7 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
   rl.scale = 1.0;
   rl.stream = c->stream;
   rl.active = active;
+  rl.gate = c->g.gate;
   KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   return PM_OK;
 }
@@ -829,6 +847,11 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   c->d_es_tab = (int32_t*)(ws + L.off_es_tab);
   c->d_esdec = (float*)(ws + L.off_esdec);
   c->d_lptkeep = (float*)(ws + L.off_lptkeep);
+  c->d_gate = (int32_t*)(ws + L.off_gate);
+  c->d_gsteps = (int32_t*)(ws + L.off_gsteps);
+  c->d_sched = (float*)(ws + L.off_sched);
+  c->sched_dirty.assign(B, 1);
+  ++c->bind_gen;
   c->force3 = c->cfg.force == PM_FORCE_NUFFT ? (float*)(ws + L.off_force3) : nullptr;
   c->spec2 = c->cfg.force == PM_FORCE_NUFFT ? (float2*)(ws + L.off_spec2) : nullptr;
   c->umax = (float*)(ws + L.off_umax);
@@ -852,6 +875,12 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   HIPCHK(c, hipMemcpyAsync(c->d_es_tab, c->es_tab.data(), sizeof(int32_t) * c->es_tab.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_esdec, c->esdec.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_lptkeep, c->lptkeep.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+  {
+    GateSet gs{};
+    gs.batch = B;
+    for (int b = 0; b < B; ++b) gs.k[b] = -1;
+    HIPCHK(c, launch_set_gate(c->d_gate, gs, c->stream));
+  }
   // host tables must outlive the copies: wait for them here (bind is not on the hot path)
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->bound = true;
@@ -938,6 +967,7 @@ pm_status pm_set_slot_params(pm_ctx* c, const int32_t* n_steps, const double* si
   // initial conditions read): rebuild it only when a step count changes
   for (int b = 0; b < c->cfg.batch; ++b) {
     if (n_steps && n_steps[b] != c->slot_steps[b]) {
+      if ((int)c->sched_dirty.size() == c->cfg.batch) c->sched_dirty[b] = 1;
       c->slot_steps[b] = n_steps[b];
       c->slot_table[b] = step_table(c->growth, c->cfg.a_start, c->cfg.a_end, n_steps[b], c->cfg.stepper,
                                     c->cfg.time_var);
@@ -1046,6 +1076,119 @@ pm_status pm_step(pm_ctx* c, const int32_t* step_index) {
   pm_status st = step_common(c, tp.data(), true, s.data(), al.data(), be.data(), tq.data(), act);
   if (st) return st;
   c->ran = true;
+  return PM_OK;
+}
+
+// ---- device-indexed steps: every slot's step index and step scalars live in
+// device memory, so one captured graph advances any mix of slots
+static pm_status device_steps_ok(pm_ctx* c) {
+  if (pm_status st = check_bound(c)) return st;
+  if (c->cfg.force != PM_FORCE_PM)
+    return fail(c, PM_EUNSUPPORTED, "device-indexed steps cover the PM force");
+  if (c->cfg.n_steps > kMaxSchedSteps) return fail(c, PM_EUNSUPPORTED, "device schedules hold at most 96 steps");
+  return PM_OK;
+}
+
+// upload the schedule rows of slots whose step count changed (stream-ordered,
+// by value)
+static pm_status upload_schedules(pm_ctx* c) {
+  const double r = (double)(1 << c->g.log2_r), n3 = (double)c->g.M;
+  for (int b = 0; b < c->cfg.batch; ++b) {
+    if (!c->sched_dirty[b]) continue;
+    SchedRows rows{};
+    rows.n = c->slot_steps[b];
+    rows.slot = b;
+    rows.stride = kMaxSchedSteps;
+    for (int k = 0; k < rows.n; ++k) {
+      const StepCoef& sc = c->slot_table[b][k];
+      float* v = rows.v + k * kSch;
+      v[kSchTau1] = (float)sc.tau1;
+      v[kSchAlpha] = (float)sc.alpha;
+      v[kSchBeta] = (float)sc.beta;
+      v[kSchTau2] = (float)sc.tau2;
+      v[kSchCoef] = (float)(-sc.s / (r * n3));  // the PM multiplier's coefficient, as poisson_to_real forms it
+    }
+    KLAUNCH(c, PM_K_MISC, launch_set_sched(c->d_sched, c->d_gsteps, rows, c->stream));
+    c->sched_dirty[b] = 0;
+  }
+  return PM_OK;
+}
+
+pm_status pm_set_step_index(pm_ctx* c, const int32_t* step_index) {
+  if (pm_status st = device_steps_ok(c)) return st;
+  if (!step_index) return PM_EINVAL;
+  GateSet g{};
+  g.batch = c->cfg.batch;
+  for (int b = 0; b < g.batch; ++b) {
+    const int k = step_index[b];
+    if (k < -2 || k >= c->slot_steps[b]) return fail(c, PM_EINVAL, "step index out of range");
+    g.k[b] = k;
+  }
+  if (pm_status st = upload_schedules(c)) return st;
+  KLAUNCH(c, PM_K_MISC, launch_set_gate(c->d_gate, g, c->stream));
+  return PM_OK;
+}
+
+// one step of every slot at its device step index, then the indices advance
+static pm_status device_step_launches(pm_ctx* c) {
+  const int B = c->cfg.batch;
+  std::vector<double> unused(B, 0.0);
+  c->g.gate = c->d_gate;
+  c->g.sched = c->d_sched;
+  c->g.sched_steps = kMaxSchedSteps;
+  pm_status st = step_common(c, unused.data(), true, unused.data(), unused.data(), unused.data(), unused.data(),
+                             all_mask(B));
+  c->g.gate = nullptr;
+  c->g.sched = nullptr;
+  c->g.sched_steps = 0;
+  if (st) return st;
+  KLAUNCH(c, PM_K_MISC, launch_advance_gate(c->d_gate, c->d_gsteps, B, c->stream));
+  return PM_OK;
+}
+
+pm_status pm_step_device(pm_ctx* c) {
+  if (pm_status st = device_steps_ok(c)) return st;
+  if (!c->ics_done) return fail(c, PM_ESTATE, "pm_step_device before pm_init_ics");
+  if (pm_status st = upload_schedules(c)) return st;
+  if (!c->use_graph || c->prof) {
+    if (pm_status st = device_step_launches(c)) return st;
+  } else {
+    if (!c->step_exec || c->step_bind_gen != c->bind_gen) {
+      if (c->step_exec) {
+        HIPCHK(c, hipGraphExecDestroy(c->step_exec));
+        c->step_exec = nullptr;
+      }
+      hipStream_t user = c->stream;
+      c->stream = c->cap;
+      HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+      pm_status st = device_step_launches(c);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->cap, &g);
+      c->stream = user;
+      if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(c, PM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&c->step_exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        c->step_exec = nullptr;
+        return fail(c, PM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+      }
+      c->step_bind_gen = c->bind_gen;
+    }
+    HIPCHK(c, hipGraphLaunch(c->step_exec, c->stream));
+  }
+  c->ran = true;
+  return PM_OK;
+}
+
+pm_status pm_get_step_index(pm_ctx* c, int32_t* step_index) {
+  if (pm_status st = device_steps_ok(c)) return st;
+  if (!step_index) return PM_EINVAL;
+  HIPCHK(c, hipMemcpyAsync(step_index, c->d_gate, sizeof(int32_t) * c->cfg.batch, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return PM_OK;
 }
 

@@ -4,18 +4,18 @@ A request asks for the binned P(k) of one simulated universe ("pk") or for
 the gradient of an L2 density loss with respect to its white noise and sigma8
 ("grad"), with its own particle count, sigma8, number of BullFrog steps and
 seed.  The loop keeps one context per (shape, kind) bucket with B slots
-(sized by the HBM budget), each on its own HIP stream (streams shared
-between buckets measured slower: a bucket's queued steps then wait for the
-other bucket's work):
+(sized by the HBM budget), each on its own HIP stream:
 
-* forward buckets batch continuously: a request that arrives while others
-  run is admitted into a free slot (ICs for that slot only), all busy slots
-  advance one BullFrog step per launch whatever their step index (up to three
-  steps queued ahead of the host loop), and a slot that finishes is read out
-  and refilled at once;
-* gradient buckets run the requests waiting at launch time as one batch
-  (forward, loss cotangent, adjoint), because the adjoint integrates every
-  slot of a context backwards together.
+* forward buckets batch continuously on device-indexed steps: a request that
+  arrives while others run is admitted into a free slot (ICs for that slot
+  only, its device step index set to 0), and one replay of the bucket's
+  captured step graph advances every busy slot by one BullFrog step whatever
+  its step index (up to three steps queued ahead of the host loop); a slot
+  that finishes is read out and refilled at once;
+* gradient buckets run cohorts: the requests waiting at launch time take the
+  free slots and run forward, loss cotangent and adjoint together (the
+  adjoint integrates its slots backwards as one), and a new cohort is queued
+  on the remaining free slots without waiting for earlier cohorts to finish.
 
 Device work is enqueued asynchronously and completion is observed with
 events, so buckets overlap on the GPU.  The sequential baseline runs the
@@ -59,6 +59,7 @@ class Result:
     dw_norm: float | None = None
     dw_bits: int | None = None       # sum of the FP32 bit patterns of dL/dw (order-free, exact)
     batch: int = 1
+    dw: np.ndarray | None = None     # dL/dw itself (kept on request, for tests)
 
     @property
     def latency(self):
@@ -111,6 +112,15 @@ class Targets:
 
 # ------------------------------------------------------------ batched loop
 
+def _to_host(t):
+    """Copy to pinned host memory on the current stream without waiting: the
+    copy completes with the next event recorded on that stream (a blocking
+    .cpu() would also wait for every other bucket's stream)."""
+    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+    h.copy_(t, non_blocking=True)
+    return h
+
+
 class _PkBucket:
     AHEAD = 3  # steps queued ahead of the host loop
 
@@ -120,12 +130,11 @@ class _PkBucket:
         with torch.cuda.stream(self.stream):
             self.sim = PMSim(shape_config(n_p, B), with_adjoint=False)
         self.req = [None] * B
-        self.k = [0] * B
+        self.k = [-1] * B          # host mirror of the device step index
         self.steps = [12] * B
         self.sig = [0.81] * B
         self.queue = deque()
-        self.pending = []        # (event, slots, k, pk tensors)
-        self.launched = 0
+        self.pending = []          # (event, finished slots and their requests, pk tensors)
         self.occupancy = []
 
     def busy(self):
@@ -137,7 +146,7 @@ class _PkBucket:
         while free and self.queue:
             b = free.pop(0)
             r = self.queue.popleft()
-            self.req[b], self.k[b] = r, 0
+            self.req[b] = r
             self.steps[b], self.sig[b] = r.n_steps, r.sigma8
             new.append(b)
         if not new:
@@ -145,35 +154,39 @@ class _PkBucket:
         with torch.cuda.stream(self.stream):
             self.sim.set_slot_params(n_steps=self.steps, sigma8=self.sig)
             self.sim.set_active(new)
-            self.sim.init_ics([self.req[b].seed if self.req[b] else 0 for b in range(self.B)])
+            self.sim.init_ics([self.req[b].seed if b in new else 0 for b in range(self.B)])
             self.sim.set_active(None)
+            self.sim.set_step_index([0 if b in new else -2 for b in range(self.B)])
+        for b in new:
+            self.k[b] = 0
 
     def advance(self):
-        """Enqueue one step for every slot that still has steps to run, then
-        the read-out of the slots that just finished."""
+        """Enqueue one device step (every slot with steps left), then the
+        read-out of the slots that just finished."""
         if sum(1 for p in self.pending if not p[0].query()) >= self.AHEAD:
             return  # at most AHEAD steps in flight per bucket
-        idx = [self.k[b] if (self.req[b] is not None and self.k[b] < self.steps[b]) else -1
-               for b in range(self.B)]
-        if all(i < 0 for i in idx):
+        running = [b for b in range(self.B) if self.k[b] >= 0]
+        if not running:
             return
         with torch.cuda.stream(self.stream):
-            self.sim.step(idx)
-            self.occupancy.append(sum(i >= 0 for i in idx) / self.B)
+            self.sim.step_device()
+            self.occupancy.append(len(running) / self.B)
             done = []
-            for b in range(self.B):
-                if idx[b] >= 0:
-                    self.k[b] += 1
-                    if self.k[b] == self.steps[b]:
-                        done.append(b)
+            for b in running:
+                self.k[b] = self.k[b] + 1 if self.k[b] + 1 < self.steps[b] else -1
+                if self.k[b] < 0:
+                    done.append(b)
             pk = None
             if done:
                 self.sim.set_active(done)
-                pk = self.sim.power_spectrum(self.n_p)
+                pk = _to_host(self.sim.power_spectrum(self.n_p)[1])
                 self.sim.set_active(None)
             ev = torch.cuda.Event()
             ev.record(self.stream)
-        self.pending.append((ev, done, pk))
+        # the slots are handed back once their P(k) has been read
+        self.pending.append((ev, [(b, self.req[b]) for b in done], pk))
+        for b in done:
+            self.req[b] = _Reserved
 
     def collect(self, now_fn, results):
         keep = []
@@ -182,63 +195,96 @@ class _PkBucket:
                 keep.append((ev, done, pk))
                 continue
             if done:
-                p = pk[1].cpu().numpy()
+                p = pk.numpy()         # pinned copy, complete with the event
                 t = now_fn()
-                for b in done:
-                    r = self.req[b]
+                for b, r in done:
                     results.append(Result(r.rid, "pk", r.arrival, t, pk=p[b].copy(), batch=self.B))
                     self.req[b] = None
         self.pending = keep
 
 
+class _ReservedSlot:
+    """Marks a slot whose request finished but whose read-out is in flight."""
+
+
+_Reserved = _ReservedSlot()
+
+
 class _GradBucket:
-    def __init__(self, n_p, B, targets, stream):
+    def __init__(self, n_p, B, targets, stream, keep_arrays=False):
         self.n_p, self.B = n_p, B
         self.stream = stream
         with torch.cuda.stream(self.stream):
             self.sim = PMSim(shape_config(n_p, B), with_adjoint=True)
         self.queue = deque()
-        self.inflight = None
+        self.cohorts = []          # (event, requests, slots, ds, dw norms, dw bit sums, dw)
+        self.free = list(range(B))
+        self.steps = [12] * B
+        self.sig = [0.81] * B
         self.target = targets.get(n_p)
+        self.keep_arrays = keep_arrays
         self.occupancy = []
 
     def busy(self):
-        return self.inflight is not None
+        return bool(self.cohorts)
 
     def launch(self):
-        if self.inflight is not None or not self.queue:
+        """Queue a cohort of waiting requests on the free slots (behind any
+        cohort still in flight on this bucket's stream)."""
+        if not self.free or not self.queue:
             return
-        reqs = [self.queue.popleft() for _ in range(min(self.B, len(self.queue)))]
-        slots = list(range(len(reqs)))
-        steps = [r.n_steps for r in reqs] + [12] * (self.B - len(reqs))
-        sig = [r.sigma8 for r in reqs] + [0.81] * (self.B - len(reqs))
-        seeds = [r.seed for r in reqs] + [0] * (self.B - len(reqs))
+        n = min(len(self.free), len(self.queue))
+        reqs = [self.queue.popleft() for _ in range(n)]
+        slots = [self.free.pop(0) for _ in range(n)]
+        seeds = [0] * self.B
+        for b, r in zip(slots, reqs):
+            self.steps[b], self.sig[b], seeds[b] = r.n_steps, r.sigma8, r.seed
         with torch.cuda.stream(self.stream):
-            self.sim.set_slot_params(n_steps=steps, sigma8=sig)
+            self.sim.set_slot_params(n_steps=self.steps, sigma8=self.sig)
             self.sim.set_active(slots)
             self.sim.init_ics(seeds)
-            self.sim.run()
+            # the forward on device-indexed steps: one graph replay per step
+            # for the whole cohort (earlier cohorts' indices are back at -1)
+            self.sim.set_step_index([0 if b in slots else -2 for b in range(self.B)])
+            for _ in range(max(r.n_steps for r in reqs)):
+                self.sim.step_device()
             delta = self.sim.density()
             g = 2.0 * (delta - self.target.unsqueeze(0))
             dw, ds = self.sim.adjoint(g)
-            dwn = dw.double().norm(dim=1)
-            dwb = dw.view(torch.int32).long().sum(dim=1)
+            # the slot index goes up asynchronously from pinned memory (a
+            # pageable copy would wait for everything queued on this stream)
+            idx_h = torch.tensor(slots, dtype=torch.long).pin_memory()
+            idx = idx_h.to(dw.device, non_blocking=True)
+            dws = dw.index_select(0, idx)
+            dwn = dws.double().norm(dim=1)
+            dwb = dws.view(torch.int32).long().sum(dim=1)
+            dss = ds.index_select(0, idx)
             self.sim.set_active(None)
+            dss, dwn, dwb = _to_host(dss), _to_host(dwn), _to_host(dwb)
+            dws = _to_host(dws) if self.keep_arrays else None
             ev = torch.cuda.Event()
             ev.record(self.stream)
-        self.occupancy.append(len(reqs) / self.B)
-        self.inflight = (ev, reqs, ds, dwn, dwb)
+        self.occupancy.append(n / self.B)
+        self.cohorts.append((ev, reqs, slots, dss, dwn, dwb, dws, idx_h))
 
     def collect(self, now_fn, results):
-        if self.inflight is None or not self.inflight[0].query():
-            return
-        _, reqs, ds, dwn, dwb = self.inflight
-        ds, dwn, dwb = ds.cpu().numpy(), dwn.cpu().numpy(), dwb.cpu().numpy()
-        t = now_fn()
-        for b, r in enumerate(reqs):
-            results.append(Result(r.rid, "grad", r.arrival, t, dsigma8=float(ds[b]), dw_norm=float(dwn[b]),
-                                  dw_bits=int(dwb[b]), batch=self.B))
-        self.inflight = None
+        keep = []
+        for co in self.cohorts:
+            ev, reqs, slots, ds, dwn, dwb, dws, _ = co
+            if not ev.query():
+                keep.append(co)
+                continue
+            ds, dwn, dwb = ds.numpy(), dwn.numpy(), dwb.numpy()   # pinned copies, complete with the event
+            dw = dws.numpy() if dws is not None else None
+            t = now_fn()
+            for q, r in enumerate(reqs):
+                res = Result(r.rid, "grad", r.arrival, t, dsigma8=float(ds[q]), dw_norm=float(dwn[q]),
+                             dw_bits=int(dwb[q]), batch=self.B)
+                if dw is not None:
+                    res.dw = dw[q].copy()
+                results.append(res)
+            self.free.extend(slots)
+        self.cohorts = keep
 
 
 def workspace_bytes(cfg, with_adjoint):
@@ -270,41 +316,49 @@ def plan_batches(hbm_budget_bytes, max_batch=16, sizes=MIX_N, weights=MIX_W):
     return out
 
 
-def serve_batched(requests, hbm_budget_gb=160.0, max_batch=16, targets=None):
+def serve_batched(requests, hbm_budget_gb=160.0, max_batch=16, targets=None, keep_arrays=False):
     """Run the trace with continuous batching; returns results and stats."""
     targets = targets or Targets()
     sizes = sorted({r.n_p for r in requests})
     plan = plan_batches(hbm_budget_gb * 1e9, max_batch, MIX_N, MIX_W)
     pk_b = {n: _PkBucket(n, plan[("pk", n)], torch.cuda.Stream()) for n in sizes}
-    gr_b = {n: _GradBucket(n, plan[("grad", n)], targets, torch.cuda.Stream()) for n in sizes}
+    gr_b = {n: _GradBucket(n, plan[("grad", n)], targets, torch.cuda.Stream(), keep_arrays) for n in sizes}
     torch.cuda.synchronize()
     reqs = deque(sorted(requests, key=lambda r: r.arrival))
     results = []
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0
     total = len(reqs)
+    host = {}          # host seconds spent per bucket and phase (enqueueing, not GPU time)
+
+    def timed(key, fn, *a):
+        s0 = time.perf_counter()
+        fn(*a)
+        host[key] = host.get(key, 0.0) + time.perf_counter() - s0
+
     while len(results) < total:
         t = now()
         while reqs and reqs[0].arrival <= t:
             r = reqs.popleft()
             (pk_b if r.kind == "pk" else gr_b)[r.n_p].queue.append(r)
-        for b in pk_b.values():
-            b.collect(now, results)
-            b.admit()
-            b.advance()
-        for b in gr_b.values():
-            b.collect(now, results)
-            b.launch()
+        for n, b in pk_b.items():
+            timed(f"pk_{n}_collect", b.collect, now, results)
+            timed(f"pk_{n}_admit", b.admit)
+            timed(f"pk_{n}_advance", b.advance)
+        for n, b in gr_b.items():
+            timed(f"grad_{n}_collect", b.collect, now, results)
+            timed(f"grad_{n}_launch", b.launch)
         if reqs and not any(b.busy() or b.queue for b in list(pk_b.values()) + list(gr_b.values())):
             time.sleep(max(0.0, min(0.002, reqs[0].arrival - now())))
     makespan = now()
     occ = [o for b in pk_b.values() for o in b.occupancy] + [o for b in gr_b.values() for o in b.occupancy]
     stats = {"makespan_s": makespan, "plan": {f"{k}_{n}": v for (k, n), v in plan.items()},
-             "mean_occupancy": float(np.mean(occ)) if occ else 0.0}
+             "mean_occupancy": float(np.mean(occ)) if occ else 0.0,
+             "host_s": {k: round(v, 4) for k, v in sorted(host.items(), key=lambda kv: -kv[1]) if v > 1e-3}}
     return results, stats
 
 
-def serve_sequential(requests, targets=None):
+def serve_sequential(requests, targets=None, keep_arrays=False):
     """The plain method: one request at a time, in arrival order, one-slot
     contexts (built once per shape and kind, not timed)."""
     targets = targets or Targets()
@@ -334,8 +388,10 @@ def serve_sequential(requests, targets=None):
             dw, ds = sim.adjoint(2.0 * (delta - targets.get(r.n_p).unsqueeze(0)))
             dwn = float(dw.double().norm())
             dwb = int(dw.view(torch.int32).long().sum())
-            results.append(Result(r.rid, "grad", r.arrival, now(), dsigma8=float(ds.cpu()[0]), dw_norm=dwn,
-                                  dw_bits=dwb))
+            res = Result(r.rid, "grad", r.arrival, now(), dsigma8=float(ds.cpu()[0]), dw_norm=dwn, dw_bits=dwb)
+            if keep_arrays:
+                res.dw = dw[0].cpu().numpy().copy()
+            results.append(res)
         service.append(now() - s)
     return results, {"makespan_s": now(), "mean_service_s": float(np.mean(service))}
 

@@ -98,7 +98,7 @@ class PMSim:
 
     # --------------------------------------------------------------- calls
     _STATE_CALLS = frozenset({"pm_init_ics", "pm_step", "pm_run", "pm_adjoint", "pm_set_state", "pm_deposit",
-                              "pm_force", "pm_force_vjp", "pm_set_active"})
+                              "pm_force", "pm_force_vjp", "pm_set_active", "pm_step_device"})
 
     def _call(self, name, *args):
         if name in self._STATE_CALLS:
@@ -129,6 +129,21 @@ class PMSim:
 
     def run(self):
         self._call("pm_run")
+
+    def set_step_index(self, step_index):
+        """Device step index per slot: k >= 0 next step, -1 idle, -2 keep."""
+        B = self.cfg.batch
+        self._call("pm_set_step_index", (C.c_int32 * B)(*[int(k) for k in step_index]))
+
+    def step_device(self):
+        """Advance every slot with a device step index >= 0 by one step."""
+        self._call("pm_step_device")
+
+    def get_step_index(self):
+        B = self.cfg.batch
+        out = (C.c_int32 * B)()
+        self._call("pm_get_step_index", out)
+        return list(out)
 
     def adjoint(self, dL_ddelta):
         B = self.cfg.batch
