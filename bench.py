@@ -309,10 +309,6 @@ def main():
               f"(one process per GPU, each on its own slots, is how it would shard)", file=sys.stderr)
         sys.exit(2)
     if args.serve:
-        # one hardware queue per serving bucket (8 buckets; HIP's default is
-        # 4, so buckets would share queues and small requests would wait in
-        # line behind large ones); must be set before the runtime starts
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
         import torch
         torch.cuda.set_device(0)
         print(json.dumps(serve_bench(args.requests, args.hbm_budget_gb)), flush=True)
