@@ -214,6 +214,17 @@ pm_status pm_use_graphs(pm_ctx* ctx, int32_t enable);
  * initial conditions. */
 pm_status pm_adjoint(pm_ctx* ctx, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8);
 
+/* pm_adjoint plus the adjoints of the step scalars of tab. adjoint_dkd:
+ * dL_dtime (device doubles [B][n_steps][4], n_steps of the configuration)
+ * receives per slot and step n the row (dL/dtau1, dL/dtau2, dL/dalpha,
+ * dL/dbeta) of V^{n+1} = alpha V^n + beta A, X^{n+1/2} = X^n + tau1 V^n,
+ * X^{n+1} = X^{n+1/2} + tau2 V^{n+1}; rows beyond a slot's own step count are
+ * zero.  FP64 dot products over the particles of the reverse pass's states;
+ * dL/dbeta is formed as (V_bar . V^{n+1} - alpha V_bar . V^n) / beta, with
+ * V_bar the cotangent of the kick's output.  dL_dtime = NULL is pm_adjoint. */
+pm_status pm_adjoint_full(pm_ctx* ctx, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8,
+                          double* dL_dtime);
+
 /* Device-indexed steps for continuous batching (serving): each slot's next
  * step index lives in device memory, so slots at different steps, admitted
  * at different times, advance together through one captured graph with no

@@ -82,11 +82,13 @@ def ic_vjp(prob, psibar):
     return np.fft.irfftn(acc, s=(n, n, n), axes=(0, 1, 2))
 
 
-def gradient(prob, w, dL_ddelta, progress=None):
+def gradient(prob, w, dL_ddelta, progress=None, temporal=None):
     """Reverse-mode gradient of L(delta_final) w.r.t. the white noise w and
     sigma8, given a function dL_ddelta(delta) -> cotangent mesh.
     Returns (w_bar (n_p^3,), dL/dsigma8, delta_final).  ``progress``, if
-    given, is called with a short message after each forward and reverse step."""
+    given, is called with a short message after each forward and reverse step;
+    ``temporal`` (a list), if given, receives the per-step adjoints of
+    (tau1, tau2, alpha, beta) (see reverse_cotangents)."""
     from .nbody import initial_state, run_from
     if prob.lpt_order != 1:
         raise NotImplementedError("the reverse pass covers Zel'dovich initial conditions")
@@ -96,7 +98,7 @@ def gradient(prob, w, dL_ddelta, progress=None):
     delta = final_density(prob, psiN)
     xbar = density_vjp(psiN, prob.pm.n_p, prob.pm.n_g, dL_ddelta(delta))
     vbar = np.zeros_like(xbar)
-    xbar, vbar = reverse_cotangents(prob, record, xbar, vbar, progress)
+    xbar, vbar = reverse_cotangents(prob, record, xbar, vbar, progress, temporal)
     psibar = prob.D_start() * xbar + vbar
     wbar = ic_vjp(prob, psibar)
     # the power-law spectrum is normalised by its rms displacement, not by
@@ -105,14 +107,31 @@ def gradient(prob, w, dL_ddelta, progress=None):
     return wbar.reshape(-1), dsig, delta
 
 
-def reverse_cotangents(prob, record, xbar, vbar, progress=None):
+def reverse_cotangents(prob, record, xbar, vbar, progress=None, temporal=None):
     """Apply the cotangent recurrences of tab. adjoint_dkd over the stored
-    midpoints, last step first."""
-    for i, (st, (psi_half, _acc)) in enumerate(zip(reversed(prob.steps()), reversed(record))):
+    midpoints, last step first.  ``temporal`` (a list), if given, receives
+    per step, first step first, the adjoints of its scalars (tau1, tau2,
+    alpha, beta): for V^{n+1} = alpha V^n + beta A, X^{n+1} = X^{n+1/2} +
+    tau2 V^{n+1}, X^{n+1/2} = X^n + tau1 V^n,
+      tau2_bar = X_bar^{n+1} . V^{n+1},  alpha_bar = V_bar^{n+1/2} . V^n,
+      beta_bar = V_bar^{n+1/2} . A^{n+1/2},  tau1_bar = X_bar^{n+1/2} . V^n,
+    with V_bar^{n+1/2} the cotangent of the kick's output and X_bar^{n+1/2}
+    that of the midpoint position (the table prints V^n for the velocity in
+    the alpha row, read as the kick's input, the only factor the kick
+    multiplies by alpha)."""
+    out = []
+    for i, (st, (psi_half, acc, v_n, v_np1)) in enumerate(zip(reversed(prob.steps()), reversed(record))):
+        tau2_bar = float(np.sum(xbar * v_np1))
         vbar = vbar + st.tau2 * xbar                    # adjoint of drift 2
+        alpha_bar = float(np.sum(vbar * v_n))
+        beta_bar = float(np.sum(vbar * acc))
         xbar = xbar + problem_force_vjp(prob, psi_half, st.s, st.beta * vbar)  # adjoint kick
         vbar = st.alpha * vbar                          # velocity rescale
+        tau1_bar = float(np.sum(xbar * v_n))
         vbar = vbar + st.tau1 * xbar                    # adjoint of drift 1
+        out.append((tau1_bar, tau2_bar, alpha_bar, beta_bar))
         if progress is not None:
             progress(f"oracle reverse step {i} done")
+    if temporal is not None:
+        temporal.extend(reversed(out))
     return xbar, vbar

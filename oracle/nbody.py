@@ -85,17 +85,18 @@ def white_noise(prob: Problem, seed):
 
 def run_from(prob: Problem, psi, vel, steps=None, record=None, progress=None):
     """Integrate (Psi, V) through the BullFrog steps; ``record`` (a list), if
-    given, receives (Psi^{n+1/2}, A^{n+1/2}) per step; ``progress``, if given,
-    is called with a short message after each step."""
+    given, receives (Psi^{n+1/2}, A^{n+1/2}, V^n, V^{n+1}) per step;
+    ``progress``, if given, is called with a short message after each step."""
     force = prob.force_fn()
     psi = np.array(psi, dtype=np.float64)
     vel = np.array(vel, dtype=np.float64)
     for i, st in enumerate(prob.steps() if steps is None else steps):
         psi += st.tau1 * vel
         acc = force(psi, st.s)
-        if record is not None:
-            record.append((psi.copy(), acc))
+        v_before = vel
         vel = st.alpha * vel + st.beta * acc
+        if record is not None:
+            record.append((psi.copy(), acc, v_before.copy(), vel.copy()))
         psi += st.tau2 * vel
         if progress is not None:
             progress(f"oracle forward step {i} done")

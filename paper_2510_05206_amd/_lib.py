@@ -61,6 +61,7 @@ EXPORTS = {
     "pm_get_step_index": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pm_run": (C.c_int, [C.c_void_p]),
     "pm_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pm_adjoint_full": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_power_spectrum": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

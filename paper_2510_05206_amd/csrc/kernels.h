@@ -106,7 +106,13 @@ hipError_t launch_reorder(const float* src, float* dst, long long N, long long s
                           int log2_np, int log2_pb, bool to_blocked, unsigned long long active, hipStream_t s);
 hipError_t launch_dot(const float* a, const float* b, long long n, long long stride, int batch,
                       double* partial, double* out, const double* scale, unsigned long long active,
-                      hipStream_t s);
+                      hipStream_t s, const long long* out_idx = nullptr);
+struct TimeAB {
+  double alpha[kMaxBatch], beta[kMaxBatch];
+  long long idx[kMaxBatch];  // first element of the slot's (tau1, tau2, alpha, beta) row
+};
+hipError_t launch_time_ab(const double* d1, const double* d2, double* out, const TimeAB& t,
+                          unsigned long long active, hipStream_t s);
 hipError_t launch_i64_to_delta(const long long* m, float* delta, long long M, long long stride,
                                int batch, double scale, unsigned long long active, hipStream_t s);
 hipError_t launch_pk(const float2* spec, long long slot_stride, int n, int batch, int n_bins,

@@ -174,24 +174,49 @@ __global__ void k_dot_partial(const float* a, const float* b, long long n, long 
   if (threadIdx.x == 0) partial[slot * kDotBlocks + blockIdx.x] = sh[0];
 }
 
-struct Scales { double s[kMaxBatch]; };
+struct Scales {
+  double s[kMaxBatch];
+  long long idx[kMaxBatch];  // output element of each slot
+};
 __global__ void k_dot_final(const double* partial, double* out, Scales sc, unsigned long long active) {
   const int slot = blockIdx.x;
   if (!((active >> slot) & 1ull)) return;
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int i = 0; i < kDotBlocks; ++i) t += partial[slot * kDotBlocks + i];
-    out[slot] = t * sc.s[slot];
+    out[sc.idx[slot]] = t * sc.s[slot];
   }
 }
 
+// out[out_idx[b]] = scale[b] sum_i a[b][i] b[b][i] (FP64, fixed order);
+// out_idx null: out[b]
 hipError_t launch_dot(const float* a, const float* b, long long n, long long stride, int batch,
                       double* partial, double* out, const double* scale, unsigned long long active,
-                      hipStream_t s) {
+                      hipStream_t s, const long long* out_idx) {
   k_dot_partial<<<dim3(kDotBlocks, batch), 256, 0, s>>>(a, b, n, stride, partial, active);
   Scales sc;
-  for (int i = 0; i < batch; ++i) sc.s[i] = scale[i];
+  for (int i = 0; i < batch; ++i) {
+    sc.s[i] = scale[i];
+    sc.idx[i] = out_idx ? out_idx[i] : i;
+  }
   k_dot_final<<<batch, 64, 0, s>>>(partial, out, sc, active);
+  return hipGetLastError();
+}
+
+// temporal adjoints of one reverse step from the dots taken around its
+// adjoint kick: d1 = V_bar^{n+1/2} . V^{n+1} before it, d2 = (alpha
+// V_bar^{n+1/2}) . V^n after it; alpha_bar = d2 / alpha, beta_bar =
+// V_bar^{n+1/2} . A = (d1 - d2) / beta (V^{n+1} - alpha V^n = beta A)
+__global__ void k_time_ab(const double* d1, const double* d2, double* out, TimeAB t, unsigned long long active) {
+  const int slot = threadIdx.x;
+  if (slot >= kMaxBatch || !((active >> slot) & 1ull)) return;
+  out[t.idx[slot] + 2] = d2[slot] / t.alpha[slot];
+  out[t.idx[slot] + 3] = t.beta[slot] != 0.0 ? (d1[slot] - d2[slot]) / t.beta[slot] : 0.0;
+}
+
+hipError_t launch_time_ab(const double* d1, const double* d2, double* out, const TimeAB& t,
+                          unsigned long long active, hipStream_t s) {
+  k_time_ab<<<1, kMaxBatch, 0, s>>>(d1, d2, out, t, active);
   return hipGetLastError();
 }
 

@@ -67,6 +67,7 @@ struct pm_ctx {
   long long icspec_comp = 0;         // float2 per spectrum
   double* pk_partial = nullptr;
   double* dot_partial = nullptr;
+  double* tdots = nullptr;           // temporal adjoints: the two dots around each adjoint kick [2][kMaxBatch]
   // state
   bool ics_done = false, ran = false;
   unsigned long long user_mask = 1;  // slots the whole-context calls act on (pm_set_active)
@@ -152,6 +153,7 @@ struct Layout {
   size_t off_disp, off_vel, off_w, off_xbar, off_vbar;
   size_t off_mesh, off_spec, off_phi, off_icspec, off_pk, off_dot;
   size_t off_key, off_rank, off_sorted, off_count, off_offset, off_scanp, off_scratch, off_u, off_umax, off_scale;
+  size_t off_tdots;
   size_t off_es_tab, off_esdec, off_force3, off_spec2, off_lptkeep, off_gate, off_gsteps, off_sched;
   size_t total;
 };
@@ -217,6 +219,7 @@ Layout layout(const pm_ctx* c, bool adj) {
   L.off_icspec = take(sizeof(float2) * 4 * align_up(spec_elems(np)) * B);
   L.off_pk = take(sizeof(double) * 3 * (size_t)n * n * B);  // n_bins <= n
   L.off_dot = take(sizeof(double) * 256 * B);
+  L.off_tdots = take(sizeof(double) * 2 * kMaxBatch);
   L.total = o;
   return L;
 }
@@ -860,6 +863,7 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   c->icspec = (float2*)(ws + L.off_icspec);
   c->pk_partial = (double*)(ws + L.off_pk);
   c->dot_partial = (double*)(ws + L.off_dot);
+  c->tdots = (double*)(ws + L.off_tdots);
   const int n = c->cfg.n_g, np = c->cfg.n_p;
   c->icspec_comp = (long long)(align_up(spec_elems(np)));
   c->icspec_stride = 4 * c->icspec_comp;
@@ -1267,8 +1271,10 @@ static pm_status run_steps(pm_ctx* c) {
 // is -i k_c times that of the spread of u_c), R2C, the real remainder of the
 // multiplier, C2R; its gradient gather (the transposed spreading) fused with
 // the reverse drift
+pm_status kick_dot(pm_ctx* c, double* out, unsigned long long act);
+
 pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, const double* beta,
-                             const double* tau, unsigned long long act, int parts) {
+                             const double* tau, unsigned long long act, int parts, double* kdot) {
   const int B = c->cfg.batch, ng = c->cfg.n_g;
   const long long N = c->g.N, M = c->g.M;
   TileArgs k = tile_args(c, c->disp, act);
@@ -1280,6 +1286,7 @@ pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, co
     k.beta[b] = (float)beta[b];
   }
   KLAUNCH(c, PM_K_ADJ_KICK, launch_tile_es(k, TK_ES_ADJ_KICK, c->stream));
+  if (pm_status st = kick_dot(c, kdot, act)) return st;
   if (!(parts & 1))
     KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
   if (!(parts & 2)) return PM_OK;
@@ -1358,10 +1365,19 @@ pm_status nufft_adjoint_step(pm_ctx* c, const double* s, const double* alpha, co
 // scatter-w.r.t.-positions term with the reverse drift by tau.  parts: bit 0
 // keeps the direct term, bit 1 runs the mesh path (the force-VJP test hook
 // separates them; the adjoint uses both).
+// dot of V_bar and V right after the adjoint kick (temporal adjoints)
+pm_status kick_dot(pm_ctx* c, double* out, unsigned long long act) {
+  if (!out) return PM_OK;
+  std::vector<double> ones(c->cfg.batch, 1.0);
+  KLAUNCH(c, PM_K_MISC, launch_dot(c->vbar, c->vel, 3 * c->g.N, 3 * c->g.N, c->cfg.batch, c->dot_partial, out,
+                                   ones.data(), act, c->stream));
+  return PM_OK;
+}
+
 pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, const double* beta,
-                             const double* tau, unsigned long long act, int parts) {
+                             const double* tau, unsigned long long act, int parts, double* kdot = nullptr) {
   KLAUNCH(c, PM_K_FILL, launch_fill(c->umax, (long long)sizeof(float) * kMaxBatch, c->stream));
-  if (c->cfg.force == PM_FORCE_NUFFT) return nufft_adjoint_step(c, s, alpha, beta, tau, act, parts);
+  if (c->cfg.force == PM_FORCE_NUFFT) return nufft_adjoint_step(c, s, alpha, beta, tau, act, parts, kdot);
   const int B = c->cfg.batch;
   const long long N = c->g.N, M = c->g.M;
   const double mfac = (double)M / (double)N;
@@ -1375,6 +1391,7 @@ pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, co
     k.beta[b] = (float)beta[b];
   }
   KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(k, TK_ADJ_KICK, mak, ord, c->stream));
+  if (pm_status st = kick_dot(c, kdot, act)) return st;
   if (!(parts & 1))
     KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
   if (!(parts & 2)) return PM_OK;
@@ -1399,7 +1416,13 @@ pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, co
   return PM_OK;
 }
 
+pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8, double* dL_dtime);
+
 pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8) {
+  return pm_adjoint_full(c, dL_ddelta, dL_dw, dL_dsigma8, nullptr);
+}
+
+pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8, double* dL_dtime) {
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!c->ran) return fail(c, PM_ESTATE, "pm_adjoint before pm_run");
@@ -1424,6 +1447,25 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
     lv.tau[b] = (float)c->slot_table[b][c->slot_steps[b] - 1].tau2;
   }
   KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile(lv, TK_ADJ_DRIFT, 2, c->cfg.grad_order, c->stream));
+  // temporal adjoints (tab. adjoint_dkd), rows (tau1, tau2, alpha, beta) per
+  // step: X_bar . V after the loss pullback gives the last tau2 of each slot;
+  // after reverse step n (its merged drift leaves X_bar and V alone) it gives
+  // tau1 of step n and tau2 of step n - 1; alpha and beta come from the dots
+  // taken around the adjoint kick
+  const int S = c->cfg.n_steps;
+  std::vector<double> ones(B, 1.0);
+  auto row = [&](int n, int field) {
+    std::vector<long long> v(B);
+    for (int b = 0; b < B; ++b) v[b] = ((long long)b * S + std::max(0, n)) * 4 + field;
+    return v;
+  };
+  if (dL_dtime) {
+    KLAUNCH(c, PM_K_FILL, launch_fill(dL_dtime, (long long)sizeof(double) * 4 * S * B, c->stream));
+    std::vector<long long> last(B);
+    for (int b = 0; b < B; ++b) last[b] = ((long long)b * S + c->slot_steps[b] - 1) * 4 + 1;
+    KLAUNCH(c, PM_K_MISC, launch_dot(c->xbar, c->vel, 3 * N, 3 * N, B, c->dot_partial, dL_dtime, ones.data(), all,
+                                     c->stream, last.data()));
+  }
   for (int n = nmax - 1; n >= 0; --n) {
     std::vector<double> s(B, 1);
     unsigned long long act = 0;
@@ -1442,8 +1484,28 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
       be[b] = T[n].beta;
       tau[b] = T[n].tau1 + (n > 0 ? T[n - 1].tau2 : 0.0);
     }
-    st = reverse_force_step(c, s.data(), al.data(), be.data(), tau.data(), act, 3);
+    double* d1 = c->tdots;
+    double* d2 = c->tdots + kMaxBatch;
+    if (dL_dtime)
+      KLAUNCH(c, PM_K_MISC, launch_dot(c->vbar, c->vel, 3 * N, 3 * N, B, c->dot_partial, d1, ones.data(), act,
+                                       c->stream));
+    st = reverse_force_step(c, s.data(), al.data(), be.data(), tau.data(), act, 3, dL_dtime ? d2 : nullptr);
     if (st) return st;
+    if (dL_dtime) {
+      TimeAB t{};
+      const std::vector<long long> r0 = row(n, 0);
+      for (int b = 0; b < B; ++b) {
+        t.alpha[b] = al[b];
+        t.beta[b] = be[b];
+        t.idx[b] = r0[b];
+      }
+      KLAUNCH(c, PM_K_MISC, launch_time_ab(d1, d2, dL_dtime, t, act, c->stream));
+      KLAUNCH(c, PM_K_MISC, launch_dot(c->xbar, c->vel, 3 * N, 3 * N, B, c->dot_partial, dL_dtime, ones.data(), act,
+                                       c->stream, r0.data()));
+      if (n > 0)
+        KLAUNCH(c, PM_K_MISC, launch_dot(c->xbar, c->vel, 3 * N, 3 * N, B, c->dot_partial, dL_dtime, ones.data(),
+                                         act, c->stream, row(n - 1, 1).data()));
+    }
   }
   // initial conditions: psi_bar = D0 X_bar + V_bar, w_bar = sum_c T_c^T psi_bar_c
   std::vector<float> d0(B, (float)c->D0);

@@ -97,7 +97,8 @@ class PMSim:
             self.ctx = None
 
     # --------------------------------------------------------------- calls
-    _STATE_CALLS = frozenset({"pm_init_ics", "pm_step", "pm_run", "pm_adjoint", "pm_set_state", "pm_deposit",
+    _STATE_CALLS = frozenset({"pm_init_ics", "pm_step", "pm_run", "pm_adjoint", "pm_adjoint_full", "pm_set_state",
+                              "pm_deposit",
                               "pm_force", "pm_force_vjp", "pm_set_active", "pm_step_device"})
 
     def _call(self, name, *args):
@@ -145,13 +146,19 @@ class PMSim:
         self._call("pm_get_step_index", out)
         return list(out)
 
-    def adjoint(self, dL_ddelta):
+    def adjoint(self, dL_ddelta, temporal=False):
+        """(dL/dw [B, N], dL/dsigma8 [B]); with temporal, also the adjoints of
+        every step's (tau1, tau2, alpha, beta) [B, n_steps, 4]."""
         B = self.cfg.batch
         g = dL_ddelta.to(self.device, torch.float32).contiguous().reshape(B, self.cfg.M)
         dw = self._new(B, self.cfg.N)
         ds = self._new(B, dtype=torch.float64)
-        self._call("pm_adjoint", _ptr(g), _ptr(dw), _ptr(ds))
-        return dw, ds
+        if not temporal:
+            self._call("pm_adjoint", _ptr(g), _ptr(dw), _ptr(ds))
+            return dw, ds
+        dt = self._new(B, self.cfg.n_steps, 4, dtype=torch.float64)
+        self._call("pm_adjoint_full", _ptr(g), _ptr(dw), _ptr(ds), _ptr(dt))
+        return dw, ds, dt
 
     def power_spectrum(self, n_bins, deconvolve=True):
         B = self.cfg.batch

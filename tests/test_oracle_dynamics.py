@@ -236,3 +236,35 @@ def test_powerlaw_spectrum_gradient_has_no_sigma8_term():
     assert np.array_equal(x1, x2)
     _, dsig, _ = adjoint.gradient(p1, w, lambda d: 2 * d)
     assert dsig == 0.0
+
+
+@pytest.mark.parametrize("stepper", ["bullfrog", "fastpm"])
+def test_temporal_adjoints_match_finite_differences(stepper):
+    # tab. adjoint_dkd: the adjoints of each step's tau1, tau2, alpha, beta
+    # against central differences of the forward map with that one scalar moved
+    import dataclasses
+    prob = _small_problem()
+    prob.stepper = stepper
+    prob._cache.clear()
+    n = prob.pm.n_p
+    rng = np.random.default_rng(11)
+    w = nbody.white_noise(prob, 5).astype(np.float64)
+    target = rng.normal(size=prob.pm.n_g ** 3)
+    temporal = []
+    adjoint.gradient(prob, w, lambda d: 2 * (d - target), temporal=temporal)
+    steps = prob.steps()
+    assert len(temporal) == len(steps)
+    psi0, v0, _ = nbody.initial_state(prob, w)
+
+    def loss_with(k, field, value):
+        st = list(steps)
+        st[k] = dataclasses.replace(st[k], **{field: value})
+        psi, _ = nbody.run_from(prob, psi0, v0, steps=st)
+        return np.sum((adjoint.final_density(prob, psi) - target) ** 2)
+
+    for k in range(len(steps)):
+        for j, field in enumerate(("tau1", "tau2", "alpha", "beta")):
+            x = getattr(steps[k], field)
+            eps = 1e-7 * max(abs(x), 1e-3)
+            fd = (loss_with(k, field, x + eps) - loss_with(k, field, x - eps)) / (2 * eps)
+            assert abs(temporal[k][j] - fd) < 1e-5 * abs(fd) + 1e-6, (k, field, temporal[k][j], fd)
