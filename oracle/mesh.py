@@ -1,8 +1,8 @@
 """Mass assignment (scatter), interpolation (gather) and their position
 derivatives, in FP64, plus the integer fixed-point deposit specification.
 
-Test infrastructure only.  Follows tab. interpolation_kernels (CIC and TSC 1D
-kernels, 3D kernel = product over axes) and App. "Custom VJP and JVP" (scatter
+Test infrastructure only.  Follows tab. interpolation_kernels (CIC, TSC and
+PCS 1D kernels, 3D kernel = product over axes) and App. "Custom VJP and JVP" (scatter
 rho_j = sum_i w_i W_j(X_i); gather v_i = sum_j rho_j W_j(X_i); position
 derivatives through grad W).
 
@@ -45,6 +45,7 @@ def weights_1d(u, order):
     CIC (order 2): nodes floor(u), floor(u)+1 with weights 1-f, f.
     TSC (order 3): n = floor(u + 1/2), x = u - n, nodes n-1, n, n+1 with
     weights (1/2)(1/2 - x)^2, 3/4 - x^2, (1/2)(1/2 + x)^2.
+    PCS (order 4): nodes floor(u)-1 .. floor(u)+2 with the cubic B-spline.
     """
     if order == 2:
         i0 = np.floor(u)
@@ -59,7 +60,18 @@ def weights_1d(u, order):
         return (np.stack([n - 1, n, n + 1]),
                 np.stack([0.5 * (0.5 - x) ** 2, 0.75 - x * x, 0.5 * (0.5 + x) ** 2]),
                 np.stack([-(0.5 - x), -2.0 * x, 0.5 + x]))
-    raise ValueError("order must be 2 (CIC) or 3 (TSC)")
+    if order == 4:
+        i0 = np.floor(u)
+        f = u - i0
+        g = 1.0 - f
+        i0 = i0.astype(np.int64)
+        # PCS: W(x) = (4 - 6x^2 + 3|x|^3)/6 for |x| <= 1, (2 - |x|)^3/6 for
+        # 1 <= |x| <= 2, at node distances 1+f, f, 1-f, 2-f
+        return (np.stack([i0 - 1, i0, i0 + 1, i0 + 2]),
+                np.stack([g ** 3 / 6.0, (4.0 - 6.0 * f * f + 3.0 * f ** 3) / 6.0,
+                          (4.0 - 6.0 * g * g + 3.0 * g ** 3) / 6.0, f ** 3 / 6.0]),
+                np.stack([-0.5 * g * g, -2.0 * f + 1.5 * f * f, 2.0 * g - 1.5 * g * g, 0.5 * f * f]))
+    raise ValueError("order must be 2 (CIC), 3 (TSC) or 4 (PCS)")
 
 
 def _stencil(psi, n_p, n_g, order):
@@ -168,7 +180,29 @@ def fixed_weights_1d(U, order):
         wr = _rne_shift(((one >> 1) + X) ** 2, s)
         wc = (1 << K_W) - wl - wr
         return np.stack([n - 1, n, n + 1]), np.stack([wl, wc, wr])
-    raise ValueError("order must be 2 or 3")
+    if order == 4:
+        # PCS with F = frac(u) 2^B, G = 2^B - F (B = K = 20): the outer
+        # weights G^3/6 and F^3/6 and the node-below weight (4 - 6f^2 + 3f^3)/6
+        # rounded half-even from exact integers, the last one the remainder
+        i0 = U >> B_FRAC
+        F = U & (one - 1)
+        G = one - F
+        D = 6 << (2 * B_FRAC)
+        wa = _rne_div(G ** 3, D)
+        wd = _rne_div(F ** 3, D)
+        wb = _rne_div((4 << (3 * B_FRAC)) + 3 * F ** 3 - 6 * F * F * one, D)
+        wc = (1 << K_W) - wa - wb - wd
+        return np.stack([i0 - 1, i0, i0 + 1, i0 + 2]), np.stack([wa, wb, wc, wd])
+    raise ValueError("order must be 2, 3 or 4")
+
+
+def _rne_div(p, d):
+    """Round-half-to-even of p / d for non-negative int64 p and d > 0."""
+    p = np.asarray(p, dtype=np.int64)
+    q = p // d
+    rem = p - q * d
+    up = (2 * rem > d) | ((2 * rem == d) & ((q & 1) == 1))
+    return q + up.astype(np.int64)
 
 
 def fixed_stencil_weights(U, order):

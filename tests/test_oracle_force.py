@@ -152,7 +152,7 @@ def test_plane_wave_force_converges_at_fourth_order():
     assert 14 < errs[0] / errs[1] < 18
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_window_is_single_particle_aliased_spectrum(order):
     # tab. interpolation_kernels, Fourier column: the DFT of one particle's
     # real-space deposit is, by Poisson summation, the aliased sum over images
@@ -174,7 +174,7 @@ def test_window_is_single_particle_aliased_spectrum(order):
         assert np.abs(got - ref).max() < 1e-8
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_deconvolution_divides_by_the_squared_window(order):
     # a plane wave on the mesh: the deconvolved multiplier is the plain one
     # divided by W(theta_x)^2 W(theta_y)^2 W(theta_z)^2 with the kernel's own
@@ -189,4 +189,4 @@ def test_deconvolution_divides_by_the_squared_window(order):
     g1 = force.force_meshes(dec, delta, 1.0)
     th = 2 * np.pi * m0 / n
     W = np.prod(force.window_1d(th, order))
-    assert np.abs(g1 - g0 / (W * W)).max() < 1e-14 * np.abs(g1).max()
+    assert np.abs(g1 - g0 / (W * W)).max() < 1e-13 * np.abs(g1).max()   # FP64 rounding (PCS divides by 0.48)

@@ -11,7 +11,7 @@ def _rand_psi(n_p, seed, scale=1.5):
     return rng.normal(0.0, scale, (3, n_p ** 3))
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_bspline_moments(order):
     # partition of unity, first moment = position, and the sampled second
     # moment of the B-spline (TSC: 1/4 for every position; CIC: f (1 - f))
@@ -21,14 +21,17 @@ def test_bspline_moments(order):
     assert np.allclose(w.sum(0), 1.0, atol=1e-14)
     assert np.allclose((w * d).sum(0), 0.0, atol=1e-13)
     m2 = (w * d * d).sum(0)
-    if order == 3:
-        assert np.allclose(m2, 0.25, atol=1e-13)
+    if order >= 3:
+        # B-splines of order >= 3 sample their variance p/12 exactly
+        assert np.allclose(m2, order / 12.0, atol=1e-13)
+        if order == 4:
+            assert np.allclose((w * d ** 3).sum(0), 0.0, atol=1e-12)
     else:
         f = u - np.floor(u)
         assert np.allclose(m2, f * (1 - f), atol=1e-13)
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_scatter_gather_adjoint(order):
     # App. "Custom VJP and JVP": <scatter(w), rho> = <w, gather(rho)>
     n_p, n_g = 8, 16
@@ -41,7 +44,7 @@ def test_scatter_gather_adjoint(order):
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_gather_reproduces_linear_field(order):
     n_p, n_g = 8, 16
     psi = _rand_psi(n_p, 3, 0.3)
@@ -56,7 +59,7 @@ def test_gather_reproduces_linear_field(order):
     assert np.allclose(mesh.gather(np.full(n_g ** 3, 3.5), psi, n_p, n_g, order), 3.5)
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_grad_gather_matches_finite_differences(order):
     n_p, n_g = 4, 8
     psi = _rand_psi(n_p, 4)
@@ -72,7 +75,7 @@ def test_grad_gather_matches_finite_differences(order):
         assert np.allclose(g[a], fd, atol=1e-6)
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_fixedpoint_mass_and_float_agreement(order):
     n_p, n_g = 16, 32
     psi = _rand_psi(n_p, 6, 3.0).astype(np.float32)
@@ -86,7 +89,7 @@ def test_fixedpoint_mass_and_float_agreement(order):
     assert np.linalg.norm(fx / 2.0 ** 32 - fl) / np.linalg.norm(fl) < 4e-6
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_fixedpoint_per_particle_weights_sum_exactly(order):
     n_p, n_g = 8, 16
     psi = _rand_psi(n_p, 7, 2.0).astype(np.float32)
@@ -96,7 +99,7 @@ def test_fixedpoint_per_particle_weights_sum_exactly(order):
     assert np.all(W3 >= 0)
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_fixedpoint_boundary_cases(order):
     # exactly on mesh nodes, on CIC faces / TSC midpoints, and wrapping the box
     n_p, n_g = 4, 8
