@@ -75,7 +75,8 @@ enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
  *                  3D rms displacement at a_start in PM-mesh cells)
  *   a_start, a_end, n_steps   uniform steps in D between D(a_start), D(a_end)
  *   force          PM_FORCE_PM or PM_FORCE_NUFFT
- *   mak            2 = CIC, 3 = TSC (PM force; the final density and P(k) are
+ *   mak            2 = CIC, 3 = TSC, 4 = PCS with grad_order 2 or 4
+ *                  (tab. interpolation_kernels; PM force; the final density and P(k) are
  *                  always CIC)
  *   deconvolve     divide the PM multiplier by the squared window
  *   grad_order     0 exact i k (NUFFT only), 2/4/6 finite differences (PM)
@@ -263,9 +264,9 @@ pm_status pm_get_state(pm_ctx* ctx, float* disp, float* vel);
 pm_status pm_set_state(pm_ctx* ctx, const float* disp, const float* vel);
 
 /* Deposit the given displacements (device [B][3][N]) with kernel order
- * mak (2 CIC, 3 TSC, 6 = ES of the NUFFT grid) into the int64 mesh
- * mesh_out (device [B][n^3], n = n_g).  Bit-exact fixed-point spec: CIC and
- * TSC put 2^32 per particle; the ES spreading (Sec. "Force evaluation",
+ * mak (2 CIC, 3 TSC, 4 PCS in a PCS context, 6 = ES of the NUFFT grid) into
+ * the int64 mesh mesh_out (device [B][n^3], n = n_g).  Bit-exact fixed-point
+ * spec: CIC, TSC and PCS put 2^32 per particle; the ES spreading (Sec. "Force evaluation",
  * NUFFT paragraphs) puts floor(floor(w_x w_y / 2^17) w_z / 2^12) on each of
  * its 6^3 nodes from 20-bit 1D table weights, 2^31 at the kernel's peak.
  * This and the two hooks below load disp as the context's particle

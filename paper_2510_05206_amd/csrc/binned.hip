@@ -178,11 +178,11 @@ __global__ void __launch_bounds__(256) k_bin_scatter(BinArgs a) {
 
 template <int P>
 __global__ void __launch_bounds__(kPmDepositThreads) k_tile_deposit(TileArgs a) {
-  constexpr int NT = kPmDepositThreads;
-  __shared__ unsigned long long win[(kTileMax + 2) * (kTileMax + 2) * (kTileMax + 2)];
+  constexpr int NT = kPmDepositThreads, KR = kernel_reach<P>();
+  __shared__ unsigned long long win[(kTileMax + 2 * KR) * (kTileMax + 2 * KR) * (kTileMax + 2 * KR)];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!slot_on(a.g.gate, a.active, slot)) return;
-  const int T = a.T, W = T + 2, W3 = W * W * W;
+  const int T = a.T, W = T + 2 * KR, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   // the first particle's loads are in flight while the window is cleared;
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(kPmDepositThreads) k_tile_deposit(TileArgs a) 
       long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
       weights1d<P>(U, w[c]);
       // local index of the first stencil node in the window (home at h - o + 1)
-      l0[c] = home_node<P>(U, nm) - o[c] + 1 - (P == 3 ? 1 : 0);
+      l0[c] = home_node<P>(U, nm) - o[c] + KR + first_node<P>();
     }
     if (p + NT < end) {
       i = a.sorted[slot * N + p + NT];
@@ -382,14 +382,14 @@ __device__ __forceinline__ void tile_weights(const TileArgs& a, long long i, con
   for (int c = 0; c < 3; ++c) {
     long long U = fixed_coord(j[c], p[c], a.g.log2_r, umask);
     weights1d_f<P>(U, w[c], dw[c]);
-    l0[c] = home_node<P>(U, nm) - o[c] + R - (P == 3 ? 1 : 0);
+    l0[c] = home_node<P>(U, nm) - o[c] + R + first_node<P>();
   }
 }
 
 // forward: A = gather(FD phi); V = alpha V + beta A; X += tau V (or A only)
 template <int P, int ORD>
 __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
-  constexpr int R = 1 + ORD / 2;
+  constexpr int R = kernel_reach<P>() + ORD / 2;
   __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!slot_on(a.g.gate, a.active, slot)) return;
@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
 // max|u| reduced per slot (fixed-point scale of the scatter)
 template <int P, int ORD>
 __global__ void __launch_bounds__(256, 2) k_tile_adj_kick(TileArgs a) {  // <= 256 VGPRs (two workgroups per CU)
-  constexpr int R = 1 + ORD / 2;
+  constexpr int R = kernel_reach<P>() + ORD / 2;
   __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
   __shared__ float red[256];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -502,7 +502,7 @@ __global__ void k_dipole_scale(const unsigned int* umax_bits, double* scale, dou
 template <int P, int ORD>
 __global__ void __launch_bounds__(kPmDipoleThreads) k_tile_dipole(TileArgs a) {
   constexpr int NT = kPmDipoleThreads;
-  constexpr int H = ORD / 2, R = 1 + H, Q = P + 2 * H;
+  constexpr int H = ORD / 2, R = kernel_reach<P>() + H, Q = P + 2 * H;
   extern __shared__ unsigned long long dwin[];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
@@ -582,15 +582,15 @@ __global__ void __launch_bounds__(kPmDipoleThreads) k_tile_dipole(TileArgs a) {
 // reverse drift X -= tau V, V_bar += tau X_bar
 template <int P>
 __global__ void __launch_bounds__(256) k_tile_adj_drift(TileArgs a) {
-  constexpr int R = 1;
-  __shared__ float win[(kTileMax + 2) * (kTileMax + 2) * (kTileMax + 2)];
+  constexpr int R = kernel_reach<P>();
+  __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
   const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
   if (!((a.active >> slot) & 1ull)) return;
   int o[3];
   tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
   load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, R, a.g.log2_ng, a.g.n_g - 1);
   __syncthreads();
-  const int W = a.T + 2;
+  const int W = a.T + 2 * R;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
   const float cf = a.coef[slot] * (float)(1 << a.g.log2_r), tau = a.tau[slot];
@@ -631,7 +631,8 @@ __global__ void __launch_bounds__(256) k_tile_adj_drift(TileArgs a) {
 hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s) {
   dim3 grid((unsigned)((a.g.N + 255) / 256), a.batch);
   if (mak == 2) k_bin_count<2><<<grid, 256, 0, s>>>(a);
-  else k_bin_count<3><<<grid, 256, 0, s>>>(a);
+  else if (mak == 3) k_bin_count<3><<<grid, 256, 0, s>>>(a);
+  else k_bin_count<4><<<grid, 256, 0, s>>>(a);
   const int nb = (a.n_tiles + 1023) / 1024;
   if (nb > a.scan_np) return hipErrorInvalidValue;
   k_bin_scan_blocks<<<dim3((unsigned)nb, a.batch), 1024, 0, s>>>(a.count, a.offset, a.scan_partial, a.n_tiles, a.ts,
@@ -650,31 +651,45 @@ hipError_t launch_tile(const TileArgs& a, int kind, int mak, int ord, hipStream_
     else if (ord == 4) KER<P, 4><<<grid, 256, 0, s>>>(a);                     \
     else KER<P, 6><<<grid, 256, 0, s>>>(a);                                   \
   } while (0)
+  // PCS windows with the order-6 stencil would exceed a workgroup's static
+  // LDS: PCS runs with FD2 / FD4 (the context refuses FD6)
+#define PM_TILE_ORD4(KER)                                                     \
+  do {                                                                        \
+    if (ord == 2) KER<4, 2><<<grid, 256, 0, s>>>(a);                          \
+    else if (ord == 4) KER<4, 4><<<grid, 256, 0, s>>>(a);                     \
+    else return hipErrorInvalidValue;                                         \
+  } while (0)
   switch (kind) {
     case TK_DEPOSIT:
       if (mak == 2) k_tile_deposit<2><<<grid, kPmDepositThreads, 0, s>>>(a);
-      else k_tile_deposit<3><<<grid, kPmDepositThreads, 0, s>>>(a);
+      else if (mak == 3) k_tile_deposit<3><<<grid, kPmDepositThreads, 0, s>>>(a);
+      else k_tile_deposit<4><<<grid, kPmDepositThreads, 0, s>>>(a);
       break;
     case TK_KICK:
-      if (mak == 2) PM_TILE_ORD(k_tile_kick, 2); else PM_TILE_ORD(k_tile_kick, 3);
+      if (mak == 2) PM_TILE_ORD(k_tile_kick, 2); else if (mak == 3) PM_TILE_ORD(k_tile_kick, 3);
+      else PM_TILE_ORD4(k_tile_kick);
       break;
     case TK_ADJ_KICK:
-      if (mak == 2) PM_TILE_ORD(k_tile_adj_kick, 2); else PM_TILE_ORD(k_tile_adj_kick, 3);
+      if (mak == 2) PM_TILE_ORD(k_tile_adj_kick, 2); else if (mak == 3) PM_TILE_ORD(k_tile_adj_kick, 3);
+      else PM_TILE_ORD4(k_tile_adj_kick);
       break;
     case TK_ADJ_DRIFT:
       if (mak == 2) k_tile_adj_drift<2><<<grid, 256, 0, s>>>(a);
-      else k_tile_adj_drift<3><<<grid, 256, 0, s>>>(a);
+      else if (mak == 3) k_tile_adj_drift<3><<<grid, 256, 0, s>>>(a);
+      else k_tile_adj_drift<4><<<grid, 256, 0, s>>>(a);
       break;
     case TK_DIPOLE: {
-      int R = 1 + ord / 2, W = a.T + 2 * R;
+      int R = (mak == 4 ? 2 : 1) + ord / 2, W = a.T + 2 * R;
       size_t lds = (size_t)W * W * W * sizeof(unsigned long long);
-      // ORD 6 needs 110 KB of LDS: above the default dynamic limit (raised
-      // once by configure_tile_kernels)
+      // ORD 6 (and PCS with ORD 4) needs 110 KB of LDS: above the default
+      // dynamic limit (raised once by configure_tile_kernels)
 #define PM_DIPOLE(P, O) k_tile_dipole<P, O><<<grid, kPmDipoleThreads, lds, s>>>(a)
       if (mak == 2) {
         if (ord == 2) PM_DIPOLE(2, 2); else if (ord == 4) PM_DIPOLE(2, 4); else PM_DIPOLE(2, 6);
-      } else {
+      } else if (mak == 3) {
         if (ord == 2) PM_DIPOLE(3, 2); else if (ord == 4) PM_DIPOLE(3, 4); else PM_DIPOLE(3, 6);
+      } else {
+        if (ord == 2) PM_DIPOLE(4, 2); else if (ord == 4) PM_DIPOLE(4, 4); else return hipErrorInvalidValue;
       }
 #undef PM_DIPOLE
       break;
@@ -683,6 +698,7 @@ hipError_t launch_tile(const TileArgs& a, int kind, int mak, int ord, hipStream_
       return hipErrorInvalidValue;
   }
 #undef PM_TILE_ORD
+#undef PM_TILE_ORD4
   return hipGetLastError();
 }
 
@@ -1299,19 +1315,21 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
 hipError_t configure_tile_kernels() {
   constexpr int We = kTileMax + kEsLo + kEsHi;
   const int es64 = We * We * We * 8, es32 = kEsWinLds * 4;
-  auto dip = [](int o) { int W = kTileMax + 2 * (1 + o / 2); return W * W * W * 8; };
+  auto dip = [](int o, int kr) { int W = kTileMax + 2 * (kr + o / 2); return W * W * W * 8; };
   const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
   hipError_t e = hipSuccess;
   auto set = [&](const void* f, int bytes) {
     hipError_t r = hipFuncSetAttribute(f, A, bytes);
     if (e == hipSuccess) e = r;
   };
-  set((const void*)k_tile_dipole<2, 2>, dip(2));
-  set((const void*)k_tile_dipole<2, 4>, dip(4));
-  set((const void*)k_tile_dipole<2, 6>, dip(6));
-  set((const void*)k_tile_dipole<3, 2>, dip(2));
-  set((const void*)k_tile_dipole<3, 4>, dip(4));
-  set((const void*)k_tile_dipole<3, 6>, dip(6));
+  set((const void*)k_tile_dipole<2, 2>, dip(2, 1));
+  set((const void*)k_tile_dipole<2, 4>, dip(4, 1));
+  set((const void*)k_tile_dipole<2, 6>, dip(6, 1));
+  set((const void*)k_tile_dipole<3, 2>, dip(2, 1));
+  set((const void*)k_tile_dipole<3, 4>, dip(4, 1));
+  set((const void*)k_tile_dipole<3, 6>, dip(6, 1));
+  set((const void*)k_tile_dipole<4, 2>, dip(2, 2));
+  set((const void*)k_tile_dipole<4, 4>, dip(4, 2));
   set((const void*)k_tile_es_deposit, es64);
   set((const void*)k_tile_es_kick, es32);
   set((const void*)k_tile_es_adj_kick, es32);

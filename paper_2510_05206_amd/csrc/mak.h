@@ -19,11 +19,24 @@ __device__ __forceinline__ unsigned long long rne_shift(unsigned long long p, in
   return q + ((rem > half) || (rem == half && (q & 1ull)));
 }
 
-// home node of a particle on one axis (wrapped): CIC floor(u), TSC round(u)
+// home node of a particle on one axis (wrapped): CIC and PCS floor(u), TSC
+// round(u); the stencil runs from home + first_node to home + first_node + P - 1
+// and reaches kernel_reach nodes from the home node on either side
 template <int P>
 __device__ __forceinline__ int home_node(long long U, int nm) {
-  if constexpr (P == 2) return (int)(U >> kFracBits) & nm;
+  if constexpr (P == 2 || P == 4) return (int)(U >> kFracBits) & nm;
   else return (int)((U + (1ll << (kFracBits - 1))) >> kFracBits) & nm;
+}
+template <int P>
+constexpr int first_node() { return P == 2 ? 0 : -1; }
+template <int P>
+constexpr int kernel_reach() { return P == 4 ? 2 : 1; }
+
+// round-half-even of p / d for a compile-time divisor (the PCS weights)
+template <unsigned long long D>
+__device__ __forceinline__ unsigned long long rne_div(unsigned long long p) {
+  const unsigned long long q = p / D, rem = p - q * D;
+  return q + ((2 * rem > D) || (2 * rem == D && (q & 1ull)));
 }
 
 // integer 1D weights (sum 2^20); returns the first node, unwrapped
@@ -35,7 +48,7 @@ __device__ __forceinline__ int weights1d(long long U, int w[P]) {
     w[0] = (int)one - f;
     w[1] = f;
     return (int)(U >> kFracBits);
-  } else {
+  } else if constexpr (P == 3) {
     long long n = (U + (one >> 1)) >> kFracBits;
     long long X = U - (n << kFracBits);
     long long a = (one >> 1) - X, b = (one >> 1) + X;
@@ -45,6 +58,21 @@ __device__ __forceinline__ int weights1d(long long U, int w[P]) {
     w[1] = (1 << kWeightBits) - wl - wr;
     w[2] = wr;
     return (int)n - 1;
+  } else {
+    // PCS (cubic B-spline) at F = frac(u) 2^20, G = 2^20 - F: G^3/6, F^3/6 and
+    // (4 - 6f^2 + 3f^3)/6 rounded half-even from exact integers, the
+    // remaining node takes the rest of 2^20
+    static_assert(P == 4 && kWeightBits == kFracBits, "PCS weights in the position's fixed point");
+    const unsigned long long F = (unsigned long long)(U & (one - 1)), G = (unsigned long long)one - F;
+    constexpr unsigned long long D = 6ull << (2 * kFracBits);
+    const int wa = (int)rne_div<D>(G * G * G);
+    const int wd = (int)rne_div<D>(F * F * F);
+    const int wb = (int)rne_div<D>((4ull << (3 * kFracBits)) + 3 * F * F * F - 6 * F * F * (unsigned long long)one);
+    w[0] = wa;
+    w[1] = wb;
+    w[2] = (1 << kWeightBits) - wa - wb - wd;
+    w[3] = wd;
+    return (int)(U >> kFracBits) - 1;
   }
 }
 
@@ -59,13 +87,21 @@ __device__ __forceinline__ int weights1d_f(long long U, float w[P], float dw[P])
   if constexpr (P == 2) {
     dw[0] = -1.f;
     dw[1] = 1.f;
-  } else {
+  } else if constexpr (P == 3) {
     constexpr long long one = 1ll << kFracBits;
     long long n = (U + (one >> 1)) >> kFracBits;
     float x = (float)(U - (n << kFracBits)) * (1.0f / (float)one);
     dw[0] = -(0.5f - x);
     dw[1] = -2.f * x;
     dw[2] = 0.5f + x;
+  } else {
+    // d/du of the PCS weights at f = frac(u), g = 1 - f
+    constexpr long long one = 1ll << kFracBits;
+    const float f = (float)(U & (one - 1)) * (1.0f / (float)one), g = 1.f - f;
+    dw[0] = -0.5f * g * g;
+    dw[1] = f * (1.5f * f - 2.f);
+    dw[2] = g * (2.f - 1.5f * g);
+    dw[3] = 0.5f * f * f;
   }
   return i0;
 }

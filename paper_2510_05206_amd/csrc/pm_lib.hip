@@ -161,7 +161,8 @@ struct Layout {
 // tile edge (16 cells, or the whole mesh when smaller), and the window halo
 // of the adjoint's transposed FD gather (kernel reach 1 + FD reach)
 int tile_edge(int n) { return n < 16 ? n : 16; }
-int dipole_halo(int grad_order) { return 1 + grad_order / 2; }
+int kernel_reach_of(int mak) { return mak == 4 ? 2 : 1; }  // mass-assignment stencil reach (mak.h)
+int dipole_halo(int grad_order, int mak) { return kernel_reach_of(mak) + grad_order / 2; }
 // block totals of the tile-count scan (1024 tiles per block), padded
 int scan_np(long long n_tiles) { return (int)((n_tiles + 1023) / 1024 + 63) / 64 * 64; }
 
@@ -201,8 +202,8 @@ Layout layout(const pm_ctx* c, bool adj) {
   L.off_offset = take(sizeof(int32_t) * ts * B);
   L.off_scanp = take(sizeof(int32_t) * scan_np(n_tiles) * B);
   const bool nufft = c->cfg.force == PM_FORCE_NUFFT;
-  long long W = T + 2;
-  if (adj) W = std::max(W, (long long)T + 2 * dipole_halo(c->cfg.grad_order));
+  long long W = T + 2 * kernel_reach_of(c->cfg.mak);
+  if (adj) W = std::max(W, (long long)T + 2 * dipole_halo(c->cfg.grad_order, c->cfg.mak));
   if (nufft) W = std::max(W, (long long)T + kEsHaloLo + kEsHaloHi);
   L.off_es_tab = take(sizeof(int32_t) * c->es_tab.size());
   L.off_esdec = take(sizeof(float) * n);
@@ -504,7 +505,7 @@ pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* ta
   pm_status st = bin(c, disp, vel_pre, tau, mak, active);
   if (st) return st;
   TileArgs t = tile_args(c, disp, active);
-  AssembleArgs a = assemble_args(c, 1, 1, mesh, active);
+  AssembleArgs a = assemble_args(c, kernel_reach_of(mak), kernel_reach_of(mak), mesh, active);
   KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile(t, TK_DEPOSIT, mak, 0, c->stream), launch_assemble(a, false, c->stream)));
   return PM_OK;
 }
@@ -523,7 +524,7 @@ pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* 
   if (st) return st;
   TileArgs t = tile_args(c, disp, active);
   float* rho = reinterpret_cast<float*>(c->mesh);
-  AssembleArgs as = assemble_args(c, 1, 1, rho, active);
+  AssembleArgs as = assemble_args(c, kernel_reach_of(c->cfg.mak), kernel_reach_of(c->cfg.mak), rho, active);
   as.inv_scale = nullptr;
   as.scale = n3 / N / 4294967296.0;
   as.shift = 1.0;
@@ -765,7 +766,9 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
       c.batch > kMaxBatch || c.omega_m <= 0 || c.omega_m > 1)
     return PM_EINVAL;
   if (c.force == PM_FORCE_PM) {
-    if ((c.mak != 2 && c.mak != 3) || (c.grad_order != 2 && c.grad_order != 4 && c.grad_order != 6) ||
+    // PCS (mak 4) runs with FD2 / FD4: its FD6 windows would not fit a workgroup's LDS
+    if ((c.mak < 2 || c.mak > 4) || (c.grad_order != 2 && c.grad_order != 4 && c.grad_order != 6) ||
+        (c.mak == 4 && c.grad_order == 6) ||
         (c.lap_order != 0 && c.lap_order != 2 && c.lap_order != 4 && c.lap_order != 6))
       return PM_EINVAL;
   } else if (c.force == PM_FORCE_NUFFT) {
@@ -1400,7 +1403,7 @@ pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, co
                                             3.0 * fd_l1 * (double)N, fd_l1, B, c->stream));
   // transposed multiplier (H is real and even)
   float* d = reinterpret_cast<float*>(c->mesh);
-  AssembleArgs as = assemble_args(c, dipole_halo(ord), dipole_halo(ord), d, act);
+  AssembleArgs as = assemble_args(c, dipole_halo(ord, mak), dipole_halo(ord, mak), d, act);
   KLAUNCH(c, PM_K_DIPOLE, both(launch_tile(k, TK_DIPOLE, mak, ord, c->stream), launch_assemble(as, true, c->stream)));
   pm_status st = r2c_mesh(c, d, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
   if (st) return st;
@@ -1638,9 +1641,10 @@ pm_status pm_set_state(pm_ctx* c, const float* disp, const float* vel) {
 
 pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_out) {
   if (pm_status st = check_bound(c)) return st;
-  if (!disp || !mesh_out || (mak != 2 && mak != 3 && mak != 6)) return PM_EINVAL;
+  if (!disp || !mesh_out || (mak != 2 && mak != 3 && mak != 4 && mak != 6)) return PM_EINVAL;
   if (mak == 6 && c->cfg.force != PM_FORCE_NUFFT)
     return fail(c, PM_EINVAL, "ES spreading needs a NUFFT context");
+  if (mak == 4 && c->cfg.mak != 4) return fail(c, PM_EINVAL, "the PCS deposit needs a PCS context (its windows)");
   if (pm_status st = from_user_order(c, disp, c->disp)) return st;  // the hooks use the particle state
   float* x = c->disp;
   const unsigned long long act = all_mask(c->cfg.batch);

@@ -37,7 +37,9 @@ def _create(lib, **kw):
 
 
 @pytest.mark.parametrize("bad", [dict(n_p=24), dict(n_g=16, n_p=32), dict(n_g=512, n_p=32),
-                                 dict(n_steps=0), dict(batch=0), dict(batch=65), dict(mak=4),
+                                 dict(n_steps=0), dict(batch=0), dict(batch=65), dict(mak=5),
+                                 dict(mak=4, grad_order=6), dict(lpt_order=3), dict(lpt_order=2, n_p=32, n_g=32),
+                                 dict(stepper="fastpm", time_var="a", n_steps=0),
                                  dict(grad_order=3), dict(a_end=0.01), dict(box=-1.0)])
 def test_invalid_configs_are_rejected(lib, bad):
     st, ctx = _create(lib, **bad)
