@@ -32,6 +32,8 @@ def force_vjp(cfg: PMConfig, psi, s, u, parts=3):
     """J_A(Psi)^T u for the PM force A(Psi) of ``force.pm_force``; u (3, N).
     parts: 1 the direct term (gather w.r.t. positions) only, 2 the terms
     through the mesh only, 3 both."""
+    if cfg.interlace:
+        raise NotImplementedError("the VJP covers the single-grid force")
     n, N = cfg.n_g, cfg.N
     delta = mesh.contrast(mesh.deposit(psi, cfg.n_p, n, cfg.order), N, n)
     dk = np.fft.rfftn(delta.reshape(n, n, n))

@@ -34,10 +34,11 @@ class PMConfig:
     n_p: int
     n_g: int
     box: float
-    order: int = 2          # 2 CIC, 3 TSC
+    order: int = 2          # 2 CIC, 3 TSC, 4 PCS
     deconvolve: bool = False
     grad_order: int = 4     # 0 exact i k, else 2/4/6
     lap_order: int = 0      # 0 exact -k^2, else 2/4/6
+    interlace: bool = False # antialias = 1: a second grid half a cell along the diagonal
 
     @property
     def N(self):
@@ -129,13 +130,45 @@ def force_meshes(cfg: PMConfig, delta, s):
     return np.stack([np.fft.irfftn(K[c] * dk, s=(n, n, n), axes=(0, 1, 2)).reshape(-1) for c in range(3)])
 
 
+def interlace_phase(n):
+    """exp(i (theta_x + theta_y + theta_z) / 2) on the half spectrum: the
+    transform of a mesh sampled half a cell down the diagonal, times this,
+    is the transform of the same density on the original nodes."""
+    tx, ty, tz, _ = half_spectrum_theta(n)
+    return np.exp(0.5j * (tx + ty + tz))
+
+
 def pm_force_u(cfg: PMConfig, u, s):
     """A in dq units per unit D at mesh coordinates u (3, M) of M particles of
     mass 1 (the contrast is normalised by cfg.N; the k = 0 mode is removed,
-    which is the uniform neutralising background)."""
-    m = mesh.deposit_u(u, cfg.n_g, cfg.order)
-    g = force_meshes(cfg, mesh.contrast(m, cfg.N, cfg.n_g), s)
-    return np.stack([mesh.gather_u(g[c], u, cfg.n_g, cfg.order) for c in range(3)])
+    which is the uniform neutralising background).
+
+    Interlaced grids (Sec. "Discreteness suppression", antialias = 1 of
+    tab. default_parameters; the paper cites Chen 1974, Hockney & Eastwood
+    and Sefusatti et al. 2016 for the scheme): the particles are deposited
+    a second time at u + (1/2, 1/2, 1/2), i.e. onto nodes half a cell down
+    the diagonal; the two transforms are averaged with the shift's phase,
+    delta = (delta_1 + e^{i phi} delta_2) / 2, phi = (theta_x + theta_y +
+    theta_z) / 2, which cancels the aliases of odd total image order; the
+    force meshes are evaluated on both grids (the second with e^{-i phi})
+    and the two gathers averaged."""
+    n = cfg.n_g
+    if not cfg.interlace:
+        m = mesh.deposit_u(u, cfg.n_g, cfg.order)
+        g = force_meshes(cfg, mesh.contrast(m, cfg.N, cfg.n_g), s)
+        return np.stack([mesh.gather_u(g[c], u, cfg.n_g, cfg.order) for c in range(3)])
+    u2 = np.mod(np.asarray(u, dtype=np.float64) + 0.5, n)
+    d1 = np.fft.rfftn(mesh.contrast(mesh.deposit_u(u, n, cfg.order), cfg.N, n).reshape(n, n, n))
+    d2 = np.fft.rfftn(mesh.contrast(mesh.deposit_u(u2, n, cfg.order), cfg.N, n).reshape(n, n, n))
+    ph = interlace_phase(n)
+    dk = 0.5 * (d1 + ph * d2)
+    K = force_multipliers(cfg, s)
+    A = np.zeros((3, np.asarray(u).shape[1]))
+    for c in range(3):
+        g1 = np.fft.irfftn(K[c] * dk, s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
+        g2 = np.fft.irfftn(K[c] * dk * np.conj(ph), s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
+        A[c] = 0.5 * (mesh.gather_u(g1, u, n, cfg.order) + mesh.gather_u(g2, u2, n, cfg.order))
+    return A
 
 
 def pm_force(cfg: PMConfig, psi, s):

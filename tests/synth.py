@@ -38,7 +38,7 @@ def oracle_problem(d, **kw):
         extra = dict(force="nufft", es_width=d["es_width"], es_beta=d["es_beta"])
     pm = PMConfig(d["n_p"], d["n_g"], d["box"], order=d.get("mak", 2),
                   deconvolve=d.get("deconvolve", False), grad_order=d.get("grad_order", 4),
-                  lap_order=d.get("lap_order", 0))
+                  lap_order=d.get("lap_order", 0), interlace=bool(d.get("antialias", 0)))
     return Problem(pm, omega_m=d.get("omega_m", 0.31), h=d.get("h", 0.68), n_s=d.get("n_s", 0.965),
                    sigma8=d.get("sigma8", 0.81), spectrum=d.get("spectrum", "bbks"),
                    rms_cells=d.get("pl_rms_cells", 0.2), a_start=d.get("a_start", 0.02),

@@ -190,3 +190,72 @@ def test_deconvolution_divides_by_the_squared_window(order):
     th = 2 * np.pi * m0 / n
     W = np.prod(force.window_1d(th, order))
     assert np.abs(g1 - g0 / (W * W)).max() < 1e-13 * np.abs(g1).max()   # FP64 rounding (PCS divides by 0.48)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_interlaced_deposit_keeps_only_even_images(order):
+    # one particle: the phase-averaged spectrum of the two grids equals the
+    # sum of the aliased window images W(theta + 2 pi a) e^{-i(theta + 2 pi a).u}
+    # over the images whose total order a_x + a_y + a_z is even (the odd ones
+    # cancel), per mode, to the truncation of the image sums
+    n = 8
+    rng = np.random.default_rng(3 + order)
+    u = rng.uniform(0, n, 3)
+    r1 = mesh.deposit_u(u[:, None], n, order).reshape(n, n, n)
+    r2 = mesh.deposit_u(np.mod(u + 0.5, n)[:, None], n, order).reshape(n, n, n)
+    got = 0.5 * (np.fft.rfftn(r1) + force.interlace_phase(n) * np.fft.rfftn(r2))
+    tx, ty, tz, _ = force.half_spectrum_theta(n)
+    img = np.arange(-400, 401)
+    even = np.zeros_like(got)
+    odd_free = np.zeros_like(got)
+    per_axis = []
+    for c, th in enumerate((tx, ty, tz)):
+        t = th[..., None] + 2 * np.pi * img
+        e = force.window_1d(t, order) * np.exp(-1j * t * u[c])
+        per_axis.append((np.sum(e, axis=-1), np.sum(e * (-1.0) ** img, axis=-1)))
+    # product over axes of (S + S_alt)/2 combinations: even total parity
+    # = (prod S + prod S_alt) / 2
+    even = 0.5 * (per_axis[0][0] * per_axis[1][0] * per_axis[2][0]
+                  + per_axis[0][1] * per_axis[1][1] * per_axis[2][1])
+    tol = 3e-6 if order == 2 else 1e-8
+    assert np.abs(got - even).max() < tol
+    # and it differs from the plain deposit by the odd images
+    assert np.abs(np.fft.rfftn(r1) - even).max() > 1e-3
+
+
+def _band_force(n_p, n_g, psi, s):
+    """The force of the exact particle density restricted to the mesh band
+    |m_a| < n_g/2 (direct sums, exact i k and -k^2, no window): what a PM
+    force without aliasing would give."""
+    u = mesh.mesh_coords(psi, n_p, n_g)
+    ms = np.arange(-(n_g // 2) + 1, n_g // 2)
+    mx, my, mz = [a.reshape(-1) for a in np.meshgrid(ms, ms, ms, indexing="ij")]
+    E = np.exp(-2j * np.pi / n_g * (np.outer(mx, u[0]) + np.outer(my, u[1]) + np.outer(mz, u[2])))
+    d = E.sum(axis=1) * (n_g ** 3 / psi.shape[1])
+    th = [2 * np.pi * m / n_g for m in (mx, my, mz)]
+    t2 = th[0] ** 2 + th[1] ** 2 + th[2] ** 2
+    z = t2 == 0
+    K = [np.where(z, 0, 1j * th[c] * s / ((n_g // n_p) * np.where(z, 1, t2))) for c in range(3)]
+    return np.stack([np.real((K[c] * d) @ np.conj(E)) / n_g ** 3 for c in range(3)])
+
+
+def test_interlaced_force_symmetries_and_aliasing():
+    # zero force on the lattice and zero net force; against the alias-free
+    # band-limited force of the same particles, interlacing (which cancels
+    # the odd images) cuts the error of the deconvolved PM force about 3x
+    n_p = 8
+    for interlace in (False, True):
+        cfg = PMConfig(n_p, 2 * n_p, 16.0, order=2, deconvolve=True, grad_order=0, lap_order=0, interlace=interlace)
+        assert np.abs(force.pm_force(cfg, np.zeros((3, n_p ** 3)), 1.0)).max() < 1e-12
+    rng = np.random.default_rng(9)
+    psi = rng.normal(0, 0.6, (3, n_p ** 3))
+    exact = _band_force(n_p, 2 * n_p, psi, 1.0)
+    for order in (2, 3):
+        errs = []
+        for interlace in (False, True):
+            cfg = PMConfig(n_p, 2 * n_p, 16.0, order=order, deconvolve=True, grad_order=0, lap_order=0,
+                           interlace=interlace)
+            a = force.pm_force(cfg, psi, 1.0)
+            assert np.abs(a.sum(axis=1)).max() < 1e-10 * np.abs(a).sum()
+            errs.append(np.linalg.norm(a - exact) / np.linalg.norm(exact))
+        assert errs[1] < 0.5 * errs[0], errs
