@@ -92,6 +92,13 @@ enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
  *                  PM_EUNSUPPORTED
  *   stepper        0 BullFrog; 1 FastPM (Sec. "Time stepping")
  *   time_var       step spacing: 0 uniform in D, 1 in a, 2 in ln a
+ *   antialias      1: interlaced grids for the PM force (Sec. "Discreteness
+ *                  suppression"; antialias of tab. default_parameters), a
+ *                  second deposit half a cell down the diagonal, the two
+ *                  spectra averaged with the shift's phase and the two
+ *                  gathers averaged; PM force with n_g >= 16 only;
+ *                  pm_adjoint, pm_force_vjp and the device-indexed steps
+ *                  return PM_EUNSUPPORTED for it
  */
 typedef struct {
   int32_t n_p, n_g;
@@ -108,6 +115,7 @@ typedef struct {
   int32_t lpt_order;
   int32_t stepper;
   int32_t time_var;
+  int32_t antialias;
 } pm_config;
 
 /* Lifecycle ------------------------------------------------------------- */

@@ -35,7 +35,7 @@ class pm_config(C.Structure):
         ("es_width", C.c_int32),
         ("es_beta", C.c_double),
         ("batch", C.c_int32),
-        ("lpt_order", C.c_int32), ("stepper", C.c_int32), ("time_var", C.c_int32),
+        ("lpt_order", C.c_int32), ("stepper", C.c_int32), ("time_var", C.c_int32), ("antialias", C.c_int32),
     ]
 
 

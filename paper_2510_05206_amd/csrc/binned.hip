@@ -77,7 +77,8 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
     const int nm = a.g.n_g - 1;
     int h[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) h[c] = (home_node<P>(fixed_coord(j[c], p[c], a.g.log2_r, umask), nm) - a.home_shift) & nm;
+    for (int c = 0; c < 3; ++c)
+      h[c] = (home_node<P>((fixed_coord(j[c], p[c], a.g.log2_r, umask) + a.g.ushift) & umask, nm) - a.home_shift) & nm;
     tile = (((h[0] >> a.log2T) << a.log2nt | (h[1] >> a.log2T)) << a.log2nt) | (h[2] >> a.log2T);
   }
   // wave-aggregated counting: one atomic per distinct tile in the wave
@@ -208,7 +209,7 @@ __global__ void __launch_bounds__(kPmDepositThreads) k_tile_deposit(TileArgs a) 
     int w[3][P], l0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
+      long long U = (fixed_coord(j[c], x[c], a.g.log2_r, umask) + a.g.ushift) & umask;
       weights1d<P>(U, w[c]);
       // local index of the first stencil node in the window (home at h - o + 1)
       l0[c] = home_node<P>(U, nm) - o[c] + KR + first_node<P>();
@@ -380,7 +381,7 @@ __device__ __forceinline__ void tile_weights(const TileArgs& a, long long i, con
   const int nm = a.g.n_g - 1;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    long long U = fixed_coord(j[c], p[c], a.g.log2_r, umask);
+    long long U = (fixed_coord(j[c], p[c], a.g.log2_r, umask) + a.g.ushift) & umask;
     weights1d_f<P>(U, w[c], dw[c]);
     l0[c] = home_node<P>(U, nm) - o[c] + R + first_node<P>();
   }
@@ -410,6 +411,10 @@ __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
     int l0[3];
     tile_weights<P>(a, i, x, o, R, w, dw, l0);
     fd_gather<P, ORD, false>(acc, l0, w, dw, A, dA);
+    if (a.acc_in) {  // interlaced grids: the mean of the two gathers
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A[c] = 0.5f * (A[c] + a.acc_in[ps + c * N + i]);
+    }
     if (a.acc_out) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.acc_out[ps + c * N + i] = A[c];

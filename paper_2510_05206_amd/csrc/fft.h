@@ -12,7 +12,7 @@ enum { SRC_I64 = 0, SRC_F32 = 1 };
 // lattice points (even nodes) to the state
 enum { DST_F32 = 0, DST_IC = 1, DST_MU_AB = 2, DST_MU_ACC = 3, DST_MU_SQ = 4, DST_IC2 = 5 };
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4, MODE_NUFFT_C = 5,
-       MODE_NUFFT_ADJ = 6, MODE_LPT_D = 7 };
+       MODE_NUFFT_ADJ = 6, MODE_LPT_D = 7, MODE_FUSED_IL = 8 };
 
 // z-row pass: real rows of n <-> half-spectrum rows of n/2+1
 struct RowLaunch {
@@ -50,6 +50,11 @@ struct ColArgs {
   const float2* tw;
   int tws;             // Lmax / n
   // PM multiplier H = coef / ((lap[ix]+lap[iy]+lap[iz]) win2[ix] win2[iy] win2[iz]), 0 at k = 0
+  // (MODE_FUSED_IL, interlaced grids: the x pass of grid 1 averages its
+  // spectrum with the x-transformed spectrum of grid 2 in src3, phase
+  // e^{i phi}, phi = (theta_x + theta_y + theta_z)/2, applies H, writes
+  // H delta e^{-i phi} to dst3 (the same array) for grid 2 and inverts x for
+  // grid 1)
   const float* lap;
   const float* win2;
   float coef[kMaxBatch];

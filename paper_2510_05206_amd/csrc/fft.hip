@@ -370,7 +370,11 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
   for (int q = 0; q < NK; ++q) {
     const int k = n1 + P * q;
     if (k > L / 2) continue;
-    const float2 xk = xks[q], xm = xms[q];
+    float2 xk = xks[q], xm = xms[q];
+    // a real row takes the real parts of its k = 0 and k = n/2 coefficients
+    // (zero imaginary parts for a Hermitian spectrum; interlaced grids'
+    // phase leaves them nonzero on those planes)
+    if (k == 0) xk.y = xm.y = 0.f;
     const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);
     const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
     float2 w = tw[k * tws_full];
@@ -509,8 +513,8 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
     }
     v[r] = x;
   }
-  constexpr bool kFwdFirst =
-      MODE == MODE_FWD || MODE == MODE_FUSED_H || MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ;
+  constexpr bool kFwdFirst = MODE == MODE_FWD || MODE == MODE_FUSED_H || MODE == MODE_NUFFT_C ||
+                             MODE == MODE_NUFFT_ADJ || MODE == MODE_FUSED_IL;
   bool inverse_next = !kFwdFirst;  // input layout holds data for an inverse transform
   if constexpr (kFwdFirst) {
     freg::pass_a<S, false>(v, n1, a.tw, a.tws);
@@ -526,6 +530,27 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
         float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : fused_coef(a, slot) / (l * w);
         v[r].x *= h;
         v[r].y *= h;
+      }
+      inverse_next = true;
+    }
+    if constexpr (MODE == MODE_FUSED_IL) {
+      const float inv_n = 1.f / (float)a.n;  // phi = pi (m_x + m_y + m_z) / n
+#pragma unroll
+      for (int r = 0; r < S::E; ++r) {
+        const int t = S::t_out(n1, r);
+        float l = a.lap[t] + a.lap[outer] + (valid ? a.lap[iz] : 0.f);
+        float w = a.win2[t] * a.win2[outer] * (valid ? a.win2[iz] : 1.f);
+        float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : fused_coef(a, slot) / (l * w);
+        float2 d2 = make_float2(0.f, 0.f);
+        float cs = 1.f, sn = 0.f;
+        if (valid) {
+          d2 = a.src3[col + t * stride_t];
+          sincospif((float)(signed_mode(t, a.n) + signed_mode(outer, a.n) + iz) * inv_n, &sn, &cs);
+        }
+        // delta = (d1 + e^{i phi} d2) / 2; grid 1 keeps H delta, grid 2 gets H delta e^{-i phi}
+        const float dr = 0.5f * (v[r].x + cs * d2.x - sn * d2.y), di = 0.5f * (v[r].y + cs * d2.y + sn * d2.x);
+        v[r] = make_float2(h * dr, h * di);
+        if (valid) a.dst3[col + t * stride_t] = make_float2(h * (cs * dr + sn * di), h * (cs * di - sn * dr));
       }
       inverse_next = true;
     }
@@ -678,6 +703,7 @@ static hipError_t launch_cols_r(const ColArgs& a, int mode, int batch, hipStream
     case MODE_NUFFT_C: k_cols_reg<L, C, MODE_NUFFT_C><<<grid, 256, 0, s>>>(a); break;
     case MODE_NUFFT_ADJ: k_cols_reg<L, C, MODE_NUFFT_ADJ><<<grid, 256, 0, s>>>(a); break;
     case MODE_LPT_D: k_cols_reg<L, C, MODE_LPT_D><<<grid, 256, 0, s>>>(a); break;
+    case MODE_FUSED_IL: k_cols_reg<L, C, MODE_FUSED_IL><<<grid, 256, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -692,7 +718,8 @@ static hipError_t launch_cols(const ColArgs& a, int mode, int batch, hipStream_t
     return launch_cols_r<L, C>(a, mode, batch, s);
   } else {
     // the NUFFT passes and pruning exist only in the register kernels
-    if (mode == MODE_NUFFT_C || mode == MODE_NUFFT_ADJ || mode == MODE_LPT_D || a.keep || a.zlim)
+    if (mode == MODE_NUFFT_C || mode == MODE_NUFFT_ADJ || mode == MODE_LPT_D || mode == MODE_FUSED_IL || a.keep ||
+        a.zlim)
       return hipErrorInvalidValue;
     return launch_cols_c<L, 16>(a, mode, batch, s);
   }

@@ -42,6 +42,7 @@ struct TileArgs {
   const float* mesh_in;    // potential (kicks) or mesh cotangent (adjoint drift)
   void* scratch;           // window slab [B][n_tiles][W^3] int64
   float* acc_out;          // force-only output
+  const float* acc_in;     // interlaced grids: the other grid's forces, averaged in the kick
   float* u_sorted;         // [B][3][N] u = beta V_bar in sorted order
   float* umax;             // [B] max |u| (as uint bits)
   const double* scale;     // [B] fixed-point scale of the cotangent scatter

@@ -71,6 +71,9 @@ struct Geom {
   const int32_t* gate;
   const float* sched;
   int sched_steps;
+  // interlaced grids: added to every fixed-point mesh coordinate of the PM
+  // tile kernels (half a cell, 2^19, for the second grid; 0 otherwise)
+  long long ushift;
 };
 
 // fields of one device schedule row (the same floats the by-value path passes)

@@ -48,7 +48,9 @@ struct pm_ctx {
   hipGraphExec_t step_exec = nullptr;
   unsigned long long bind_gen = 0, step_bind_gen = 0;
   float* force3 = nullptr;           // NUFFT: 3 force meshes [B][3][M]
-  float2* spec2 = nullptr;           // NUFFT: per-component spectrum
+  float2* spec2 = nullptr;           // NUFFT: per-component spectrum; interlaced PM: the second grid's
+  float* accbuf = nullptr;           // interlaced PM: the second grid's forces [B][3][N]
+  float* phi2 = nullptr;             // interlaced PM: the second grid's potential (in the mesh buffer)
   float *disp = nullptr, *vel = nullptr, *w = nullptr, *xbar = nullptr, *vbar = nullptr;
   long long* mesh = nullptr;
   float2* spec = nullptr;
@@ -153,7 +155,7 @@ struct Layout {
   size_t off_disp, off_vel, off_w, off_xbar, off_vbar;
   size_t off_mesh, off_spec, off_phi, off_icspec, off_pk, off_dot;
   size_t off_key, off_rank, off_sorted, off_count, off_offset, off_scanp, off_scratch, off_u, off_umax, off_scale;
-  size_t off_tdots;
+  size_t off_tdots, off_accbuf;
   size_t off_es_tab, off_esdec, off_force3, off_spec2, off_lptkeep, off_gate, off_gsteps, off_sched;
   size_t total;
 };
@@ -212,7 +214,8 @@ Layout layout(const pm_ctx* c, bool adj) {
   L.off_gsteps = take(sizeof(int32_t) * kMaxBatch);
   L.off_sched = take(sizeof(float) * kSch * (size_t)kMaxSchedSteps * B);  // fixed: memory independent of n_steps
   L.off_force3 = nufft ? take(sizeof(float) * 3 * M * B) : 0;
-  L.off_spec2 = nufft ? take(sizeof(float2) * spec_elems(n) * B) : 0;
+  L.off_spec2 = (nufft || c->cfg.antialias) ? take(sizeof(float2) * spec_elems(n) * B) : 0;
+  L.off_accbuf = c->cfg.antialias ? take(sizeof(float) * 3 * N * B) : 0;
   L.off_scratch = take(sizeof(long long) * W * W * W * n_tiles * B);
   L.off_u = adj ? take(sizeof(float) * 3 * N * B) : 0;
   L.off_umax = take(sizeof(float) * kMaxBatch);
@@ -432,6 +435,8 @@ pm_status poisson_to_real(pm_ctx* c, const double* s, float* out, unsigned long 
 // deposit of `disp` (optionally drifting by tau first) into the int64 mesh
 // counting sort of the particles of `disp` by the tile of their home node
 // (optionally drifting them by tau first); fills key/rank/sorted/offset
+TileArgs tile_args(pm_ctx* c, float* disp, unsigned long long active);
+
 pm_status bin(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, int mak,
               unsigned long long active, int home_shift = 0) {
   KLAUNCH(c, PM_K_FILL, launch_fill(c->count, (long long)sizeof(int32_t) * c->ts * c->cfg.batch, c->stream));
@@ -515,9 +520,13 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
 
 // potential phi of the positions `disp` for the midpoint normalisation s
 // (NUFFT: the three force meshes)
+pm_status potential_interlaced(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
+                               unsigned long long active);
+
 pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
                     unsigned long long active) {
   if (c->cfg.force == PM_FORCE_NUFFT) return nufft_meshes(c, disp, vel_pre, tau, s, active);
+  if (c->cfg.antialias) return potential_interlaced(c, disp, vel_pre, tau, s, active);
   const double N = (double)c->g.N, n3 = (double)c->g.M;
   // the halo sum of the int64 windows writes the FP32 contrast directly
   pm_status st = bin(c, disp, vel_pre, tau, c->cfg.mak, active);
@@ -532,6 +541,91 @@ pm_status potential(pm_ctx* c, float* disp, const float* vel_pre, const double* 
   st = r2c_mesh(c, rho, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, active);
   if (st) return st;
   return poisson_to_real(c, s, c->phi, active);
+}
+
+// x pass, y inverse and C2R of a half spectrum after its y pass (the plain
+// PM multiplier: mode MODE_FUSED_H; interlaced: MODE_FUSED_IL with the second
+// grid's x-transformed spectrum in `other`; MODE_INV: inverse only)
+pm_status spectrum_to_real(pm_ctx* c, float2* spec, int mode, const double* s, float2* other, float* out,
+                           unsigned long long active) {
+  const int n = c->cfg.n_g;
+  ColArgs a{};
+  a.data = spec;
+  a.slot_stride = c->g.spec_stride;
+  a.n = n;
+  a.nh = n / 2 + 1;
+  a.rs = spec_rs(n);
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / n;
+  a.lap = c->d_lap;
+  a.win2 = c->d_win2;
+  a.active = active;
+  a.src3 = other;
+  a.dst3 = other;
+  const double r = (double)(1 << c->g.log2_r);
+  const double n3 = (double)n * n * n;
+  for (int b = 0; b < c->cfg.batch; ++b) a.coef[b] = s ? (float)(-s[b] / (r * n3)) : 0.f;
+  a.axis = 0;
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, mode, c->cfg.batch, c->stream));
+  a.axis = 1;
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_INV, c->cfg.batch, c->stream));
+  RowLaunch rl{};
+  rl.n = n;
+  rl.rs = spec_rs(n);
+  rl.n_rows = (long long)n * n;
+  rl.batch = c->cfg.batch;
+  rl.inverse = true;
+  rl.dst_mode = DST_F32;
+  rl.src = spec;
+  rl.src_stride = c->g.spec_stride;
+  rl.dst = out;
+  rl.dst_stride = c->g.mesh_stride;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (n / 2);
+  rl.tws_full = c->Lmax / n;
+  rl.scale = 1.0;
+  rl.stream = c->stream;
+  rl.active = active;
+  KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
+  return PM_OK;
+}
+
+// Interlaced grids (antialias 1): the contrast of the particles and of the
+// particles half a cell up the diagonal (fixed-point coordinate + 2^19 on
+// every axis; the second grid's nodes sit half a cell down the diagonal),
+// both transformed; the x pass of grid 1 forms (d1 + e^{i phi} d2)/2, applies
+// the multiplier and hands H delta e^{-i phi} to grid 2; each grid's inverse
+// gives its potential (phi on c->phi, the second in the mesh buffer behind
+// the first grid's contrast).  The binning left behind is grid 2's.
+pm_status potential_interlaced(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
+                               unsigned long long active) {
+  const double N = (double)c->g.N, n3 = (double)c->g.M;
+  const int kr = kernel_reach_of(c->cfg.mak);
+  float* rho1 = reinterpret_cast<float*>(c->mesh);
+  float* rho2 = rho1 + (long long)c->cfg.batch * c->g.M;
+  for (int grid = 0; grid < 2; ++grid) {
+    c->g.ushift = grid ? (1ll << (kFracBits - 1)) : 0;
+    pm_status st = grid ? bin(c, disp, nullptr, nullptr, c->cfg.mak, active)
+                        : bin(c, disp, vel_pre, tau, c->cfg.mak, active);
+    if (st) { c->g.ushift = 0; return st; }
+    TileArgs t = tile_args(c, disp, active);
+    AssembleArgs as = assemble_args(c, kr, kr, grid ? rho2 : rho1, active);
+    as.inv_scale = nullptr;
+    as.scale = n3 / N / 4294967296.0;
+    as.shift = 1.0;
+    KLAUNCH(c, PM_K_DEPOSIT,
+            both(launch_tile(t, TK_DEPOSIT, c->cfg.mak, 0, c->stream), launch_assemble(as, true, c->stream)));
+    c->g.ushift = 0;
+  }
+  pm_status st = r2c_mesh(c, rho1, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false,
+                          active);
+  if (st) return st;
+  st = r2c_mesh(c, rho2, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec2, c->g.spec_stride, c->cfg.n_g, true, active);
+  if (st) return st;
+  st = spectrum_to_real(c, c->spec, MODE_FUSED_IL, s, c->spec2, c->phi, active);
+  if (st) return st;
+  c->phi2 = rho2;
+  return spectrum_to_real(c, c->spec2, MODE_INV, nullptr, nullptr, c->phi2, active);
 }
 
 // NUFFT force meshes: ES spreading (type 1) -> R2C -> truncate, deconvolve,
@@ -621,6 +715,19 @@ pm_status kick(pm_ctx* c, float* disp, const double* alpha, const double* beta, 
     a.comp_stride = c->g.M;
     a.es_tab = c->d_es_tab;
     KLAUNCH(c, PM_K_GATHER_KICK, launch_tile_es(a, TK_ES_KICK, c->stream));
+  } else if (c->cfg.antialias) {
+    // grid 2 first, on its binning (the current one): its forces alone
+    c->g.ushift = 1ll << (kFracBits - 1);
+    TileArgs a2 = tile_args(c, disp, active);
+    c->g.ushift = 0;
+    a2.mesh_in = c->phi2;
+    a2.acc_out = c->accbuf;
+    KLAUNCH(c, PM_K_GATHER_KICK, launch_tile(a2, TK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
+    // grid 1 on the particles' own binning: the mean of the two gathers kicks
+    if (pm_status st = bin(c, disp, nullptr, nullptr, c->cfg.mak, active)) return st;
+    a.mesh_in = c->phi;
+    a.acc_in = c->accbuf;
+    KLAUNCH(c, PM_K_GATHER_KICK, launch_tile(a, TK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
   } else {
     a.mesh_in = c->phi;
     KLAUNCH(c, PM_K_GATHER_KICK, launch_tile(a, TK_KICK, c->cfg.mak, c->cfg.grad_order, c->stream));
@@ -787,6 +894,8 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
   if (c.lpt_order < 0 || c.lpt_order > 2 || (c.lpt_order == 2 && (c.n_g < 2 * c.n_p || c.n_p < 8)))
     return PM_EINVAL;
   if (c.stepper < 0 || c.stepper > 1 || c.time_var < 0 || c.time_var > 2) return PM_EINVAL;
+  if (c.antialias < 0 || c.antialias > 1 || (c.antialias && (c.force != PM_FORCE_PM || c.n_g < 16)))
+    return PM_EINVAL;
   pm_ctx* ctx = new (std::nothrow) pm_ctx();
   if (!ctx) return PM_ENOMEM;
   ctx->cfg = c;
@@ -859,7 +968,8 @@ pm_status pm_bind(pm_ctx* c, void* workspace, size_t bytes, int32_t with_adjoint
   c->sched_dirty.assign(B, 1);
   ++c->bind_gen;
   c->force3 = c->cfg.force == PM_FORCE_NUFFT ? (float*)(ws + L.off_force3) : nullptr;
-  c->spec2 = c->cfg.force == PM_FORCE_NUFFT ? (float2*)(ws + L.off_spec2) : nullptr;
+  c->spec2 = (c->cfg.force == PM_FORCE_NUFFT || c->cfg.antialias) ? (float2*)(ws + L.off_spec2) : nullptr;
+  c->accbuf = c->cfg.antialias ? (float*)(ws + L.off_accbuf) : nullptr;
   c->umax = (float*)(ws + L.off_umax);
   c->scale = (double*)(ws + L.off_scale);
   c->inv_scale = c->scale + kMaxBatch;
@@ -1093,6 +1203,7 @@ static pm_status device_steps_ok(pm_ctx* c) {
   if (c->cfg.force != PM_FORCE_PM)
     return fail(c, PM_EUNSUPPORTED, "device-indexed steps cover the PM force");
   if (c->cfg.n_steps > kMaxSchedSteps) return fail(c, PM_EUNSUPPORTED, "device schedules hold at most 96 steps");
+  if (c->cfg.antialias) return fail(c, PM_EUNSUPPORTED, "device-indexed steps cover the single-grid force");
   return PM_OK;
 }
 
@@ -1432,6 +1543,7 @@ pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, doubl
   if (!dL_ddelta || !dL_dw || !dL_dsigma8) return PM_EINVAL;
   if (c->cfg.lpt_order == 2)
     return fail(c, PM_EUNSUPPORTED, "the adjoint covers Zel'dovich initial conditions only");
+  if (c->cfg.antialias) return fail(c, PM_EUNSUPPORTED, "the adjoint covers the single-grid force");
   const int B = c->cfg.batch, np = c->cfg.n_p;
   const long long N = c->g.N, M = c->g.M;
   const double mfac = (double)M / (double)N;
@@ -1676,6 +1788,7 @@ pm_status pm_force_vjp(pm_ctx* c, const float* disp, double s, const float* u, i
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!disp || !u || !xbar_out || parts < 1 || parts > 3) return PM_EINVAL;
+  if (c->cfg.antialias) return fail(c, PM_EUNSUPPORTED, "the force VJP covers the single-grid force");
   const int B = c->cfg.batch;
   const long long N = c->g.N;
   const size_t bytes = sizeof(float) * 3 * N * B;

@@ -37,6 +37,7 @@ class Config:
     lpt_order: int = 1            # 1 Zel'dovich, 2 second-order LPT initial state
     stepper: str = "bullfrog"     # "bullfrog" | "fastpm"
     time_var: str = "D"           # step spacing uniform in "D" | "a" | "lna"
+    antialias: int = 0            # 1: interlaced grids for the PM force
 
     def to_c(self):
         c = _lib.pm_config()

@@ -74,7 +74,8 @@ def test_nufft_force_against_direct_nudft():
     assert rel_l2(a, ref) < 3e-5
 
 
-@pytest.mark.parametrize("wl", ["C3_SMALL", "C3_SUB"])
+# the FP64 oracle takes minutes over the 128^3 run
+@pytest.mark.parametrize("wl", ["C3_SMALL", pytest.param("C3_SUB", marks=pytest.mark.timeout(900))])
 def test_nufft_run_matches_oracle(wl):
     d = getattr(synth, wl)
     say("nufft run", wl)
