@@ -25,7 +25,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import ics, mesh
-from .force import force_multipliers, PMConfig
+from .force import force_multipliers, interlace_phase, PMConfig
 
 
 def force_vjp(cfg: PMConfig, psi, s, u, parts=3):
@@ -33,7 +33,7 @@ def force_vjp(cfg: PMConfig, psi, s, u, parts=3):
     parts: 1 the direct term (gather w.r.t. positions) only, 2 the terms
     through the mesh only, 3 both."""
     if cfg.interlace:
-        raise NotImplementedError("the VJP covers the single-grid force")
+        return force_vjp_interlaced(cfg, psi, s, u, parts)
     n, N = cfg.n_g, cfg.N
     delta = mesh.contrast(mesh.deposit(psi, cfg.n_p, n, cfg.order), N, n)
     dk = np.fft.rfftn(delta.reshape(n, n, n))
@@ -52,6 +52,43 @@ def force_vjp(cfg: PMConfig, psi, s, u, parts=3):
     # delta = (n^3/N) m - 1, and m = scatter(1): scatter^T w.r.t. positions
     if parts & 2:
         xbar += mesh.grad_gather(dbar * (n ** 3 / N), psi, cfg.n_p, n, cfg.order)
+    return xbar
+
+
+def force_vjp_interlaced(cfg: PMConfig, psi, s, u, parts=3):
+    """J_A^T u for the interlaced force of ``force.pm_force_u``: with u1 the
+    mesh coordinates and u2 = u1 + 1/2, A_c = (gather(g1_c, u1) +
+    gather(g2_c, u2)) / 2, g1_c = IDFT(K_c dk), g2_c = IDFT(K_c e^{-i phi}
+    dk), dk = (DFT(delta1) + e^{i phi} DFT(delta2)) / 2.  The same rules as
+    the single grid apply per grid; the transposed multipliers carry the
+    conjugate phase, so the mesh cotangents are
+    delta1_bar = IDFT(B1 + e^{i phi} B2) / 2 and
+    delta2_bar = IDFT(e^{-i phi} B1 + B2) / 2, with Bg = sum_c conj(K_c)
+    DFT(scatter of u_c / 2 at ug)."""
+    n, N, r = cfg.n_g, cfg.N, cfg.r
+    x1 = mesh.mesh_coords(psi, cfg.n_p, n)
+    x2 = np.mod(x1 + 0.5, n)
+    d1 = np.fft.rfftn(mesh.contrast(mesh.deposit_u(x1, n, cfg.order), N, n).reshape(n, n, n))
+    d2 = np.fft.rfftn(mesh.contrast(mesh.deposit_u(x2, n, cfg.order), N, n).reshape(n, n, n))
+    ph = interlace_phase(n)
+    dk = 0.5 * (d1 + ph * d2)
+    K = force_multipliers(cfg, s)
+    xbar = np.zeros((3, N))
+    B1 = np.zeros_like(dk)
+    B2 = np.zeros_like(dk)
+    for c in range(3):
+        if parts & 1:
+            g1 = np.fft.irfftn(K[c] * dk, s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
+            g2 = np.fft.irfftn(K[c] * dk * np.conj(ph), s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
+            xbar += 0.5 * r * u[c] * (mesh.grad_gather_u(g1, x1, n, cfg.order)
+                                      + mesh.grad_gather_u(g2, x2, n, cfg.order))
+        B1 += np.conj(K[c]) * np.fft.rfftn(mesh.deposit_u(x1, n, cfg.order, weights=0.5 * u[c]).reshape(n, n, n))
+        B2 += np.conj(K[c]) * np.fft.rfftn(mesh.deposit_u(x2, n, cfg.order, weights=0.5 * u[c]).reshape(n, n, n))
+    if parts & 2:
+        db1 = 0.5 * np.fft.irfftn(B1 + ph * B2, s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
+        db2 = 0.5 * np.fft.irfftn(np.conj(ph) * B1 + B2, s=(n, n, n), axes=(0, 1, 2)).reshape(-1)
+        f = n ** 3 / N
+        xbar += r * (mesh.grad_gather_u(db1 * f, x1, n, cfg.order) + mesh.grad_gather_u(db2 * f, x2, n, cfg.order))
     return xbar
 
 

@@ -110,6 +110,19 @@ def gather_u(field, u, n_g, order):
     return v
 
 
+def grad_gather_u(field, u, n_g, order):
+    """d/du_i of sum_j field_j W_j(u_i) in mesh units, shape (3, M)."""
+    st = [weights_1d(np.asarray(u[a], dtype=np.float64), order) for a in range(3)]
+    f = np.asarray(field, dtype=np.float64).reshape(-1)
+    g = np.zeros((3, np.asarray(u).shape[1]))
+    for idx, (wx, wy, wz), (dx, dy, dz) in _loop(st, n_g, order):
+        fv = f[idx]
+        g[0] += fv * dx * wy * wz
+        g[1] += fv * wx * dy * wz
+        g[2] += fv * wx * wy * dz
+    return g
+
+
 def deposit(psi, n_p, n_g, order, weights=None):
     """rho_j = sum_i w_i W_j(X_i) on the n_g^3 mesh (flat, FP64)."""
     return deposit_u(mesh_coords(psi, n_p, n_g), n_g, order, weights)

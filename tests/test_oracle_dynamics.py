@@ -6,7 +6,7 @@ import numpy as np
 from scipy.integrate import quad
 import pytest
 
-from oracle import adjoint, cosmo, ics, mesh, nbody, nufft, pk
+from oracle import adjoint, cosmo, force, ics, mesh, nbody, nufft, pk
 from oracle.force import PMConfig
 
 
@@ -184,6 +184,49 @@ def test_force_vjp_matches_finite_differences():
     fd = (np.sum(u * prob.force_fn()(psi + eps * v, 2.0))
           - np.sum(u * prob.force_fn()(psi - eps * v, 2.0))) / (2 * eps)
     assert abs(np.sum(jt * v) - fd) < 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("order,dec,g", [(2, False, 4), (3, True, 2), (4, True, 6)])
+def test_interlaced_force_vjp_matches_finite_differences(order, dec, g):
+    # the interlaced VJP against central differences of the interlaced
+    # force; its two parts add up to the whole
+    cfg = PMConfig(8, 16, 40.0, order=order, deconvolve=dec, grad_order=g, lap_order=0, interlace=True)
+    rng = np.random.default_rng(50 + order)
+    psi = rng.normal(0, 1.0, (3, cfg.N))
+    u = rng.normal(size=(3, cfg.N))
+    v = rng.normal(size=(3, cfg.N))
+    jt = adjoint.force_vjp(cfg, psi, 2.0, u)
+    eps = 1e-6
+    fd = (np.sum(u * force.pm_force(cfg, psi + eps * v, 2.0))
+          - np.sum(u * force.pm_force(cfg, psi - eps * v, 2.0))) / (2 * eps)
+    assert abs(np.sum(jt * v) - fd) < 1e-6 * abs(fd)
+    split = adjoint.force_vjp(cfg, psi, 2.0, u, parts=1) + adjoint.force_vjp(cfg, psi, 2.0, u, parts=2)
+    assert np.allclose(split, jt, rtol=0, atol=1e-12 * np.abs(jt).max())
+    # the single-grid VJP differs (the second grid's terms are in it)
+    plain = adjoint.force_vjp(PMConfig(8, 16, 40.0, order=order, deconvolve=dec, grad_order=g), psi, 2.0, u)
+    assert np.linalg.norm(plain - jt) > 1e-3 * np.linalg.norm(jt)
+
+
+def test_interlaced_gradient_matches_finite_differences():
+    cfg = PMConfig(8, 16, 40.0, order=3, deconvolve=True, grad_order=4, lap_order=0, interlace=True)
+    prob = nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=0.9)
+    n = cfg.n_p
+    rng = np.random.default_rng(8)
+    w = nbody.white_noise(prob, 4).astype(np.float64)
+    target = rng.normal(size=cfg.n_g ** 3)
+
+    def loss_of(w_):
+        psi0, v0, _ = nbody.initial_state(prob, w_.reshape(n, n, n))
+        psi, _ = nbody.run_from(prob, psi0, v0)
+        return np.sum((adjoint.final_density(prob, psi) - target) ** 2)
+
+    wbar, _, _ = adjoint.gradient(prob, w, lambda d: 2 * (d - target))
+    for _ in range(2):
+        dirn = rng.normal(size=n ** 3)
+        dirn /= np.linalg.norm(dirn)
+        eps = 1e-6
+        fd = (loss_of(w.reshape(-1) + eps * dirn) - loss_of(w.reshape(-1) - eps * dirn)) / (2 * eps)
+        assert abs(np.dot(wbar, dirn) - fd) < 1e-5 * abs(fd) + 1e-9
 
 
 def test_ic_vjp_is_the_transpose():
