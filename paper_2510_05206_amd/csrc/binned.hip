@@ -866,9 +866,9 @@ __device__ __forceinline__ void load_window_es(float* win, const float* __restri
 
 // Particle loads are software-pipelined: the next particle's index and
 // coordinates are in flight while the current one scatters.  Lanes of a wave
-// take particles 16 apart in the tile's (lattice-ordered) list: neighbours
-// in the list often share a cell, and int64 atomics of one instruction to one
-// address serialise (measured 3.5% faster than consecutive lanes).
+// take consecutive entries of the tile's bank order (below), whose window
+// bases mostly differ modulo 64: the int64 atomics of one instruction rarely
+// share a bank or an address.
 __global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_deposit(TileArgs a) {
   constexpr int NT = kEsSpreadThreads;
   extern __shared__ unsigned long long ewin[];
@@ -877,11 +877,11 @@ __global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_deposit(TileArgs a
   constexpr int W = kEsWin, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
-  int p = beg + (int)(((threadIdx.x % (NT / 16)) * 16) + threadIdx.x / (NT / 16));  // lanes 16 apart in the tile order
+  int p = beg + (int)threadIdx.x;  // consecutive lanes of the bank order: window bases spread over the banks
   long long i = 0;
   float x0 = 0.f, x1 = 0.f, x2 = 0.f;
   if (p < end) {
-    i = a.sorted[slot * N + p];
+    i = a.sorted[slot * N + a.bank[slot * N + p]];
     x0 = a.disp[ps + i];
     x1 = a.disp[ps + N + i];
     x2 = a.disp[ps + 2 * N + i];
@@ -903,7 +903,7 @@ __global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_deposit(TileArgs a
       l0[c] = ((es_weights(U, a.es_tab, w[c]) - kEsAnchor) & nm) - o[c];  // first node floor(u) - 2
     }
     if (p + NT < end) {
-      i = a.sorted[slot * N + p + NT];
+      i = a.sorted[slot * N + a.bank[slot * N + p + NT]];
       x0 = a.disp[ps + i];
       x1 = a.disp[ps + N + i];
       x2 = a.disp[ps + 2 * N + i];
@@ -1185,14 +1185,15 @@ __global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_divspread(TileArgs
   constexpr int W = kEsWin, W3 = W * W * W;
   const long long N = a.g.N, ps = slot * a.g.part_stride;
   const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
-  int p = beg + (int)(((threadIdx.x % (NT / 16)) * 16) + threadIdx.x / (NT / 16));  // lanes 16 apart in the tile order
+  int p = beg + (int)threadIdx.x;  // consecutive lanes of the bank order: window bases spread over the banks
   long long i = 0;
   float u0 = 0.f, u1 = 0.f, u2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
   if (p < end) {
-    i = a.sorted[slot * N + p];
-    u0 = a.u_sorted[ps + p];
-    u1 = a.u_sorted[ps + N + p];
-    u2 = a.u_sorted[ps + 2 * N + p];
+    const int q = a.bank[slot * N + p];
+    i = a.sorted[slot * N + q];
+    u0 = a.u_sorted[ps + q];
+    u1 = a.u_sorted[ps + N + q];
+    u2 = a.u_sorted[ps + 2 * N + q];
     x0 = a.disp[ps + i];
     x1 = a.disp[ps + N + i];
     x2 = a.disp[ps + 2 * N + i];
@@ -1218,7 +1219,7 @@ __global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_divspread(TileArgs
       l0[c] = ((es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) - kEsAnchor) & nm) - o[c];
     }
     if (p + NT < end) {
-      const int q = p + NT;
+      const int q = a.bank[slot * N + p + NT];
       i = a.sorted[slot * N + q];
       u0 = a.u_sorted[ps + q];
       u1 = a.u_sorted[ps + N + q];
@@ -1341,6 +1342,91 @@ hipError_t configure_tile_kernels() {
   set((const void*)k_tile_es_divspread, es64);
   set((const void*)k_tile_es_adj_drift, es32);
   return e;
+}
+
+// ------------------------------------------------ LDS bank order (ES)
+
+// Every LDS access of an ES spread is a particle's window base plus an offset
+// that all lanes of the instruction share (the unrolled 6^3 loop), so the
+// bank conflicts of an instruction (32 banks of 4 bytes; a wave's 64 lanes
+// take two cycles when no bank holds more than two distinct addresses) are
+// set by the bases of the wave's particles.  For each tile this writes
+// `bank`, an order of its entries in `sorted`, in chunks of kBankChunk: a
+// counting sort by base mod 64, then a transpose that deals the sorted
+// entries so that every 64 consecutive positions (one wave of a spread
+// kernel) step through the residues.  The spreads take their particles in
+// this order; their results are integer sums and do not depend on it.  The
+// gathers keep the tile's lattice order, whose particle data is contiguous
+// in memory.
+constexpr int kBankChunk = 1024;
+
+__global__ void __launch_bounds__(256) k_tile_es_bank_order(TileArgs a, int32_t* bank) {
+  constexpr int KE = kBankChunk / 256;
+  __shared__ int cnt[64], start[64];
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
+  if (!((a.active >> slot) & 1ull)) return;
+  constexpr int W = kEsWin;  // the spread windows' row stride
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+  const int32_t* list = a.sorted + slot * N;
+  int32_t* out = bank + slot * N;
+  for (int c0 = beg; c0 < end; c0 += kBankChunk) {
+    const int m = min(kBankChunk, end - c0);
+    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int res[KE], rank[KE];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int e = (int)threadIdx.x + 256 * k;
+      res[k] = rank[k] = 0;
+      if (e < m) {
+        const int32_t id = list[c0 + e];
+        long long j[3];
+        lattice_of(id, a.g.log2_np, a.g.log2_pb, j);
+        int l0[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const long long U = fixed_coord(j[c], a.disp[ps + c * N + id], a.g.log2_r, umask);
+          l0[c] = (((int)(U >> kFracBits) - kEsAnchor) & nm) - o[c];
+        }
+        res[k] = ((l0[0] * W + l0[1]) * W + l0[2]) & 63;
+        rank[k] = atomicAdd(&cnt[res[k]], 1);
+      }
+    }
+    __syncthreads();  // every entry of the chunk is counted
+    if (threadIdx.x < 64) {
+      const int own = cnt[threadIdx.x];
+      int v = own;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(v, d, 64);
+        if ((int)threadIdx.x >= d) v += y;
+      }
+      start[threadIdx.x] = v - own;
+    }
+    __syncthreads();
+    // residue-sorted position sp -> row g = sp mod G, column sp / G of the m
+    // entries laid out in rows of G; the rows follow one another
+    const int G = (m + 63) >> 6, q = m / G, rem = m - q * G;
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int e = (int)threadIdx.x + 256 * k;
+      if (e >= m) continue;
+      const int sp = start[res[k]] + rank[k], g = sp % G;
+      out[c0 + g * q + min(g, rem) + sp / G] = c0 + e;
+    }
+    __syncthreads();  // the counters are read before the next chunk clears them
+  }
+}
+
+hipError_t launch_es_bank_order(const TileArgs& a, int32_t* bank, hipStream_t s) {
+  if (a.T != kTileMax) return hipErrorInvalidValue;
+  k_tile_es_bank_order<<<dim3((unsigned)a.n_tiles, a.batch), 256, 0, s>>>(a, bank);
+  return hipGetLastError();
 }
 
 hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {

@@ -35,6 +35,7 @@ struct TileArgs {
   long long ts;
   const int32_t* sorted;
   const int32_t* offset;
+  const int32_t* bank;     // ES spreads: positions into sorted, per tile in LDS-bank order
   float* disp;
   float* vel;
   float* xbar;
@@ -79,6 +80,10 @@ hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s);
 hipError_t launch_tile(const TileArgs& a, int kind, int mak, int fd_order, hipStream_t s);
 hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s);
 hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s);
+// the ES spreads' order of each tile's entries of `sorted` (bank, [B][N]
+// positions into sorted), which spreads a wave's window bases over the LDS
+// banks
+hipError_t launch_es_bank_order(const TileArgs& a, int32_t* bank, hipStream_t s);
 hipError_t configure_tile_kernels();
 hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, double* inv_scale,
                                double bound_per_u, double node_per_u, int batch, hipStream_t s);

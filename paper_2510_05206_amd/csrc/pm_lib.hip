@@ -460,6 +460,10 @@ pm_status bin(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, i
   b.scan_partial = c->scan_partial;
   b.scan_np = scan_np(c->n_tiles);
   KLAUNCH(c, PM_K_BIN, launch_binning(b, mak, c->stream));
+  if (home_shift == kEsAnchor) {  // ES binning: the spreads' LDS-bank order (in the rank buffer, free by now)
+    TileArgs t = tile_args(c, disp, active);
+    KLAUNCH(c, PM_K_MISC, launch_es_bank_order(t, c->rank, c->stream));
+  }
   return PM_OK;
 }
 
@@ -475,6 +479,7 @@ TileArgs tile_args(pm_ctx* c, float* disp, unsigned long long active) {
   t.ts = c->ts;
   t.sorted = c->sorted;
   t.offset = c->offset;
+  t.bank = c->rank;  // written by an ES binning
   t.disp = disp;
   t.vel = c->vel;
   t.xbar = c->xbar;
