@@ -96,9 +96,10 @@ enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
  *                  suppression"; antialias of tab. default_parameters), a
  *                  second deposit half a cell down the diagonal, the two
  *                  spectra averaged with the shift's phase and the two
- *                  gathers averaged; PM force with n_g >= 16 only;
- *                  pm_adjoint, pm_force_vjp and the device-indexed steps
- *                  return PM_EUNSUPPORTED for it
+ *                  gathers averaged (the adjoint and pm_force_vjp average
+ *                  the two grids' terms likewise); PM force with n_g >= 16
+ *                  only; the device-indexed steps return PM_EUNSUPPORTED
+ *                  for it
  */
 typedef struct {
   int32_t n_p, n_g;

@@ -456,19 +456,41 @@ __global__ void __launch_bounds__(256, 2) k_tile_adj_kick(TileArgs a) {  // <= 2
     int l0[3];
     tile_weights<P>(a, i, x, o, R, w, dw, l0);
     fd_gather<P, ORD, true>(acc, l0, w, dw, A, dA);
-    float u[3];
+    float vb[3], u[3], tx[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float vb = a.vbar[ps + c * N + i];
-      u[c] = be * vb;
-      a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A[c]) / al;
-      a.vbar[ps + c * N + i] = al * vb;
+      vb[c] = a.vbar[ps + c * N + i];
+      u[c] = be * vb[c];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) tx[d] = r * (u[0] * dA[0][d] + u[1] * dA[1][d] + u[2] * dA[2][d]);
+    if (a.il_in) {  // interlaced grids: the mean of the two grids' force and direct term
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        A[c] = 0.5f * (A[c] + a.il_in[2 * ps + c * N + i]);
+        tx[c] = 0.5f * (tx[c] + a.il_in[2 * ps + (3 + c) * N + i]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
       a.u_sorted[ps + c * N + p] = u[c];
       umax = fmaxf(umax, fabsf(u[c]));
     }
+    if (a.il_out) {  // the second grid: its terms only, the state untouched
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-      a.xbar[ps + d * N + i] += r * (u[0] * dA[0][d] + u[1] * dA[1][d] + u[2] * dA[2][d]);
+      for (int c = 0; c < 3; ++c) {
+        a.il_out[2 * ps + c * N + i] = A[c];
+        a.il_out[2 * ps + (3 + c) * N + i] = tx[c];
+      }
+      continue;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A[c]) / al;
+      a.vbar[ps + c * N + i] = al * vb[c];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.xbar[ps + d * N + i] += tx[d];
   }
   red[threadIdx.x] = umax;
   __syncthreads();
@@ -619,10 +641,19 @@ __global__ void __launch_bounds__(256) k_tile_adj_drift(TileArgs a) {
           gz += f * w[0][xx] * w[1][yy] * dw[2][zz];
         }
       }
-    float g[3] = {gx, gy, gz};
+    float g[3] = {cf * gx, cf * gy, cf * gz};
+    if (a.il_in) {  // interlaced grids: the mean of the two grids' scatter terms
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[c] = 0.5f * (g[c] + a.il_in[2 * ps + c * N + i]);
+    }
+    if (a.il_out) {  // the first grid: its term only, the state untouched
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.il_out[2 * ps + c * N + i] = g[c];
+      continue;
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float xb = a.xbar[ps + c * N + i] + cf * g[c];
+      float xb = a.xbar[ps + c * N + i] + g[c];
       float v = a.vel[ps + c * N + i];
       a.disp[ps + c * N + i] = x[c] - tau * v;
       a.xbar[ps + c * N + i] = xb;
@@ -1303,10 +1334,19 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
       gy += w[0][xx] * sdw;
       gz += w[0][xx] * swd;
     }
-    float g[3] = {gx, gy, gz};
+    float g[3] = {cf * gx, cf * gy, cf * gz};
+    if (a.il_in) {  // interlaced grids: the mean of the two grids' scatter terms
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[c] = 0.5f * (g[c] + a.il_in[2 * ps + c * N + i]);
+    }
+    if (a.il_out) {  // the first grid: its term only, the state untouched
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.il_out[2 * ps + c * N + i] = g[c];
+      continue;
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float xb = a.xbar[ps + c * N + i] + cf * g[c];
+      float xb = a.xbar[ps + c * N + i] + g[c];
       float v = a.vel[ps + c * N + i];
       a.disp[ps + c * N + i] = x[c] - tau * v;
       a.xbar[ps + c * N + i] = xb;

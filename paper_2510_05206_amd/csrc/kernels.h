@@ -44,6 +44,12 @@ struct TileArgs {
   void* scratch;           // window slab [B][n_tiles][W^3] int64
   float* acc_out;          // force-only output
   const float* acc_in;     // interlaced grids: the other grid's forces, averaged in the kick
+  // interlaced grids, reverse pass ([B][6][N]): the second grid's adjoint kick
+  // writes its force (3) and direct position term (3) to il_out, the adjoint
+  // drift of the first grid writes its scatter term (3); the other grid's
+  // pass averages its own with il_in
+  float* il_out;
+  const float* il_in;
   float* u_sorted;         // [B][3][N] u = beta V_bar in sorted order
   float* umax;             // [B] max |u| (as uint bits)
   const double* scale;     // [B] fixed-point scale of the cotangent scatter

@@ -49,7 +49,7 @@ struct pm_ctx {
   unsigned long long bind_gen = 0, step_bind_gen = 0;
   float* force3 = nullptr;           // NUFFT: 3 force meshes [B][3][M]
   float2* spec2 = nullptr;           // NUFFT: per-component spectrum; interlaced PM: the second grid's
-  float* accbuf = nullptr;           // interlaced PM: the second grid's forces [B][3][N]
+  float* accbuf = nullptr;           // interlaced PM: one grid's per-particle terms [B][6][N]
   float* phi2 = nullptr;             // interlaced PM: the second grid's potential (in the mesh buffer)
   float *disp = nullptr, *vel = nullptr, *w = nullptr, *xbar = nullptr, *vbar = nullptr;
   long long* mesh = nullptr;
@@ -215,7 +215,7 @@ Layout layout(const pm_ctx* c, bool adj) {
   L.off_sched = take(sizeof(float) * kSch * (size_t)kMaxSchedSteps * B);  // fixed: memory independent of n_steps
   L.off_force3 = nufft ? take(sizeof(float) * 3 * M * B) : 0;
   L.off_spec2 = (nufft || c->cfg.antialias) ? take(sizeof(float2) * spec_elems(n) * B) : 0;
-  L.off_accbuf = c->cfg.antialias ? take(sizeof(float) * 3 * N * B) : 0;
+  L.off_accbuf = c->cfg.antialias ? take(sizeof(float) * 6 * N * B) : 0;
   L.off_scratch = take(sizeof(long long) * W * W * W * n_tiles * B);
   L.off_u = adj ? take(sizeof(float) * 3 * N * B) : 0;
   L.off_umax = take(sizeof(float) * kMaxBatch);
@@ -1493,10 +1493,14 @@ pm_status kick_dot(pm_ctx* c, double* out, unsigned long long act) {
   return PM_OK;
 }
 
+pm_status reverse_force_step_interlaced(pm_ctx* c, const double* s, const double* alpha, const double* beta,
+                                        const double* tau, unsigned long long act, int parts, double* kdot);
+
 pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, const double* beta,
                              const double* tau, unsigned long long act, int parts, double* kdot = nullptr) {
   KLAUNCH(c, PM_K_FILL, launch_fill(c->umax, (long long)sizeof(float) * kMaxBatch, c->stream));
   if (c->cfg.force == PM_FORCE_NUFFT) return nufft_adjoint_step(c, s, alpha, beta, tau, act, parts, kdot);
+  if (c->cfg.antialias) return reverse_force_step_interlaced(c, s, alpha, beta, tau, act, parts, kdot);
   const int B = c->cfg.batch;
   const long long N = c->g.N, M = c->g.M;
   const double mfac = (double)M / (double)N;
@@ -1535,6 +1539,89 @@ pm_status reverse_force_step(pm_ctx* c, const double* s, const double* alpha, co
   return PM_OK;
 }
 
+// The reverse step through interlaced grids (the force averages two grids,
+// the second at the positions + (1/2, 1/2, 1/2) cells): every term of the
+// force VJP is the mean of the two grids' terms.  The mesh cotangents of the
+// two deposits come from the transposed gathers of u on each grid through the
+// same two-grid chain as the forward force (the transposed multiplier of grid
+// 1 with the phase is that of grid 2 with the conjugate phase).  The passes
+// that need the other grid's binning run first and leave their terms in the
+// per-particle buffer; the binning left behind is the second grid's.
+pm_status reverse_force_step_interlaced(pm_ctx* c, const double* s, const double* alpha, const double* beta,
+                                        const double* tau, unsigned long long act, int parts, double* kdot) {
+  const int B = c->cfg.batch;
+  const long long N = c->g.N, M = c->g.M;
+  const double mfac = (double)M / (double)N;
+  const int ord = c->cfg.grad_order, mak = c->cfg.mak;
+  const double fd_l1 = ord == 2 ? 1.0 : (ord == 4 ? 1.5 : 110.0 / 60.0);
+  const long long half = 1ll << (kFracBits - 1);
+  float* d1 = reinterpret_cast<float*>(c->mesh);
+  float* d2 = d1 + (long long)B * M;  // the second grid's potential, then its cotangents
+  auto args = [&](long long ushift) {
+    c->g.ushift = ushift;
+    TileArgs k = tile_args(c, c->disp, act);
+    c->g.ushift = 0;
+    for (int b = 0; b < B; ++b) {
+      k.alpha[b] = (float)alpha[b];
+      k.beta[b] = (float)beta[b];
+      k.coef[b] = (float)mfac;
+      k.tau[b] = (float)tau[b];
+    }
+    return k;
+  };
+  auto dipole = [&](const TileArgs& k, float* out) -> pm_status {
+    AssembleArgs as = assemble_args(c, dipole_halo(ord, mak), dipole_halo(ord, mak), out, act);
+    KLAUNCH(c, PM_K_DIPOLE,
+            both(launch_tile(k, TK_DIPOLE, mak, ord, c->stream), launch_assemble(as, true, c->stream)));
+    return PM_OK;
+  };
+  // second grid (its binning is current): force and direct term, u in its order
+  TileArgs k2 = args(half);
+  k2.mesh_in = c->phi2;
+  k2.il_out = c->accbuf;
+  KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(k2, TK_ADJ_KICK, mak, ord, c->stream));
+  if (parts & 2) {
+    KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
+                                              3.0 * fd_l1 * (double)N, fd_l1, B, c->stream));
+    if (pm_status st = dipole(k2, d2)) return st;
+  }
+  // first grid: the reverse kick with the means
+  if (pm_status st = bin(c, c->disp, nullptr, nullptr, mak, act)) return st;
+  TileArgs k1 = args(0);
+  k1.mesh_in = c->phi;
+  k1.il_in = c->accbuf;
+  KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(k1, TK_ADJ_KICK, mak, ord, c->stream));
+  if (pm_status st = kick_dot(c, kdot, act)) return st;
+  if (!(parts & 1))
+    KLAUNCH(c, PM_K_FILL, launch_fill(c->xbar, (long long)sizeof(float) * 3 * N * B, c->stream));
+  if (!(parts & 2)) return PM_OK;
+  if (pm_status st = dipole(k1, d1)) return st;
+  // mesh cotangents of the two deposits (cotangent 1 on c->phi, 2 on d2)
+  pm_status st = r2c_mesh(c, d1, SRC_F32, M, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
+  if (st) return st;
+  st = r2c_mesh(c, d2, SRC_F32, M, 1.0, 0.0, c->spec2, c->g.spec_stride, c->cfg.n_g, true, act);
+  if (st) return st;
+  st = spectrum_to_real(c, c->spec, MODE_FUSED_IL, s, c->spec2, c->phi, act);
+  if (st) return st;
+  st = spectrum_to_real(c, c->spec2, MODE_INV, nullptr, nullptr, d2, act);
+  if (st) return st;
+  // scatter terms: the first grid's into the buffer, then the second grid's
+  // pass takes the mean and reverses the drift
+  TileArgs r1 = args(0);
+  r1.mesh_in = c->phi;
+  r1.il_out = c->accbuf;
+  KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile(r1, TK_ADJ_DRIFT, mak, ord, c->stream));
+  c->g.ushift = half;
+  st = bin(c, c->disp, nullptr, nullptr, mak, act);
+  c->g.ushift = 0;
+  if (st) return st;
+  TileArgs r2 = args(half);
+  r2.mesh_in = d2;
+  r2.il_in = c->accbuf;
+  KLAUNCH(c, PM_K_ADJ_DRIFT, launch_tile(r2, TK_ADJ_DRIFT, mak, ord, c->stream));
+  return PM_OK;
+}
+
 pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8, double* dL_dtime);
 
 pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8) {
@@ -1548,7 +1635,6 @@ pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, doubl
   if (!dL_ddelta || !dL_dw || !dL_dsigma8) return PM_EINVAL;
   if (c->cfg.lpt_order == 2)
     return fail(c, PM_EUNSUPPORTED, "the adjoint covers Zel'dovich initial conditions only");
-  if (c->cfg.antialias) return fail(c, PM_EUNSUPPORTED, "the adjoint covers the single-grid force");
   const int B = c->cfg.batch, np = c->cfg.n_p;
   const long long N = c->g.N, M = c->g.M;
   const double mfac = (double)M / (double)N;
@@ -1793,7 +1879,6 @@ pm_status pm_force_vjp(pm_ctx* c, const float* disp, double s, const float* u, i
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!disp || !u || !xbar_out || parts < 1 || parts > 3) return PM_EINVAL;
-  if (c->cfg.antialias) return fail(c, PM_EUNSUPPORTED, "the force VJP covers the single-grid force");
   const int B = c->cfg.batch;
   const long long N = c->g.N;
   const size_t bytes = sizeof(float) * 3 * N * B;
