@@ -261,6 +261,29 @@ pm_status pm_get_step_index(pm_ctx* ctx, int32_t* step_index);
 pm_status pm_power_spectrum(pm_ctx* ctx, int32_t n_bins, int32_t deconvolve_cic,
                             double* k_mean, double* pk, int64_t* n_modes);
 
+/* Forward mode (Sec. "Automatic differentiation", forward mode; App.
+ * "Custom VJP and JVP", subsection "VJP and JVP derivations"): the tangent
+ * of the run along the direction (w_dot, sigma8_dot) of the white noise and
+ * sigma8.  Reruns the forward from the white noise of the last pm_init_ics
+ * while carrying the tangent positions and velocities (the JVP of a scatter
+ * w.r.t. the positions is a scatter with the gradient kernel; of a gather,
+ * a gather of the tangent mesh plus a gather with the gradient kernel), and
+ * leaves the context at the run's final state (as pm_run).  w_dot: device
+ * [B][N] in lattice order; sigma8_dot: host [B] or NULL (0; no effect with
+ * the power-law spectrum, whose amplitude is not set by sigma8);
+ * delta_dot_out: device [B][n_g^3], the tangent of the final CIC contrast.
+ * Needs a workspace bound with adjoint buffers (the tangents use them;
+ * PM_ESTATE otherwise); single-grid PM force and Zel'dovich initial
+ * conditions only (PM_EUNSUPPORTED otherwise). */
+pm_status pm_jvp(pm_ctx* ctx, const float* w_dot, const double* sigma8_dot, float* delta_dot_out);
+
+/* pm_power_spectrum of the current state plus pk_dot (device [B][n_bins]),
+ * the tangent of P(k_b) when the contrast moves along delta_dot (device
+ * [B][n_g^3], e.g. from pm_jvp): the same bins of 2 Re(conj(delta_m)
+ * delta_dot_m) / W^2. */
+pm_status pm_power_spectrum_jvp(pm_ctx* ctx, const float* delta_dot, int32_t n_bins, int32_t deconvolve_cic,
+                                double* k_mean, double* pk, double* pk_dot, int64_t* n_modes);
+
 /* State access and single-kernel entry points (tests, loss, resume) ------- */
 
 /* Final CIC density contrast delta = m n_g^3/N - 1 of the current positions

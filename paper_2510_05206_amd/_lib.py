@@ -63,6 +63,9 @@ EXPORTS = {
     "pm_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_adjoint_full": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_power_spectrum": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pm_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pm_power_spectrum_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]),
     "pm_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -662,6 +662,117 @@ __global__ void __launch_bounds__(256) k_tile_adj_drift(TileArgs a) {
   }
 }
 
+// ------------------------------------------- forward-mode tangents (PM)
+
+// JVP of the deposit w.r.t. the positions (a scatter with the gradient
+// kernel dotted with the tangent positions, held in xbar): node +=
+// coef sum_c xdot_c dW/du_c, coef = r n_g^3 / N (the contrast's
+// normalisation and dq -> mesh units), in int64 fixed point at the slot's
+// scale (every node value of one particle is below 3 coef max|xdot| < 2^31
+// there, as |W| <= 1 and |dW/du| <= 1 per cell for CIC, TSC and PCS)
+template <int P>
+__global__ void __launch_bounds__(256) k_tile_tan_spread(TileArgs a) {
+  constexpr int R = kernel_reach<P>();
+  __shared__ unsigned long long win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
+  if (!((a.active >> slot) & 1ull)) return;
+  const int W = a.T + 2 * R, W3 = W * W * W;
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  for (int e = threadIdx.x; e < W3; e += 256) win[e] = 0ull;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  __syncthreads();
+  const float S = (float)a.scale[slot] * a.coef[slot];
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    const float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][P], dw[3][P];
+    int l0[3];
+    tile_weights<P>(a, i, x, o, R, w, dw, l0);
+    const float td[3] = {a.xbar[ps + i] * S, a.xbar[ps + N + i] * S, a.xbar[ps + 2 * N + i] * S};
+#pragma unroll
+    for (int xx = 0; xx < P; ++xx)
+#pragma unroll
+      for (int yy = 0; yy < P; ++yy) {
+        const float cx = td[0] * dw[0][xx] * w[1][yy], cy = td[1] * w[0][xx] * dw[1][yy],
+                    cz = td[2] * w[0][xx] * w[1][yy];
+        unsigned long long* row = win + ((l0[0] + xx) * W + l0[1] + yy) * W + l0[2];
+#pragma unroll
+        for (int zz = 0; zz < P; ++zz) {
+          const float v = (cx + cy) * w[2][zz] + cz * dw[2][zz];
+          atomicAdd(row + zz, (unsigned long long)(long long)(int)rintf(v));
+        }
+      }
+  }
+  __syncthreads();
+  store_window(win, reinterpret_cast<unsigned long long*>(a.scratch) + (long long)slot * a.n_tiles * W3, t, W,
+               a.log2nt);
+}
+
+// direct part of J_A xdot (the gather's JVP w.r.t. the positions, phi
+// fixed): r sum_d dA_c/du_d xdot_d into acc_out
+template <int P, int ORD>
+__global__ void __launch_bounds__(256, 2) k_tile_tan_direct(TileArgs a) {
+  constexpr int R = kernel_reach<P>() + ORD / 2;
+  __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
+  if (!((a.active >> slot) & 1ull)) return;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, R, a.g.log2_ng, a.g.n_g - 1);
+  __syncthreads();
+  const WinAcc acc{win, a.T + 2 * R};
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const float r = (float)(1 << a.g.log2_r);
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    const float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][P], dw[3][P], A[3], dA[3][3];
+    int l0[3];
+    tile_weights<P>(a, i, x, o, R, w, dw, l0);
+    fd_gather<P, ORD, true>(acc, l0, w, dw, A, dA);
+    const float td[3] = {a.xbar[ps + i], a.xbar[ps + N + i], a.xbar[ps + 2 * N + i]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      a.acc_out[ps + c * N + i] = r * (dA[c][0] * td[0] + dA[c][1] * td[1] + dA[c][2] * td[2]);
+  }
+}
+
+// the tangent kick and drift: J = gather(FD grad of the tangent potential)
+// + the direct part (acc_in); Vdot = alpha Vdot + beta J, Xdot += tau Vdot
+// (Xdot in xbar, Vdot in vbar)
+template <int P, int ORD>
+__global__ void __launch_bounds__(256) k_tile_tan_kick(TileArgs a) {
+  constexpr int R = kernel_reach<P>() + ORD / 2;
+  __shared__ float win[(kTileMax + 2 * R) * (kTileMax + 2 * R) * (kTileMax + 2 * R)];
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
+  if (!((a.active >> slot) & 1ull)) return;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  load_window(win, a.mesh_in + slot * a.g.mesh_stride, o, a.T, R, R, a.g.log2_ng, a.g.n_g - 1);
+  __syncthreads();
+  const WinAcc acc{win, a.T + 2 * R};
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const float al = a.alpha[slot], be = a.beta[slot], tp = a.tau[slot];
+  for (int p = beg + threadIdx.x; p < end; p += 256) {
+    const long long i = a.sorted[slot * N + p];
+    const float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+    float w[3][P], dw[3][P], A[3], dA[3][3];
+    int l0[3];
+    tile_weights<P>(a, i, x, o, R, w, dw, l0);
+    fd_gather<P, ORD, false>(acc, l0, w, dw, A, dA);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float v = al * a.vbar[ps + c * N + i] + be * (A[c] + a.acc_in[ps + c * N + i]);
+      a.vbar[ps + c * N + i] = v;
+      a.xbar[ps + c * N + i] += tp * v;
+    }
+  }
+}
+
 // ------------------------------------------------------------- launchers
 
 hipError_t launch_binning(const BinArgs& a, int mak, hipStream_t s) {
@@ -708,6 +819,19 @@ hipError_t launch_tile(const TileArgs& a, int kind, int mak, int ord, hipStream_
     case TK_ADJ_KICK:
       if (mak == 2) PM_TILE_ORD(k_tile_adj_kick, 2); else if (mak == 3) PM_TILE_ORD(k_tile_adj_kick, 3);
       else PM_TILE_ORD4(k_tile_adj_kick);
+      break;
+    case TK_TAN_SPREAD:
+      if (mak == 2) k_tile_tan_spread<2><<<grid, 256, 0, s>>>(a);
+      else if (mak == 3) k_tile_tan_spread<3><<<grid, 256, 0, s>>>(a);
+      else k_tile_tan_spread<4><<<grid, 256, 0, s>>>(a);
+      break;
+    case TK_TAN_DIRECT:
+      if (mak == 2) PM_TILE_ORD(k_tile_tan_direct, 2); else if (mak == 3) PM_TILE_ORD(k_tile_tan_direct, 3);
+      else PM_TILE_ORD4(k_tile_tan_direct);
+      break;
+    case TK_TAN_KICK:
+      if (mak == 2) PM_TILE_ORD(k_tile_tan_kick, 2); else if (mak == 3) PM_TILE_ORD(k_tile_tan_kick, 3);
+      else PM_TILE_ORD4(k_tile_tan_kick);
       break;
     case TK_ADJ_DRIFT:
       if (mak == 2) k_tile_adj_drift<2><<<grid, 256, 0, s>>>(a);

@@ -25,7 +25,8 @@ struct BinArgs {
 };
 
 enum { TK_DEPOSIT = 0, TK_KICK = 1, TK_ADJ_KICK = 2, TK_ADJ_DRIFT = 3, TK_DIPOLE = 4, TK_ES_DEPOSIT = 5,
-       TK_ES_KICK = 6, TK_ES_ADJ_KICK = 7, TK_ES_DIPOLE = 8, TK_ES_ADJ_DRIFT = 9 };
+       TK_ES_KICK = 6, TK_ES_ADJ_KICK = 7, TK_ES_DIPOLE = 8, TK_ES_ADJ_DRIFT = 9, TK_TAN_SPREAD = 10,
+       TK_TAN_DIRECT = 11, TK_TAN_KICK = 12 };
 
 struct TileArgs {
   Geom g;
@@ -96,6 +97,16 @@ hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, dou
 
 // auxiliary kernels (misc.hip)
 hipError_t launch_fill(void* p, long long bytes, hipStream_t s);
+struct SlotCoef {
+  float v[kMaxBatch];
+};
+// out = a + coef[slot] x over n floats per slot (slot stride n)
+hipError_t launch_lincomb(const float* a, const float* x, float* out, long long n, const SlotCoef& coef, int batch,
+                          unsigned long long active, hipStream_t s);
+// xd += tau[slot] vd over n floats per slot (stride `stride`), then
+// amax[slot] = max(amax[slot], max |xd|) as float bits (amax starts at 0)
+hipError_t launch_tan_drift(float* xd, const float* vd, long long n, long long stride, const SlotCoef& tau,
+                            unsigned int* amax, int batch, unsigned long long active, hipStream_t s);
 // device-indexed step state (by-value uploads, no host buffers in flight)
 constexpr int kMaxSchedSteps = 96;   // steps per slot a device schedule holds
 struct GateSet {
@@ -130,6 +141,6 @@ hipError_t launch_i64_to_delta(const long long* m, float* delta, long long M, lo
 hipError_t launch_pk(const float2* spec, long long slot_stride, int n, int batch, int n_bins,
                      double kf, double norm, const double* cic4, int deconv, double* partial,
                      double* k_mean, double* pk, long long* n_modes, unsigned long long active,
-                     int rs, hipStream_t s);
+                     int rs, hipStream_t s, const float2* spec2 = nullptr);
 
 }  // namespace pm

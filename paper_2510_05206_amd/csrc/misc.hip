@@ -21,6 +21,57 @@ hipError_t launch_fill(void* p, long long bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_lincomb(const float* a, const float* x, float* out, long long n, SlotCoef coef,
+                          unsigned long long active) {
+  const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
+  const float k = coef.v[slot];
+  const long long o = slot * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[o + i] = a[o + i] + k * x[o + i];
+}
+
+hipError_t launch_lincomb(const float* a, const float* x, float* out, long long n, const SlotCoef& coef, int batch,
+                          unsigned long long active, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_lincomb<<<dim3((unsigned)blocks, batch), 256, 0, s>>>(a, x, out, n, coef, active);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_tan_drift(float* xd, const float* vd, long long n, long long stride,
+                                                   SlotCoef tau, unsigned int* amax, unsigned long long active) {
+  __shared__ float red[256];
+  const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
+  const float tp = tau.v[slot];
+  const long long o = slot * stride;
+  float m = 0.f;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    float x = xd[o + i];
+    if (tp != 0.f) {
+      x += tp * vd[o + i];
+      xd[o + i] = x;
+    }
+    m = fmaxf(m, fabsf(x));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] > 0.f) atomicMax(amax + slot, __float_as_uint(red[0]));
+}
+
+hipError_t launch_tan_drift(float* xd, const float* vd, long long n, long long stride, const SlotCoef& tau,
+                            unsigned int* amax, int batch, unsigned long long active, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  k_tan_drift<<<dim3((unsigned)blocks, batch), 256, 0, s>>>(xd, vd, n, stride, tau, amax, active);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------- device-indexed step state
 // gate[b]: the step slot b runs next (-1 idle).  Set from the host by value
 // (k[b] = -2 keeps the current value), advanced at the end of each device
@@ -251,8 +302,10 @@ __device__ __forceinline__ int pk_bin(long long m2) {
   return (int)((r + 1) / 2);
 }
 
-__global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, long long slot_stride, int n,
-                                                    int n_bins, double kf, const double* cic4,
+// bins of |X|^2, or of 2 Re(conj(X) Y) with a second spectrum Y (the
+// tangent of |X|^2 when X moves along Y)
+__global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, const float2* spec2, long long slot_stride,
+                                                    int n, int n_bins, double kf, const double* cic4,
                                                     int deconv, double* partial,
                                                     unsigned long long active, int rs) {
   extern __shared__ double acc[];  // [3][n_bins][4]
@@ -277,8 +330,15 @@ __global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, long lon
         }
         if (b) {
           double wm = (z == 0 || z == n / 2) ? 1.0 : 2.0;
-          float2 X = spec[slot * slot_stride + ((long long)x * n + y) * rs + z];
-          double p = (double)X.x * X.x + (double)X.y * X.y;
+          const long long e = slot * slot_stride + ((long long)x * n + y) * rs + z;
+          float2 X = spec[e];
+          double p;
+          if (spec2) {
+            const float2 Y = spec2[e];
+            p = 2.0 * ((double)X.x * Y.x + (double)X.y * Y.y);
+          } else {
+            p = (double)X.x * X.x + (double)X.y * X.y;
+          }
           if (deconv) p /= cic4[x] * cic4[y] * cic4[z];
           vp = wm * p;
           vk = wm * kf * sqrt((double)m2);
@@ -331,9 +391,9 @@ __global__ void k_pk_final(const double* partial, int n, int n_bins, double norm
 hipError_t launch_pk(const float2* spec, long long slot_stride, int n, int batch, int n_bins,
                      double kf, double norm, const double* cic4, int deconv, double* partial,
                      double* k_mean, double* pk, long long* n_modes, unsigned long long active,
-                     int rs, hipStream_t s) {
+                     int rs, hipStream_t s, const float2* spec2) {
   size_t lds = (size_t)3 * n_bins * 4 * sizeof(double);
-  k_pk_partial<<<dim3(n, batch), 256, lds, s>>>(spec, slot_stride, n, n_bins, kf, cic4, deconv,
+  k_pk_partial<<<dim3(n, batch), 256, lds, s>>>(spec, spec2, slot_stride, n, n_bins, kf, cic4, deconv,
                                                 partial, active, rs);
   k_pk_final<<<dim3((n_bins + 63) / 64, batch), 64, 0, s>>>(partial, n, n_bins, norm, k_mean, pk,
                                                            n_modes, active);

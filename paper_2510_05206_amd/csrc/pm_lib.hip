@@ -1100,6 +1100,8 @@ pm_status pm_set_slot_params(pm_ctx* c, const int32_t* n_steps, const double* si
   return PM_OK;
 }
 
+static pm_status ic_chain(pm_ctx* c, const float* w, float* disp, float* vel, unsigned long long act);
+
 pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float* w_out) {
   if (pm_status st = check_bound(c)) return st;
   if (!seeds && !w_in) return fail(c, PM_EINVAL, "need seeds or w_in");
@@ -1112,8 +1114,25 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
         HIPCHK(c, hipMemcpyAsync(c->w + b * N, w_in + b * N, sizeof(float) * N, hipMemcpyDeviceToDevice, c->stream));
   } else
     KLAUNCH(c, PM_K_MISC, launch_white_noise(c->w, N, N, B, seeds, act, c->stream));
+  if (pm_status st = ic_chain(c, c->w, c->disp, c->vel, act)) return st;
+  if (c->cfg.lpt_order == 2)
+    if (pm_status st2 = lpt2(c, act)) return st2;
+  if (w_out)
+    for (int b = 0; b < B; ++b)
+      if ((act >> b) & 1ull)
+        HIPCHK(c, hipMemcpyAsync(w_out + b * N, c->w + b * N, sizeof(float) * N, hipMemcpyDeviceToDevice, c->stream));
+  c->ics_done = true;
+  c->ran = false;
+  return PM_OK;
+}
+
+// Zel'dovich state from white noise w ([B][N], lattice order): Psi = D_start
+// psi into disp, V = psi into vel (lattice blocks); psi = IDFT(h_c DFT(w))
+static pm_status ic_chain(pm_ctx* c, const float* w, float* disp, float* vel, unsigned long long act) {
+  const int B = c->cfg.batch, np = c->cfg.n_p;
+  const long long N = c->g.N;
   float2* wspec = c->icspec + 3 * c->icspec_comp;
-  pm_status st = r2c_mesh(c, c->w, SRC_F32, N, 1.0, 0.0, wspec, c->icspec_stride, np, true, act);
+  pm_status st = r2c_mesh(c, w, SRC_F32, N, 1.0, 0.0, wspec, c->icspec_stride, np, true, act);
   if (st) return st;
   ColArgs a{};
   a.data = wspec;
@@ -1146,8 +1165,8 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
     rl.dst_mode = DST_IC;
     rl.src = out;
     rl.src_stride = c->icspec_stride;
-    rl.dst = c->vel + comp * N;
-    rl.dst2 = c->disp + comp * N;
+    rl.dst = vel + comp * N;
+    rl.dst2 = disp + comp * N;
     rl.dst_stride = 3 * N;
     rl.tw = c->d_tw;
     rl.tws_half = c->Lmax / (np / 2);
@@ -1159,14 +1178,6 @@ pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float
     rl.active = act;
     KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   }
-  if (c->cfg.lpt_order == 2)
-    if (pm_status st2 = lpt2(c, act)) return st2;
-  if (w_out)
-    for (int b = 0; b < B; ++b)
-      if ((act >> b) & 1ull)
-        HIPCHK(c, hipMemcpyAsync(w_out + b * N, c->w + b * N, sizeof(float) * N, hipMemcpyDeviceToDevice, c->stream));
-  c->ics_done = true;
-  c->ran = false;
   return PM_OK;
 }
 
@@ -1789,6 +1800,121 @@ pm_status pm_power_spectrum(pm_ctx* c, int32_t n_bins, int32_t deconvolve_cic, d
   KLAUNCH(c, PM_K_MISC, launch_pk(c->spec, c->g.spec_stride, n, c->cfg.batch, n_bins, 2.0 * M_PI / L,
                       L * L * L / (n3 * n3), c->d_cic4, deconvolve_cic, c->pk_partial, k_mean, pk,
                       (long long*)n_modes, act, spec_rs(n), c->stream));
+  return PM_OK;
+}
+
+// ------------------------------------------------------------ forward mode
+
+// tangent of the contrast at the current binning for the tangent positions
+// in xbar (max |xdot| already reduced into umax): out = r n_g^3 / N
+// sum_i grad W . xdot_i, as FP32 [B][M]
+static pm_status tangent_contrast(pm_ctx* c, int mak, float* out, unsigned long long act) {
+  const int B = c->cfg.batch;
+  const double N = (double)c->g.N, coef = (double)(1 << c->g.log2_r) * (double)c->g.M / N;
+  KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale, 3.0 * coef * N,
+                                            3.0 * coef, B, c->stream));
+  TileArgs t = tile_args(c, c->disp, act);
+  for (int b = 0; b < B; ++b) t.coef[b] = (float)coef;
+  const int kr = kernel_reach_of(mak);
+  AssembleArgs as = assemble_args(c, kr, kr, out, act);
+  KLAUNCH(c, PM_K_DIPOLE,
+          both(launch_tile(t, TK_TAN_SPREAD, mak, 0, c->stream), launch_assemble(as, true, c->stream)));
+  return PM_OK;
+}
+
+static pm_status absmax_tangent(pm_ctx* c, const SlotCoef& tau, unsigned long long act) {
+  const long long N = c->g.N;
+  KLAUNCH(c, PM_K_FILL, launch_fill(c->umax, (long long)sizeof(float) * kMaxBatch, c->stream));
+  KLAUNCH(c, PM_K_MISC, launch_tan_drift(c->xbar, c->vbar, 3 * N, 3 * N, tau, (unsigned int*)c->umax,
+                                         c->cfg.batch, act, c->stream));
+  return PM_OK;
+}
+
+pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float* delta_dot_out) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers (the tangents live there)");
+  if (!c->ics_done) return fail(c, PM_ESTATE, "pm_jvp before pm_init_ics");
+  if (!w_dot || !delta_dot_out) return PM_EINVAL;
+  if (c->cfg.force != PM_FORCE_PM || c->cfg.antialias)
+    return fail(c, PM_EUNSUPPORTED, "the tangents cover the single-grid PM force");
+  if (c->cfg.lpt_order == 2) return fail(c, PM_EUNSUPPORTED, "the tangents cover Zel'dovich initial conditions");
+  const int B = c->cfg.batch, mak = c->cfg.mak, ord = c->cfg.grad_order;
+  const long long N = c->g.N;
+  const unsigned long long all = c->user_mask;
+  // primal initial state again from the stored white noise; tangent initial
+  // state psi(w_dot + (sigma8_dot / sigma8) w): psi is linear in w and, with
+  // the BBKS spectrum, proportional to sigma8
+  if (pm_status st = ic_chain(c, c->w, c->disp, c->vel, all)) return st;
+  SlotCoef k{};
+  for (int b = 0; b < B; ++b)
+    k.v[b] = (sigma8_dot && c->cfg.spectrum == PM_SPEC_BBKS) ? (float)(sigma8_dot[b] / c->slot_sigma8[b]) : 0.f;
+  float* weff = c->u_sorted;  // [B][N] of the [B][3][N] adjoint buffer, idle here
+  KLAUNCH(c, PM_K_MISC, launch_lincomb(w_dot, c->w, weff, N, k, B, all, c->stream));
+  if (pm_status st = ic_chain(c, weff, c->xbar, c->vbar, all)) return st;
+  int nmax = 0;
+  for (int b = 0; b < B; ++b) nmax = std::max(nmax, c->slot_steps[b]);
+  float* dd = reinterpret_cast<float*>(c->mesh);  // tangent contrast, then tangent potential
+  for (int n = 0; n < nmax; ++n) {
+    std::vector<double> tp(B, 0), s(B, 1), al(B, 1), be(B, 0), tq(B, 0);
+    SlotCoef t1{};
+    unsigned long long act = 0;
+    for (int b = 0; b < B; ++b) {
+      if (n >= c->slot_steps[b]) continue;
+      const StepCoef& sc = c->slot_table[b][n];
+      tp[b] = sc.tau1; s[b] = sc.s; al[b] = sc.alpha; be[b] = sc.beta; tq[b] = sc.tau2;
+      t1.v[b] = (float)sc.tau1;
+      act |= 1ull << b;
+    }
+    act &= all;
+    if (!act) continue;
+    // Xdot += tau1 Vdot (and max |Xdot|); the primal drift rides on the binning
+    if (pm_status st = absmax_tangent(c, t1, act)) return st;
+    pm_status st = potential(c, c->disp, c->vel, tp.data(), s.data(), act);
+    if (st) return st;
+    // J_A Xdot at X^{n+1/2}: the tangent contrast through the same multiplier,
+    // gathered like the force, plus the gather's position term
+    if ((st = tangent_contrast(c, mak, dd, act))) return st;
+    st = r2c_mesh(c, dd, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
+    if (st) return st;
+    if ((st = poisson_to_real(c, s.data(), dd, act))) return st;
+    TileArgs d = tile_args(c, c->disp, act);
+    d.mesh_in = c->phi;
+    d.acc_out = c->u_sorted;
+    KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(d, TK_TAN_DIRECT, mak, ord, c->stream));
+    TileArgs q = tile_args(c, c->disp, act);
+    q.mesh_in = dd;
+    q.acc_in = c->u_sorted;
+    for (int b = 0; b < B; ++b) {
+      q.alpha[b] = (float)al[b];
+      q.beta[b] = (float)be[b];
+      q.tau[b] = (float)tq[b];
+    }
+    KLAUNCH(c, PM_K_GATHER_KICK, launch_tile(q, TK_TAN_KICK, mak, ord, c->stream));
+    // the primal kick and drift
+    if ((st = kick(c, c->disp, al.data(), be.data(), tq.data(), nullptr, act))) return st;
+  }
+  // tangent of the final CIC contrast
+  if (pm_status st = absmax_tangent(c, SlotCoef{}, all)) return st;
+  if (pm_status st = bin(c, c->disp, nullptr, nullptr, 2, all)) return st;
+  if (pm_status st = tangent_contrast(c, 2, delta_dot_out, all)) return st;
+  c->ran = true;
+  return PM_OK;
+}
+
+pm_status pm_power_spectrum_jvp(pm_ctx* c, const float* delta_dot, int32_t n_bins, int32_t deconvolve_cic,
+                                double* k_mean, double* pk, double* pk_dot, int64_t* n_modes) {
+  if (!delta_dot || !pk_dot) return PM_EINVAL;
+  if (pm_status st = pm_power_spectrum(c, n_bins, deconvolve_cic, k_mean, pk, n_modes)) return st;
+  // the tangent's spectrum in the (now free) mesh buffer: n^2 rs <= n^3
+  const int n = c->cfg.n_g;
+  const unsigned long long act = c->user_mask;
+  float2* spec2 = reinterpret_cast<float2*>(c->mesh);
+  pm_status st = r2c_mesh(c, delta_dot, SRC_F32, c->g.mesh_stride, 1.0, 0.0, spec2, c->g.spec_stride, n, true, act);
+  if (st) return st;
+  const double L = c->cfg.box, n3 = (double)c->g.M;
+  KLAUNCH(c, PM_K_MISC, launch_pk(c->spec, c->g.spec_stride, n, c->cfg.batch, n_bins, 2.0 * M_PI / L,
+                                  L * L * L / (n3 * n3), c->d_cic4, deconvolve_cic, c->pk_partial, k_mean, pk_dot,
+                                  (long long*)n_modes, act, spec_rs(n), c->stream, spec2));
   return PM_OK;
 }
 

@@ -100,7 +100,7 @@ class PMSim:
     # --------------------------------------------------------------- calls
     _STATE_CALLS = frozenset({"pm_init_ics", "pm_step", "pm_run", "pm_adjoint", "pm_adjoint_full", "pm_set_state",
                               "pm_deposit",
-                              "pm_force", "pm_force_vjp", "pm_set_active", "pm_step_device"})
+                              "pm_force", "pm_force_vjp", "pm_set_active", "pm_step_device", "pm_jvp"})
 
     def _call(self, name, *args):
         if name in self._STATE_CALLS:
@@ -168,6 +168,30 @@ class PMSim:
         n = self._new(B, n_bins, dtype=torch.int64)
         self._call("pm_power_spectrum", int(n_bins), int(bool(deconvolve)), _ptr(k), _ptr(p), _ptr(n))
         return k, p, n
+
+    def jvp(self, w_dot, sigma8_dot=None):
+        """Forward-mode tangent of the final CIC contrast [B, M] along
+        (w_dot [B, N], sigma8_dot [B]); reruns the forward from the white
+        noise of init_ics and leaves the context at its final state."""
+        B = self.cfg.batch
+        wd = w_dot.to(self.device, torch.float32).contiguous().reshape(B, self.cfg.N)
+        sd = (C.c_double * B)(*[float(x) for x in sigma8_dot]) if sigma8_dot is not None else None
+        dd = self._new(B, self.cfg.M)
+        self._call("pm_jvp", _ptr(wd), sd, _ptr(dd))
+        return dd
+
+    def power_spectrum_jvp(self, delta_dot, n_bins, deconvolve=True):
+        """(k, P, P_dot, counts) of the current final state, P_dot the
+        tangent of P when the contrast moves along delta_dot [B, M]."""
+        B = self.cfg.batch
+        dd = delta_dot.to(self.device, torch.float32).contiguous().reshape(B, self.cfg.M)
+        k = self._new(B, n_bins, dtype=torch.float64)
+        p = self._new(B, n_bins, dtype=torch.float64)
+        pd = self._new(B, n_bins, dtype=torch.float64)
+        n = self._new(B, n_bins, dtype=torch.int64)
+        self._call("pm_power_spectrum_jvp", _ptr(dd), int(n_bins), int(bool(deconvolve)), _ptr(k), _ptr(p),
+                   _ptr(pd), _ptr(n))
+        return k, p, pd, n
 
     def density(self, fixed=False):
         B = self.cfg.batch

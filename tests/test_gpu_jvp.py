@@ -1,0 +1,137 @@
+"""GPU forward-mode tangents (pm_jvp, pm_power_spectrum_jvp) through the C
+ABI against the FP64 oracle (oracle/jvp.py, pinned by differences and by
+duality with the VJP): the tangent of the final density along a white-noise
+and sigma8 direction, the P(k) tangent on identical inputs, duality with the
+GPU adjoint, the large-scale sigma8 log-derivative, and the refusals."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import jvp as ojvp
+from oracle import philox as ophilox
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_05206_amd as P
+    P.load()
+
+
+def make_sim(d, adj=True, **kw):
+    from paper_2510_05206_amd import PMSim
+    return PMSim(synth.gpu_config(d, **kw), with_adjoint=adj)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def direction(n_p, seed):
+    return np.random.default_rng(seed).normal(size=n_p ** 3).astype(np.float32)
+
+
+# CIC: the tangent holds the kernel's first derivative, a step at every node
+# plane, and a particle whose FP32 and FP64 positions fall on two sides of
+# one changes its nodes by O(|Xdot|): with ~2 of 32^3 such particles the
+# relative L2 error is ~sqrt(2/N) ~ 1e-2.  TSC and PCS have continuous
+# derivatives.  With deconvolution the PCS multiplier grows to 1/W^2 ~ 5e4 at
+# the corner modes (TSC ~ 3e3), which scales the FP32 noise of the force
+# tangent there; the dynamics carries part of it to all scales (measured
+# 5e-3 overall, 8e-4 on the low modes, against 4e-6 and 1e-6 without
+# deconvolution).
+@pytest.mark.parametrize("wl,mak,dec,tol,tol_low", [("C4_SMALL", 2, False, 1e-2, 2e-3),
+                                                    ("C2_SMALL", 3, True, 1e-4, 1e-4),
+                                                    ("C2_SMALL", 3, False, 1e-4, 1e-4),
+                                                    ("C2_SMALL", 4, False, 1e-4, 1e-4),
+                                                    ("C2_SMALL", 4, True, 1e-2, 2e-3)])
+def test_density_tangent_matches_oracle(wl, mak, dec, tol, tol_low):
+    d = dict(getattr(synth, wl), mak=mak, grad_order=4, deconvolve=dec)
+    say("jvp", wl, mak, dec)
+    sim = make_sim(d)
+    sim.init_ics([synth.SEED_W])
+    sim.run()
+    delta_run = sim.density()
+    wd = direction(d["n_p"], 31)
+    dd = sim.jvp(torch.from_numpy(wd), [0.25]).cpu().numpy()[0]
+    assert torch.equal(sim.density(), delta_run)        # the primal rerun equals pm_run
+    prob = synth.oracle_problem(d)
+    w = ophilox.white_noise(synth.SEED_W, d["n_p"]).astype(np.float64)
+    _, _, _, ref = ojvp.run_jvp(prob, w, wd.astype(np.float64), 0.25)
+    err = rel_l2(dd, ref)
+    # the modes |m| < n_g / 8 per axis, where neither the kinks' white noise
+    # nor the deconvolution's gain reaches
+    n = d["n_g"]
+    keep = np.abs(np.fft.fftfreq(n, 1.0 / n)) < n // 8
+    sel = keep[:, None, None] & keep[None, :, None] & (np.arange(n // 2 + 1) < n // 8)[None, None, :]
+    low = rel_l2(np.fft.rfftn(dd.reshape(n, n, n))[sel], np.fft.rfftn(ref.reshape(n, n, n))[sel])
+    say(f"  tangent rel L2 {err:.2e}, low modes {low:.2e}")
+    assert err < tol and low < tol_low
+
+
+def test_pk_tangent_on_identical_inputs():
+    d = synth.C2_SMALL
+    sim = make_sim(d)
+    sim.init_ics([synth.SEED_W])
+    dd = sim.jvp(torch.from_numpy(direction(d["n_p"], 32)), [0.1])
+    delta = sim.density()
+    k, p, pd, n = (t.cpu().numpy()[0] for t in sim.power_spectrum_jvp(dd, 24))
+    kr, pr, pdr, nr = ojvp.power_spectrum_jvp(delta.cpu().numpy()[0].astype(np.float64),
+                                              dd.cpu().numpy()[0].astype(np.float64), d["box"], 24)
+    assert np.array_equal(n, nr)
+    assert np.abs(p / pr - 1).max() < 1e-5
+    assert np.abs(pd - pdr).max() < 1e-5 * np.abs(pdr).max()
+
+
+def test_tangent_and_adjoint_are_dual():
+    # <L_bar, J w_dot> = <J^T L_bar, w_dot> + dL/dsigma8 sigma8_dot, both sides on the GPU
+    d = synth.C4_SMALL
+    sim = make_sim(d)
+    sim.init_ics([synth.SEED_W])
+    wd = direction(d["n_p"], 33)
+    dd = sim.jvp(torch.from_numpy(wd), [0.2]).double()
+    g = torch.from_numpy(np.random.default_rng(34).normal(size=(1, d["n_g"] ** 3)).astype(np.float32)).cuda()
+    sim.init_ics([synth.SEED_W])
+    sim.run()
+    dw, ds = sim.adjoint(g)
+    lhs = float((g.double() * dd).sum())
+    rhs = float((dw.double() * torch.from_numpy(wd).cuda().double()).sum()) + float(ds[0]) * 0.2
+    say(f"duality {lhs:.6e} vs {rhs:.6e}")
+    assert abs(lhs - rhs) < 1e-3 * abs(lhs)
+
+
+def test_sigma8_log_derivative_is_two_on_linear_scales():
+    d = dict(synth.C4_SMALL, n_p=32, n_g=64, box=1000.0, n_steps=6)
+    sim = make_sim(d)
+    sim.init_ics([synth.SEED_W])
+    dd = sim.jvp(torch.zeros(d["n_p"] ** 3), [d["sigma8"]])
+    k, p, pd, n = (t.cpu().numpy()[0] for t in sim.power_spectrum_jvp(dd, 32))
+    logd = pd / p
+    say("d log P / d log sigma8:", np.round(logd[:8], 3))
+    assert abs(logd[0] - 2.0) < 0.03 and np.all(np.abs(logd[:3] - 2.0) < 0.1)
+
+
+def test_jvp_refusals():
+    from paper_2510_05206_amd import PMError
+    wd = torch.zeros(32 ** 3)
+    sim = make_sim(synth.C4_SMALL, adj=False)
+    sim.init_ics([1])
+    with pytest.raises(PMError, match="PM_ESTATE"):
+        sim.jvp(wd)
+    for bad in (dict(synth.C3_SMALL), dict(synth.C4_SMALL, antialias=1), dict(synth.C4_SMALL, lpt_order=2)):
+        sim = make_sim(bad)
+        sim.init_ics([1])
+        with pytest.raises(PMError, match="PM_EUNSUPPORTED"):
+            sim.jvp(wd)
