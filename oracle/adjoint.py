@@ -14,11 +14,13 @@ scatter/gather rules of App. "Custom VJP and JVP":
 * the transposed Fourier multiplier (conj K_c),
 * scatter w.r.t. positions (a gather of the mesh cotangent with grad W).
 
-The initial-condition VJP uses Psi^0 = D_start psi, V^0 = psi and the
+The initial-condition VJP uses Psi^0 = D_start psi, V^0 = psi (plus
+D^2 psi2 and 2 D psi2 at second order, psi2 quadratic in psi) and the
 transposed IC multiplier; with the BBKS spectrum psi is proportional to
-sigma8 and the BullFrog coefficients do not depend on it, so
-dL/dsigma8 = <psi_bar, psi> / sigma8 (0 for the power-law spectrum, whose
-amplitude is set by its rms displacement).
+sigma8 (psi2 to its square) and the BullFrog coefficients do not depend on
+it, so dL/dsigma8 = <psi_bar, psi> / sigma8 with psi_bar the total cotangent
+of psi (Euler's theorem for the quadratic term; 0 for the power-law
+spectrum, whose amplitude is set by its rms displacement).
 """
 from __future__ import annotations
 
@@ -129,8 +131,6 @@ def gradient(prob, w, dL_ddelta, progress=None, temporal=None):
     ``temporal`` (a list), if given, receives the per-step adjoints of
     (tau1, tau2, alpha, beta) (see reverse_cotangents)."""
     from .nbody import initial_state, run_from
-    if prob.lpt_order != 1:
-        raise NotImplementedError("the reverse pass covers Zel'dovich initial conditions")
     psi0, vel0, psi_lin = initial_state(prob, w)
     record = []
     psiN, _ = run_from(prob, psi0, vel0, record=record, progress=progress)
@@ -138,7 +138,11 @@ def gradient(prob, w, dL_ddelta, progress=None, temporal=None):
     xbar = density_vjp(psiN, prob.pm.n_p, prob.pm.n_g, dL_ddelta(delta))
     vbar = np.zeros_like(xbar)
     xbar, vbar = reverse_cotangents(prob, record, xbar, vbar, progress, temporal)
-    psibar = prob.D_start() * xbar + vbar
+    D = prob.D_start()
+    psibar = D * xbar + vbar
+    if prob.lpt_order == 2:
+        # Psi = D psi1 + D^2 psi2(psi1), V = psi1 + 2 D psi2(psi1)
+        psibar = psibar + ics.second_order_psi_vjp(psi_lin, prob.pm.n_p, D * D * xbar + 2.0 * D * vbar)
     wbar = ic_vjp(prob, psibar)
     # the power-law spectrum is normalised by its rms displacement, not by
     # sigma8, so there the initial conditions do not depend on sigma8

@@ -100,6 +100,80 @@ def second_order_psi(psi1, n):
     return np.stack([np.fft.ifftn(1j * kk[c] * inv * L2).real.reshape(-1) for c in range(3)])
 
 
+def _second_order_parts(psi1, n):
+    """The band-limited spectra of psi^(1), the derivative fields g_ij =
+    d psi_i / d q_j on the padded grid, and the helpers of second_order_psi."""
+    psi1 = np.asarray(psi1, dtype=np.float64)
+    P = np.stack([np.fft.fftn(psi1[c].reshape(n, n, n)) for c in range(3)])
+    m = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
+    band = np.abs(m) < n // 2
+    keep = band[:, None, None] & band[None, :, None] & band[None, None, :]
+    P = P * keep
+    k = 2.0 * np.pi * m / n
+    kk = [k[:, None, None], k[None, :, None], k[None, None, :]]
+    npad = 3 * n // 2
+    idx = m[band] % npad
+
+    def padded_real(spec):
+        big = np.zeros((npad, npad, npad), dtype=np.complex128)
+        big[np.ix_(idx, idx, idx)] = spec[np.ix_(band, band, band)]
+        return np.fft.ifftn(big).real * (npad / n) ** 3
+
+    def crop(big):
+        out = np.zeros((n, n, n), dtype=np.complex128)
+        out[np.ix_(band, band, band)] = big[np.ix_(idx, idx, idx)]
+        return out
+
+    g = [[padded_real(1j * kk[j] * P[i]) for j in range(3)] for i in range(3)]
+    k2 = kk[0] ** 2 + kk[1] ** 2 + kk[2] ** 2
+    inv = np.where(k2 > 0, -1.0 / np.where(k2 > 0, k2, 1.0), 0.0)
+    return g, kk, inv, band, idx, npad, crop
+
+
+def second_order_psi_vjp(psi1, n, psi2_bar):
+    """(d psi^(2) / d psi^(1))^T psi2_bar, shape (3, N): the transposes of
+    second_order_psi's steps in reverse order.  With M_c = -(3/7) i k_c / -k^2
+    the multiplier from mu to psi^(2)_c (odd and imaginary),
+      mu_bar = ifft_pad(pad(sum_c conj(M_c) fft(psi2_bar_c))) (real),
+    d mu / d g_ab = S delta_ab - g_ba (S the trace g_ii), and the transpose of
+    psi1_i -> g_ij = padded_real(i k_j fft(psi1_i)) maps g_bar to
+    ifft(-i k_j crop(fft_pad(g_bar))) (the (npad/n)^3 of padded_real and the
+    1/npad^3 of its inverse transform cancel against the crop's unnormalised
+    forward transform)."""
+    g, kk, inv, band, idx, npad, crop = _second_order_parts(psi1, n)
+    pb = np.asarray(psi2_bar, dtype=np.float64)
+    keep = band[:, None, None] & band[None, :, None] & band[None, None, :]
+    mbar = np.zeros((n, n, n), dtype=np.complex128)
+    for c in range(3):
+        Mc = 1j * kk[c] * inv * (-3.0 / 7.0)
+        mbar += np.conj(Mc) * np.fft.fftn(pb[c].reshape(n, n, n))
+    mbar *= keep
+    big = np.zeros((npad, npad, npad), dtype=np.complex128)
+    big[np.ix_(idx, idx, idx)] = mbar[np.ix_(band, band, band)]
+    mu_bar = np.fft.ifftn(big).real
+    S = g[0][0] + g[1][1] + g[2][2]
+    out = np.zeros((3, n ** 3))
+    for i in range(3):
+        for j in range(3):
+            gbar = mu_bar * ((S if i == j else 0.0) - g[j][i])
+            out[i] += np.fft.ifftn(-1j * kk[j] * crop(np.fft.fftn(gbar))).real.reshape(-1)
+    return out
+
+
+def second_order_psi_jvp(psi1, n, psi1_dot):
+    """d psi^(2) along psi1_dot: mu_dot = sum_ab (S delta_ab - g_ba) g_dot_ab
+    through the same crop and multiplier as second_order_psi."""
+    g, kk, inv, band, idx, npad, crop = _second_order_parts(psi1, n)
+    gd, _, _, _, _, _, _ = _second_order_parts(psi1_dot, n)
+    S = g[0][0] + g[1][1] + g[2][2]
+    mu_dot = np.zeros((npad, npad, npad))
+    for a in range(3):
+        for b in range(3):
+            mu_dot += ((S if a == b else 0.0) - g[b][a]) * gd[a][b]
+    L2 = -3.0 / 7.0 * crop(np.fft.fftn(mu_dot)) * (n / npad) ** 3
+    return np.stack([np.fft.ifftn(1j * kk[c] * inv * L2).real.reshape(-1) for c in range(3)])
+
+
 def lpt_state(psi1, psi2, D):
     """Displacement and D-time velocity of the LPT series truncated at second
     order (eq. LPT, D^n approximation): Psi = D psi1 + D^2 psi2, V = dPsi/dD."""

@@ -72,16 +72,18 @@ def density_jvp(psi, n_p, n_g, xdot):
 
 
 def initial_tangent(prob, w_dot, psi_lin, sigma8_dot=0.0):
-    """(Psi_dot, V_dot) at a_start for the Zel'dovich state Psi = D psi,
-    V = psi."""
-    if prob.lpt_order != 1:
-        raise NotImplementedError("the tangents cover Zel'dovich initial conditions")
+    """(Psi_dot, V_dot) at a_start for the state Psi = D psi (+ D^2 psi2),
+    V = psi (+ 2 D psi2)."""
     n = prob.pm.n_p
     psi_dot = ics.zeldovich_psi(np.asarray(w_dot, dtype=np.float64).reshape(n, n, n), prob.pm.box,
                                 prob.spectrum_fn(), prob.D_ref())
     if prob.spectrum == "bbks":  # the power-law amplitude is set by its rms displacement
         psi_dot = psi_dot + (sigma8_dot / prob.sigma8) * psi_lin
-    return prob.D_start() * psi_dot, psi_dot
+    D = prob.D_start()
+    if prob.lpt_order == 2:
+        psi2_dot = ics.second_order_psi_jvp(psi_lin, n, psi_dot)
+        return D * psi_dot + D * D * psi2_dot, psi_dot + 2.0 * D * psi2_dot
+    return D * psi_dot, psi_dot
 
 
 def run_jvp(prob, w, w_dot, sigma8_dot=0.0):

@@ -16,7 +16,8 @@ trajectory with 2LPT after every step).  Three independent checks:
 import numpy as np
 import pytest
 
-from oracle import cosmo, ics, nufft
+from oracle import cosmo, ics, nbody, nufft
+from oracle.force import PMConfig
 
 
 def lattice(n):
@@ -123,3 +124,50 @@ def test_bullfrog_stays_on_2lpt_in_eds(steps):
     # started on Zel'dovich, the run misses the second-order term
     Xz, _ = _bullfrog_direct(*ics.lpt_state(psi1, None, a0), n, steps, a0)
     assert np.linalg.norm(Xz - X1) > 0.3 * np.linalg.norm(psi2)
+
+
+def test_second_order_vjp_and_jvp_match_differences():
+    # the transposed and tangent maps of psi2(psi1) against central
+    # differences of second_order_psi (a quadratic map: the differences are
+    # exact up to rounding), their duality and Euler's identity for a
+    # homogeneous quadratic, <VJP(b), psi1> = 2 <b, psi2>
+    from oracle import ics
+    rng = np.random.default_rng(11)
+    n = 8
+    psi1 = rng.normal(size=(3, n ** 3))
+    b = rng.normal(size=(3, n ** 3))
+    d = rng.normal(size=(3, n ** 3))
+    eps = 1e-5
+    fd = (ics.second_order_psi(psi1 + eps * d, n) - ics.second_order_psi(psi1 - eps * d, n)) / (2 * eps)
+    jv = ics.second_order_psi_jvp(psi1, n, d)
+    assert np.linalg.norm(jv - fd) < 1e-9 * np.linalg.norm(fd)
+    vj = ics.second_order_psi_vjp(psi1, n, b)
+    assert abs(np.sum(vj * d) - np.sum(b * jv)) < 1e-12 * abs(np.sum(b * jv))
+    assert abs(np.sum(vj * psi1) - 2 * np.sum(b * ics.second_order_psi(psi1, n))) < 1e-12 * np.sum(np.abs(vj * psi1))
+
+
+def test_second_order_gradient_and_tangent_match_differences():
+    from oracle import adjoint, jvp
+    cfg = PMConfig(8, 16, 40.0, order=3, deconvolve=False, grad_order=4)
+    prob = nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=0.9, lpt_order=2)
+    n = cfg.n_p
+    rng = np.random.default_rng(12)
+    w = nbody.white_noise(prob, 6).astype(np.float64)
+    target = rng.normal(size=cfg.n_g ** 3)
+
+    def final(wv, s8):
+        p = nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=s8, lpt_order=2)
+        x, _ = nbody.run(p, w=wv.reshape(n, n, n))
+        return adjoint.final_density(p, x)
+
+    wbar, dsig, _ = adjoint.gradient(prob, w, lambda d: 2 * (d - target))
+    dirn = rng.normal(size=n ** 3)
+    eps = 1e-6
+    loss = lambda wv, s8: np.sum((final(wv, s8) - target) ** 2)
+    fd = (loss(w.reshape(-1) + eps * dirn, 0.9) - loss(w.reshape(-1) - eps * dirn, 0.9)) / (2 * eps)
+    assert abs(np.dot(wbar, dirn) - fd) < 1e-6 * abs(fd)
+    fd = (loss(w.reshape(-1), 0.9 + eps) - loss(w.reshape(-1), 0.9 - eps)) / (2 * eps)
+    assert abs(dsig - fd) < 1e-6 * abs(fd)
+    _, _, _, dd = jvp.run_jvp(prob, w, dirn, 0.2)
+    fd = (final(w.reshape(-1) + eps * dirn, 0.9 + 0.2 * eps) - final(w.reshape(-1) - eps * dirn, 0.9 - 0.2 * eps)) / (2 * eps)
+    assert np.linalg.norm(dd - fd) < 1e-7 * np.linalg.norm(fd)
