@@ -88,8 +88,9 @@ enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
  *                  perturbation theory" (eq. LPT, D^n approximation): 1 (or
  *                  0) Zel'dovich, 2 adds D^2 psi^(2) (eq. LPT_L at n = 2,
  *                  eq. helmholtz; de-aliased products).  2 needs
- *                  n_g >= 2 n_p and n_p >= 8; pm_adjoint then returns
- *                  PM_EUNSUPPORTED
+ *                  n_g >= 2 n_p and n_p >= 8; pm_adjoint pulls the
+ *                  cotangent back through the second-order term as well
+ *                  (pm_jvp returns PM_EUNSUPPORTED for it)
  *   stepper        0 BullFrog; 1 FastPM (Sec. "Time stepping")
  *   time_var       step spacing: 0 uniform in D, 1 in a, 2 in ln a
  *   antialias      1: interlaced grids for the PM force (Sec. "Discreteness

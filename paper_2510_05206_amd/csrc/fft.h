@@ -9,10 +9,16 @@ enum { SRC_I64 = 0, SRC_F32 = 1 };
 // second-order LPT grid (twice the lattice per axis) DST_MU_AB / DST_MU_ACC /
 // DST_MU_SQ accumulate the source mu from the derivative fields (dst = A, the
 // running diagonal sum, dst2 = mu), DST_IC2 adds the second-order term at the
-// lattice points (even nodes) to the state
-enum { DST_F32 = 0, DST_IC = 1, DST_MU_AB = 2, DST_MU_ACC = 3, DST_MU_SQ = 4, DST_IC2 = 5 };
+// lattice points (even nodes) to the state.  Reverse pass through the second
+// order: DST_ACC adds the row to dst; DST_GBAR_DIAG / DST_GBAR_OFF write the
+// cotangent of a derivative field g (the row) into dst: mu_bar (S - g) for a
+// diagonal field, -2 mu_bar g for an off-diagonal one, with mu_bar and the
+// diagonal sum S read from dst2 and dst2 + dst_stride (slot stride
+// 2 dst_stride there)
+enum { DST_F32 = 0, DST_IC = 1, DST_MU_AB = 2, DST_MU_ACC = 3, DST_MU_SQ = 4, DST_IC2 = 5, DST_ACC = 6,
+       DST_GBAR_DIAG = 7, DST_GBAR_OFF = 8 };
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_FUSED_H = 2, MODE_IC_C = 3, MODE_COMBINE_IC = 4, MODE_NUFFT_C = 5,
-       MODE_NUFFT_ADJ = 6, MODE_LPT_D = 7, MODE_FUSED_IL = 8 };
+       MODE_NUFFT_ADJ = 6, MODE_LPT_D = 7, MODE_FUSED_IL = 8, MODE_LPT_MUBAR = 9, MODE_LPT_DT = 10 };
 
 // z-row pass: real rows of n <-> half-spectrum rows of n/2+1
 struct RowLaunch {
@@ -73,6 +79,16 @@ struct ColArgs {
   // src_slot_stride), zero-padded to the modes |m| < n_p / 2, into dst3
   int comp2, src_rs;
   long long src_slot_stride;
+  // MODE_LPT_MUBAR (x pass on the padded grid): sum_c conj(h_c) S_c of the
+  // three particle-grid spectra S_c in src3 (comp_stride apart), h_c = i coef
+  // k_c / |k|^2 on the kept modes (the transpose of the second-order
+  // multiplier), zero-padded, then the inverse x transform
+  // MODE_LPT_DT (x pass on the padded grid, forward): the transpose of
+  // MODE_LPT_D, its real multiplier for (comp, comp2) times the transformed
+  // field, added into the particle-grid spectrum dst3 on the kept modes
+  // MODE_COMBINE_IC with combine_add: the combination is added to the
+  // spectrum already in data
+  int combine_add;
   unsigned long long active;  // bit b set: slot b takes part
   // pruning for spectra truncated to |m| < keep/2 per axis (keep = 0: none):
   // only columns iz < zlim (0 = all nh); keep_in: indices along the pass

@@ -411,6 +411,28 @@ __global__ void __launch_bounds__(256) k_c2r_rows_reg(const float2* __restrict__
     }
     return;
   }
+  if constexpr (DST == DST_ACC || DST == DST_GBAR_DIAG || DST == DST_GBAR_OFF) {
+#pragma unroll
+    for (int r = 0; r < S::E; ++r) {
+      const long long e = row * n + 2 * S::t_out(n1, r);
+      const float2 z = make_float2(v[r].x * scale, v[r].y * scale);
+      float2* op = reinterpret_cast<float2*>(dst + slot * dst_stride + e);
+      if constexpr (DST == DST_ACC) {
+        const float2 ov = *op;
+        *op = make_float2(ov.x + z.x, ov.y + z.y);
+      } else {
+        const float* mb = dst2 + slot * 2 * dst_stride + e;
+        const float2 m = *reinterpret_cast<const float2*>(mb);
+        if constexpr (DST == DST_GBAR_DIAG) {
+          const float2 sd = *reinterpret_cast<const float2*>(mb + dst_stride);
+          *op = make_float2(m.x * (sd.x - z.x), m.y * (sd.y - z.y));
+        } else {
+          *op = make_float2(-2.f * m.x * z.x, -2.f * m.y * z.y);
+        }
+      }
+    }
+    return;
+  }
   if constexpr (DST == DST_MU_AB || DST == DST_MU_ACC || DST == DST_MU_SQ) {
     // dst = A (running sum of the diagonal derivatives), dst2 = mu
 #pragma unroll
@@ -477,6 +499,7 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
     if (valid && !(a.keep_in && !kept(t))) {
       if constexpr (MODE == MODE_COMBINE_IC) {
         // x pass: t = ix, outer = iy: sum_c conj(h_c) S_c, h_c = i h
+        if (a.combine_add) x = a.data[col + t * stride_t];
         int mx = signed_mode(t, a.n), my = signed_mode(outer, a.n);
         float amp = a.amp[mx * mx + my * my + iz * iz] * a.fac[slot];
         int ms[3] = {mx, my, iz};
@@ -489,6 +512,29 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
           x.x += h * sv.y;
           x.y -= h * sv.x;
         }
+      } else if constexpr (MODE == MODE_LPT_MUBAR) {
+        // x pass: t = ix, outer = iy on the padded grid; kept modes only
+        const int mx = signed_mode(t, a.n), my = signed_mode(outer, a.n), np = a.n_p;
+        if (2 * (mx < 0 ? -mx : mx) < np && 2 * (my < 0 ? -my : my) < np && 2 * iz < np) {
+          const int ms[3] = {mx, my, iz};
+          const float k0 = 6.283185307179586f / (float)np;
+          float th2 = 0.f;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
+          if (th2 > 0.f) {
+            const float2* s3 = a.src3 + slot * a.src_slot_stride +
+                               (long long)((mx & (np - 1)) * np + (my & (np - 1))) * a.src_rs + iz;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const float2 sv = s3[q * a.comp_stride];
+              const float h = a.coef[slot] * (k0 * ms[q]) / th2;
+              x.x += h * sv.y;  // conj(i h) sv
+              x.y -= h * sv.x;
+            }
+          }
+        }
+      } else if constexpr (MODE == MODE_LPT_DT) {
+        x = a.data[col + t * stride_t];
       } else if constexpr (MODE == MODE_LPT_D) {
         // x pass: t = ix, outer = iy on the padded grid; kept modes only
         const int mx = signed_mode(t, a.n), my = signed_mode(outer, a.n), np = a.n_p;
@@ -514,7 +560,7 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
     v[r] = x;
   }
   constexpr bool kFwdFirst = MODE == MODE_FWD || MODE == MODE_FUSED_H || MODE == MODE_NUFFT_C ||
-                             MODE == MODE_NUFFT_ADJ || MODE == MODE_FUSED_IL;
+                             MODE == MODE_NUFFT_ADJ || MODE == MODE_FUSED_IL || MODE == MODE_LPT_DT;
   bool inverse_next = !kFwdFirst;  // input layout holds data for an inverse transform
   if constexpr (kFwdFirst) {
     freg::pass_a<S, false>(v, n1, a.tw, a.tws);
@@ -532,6 +578,23 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
         v[r].y *= h;
       }
       inverse_next = true;
+    }
+    if constexpr (MODE == MODE_LPT_DT) {
+      // output t = ix: the kept modes add h v to the particle-grid spectrum
+      if (!valid) return;
+      const int my = signed_mode(outer, a.n), np = a.n_p;
+#pragma unroll
+      for (int r = 0; r < S::E; ++r) {
+        const int t = S::t_out(n1, r), mx = signed_mode(t, a.n);
+        if (!(2 * (mx < 0 ? -mx : mx) < np && 2 * (my < 0 ? -my : my) < np && 2 * iz < np)) continue;
+        const int ms[3] = {mx, my, iz};
+        const float h = -(6.283185307179586f / (float)np) * (float)(ms[a.comp] * ms[a.comp2]) *
+                        a.amp[mx * mx + my * my + iz * iz] * a.fac[slot];
+        float2* q = a.dst3 + slot * a.src_slot_stride + (long long)((mx & (np - 1)) * np + (my & (np - 1))) * a.src_rs + iz;
+        const float2 qv = *q;
+        *q = make_float2(qv.x + h * v[r].x, qv.y + h * v[r].y);
+      }
+      return;
     }
     if constexpr (MODE == MODE_FUSED_IL) {
       const float inv_n = 1.f / (float)a.n;  // phi = pi (m_x + m_y + m_z) / n
@@ -639,6 +702,9 @@ static hipError_t launch_rows_reg(const RowLaunch& r) {
       case DST_MU_ACC: PM_C2R(DST_MU_ACC); break;
       case DST_MU_SQ: PM_C2R(DST_MU_SQ); break;
       case DST_IC2: PM_C2R(DST_IC2); break;
+      case DST_ACC: PM_C2R(DST_ACC); break;
+      case DST_GBAR_DIAG: PM_C2R(DST_GBAR_DIAG); break;
+      case DST_GBAR_OFF: PM_C2R(DST_GBAR_OFF); break;
       default: return hipErrorInvalidValue;
     }
 #undef PM_C2R
@@ -704,6 +770,8 @@ static hipError_t launch_cols_r(const ColArgs& a, int mode, int batch, hipStream
     case MODE_NUFFT_ADJ: k_cols_reg<L, C, MODE_NUFFT_ADJ><<<grid, 256, 0, s>>>(a); break;
     case MODE_LPT_D: k_cols_reg<L, C, MODE_LPT_D><<<grid, 256, 0, s>>>(a); break;
     case MODE_FUSED_IL: k_cols_reg<L, C, MODE_FUSED_IL><<<grid, 256, 0, s>>>(a); break;
+    case MODE_LPT_MUBAR: k_cols_reg<L, C, MODE_LPT_MUBAR><<<grid, 256, 0, s>>>(a); break;
+    case MODE_LPT_DT: k_cols_reg<L, C, MODE_LPT_DT><<<grid, 256, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -718,7 +786,8 @@ static hipError_t launch_cols(const ColArgs& a, int mode, int batch, hipStream_t
     return launch_cols_r<L, C>(a, mode, batch, s);
   } else {
     // the NUFFT passes and pruning exist only in the register kernels
-    if (mode == MODE_NUFFT_C || mode == MODE_NUFFT_ADJ || mode == MODE_LPT_D || mode == MODE_FUSED_IL || a.keep ||
+    if (mode == MODE_NUFFT_C || mode == MODE_NUFFT_ADJ || mode == MODE_LPT_D || mode == MODE_FUSED_IL ||
+        mode == MODE_LPT_MUBAR || mode == MODE_LPT_DT || a.keep ||
         a.zlim)
       return hipErrorInvalidValue;
     return launch_cols_c<L, 16>(a, mode, batch, s);

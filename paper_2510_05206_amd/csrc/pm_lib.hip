@@ -1633,6 +1633,138 @@ pm_status reverse_force_step_interlaced(pm_ctx* c, const double* s, const double
   return PM_OK;
 }
 
+// Reverse pass through the second-order displacement (the transposes of
+// lpt2 in reverse order): psi2_bar = D0^2 X_bar + 2 D0 V_bar on the lattice;
+// mu_bar on the padded grid through the conjugate multiplier; the cotangents
+// of the six derivative fields, mu_bar (S - g_ii) and -2 mu_bar g_ij
+// (d mu / d g, S the diagonal sum, the fields recomputed from the noise);
+// each transformed and pulled back through its real multiplier into the
+// particle-grid spectrum at icspec component 3, which the Zel'dovich
+// combination then adds to.
+static pm_status lpt2_adjoint(pm_ctx* c, unsigned long long act) {
+  const int np = c->cfg.n_p, P = 2 * np, B = c->cfg.batch;
+  const long long N = c->g.N, M = c->g.M;
+  float* A = reinterpret_cast<float*>(c->mesh);  // mu_bar, and S at A + M (slot stride 2M)
+  float* gb = c->phi;                              // one field's cotangent (slot stride M)
+  float2* fspec = c->spec;
+  float2* Q = c->icspec + 3 * c->icspec_comp;
+  float* psibar = c->u_sorted;
+  // psi2_bar = 2 D0 (D0/2 X_bar + V_bar); the factor 2 D0 rides on the multiplier
+  std::vector<float> half(B, (float)(0.5 * c->D0));
+  KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, half.data(), c->g.log2_np,
+                                       c->g.log2_pb, act, c->stream));
+  for (int comp = 0; comp < 3; ++comp) {
+    pm_status st = r2c_mesh(c, psibar + comp * N, SRC_F32, 3 * N, 1.0, 0.0, c->icspec + comp * c->icspec_comp,
+                            c->icspec_stride, np, true, act);
+    if (st) return st;
+  }
+  ColArgs m{};
+  m.data = fspec;
+  m.slot_stride = c->g.spec_stride;
+  m.n = P;
+  m.nh = P / 2 + 1;
+  m.rs = spec_rs(P);
+  m.tw = c->d_tw;
+  m.tws = c->Lmax / P;
+  m.src3 = c->icspec;
+  m.comp_stride = c->icspec_comp;
+  m.src_slot_stride = c->icspec_stride;
+  m.src_rs = spec_rs(np);
+  m.n_p = np;
+  m.active = act;
+  m.axis = 0;
+  m.zlim = np / 2;
+  m.keep = np;
+  m.keep_outer = 1;
+  for (int b = 0; b < B; ++b) m.coef[b] = (float)(3.0 / 7.0 / ((double)P * P * P) * 2.0 * c->D0);
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(m, MODE_LPT_MUBAR, B, c->stream));
+  ColArgs my = m;
+  my.axis = 1;
+  my.keep_outer = 0;
+  my.keep_in = 1;
+  KLAUNCH(c, PM_K_FFT_COLS, fft_cols(my, MODE_INV, B, c->stream));
+  RowLaunch rl{};
+  rl.n = P;
+  rl.rs = spec_rs(P);
+  rl.kz_lim = np / 2;
+  rl.n_rows = (long long)P * P;
+  rl.batch = B;
+  rl.inverse = true;
+  rl.src = fspec;
+  rl.src_stride = c->g.spec_stride;
+  rl.dst = A;
+  rl.dst_stride = 2 * M;
+  rl.dst_mode = DST_F32;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (P / 2);
+  rl.tws_full = c->Lmax / P;
+  rl.scale = 1.0;
+  rl.stream = c->stream;
+  rl.active = act;
+  KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
+  // the noise spectrum again (component 0; the psi2_bar spectra are spent)
+  pm_status st = r2c_mesh(c, c->w, SRC_F32, N, 1.0, 0.0, c->icspec, c->icspec_stride, np, true, act);
+  if (st) return st;
+  ColArgs a{};
+  a.n = P;
+  a.nh = P / 2 + 1;
+  a.rs = spec_rs(P);
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / P;
+  a.amp = c->d_amp;
+  a.active = act;
+  a.n_p = np;
+  for (int b = 0; b < B; ++b)
+    a.fac[b] = (float)(c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0);
+  a.src3 = c->icspec;
+  a.src_slot_stride = c->icspec_stride;
+  a.src_rs = spec_rs(np);
+  a.slot_stride = c->g.spec_stride;
+  a.data = fspec;
+  a.dst3 = fspec;
+  a.axis = 0;
+  a.zlim = np / 2;
+  a.keep = np;
+  a.keep_outer = 1;
+  auto field = [&](int i, int j, int mode, float* dst, long long dst_stride, float* dst2) -> pm_status {
+    a.comp = i;
+    a.comp2 = j;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_LPT_D, B, c->stream));
+    ColArgs y = a;
+    y.axis = 1;
+    y.keep_outer = 0;
+    y.keep_in = 1;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
+    RowLaunch r = rl;
+    r.dst_mode = mode;
+    r.dst = dst;
+    r.dst_stride = dst_stride;
+    r.dst2 = dst2;
+    KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(r));
+    return PM_OK;
+  };
+  // S = g_00 + g_11 + g_22
+  for (int i = 0; i < 3; ++i)
+    if ((st = field(i, i, i ? DST_ACC : DST_F32, A + M, 2 * M, nullptr))) return st;
+  for (int b = 0; b < B; ++b)
+    if ((act >> b) & 1ull)
+      KLAUNCH(c, PM_K_FILL, launch_fill(Q + b * c->icspec_stride, (long long)sizeof(float2) * c->icspec_comp,
+                                        c->stream));
+  const int pairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  for (int q = 0; q < 6; ++q) {
+    const int i = pairs[q][0], j = pairs[q][1];
+    if ((st = field(i, j, i == j ? DST_GBAR_DIAG : DST_GBAR_OFF, gb, M, A))) return st;
+    st = r2c_mesh(c, gb, SRC_F32, M, 1.0, 0.0, fspec, c->g.spec_stride, P, false, act, np);
+    if (st) return st;
+    ColArgs t = a;
+    t.dst3 = Q;
+    t.comp = i;
+    t.comp2 = j;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(t, MODE_LPT_DT, B, c->stream));
+  }
+  return PM_OK;
+}
+
 pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8, double* dL_dtime);
 
 pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8) {
@@ -1644,8 +1776,6 @@ pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, doubl
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!c->ran) return fail(c, PM_ESTATE, "pm_adjoint before pm_run");
   if (!dL_ddelta || !dL_dw || !dL_dsigma8) return PM_EINVAL;
-  if (c->cfg.lpt_order == 2)
-    return fail(c, PM_EUNSUPPORTED, "the adjoint covers Zel'dovich initial conditions only");
   const int B = c->cfg.batch, np = c->cfg.n_p;
   const long long N = c->g.N, M = c->g.M;
   const double mfac = (double)M / (double)N;
@@ -1725,6 +1855,9 @@ pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, doubl
     }
   }
   // initial conditions: psi_bar = D0 X_bar + V_bar, w_bar = sum_c T_c^T psi_bar_c
+  // (plus the second-order term's pullback, gathered first)
+  if (c->cfg.lpt_order == 2)
+    if (pm_status st = lpt2_adjoint(c, c->user_mask)) return st;
   std::vector<float> d0(B, (float)c->D0);
   float* psibar = c->u_sorted;
   KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->g.log2_np, c->g.log2_pb,
@@ -1751,6 +1884,7 @@ pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, doubl
   ca.axis = 0;
   for (int b = 0; b < B; ++b)
     ca.fac[b] = (float)(c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0);
+  ca.combine_add = c->cfg.lpt_order == 2;
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(ca, MODE_COMBINE_IC, B, c->stream));
   ca.axis = 1;
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(ca, MODE_INV, B, c->stream));
