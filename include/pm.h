@@ -88,9 +88,8 @@ enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
  *                  perturbation theory" (eq. LPT, D^n approximation): 1 (or
  *                  0) Zel'dovich, 2 adds D^2 psi^(2) (eq. LPT_L at n = 2,
  *                  eq. helmholtz; de-aliased products).  2 needs
- *                  n_g >= 2 n_p and n_p >= 8; pm_adjoint pulls the
- *                  cotangent back through the second-order term as well
- *                  (pm_jvp returns PM_EUNSUPPORTED for it)
+ *                  n_g >= 2 n_p and n_p >= 8; pm_adjoint and pm_jvp
+ *                  differentiate through the second-order term as well
  *   stepper        0 BullFrog; 1 FastPM (Sec. "Time stepping")
  *   time_var       step spacing: 0 uniform in D, 1 in a, 2 in ln a
  *   antialias      1: interlaced grids for the PM force (Sec. "Discreteness
@@ -274,9 +273,15 @@ pm_status pm_power_spectrum(pm_ctx* ctx, int32_t n_bins, int32_t deconvolve_cic,
  * the power-law spectrum, whose amplitude is not set by sigma8);
  * delta_dot_out: device [B][n_g^3], the tangent of the final CIC contrast.
  * Needs a workspace bound with adjoint buffers (the tangents use them;
- * PM_ESTATE otherwise); single-grid PM force and Zel'dovich initial
- * conditions only (PM_EUNSUPPORTED otherwise). */
+ * PM_ESTATE otherwise); single-grid PM force only (PM_EUNSUPPORTED
+ * otherwise).  With second-order initial conditions the tangent of psi2 is
+ * its bilinear form in (psi, psi_dot). */
 pm_status pm_jvp(pm_ctx* ctx, const float* w_dot, const double* sigma8_dot, float* delta_dot_out);
+
+/* The tangent displacement and velocity of the final state after pm_jvp
+ * (device [B][3][N], lattice order; either may be NULL).  PM_ESTATE unless
+ * pm_jvp was the last call that moved the state. */
+pm_status pm_get_tangent(pm_ctx* ctx, float* disp_dot, float* vel_dot);
 
 /* pm_power_spectrum of the current state plus pk_dot (device [B][n_bins]),
  * the tangent of P(k_b) when the contrast moves along delta_dot (device

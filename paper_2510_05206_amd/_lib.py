@@ -64,6 +64,7 @@ EXPORTS = {
     "pm_adjoint_full": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_power_spectrum": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pm_get_tangent": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pm_power_spectrum_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p]),
     "pm_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -103,6 +103,9 @@ struct SlotCoef {
 // out = a + coef[slot] x over n floats per slot (slot stride n)
 hipError_t launch_lincomb(const float* a, const float* x, float* out, long long n, const SlotCoef& coef, int batch,
                           unsigned long long active, hipStream_t s);
+// out = a b elementwise over n floats per slot (slot strides sa, sb, so)
+hipError_t launch_mul(const float* a, long long sa, const float* b, long long sb, float* out, long long so,
+                      long long n, int batch, unsigned long long active, hipStream_t s);
 // xd += tau[slot] vd over n floats per slot (stride `stride`), then
 // amax[slot] = max(amax[slot], max |xd|) as float bits (amax starts at 0)
 hipError_t launch_tan_drift(float* xd, const float* vd, long long n, long long stride, const SlotCoef& tau,

@@ -39,6 +39,22 @@ hipError_t launch_lincomb(const float* a, const float* x, float* out, long long 
   return hipGetLastError();
 }
 
+__global__ void k_mul(const float* a, long long sa, const float* b, long long sb, float* out, long long so,
+                      long long n, unsigned long long active) {
+  const int slot = blockIdx.y;
+  if (!((active >> slot) & 1ull)) return;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[slot * so + i] = a[slot * sa + i] * b[slot * sb + i];
+}
+
+hipError_t launch_mul(const float* a, long long sa, const float* b, long long sb, float* out, long long so,
+                      long long n, int batch, unsigned long long active, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_mul<<<dim3((unsigned)blocks, batch), 256, 0, s>>>(a, sa, b, sb, out, so, n, active);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) k_tan_drift(float* xd, const float* vd, long long n, long long stride,
                                                    SlotCoef tau, unsigned int* amax, unsigned long long active) {
   __shared__ float red[256];

@@ -50,7 +50,8 @@ struct pm_ctx {
   float* force3 = nullptr;           // NUFFT: 3 force meshes [B][3][M]
   float2* spec2 = nullptr;           // NUFFT: per-component spectrum; interlaced PM: the second grid's
   float* accbuf = nullptr;           // interlaced PM: one grid's per-particle terms [B][6][N]
-  float* phi2 = nullptr;             // interlaced PM: the second grid's potential (in the mesh buffer)
+  float* phi2 = nullptr;
+  bool tangent_valid = false;        // xbar/vbar hold pm_jvp's final tangents             // interlaced PM: the second grid's potential (in the mesh buffer)
   float *disp = nullptr, *vel = nullptr, *w = nullptr, *xbar = nullptr, *vbar = nullptr;
   long long* mesh = nullptr;
   float2* spec = nullptr;
@@ -752,6 +753,9 @@ pm_status kick(pm_ctx* c, float* disp, const double* alpha, const double* beta, 
 // while the initial state is built): the mesh holds A = running diagonal sum
 // and mu (P^3 floats each per slot), spec and the tile scratch hold P-grid
 // half spectra.
+pm_status lpt2_from_mu(pm_ctx* c, const float* mu, long long mu_stride, float* vel, float* disp,
+                       unsigned long long act);
+
 pm_status lpt2(pm_ctx* c, unsigned long long act) {
   const int np = c->cfg.n_p, P = 2 * np, B = c->cfg.batch;
   const long long N = c->g.N, M = c->g.M;  // M = n_g^3 >= P^3
@@ -811,8 +815,33 @@ pm_status lpt2(pm_ctx* c, unsigned long long act) {
     rl.dst_mode = epi[q];
     KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(rl));
   }
-  pm_status st = r2c_mesh(c, A + M, SRC_F32, 2 * M, 1.0, 0.0, fspec, c->g.spec_stride, P, false, act, np);
+  return lpt2_from_mu(c, A + M, 2 * M, c->vel, c->disp, act);
+}
+
+// psi2 = (3/7) i k / k^2 of the source mu (padded grid, slot stride
+// mu_stride) on the kept modes, read off at the lattice points: adds
+// 2 D0 psi2 to vel and D0^2 psi2 to disp (lattice-block order)
+pm_status lpt2_from_mu(pm_ctx* c, const float* mu, long long mu_stride, float* vel, float* disp,
+                       unsigned long long act) {
+  const int np = c->cfg.n_p, P = 2 * np, B = c->cfg.batch;
+  const long long N = c->g.N;
+  float2* fspec = c->spec;
+  float2* cspec = reinterpret_cast<float2*>(c->scratch);
+  pm_status st = r2c_mesh(c, mu, SRC_F32, mu_stride, 1.0, 0.0, fspec, c->g.spec_stride, P, false, act, np);
   if (st) return st;
+  RowLaunch rl{};
+  rl.n = P;
+  rl.rs = spec_rs(P);
+  rl.kz_lim = np / 2;
+  rl.n_rows = (long long)P * P;
+  rl.batch = B;
+  rl.inverse = true;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (P / 2);
+  rl.tws_full = c->Lmax / P;
+  rl.stream = c->stream;
+  rl.active = act;
+  rl.src_stride = c->g.spec_stride;
   ColArgs x{};
   x.data = fspec;
   x.dst3 = cspec;
@@ -848,8 +877,8 @@ pm_status lpt2(pm_ctx* c, unsigned long long act) {
     y.keep_outer = 0;
     y.keep_in = 1;
     KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
-    r2.dst = c->vel + comp * N;
-    r2.dst2 = c->disp + comp * N;
+    r2.dst = vel + comp * N;
+    r2.dst2 = disp + comp * N;
     KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(r2));
   }
   return PM_OK;
@@ -1103,6 +1132,7 @@ pm_status pm_set_slot_params(pm_ctx* c, const int32_t* n_steps, const double* si
 static pm_status ic_chain(pm_ctx* c, const float* w, float* disp, float* vel, unsigned long long act);
 
 pm_status pm_init_ics(pm_ctx* c, const uint64_t* seeds, const float* w_in, float* w_out) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = check_bound(c)) return st;
   if (!seeds && !w_in) return fail(c, PM_EINVAL, "need seeds or w_in");
   const int B = c->cfg.batch, np = c->cfg.n_p;
@@ -1190,6 +1220,7 @@ static pm_status step_common(pm_ctx* c, const double* tau_pre, bool pre_drift, c
 }
 
 pm_status pm_step(pm_ctx* c, const int32_t* step_index) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = check_bound(c)) return st;
   if (!c->ics_done) return fail(c, PM_ESTATE, "pm_step before pm_init_ics");
   if (!step_index) return PM_EINVAL;
@@ -1281,6 +1312,7 @@ static pm_status device_step_launches(pm_ctx* c) {
 }
 
 pm_status pm_step_device(pm_ctx* c) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = device_steps_ok(c)) return st;
   if (!c->ics_done) return fail(c, PM_ESTATE, "pm_step_device before pm_init_ics");
   if (pm_status st = upload_schedules(c)) return st;
@@ -1329,6 +1361,7 @@ pm_status pm_get_step_index(pm_ctx* c, int32_t* step_index) {
 static pm_status run_steps(pm_ctx* c);
 
 pm_status pm_run(pm_ctx* c) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = check_bound(c)) return st;
   if (!c->ics_done) return fail(c, PM_ESTATE, "pm_run before pm_init_ics");
   if (!c->use_graph || c->prof) {
@@ -1772,6 +1805,7 @@ pm_status pm_adjoint(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL
 }
 
 pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, double* dL_dsigma8, double* dL_dtime) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!c->ran) return fail(c, PM_ESTATE, "pm_adjoint before pm_run");
@@ -1964,6 +1998,89 @@ static pm_status absmax_tangent(pm_ctx* c, const SlotCoef& tau, unsigned long lo
   return PM_OK;
 }
 
+// Tangent of the second-order term along the noise w_eff (whose spectrum
+// is at icspec component 3, left there by its IC chain): with g the six
+// derivative fields of w and gd those of w_eff, S and Sd their traces,
+//   mu_dot = S Sd - sum_i g_ii gd_ii - 2 sum_{i<j} g_ij gd_ij,
+// then the same multiplier as the primal term, added to (xbar, vbar).
+static pm_status lpt2_tangent(pm_ctx* c, unsigned long long act) {
+  const int np = c->cfg.n_p, P = 2 * np, B = c->cfg.batch;
+  const long long N = c->g.N, M = c->g.M, P3 = (long long)P * P * P;
+  float* F = reinterpret_cast<float*>(c->mesh);  // Sd, then -c g_ij (slot stride 2M)
+  float* mud = F + M;                             // mu_dot (slot stride 2M)
+  float* S = c->phi;                              // trace of g (slot stride M)
+  pm_status st = r2c_mesh(c, c->w, SRC_F32, N, 1.0, 0.0, c->icspec, c->icspec_stride, np, true, act);
+  if (st) return st;
+  ColArgs a{};
+  a.n = P;
+  a.nh = P / 2 + 1;
+  a.rs = spec_rs(P);
+  a.tw = c->d_tw;
+  a.tws = c->Lmax / P;
+  a.amp = c->d_amp;
+  a.active = act;
+  a.n_p = np;
+  for (int b = 0; b < B; ++b)
+    a.fac[b] = (float)(c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0);
+  a.src_slot_stride = c->icspec_stride;
+  a.src_rs = spec_rs(np);
+  a.slot_stride = c->g.spec_stride;
+  a.data = c->spec;
+  a.dst3 = c->spec;
+  a.axis = 0;
+  a.zlim = np / 2;
+  a.keep = np;
+  a.keep_outer = 1;
+  RowLaunch rl{};
+  rl.n = P;
+  rl.rs = spec_rs(P);
+  rl.kz_lim = np / 2;
+  rl.n_rows = (long long)P * P;
+  rl.batch = B;
+  rl.inverse = true;
+  rl.src = c->spec;
+  rl.src_stride = c->g.spec_stride;
+  rl.tw = c->d_tw;
+  rl.tws_half = c->Lmax / (P / 2);
+  rl.tws_full = c->Lmax / P;
+  rl.stream = c->stream;
+  rl.active = act;
+  const float2* wspec = c->icspec;                           // the primal noise
+  const float2* dspec = c->icspec + 3 * c->icspec_comp;      // the tangent noise
+  auto field = [&](const float2* src, int i, int j, int mode, double scale, float* dst, long long stride,
+                   float* dst2) -> pm_status {
+    a.src3 = src;
+    a.comp = i;
+    a.comp2 = j;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(a, MODE_LPT_D, B, c->stream));
+    ColArgs y = a;
+    y.axis = 1;
+    y.keep_outer = 0;
+    y.keep_in = 1;
+    KLAUNCH(c, PM_K_FFT_COLS, fft_cols(y, MODE_INV, B, c->stream));
+    RowLaunch r = rl;
+    r.dst_mode = mode;
+    r.scale = scale;
+    r.dst = dst;
+    r.dst_stride = stride;
+    r.dst2 = dst2;
+    KLAUNCH(c, PM_K_FFT_ROWS, fft_rows(r));
+    return PM_OK;
+  };
+  for (int i = 0; i < 3; ++i) {
+    if ((st = field(wspec, i, i, i ? DST_ACC : DST_F32, 1.0, S, M, nullptr))) return st;
+    if ((st = field(dspec, i, i, i ? DST_ACC : DST_F32, 1.0, F, 2 * M, nullptr))) return st;
+  }
+  KLAUNCH(c, PM_K_MISC, launch_mul(S, M, F, 2 * M, mud, 2 * M, P3, B, act, c->stream));
+  const int pairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  for (int q = 0; q < 6; ++q) {
+    const int i = pairs[q][0], j = pairs[q][1];
+    if ((st = field(wspec, i, j, DST_F32, i == j ? -1.0 : -2.0, F, 2 * M, nullptr))) return st;
+    if ((st = field(dspec, i, j, DST_MU_ACC, 1.0, F, 2 * M, mud))) return st;
+  }
+  return lpt2_from_mu(c, mud, 2 * M, c->vbar, c->xbar, act);
+}
+
 pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float* delta_dot_out) {
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers (the tangents live there)");
@@ -1971,7 +2088,6 @@ pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float*
   if (!w_dot || !delta_dot_out) return PM_EINVAL;
   if (c->cfg.force != PM_FORCE_PM || c->cfg.antialias)
     return fail(c, PM_EUNSUPPORTED, "the tangents cover the single-grid PM force");
-  if (c->cfg.lpt_order == 2) return fail(c, PM_EUNSUPPORTED, "the tangents cover Zel'dovich initial conditions");
   const int B = c->cfg.batch, mak = c->cfg.mak, ord = c->cfg.grad_order;
   const long long N = c->g.N;
   const unsigned long long all = c->user_mask;
@@ -1979,12 +2095,16 @@ pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float*
   // state psi(w_dot + (sigma8_dot / sigma8) w): psi is linear in w and, with
   // the BBKS spectrum, proportional to sigma8
   if (pm_status st = ic_chain(c, c->w, c->disp, c->vel, all)) return st;
+  if (c->cfg.lpt_order == 2)
+    if (pm_status st = lpt2(c, all)) return st;
   SlotCoef k{};
   for (int b = 0; b < B; ++b)
     k.v[b] = (sigma8_dot && c->cfg.spectrum == PM_SPEC_BBKS) ? (float)(sigma8_dot[b] / c->slot_sigma8[b]) : 0.f;
   float* weff = c->u_sorted;  // [B][N] of the [B][3][N] adjoint buffer, idle here
   KLAUNCH(c, PM_K_MISC, launch_lincomb(w_dot, c->w, weff, N, k, B, all, c->stream));
   if (pm_status st = ic_chain(c, weff, c->xbar, c->vbar, all)) return st;
+  if (c->cfg.lpt_order == 2)
+    if (pm_status st = lpt2_tangent(c, all)) return st;
   int nmax = 0;
   for (int b = 0; b < B; ++b) nmax = std::max(nmax, c->slot_steps[b]);
   float* dd = reinterpret_cast<float*>(c->mesh);  // tangent contrast, then tangent potential
@@ -2032,8 +2152,10 @@ pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float*
   if (pm_status st = bin(c, c->disp, nullptr, nullptr, 2, all)) return st;
   if (pm_status st = tangent_contrast(c, 2, delta_dot_out, all)) return st;
   c->ran = true;
+  c->tangent_valid = true;
   return PM_OK;
 }
+
 
 pm_status pm_power_spectrum_jvp(pm_ctx* c, const float* delta_dot, int32_t n_bins, int32_t deconvolve_cic,
                                 double* k_mean, double* pk, double* pk_dot, int64_t* n_modes) {
@@ -2092,7 +2214,18 @@ pm_status pm_get_state(pm_ctx* c, float* disp, float* vel) {
   return PM_OK;
 }
 
+pm_status pm_get_tangent(pm_ctx* c, float* disp_dot, float* vel_dot) {
+  if (pm_status st = check_bound(c)) return st;
+  if (!c->tangent_valid) return fail(c, PM_ESTATE, "no tangents: pm_jvp was not the last call that moved the state");
+  if (disp_dot)
+    if (pm_status st = to_user_order(c, c->xbar, disp_dot)) return st;
+  if (vel_dot)
+    if (pm_status st = to_user_order(c, c->vbar, vel_dot)) return st;
+  return PM_OK;
+}
+
 pm_status pm_set_state(pm_ctx* c, const float* disp, const float* vel) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = check_bound(c)) return st;
   if (!disp || !vel) return PM_EINVAL;
   if (pm_status st = from_user_order(c, disp, c->disp)) return st;
@@ -2103,6 +2236,7 @@ pm_status pm_set_state(pm_ctx* c, const float* disp, const float* vel) {
 }
 
 pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_out) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = check_bound(c)) return st;
   if (!disp || !mesh_out || (mak != 2 && mak != 3 && mak != 4 && mak != 6)) return PM_EINVAL;
   if (mak == 6 && c->cfg.force != PM_FORCE_NUFFT)
@@ -2122,6 +2256,7 @@ pm_status pm_deposit(pm_ctx* c, const float* disp, int32_t mak, int64_t* mesh_ou
 }
 
 pm_status pm_force(pm_ctx* c, const float* disp, double s, float* acc_out) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = check_bound(c)) return st;
   if (!disp || !acc_out) return PM_EINVAL;
   const int B = c->cfg.batch;
@@ -2136,6 +2271,7 @@ pm_status pm_force(pm_ctx* c, const float* disp, double s, float* acc_out) {
 }
 
 pm_status pm_force_vjp(pm_ctx* c, const float* disp, double s, const float* u, int32_t parts, float* xbar_out) {
+  if (c) c->tangent_valid = false;
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers");
   if (!disp || !u || !xbar_out || parts < 1 || parts > 3) return PM_EINVAL;

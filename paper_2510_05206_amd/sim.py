@@ -180,6 +180,13 @@ class PMSim:
         self._call("pm_jvp", _ptr(wd), sd, _ptr(dd))
         return dd
 
+    def get_tangent(self):
+        """(Xdot, Vdot) [B, 3, N] of the final state after jvp."""
+        B, N = self.cfg.batch, self.cfg.N
+        x, v = self._new(B, 3, N), self._new(B, 3, N)
+        self._call("pm_get_tangent", _ptr(x), _ptr(v))
+        return x, v
+
     def power_spectrum_jvp(self, delta_dot, n_bins, deconvolve=True):
         """(k, P, P_dot, counts) of the current final state, P_dot the
         tangent of P when the contrast moves along delta_dot [B, M]."""

@@ -43,42 +43,41 @@ def direction(n_p, seed):
     return np.random.default_rng(seed).normal(size=n_p ** 3).astype(np.float32)
 
 
-# CIC: the tangent holds the kernel's first derivative, a step at every node
-# plane, and a particle whose FP32 and FP64 positions fall on two sides of
-# one changes its nodes by O(|Xdot|): with ~2 of 32^3 such particles the
-# relative L2 error is ~sqrt(2/N) ~ 1e-2.  TSC and PCS have continuous
-# derivatives.  With deconvolution the PCS multiplier grows to 1/W^2 ~ 5e4 at
-# the corner modes (TSC ~ 3e3), which scales the FP32 noise of the force
-# tangent there; the dynamics carries part of it to all scales (measured
-# 5e-3 overall, 8e-4 on the low modes, against 4e-6 and 1e-6 without
-# deconvolution).
-@pytest.mark.parametrize("wl,mak,dec,tol,tol_low", [("C4_SMALL", 2, False, 1e-2, 2e-3),
-                                                    ("C2_SMALL", 3, True, 1e-4, 1e-4),
-                                                    ("C2_SMALL", 3, False, 1e-4, 1e-4),
-                                                    ("C2_SMALL", 4, False, 1e-4, 1e-4),
-                                                    ("C2_SMALL", 4, True, 1e-2, 2e-3)])
-def test_density_tangent_matches_oracle(wl, mak, dec, tol, tol_low):
-    d = dict(getattr(synth, wl), mak=mak, grad_order=4, deconvolve=dec)
-    say("jvp", wl, mak, dec)
+# The final contrast's tangent is a CIC scatter with the gradient kernel,
+# which steps at every node plane: a particle whose FP32 and FP64 positions
+# fall on two sides of one moves its nodes by O(|Xdot|), ~sqrt(k/N) in
+# relative L2 for k such particles (early states sit near the nodes, so k is
+# a few even at 32^3), so the contrast is held to 2e-2 and its modes
+# |m| < n_g / 8 (where that white noise is thin) to 2e-3.  The tangent
+# positions carry no such steps when the force kernel has a continuous
+# derivative (TSC, PCS): 1e-4; with the CIC force the same steps enter the
+# dynamics (measured 2e-6 here): 1e-3.
+@pytest.mark.parametrize("wl,mak,dec,lpt,tol_x", [("C4_SMALL", 2, False, 1, 1e-3), ("C2_SMALL", 3, True, 1, 1e-4),
+                                                  ("C2_SMALL", 3, False, 1, 1e-4), ("C2_SMALL", 4, False, 1, 1e-4),
+                                                  ("C2_SMALL", 4, True, 1, 1e-4), ("C2_SMALL", 3, False, 2, 1e-4),
+                                                  ("C1", 3, False, 2, 1e-4)])
+def test_tangent_matches_oracle(wl, mak, dec, lpt, tol_x):
+    d = dict(getattr(synth, wl), mak=mak, grad_order=4, deconvolve=dec, lpt_order=lpt)
+    say("jvp", wl, mak, dec, lpt)
     sim = make_sim(d)
     sim.init_ics([synth.SEED_W])
     sim.run()
     delta_run = sim.density()
     wd = direction(d["n_p"], 31)
     dd = sim.jvp(torch.from_numpy(wd), [0.25]).cpu().numpy()[0]
+    xd = sim.get_tangent()[0].cpu().numpy()[0]
     assert torch.equal(sim.density(), delta_run)        # the primal rerun equals pm_run
     prob = synth.oracle_problem(d)
     w = ophilox.white_noise(synth.SEED_W, d["n_p"]).astype(np.float64)
-    _, _, _, ref = ojvp.run_jvp(prob, w, wd.astype(np.float64), 0.25)
+    _, xref, _, ref = ojvp.run_jvp(prob, w, wd.astype(np.float64), 0.25)
+    ex = rel_l2(xd, xref)
     err = rel_l2(dd, ref)
-    # the modes |m| < n_g / 8 per axis, where neither the kinks' white noise
-    # nor the deconvolution's gain reaches
     n = d["n_g"]
     keep = np.abs(np.fft.fftfreq(n, 1.0 / n)) < n // 8
     sel = keep[:, None, None] & keep[None, :, None] & (np.arange(n // 2 + 1) < n // 8)[None, None, :]
     low = rel_l2(np.fft.rfftn(dd.reshape(n, n, n))[sel], np.fft.rfftn(ref.reshape(n, n, n))[sel])
-    say(f"  tangent rel L2 {err:.2e}, low modes {low:.2e}")
-    assert err < tol and low < tol_low
+    say(f"  tangent positions rel L2 {ex:.2e}; contrast {err:.2e}, its low modes {low:.2e}")
+    assert ex < tol_x and err < 2e-2 and low < 2e-3
 
 
 def test_pk_tangent_on_identical_inputs():
@@ -130,7 +129,7 @@ def test_jvp_refusals():
     sim.init_ics([1])
     with pytest.raises(PMError, match="PM_ESTATE"):
         sim.jvp(wd)
-    for bad in (dict(synth.C3_SMALL), dict(synth.C4_SMALL, antialias=1), dict(synth.C4_SMALL, lpt_order=2)):
+    for bad in (dict(synth.C3_SMALL), dict(synth.C4_SMALL, antialias=1)):
         sim = make_sim(bad)
         sim.init_ics([1])
         with pytest.raises(PMError, match="PM_EUNSUPPORTED"):
