@@ -64,6 +64,14 @@ def force_jvp(cfg: PMConfig, psi, s, xdot):
     return out
 
 
+def problem_force_jvp(prob, psi, s, xdot):
+    """JVP of the force the problem uses (PM or NUFFT)."""
+    if prob.force == "pm":
+        return force_jvp(prob.pm, psi, s, xdot)
+    from . import nufft
+    return nufft.nufft_force_jvp(prob.pm.n_p, prob.pm.n_g, psi, s, xdot, prob.es_width, prob.es_beta)
+
+
 def density_jvp(psi, n_p, n_g, xdot):
     """Tangent of the final CIC contrast when Psi moves along xdot."""
     r = n_g // n_p
@@ -90,8 +98,6 @@ def run_jvp(prob, w, w_dot, sigma8_dot=0.0):
     """Primal and tangent of the run: returns (Psi, Psi_dot, delta,
     delta_dot) at a_end for the direction (w_dot, sigma8_dot)."""
     from .nbody import initial_state
-    if prob.force != "pm":
-        raise NotImplementedError("the tangents cover the PM force")
     X, V, psi_lin = initial_state(prob, w)
     Xd, Vd = initial_tangent(prob, w_dot, psi_lin, sigma8_dot)
     X = np.array(X, dtype=np.float64)
@@ -101,7 +107,7 @@ def run_jvp(prob, w, w_dot, sigma8_dot=0.0):
         X += st.tau1 * V
         Xd = Xd + st.tau1 * Vd
         acc = force(X, st.s)
-        jd = force_jvp(prob.pm, X, st.s, Xd)
+        jd = problem_force_jvp(prob, X, st.s, Xd)
         V = st.alpha * V + st.beta * acc
         Vd = st.alpha * Vd + st.beta * jd
         X += st.tau2 * V

@@ -233,6 +233,53 @@ def nufft_force_vjp(n_p, n_f, psi, s, v, width=6, beta=13.8, parts=3):
     return xbar * sig
 
 
+def _spread_grad(u, n_f, width, beta, t):
+    """b_dot_j = sum_i t_i . d/du_i phi(j - u_i) = sum_i t_i . grad phi(u_i - j):
+    the spread's tangent when the positions u (3, M) move along t (3, M)."""
+    base = np.floor(u).astype(np.int64) - (width // 2 - 1)
+    w = [np.stack([es_kernel(base[a] + o - u[a], width, beta) for o in range(width)]) for a in range(3)]
+    d = [np.stack([es_kernel_deriv(u[a] - (base[a] + o), width, beta) for o in range(width)])
+         for a in range(3)]
+    out = np.zeros(n_f ** 3)
+    for a in range(width):
+        ix = (base[0] + a) % n_f
+        for b in range(width):
+            iy = (base[1] + b) % n_f
+            for c in range(width):
+                iz = (base[2] + c) % n_f
+                v = (t[0] * d[0][a] * w[1][b] * w[2][c] + t[1] * w[0][a] * d[1][b] * w[2][c]
+                     + t[2] * w[0][a] * w[1][b] * d[2][c])
+                out += np.bincount((ix * n_f + iy) * n_f + iz, weights=v, minlength=n_f ** 3)
+    return out
+
+
+def nufft_force_jvp(n_p, n_f, psi, s, xdot, width=6, beta=13.8):
+    """J_A(Psi) xdot for the spreading NUFFT force of ``nufft_force``; xdot
+    (3, N) in dq units.  The JVP rules of App. "Custom VJP and JVP": the
+    spread's tangent is a spread with grad phi dotted with the tangent
+    positions, carried through the same linear map to tangent meshes and
+    interpolated; the interpolation's own tangent is its gradient dotted
+    with the tangent positions."""
+    u = fine_coords(psi, n_p, n_f)
+    N = u.shape[1]
+    t = (n_f / n_p) * np.asarray(xdot, dtype=np.float64)
+    ix, mz, D = _nufft_pieces(n_p, n_f, N, s, width, beta)
+
+    def meshes_of(b):
+        sub = np.fft.rfftn(b.reshape(n_f, n_f, n_f))[np.ix_(ix, ix, mz)]
+        out = []
+        for c in range(3):
+            full = np.zeros((n_f, n_f, n_f // 2 + 1), dtype=np.complex128)
+            full[np.ix_(ix, ix, mz)] = D[c] * sub
+            out.append(np.fft.irfftn(full, s=(n_f, n_f, n_f), axes=(0, 1, 2)).reshape(-1) * n_f ** 3)
+        return np.stack(out, axis=1)
+
+    g = _interp_grad(meshes_of(_spread_float(u, n_f, width, beta)), u, n_f, width, beta)   # (N, 3, 3)
+    direct = np.einsum("icd,di->ci", g, t)
+    through = _interp_float(meshes_of(_spread_grad(u, n_f, width, beta, t)), u, n_f, width, beta).T
+    return (direct + through) / n_p ** 3
+
+
 def nufft_force(n_p, n_f, psi, s, width=6, beta=13.8):
     """Spreading-based NUFFT force A(X) (3, N) in dq units per unit D."""
     u = fine_coords(psi, n_p, n_f)

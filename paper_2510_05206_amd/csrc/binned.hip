@@ -1343,12 +1343,15 @@ __global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_divspread(TileArgs
   int p = beg + (int)threadIdx.x;  // consecutive lanes of the bank order: window bases spread over the banks
   long long i = 0;
   float u0 = 0.f, u1 = 0.f, u2 = 0.f, x0 = 0.f, x1 = 0.f, x2 = 0.f;
+  // forward mode (tan_xbar): the spread's tangent, u = coef Xdot from xbar
+  const bool tan = a.tan_xbar != 0;
+  const float tc = a.coef[slot];
   if (p < end) {
     const int q = a.bank[slot * N + p];
     i = a.sorted[slot * N + q];
-    u0 = a.u_sorted[ps + q];
-    u1 = a.u_sorted[ps + N + q];
-    u2 = a.u_sorted[ps + 2 * N + q];
+    u0 = tan ? tc * a.xbar[ps + i] : a.u_sorted[ps + q];
+    u1 = tan ? tc * a.xbar[ps + N + i] : a.u_sorted[ps + N + q];
+    u2 = tan ? tc * a.xbar[ps + 2 * N + i] : a.u_sorted[ps + 2 * N + q];
     x0 = a.disp[ps + i];
     x1 = a.disp[ps + N + i];
     x2 = a.disp[ps + 2 * N + i];
@@ -1376,9 +1379,9 @@ __global__ void __launch_bounds__(kEsSpreadThreads) k_tile_es_divspread(TileArgs
     if (p + NT < end) {
       const int q = a.bank[slot * N + p + NT];
       i = a.sorted[slot * N + q];
-      u0 = a.u_sorted[ps + q];
-      u1 = a.u_sorted[ps + N + q];
-      u2 = a.u_sorted[ps + 2 * N + q];
+      u0 = tan ? tc * a.xbar[ps + i] : a.u_sorted[ps + q];
+      u1 = tan ? tc * a.xbar[ps + N + i] : a.u_sorted[ps + N + q];
+      u2 = tan ? tc * a.xbar[ps + 2 * N + i] : a.u_sorted[ps + 2 * N + q];
       x0 = a.disp[ps + i];
       x1 = a.disp[ps + N + i];
       x2 = a.disp[ps + 2 * N + i];
@@ -1479,6 +1482,59 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
   }
 }
 
+// Forward-mode tangent kick with the ES kernel: per component, the direct
+// part r sum_d dA_c/du_d Xdot_d from the primal force mesh (into acc_out,
+// [B][3][N]), then the gather of the tangent force mesh (mesh_in2) and
+// Vdot_c = alpha Vdot_c + beta (both); finally Xdot += tau Vdot (Xdot in
+// xbar, Vdot in vbar)
+__global__ void __launch_bounds__(256) k_tile_es_tan_kick(TileArgs a) {
+  extern __shared__ float fwin[];  // one (T + 5)^3 window, the meshes in turn
+  const int slot = blockIdx.y, t = (int)xcd_block(blockIdx.x, gridDim.x);
+  if (!((a.active >> slot) & 1ull)) return;
+  const int W = a.T + kEsLo + kEsHi;
+  int o[3];
+  tile_origin(t, TileGeo{a.T, a.log2T, a.log2nt, a.n_tiles, a.ts}, o);
+  const long long N = a.g.N, ps = slot * a.g.part_stride;
+  const int beg = a.offset[slot * a.ts + t], end = a.offset[slot * a.ts + t + 1];
+  const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
+  const int nm = a.g.n_g - 1;
+  const float al = a.alpha[slot], be = a.beta[slot], tp = a.tau[slot];
+  const float r = (float)(1 << a.g.log2_r);
+  for (int c = 0; c < 3; ++c) {
+    if (c) __syncthreads();
+    load_window_es(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.g.log2_ng, nm);
+    __syncthreads();
+    for (int p = beg + threadIdx.x; p < end; p += 256) {
+      const long long i = a.sorted[slot * N + p];
+      const float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
+      float w[3][kEsW], dw[3][kEsW];
+      int l0[3];
+      es_particle_d(a, i, x, o, umask, nm, w, dw, l0);
+      float A, dA[3];
+      es_contract_grad(fwin, W, l0, w, dw, A, dA);
+      a.acc_out[ps + c * N + i] =
+          r * (dA[0] * a.xbar[ps + i] + dA[1] * a.xbar[ps + N + i] + dA[2] * a.xbar[ps + 2 * N + i]);
+    }
+    __syncthreads();
+    load_window_es(fwin, a.mesh_in2 + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.g.log2_ng, nm);
+    __syncthreads();
+    for (int p = beg + threadIdx.x; p < end; p += 256) {
+      const long long i = a.sorted[slot * N + p];
+      float w[3][kEsW];
+      int l0[3];
+      es_particle(a, i, o, umask, nm, w, l0);
+      const float J = es_contract(fwin, W, l0, w) + a.acc_out[ps + c * N + i];
+      a.vbar[ps + c * N + i] = al * a.vbar[ps + c * N + i] + be * J;
+    }
+  }
+  for (int p = beg + threadIdx.x; p < end; p += 256) {  // this thread's own particles
+    const long long i = a.sorted[slot * N + p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.xbar[ps + c * N + i] += tp * a.vbar[ps + c * N + i];
+  }
+}
+
+
 // raise the dynamic-LDS limit of every kernel that needs more than the
 // default, to its largest window (16^3 tiles); called once per bind, outside
 // any stream capture
@@ -1505,6 +1561,7 @@ hipError_t configure_tile_kernels() {
   set((const void*)k_tile_es_adj_kick, es32);
   set((const void*)k_tile_es_divspread, es64);
   set((const void*)k_tile_es_adj_drift, es32);
+  set((const void*)k_tile_es_tan_kick, es32);
   return e;
 }
 
@@ -1610,6 +1667,8 @@ hipError_t launch_tile_es(const TileArgs& a, int kind, hipStream_t s) {
     k_tile_es_divspread<<<grid, kEsSpreadThreads, lds, s>>>(a);
   } else if (kind == TK_ES_ADJ_DRIFT) {
     k_tile_es_adj_drift<<<grid, 256, fl, s>>>(a);
+  } else if (kind == TK_ES_TAN_KICK) {
+    k_tile_es_tan_kick<<<grid, 256, fl, s>>>(a);
   } else {
     return hipErrorInvalidValue;
   }

@@ -26,7 +26,7 @@ struct BinArgs {
 
 enum { TK_DEPOSIT = 0, TK_KICK = 1, TK_ADJ_KICK = 2, TK_ADJ_DRIFT = 3, TK_DIPOLE = 4, TK_ES_DEPOSIT = 5,
        TK_ES_KICK = 6, TK_ES_ADJ_KICK = 7, TK_ES_DIPOLE = 8, TK_ES_ADJ_DRIFT = 9, TK_TAN_SPREAD = 10,
-       TK_TAN_DIRECT = 11, TK_TAN_KICK = 12 };
+       TK_TAN_DIRECT = 11, TK_TAN_KICK = 12, TK_ES_TAN_KICK = 13 };
 
 struct TileArgs {
   Geom g;
@@ -42,6 +42,8 @@ struct TileArgs {
   float* xbar;
   float* vbar;
   const float* mesh_in;    // potential (kicks) or mesh cotangent (adjoint drift)
+  const float* mesh_in2;   // ES tangent kick: the tangent force meshes
+  int tan_xbar;            // ES gradient spread of the tangent positions (xbar, times coef)
   void* scratch;           // window slab [B][n_tiles][W^3] int64
   float* acc_out;          // force-only output
   const float* acc_in;     // interlaced grids: the other grid's forces, averaged in the kick

@@ -523,6 +523,7 @@ pm_status deposit(pm_ctx* c, float* disp, const float* vel_pre, const double* ta
 
 pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const double* tau, const double* s,
                        unsigned long long active);
+pm_status nufft_force_chain(pm_ctx* c, const float* rho, const double* s, float* out, unsigned long long active);
 
 // potential phi of the positions `disp` for the midpoint normalisation s
 // (NUFFT: the three force meshes)
@@ -654,7 +655,16 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
   as.slab_f32 = 1;
   as.shift = mean;
   KLAUNCH(c, PM_K_DEPOSIT, both(launch_tile_es(t, TK_ES_DEPOSIT, c->stream), launch_assemble(as, true, c->stream)));
-  st = r2c_mesh(c, rho, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, n, false, active, np);
+  return nufft_force_chain(c, rho, s, c->force3, active);
+}
+
+// the three NUFFT force meshes (out: [B][3][M]) of a spread density rho
+// ([B][M], slot stride M): R2C -> truncation, deconvolution, i k_c s / k^2
+// (x pass) -> y inverse, C2R per component
+pm_status nufft_force_chain(pm_ctx* c, const float* rho, const double* s, float* out, unsigned long long active) {
+  const int n = c->cfg.n_g, np = c->cfg.n_p;
+  const double N = (double)c->g.N;
+  pm_status st = r2c_mesh(c, rho, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, n, false, active, np);
   if (st) return st;
   ColArgs a{};
   a.data = c->spec;
@@ -693,7 +703,7 @@ pm_status nufft_meshes(pm_ctx* c, float* disp, const float* vel_pre, const doubl
     rl.dst_mode = DST_F32;
     rl.src = c->spec2;
     rl.src_stride = c->g.spec_stride;
-    rl.dst = c->force3 + comp * c->g.M;
+    rl.dst = out + comp * c->g.M;
     rl.dst_stride = 3 * c->g.M;
     rl.tw = c->d_tw;
     rl.tws_half = c->Lmax / (n / 2);
@@ -2081,13 +2091,54 @@ static pm_status lpt2_tangent(pm_ctx* c, unsigned long long act) {
   return lpt2_from_mu(c, mud, 2 * M, c->vbar, c->xbar, act);
 }
 
+// NUFFT tangent kick at X^{n+1/2} (the primal force meshes in force3, the
+// binning current): the spread's tangent (the ES gradient spread of
+// r Xdot, fixed point at the scale of max |Xdot|), the force chain to three
+// tangent meshes (in the scratch slab, free between spreads: 3M <= 8 W^3
+// n_tiles / 4 floats per slot), then the ES tangent kick and drift
+static pm_status nufft_tangent_kick(pm_ctx* c, const double* s, const double* al, const double* be,
+                                    const double* tau, unsigned long long act) {
+  const int B = c->cfg.batch;
+  const long long N = c->g.N;
+  const double r = (double)(1 << c->g.log2_r);
+  KLAUNCH(c, PM_K_MISC, launch_dipole_scale((const unsigned int*)c->umax, c->scale, c->inv_scale,
+                                            3.0 * r * (double)N, 3.0 * r, B, c->stream));
+  TileArgs k = tile_args(c, c->disp, act);
+  k.es_tab = c->d_es_tab;
+  k.tan_xbar = 1;
+  k.win_f32 = 1;  // FP32 partial sums at the slot's inverse scale
+  k.win_scale = 0.0;
+  k.inv_scale = c->inv_scale;
+  for (int b = 0; b < B; ++b) k.coef[b] = (float)r;
+  float* d = reinterpret_cast<float*>(c->mesh);
+  AssembleArgs as = assemble_args(c, kEsHaloLo, kEsHaloHi, d, act);
+  as.slab_f32 = 1;
+  as.shift = 0.0;
+  KLAUNCH(c, PM_K_DIPOLE, both(launch_tile_es(k, TK_ES_DIPOLE, c->stream), launch_assemble(as, true, c->stream)));
+  float* tmesh = reinterpret_cast<float*>(c->scratch);
+  if (pm_status st = nufft_force_chain(c, d, s, tmesh, act)) return st;
+  TileArgs q = tile_args(c, c->disp, act);
+  q.es_tab = c->d_es_tab;
+  q.mesh_in = c->force3;
+  q.mesh_in2 = tmesh;
+  q.comp_stride = c->g.M;
+  q.acc_out = c->u_sorted;
+  for (int b = 0; b < B; ++b) {
+    q.alpha[b] = (float)al[b];
+    q.beta[b] = (float)be[b];
+    q.tau[b] = (float)tau[b];
+  }
+  KLAUNCH(c, PM_K_GATHER_KICK, launch_tile_es(q, TK_ES_TAN_KICK, c->stream));
+  return PM_OK;
+}
+
 pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float* delta_dot_out) {
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers (the tangents live there)");
   if (!c->ics_done) return fail(c, PM_ESTATE, "pm_jvp before pm_init_ics");
   if (!w_dot || !delta_dot_out) return PM_EINVAL;
-  if (c->cfg.force != PM_FORCE_PM || c->cfg.antialias)
-    return fail(c, PM_EUNSUPPORTED, "the tangents cover the single-grid PM force");
+  if (c->cfg.antialias) return fail(c, PM_EUNSUPPORTED, "the tangents cover the single-grid force");
+  const bool nufft = c->cfg.force == PM_FORCE_NUFFT;
   const int B = c->cfg.batch, mak = c->cfg.mak, ord = c->cfg.grad_order;
   const long long N = c->g.N;
   const unsigned long long all = c->user_mask;
@@ -2125,6 +2176,11 @@ pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float*
     if (pm_status st = absmax_tangent(c, t1, act)) return st;
     pm_status st = potential(c, c->disp, c->vel, tp.data(), s.data(), act);
     if (st) return st;
+    if (nufft) {
+      if ((st = nufft_tangent_kick(c, s.data(), al.data(), be.data(), tq.data(), act))) return st;
+      if ((st = kick(c, c->disp, al.data(), be.data(), tq.data(), nullptr, act))) return st;
+      continue;
+    }
     // J_A Xdot at X^{n+1/2}: the tangent contrast through the same multiplier,
     // gathered like the force, plus the gather's position term
     if ((st = tangent_contrast(c, mak, dd, act))) return st;

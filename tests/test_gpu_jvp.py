@@ -50,14 +50,17 @@ def direction(n_p, seed):
 # a few even at 32^3), so the contrast is held to 2e-2 and its modes
 # |m| < n_g / 8 (where that white noise is thin) to 2e-3.  The tangent
 # positions carry no such steps when the force kernel has a continuous
-# derivative (TSC, PCS): 1e-4; with the CIC force the same steps enter the
+# derivative (TSC, PCS, the NUFFT's ES kernel): 1e-4; with the CIC force the same steps enter the
 # dynamics (measured 2e-6 here): 1e-3.
 @pytest.mark.parametrize("wl,mak,dec,lpt,tol_x", [("C4_SMALL", 2, False, 1, 1e-3), ("C2_SMALL", 3, True, 1, 1e-4),
                                                   ("C2_SMALL", 3, False, 1, 1e-4), ("C2_SMALL", 4, False, 1, 1e-4),
                                                   ("C2_SMALL", 4, True, 1, 1e-4), ("C2_SMALL", 3, False, 2, 1e-4),
-                                                  ("C1", 3, False, 2, 1e-4)])
+                                                  ("C1", 3, False, 2, 1e-4), ("C3_SMALL", 2, False, 1, 1e-4),
+                                                  ("C3_SMALL", 2, False, 2, 1e-4)])
 def test_tangent_matches_oracle(wl, mak, dec, lpt, tol_x):
-    d = dict(getattr(synth, wl), mak=mak, grad_order=4, deconvolve=dec, lpt_order=lpt)
+    d = dict(getattr(synth, wl), lpt_order=lpt)
+    if d.get("force") != "nufft":
+        d.update(mak=mak, grad_order=4, deconvolve=dec)
     say("jvp", wl, mak, dec, lpt)
     sim = make_sim(d)
     sim.init_ics([synth.SEED_W])
@@ -129,7 +132,7 @@ def test_jvp_refusals():
     sim.init_ics([1])
     with pytest.raises(PMError, match="PM_ESTATE"):
         sim.jvp(wd)
-    for bad in (dict(synth.C3_SMALL), dict(synth.C4_SMALL, antialias=1)):
+    for bad in (dict(synth.C4_SMALL, antialias=1),):
         sim = make_sim(bad)
         sim.init_ics([1])
         with pytest.raises(PMError, match="PM_EUNSUPPORTED"):

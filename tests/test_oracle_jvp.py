@@ -87,3 +87,19 @@ def test_sigma8_log_derivative_is_two_on_linear_scales():
     logd = pdot / p
     assert abs(logd[0] - 2.0) < 0.03
     assert np.all(np.abs(logd[:3] - 2.0) < 0.1)
+
+
+def test_nufft_force_jvp_matches_differences_and_vjp():
+    from oracle import nufft
+    rng = np.random.default_rng(40)
+    n_p, n_f = 8, 16
+    psi = rng.normal(0, 0.8, (3, n_p ** 3))
+    xd = rng.normal(size=(3, n_p ** 3))
+    u = rng.normal(size=(3, n_p ** 3))
+    J = nufft.nufft_force_jvp(n_p, n_f, psi, 1.3, xd)
+    eps = 1e-6
+    fd = (nufft.nufft_force(n_p, n_f, psi + eps * xd, 1.3) - nufft.nufft_force(n_p, n_f, psi - eps * xd, 1.3)) / (2 * eps)
+    assert rel(J, fd) < 1e-6
+    lhs = np.sum(u * J)
+    rhs = np.sum(nufft.nufft_force_vjp(n_p, n_f, psi, 1.3, u) * xd)
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
