@@ -273,8 +273,7 @@ pm_status pm_power_spectrum(pm_ctx* ctx, int32_t n_bins, int32_t deconvolve_cic,
  * the power-law spectrum, whose amplitude is not set by sigma8);
  * delta_dot_out: device [B][n_g^3], the tangent of the final CIC contrast.
  * Needs a workspace bound with adjoint buffers (the tangents use them;
- * PM_ESTATE otherwise); PM or NUFFT force, not interlaced grids
- * (PM_EUNSUPPORTED).  With second-order initial conditions the tangent of psi2 is
+ * PM_ESTATE otherwise); PM (single or interlaced grids) or NUFFT force.  With second-order initial conditions the tangent of psi2 is
  * its bilinear form in (psi, psi_dot). */
 pm_status pm_jvp(pm_ctx* ctx, const float* w_dot, const double* sigma8_dot, float* delta_dot_out);
 

@@ -764,9 +764,21 @@ __global__ void __launch_bounds__(256) k_tile_tan_kick(TileArgs a) {
     int l0[3];
     tile_weights<P>(a, i, x, o, R, w, dw, l0);
     fd_gather<P, ORD, false>(acc, l0, w, dw, A, dA);
+    float J[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) J[c] = A[c] + a.acc_in[ps + c * N + i];
+    if (a.il_in) {  // interlaced grids: the mean with the other grid's J ([B][3][N])
+#pragma unroll
+      for (int c = 0; c < 3; ++c) J[c] = 0.5f * (J[c] + a.il_in[ps + c * N + i]);
+    }
+    if (a.il_out) {  // interlaced grids: this grid's J only, the state untouched
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.il_out[ps + c * N + i] = J[c];
+      continue;
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float v = al * a.vbar[ps + c * N + i] + be * (A[c] + a.acc_in[ps + c * N + i]);
+      const float v = al * a.vbar[ps + c * N + i] + be * J[c];
       a.vbar[ps + c * N + i] = v;
       a.xbar[ps + c * N + i] += tp * v;
     }

@@ -2132,12 +2132,79 @@ static pm_status nufft_tangent_kick(pm_ctx* c, const double* s, const double* al
   return PM_OK;
 }
 
+// Interlaced tangent kick at X^{n+1/2} (primal potentials phi_1 on c->phi,
+// phi_2 on c->phi2; the second grid's binning current): every term of J_A
+// Xdot is the mean of the two grids' terms.  The tangent contrasts of both
+// grids go through the same two-grid chain as the force; the grid passes
+// that need the other binning leave their terms in the per-particle buffer
+// ([B][3][N] views of its two halves); the second grid's binning and both
+// primal potentials are left for the primal kick.
+static pm_status interlaced_tangent_kick(pm_ctx* c, const double* s, const double* al, const double* be,
+                                         const double* tau, unsigned long long act) {
+  const int B = c->cfg.batch, mak = c->cfg.mak, ord = c->cfg.grad_order;
+  const long long N = c->g.N;
+  const long long half = 1ll << (kFracBits - 1);
+  float* d1 = reinterpret_cast<float*>(c->mesh);      // tangent contrast, then tangent potential 1
+  float* d2 = c->phi2;                                 // primal potential 2 (the primal kick reads it too)
+  float* t2 = reinterpret_cast<float*>(c->scratch);    // tangent potential 2 (the slab is free after the spreads)
+  float* dir2 = c->accbuf;                             // grid 2's direct term
+  float* j1 = c->accbuf + 3 * N * B;                   // grid 1's J
+  auto args = [&](long long ushift) {
+    c->g.ushift = ushift;
+    TileArgs k = tile_args(c, c->disp, act);
+    c->g.ushift = 0;
+    for (int b = 0; b < B; ++b) {
+      k.alpha[b] = (float)al[b];
+      k.beta[b] = (float)be[b];
+      k.tau[b] = (float)tau[b];
+    }
+    return k;
+  };
+  // grid 2: direct term, then its tangent contrast to the spectrum (full transform)
+  TileArgs k2 = args(half);
+  k2.mesh_in = d2;
+  k2.acc_out = dir2;
+  KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(k2, TK_TAN_DIRECT, mak, ord, c->stream));
+  c->g.ushift = half;
+  pm_status st = tangent_contrast(c, mak, d1, act);
+  c->g.ushift = 0;
+  if (st) return st;
+  st = r2c_mesh(c, d1, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec2, c->g.spec_stride, c->cfg.n_g, true, act);
+  if (st) return st;
+  // grid 1: its tangent contrast, the two-grid chain to both tangent potentials
+  if ((st = bin(c, c->disp, nullptr, nullptr, mak, act))) return st;
+  if ((st = tangent_contrast(c, mak, d1, act))) return st;
+  st = r2c_mesh(c, d1, SRC_F32, c->g.mesh_stride, 1.0, 0.0, c->spec, c->g.spec_stride, c->cfg.n_g, false, act);
+  if (st) return st;
+  if ((st = spectrum_to_real(c, c->spec, MODE_FUSED_IL, s, c->spec2, d1, act))) return st;
+  if ((st = spectrum_to_real(c, c->spec2, MODE_INV, nullptr, nullptr, t2, act))) return st;
+  TileArgs k1 = args(0);
+  k1.mesh_in = c->phi;
+  k1.acc_out = c->u_sorted;
+  KLAUNCH(c, PM_K_ADJ_KICK, launch_tile(k1, TK_TAN_DIRECT, mak, ord, c->stream));
+  TileArgs q1 = args(0);
+  q1.mesh_in = d1;
+  q1.acc_in = c->u_sorted;
+  q1.il_out = j1;
+  KLAUNCH(c, PM_K_GATHER_KICK, launch_tile(q1, TK_TAN_KICK, mak, ord, c->stream));
+  // grid 2 again: its J, the mean, the tangent kick and drift
+  c->g.ushift = half;
+  st = bin(c, c->disp, nullptr, nullptr, mak, act);
+  c->g.ushift = 0;
+  if (st) return st;
+  TileArgs q2 = args(half);
+  q2.mesh_in = t2;
+  q2.acc_in = dir2;
+  q2.il_in = j1;
+  KLAUNCH(c, PM_K_GATHER_KICK, launch_tile(q2, TK_TAN_KICK, mak, ord, c->stream));
+  return PM_OK;
+}
+
 pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float* delta_dot_out) {
   if (pm_status st = check_bound(c)) return st;
   if (!c->with_adj) return fail(c, PM_ESTATE, "workspace bound without adjoint buffers (the tangents live there)");
   if (!c->ics_done) return fail(c, PM_ESTATE, "pm_jvp before pm_init_ics");
   if (!w_dot || !delta_dot_out) return PM_EINVAL;
-  if (c->cfg.antialias) return fail(c, PM_EUNSUPPORTED, "the tangents cover the single-grid force");
   const bool nufft = c->cfg.force == PM_FORCE_NUFFT;
   const int B = c->cfg.batch, mak = c->cfg.mak, ord = c->cfg.grad_order;
   const long long N = c->g.N;
@@ -2176,8 +2243,10 @@ pm_status pm_jvp(pm_ctx* c, const float* w_dot, const double* sigma8_dot, float*
     if (pm_status st = absmax_tangent(c, t1, act)) return st;
     pm_status st = potential(c, c->disp, c->vel, tp.data(), s.data(), act);
     if (st) return st;
-    if (nufft) {
-      if ((st = nufft_tangent_kick(c, s.data(), al.data(), be.data(), tq.data(), act))) return st;
+    if (nufft || c->cfg.antialias) {
+      st = nufft ? nufft_tangent_kick(c, s.data(), al.data(), be.data(), tq.data(), act)
+                 : interlaced_tangent_kick(c, s.data(), al.data(), be.data(), tq.data(), act);
+      if (st) return st;
       if ((st = kick(c, c->disp, al.data(), be.data(), tq.data(), nullptr, act))) return st;
       continue;
     }
