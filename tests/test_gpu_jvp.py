@@ -136,3 +136,31 @@ def test_jvp_refusals():
         sim.jvp(wd)
     with pytest.raises(PMError, match="PM_ESTATE"):
         sim.get_tangent()
+
+
+@pytest.mark.parametrize("case", ["pm", "nufft", "lpt2", "interlaced"])
+def test_batched_slots_equal_single_runs(case):
+    # every slot of a two-slot context carries its own seed, direction and
+    # sigma8 tangent; each equals the one-slot context bit for bit, for the
+    # tangent contrast, the tangent positions and the adjoint's w_bar
+    base = {"pm": synth.C2_SMALL, "nufft": synth.C3_SMALL, "lpt2": dict(synth.C2_SMALL, lpt_order=2),
+            "interlaced": dict(synth.C2_SMALL, antialias=1)}[case]
+    seeds, dirs, s8d = [21, 22], [direction(32, 41), direction(32, 42)], [0.1, -0.3]
+    both = make_sim(dict(base, batch=2))
+    both.init_ics(seeds)
+    dd2 = both.jvp(torch.from_numpy(np.stack(dirs)), s8d)
+    xd2 = both.get_tangent()[0]
+    g = torch.from_numpy(np.random.default_rng(43).normal(size=(2, base["n_g"] ** 3)).astype(np.float32))
+    both.init_ics(seeds)
+    both.run()
+    dw2, ds2 = both.adjoint(g)
+    for b in range(2):
+        one = make_sim(dict(base, batch=1))
+        one.init_ics([seeds[b]])
+        dd1 = one.jvp(torch.from_numpy(dirs[b][None]), [s8d[b]])
+        xd1 = one.get_tangent()[0]
+        one.init_ics([seeds[b]])
+        one.run()
+        dw1, ds1 = one.adjoint(g[b:b + 1])
+        assert torch.equal(dd2[b], dd1[0]) and torch.equal(xd2[b], xd1[0]), (case, b)
+        assert torch.equal(dw2[b], dw1[0]) and torch.equal(ds2[b], ds1[0]), (case, b)
