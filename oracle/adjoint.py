@@ -26,7 +26,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import ics, mesh
+from . import ics, mesh, nbody
 from .force import force_multipliers, interlace_phase, PMConfig
 
 
@@ -139,10 +139,11 @@ def gradient(prob, w, dL_ddelta, progress=None, temporal=None):
     vbar = np.zeros_like(xbar)
     xbar, vbar = reverse_cotangents(prob, record, xbar, vbar, progress, temporal)
     D = prob.D_start()
-    psibar = D * xbar + vbar
+    vf = nbody.velocity_factor(prob)
+    psibar = D * xbar + vf * vbar
     if prob.lpt_order == 2:
-        # Psi = D psi1 + D^2 psi2(psi1), V = psi1 + 2 D psi2(psi1)
-        psibar = psibar + ics.second_order_psi_vjp(psi_lin, prob.pm.n_p, D * D * xbar + 2.0 * D * vbar)
+        # Psi = D psi1 + D^2 psi2(psi1), V = vf (psi1 + 2 D psi2(psi1))
+        psibar = psibar + ics.second_order_psi_vjp(psi_lin, prob.pm.n_p, D * D * xbar + 2.0 * D * vf * vbar)
     wbar = ic_vjp(prob, psibar)
     # the power-law spectrum is normalised by its rms displacement, not by
     # sigma8, so there the initial conditions do not depend on sigma8

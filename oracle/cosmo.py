@@ -117,16 +117,37 @@ class StepCoeffs:
     s: float  # 1 / D_{n+1/2}^2: D-time normalisation of the acceleration
 
 
+def zeta(omega_m, a):
+    """H(a) a^3 dD/da (EdS: a^(3/2)); D normalised as D ~ a at early times."""
+    if omega_m == 1.0:
+        return float(a) ** 1.5
+    g = Growth(omega_m)
+    return float(hubble(a, omega_m)) * a * a * float(g.dDdlna(a))
+
+
+def superconformal(omega_m, a0, a):
+    """Superconformal time from a0 to a, int da / (a^3 H) (dt_sc = dt / a^2,
+    H0 = 1)."""
+    return integrate.quad(lambda x: 1.0 / (x ** 3 * float(hubble(x, omega_m))), a0, a,
+                          epsabs=0.0, epsrel=1e-13, limit=200)[0]
+
+
 def step_table(omega_m, a_start, a_end, n_steps, stepper="bullfrog", time_var="D"):
     """Drift-kick-drift coefficients of eq. dkd (Sec. "Time stepping").
 
-    Nodes uniform in the time variable t (D, a or ln a), the midpoint centred
-    in t: D_n = D(t_n), D_{n+1/2} = D(t_0 + (n + 1/2) dt); tau1 = D_{n+1/2} - D_n,
-    tau2 = D_{n+1} - D_{n+1/2}; beta = (1 - alpha) D_{n+1/2} (Zel'dovich
-    consistency) with
+    Nodes uniform in the time variable t (D, a, ln a or superconformal time
+    int da / (a^3 H)), the midpoint centred in t: D_n = D(t_n),
+    D_{n+1/2} = D(t_0 + (n + 1/2) dt).  With the growth-time velocity
+    V = dX/dD: tau1 = D_{n+1/2} - D_n, tau2 = D_{n+1} - D_{n+1/2},
+    beta = (1 - alpha) D_{n+1/2} (Zel'dovich consistency), force scale
+    s = 1 / D_{n+1/2}^2, and
       BullFrog: xi    = (E_n + E'(D_n) (D_{n+1} - D_n) / 2) / D_{n+1/2} - D_{n+1/2}
                 alpha = (E'(D_{n+1}) - xi) / (E'(D_n) - xi)
       FastPM:   alpha = zeta(a_n) / zeta(a_{n+1}),  zeta(a) = H(a) a^3 dD/da.
+    With the canonical momentum V = a^2 dX/dt (leapfrog, symplectic):
+    alpha = 1, beta = int_{a_n}^{a_{n+1}} da / (H a^2), tau1 and tau2 the
+    integrals of da / (H a^3) over the two halves, and the force of the
+    comoving Poisson equation, s = (3/2) Omega_m (H0 = 1, lengths in dq).
     """
     if omega_m == 1.0:  # EdS closed forms: D = a, E = -(3/7) D^2, zeta = a^(3/2)
         Dfun = lambda a: a
@@ -148,6 +169,14 @@ def step_table(omega_m, a_start, a_end, n_steps, stepper="bullfrog", time_var="D
         t0, t1, D_of_t = a_start, a_end, Dfun
     elif time_var == "lna":
         t0, t1, D_of_t = math.log(a_start), math.log(a_end), (lambda t: Dfun(math.exp(t)))
+    elif time_var == "superconft":
+        def a_of_sc(t):
+            if t <= 0.0:
+                return a_start
+            return optimize.brentq(lambda a: superconformal(omega_m, a_start, a) - t, a_start, a_end * 1.5,
+                                   xtol=1e-15, rtol=1e-15)
+        t0, t1 = 0.0, superconformal(omega_m, a_start, a_end)
+        D_of_t = lambda t: Dfun(a_of_sc(t))
     else:
         raise ValueError(time_var)
     dt = (t1 - t0) / n_steps
@@ -162,6 +191,15 @@ def step_table(omega_m, a_start, a_end, n_steps, stepper="bullfrog", time_var="D
             alpha = (Epp - xi) / (Epn - xi)
         elif stepper == "fastpm":
             alpha = zeta(afun(Dn)) / zeta(afun(Dp))
+        elif stepper == "leapfrog":
+            an, ah, ap = afun(Dn), afun(Dh), afun(Dp)
+            h = lambda x: float(hubble(x, omega_m))
+            q = lambda f, lo, hi: integrate.quad(f, lo, hi, epsabs=0.0, epsrel=1e-13, limit=200)[0]
+            kick = q(lambda x: 1.0 / (h(x) * x * x), an, ap)
+            t1_ = q(lambda x: 1.0 / (h(x) * x ** 3), an, ah)
+            t2_ = q(lambda x: 1.0 / (h(x) * x ** 3), ah, ap)
+            out.append(StepCoeffs(Dn, Dh, Dp, 1.0, kick, t1_, t2_, 1.5 * omega_m))
+            continue
         else:
             raise ValueError(stepper)
         beta = (1.0 - alpha) * Dh

@@ -87,11 +87,12 @@ def initial_tangent(prob, w_dot, psi_lin, sigma8_dot=0.0):
                                 prob.spectrum_fn(), prob.D_ref())
     if prob.spectrum == "bbks":  # the power-law amplitude is set by its rms displacement
         psi_dot = psi_dot + (sigma8_dot / prob.sigma8) * psi_lin
-    D = prob.D_start()
+    from .nbody import velocity_factor
+    D, vf = prob.D_start(), velocity_factor(prob)
     if prob.lpt_order == 2:
         psi2_dot = ics.second_order_psi_jvp(psi_lin, n, psi_dot)
-        return D * psi_dot + D * D * psi2_dot, psi_dot + 2.0 * D * psi2_dot
-    return D * psi_dot, psi_dot
+        return D * psi_dot + D * D * psi2_dot, vf * (psi_dot + 2.0 * D * psi2_dot)
+    return D * psi_dot, vf * psi_dot
 
 
 def run_jvp(prob, w, w_dot, sigma8_dot=0.0):

@@ -33,8 +33,8 @@ class Problem:
     n_steps: int = 6
     force: str = "pm"               # "pm" or "nufft"
     lpt_order: int = 1              # 1 Zel'dovich, 2 second-order LPT initial state
-    stepper: str = "bullfrog"       # "bullfrog" or "fastpm"
-    time_var: str = "D"             # steps uniform in "D", "a" or "lna"
+    stepper: str = "bullfrog"       # "bullfrog", "fastpm" or "leapfrog" (canonical momentum)
+    time_var: str = "D"             # steps uniform in "D", "a", "lna" or "superconft"
     es_width: int = 6
     es_beta: float = 13.8
     _cache: dict = field(default_factory=dict, repr=False)
@@ -70,13 +70,20 @@ class Problem:
                                                 self.es_width, self.es_beta)
 
 
+def velocity_factor(prob: Problem):
+    """V per unit dX/dD at a_start: 1 for the growth-time velocity, and
+    a^2 dX/dt = a^3 H dD/da dX/dD = zeta(a_start) for the canonical momentum."""
+    return cosmo.zeta(prob.omega_m, prob.a_start) if prob.stepper == "leapfrog" else 1.0
+
+
 def initial_state(prob: Problem, w):
     """(Psi, V, psi1) at a_start: the LPT series of eq. LPT truncated at
-    prob.lpt_order (1: Zel'dovich; 2: plus the second-order term)."""
+    prob.lpt_order (1: Zel'dovich; 2: plus the second-order term), V in the
+    stepper's velocity variable."""
     psi = ics.zeldovich_psi(w, prob.pm.box, prob.spectrum_fn(), prob.D_ref())
     psi2 = ics.second_order_psi(psi, prob.pm.n_p) if prob.lpt_order == 2 else None
     X, V = ics.lpt_state(psi, psi2, prob.D_start())
-    return X, V, psi
+    return X, velocity_factor(prob) * V, psi
 
 
 def white_noise(prob: Problem, seed):

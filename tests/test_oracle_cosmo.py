@@ -59,6 +59,21 @@ def _bullfrog_toy_run(steps, D0):
     return X, V
 
 
+def _leapfrog_toy_run(steps, a0):
+    """The same toy in canonical variables (EdS, H0 = 1): p = a^2 dX/dt =
+    a^(3/2) dX/dD, dp/dt = (3/2) F / a with the toy field F = X - a^2 e2
+    (D^2 A of the D-time toy), whose exact solution is again
+    X = a e1 - (3/7) a^2 e2.  Kick p += beta s F(X^{n+1/2}, a_{n+1/2})."""
+    X = np.array([a0, -3 / 7 * a0 ** 2])
+    p = a0 ** 1.5 * np.array([1.0, -6 / 7 * a0])
+    for st in steps:
+        X = X + st.tau1 * p
+        F = X - st.D_half ** 2 * np.array([0.0, 1.0])
+        p = st.alpha * p + st.beta * st.s * F
+        X = X + st.tau2 * p
+    return X, p
+
+
 @pytest.mark.parametrize("a0,a1,n", [(0.02, 1.0, 6), (0.5, 1.0, 1), (0.1, 0.11, 1), (0.02, 1.0, 1),
                                      (0.05, 0.8, 13)])
 def test_bullfrog_is_2lpt_exact_in_eds(a0, a1, n):
@@ -146,3 +161,46 @@ def test_fastpm_is_first_order_consistent_only():
         assert abs(X[0] - 1.0) < 1e-13 and abs(V[0] - 1.0) < 1e-13
         errs.append(abs(X[1] + 3 / 7))
     assert errs[0] > 1e-2 and errs[0] / errs[1] > 2.0 and errs[1] / errs[2] > 2.0
+
+
+def test_leapfrog_coefficients_closed_forms():
+    # canonical momentum in EdS (H = a^-3/2): the drift integrals
+    # int da / (a^3 H) = 2 (a^-1/2 - b^-1/2), the kick int da / (a^2 H)
+    # = 2 (b^1/2 - a^1/2), alpha = 1, s = 3/2 Omega_m
+    for tv in ("a", "superconft"):
+        for st in cosmo.step_table(1.0, 0.02, 1.0, 6, "leapfrog", tv):
+            a, h, b = st.D_n, st.D_half, st.D_np1  # D = a in EdS
+            assert st.alpha == 1.0 and st.s == 1.5
+            assert abs(st.tau1 / (2 * (a ** -0.5 - h ** -0.5)) - 1) < 1e-11
+            assert abs(st.tau2 / (2 * (h ** -0.5 - b ** -0.5)) - 1) < 1e-11
+            assert abs(st.beta / (2 * (b ** 0.5 - a ** 0.5)) - 1) < 1e-11
+    # LCDM: the drift over the whole run is the superconformal interval, and a
+    # superconformal spacing gives equal drifts
+    om = 0.31
+    steps = cosmo.step_table(om, 0.02, 1.0, 5, "leapfrog", "superconft")
+    tau = [st.tau1 + st.tau2 for st in steps]
+    assert abs(sum(tau) / cosmo.superconformal(om, 0.02, 1.0) - 1) < 1e-9
+    assert max(tau) / min(tau) - 1 < 1e-8 and all(abs(st.tau1 / st.tau2 - 1) < 1e-8 for st in steps)
+
+
+def test_superconformal_nodes_closed_form():
+    # EdS: t(a) = 2 (a0^-1/2 - a^-1/2), so the nodes are a = (a0^-1/2 - t/2)^-2
+    a0, a1, n = 0.02, 1.0, 6
+    T = 2 * (a0 ** -0.5 - a1 ** -0.5)
+    a_of = lambda x: (a0 ** -0.5 - x * T / n / 2) ** -2
+    for i, st in enumerate(cosmo.step_table(1.0, a0, a1, n, "bullfrog", "superconft")):
+        for D, x in ((st.D_n, i), (st.D_half, i + 0.5), (st.D_np1, i + 1)):
+            assert abs(D / a_of(x) - 1) < 1e-10
+
+
+def test_leapfrog_converges_at_second_order():
+    # the toy 2LPT trajectory of EdS with the canonical momentum
+    # p = a^2 dX/dt = zeta V_D (zeta = a^3/2): the leapfrog is neither
+    # Zel'dovich nor 2LPT consistent, and with steps uniform in ln a its
+    # error falls as the step squared (uniform steps in a from a = 0.02 are
+    # far from that regime: the first step is six times a_start)
+    errs = []
+    for n in (8, 16, 32):
+        X, V = _leapfrog_toy_run(cosmo.step_table(1.0, 0.02, 1.0, n, "leapfrog", "lna"), 0.02)
+        errs.append(abs(X[0] - 1.0) + abs(X[1] + 3 / 7))
+    assert errs[0] < 0.05 and 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5

@@ -281,7 +281,7 @@ def test_powerlaw_spectrum_gradient_has_no_sigma8_term():
     assert dsig == 0.0
 
 
-@pytest.mark.parametrize("stepper", ["bullfrog", "fastpm"])
+@pytest.mark.parametrize("stepper", ["bullfrog", "fastpm", "leapfrog"])
 def test_temporal_adjoints_match_finite_differences(stepper):
     # tab. adjoint_dkd: the adjoints of each step's tau1, tau2, alpha, beta
     # against central differences of the forward map with that one scalar moved
@@ -311,3 +311,30 @@ def test_temporal_adjoints_match_finite_differences(stepper):
             eps = 1e-7 * max(abs(x), 1e-3)
             fd = (loss_with(k, field, x + eps) - loss_with(k, field, x - eps)) / (2 * eps)
             assert abs(temporal[k][j] - fd) < 1e-5 * abs(fd) + 1e-6, (k, field, temporal[k][j], fd)
+
+
+def test_leapfrog_gradient_matches_finite_differences():
+    # the store-all gradient with the canonical momentum (V = zeta(a_start)
+    # times the growth-time velocity at the start), steps uniform in
+    # superconformal time, against central differences of the run
+    cfg = PMConfig(8, 16, 40.0, order=3, deconvolve=False, grad_order=4, lap_order=0)
+    prob = nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=4, sigma8=0.9,
+                         stepper="leapfrog", time_var="superconft")
+    n = cfg.n_p
+    rng = np.random.default_rng(17)
+    w = nbody.white_noise(prob, 8).astype(np.float64)
+    target = rng.normal(size=cfg.n_g ** 3)
+
+    def loss_of(wv, s8=0.9):
+        p = nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=4, sigma8=s8,
+                          stepper="leapfrog", time_var="superconft")
+        x, _ = nbody.run(p, w=wv.reshape(n, n, n))
+        return np.sum((adjoint.final_density(p, x) - target) ** 2)
+
+    wbar, dsig, _ = adjoint.gradient(prob, w, lambda d: 2 * (d - target))
+    dirn = rng.normal(size=n ** 3)
+    eps = 1e-6
+    fd = (loss_of(w.reshape(-1) + eps * dirn) - loss_of(w.reshape(-1) - eps * dirn)) / (2 * eps)
+    assert abs(np.dot(wbar, dirn) - fd) < 1e-6 * abs(fd)
+    fd = (loss_of(w.reshape(-1), 0.9 + eps) - loss_of(w.reshape(-1), 0.9 - eps)) / (2 * eps)
+    assert abs(dsig - fd) < 1e-6 * abs(fd)

@@ -33,13 +33,15 @@ def test_force_jvp_matches_differences_and_vjp(order, dec, g, inter):
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
-def _problem(n_p=8, box=40.0, spectrum="bbks"):
+def _problem(n_p=8, box=40.0, spectrum="bbks", stepper="bullfrog", time_var="D"):
     cfg = PMConfig(n_p, 2 * n_p, box, order=2, deconvolve=False, grad_order=4)
-    return nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=0.9, spectrum=spectrum)
+    return nbody.Problem(cfg, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=0.9, spectrum=spectrum,
+                         stepper=stepper, time_var=time_var)
 
 
-def test_run_tangent_matches_differences():
-    prob = _problem()
+@pytest.mark.parametrize("stepper,tv", [("bullfrog", "D"), ("leapfrog", "superconft")])
+def test_run_tangent_matches_differences(stepper, tv):
+    prob = _problem(stepper=stepper, time_var=tv)
     n = prob.pm.n_p
     rng = np.random.default_rng(1)
     w = nbody.white_noise(prob, 3).astype(np.float64)
@@ -47,7 +49,8 @@ def test_run_tangent_matches_differences():
     _, _, delta, dd = jvp.run_jvp(prob, w, wd, 0.3)
 
     def dens(wv, s8):
-        p = nbody.Problem(prob.pm, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=s8)
+        p = nbody.Problem(prob.pm, omega_m=0.31, a_start=0.02, a_end=1.0, n_steps=3, sigma8=s8,
+                          stepper=stepper, time_var=tv)
         x, _ = nbody.run(p, w=wv.reshape(n, n, n))
         return adjoint.final_density(p, x)
 
