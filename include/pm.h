@@ -90,8 +90,13 @@ enum { PM_SPEC_POWERLAW = 0, PM_SPEC_BBKS = 1 };
  *                  eq. helmholtz; de-aliased products).  2 needs
  *                  n_g >= 2 n_p and n_p >= 8; pm_adjoint and pm_jvp
  *                  differentiate through the second-order term as well
- *   stepper        0 BullFrog; 1 FastPM (Sec. "Time stepping")
- *   time_var       step spacing: 0 uniform in D, 1 in a, 2 in ln a
+ *   stepper        0 BullFrog, 1 FastPM (velocity V = dX/dD); 2 the
+ *                  symplectic leapfrog in the canonical momentum V = a^2 dX/dt
+ *                  (H0 = 1, lengths in lattice units; the initial V is
+ *                  zeta(a_start) = H a^3 dD/da times dX/dD) (Sec. "Time
+ *                  stepping")
+ *   time_var       step spacing: 0 uniform in D, 1 in a, 2 in ln a, 3 in
+ *                  superconformal time (dt / a^2)
  *   antialias      1: interlaced grids for the PM force (Sec. "Discreteness
  *                  suppression"; antialias of tab. default_parameters), a
  *                  second deposit half a cell down the diagonal, the two

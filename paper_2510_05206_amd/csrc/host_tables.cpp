@@ -126,14 +126,53 @@ double Growth::zeta(double a) const {
 //   xi = (E_n + E'(D_n) (D_{n+1} - D_n) / 2) / D_{n+1/2} - D_{n+1/2},
 //   alpha = (E'(D_{n+1}) - xi) / (E'(D_n) - xi),
 // or FastPM alpha = zeta(a_n) / zeta(a_{n+1}).
+// int_a^b f(x) dx by 8 panels of 16-point Gauss-Legendre in ln x (the
+// integrands here are powers of x times 1/H, smooth in ln x)
+template <class F>
+static double integrate_lnx(F f, double a, double b) {
+  static const double xg[8] = {0.0950125098376374, 0.2816035507792589, 0.4580167776572274, 0.6178762444026438,
+                               0.7554044083550030, 0.8656312023878318, 0.9445750230732326, 0.9894009349916499};
+  static const double wg[8] = {0.1894506104550685, 0.1826034150449236, 0.1691565193950025, 0.1495959888165767,
+                               0.1246289712555339, 0.0951585116824928, 0.0622535239386479, 0.0271524594117541};
+  const double l0 = std::log(a), l1 = std::log(b), h = (l1 - l0) / 8.0;
+  double sum = 0.0;
+  for (int p = 0; p < 8; ++p) {
+    const double c = l0 + (p + 0.5) * h, r = 0.5 * h;
+    for (int k = 0; k < 8; ++k)
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const double x = std::exp(c + sgn * r * xg[k]);
+        sum += wg[k] * r * f(x) * x;
+      }
+  }
+  return sum;
+}
+
+static double hubble(double a, double om) { return std::sqrt(om / (a * a * a) + (1.0 - om)); }
+
 std::vector<StepCoef> step_table(const Growth& g, double a_start, double a_end, int n_steps, int stepper,
                                  int time_var) {
   std::vector<StepCoef> out;
+  const double om = g.omega_m;
+  // superconformal time from a_start (dt_sc = dt / a^2 = da / (a^3 H)) and its inverse by bisection
+  auto sconf = [&](double a) { return integrate_lnx([&](double x) { return 1.0 / (x * x * x * hubble(x, om)); }, a_start, a); };
+  auto a_of_sc = [&](double t) {
+    if (t <= 0.0) return a_start;
+    double lo = a_start, hi = a_end * 1.5;
+    for (int it = 0; it < 200 && hi - lo > 1e-16 * hi; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      (sconf(mid) < t ? lo : hi) = mid;
+    }
+    return 0.5 * (lo + hi);
+  };
   auto D_of_t = [&](double t) {
-    return time_var == 1 ? g.D_of_a(t) : (time_var == 2 ? g.D_of_a(std::exp(t)) : t);
+    return time_var == 1 ? g.D_of_a(t)
+                         : (time_var == 2 ? g.D_of_a(std::exp(t)) : (time_var == 3 ? g.D_of_a(a_of_sc(t)) : t));
   };
   double t0, t1;
-  if (time_var == 1) {
+  if (time_var == 3) {
+    t0 = 0.0;
+    t1 = sconf(a_end);
+  } else if (time_var == 1) {
     t0 = a_start;
     t1 = a_end;
   } else if (time_var == 2) {
@@ -148,6 +187,17 @@ std::vector<StepCoef> step_table(const Growth& g, double a_start, double a_end, 
     double Dn = D_of_t(t0 + n * dt), Dh = D_of_t(t0 + (n + 0.5) * dt);
     double Dp = D_of_t(n + 1 < n_steps ? t0 + (n + 1) * dt : t1);
     double alpha;
+    if (stepper == 2) {
+      // canonical momentum V = a^2 dX/dt: the symplectic leapfrog of the
+      // comoving equations (H0 = 1): alpha = 1, kick int da / (H a^2), the two
+      // drifts int da / (H a^3), force of the Poisson equation s = 3/2 Omega_m
+      const double an = g.a_of_D(Dn), ah = g.a_of_D(Dh), ap = g.a_of_D(Dp);
+      auto drift = [&](double x) { return 1.0 / (hubble(x, om) * x * x * x); };
+      auto kick = [&](double x) { return 1.0 / (hubble(x, om) * x * x); };
+      out.push_back({Dn, Dh, Dp, 1.0, integrate_lnx(kick, an, ap), integrate_lnx(drift, an, ah),
+                     integrate_lnx(drift, ah, ap), 1.5 * om});
+      continue;
+    }
     if (stepper == 1) {
       alpha = g.zeta(g.a_of_D(Dn)) / g.zeta(g.a_of_D(Dp));
     } else {

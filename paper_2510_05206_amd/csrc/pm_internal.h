@@ -39,7 +39,8 @@ struct Growth {            // D(a), E(a) of the growth ODEs (D ~ a normalisation
   double zeta(double a) const;  // H a^3 dD/da (FastPM)
 };
 
-// stepper 0 BullFrog, 1 FastPM; time_var 0 uniform in D, 1 in a, 2 in ln a
+// stepper 0 BullFrog, 1 FastPM, 2 leapfrog in the canonical momentum;
+// time_var 0 uniform in D, 1 in a, 2 in ln a, 3 in superconformal time
 std::vector<StepCoef> step_table(const Growth& g, double a_start, double a_end, int n_steps, int stepper,
                                  int time_var);
 double bbks_amplitude(double omega_m, double h, double n_s, double sigma8);

@@ -22,6 +22,7 @@ struct pm_ctx {
   std::vector<int> slot_steps;
   std::vector<double> slot_sigma8;
   double D0 = 0, D_ref = 1, amp = 0;
+  double vfac = 1;  // initial velocity per unit dX/dD: zeta(a_start) for the canonical momentum, else 1
   int Lmax = 0;
   // host tables
   std::vector<float2> tw;
@@ -875,7 +876,7 @@ pm_status lpt2_from_mu(pm_ctx* c, const float* mu, long long mu_stride, float* v
   r2.src = cspec;
   r2.dst_mode = DST_IC2;
   r2.dst_stride = 3 * N;
-  r2.scale = 2.0 * c->D0;
+  r2.scale = 2.0 * c->D0 * c->vfac;
   r2.scale2 = c->D0 * c->D0;
   r2.ic_log2pb = c->g.log2_pb;
   for (int comp = 0; comp < 3; ++comp) {
@@ -937,7 +938,7 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
   // (pruned register FFT passes: n_p >= 8)
   if (c.lpt_order < 0 || c.lpt_order > 2 || (c.lpt_order == 2 && (c.n_g < 2 * c.n_p || c.n_p < 8)))
     return PM_EINVAL;
-  if (c.stepper < 0 || c.stepper > 1 || c.time_var < 0 || c.time_var > 2) return PM_EINVAL;
+  if (c.stepper < 0 || c.stepper > 2 || c.time_var < 0 || c.time_var > 3) return PM_EINVAL;
   if (c.antialias < 0 || c.antialias > 1 || (c.antialias && (c.force != PM_FORCE_PM || c.n_g < 16)))
     return PM_EINVAL;
   pm_ctx* ctx = new (std::nothrow) pm_ctx();
@@ -946,6 +947,7 @@ pm_status pm_create(const pm_config* cfg, pm_ctx** out) {
   ctx->growth.solve(c.omega_m);
   ctx->table = step_table(ctx->growth, c.a_start, c.a_end, c.n_steps, c.stepper, c.time_var);
   ctx->D0 = ctx->growth.D_of_a(c.a_start);
+  ctx->vfac = c.stepper == 2 ? ctx->growth.zeta(c.a_start) : 1.0;
   ctx->D_ref = ctx->growth.D_of_a(1.0);
   if (c.spectrum == PM_SPEC_BBKS)
     ctx->amp = bbks_amplitude(c.omega_m, c.h, c.n_s, c.sigma8);
@@ -1211,8 +1213,8 @@ static pm_status ic_chain(pm_ctx* c, const float* w, float* disp, float* vel, un
     rl.tw = c->d_tw;
     rl.tws_half = c->Lmax / (np / 2);
     rl.tws_full = c->Lmax / np;
-    rl.scale = 1.0;
-    rl.scale2 = c->D0;
+    rl.scale = c->vfac;  // V = vfac psi, Psi = (D0 / vfac) V
+    rl.scale2 = c->D0 / c->vfac;
     rl.ic_log2pb = c->g.log2_pb;
     rl.stream = c->stream;
     rl.active = act;
@@ -1692,8 +1694,9 @@ static pm_status lpt2_adjoint(pm_ctx* c, unsigned long long act) {
   float2* fspec = c->spec;
   float2* Q = c->icspec + 3 * c->icspec_comp;
   float* psibar = c->u_sorted;
-  // psi2_bar = 2 D0 (D0/2 X_bar + V_bar); the factor 2 D0 rides on the multiplier
-  std::vector<float> half(B, (float)(0.5 * c->D0));
+  // psi2_bar = D0^2 X_bar + 2 D0 vfac V_bar = 2 D0 vfac (D0 / (2 vfac) X_bar + V_bar);
+  // the factor 2 D0 vfac rides on the multiplier
+  std::vector<float> half(B, (float)(0.5 * c->D0 / c->vfac));
   KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, half.data(), c->g.log2_np,
                                        c->g.log2_pb, act, c->stream));
   for (int comp = 0; comp < 3; ++comp) {
@@ -1719,7 +1722,7 @@ static pm_status lpt2_adjoint(pm_ctx* c, unsigned long long act) {
   m.zlim = np / 2;
   m.keep = np;
   m.keep_outer = 1;
-  for (int b = 0; b < B; ++b) m.coef[b] = (float)(3.0 / 7.0 / ((double)P * P * P) * 2.0 * c->D0);
+  for (int b = 0; b < B; ++b) m.coef[b] = (float)(3.0 / 7.0 / ((double)P * P * P) * 2.0 * c->D0 * c->vfac);
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(m, MODE_LPT_MUBAR, B, c->stream));
   ColArgs my = m;
   my.axis = 1;
@@ -1902,7 +1905,8 @@ pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, doubl
   // (plus the second-order term's pullback, gathered first)
   if (c->cfg.lpt_order == 2)
     if (pm_status st = lpt2_adjoint(c, c->user_mask)) return st;
-  std::vector<float> d0(B, (float)c->D0);
+  // with the canonical momentum V = vfac psi: psi_bar = vfac (D0 / vfac X_bar + V_bar)
+  std::vector<float> d0(B, (float)(c->D0 / c->vfac));
   float* psibar = c->u_sorted;
   KLAUNCH(c, PM_K_MISC, launch_psibar(c->xbar, c->vbar, psibar, N, 3 * N, B, d0.data(), c->g.log2_np, c->g.log2_pb,
                                        c->user_mask, c->stream));
@@ -1927,7 +1931,7 @@ pm_status pm_adjoint_full(pm_ctx* c, const float* dL_ddelta, float* dL_dw, doubl
   ca.active = act;
   ca.axis = 0;
   for (int b = 0; b < B; ++b)
-    ca.fac[b] = (float)(c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0);
+    ca.fac[b] = (float)((c->cfg.spectrum == PM_SPEC_BBKS ? c->slot_sigma8[b] / c->cfg.sigma8 : 1.0) * c->vfac);
   ca.combine_add = c->cfg.lpt_order == 2;
   KLAUNCH(c, PM_K_FFT_COLS, fft_cols(ca, MODE_COMBINE_IC, B, c->stream));
   ca.axis = 1;

@@ -35,8 +35,8 @@ class Config:
     es_beta: float = 13.8
     batch: int = 1
     lpt_order: int = 1            # 1 Zel'dovich, 2 second-order LPT initial state
-    stepper: str = "bullfrog"     # "bullfrog" | "fastpm"
-    time_var: str = "D"           # step spacing uniform in "D" | "a" | "lna"
+    stepper: str = "bullfrog"     # "bullfrog" | "fastpm" | "leapfrog" (canonical momentum)
+    time_var: str = "D"           # step spacing uniform in "D" | "a" | "lna" | "superconft"
     antialias: int = 0            # 1: interlaced grids for the PM force
 
     def to_c(self):
@@ -48,9 +48,9 @@ class Config:
             elif f.name == "force":
                 v = _lib.PM_FORCE_PM if v == "pm" else _lib.PM_FORCE_NUFFT
             elif f.name == "stepper":
-                v = {"bullfrog": 0, "fastpm": 1}[v]
+                v = {"bullfrog": 0, "fastpm": 1, "leapfrog": 2}[v]
             elif f.name == "time_var":
-                v = {"D": 0, "a": 1, "lna": 2}[v]
+                v = {"D": 0, "a": 1, "lna": 2, "superconft": 3}[v]
             elif isinstance(v, bool):
                 v = int(v)
             setattr(c, f.name, v)

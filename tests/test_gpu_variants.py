@@ -1,7 +1,9 @@
 """GPU runs with the other steppers and step spacings of Sec. "Time
-stepping" (FastPM, steps uniform in a or ln a) against the FP64 oracle,
-through the C ABI.  Only the host tables differ from the BullFrog runs; the
-runs check that they reach the kernels."""
+stepping" (FastPM, the canonical-momentum leapfrog; steps uniform in a, ln a
+or superconformal time) against the FP64 oracle, through the C ABI: runs,
+the gradient with its temporal adjoints and the forward-mode tangent.  Only
+the host tables and the initial velocity factor differ from the BullFrog
+runs; the runs check that they reach the kernels."""
 import sys
 
 import numpy as np
@@ -10,6 +12,7 @@ import torch
 
 import synth
 from oracle import adjoint as oadj
+from oracle import jvp as ojvp
 from oracle import nbody as onbody
 from oracle import philox as ophilox
 
@@ -34,7 +37,8 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("stepper,tv", [("fastpm", "D"), ("bullfrog", "a"), ("fastpm", "lna")])
+@pytest.mark.parametrize("stepper,tv", [("fastpm", "D"), ("bullfrog", "a"), ("fastpm", "lna"),
+                                       ("bullfrog", "superconft"), ("leapfrog", "a"), ("leapfrog", "superconft")])
 def test_run_with_stepper_and_time_variable(stepper, tv):
     from paper_2510_05206_amd import PMSim
     d = dict(synth.C2_SMALL, stepper=stepper, time_var=tv)
@@ -48,3 +52,81 @@ def test_run_with_stepper_and_time_variable(stepper, tv):
     err = rel_l2(delta, oadj.final_density(prob, psi))
     say(f"{stepper}/{tv}: density rel L2 {err:.2e}")
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("stepper", ["bullfrog", "fastpm"])
+def test_plane_wave_follows_zeldovich_before_shell_crossing(stepper):
+    # EdS (D = a): both steppers are Zel'dovich consistent, so a plane wave
+    # psi_x = -(A/k) sin(k q_x) (A = 1/2: half way to shell crossing at
+    # a = 1) ends at q + D psi up to the PM force error, which shrinks as
+    # the mesh is refined (TSC)
+    from paper_2510_05206_amd import PMSim
+    n_p, box, A = 32, 100.0, 0.5
+    kw, dq = 2 * np.pi / box, box / n_p
+    qx = (np.arange(n_p ** 3) // (n_p * n_p)) * dq
+    psi = np.zeros((1, 3, n_p ** 3))
+    psi[0, 0] = -(A / kw) * np.sin(kw * qx) / dq
+    errs = []
+    for n_g in (64, 128):
+        d = dict(synth.C1, n_g=n_g, mak=3, stepper=stepper, n_steps=6)
+        assert d["omega_m"] == 1.0 and d["a_start"] == 0.02 and d["a_end"] == 1.0
+        sim = PMSim(synth.gpu_config(d))
+        sim.set_state(torch.from_numpy((0.02 * psi).astype(np.float32)), torch.from_numpy(psi.astype(np.float32)))
+        sim.run()
+        x, _ = sim.get_state()
+        errs.append(np.abs(x.cpu().numpy().astype(np.float64) - psi).max() / (A / kw / dq))
+    say(f"plane wave {stepper}: max error / amplitude {errs[0]:.2e} (64^3 mesh), {errs[1]:.2e} (128^3)")
+    assert errs[0] < 0.015 and errs[1] < errs[0]
+
+
+# Steps uniform in a: the reverse pass rebuilds the trajectory from the final
+# FP32 state, and errors there grow backwards like the decaying mode, so
+# schedules that crowd the steps at early times (ln a, superconformal time)
+# rebuild the first states less well; FP32 rounding of the rebuilt states
+# alone, applied to the FP64 oracle, moves the first steps' temporal
+# adjoints by 1e-3 to 1e-2 there (1e-6 with steps uniform in a)
+@pytest.mark.parametrize("lpt", [1, 2])
+def test_leapfrog_gradient_and_temporal_adjoints_match_oracle(lpt):
+    from paper_2510_05206_amd import PMSim
+    d = dict(synth.C2_SMALL, stepper="leapfrog", time_var="a", lpt_order=lpt)
+    say("leapfrog gradient", lpt)
+    sim = PMSim(synth.gpu_config(d), with_adjoint=True)
+    sim.init_ics([synth.SEED_W])
+    sim.run()
+    delta = sim.density()
+    dw, ds, dt = sim.adjoint(2.0 * delta, temporal=True)
+    prob = synth.oracle_problem(d)
+    w = ophilox.white_noise(synth.SEED_W, d["n_p"]).astype(np.float64)
+    temporal = []
+    gw, gs, _ = oadj.gradient(prob, w, lambda dd: 2.0 * dd, temporal=temporal)
+    a = dw.cpu().numpy()[0].astype(np.float64)
+    gw = gw.reshape(-1)
+    cos = a @ gw / np.linalg.norm(a) / np.linalg.norm(gw)
+    say(f"  cosine {cos:.6f} rel {rel_l2(a, gw):.2e} dsigma8 {float(ds[0]):.5e} vs {gs:.5e}")
+    assert cos > 0.999 and rel_l2(a, gw) < 1e-2 and abs(float(ds[0]) / gs - 1) < 1e-2
+    ref = np.array(temporal)
+    got = dt.cpu().numpy()[0]
+    for j, name in enumerate(("tau1", "tau2", "alpha", "beta")):
+        rel = np.linalg.norm(got[:, j] - ref[:, j]) / np.linalg.norm(ref[:, j])
+        say(f"  {name}_bar rel L2 {rel:.2e}")
+        assert rel < 5e-3
+
+
+@pytest.mark.parametrize("lpt", [1, 2])
+def test_leapfrog_tangent_matches_oracle(lpt):
+    # TSC force (continuous derivative): the tangent positions to 1e-4, the
+    # contrast (a CIC gradient-kernel scatter with node-plane steps) to 2e-2
+    from paper_2510_05206_amd import PMSim
+    d = dict(synth.C2_SMALL, stepper="leapfrog", time_var="superconft", lpt_order=lpt, mak=3, grad_order=4)
+    say("leapfrog jvp", lpt)
+    sim = PMSim(synth.gpu_config(d), with_adjoint=True)
+    sim.init_ics([synth.SEED_W])
+    wd = np.random.default_rng(35).normal(size=d["n_p"] ** 3).astype(np.float32)
+    dd = sim.jvp(torch.from_numpy(wd), [0.25]).cpu().numpy()[0]
+    xd = sim.get_tangent()[0].cpu().numpy()[0]
+    prob = synth.oracle_problem(d)
+    w = ophilox.white_noise(synth.SEED_W, d["n_p"]).astype(np.float64)
+    _, xref, _, ref = ojvp.run_jvp(prob, w, wd.astype(np.float64), 0.25)
+    ex, err = rel_l2(xd, xref), rel_l2(dd, ref)
+    say(f"  tangent positions rel L2 {ex:.2e}; contrast {err:.2e}")
+    assert ex < 1e-4 and err < 2e-2

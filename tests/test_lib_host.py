@@ -76,9 +76,12 @@ def test_host_schedule_matches_oracle(lib, wl):
     lib.pm_destroy(ctx)
 
 
-@pytest.mark.parametrize("stepper,tv", [("fastpm", "D"), ("bullfrog", "a"), ("fastpm", "lna"), ("bullfrog", "lna")])
-def test_host_schedule_variants_match_oracle(lib, stepper, tv):
-    d = dict(synth.C2, stepper=stepper, time_var=tv)
+@pytest.mark.parametrize("stepper,tv,om", [("fastpm", "D", 0.31), ("bullfrog", "a", 0.31), ("fastpm", "lna", 0.31),
+                                           ("bullfrog", "lna", 0.31), ("bullfrog", "superconft", 0.31),
+                                           ("leapfrog", "a", 0.31), ("leapfrog", "superconft", 0.31),
+                                           ("leapfrog", "lna", 1.0), ("fastpm", "superconft", 1.0)])
+def test_host_schedule_variants_match_oracle(lib, stepper, tv, om):
+    d = dict(synth.C2, stepper=stepper, time_var=tv, omega_m=om)
     st, ctx = _create(lib, **d)
     assert st == 0
     n = d["n_steps"]
