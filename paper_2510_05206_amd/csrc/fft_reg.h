@@ -95,20 +95,20 @@ struct Shape {
   __host__ __device__ static int t_out(int n1, int r) { return (n1 + (r / P) * P) + E * (r % P); }
 };
 
-// row passes: R contiguous rows per block, lanes run along the row first so
-// that a wave reads P consecutive values of each of 64 / P rows
-template <int L_, int P_>
+// row passes: R contiguous rows per block of NT threads, lanes run along the
+// row first so that a wave reads P consecutive values of each of 64 / P rows
+template <int L_, int P_, int NT = 256>
 struct RowShape {
   static constexpr int L = L_;
   static constexpr int P = P_;
-  static constexpr int R = 256 / P;   // rows per block
+  static constexpr int R = NT / P;    // rows per block
   static constexpr int E = L / P;
   static constexpr int J = E / P;
   static constexpr int PAD = 16;
   static constexpr int KS = P * R + PAD;
   static constexpr int RS = L + 1;    // natural row stride in LDS
   static constexpr int LDS = (E * KS > R * RS) ? E * KS : R * RS;
-  static_assert(P * R == 256, "256 threads per block");
+  static_assert(P * R == NT && NT % 64 == 0, "whole waves of whole rows");
   static_assert(E >= P && E % P == 0 && E <= 32 && P <= 32, "shape");
   __host__ __device__ static int lane_c(int tid) { return tid / P; }
   __host__ __device__ static int lane_n1(int tid) { return tid % P; }
