@@ -254,9 +254,7 @@ __global__ void __launch_bounds__(kPmDepositThreads) k_tile_deposit(TileArgs a) 
                a.log2nt);
 }
 
-// Sum the windows covering each cell (windows.h), in a fixed order.  OUT_F32
-// converts the int64 sums with inv_scale (or scale and shift); with an FP32
-// slab the partial sums add in FP32 and the shift follows.
+// sum of the windows covering one cell (windows.h), in a fixed order
 template <class V>
 __device__ __forceinline__ V assemble_cell(const AssembleArgs& a, const V* __restrict__ slab, int x, int y, int z) {
   const int T = a.T, Rlo = a.Rlo, Rhi = a.Rhi, W = T + Rlo + Rhi;
@@ -265,70 +263,122 @@ __device__ __forceinline__ V assemble_cell(const AssembleArgs& a, const V* __res
                  win_cover(z, T, Rlo, Rhi, a.log2T, ntm), W, 1 << a.log2nt);
 }
 
-// z-run of one block (n >= 256): the x and y covers are block-uniform, so the
-// window-row bases are scalar and each thread only adds its z offset
-template <class V>
-__device__ __forceinline__ V assemble_run(const AssembleArgs& a, const V* __restrict__ slab, int x, int y, int z) {
+// z-runs of one block (n >= 256): the x and y covers are block-uniform, so
+// the window-row bases are scalar and each thread only adds its z offsets.
+// NX x NY covering rows (a block-uniform case); every load of the thread's
+// CPT cells is issued before the sums: the second z cover is read for every
+// cell (clamped to the first where the cell has one) and masked
+// arithmetically, since a load under a per-lane branch is waited for inside
+// it, which serialises a thread's loads.  The sums run in the order of
+// win_sum (rows by x cover, then y cover; z covers in order).
+__device__ __forceinline__ float keep_if(float v, bool k) { return v * (k ? 1.f : 0.f); }
+__device__ __forceinline__ long long keep_if(long long v, bool k) { return v & -(long long)k; }
+
+template <int NX, int NY, int CPT, class V>
+__device__ __forceinline__ void assemble_runs(const AssembleArgs& a, const V* __restrict__ slab, const Cover2& cx,
+                                              const Cover2& cy, long long e0, V (&acc)[CPT]) {
   const int T = a.T, Rlo = a.Rlo, Rhi = a.Rhi, W = T + Rlo + Rhi;
-  const int nt = 1 << a.log2nt, ntm = nt - 1;
-  const Cover2 cx = cover2(x, T, Rlo, Rhi, a.log2T, ntm), cy = cover2(y, T, Rlo, Rhi, a.log2T, ntm);
-  const Cover2 cz = cover2(z, T, Rlo, Rhi, a.log2T, ntm);
-  const int oz0 = cz.t0 * W + cz.l0, oz1 = cz.t1 * W + cz.l1;  // offsets within a row run of nt W values
-  V acc = 0;
+  const int nt = 1 << a.log2nt, ntm = nt - 1, nm = a.g.n_g - 1;
+  constexpr int NR = NX * NY;
+  const V* row[NR];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int p = 0; p < NX; ++p)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if ((p && !cx.two) || (q && !cy.two)) continue;
-      const V* row = slab + slab_row(p ? cx.t1 : cx.t0, q ? cy.t1 : cy.t0, 0, p ? cx.l1 : cx.l0, q ? cy.l1 : cy.l0,
-                                     W, nt);
-      acc += row[oz0];
-      if (cz.two) acc += row[oz1];
+    for (int q = 0; q < NY; ++q)
+      row[p * NY + q] =
+          slab + slab_row(p ? cx.t1 : cx.t0, q ? cy.t1 : cy.t0, 0, p ? cx.l1 : cx.l0, q ? cy.l1 : cy.l0, W, nt);
+  V v0[CPT][NR], v1[CPT][NR];
+  bool two[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const Cover2 cz = cover2((int)((e0 + threadIdx.x + 256 * k) & nm), T, Rlo, Rhi, a.log2T, ntm);
+    // offsets within a row run of nt W values
+    const int oz0 = cz.t0 * W + cz.l0, oz1 = cz.two ? cz.t1 * W + cz.l1 : oz0;
+    two[k] = cz.two;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      v0[k][r] = row[r][oz0];
+      v1[k][r] = row[r][oz1];
     }
-  return acc;
+  }
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    acc[k] = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      acc[k] += v0[k][r];
+      acc[k] += keep_if(v1[k][r], two[k]);
+    }
+  }
 }
 
-// CPT cells per thread, 256 CPT consecutive cells per block: with n >= 256 CPT
-// and Rlo + Rhi <= T a block is one z-run of one (x, y) row (scalar covers).
-// All of a thread's sums are formed before any store (the slab and the
-// output may not alias, but the compiler cannot know).
-template <bool OUT_F32, int CPT>
+template <bool OUT_F32>
+__device__ __forceinline__ auto assemble_out(const AssembleArgs& a, int slot, long long acc) {
+  if constexpr (OUT_F32)
+    return (float)(a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift);
+  else
+    return acc;
+}
+
+// One cell per thread, any mesh and halo, in a fixed order.  OUT_F32
+// converts the int64 sums with inv_scale (or scale and shift); with an FP32
+// slab the partial sums add in FP32 and the shift follows.
+template <bool OUT_F32>
 __global__ void __launch_bounds__(256) k_assemble(AssembleArgs a) {
+  const int slot = blockIdx.y;
+  if (!slot_on(a.g.gate, a.active, slot)) return;
+  const int L = a.g.log2_ng, nm = a.g.n_g - 1;
+  const long long e = (long long)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (e >= a.g.M) return;
+  const int W = a.T + a.Rlo + a.Rhi;
+  const long long sl = (long long)slot * a.n_tiles * W * W * W;
+  const int x = (int)(e >> (2 * L)), y = (int)((e >> L) & nm), z = (int)(e & nm);
+  using V = typename std::conditional<OUT_F32, float, long long>::type;
+  V out;
+  if constexpr (OUT_F32) {
+    if (a.slab_f32)
+      out = assemble_cell(a, reinterpret_cast<const float*>(a.scratch) + sl, x, y, z) - (float)a.shift;
+    else
+      out = assemble_out<true>(a, slot, assemble_cell(a, reinterpret_cast<const long long*>(a.scratch) + sl, x, y, z));
+  } else {
+    out = assemble_cell(a, reinterpret_cast<const long long*>(a.scratch) + sl, x, y, z);
+  }
+  reinterpret_cast<V*>(a.out)[slot * a.g.mesh_stride + e] = out;
+}
+
+// z-runs: with n >= 256 CPT and Rlo + Rhi <= T a block of 256 threads sums
+// 256 CPT consecutive cells of one (x, y) row (scalar x and y covers), CPT
+// per thread, every load issued before the sums.  SLAB_F32: the windows are
+// FP32 partial sums (out = sum - shift).
+template <bool OUT_F32, bool SLAB_F32, int CPT>
+__global__ void __launch_bounds__(256) k_assemble_run(AssembleArgs a) {
   const int slot = blockIdx.y;
   if (!slot_on(a.g.gate, a.active, slot)) return;
   const int L = a.g.log2_ng, nm = a.g.n_g - 1;
   const long long e0 = (long long)xcd_block(blockIdx.x, gridDim.x) * (256 * CPT);
   const int W = a.T + a.Rlo + a.Rhi;
   const long long sl = (long long)slot * a.n_tiles * W * W * W;
-  const bool run = (1 << L) >= 256 * CPT && a.Rlo + a.Rhi <= a.T;
+  const int x = (int)(e0 >> (2 * L)), y = (int)((e0 >> L) & nm);
+  using S = typename std::conditional<SLAB_F32, float, long long>::type;
   using V = typename std::conditional<OUT_F32, float, long long>::type;
-  V out[CPT];
-#pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    const long long e = e0 + threadIdx.x + 256 * k;
-    out[k] = 0;
-    if (e >= a.g.M) continue;
-    const long long eb = run ? e0 : e;  // (x, y) from the block start: uniform
-    const int x = (int)(eb >> (2 * L)), y = (int)((eb >> L) & nm), z = (int)(e & nm);
-    if constexpr (OUT_F32) {
-      if (a.slab_f32) {
-        const float* sf = reinterpret_cast<const float*>(a.scratch) + sl;
-        out[k] = (run ? assemble_run(a, sf, x, y, z) : assemble_cell(a, sf, x, y, z)) - (float)a.shift;
-      } else {
-        const long long* si = reinterpret_cast<const long long*>(a.scratch) + sl;
-        const long long acc = run ? assemble_run(a, si, x, y, z) : assemble_cell(a, si, x, y, z);
-        out[k] = (float)(a.inv_scale ? (double)acc * a.inv_scale[slot] : (double)acc * a.scale - a.shift);
-      }
-    } else {
-      const long long* si = reinterpret_cast<const long long*>(a.scratch) + sl;
-      out[k] = run ? assemble_run(a, si, x, y, z) : assemble_cell(a, si, x, y, z);
-    }
+  const S* slab = reinterpret_cast<const S*>(a.scratch) + sl;
+  const int ntm = (1 << a.log2nt) - 1;
+  const Cover2 cx = cover2(x, a.T, a.Rlo, a.Rhi, a.log2T, ntm), cy = cover2(y, a.T, a.Rlo, a.Rhi, a.log2T, ntm);
+  S acc[CPT];
+  if (cx.two) {
+    if (cy.two) assemble_runs<2, 2>(a, slab, cx, cy, e0, acc);
+    else assemble_runs<2, 1>(a, slab, cx, cy, e0, acc);
+  } else {
+    if (cy.two) assemble_runs<1, 2>(a, slab, cx, cy, e0, acc);
+    else assemble_runs<1, 1>(a, slab, cx, cy, e0, acc);
   }
-  V* o = reinterpret_cast<V*>(a.out) + slot * a.g.mesh_stride;
+  V* o = reinterpret_cast<V*>(a.out) + slot * a.g.mesh_stride + e0 + threadIdx.x;
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
-    const long long e = e0 + threadIdx.x + 256 * k;
-    if (e < a.g.M) o[e] = out[k];
+    if constexpr (SLAB_F32)
+      o[256 * k] = acc[k] - (float)a.shift;
+    else
+      o[256 * k] = assemble_out<OUT_F32>(a, slot, acc[k]);
   }
 }
 
@@ -881,16 +931,25 @@ hipError_t launch_dipole_scale(const unsigned int* umax_bits, double* scale, dou
 }
 
 hipError_t launch_assemble(const AssembleArgs& a, bool out_f32, hipStream_t s) {
-  // four cells per thread (one 1024-cell row per block) from n = 1024 on:
-  // fewer, longer blocks with four times the loads in flight per thread
-  if (a.g.n_g >= 1024) {
-    dim3 grid((unsigned)((a.g.M + 1023) / 1024), a.batch);
-    if (out_f32) k_assemble<true, 4><<<grid, 256, 0, s>>>(a);
-    else k_assemble<false, 4><<<grid, 256, 0, s>>>(a);
+  if (a.slab_f32 && !out_f32) return hipErrorInvalidValue;
+  if (a.g.n_g >= 256 && a.Rlo + a.Rhi <= a.T) {
+    // z-runs; four cells per thread (one 1024-cell row per block) from
+    // n = 1024 on: fewer, longer blocks with four times the loads in flight
+    if (a.g.n_g >= 1024) {
+      dim3 grid((unsigned)(a.g.M / 1024), a.batch);
+      if (a.slab_f32) k_assemble_run<true, true, 4><<<grid, 256, 0, s>>>(a);
+      else if (out_f32) k_assemble_run<true, false, 4><<<grid, 256, 0, s>>>(a);
+      else k_assemble_run<false, false, 4><<<grid, 256, 0, s>>>(a);
+    } else {
+      dim3 grid((unsigned)(a.g.M / 256), a.batch);
+      if (a.slab_f32) k_assemble_run<true, true, 1><<<grid, 256, 0, s>>>(a);
+      else if (out_f32) k_assemble_run<true, false, 1><<<grid, 256, 0, s>>>(a);
+      else k_assemble_run<false, false, 1><<<grid, 256, 0, s>>>(a);
+    }
   } else {
     dim3 grid((unsigned)((a.g.M + 255) / 256), a.batch);
-    if (out_f32) k_assemble<true, 1><<<grid, 256, 0, s>>>(a);
-    else k_assemble<false, 1><<<grid, 256, 0, s>>>(a);
+    if (out_f32) k_assemble<true><<<grid, 256, 0, s>>>(a);
+    else k_assemble<false><<<grid, 256, 0, s>>>(a);
   }
   return hipGetLastError();
 }
