@@ -1022,27 +1022,26 @@ __device__ __forceinline__ int es_weights(long long U, const int32_t* tab, int w
 // cells), from the kernel's closed form: with z = dist / 3 cells,
 // d phi / d dist = -phi beta z / (3 sqrt(1 - z^2)); 1 - z = (3 - dist) / 3 is
 // formed from the integer distance, so the edge of the support stays exact.
-// below: the node lies below u (d dist / du = +1), else above (-1)
+// below: the node lies below u (d dist / du = +1), else above (-1).
+// Branch-free: a node is at most 3 cells away, where the table's phi is 0,
+// and there 1 - z is clamped to its smallest nonzero value so that the
+// derivative is 0 times a finite factor (a branch here would wait for the
+// table row of the farthest node inside it).  The product under the square
+// root is at least 2^-21, so the bare reciprocal square root needs no
+// denormal scaling.
 __device__ __forceinline__ void es_node_d(int wi, int dist, bool below, float beta, float& w, float& dw) {
   constexpr float inv = 1.0f / (float)(1 << kWeightBits);
   constexpr int kHalf = (kEsW / 2) << kFracBits;  // 3 cells
   constexpr float kInvHalf = 1.0f / (float)kHalf;
-  if (dist >= kHalf) {
-    w = 0.f;
-    dw = 0.f;
-    return;
-  }
   const float phi = (float)wi * inv;
   w = phi;
-  const float z = (float)dist * kInvHalf, omz = (float)(kHalf - dist) * kInvHalf;
-  const float dphi = -phi * beta * z * (1.0f / (float)(kEsW / 2)) * rsqrtf(omz * (1.f + z));
+  const float z = (float)dist * kInvHalf, omz = (float)max(kHalf - dist, 1) * kInvHalf;
+  const float dphi = -phi * beta * z * (1.0f / (float)(kEsW / 2)) * __builtin_amdgcn_rsqf(omz * (1.f + z));
   dw = (below && dist > 0) ? dphi : -dphi;
 }
 
-__device__ __forceinline__ int es_weights_d(long long U, const int32_t* __restrict__ tab, float beta,
-                                            float w[kEsW], float dw[kEsW]) {
-  EsAxis e;
-  const int h = es_axis(U, tab, e);
+// weights and derivatives from an axis' table rows
+__device__ __forceinline__ void es_axis_weights_d(const EsAxis& e, float beta, float w[kEsW], float dw[kEsW]) {
   int wi[kEsW];
   es_int_weights(e, wi);
   constexpr int one = 1 << kFracBits;
@@ -1052,6 +1051,13 @@ __device__ __forceinline__ int es_weights_d(long long U, const int32_t* __restri
   es_node_d(wi[3], e.g, false, beta, w[3], dw[3]);
   es_node_d(wi[4], one + e.g, false, beta, w[4], dw[4]);
   es_node_d(wi[5], 2 * one + e.g, false, beta, w[5], dw[5]);
+}
+
+__device__ __forceinline__ int es_weights_d(long long U, const int32_t* __restrict__ tab, float beta,
+                                            float w[kEsW], float dw[kEsW]) {
+  EsAxis e;
+  const int h = es_axis(U, tab, e);
+  es_axis_weights_d(e, beta, w, dw);
   return h;
 }
 
@@ -1340,22 +1346,12 @@ __device__ __forceinline__ void es_particle_d(const TileArgs& a, long long i, co
   }
 }
 
-// reverse kick of one particle and component from its window contraction
-__device__ __forceinline__ void es_adj_kick_one(const TileArgs& a, long long i, int p, int c, float A,
-                                                const float (&dA)[3], float al, float be, float r, float& umax) {
-  const long long N = a.g.N, ps = (long long)blockIdx.y * a.g.part_stride;
-  const float vb = a.vbar[ps + c * N + i];
-  const float u = be * vb;
-  a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A) / al;
-  a.vbar[ps + c * N + i] = al * vb;
-  a.u_sorted[ps + c * N + p] = u;
-  umax = fmaxf(umax, fabsf(u));
-#pragma unroll
-  for (int d = 0; d < 3; ++d) a.xbar[ps + d * N + i] += r * u * dA[d];
-}
-
 // The weights are recomputed per component: keeping them in registers over
-// the components costs more registers than the occupancy allows.
+// the components costs more registers than the occupancy allows.  The
+// particle loop keeps its dependent loads in flight together: the table rows
+// of all three axes are issued at once, the particle's velocity and
+// cotangents (read for the update) and the next particle's index and
+// coordinates load during the weights and the contraction.
 __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
   extern __shared__ float fwin[];  // one (T + 5)^3 window, the components in turn
   __shared__ float red[256];
@@ -1375,15 +1371,46 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_kick(TileArgs a) {
     if (c) __syncthreads();
     load_window_es(fwin, a.mesh_in + slot * 3 * a.comp_stride + c * a.comp_stride, o, a.g.log2_ng, nm);
     __syncthreads();
-    for (int p = beg + threadIdx.x; p < end; p += 256) {
-      const long long i = a.sorted[slot * N + p];
-      const float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
-      float w[3][kEsW], dw[3][kEsW];
+    int p = beg + (int)threadIdx.x;
+    long long i = 0;
+    float x[3] = {0.f, 0.f, 0.f};
+    if (p < end) {
+      i = a.sorted[slot * N + p];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d] = a.disp[ps + d * N + i];
+    }
+    for (; p < end; p += 256) {
+      long long j[3];
+      lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+      EsAxis e[3];
       int l0[3];
-      es_particle_d(a, i, x, o, umask, nm, w, dw, l0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        l0[d] = ((es_axis(fixed_coord(j[d], x[d], a.g.log2_r, umask), a.es_tab, e[d]) - kEsAnchor) & nm) - o[d];
+      const float v = a.vel[ps + c * N + i], vb = a.vbar[ps + c * N + i];
+      float xb[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xb[d] = a.xbar[ps + d * N + i];
+      const long long in = a.sorted[slot * N + min(p + 256, end - 1)];  // (the last round reads its own)
+      float w[3][kEsW], dw[3][kEsW];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) es_axis_weights_d(e[d], a.es_beta, w[d], dw[d]);
+      float xn[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xn[d] = a.disp[ps + d * N + in];
       float A, dA[3];
       es_contract_grad(fwin, W, l0, w, dw, A, dA);
-      es_adj_kick_one(a, i, p, c, A, dA, al, be, r, umax);
+      // reverse kick: V = (V - beta A) / alpha, V_bar = alpha V_bar, u = beta V_bar
+      const float u = be * vb;
+      a.vel[ps + c * N + i] = (v - be * A) / al;
+      a.vbar[ps + c * N + i] = al * vb;
+      a.u_sorted[ps + c * N + p] = u;
+      umax = fmaxf(umax, fabsf(u));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.xbar[ps + d * N + i] = xb[d] + r * u * dA[d];
+      i = in;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d] = xn[d];
     }
   }
   red[threadIdx.x] = umax;

@@ -604,21 +604,23 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
       }
       inverse_next = true;
     }
+    // NUFFT multipliers: the table reads are unconditional (lanes past the
+    // last column read column 0 and hold zeros, so their h is harmless): a
+    // read under the per-lane `valid` branch would be waited for in turn
     if constexpr (MODE == MODE_NUFFT_C) {
       // truncation, deconvolution and i k_c s / k^2 of component comp
       const float k0 = 6.283185307179586f / (float)a.n_p;
+      const int izc = valid ? iz : 0;
+      const float dyz = a.esdec[outer] * a.esdec[izc];
 #pragma unroll
       for (int r = 0; r < S::E; ++r) {
         const int t = S::t_out(n1, r);
-        float h = 0.f;
-        if (valid) {
-          float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
-          int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
-          float th2 = 0.f;
+        const float dec = a.esdec[t] * dyz;
+        const int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), izc};
+        float th2 = 0.f;
 #pragma unroll
-          for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
-          h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
-        }
+        for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
+        const float h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec * (k0 * ms[a.comp]) / th2;
         v[r] = make_float2(-h * v[r].y, h * v[r].x);  // i h v
       }
       inverse_next = true;
@@ -628,18 +630,17 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
       // -i k_c of the transposed multiplier, what is left is real:
       // coef / (k^2 Phi^2) on the kept modes (coef includes n_f / n_p)
       const float k0 = 6.283185307179586f / (float)a.n_p;
+      const int izc = valid ? iz : 0;
+      const float dyz = a.esdec[outer] * a.esdec[izc];
 #pragma unroll
       for (int r = 0; r < S::E; ++r) {
         const int t = S::t_out(n1, r);
-        float h = 0.f;
-        if (valid) {
-          float dec = a.esdec[t] * a.esdec[outer] * a.esdec[iz];
-          int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), iz};
-          float th2 = 0.f;
+        const float dec = a.esdec[t] * dyz;
+        const int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), izc};
+        float th2 = 0.f;
 #pragma unroll
-          for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
-          h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec / th2;
-        }
+        for (int q = 0; q < 3; ++q) th2 += (k0 * ms[q]) * (k0 * ms[q]);
+        const float h = (dec == 0.f || th2 == 0.f) ? 0.f : a.coef[slot] * dec / th2;
         v[r].x *= h;
         v[r].y *= h;
       }
