@@ -438,6 +438,15 @@ __device__ __forceinline__ void tile_weights(const TileArgs& a, long long i, con
 }
 
 // forward: A = gather(FD phi); V = alpha V + beta A; X += tau V (or A only)
+// The kick V' = alpha V + beta A and the drift X' = X + tau V with one fixed
+// rounding in every kernel and path: whether a b + c d is contracted into a
+// fused multiply-add, and which product it keeps, depends on the code around
+// it, and the forward ES kick takes a particle through one of two paths by
+// its rank in the tile list (which the binning's atomics set), so an implicit
+// contraction would make runs differ in the last bit.
+__device__ __forceinline__ float kick_v(float al, float v, float be, float A) { return fmaf(be, A, al * v); }
+__device__ __forceinline__ float drift_x(float x, float tp, float v) { return fmaf(tp, v, x); }
+
 template <int P, int ORD>
 __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
   constexpr int R = kernel_reach<P>() + ORD / 2;
@@ -472,9 +481,9 @@ __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float v = al * a.vel[ps + c * N + i] + be * A[c];
+      const float v = kick_v(al, a.vel[ps + c * N + i], be, A[c]);
       a.vel[ps + c * N + i] = v;
-      a.disp[ps + c * N + i] = x[c] + tp * v;
+      a.disp[ps + c * N + i] = drift_x(x[c], tp, v);
     }
   }
 }
@@ -828,9 +837,9 @@ __global__ void __launch_bounds__(256) k_tile_tan_kick(TileArgs a) {
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float v = al * a.vbar[ps + c * N + i] + be * J[c];
+      const float v = kick_v(al, a.vbar[ps + c * N + i], be, J[c]);
       a.vbar[ps + c * N + i] = v;
-      a.xbar[ps + c * N + i] += tp * v;
+      a.xbar[ps + c * N + i] = drift_x(a.xbar[ps + c * N + i], tp, v);
     }
   }
 }
@@ -1267,18 +1276,46 @@ __global__ void __launch_bounds__(256, 4) k_tile_es_kick(TileArgs a) {  // <= 12
       if (force_only)
         a.acc_out[ps + c * N + ik[k]] = A;
       else
-        vk[k][c] = al * vk[k][c] + be * A;
+        vk[k][c] = kick_v(al, vk[k][c], be, A);
     }
-    for (int p = beg + threadIdx.x + 256 * K; p < end; p += 256) {
-      const long long i = a.sorted[slot * N + p];
+    // the others: the table rows of the three axes together, the velocity
+    // and the next particle's coordinates in flight during the contraction
+    int p = beg + (int)threadIdx.x + 256 * K;
+    long long i = 0;
+    float x[3] = {0.f, 0.f, 0.f};
+    if (p < end) {
+      i = a.sorted[slot * N + p];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d] = a.disp[ps + d * N + i];
+    }
+    for (; p < end; p += 256) {
       float w[3][kEsW];
       int l0[3];
-      es_particle(a, i, o, umask, nm, w, l0);
+      {
+        long long j[3];
+        lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
+        EsAxis e[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          l0[d] = ((es_axis(fixed_coord(j[d], x[d], a.g.log2_r, umask), a.es_tab, e[d]) - kEsAnchor) & nm) - o[d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          int wi[kEsW];
+          es_int_weights(e[d], wi);
+#pragma unroll
+          for (int q = 0; q < kEsW; ++q) w[d][q] = (float)wi[q] * (1.0f / (float)(1 << kWeightBits));
+        }
+      }
+      const float v = force_only ? 0.f : a.vel[ps + c * N + i];
+      const long long in = a.sorted[slot * N + min(p + 256, end - 1)];  // (the last round reads its own)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d] = a.disp[ps + d * N + in];
       const float A = es_contract(fwin, W, l0, w);
       if (force_only)
         a.acc_out[ps + c * N + i] = A;
       else
-        a.vel[ps + c * N + i] = al * a.vel[ps + c * N + i] + be * A;
+        a.vel[ps + c * N + i] = kick_v(al, v, be, A);
+      i = in;
     }
   }
   if (force_only) return;
@@ -1288,13 +1325,19 @@ __global__ void __launch_bounds__(256, 4) k_tile_es_kick(TileArgs a) {  // <= 12
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       a.vel[ps + c * N + ik[k]] = vk[k][c];
-      a.disp[ps + c * N + ik[k]] = xk[k][c] + tp * vk[k][c];
+      a.disp[ps + c * N + ik[k]] = drift_x(xk[k][c], tp, vk[k][c]);
     }
   }
   for (int p = beg + threadIdx.x + 256 * K; p < end; p += 256) {  // this thread's own V writes
     const long long i = a.sorted[slot * N + p];
+    float x[3], v[3];  // every load before the stores (which the compiler cannot order past them)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.disp[ps + c * N + i] += tp * a.vel[ps + c * N + i];
+    for (int c = 0; c < 3; ++c) {
+      x[c] = a.disp[ps + c * N + i];
+      v[c] = a.vel[ps + c * N + i];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.disp[ps + c * N + i] = drift_x(x[c], tp, v[c]);
   }
 }
 
@@ -1525,18 +1568,40 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
   const long long umask = (1ll << (a.g.log2_ng + kFracBits)) - 1;
   const int nm = a.g.n_g - 1;
   const float cf = a.coef[slot] * (float)(1 << a.g.log2_r), tau = a.tau[slot];
-  for (int p = beg + threadIdx.x; p < end; p += 256) {
-    const long long i = a.sorted[slot * N + p];
+  // as in the adjoint kick: the table rows of the three axes together, the
+  // update operands and the next particle's coordinates in flight during the
+  // contraction
+  int p = beg + (int)threadIdx.x;
+  long long i = 0;
+  float xv[3] = {0.f, 0.f, 0.f};
+  if (p < end) {
+    i = a.sorted[slot * N + p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv[c] = a.disp[ps + c * N + i];
+  }
+  for (; p < end; p += 256) {
+    const float x[3] = {xv[0], xv[1], xv[2]};
     long long j[3];
     lattice_of(i, a.g.log2_np, a.g.log2_pb, j);
-    float x[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
-    float w[3][kEsW], dw[3][kEsW];
+    EsAxis e[3];
     int l0[3];
 #pragma unroll
+    for (int c = 0; c < 3; ++c)
+      l0[c] = ((es_axis(fixed_coord(j[c], x[c], a.g.log2_r, umask), a.es_tab, e[c]) - kEsAnchor) & nm) - o[c];
+    float xb0[3], v0[3], vb0[3], il[3];
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-      long long U = fixed_coord(j[c], x[c], a.g.log2_r, umask);
-      l0[c] = ((es_weights_d(U, a.es_tab, a.es_beta, w[c], dw[c]) - kEsAnchor) & nm) - o[c];
+      xb0[c] = a.il_out ? 0.f : a.xbar[ps + c * N + i];
+      v0[c] = a.il_out ? 0.f : a.vel[ps + c * N + i];
+      vb0[c] = a.il_out ? 0.f : a.vbar[ps + c * N + i];
+      il[c] = a.il_in ? a.il_in[2 * ps + c * N + i] : 0.f;
     }
+    const long long in = a.sorted[slot * N + min(p + 256, end - 1)];  // (the last round reads its own)
+    float w[3][kEsW], dw[3][kEsW];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) es_axis_weights_d(e[c], a.es_beta, w[c], dw[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv[c] = a.disp[ps + c * N + in];
     float gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll
     for (int xx = 0; xx < kEsW; ++xx) {
@@ -1562,21 +1627,21 @@ __global__ void __launch_bounds__(256) k_tile_es_adj_drift(TileArgs a) {
     float g[3] = {cf * gx, cf * gy, cf * gz};
     if (a.il_in) {  // interlaced grids: the mean of the two grids' scatter terms
 #pragma unroll
-      for (int c = 0; c < 3; ++c) g[c] = 0.5f * (g[c] + a.il_in[2 * ps + c * N + i]);
+      for (int c = 0; c < 3; ++c) g[c] = 0.5f * (g[c] + il[c]);
     }
     if (a.il_out) {  // the first grid: its term only, the state untouched
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.il_out[2 * ps + c * N + i] = g[c];
-      continue;
-    }
+    } else {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float xb = a.xbar[ps + c * N + i] + g[c];
-      float v = a.vel[ps + c * N + i];
-      a.disp[ps + c * N + i] = x[c] - tau * v;
-      a.xbar[ps + c * N + i] = xb;
-      a.vbar[ps + c * N + i] += tau * xb;
+      for (int c = 0; c < 3; ++c) {
+        const float xb = xb0[c] + g[c];
+        a.disp[ps + c * N + i] = x[c] - tau * v0[c];
+        a.xbar[ps + c * N + i] = xb;
+        a.vbar[ps + c * N + i] = vb0[c] + tau * xb;
+      }
     }
+    i = in;
   }
 }
 
@@ -1622,13 +1687,14 @@ __global__ void __launch_bounds__(256) k_tile_es_tan_kick(TileArgs a) {
       int l0[3];
       es_particle(a, i, o, umask, nm, w, l0);
       const float J = es_contract(fwin, W, l0, w) + a.acc_out[ps + c * N + i];
-      a.vbar[ps + c * N + i] = al * a.vbar[ps + c * N + i] + be * J;
+      a.vbar[ps + c * N + i] = kick_v(al, a.vbar[ps + c * N + i], be, J);
     }
   }
   for (int p = beg + threadIdx.x; p < end; p += 256) {  // this thread's own particles
     const long long i = a.sorted[slot * N + p];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.xbar[ps + c * N + i] += tp * a.vbar[ps + c * N + i];
+    for (int c = 0; c < 3; ++c)
+      a.xbar[ps + c * N + i] = drift_x(a.xbar[ps + c * N + i], tp, a.vbar[ps + c * N + i]);
   }
 }
 
