@@ -479,11 +479,14 @@ __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
       for (int c = 0; c < 3; ++c) a.acc_out[ps + c * N + i] = A[c];
       continue;
     }
+    float v[3];  // every load before the stores, which the compiler cannot order past them
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = a.vel[ps + c * N + i];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float v = kick_v(al, a.vel[ps + c * N + i], be, A[c]);
-      a.vel[ps + c * N + i] = v;
-      a.disp[ps + c * N + i] = drift_x(x[c], tp, v);
+      v[c] = kick_v(al, v[c], be, A[c]);
+      a.vel[ps + c * N + i] = v[c];
+      a.disp[ps + c * N + i] = drift_x(x[c], tp, v[c]);
     }
   }
 }
@@ -543,13 +546,18 @@ __global__ void __launch_bounds__(256, 2) k_tile_adj_kick(TileArgs a) {  // <= 2
       }
       continue;
     }
+    float v[3], xb[3];  // every load before the stores
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      a.vel[ps + c * N + i] = (a.vel[ps + c * N + i] - be * A[c]) / al;
-      a.vbar[ps + c * N + i] = al * vb[c];
+      v[c] = a.vel[ps + c * N + i];
+      xb[c] = a.xbar[ps + c * N + i];
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) a.xbar[ps + d * N + i] += tx[d];
+    for (int c = 0; c < 3; ++c) {
+      a.vel[ps + c * N + i] = (v[c] - be * A[c]) / al;
+      a.vbar[ps + c * N + i] = al * vb[c];
+      a.xbar[ps + c * N + i] = xb[c] + tx[c];
+    }
   }
   red[threadIdx.x] = umax;
   __syncthreads();
@@ -710,13 +718,18 @@ __global__ void __launch_bounds__(256) k_tile_adj_drift(TileArgs a) {
       for (int c = 0; c < 3; ++c) a.il_out[2 * ps + c * N + i] = g[c];
       continue;
     }
+    float xb[3], v[3], vb[3];  // every load before the stores
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float xb = a.xbar[ps + c * N + i] + g[c];
-      float v = a.vel[ps + c * N + i];
-      a.disp[ps + c * N + i] = x[c] - tau * v;
-      a.xbar[ps + c * N + i] = xb;
-      a.vbar[ps + c * N + i] += tau * xb;
+      xb[c] = a.xbar[ps + c * N + i] + g[c];
+      v[c] = a.vel[ps + c * N + i];
+      vb[c] = a.vbar[ps + c * N + i];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.disp[ps + c * N + i] = x[c] - tau * v[c];
+      a.xbar[ps + c * N + i] = xb[c];
+      a.vbar[ps + c * N + i] = vb[c] + tau * xb[c];
     }
   }
 }
