@@ -473,8 +473,28 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
   const int iz = (int)(lid % gridDim.x) * C + c;
   const int zl = a.zlim > 0 && a.zlim < a.nh ? a.zlim : a.nh;
   const bool valid = iz < zl;
+  const int izc = valid ? iz : 0;  // an in-range column for table reads of the lanes past the last
   auto kept = [&](int t) { int m = signed_mode(t, a.n); return 2 * (m < 0 ? -m : m) < a.keep; };
   if (a.keep_outer && !kept(outer)) return;  // block-uniform
+  // the 1D tables of a fused multiplier, staged in LDS (visible after the
+  // forward transform's barriers): read from global memory inside the
+  // multiplier loop, a thread's E reads were waited for one at a time (the
+  // kernel sits at its register cap)
+  constexpr bool kTabDec = MODE == MODE_NUFFT_C || MODE == MODE_NUFFT_ADJ;
+  constexpr bool kTabLap = MODE == MODE_FUSED_H || MODE == MODE_FUSED_IL;
+  __shared__ float tab0[(kTabDec || kTabLap) ? L : 1], tab1[kTabLap ? L : 1];
+  if constexpr (kTabDec) {
+    for (int k = threadIdx.x; k < L; k += 256) tab0[k] = a.esdec[k];
+  }
+  if constexpr (kTabLap) {
+    for (int k = threadIdx.x; k < L; k += 256) {
+      tab0[k] = a.lap[k];
+      tab1[k] = a.win2[k];
+    }
+  }
+  // the slot's multiplier coefficient, read once (inside the loop it was
+  // re-read, and waited for, per element)
+  const float fc = kTabLap ? fused_coef(a, slot) : 0.f;
   const long long stride_t = a.axis == 1 ? (long long)a.rs : (long long)a.n * a.rs;
   const long long base0 = a.axis == 1 ? (long long)outer * a.n * a.rs : (long long)outer * a.rs;
   const long long col = slot * a.slot_stride + base0 + iz;
@@ -558,9 +578,9 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
 #pragma unroll
       for (int r = 0; r < S::E; ++r) {
         const int t = S::t_out(n1, r);
-        float l = a.lap[t] + a.lap[outer] + (valid ? a.lap[iz] : 0.f);
-        float w = a.win2[t] * a.win2[outer] * (valid ? a.win2[iz] : 1.f);
-        float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : fused_coef(a, slot) / (l * w);
+        float l = tab0[t] + tab0[outer] + (valid ? tab0[izc] : 0.f);
+        float w = tab1[t] * tab1[outer] * (valid ? tab1[izc] : 1.f);
+        float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : fc / (l * w);
         v[r].x *= h;
         v[r].y *= h;
       }
@@ -588,9 +608,9 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
 #pragma unroll
       for (int r = 0; r < S::E; ++r) {
         const int t = S::t_out(n1, r);
-        float l = a.lap[t] + a.lap[outer] + (valid ? a.lap[iz] : 0.f);
-        float w = a.win2[t] * a.win2[outer] * (valid ? a.win2[iz] : 1.f);
-        float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : fused_coef(a, slot) / (l * w);
+        float l = tab0[t] + tab0[outer] + (valid ? tab0[izc] : 0.f);
+        float w = tab1[t] * tab1[outer] * (valid ? tab1[izc] : 1.f);
+        float h = (t == 0 && outer == 0 && iz == 0) || !valid ? 0.f : fc / (l * w);
         float2 d2 = make_float2(0.f, 0.f);
         float cs = 1.f, sn = 0.f;
         if (valid) {
@@ -610,12 +630,11 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
     if constexpr (MODE == MODE_NUFFT_C) {
       // truncation, deconvolution and i k_c s / k^2 of component comp
       const float k0 = 6.283185307179586f / (float)a.n_p;
-      const int izc = valid ? iz : 0;
-      const float dyz = a.esdec[outer] * a.esdec[izc];
+      const float dyz = tab0[outer] * tab0[izc];
 #pragma unroll
       for (int r = 0; r < S::E; ++r) {
         const int t = S::t_out(n1, r);
-        const float dec = a.esdec[t] * dyz;
+        const float dec = tab0[t] * dyz;
         const int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), izc};
         float th2 = 0.f;
 #pragma unroll
@@ -630,12 +649,11 @@ __global__ void __launch_bounds__(256, 2) k_cols_reg(ColArgs a) {  // <= 256 VGP
       // -i k_c of the transposed multiplier, what is left is real:
       // coef / (k^2 Phi^2) on the kept modes (coef includes n_f / n_p)
       const float k0 = 6.283185307179586f / (float)a.n_p;
-      const int izc = valid ? iz : 0;
-      const float dyz = a.esdec[outer] * a.esdec[izc];
+      const float dyz = tab0[outer] * tab0[izc];
 #pragma unroll
       for (int r = 0; r < S::E; ++r) {
         const int t = S::t_out(n1, r);
-        const float dec = a.esdec[t] * dyz;
+        const float dec = tab0[t] * dyz;
         const int ms[3] = {signed_mode(t, a.n), signed_mode(outer, a.n), izc};
         float th2 = 0.f;
 #pragma unroll
