@@ -310,9 +310,11 @@ hipError_t launch_i64_to_delta(const long long* m, float* delta, long long M, lo
 // adds it to the wave's own LDS column.  Wave columns and then x planes are
 // summed in a fixed order: the FP64 result does not depend on scheduling.
 
-__device__ __forceinline__ int pk_bin(long long m2) {
-  long long t = 4 * m2;
-  long long r = (long long)sqrt((double)t);
+// bin of |m|^2 = m2 from s = sqrt(m2) (sqrt(4 m2) = 2 s exactly, and the
+// integer steps make r = floor(sqrt(4 m2)) exact)
+__device__ __forceinline__ int pk_bin(long long m2, double s) {
+  const long long t = 4 * m2;
+  long long r = (long long)(2.0 * s);
   while (r * r > t) --r;
   while ((r + 1) * (r + 1) <= t) ++r;
   return (int)((r + 1) / 2);
@@ -332,37 +334,53 @@ __global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, const fl
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long mx = x < n / 2 ? x : x - n;
+  constexpr int kChunks = 9;  // 64-wide z chunks of a half row (n <= 1024)
   for (int y = wave; y < n; y += 4) {
     const long long my = y < n / 2 ? y : y - n;
-    for (int z0 = 0; z0 < nh; z0 += 64) {
-      int z = z0 + lane;
-      int b = 0;
-      double vp = 0.0, vk = 0.0, vc = 0.0;
+    // the whole half row's values first (in-range z for every lane), so that
+    // a row costs one memory round trip rather than one per chunk
+    // (unconditional reads: a read under a condition is waited for inside it)
+    const long long row = slot * slot_stride + ((long long)x * n + y) * rs;
+    const float2* s2 = spec2 ? spec2 : spec;
+    float2 Xs[kChunks], Ys[kChunks];
+#pragma unroll
+    for (int ch = 0; ch < kChunks; ++ch) {
+      const long long e = row + min(64 * ch + lane, nh - 1);
+      Xs[ch] = spec[e];
+      Ys[ch] = s2[e];
+    }
+#pragma unroll
+    for (int ch = 0; ch < kChunks; ++ch) {
+      if (64 * ch >= nh) break;
+      int z = 64 * ch + lane;
+      int b = 0, vc = 0;  // (the mode count is an integer: one shuffle instead of two)
+      double vp = 0.0, vk = 0.0;
       if (z < nh) {
         long long m2 = mx * mx + my * my + (long long)z * z;
+        const double sm = sqrt((double)m2);  // one square root for the bin and |k|
         if (m2 > 0) {
-          b = pk_bin(m2);
+          b = pk_bin(m2, sm);
           if (b > n_bins) b = 0;
         }
         if (b) {
           double wm = (z == 0 || z == n / 2) ? 1.0 : 2.0;
-          const long long e = slot * slot_stride + ((long long)x * n + y) * rs + z;
-          float2 X = spec[e];
+          const float2 X = Xs[ch];
           double p;
           if (spec2) {
-            const float2 Y = spec2[e];
+            const float2 Y = Ys[ch];
             p = 2.0 * ((double)X.x * Y.x + (double)X.y * Y.y);
           } else {
             p = (double)X.x * X.x + (double)X.y * X.y;
           }
           if (deconv) p /= cic4[x] * cic4[y] * cic4[z];
           vp = wm * p;
-          vk = wm * kf * sqrt((double)m2);
-          vc = wm;
+          vk = wm * kf * sm;
+          vc = (int)wm;
         }
       }
       for (int off = 1; off < 64; off <<= 1) {
-        double up = __shfl_up(vp, off), uk = __shfl_up(vk, off), uc = __shfl_up(vc, off);
+        double up = __shfl_up(vp, off), uk = __shfl_up(vk, off);
+        int uc = __shfl_up(vc, off);
         int ub = __shfl_up(b, off);
         if (lane >= off && ub == b) { vp += up; vk += uk; vc += uc; }
       }
@@ -371,7 +389,7 @@ __global__ void __launch_bounds__(256) k_pk_partial(const float2* spec, const fl
       if (b && last) {
         acc[(0 * n_bins + b - 1) * 4 + wave] += vp;
         acc[(1 * n_bins + b - 1) * 4 + wave] += vk;
-        acc[(2 * n_bins + b - 1) * 4 + wave] += vc;
+        acc[(2 * n_bins + b - 1) * 4 + wave] += (double)vc;
       }
     }
   }
