@@ -52,6 +52,15 @@ __device__ __forceinline__ void tile_origin(int t, const TileGeo& tg, int o[3]) 
 
 // ------------------------------------------------------------- binning
 
+// The kick V' = alpha V + beta A and the drift X' = X + tau V with one fixed
+// rounding in every kernel and path: whether a b + c d is contracted into a
+// fused multiply-add, and which product it keeps, depends on the code around
+// it, and the forward ES kick takes a particle through one of two paths by
+// its rank in the tile list (which the binning's atomics set), so an implicit
+// contraction would make runs differ in the last bit.
+__device__ __forceinline__ float kick_v(float al, float v, float be, float A) { return fmaf(be, A, al * v); }
+__device__ __forceinline__ float drift_x(float x, float tp, float v) { return fmaf(tp, v, x); }
+
 template <int P>
 __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
   const int slot = blockIdx.y;
@@ -63,11 +72,14 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
   int tile = -1;
   if (valid) {
     float p[3] = {a.disp[ps + i], a.disp[ps + N + i], a.disp[ps + 2 * N + i]};
-    if (a.vel) {  // merged first drift X += tau V, written back
+    if (a.vel) {  // merged first drift X += tau V, written back (every load before the stores)
       const float t = slot_f(a.g.gate, a.g.sched, a.g.sched_steps, a.tau, slot, kSchTau1);
+      float v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = a.vel[ps + c * N + i];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        p[c] += t * a.vel[ps + c * N + i];
+        p[c] = drift_x(p[c], t, v[c]);
         a.disp[ps + c * N + i] = p[c];
       }
     }
@@ -438,15 +450,6 @@ __device__ __forceinline__ void tile_weights(const TileArgs& a, long long i, con
 }
 
 // forward: A = gather(FD phi); V = alpha V + beta A; X += tau V (or A only)
-// The kick V' = alpha V + beta A and the drift X' = X + tau V with one fixed
-// rounding in every kernel and path: whether a b + c d is contracted into a
-// fused multiply-add, and which product it keeps, depends on the code around
-// it, and the forward ES kick takes a particle through one of two paths by
-// its rank in the tile list (which the binning's atomics set), so an implicit
-// contraction would make runs differ in the last bit.
-__device__ __forceinline__ float kick_v(float al, float v, float be, float A) { return fmaf(be, A, al * v); }
-__device__ __forceinline__ float drift_x(float x, float tp, float v) { return fmaf(tp, v, x); }
-
 template <int P, int ORD>
 __global__ void __launch_bounds__(256) k_tile_kick(TileArgs a) {
   constexpr int R = kernel_reach<P>() + ORD / 2;
@@ -1776,19 +1779,29 @@ __global__ void __launch_bounds__(256) k_tile_es_bank_order(TileArgs a, int32_t*
     const int m = min(kBankChunk, end - c0);
     if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
     __syncthreads();
+    // every entry's index, then every coordinate, before any use (entries
+    // past the chunk read its last one): loads under the per-entry branch
+    // were waited for one after another
+    int32_t id[KE];
+    float xq[KE][3];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) id[k] = list[c0 + min((int)threadIdx.x + 256 * k, m - 1)];
+#pragma unroll
+    for (int k = 0; k < KE; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xq[k][c] = a.disp[ps + c * N + id[k]];
     int res[KE], rank[KE];
 #pragma unroll
     for (int k = 0; k < KE; ++k) {
       const int e = (int)threadIdx.x + 256 * k;
       res[k] = rank[k] = 0;
       if (e < m) {
-        const int32_t id = list[c0 + e];
         long long j[3];
-        lattice_of(id, a.g.log2_np, a.g.log2_pb, j);
+        lattice_of(id[k], a.g.log2_np, a.g.log2_pb, j);
         int l0[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const long long U = fixed_coord(j[c], a.disp[ps + c * N + id], a.g.log2_r, umask);
+          const long long U = fixed_coord(j[c], xq[k][c], a.g.log2_r, umask);
           l0[c] = (((int)(U >> kFracBits) - kEsAnchor) & nm) - o[c];
         }
         res[k] = ((l0[0] * W + l0[1]) * W + l0[2]) & 63;
