@@ -7,9 +7,10 @@
 //   k_tile_deposit   accumulates the fixed-point CIC/TSC mass in an int64 LDS
 //                    window (tile + 1 cell each side) and writes the whole
 //                    window to a scratch slab;
-//   k_assemble       sums, for every cell, the window values of the (up to 8)
+//   k_assemble_run   sums, for every cell, the window values of the (up to 8)
 //                    tiles whose window covers it (int64: order-free; the FP32
-//                    partial sums of the ES force chains in a fixed order);
+//                    partial sums of the ES force chains in a fixed order),
+//                    one z-run of cells per block (k_assemble: small meshes);
 //   k_tile_kick      stages the potential over the tile + stencil reach in LDS
 //                    and does the FD-gradient gather, kick and drift;
 //   k_tile_adj_kick  the same gather with the position gradient for the
