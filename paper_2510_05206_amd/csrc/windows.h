@@ -48,17 +48,18 @@ __device__ __forceinline__ V win_sum(const V* __restrict__ slab, const WinCover&
 }
 
 // store an LDS window (z fastest, W <= 32) of tile t into the slot's slab:
-// the block's groups of 32 lanes take rows (lx, ly) in turn, one lane per z
+// the block's groups of 32 lanes take rows r = lx W + ly in turn, one lane
+// per z.  slab_row(tx, ty, tz, lx, ly) = slab_row(tx, ty, tz, 0, 0) +
+// r nt W, so the addresses advance by a constant (no division by W per row)
 template <class V>
 __device__ __forceinline__ void store_window(const V* win, V* slab, int t, int W, int log2nt) {
   const int nt = 1 << log2nt, m = nt - 1;
   const int tx = t >> (2 * log2nt), ty = (t >> log2nt) & m, tz = t & m;
   const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5, W2 = W * W, ng = blockDim.x >> 5;
   if (lane >= W) return;
-  for (int r = grp; r < W2; r += ng) {
-    const int lx = r / W, ly = r - lx * W;
-    slab[slab_row(tx, ty, tz, lx, ly, W, nt) + lane] = win[r * W + lane];
-  }
+  const long long ntW = (long long)nt * W;
+  long long o = slab_row(tx, ty, tz, 0, 0, W, nt) + grp * ntW + lane;
+  for (int r = grp; r < W2; r += ng, o += ng * ntW) slab[o] = win[r * W + lane];
 }
 
 // the same with the int64 window converted to FP32 partial sums (value
@@ -69,10 +70,9 @@ __device__ __forceinline__ void store_window_f32(const unsigned long long* win, 
   const int tx = t >> (2 * log2nt), ty = (t >> log2nt) & m, tz = t & m;
   const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5, W2 = W * W, ng = blockDim.x >> 5;
   if (lane >= W) return;
-  for (int r = grp; r < W2; r += ng) {
-    const int lx = r / W, ly = r - lx * W;
-    slab[slab_row(tx, ty, tz, lx, ly, W, nt) + lane] = (float)((double)(long long)win[r * W + lane] * scale);
-  }
+  const long long ntW = (long long)nt * W;
+  long long o = slab_row(tx, ty, tz, 0, 0, W, nt) + grp * ntW + lane;
+  for (int r = grp; r < W2; r += ng, o += ng * ntW) slab[o] = (float)((double)(long long)win[r * W + lane] * scale);
 }
 
 // the same cover when Rlo + Rhi <= T: the own tile and at most one
