@@ -407,7 +407,10 @@ __device__ __forceinline__ void load_window(float* win, const float* mesh, const
   const int W = T + Rlo + Rhi, W2 = W * W;
   const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
   const bool zok = lane < W;
-  const long long gz = (o[2] - Rlo + lane) & nm;
+  const unsigned gz = (unsigned)((o[2] - Rlo + lane) & nm);
+  // rows r = lx W + ly step by 8 (one carry when W > 8), no division per
+  // row; a mesh of at most 1024^3 cells indexes in 32 bits
+  int lx = grp / W, ly = grp - lx * W;
   for (int r0 = grp; r0 < W2; r0 += 8 * U) {
     float v[U];
 #pragma unroll
@@ -415,9 +418,13 @@ __device__ __forceinline__ void load_window(float* win, const float* mesh, const
       const int r = r0 + 8 * u;
       v[u] = 0.f;
       if (zok && r < W2) {
-        const int lx = r / W, ly = r - lx * W;
-        const int gx = (o[0] - Rlo + lx) & nm, gy = (o[1] - Rlo + ly) & nm;
-        v[u] = mesh[((long long)((gx << L) + gy) << L) + gz];
+        const unsigned gx = (unsigned)((o[0] - Rlo + lx) & nm), gy = (unsigned)((o[1] - Rlo + ly) & nm);
+        v[u] = mesh[((gx << L | gy) << L) | gz];
+      }
+      ly += 8;
+      while (ly >= W) {
+        ly -= W;
+        ++lx;
       }
     }
 #pragma unroll
@@ -1115,7 +1122,8 @@ __device__ __forceinline__ void load_window_es(float* win, const float* __restri
     const int e0 = 256 * k + wbase, e = min(e0 + lane, kEsWin3 - 1);
     const int lx = e / W2, r = e - lx * W2, ly = r / W, lz = r - ly * W;
     const int gx = (o[0] - kEsLo + lx) & nm, gy = (o[1] - kEsLo + ly) & nm, gz = (o[2] - kEsLo + lz) & nm;
-    const float* src = mesh + (((long long)((gx << L) + gy) << L) + gz);
+    // (a mesh of at most 1024^3 cells: the cell index fits 32 bits)
+    const float* src = mesh + ((((unsigned)gx << L | (unsigned)gy) << L) | (unsigned)gz);
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(win + e0), 4, 0, 0);
   }
   __builtin_amdgcn_s_waitcnt(0);  // this thread's window loads have landed (the caller's barrier does the rest)
